@@ -1,0 +1,207 @@
+/*
+ * dtn.h -- C-ABI of the MI355X library for the local Dirichlet-to-Neumann
+ * (DtN) method of Yan, Cai & Zeng, "A parallel method for solving Laplace
+ * equations with Dirichlet data using local boundary integral equations and
+ * random walks" (BIE-WOS).
+ *
+ * The problem (Sec. 2, eqs. bw01 and bw03): given Dirichlet data phi on the
+ * boundary of a domain Omega, find the Neumann data du/dn on patches of the
+ * boundary, then u anywhere from both.  The method (Sec. 4, the two-step
+ * BIE-WOS algorithm):
+ *   step 1  u at quadrature nodes on a hemisphere over each patch, by the
+ *           Feynman-Kac formula sampled with walk on spheres (Sec. 2, eq. bw13;
+ *           node estimator eq. bw87)                         -> dtn_wos_eval
+ *   step 2  collocation solve of the local first-kind BIE K sigma = b on the
+ *           patch (eqs. bw49-bw51; Sec. 5.2)                 -> dtn_patch_solve
+ *   then    u at arbitrary points from eq. bw03              -> dtn_potential
+ *
+ * Conventions
+ *   - Bulk arrays are DEVICE pointers owned by the caller (e.g. the data_ptr
+ *     of a torch tensor on the GPU).  They must stay allocated until the work
+ *     enqueued on `stream` has completed.  The library never frees them.
+ *   - Descriptors (dtn_geometry_desc, dtn_patch arrays given to
+ *     dtn_create_plan) are HOST memory, copied during the call.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Compute calls
+ *     only enqueue work; results are valid once the stream has synchronised.
+ *   - Errors: a call returns DTN_OK or a negative dtn_status; argument and
+ *     shape errors are detected before anything is enqueued.  A HIP error
+ *     raised while enqueuing is returned as DTN_E_DEVICE.  dtn_last_error()
+ *     gives a message for the last failing call on the calling thread.  No
+ *     C++ exception crosses this interface.
+ *   - Geometries and plans are immutable after creation and may be used from
+ *     several streams and threads at once.
+ *   - Randomness: walk k from a point with stream id s uses Philox4x32-10
+ *     (Salmon et al., SC'11) with key = seed and counter = (k lo, k hi, draw,
+ *     s); one block feeds two steps.  A walk's path is thus a pure function
+ *     of (seed, s, k), independent of batching and launch configuration.
+ *   - The normal n is the OUTWARD normal of Omega, the domain in which the
+ *     walks run; dtn_patch_solve returns du/dn for that n.
+ */
+#ifndef DTN_H
+#define DTN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DTN_OK = 0,
+    DTN_E_ARG = -1,         /* invalid argument, shape or descriptor      */
+    DTN_E_DEVICE = -2,      /* HIP runtime error                          */
+    DTN_E_OOM = -3,         /* device or host allocation failed           */
+    DTN_E_UNSUPPORTED = -4, /* valid request this build does not support  */
+    DTN_E_NOCONV = -5,      /* iterative refinement did not converge      */
+    DTN_E_MAXSTEPS = -6     /* reserved: walks capped (see dtn_wos_eval)  */
+} dtn_status;
+
+/* Domain kinds (all interior: walks run inside Omega). */
+enum { DTN_BALL = 0, DTN_BOX = 1, DTN_BOX_MINUS_BOXES = 2 };
+/* Dirichlet data kinds. */
+enum { DTN_DATA_HARMONIC_QUADRATIC = 0, DTN_DATA_POINT_SOURCES = 1 };
+/* Arithmetic of the walks and of the collocation solve. */
+enum { DTN_FP64 = 0, DTN_FP32_MIXED = 1 };
+
+typedef struct dtn_geometry_s *dtn_geometry; /* opaque, library-owned */
+typedef struct dtn_plan_s *dtn_plan;         /* opaque, library-owned */
+
+/* Domain, Dirichlet data and walk parameters (host memory, copied).
+ *   kind DTN_BALL:            |x - ball_c| < ball_r
+ *   kind DTN_BOX:             box_lo < x < box_hi
+ *   kind DTN_BOX_MINUS_BOXES: the box minus n_holes closed axis-aligned
+ *                             boxes holes[i] = (lo x,y,z, hi x,y,z), which
+ *                             must lie inside it and not overlap.
+ *   data DTN_DATA_HARMONIC_QUADRATIC: phi = q0 + q1 x + q2 y + q3 z + q4 x^2
+ *        + q5 y^2 + q6 z^2 + q7 xy + q8 yz + q9 xz, harmonic (q4+q5+q6 = 0).
+ *   data DTN_DATA_POINT_SOURCES: phi = sum_k src[k].q / |x - src[k].xyz|,
+ *        src rows (x, y, z, q), every source outside the closed domain.
+ *   eps: width of the absorbing shell (Sec. 2, epsilon-shell WOS), > 0.
+ *   max_steps: a walk still alive after max_steps steps is scored at its
+ *        closest boundary point and counted as capped. */
+typedef struct {
+    int32_t kind;
+    int32_t data_kind;
+    double ball_c[3];
+    double ball_r;
+    double box_lo[3];
+    double box_hi[3];
+    int32_t n_holes;
+    int32_t n_src;
+    const double *holes; /* host [n_holes][6] */
+    const double *src;   /* host [n_src][4]   */
+    double quad_coef[10];
+    double eps;
+    int64_t max_steps;
+} dtn_geometry_desc;
+
+/* One boundary patch S with its hemisphere (Sec. 4, Fig. fig_biewos).
+ *   c: centre on the boundary; n: outward unit normal at c; t1: unit tangent
+ *   (t2 = n x t1); h: hemisphere radius = radius of S.
+ *   Nodes (step 1): n_theta Gauss-Legendre polar angles on [0, theta_max]
+ *   measured from -n (as eq. bw85), times n_phi equispaced azimuths from t1;
+ *   theta_max = pi/2 on a plane, arccos(h / 2R) on a sphere of radius R.
+ *   Node order: patch-major, theta-major, phi-minor.
+ *   Panels (step 2): n_rings x n_sectors polar panels of S (ring-major),
+ *   collocation at the parametric panel centres; on a sphere the rings are
+ *   uniform in geodesic angle.
+ *   Supported: n_theta in [2,32], n_phi even in [4,64], n_rings in [1,16],
+ *   n_sectors in [2,32], n_rings*n_sectors <= 128.  96 bytes. */
+typedef struct {
+    double c[3];
+    double n[3];
+    double t1[3];
+    double h;
+    int32_t n_theta, n_phi, n_rings, n_sectors;
+} dtn_patch;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *dtn_last_error(void);
+
+/* Library version string. */
+const char *dtn_version(void);
+
+/* Create / destroy a geometry.  Uploads the boundary description and data to
+ * the current HIP device.  Errors: DTN_E_ARG for an invalid descriptor
+ * (negative sizes, eps <= 0, non-harmonic quadratic, holes outside the box),
+ * DTN_E_OOM / DTN_E_DEVICE on allocation or copy failure. */
+dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out);
+void dtn_destroy_geometry(dtn_geometry g);
+
+/* Step 1: u at n points by walk on spheres (Sec. 2 eq. bw13; eq. bw87).
+ *   pts        device [n][3] points inside Omega (a point already within
+ *              eps of the boundary ends its walks at once, with 0 steps)
+ *   walks      device [n] walks per point (values < 0 are taken as 0)
+ *   walk_begin device [n] index of each point's first walk, or NULL for 0
+ *              (lets a caller extend an estimate: walks [b, b+walks))
+ *   seed       Philox key
+ *   stream_id  device [n] per-point stream ids, or NULL for the point index
+ *   precision  DTN_FP64 (all in FP64) or DTN_FP32_MIXED (direction, distance
+ *              and jump in FP32; position, epsilon test, projection, scores
+ *              and sums in FP64)
+ *   stats      device [n][4] out: (count, mean, M2, steps), M2 = sum of
+ *              squared deviations from the mean; count = 0 gives zeros
+ *   capped     device [n] out (int64): walks ended by max_steps, or NULL
+ * Scratch is taken from the stream-ordered allocator and released on the
+ * same stream.  Errors: DTN_E_ARG (n < 0, NULL pts/walks/stats when n > 0,
+ * unknown precision). */
+dtn_status dtn_wos_eval(dtn_geometry g, const double *pts, int64_t n, const int64_t *walks,
+                        const int64_t *walk_begin, uint64_t seed, const uint32_t *stream_id,
+                        int32_t precision, double *stats, int64_t *capped, void *stream);
+
+/* A plan holds the patches of a DtN request and, per class of congruent
+ * patches, the collocation operators of step 2: the single-layer matrix K
+ * (eq. bw50) and its LU factors, the Gamma operator (Poisson kernel against
+ * the interpolant of the node values, Sec. 5.2), the double-layer table on
+ * curved patches, and the tile fit used by dtn_potential.  Built once on the
+ * host and uploaded; the FP32 LU factors are computed on the device.
+ *   patches  host [n_patches] (copied)
+ * Errors: DTN_E_ARG for a patch outside the supported layouts, a patch whose
+ * hemisphere is not inside Omega's supported shapes (plane faces of a box,
+ * or the sphere of a ball), or n_patches < 1. */
+dtn_status dtn_create_plan(dtn_geometry g, const dtn_patch *patches, int64_t n_patches, dtn_plan *out);
+void dtn_destroy_plan(dtn_plan p);
+/* Sizes of a plan: total nodes and total panels over its patches. */
+int64_t dtn_plan_num_nodes(dtn_plan p);
+int64_t dtn_plan_num_panels(dtn_plan p);
+
+/* Hemisphere nodes of every patch of the plan (device [num_nodes][3] out). */
+dtn_status dtn_patch_nodes(dtn_plan p, double *nodes, void *stream);
+
+/* Step 2: Neumann data on every panel of every patch (eqs. bw49-bw51):
+ *   b = phi(x)/2 + DL(x) - sum_k (Q.I)_k u_k,  K sigma = b,
+ * DL the double-layer integral of phi over S (zero on plane patches), u_k the
+ * node means, and SE(sigma) = sqrt(sum_k A_k^2 SE_k^2), A = K^-1 (Q.I).
+ *   node_stats device [num_nodes][4] from dtn_wos_eval, node order
+ *   precision  DTN_FP64: FP64 LU solve; DTN_FP32_MIXED: FP32 LU factors
+ *              (computed on the device with MFMA) + FP64 residual iterative
+ *              refinement
+ *   neumann    device [num_panels] out, patch-major, ring-major
+ *   neumann_se device [num_panels] out, or NULL */
+dtn_status dtn_patch_solve(dtn_plan p, const double *node_stats, int32_t precision, double *neumann,
+                           double *neumann_se, void *stream);
+
+/* u at m targets off the boundary by eq. bw03 (G = 1/(4 pi |x - y|)).
+ * Requires every patch to be a square tile [-h,h]^2 of a box face (tiles
+ * covering the boundary, as produced by splitting each face into squares):
+ * per tile, the Neumann data is the least-squares quadratic through the
+ * panels within 0.7 h of the centre and the tile integral a 4 x 4 Gauss rule
+ * with the exact Dirichlet data.  DTN_E_UNSUPPORTED for other plans.
+ *   neumann device [num_panels]; targets device [m][3]; u_out device [m] */
+dtn_status dtn_potential(dtn_plan p, const double *neumann, const double *targets, int64_t m,
+                         double *u_out, void *stream);
+
+/* Diagnostic, host only (no device needed): the class operators that
+ * dtn_create_plan builds for patches with this layout and curvature, in local
+ * coordinates scaled by 1/h (rr = R/h on a sphere of radius R, 0 on a plane).
+ * Outputs are host arrays (any may be NULL):
+ *   node_tab [n_theta*n_phi][3], col_tab [P][3], K [P][P] (at h = 1),
+ *   QI [P][n_theta*n_phi], A2 [P][n_theta*n_phi], fit [16][P];
+ *   P = n_rings*n_sectors.  Lets a caller inspect or test step 2's operators. */
+dtn_status dtn_class_operators(int32_t n_theta, int32_t n_phi, int32_t n_rings, int32_t n_sectors, double rr,
+                               double *node_tab, double *col_tab, double *K, double *QI, double *A2, double *fit);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DTN_H */

@@ -1,0 +1,484 @@
+// C-ABI of the library: geometries, plans, argument checks, error strings.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "dtn_internal.h"
+
+namespace dtn {
+
+namespace {
+thread_local std::string g_last_error;
+
+struct ClassKey {
+    int nt, nf, nr, ns;
+    double rr;
+    bool operator<(const ClassKey &o) const
+    {
+        return std::tie(nt, nf, nr, ns, rr) < std::tie(o.nt, o.nf, o.nr, o.ns, o.rr);
+    }
+};
+
+// Device-resident class operators, shared by all plans of a process and
+// kept until exit (a class is a few hundred KB at most).
+struct ClassEntry {
+    DevClass dev{};
+    int device = -1;
+};
+std::mutex g_class_mu;
+std::map<std::pair<int, ClassKey>, ClassEntry> g_classes;
+
+template <class T>
+hipError_t upload(const std::vector<T> &v, T **out)
+{
+    *out = nullptr;
+    if (v.empty()) return hipSuccess;
+    hipError_t e = hipMalloc((void **)out, sizeof(T) * v.size());
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*out, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
+}
+
+dtn_status get_class(const ClassKey &key, int device, DevClass &out, bool &fresh)
+{
+    std::lock_guard<std::mutex> lk(g_class_mu);
+    auto it = g_classes.find({device, key});
+    fresh = false;
+    if (it != g_classes.end()) {
+        out = it->second.dev;
+        return DTN_OK;
+    }
+    ClassOps ops;
+    ops.n_theta = key.nt;
+    ops.n_phi = key.nf;
+    ops.n_rings = key.nr;
+    ops.n_sectors = key.ns;
+    ops.rr = key.rr;
+    std::string err;
+    if (!build_class_ops(ops, err)) return fail(DTN_E_ARG, "dtn_create_plan: " + err);
+    DevClass d{};
+    d.n_theta = key.nt;
+    d.n_phi = key.nf;
+    d.n_rings = key.nr;
+    d.n_sectors = key.ns;
+    d.n_nodes = key.nt * key.nf;
+    d.n_panels = key.nr * key.ns;
+    d.curved = key.rr != 0.0 ? 1 : 0;
+    d.n_dl = ops.n_dl;
+    d.rr = key.rr;
+    double *p = nullptr;
+    int32_t *ip = nullptr;
+    hipError_t e = hipSuccess;
+#define UP(field, vec)                                   \
+    if (e == hipSuccess) {                               \
+        e = upload(ops.vec, &p);                         \
+        d.field = p;                                     \
+    }
+    UP(node_tab, node_tab)
+    UP(col_tab, col_tab)
+    UP(K, K)
+    UP(LU, LU)
+    UP(QI, QI)
+    UP(A2, A2)
+    UP(dl_pts, dl_pts)
+    UP(dl_w, dl_w)
+    UP(fit, fit)
+    UP(tile_gl, tile_gl)
+#undef UP
+    if (e == hipSuccess) {
+        e = upload(ops.piv, &ip);
+        d.piv = ip;
+    }
+    if (e == hipSuccess) e = hipMalloc((void **)&d.LU32, sizeof(float) * d.n_panels * d.n_panels);
+    if (e == hipSuccess) e = hipMalloc((void **)&d.piv32, sizeof(int32_t) * d.n_panels);
+    if (e != hipSuccess) return fail(DTN_E_OOM, std::string("dtn_create_plan: ") + hipGetErrorString(e));
+    g_classes[{device, key}] = ClassEntry{d, device};
+    out = d;
+    fresh = true;
+    return DTN_OK;
+}
+
+bool unit(const double *v, double tol = 1e-12) { return std::fabs(std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) - 1.0) < tol; }
+
+// distance from a point to a closed axis-aligned box (0 inside)
+double box_dist(const double *x, const double *lo, const double *hi)
+{
+    double s = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double q = std::max({lo[k] - x[k], 0.0, x[k] - hi[k]});
+        s += q * q;
+    }
+    return std::sqrt(s);
+}
+
+// Check that a plane patch lies on a face of the box or of a hole, that S
+// fits inside that face and that the half ball over it stays in Omega.
+bool check_plane_patch(const Geometry &g, const dtn_patch &p, std::string &why)
+{
+    int k = -1;
+    double sgn = 0.0;
+    for (int a = 0; a < 3; ++a)
+        if (std::fabs(std::fabs(p.n[a]) - 1.0) < 1e-12) {
+            k = a;
+            sgn = p.n[a] > 0 ? 1.0 : -1.0;
+        }
+    if (k < 0 || std::fabs(p.n[(k + 1) % 3]) > 1e-12 || std::fabs(p.n[(k + 2) % 3]) > 1e-12) {
+        why = "normal is not an axis direction";
+        return false;
+    }
+    const double *lo = g.dev.lo, *hi = g.dev.hi;
+    const double scale = 1.0 + std::max({std::fabs(lo[0]), std::fabs(lo[1]), std::fabs(lo[2]), std::fabs(hi[0]),
+                                         std::fabs(hi[1]), std::fabs(hi[2])});
+    const double tol = 1e-9 * scale;
+    const int a = (k + 1) % 3, b = (k + 2) % 3;
+    auto fits = [&](const double *flo, const double *fhi) {
+        return p.c[a] - p.h >= flo[a] - tol && p.c[a] + p.h <= fhi[a] + tol && p.c[b] - p.h >= flo[b] - tol &&
+               p.c[b] + p.h <= fhi[b] + tol;
+    };
+    int face_hole = -2;  // -1: outer box face, >= 0: hole index
+    const double plane = sgn < 0 ? lo[k] : hi[k];
+    if (std::fabs(p.c[k] - plane) < tol && fits(lo, hi)) face_hole = -1;
+    for (int i = 0; i < g.dev.n_holes && face_hole == -2; ++i) {
+        const double *hl = &g.holes[6 * i], *hh = &g.holes[6 * i + 3];
+        const double hp = sgn > 0 ? hl[k] : hh[k];  // Omega's outward normal points into the hole
+        if (std::fabs(p.c[k] - hp) < tol && fits(hl, hh)) face_hole = i;
+    }
+    if (face_hole == -2) {
+        why = "centre and disk do not lie on a face with this outward normal";
+        return false;
+    }
+    // the half ball on the Omega side must keep clear of every other surface
+    for (int a2 = 0; a2 < 3; ++a2) {
+        if (face_hole == -1 && a2 == k) {
+            const double other = sgn < 0 ? hi[k] : lo[k];
+            if (std::fabs(p.c[k] - other) < p.h - tol) {
+                why = "hemisphere crosses the opposite face";
+                return false;
+            }
+            continue;
+        }
+        if (p.c[a2] - lo[a2] < p.h - tol || hi[a2] - p.c[a2] < p.h - tol) {
+            if (!(face_hole == -1 && a2 == k)) {
+                why = "hemisphere crosses an outer face";
+                return false;
+            }
+        }
+    }
+    for (int i = 0; i < g.dev.n_holes; ++i) {
+        if (i == face_hole) continue;
+        if (box_dist(p.c, &g.holes[6 * i], &g.holes[6 * i + 3]) < p.h - tol) {
+            why = "hemisphere crosses a hole";
+            return false;
+        }
+    }
+    return true;
+}
+
+}  // namespace
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+dtn_status fail(dtn_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+}  // namespace dtn
+
+using namespace dtn;
+
+extern "C" {
+
+struct dtn_geometry_s {
+    Geometry g;
+};
+struct dtn_plan_s {
+    Plan p;
+};
+
+const char *dtn_last_error(void) { return g_last_error.c_str(); }
+const char *dtn_version(void) { return "dtn-wos-mi355x 0.1 (gfx950)"; }
+
+dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
+{
+    try {
+        if (!desc || !out) return fail(DTN_E_ARG, "dtn_create_geometry: NULL argument");
+        *out = nullptr;
+        const dtn_geometry_desc &d = *desc;
+        if (d.kind < DTN_BALL || d.kind > DTN_BOX_MINUS_BOXES) return fail(DTN_E_ARG, "dtn_create_geometry: bad kind");
+        if (d.data_kind != DTN_DATA_HARMONIC_QUADRATIC && d.data_kind != DTN_DATA_POINT_SOURCES)
+            return fail(DTN_E_ARG, "dtn_create_geometry: bad data_kind");
+        if (!(d.eps > 0.0)) return fail(DTN_E_ARG, "dtn_create_geometry: eps must be > 0");
+        if (d.max_steps < 0) return fail(DTN_E_ARG, "dtn_create_geometry: max_steps < 0");
+        if (d.kind == DTN_BALL && !(d.ball_r > 0.0)) return fail(DTN_E_ARG, "dtn_create_geometry: ball_r <= 0");
+        if (d.kind != DTN_BALL)
+            for (int k = 0; k < 3; ++k)
+                if (!(d.box_hi[k] > d.box_lo[k])) return fail(DTN_E_ARG, "dtn_create_geometry: empty box");
+        if (d.n_holes < 0 || d.n_src < 0) return fail(DTN_E_ARG, "dtn_create_geometry: negative count");
+        if (d.kind == DTN_BOX_MINUS_BOXES && d.n_holes > 0 && !d.holes)
+            return fail(DTN_E_ARG, "dtn_create_geometry: holes is NULL");
+        if (d.data_kind == DTN_DATA_POINT_SOURCES && (d.n_src < 1 || !d.src))
+            return fail(DTN_E_ARG, "dtn_create_geometry: point-source data needs sources");
+        if (d.data_kind == DTN_DATA_HARMONIC_QUADRATIC &&
+            std::fabs(d.quad_coef[4] + d.quad_coef[5] + d.quad_coef[6]) >
+                1e-12 * (1.0 + std::fabs(d.quad_coef[4]) + std::fabs(d.quad_coef[5]) + std::fabs(d.quad_coef[6])))
+            return fail(DTN_E_ARG, "dtn_create_geometry: quadratic data is not harmonic");
+        std::unique_ptr<dtn_geometry_s> G(new (std::nothrow) dtn_geometry_s());
+        if (!G) return fail(DTN_E_OOM, "dtn_create_geometry: out of host memory");
+        Geometry &g = G->g;
+        g.desc = d;
+        g.dev.kind = d.kind;
+        g.dev.data_kind = d.data_kind;
+        for (int k = 0; k < 3; ++k) {
+            g.dev.c[k] = d.ball_c[k];
+            g.dev.lo[k] = d.box_lo[k];
+            g.dev.hi[k] = d.box_hi[k];
+        }
+        g.dev.r = d.ball_r;
+        for (int k = 0; k < 10; ++k) g.dev.quad[k] = d.quad_coef[k];
+        g.dev.eps = d.eps;
+        g.dev.max_steps = d.max_steps;
+        const int nh = d.kind == DTN_BOX_MINUS_BOXES ? d.n_holes : 0;
+        g.dev.n_holes = nh;
+        g.holes.assign(d.holes ? d.holes : nullptr, d.holes ? d.holes + 6 * nh : nullptr);
+        std::vector<double> ce(6 * (size_t)nh);
+        for (int i = 0; i < nh; ++i) {
+            const double *h = &g.holes[6 * i];
+            for (int k = 0; k < 3; ++k) {
+                if (!(h[3 + k] > h[k]) || h[k] <= d.box_lo[k] || h[3 + k] >= d.box_hi[k])
+                    return fail(DTN_E_ARG, "dtn_create_geometry: hole " + std::to_string(i) +
+                                               " is empty or not strictly inside the box");
+                ce[6 * i + k] = 0.5 * (h[k] + h[3 + k]);
+                ce[6 * i + 3 + k] = 0.5 * (h[3 + k] - h[k]);
+            }
+        }
+        const int ns = d.data_kind == DTN_DATA_POINT_SOURCES ? d.n_src : 0;
+        g.dev.n_src = ns;
+        if (ns) g.src.assign(d.src, d.src + 4 * ns);
+        hipError_t e = hipGetDevice(&g.device);
+        if (e == hipSuccess) e = upload(ce, &g.d_hole_ce);
+        if (e == hipSuccess) e = upload(g.holes, &g.d_hole_box);
+        if (e == hipSuccess) e = upload(g.src, &g.d_src);
+        if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_create_geometry: ") + hipGetErrorString(e));
+        g.dev.hole_ce = g.d_hole_ce;
+        g.dev.hole_box = g.d_hole_box;
+        g.dev.src = g.d_src;
+        // keep stream-ordered scratch in the pool between calls
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, g.device) == hipSuccess) {
+            uint64_t thr = UINT64_MAX;
+            hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        }
+        *out = G.release();
+        return DTN_OK;
+    } catch (...) {
+        return fail(DTN_E_OOM, "dtn_create_geometry: exception");
+    }
+}
+
+void dtn_destroy_geometry(dtn_geometry g)
+{
+    if (!g) return;
+    hipFree(g->g.d_hole_ce);
+    hipFree(g->g.d_hole_box);
+    hipFree(g->g.d_src);
+    delete g;
+}
+
+dtn_status dtn_wos_eval(dtn_geometry g, const double *pts, int64_t n, const int64_t *walks,
+                        const int64_t *walk_begin, uint64_t seed, const uint32_t *stream_id, int32_t precision,
+                        double *stats, int64_t *capped, void *stream)
+{
+    try {
+        if (!g) return fail(DTN_E_ARG, "dtn_wos_eval: NULL geometry");
+        if (n < 0) return fail(DTN_E_ARG, "dtn_wos_eval: n < 0");
+        if (precision != DTN_FP64 && precision != DTN_FP32_MIXED)
+            return fail(DTN_E_ARG, "dtn_wos_eval: unknown precision");
+        if (n > 0 && (!pts || !walks || !stats)) return fail(DTN_E_ARG, "dtn_wos_eval: NULL array");
+        if (n > ((int64_t)1 << 40)) return fail(DTN_E_ARG, "dtn_wos_eval: n too large");
+        return launch_wos(g->g, pts, n, walks, walk_begin, seed, stream_id, precision, stats, capped,
+                          (hipStream_t)stream);
+    } catch (...) {
+        return fail(DTN_E_DEVICE, "dtn_wos_eval: exception");
+    }
+}
+
+dtn_status dtn_create_plan(dtn_geometry g, const dtn_patch *patches, int64_t n_patches, dtn_plan *out)
+{
+    try {
+        if (!g || !patches || !out) return fail(DTN_E_ARG, "dtn_create_plan: NULL argument");
+        *out = nullptr;
+        if (n_patches < 1 || n_patches > (1 << 26)) return fail(DTN_E_ARG, "dtn_create_plan: bad n_patches");
+        const Geometry &G = g->g;
+        std::unique_ptr<dtn_plan_s> P(new (std::nothrow) dtn_plan_s());
+        if (!P) return fail(DTN_E_OOM, "dtn_create_plan: out of host memory");
+        Plan &p = P->p;
+        p.geom = &g->g;
+        p.patches.assign(patches, patches + n_patches);
+        p.node_off.assign(n_patches + 1, 0);
+        p.panel_off.assign(n_patches + 1, 0);
+        p.patch_class.resize(n_patches);
+        std::map<ClassKey, int> local;
+        std::vector<ClassKey> keys;
+        p.tiles_ok = G.dev.kind == DTN_BOX;
+        for (int64_t i = 0; i < n_patches; ++i) {
+            const dtn_patch &q = p.patches[i];
+            const std::string at = "dtn_create_plan: patch " + std::to_string(i) + ": ";
+            if (q.n_theta < 2 || q.n_theta > 32 || q.n_phi < 4 || q.n_phi > 64 || (q.n_phi & 1) || q.n_rings < 1 ||
+                q.n_rings > 16 || q.n_sectors < 2 || q.n_sectors > 32 || q.n_rings * q.n_sectors > 128)
+                return fail(DTN_E_ARG, at + "unsupported node or panel layout");
+            if (!(q.h > 0.0) || !unit(q.n) || !unit(q.t1) ||
+                std::fabs(q.n[0] * q.t1[0] + q.n[1] * q.t1[1] + q.n[2] * q.t1[2]) > 1e-12)
+                return fail(DTN_E_ARG, at + "h <= 0 or frame (n, t1) not orthonormal");
+            double rr = 0.0;
+            if (G.dev.kind == DTN_BALL) {
+                const double R = G.dev.r;
+                double v[3], rv = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    v[k] = q.c[k] - G.dev.c[k];
+                    rv += v[k] * v[k];
+                }
+                rv = std::sqrt(rv);
+                if (std::fabs(rv - R) > 1e-12 * R) return fail(DTN_E_ARG, at + "centre is not on the sphere");
+                for (int k = 0; k < 3; ++k)
+                    if (std::fabs(v[k] / rv - q.n[k]) > 1e-12) return fail(DTN_E_ARG, at + "n is not the outward normal");
+                if (!(q.h <= R)) return fail(DTN_E_ARG, at + "h must not exceed the ball radius");
+                rr = R / q.h;
+            } else {
+                std::string why;
+                if (!check_plane_patch(G, q, why)) return fail(DTN_E_ARG, at + why);
+                // potential tiles: patches on the outer faces only
+                const int k = std::fabs(q.n[0]) > 0.5 ? 0 : (std::fabs(q.n[1]) > 0.5 ? 1 : 2);
+                const double plane = q.n[k] < 0 ? G.dev.lo[k] : G.dev.hi[k];
+                if (std::fabs(q.c[k] - plane) > 1e-9) p.tiles_ok = false;
+            }
+            const ClassKey key{q.n_theta, q.n_phi, q.n_rings, q.n_sectors, rr};
+            auto it = local.find(key);
+            int ci;
+            if (it == local.end()) {
+                ci = (int)keys.size();
+                local[key] = ci;
+                keys.push_back(key);
+            } else {
+                ci = it->second;
+            }
+            p.patch_class[i] = ci;
+            p.node_off[i + 1] = p.node_off[i] + (int64_t)q.n_theta * q.n_phi;
+            p.panel_off[i + 1] = p.panel_off[i] + (int64_t)q.n_rings * q.n_sectors;
+        }
+        p.n_nodes = p.node_off[n_patches];
+        p.n_panels = p.panel_off[n_patches];
+        hipError_t e = hipGetDevice(&p.device);
+        if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_create_plan: ") + hipGetErrorString(e));
+        std::vector<DevClass> dc(keys.size());
+        std::vector<char> fresh(keys.size(), 0);
+        for (size_t c = 0; c < keys.size(); ++c) {
+            bool f = false;
+            const dtn_status s = get_class(keys[c], p.device, dc[c], f);
+            if (s != DTN_OK) return s;
+            fresh[c] = f;
+        }
+        p.classes.resize(keys.size());
+        for (size_t c = 0; c < keys.size(); ++c) p.classes[c].dev = dc[c];
+        if (e == hipSuccess) e = upload(dc, &p.d_classes);
+        if (e == hipSuccess) e = upload(p.patches, &p.d_patches);
+        if (e == hipSuccess) e = upload(p.patch_class, &p.d_patch_class);
+        if (e == hipSuccess) e = upload(p.node_off, &p.d_node_off);
+        if (e == hipSuccess) e = upload(p.panel_off, &p.d_panel_off);
+        if (e != hipSuccess) return fail(DTN_E_OOM, std::string("dtn_create_plan: ") + hipGetErrorString(e));
+        // FP32 LU factors of new classes, on the device (MFMA trailing updates)
+        bool any_fresh = false;
+        for (char f : fresh) any_fresh = any_fresh || f;
+        if (any_fresh) {
+            std::lock_guard<std::mutex> lk(g_class_mu);
+            const dtn_status s = launch_lu32(p, nullptr);
+            if (s != DTN_OK) return s;
+            e = hipStreamSynchronize(nullptr);
+            if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_create_plan: ") + hipGetErrorString(e));
+        }
+        *out = P.release();
+        return DTN_OK;
+    } catch (...) {
+        return fail(DTN_E_OOM, "dtn_create_plan: exception");
+    }
+}
+
+void dtn_destroy_plan(dtn_plan p)
+{
+    if (!p) return;
+    hipFree(p->p.d_classes);
+    hipFree(p->p.d_patches);
+    hipFree(p->p.d_patch_class);
+    hipFree(p->p.d_node_off);
+    hipFree(p->p.d_panel_off);
+    delete p;
+}
+
+int64_t dtn_plan_num_nodes(dtn_plan p) { return p ? p->p.n_nodes : -1; }
+int64_t dtn_plan_num_panels(dtn_plan p) { return p ? p->p.n_panels : -1; }
+
+dtn_status dtn_patch_nodes(dtn_plan p, double *nodes, void *stream)
+{
+    if (!p || !nodes) return fail(DTN_E_ARG, "dtn_patch_nodes: NULL argument");
+    return launch_nodes(p->p, nodes, (hipStream_t)stream);
+}
+
+dtn_status dtn_patch_solve(dtn_plan p, const double *node_stats, int32_t precision, double *neumann,
+                           double *neumann_se, void *stream)
+{
+    if (!p || !node_stats || !neumann) return fail(DTN_E_ARG, "dtn_patch_solve: NULL argument");
+    if (precision != DTN_FP64 && precision != DTN_FP32_MIXED)
+        return fail(DTN_E_ARG, "dtn_patch_solve: unknown precision");
+    return launch_solve(p->p, node_stats, precision, neumann, neumann_se, (hipStream_t)stream);
+}
+
+dtn_status dtn_potential(dtn_plan p, const double *neumann, const double *targets, int64_t m, double *u_out,
+                         void *stream)
+{
+    if (!p) return fail(DTN_E_ARG, "dtn_potential: NULL plan");
+    if (m < 0) return fail(DTN_E_ARG, "dtn_potential: m < 0");
+    if (m > 0 && (!neumann || !targets || !u_out)) return fail(DTN_E_ARG, "dtn_potential: NULL array");
+    if (!p->p.tiles_ok)
+        return fail(DTN_E_UNSUPPORTED, "dtn_potential: needs square tiles on the faces of a box domain");
+    return launch_potential(p->p, neumann, targets, m, u_out, (hipStream_t)stream);
+}
+
+dtn_status dtn_class_operators(int32_t n_theta, int32_t n_phi, int32_t n_rings, int32_t n_sectors, double rr,
+                               double *node_tab, double *col_tab, double *K, double *QI, double *A2, double *fit)
+{
+    try {
+        ClassOps ops;
+        ops.n_theta = n_theta;
+        ops.n_phi = n_phi;
+        ops.n_rings = n_rings;
+        ops.n_sectors = n_sectors;
+        ops.rr = rr;
+        if (n_theta < 2 || n_theta > 32 || n_phi < 4 || n_phi > 64 || (n_phi & 1) || n_rings < 1 || n_rings > 16 ||
+            n_sectors < 2 || n_sectors > 32 || n_rings * n_sectors > 128 || rr < 0.0 || (rr > 0.0 && rr < 1.0))
+            return fail(DTN_E_ARG, "dtn_class_operators: unsupported layout");
+        std::string err;
+        if (!build_class_ops(ops, err)) return fail(DTN_E_ARG, "dtn_class_operators: " + err);
+        auto put = [](const std::vector<double> &v, double *o) {
+            if (o) std::copy(v.begin(), v.end(), o);
+        };
+        put(ops.node_tab, node_tab);
+        put(ops.col_tab, col_tab);
+        put(ops.K, K);
+        put(ops.QI, QI);
+        put(ops.A2, A2);
+        put(ops.fit, fit);
+        return DTN_OK;
+    } catch (...) {
+        return fail(DTN_E_OOM, "dtn_class_operators: exception");
+    }
+}
+
+}  // extern "C"

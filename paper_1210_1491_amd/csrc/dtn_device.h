@@ -1,0 +1,243 @@
+// Device primitives for the walk-on-spheres kernels (CDNA4, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dtn_internal.h"
+
+namespace dtn {
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------------ Philox
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of the
+// two-multiplier S-box with the key bumped by the Weyl constants between
+// rounds.  The 32x32->64 products map to v_mad_u64_u32; the key schedule is
+// wave-uniform and stays in SGPRs.
+struct Philox4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                 uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return {c0, c1, c2, c3};
+}
+
+// FP64 uniform in (0,1): (k + 1/2) 2^-32, exact.
+__device__ __forceinline__ double u01_f64(uint32_t k) { return fma((double)k, 0x1p-32, 0x1p-33); }
+// FP32 uniform in (0,1): ((k >> 8) + 1/2) 2^-24, exact.
+__device__ __forceinline__ float u01_f32(uint32_t k) { return fmaf((float)(k >> 8), 0x1p-24f, 0x1p-25f); }
+
+// ------------------------------------------------------------- Dirichlet data
+
+template <int DATA>
+__device__ __forceinline__ double phi_eval(const DevGeom &g, double x, double y, double z)
+{
+    if constexpr (DATA == DTN_DATA_HARMONIC_QUADRATIC) {
+        const double *c = g.quad;
+        return c[0] + c[1] * x + c[2] * y + c[3] * z + c[4] * x * x + c[5] * y * y + c[6] * z * z +
+               c[7] * x * y + c[8] * y * z + c[9] * x * z;
+    } else {
+        double s = 0.0;
+        for (int k = 0; k < g.n_src; ++k) {
+            const double *q = g.src + 4 * k;
+            const double dx = x - q[0], dy = y - q[1], dz = z - q[2];
+            s += q[3] / sqrt(dx * dx + dy * dy + dz * dz);
+        }
+        return s;
+    }
+}
+
+// --------------------------------------------------------------- distances
+// Distance from an interior point to the boundary.  Ties for the closest
+// surface go to the lowest index: outer faces -x,+x,-y,+y,-z,+z, then holes.
+
+template <int KIND>
+__device__ __forceinline__ double dist_f64(const DevGeom &g, double x, double y, double z)
+{
+    if constexpr (KIND == DTN_BALL) {
+        const double dx = x - g.c[0], dy = y - g.c[1], dz = z - g.c[2];
+        return g.r - sqrt(dx * dx + dy * dy + dz * dz);
+    } else {
+        double d = fmin(fmin(fmin(x - g.lo[0], g.hi[0] - x), fmin(y - g.lo[1], g.hi[1] - y)),
+                        fmin(z - g.lo[2], g.hi[2] - z));
+        if constexpr (KIND == DTN_BOX_MINUS_BOXES) {
+            for (int i = 0; i < g.n_holes; ++i) {
+                const double *h = g.hole_ce + 6 * i;
+                const double qx = fmax(fabs(x - h[0]) - h[3], 0.0);
+                const double qy = fmax(fabs(y - h[1]) - h[4], 0.0);
+                const double qz = fmax(fabs(z - h[2]) - h[5], 0.0);
+                d = fmin(d, sqrt(qx * qx + qy * qy + qz * qz));
+            }
+        }
+        return d;
+    }
+}
+
+template <int KIND>
+__device__ __forceinline__ float dist_f32(const DevGeom &g, float x, float y, float z)
+{
+    if constexpr (KIND == DTN_BALL) {
+        const float dx = x - (float)g.c[0], dy = y - (float)g.c[1], dz = z - (float)g.c[2];
+        return (float)g.r - sqrtf(dx * dx + dy * dy + dz * dz);
+    } else {
+        float d = fminf(fminf(fminf(x - (float)g.lo[0], (float)g.hi[0] - x),
+                              fminf(y - (float)g.lo[1], (float)g.hi[1] - y)),
+                        fminf(z - (float)g.lo[2], (float)g.hi[2] - z));
+        if constexpr (KIND == DTN_BOX_MINUS_BOXES) {
+            for (int i = 0; i < g.n_holes; ++i) {
+                const double *h = g.hole_ce + 6 * i;
+                const float qx = fmaxf(fabsf(x - (float)h[0]) - (float)h[3], 0.0f);
+                const float qy = fmaxf(fabsf(y - (float)h[1]) - (float)h[4], 0.0f);
+                const float qz = fmaxf(fabsf(z - (float)h[2]) - (float)h[5], 0.0f);
+                d = fminf(d, sqrtf(qx * qx + qy * qy + qz * qz));
+            }
+        }
+        return d;
+    }
+}
+
+// Closest boundary point of an interior point (FP64).
+template <int KIND>
+__device__ __forceinline__ void project_f64(const DevGeom &g, double &x, double &y, double &z)
+{
+    if constexpr (KIND == DTN_BALL) {
+        const double dx = x - g.c[0], dy = y - g.c[1], dz = z - g.c[2];
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        if (r > 0.0) {
+            x = g.c[0] + g.r * dx / r;
+            y = g.c[1] + g.r * dy / r;
+            z = g.c[2] + g.r * dz / r;
+        } else {
+            x = g.c[0] + g.r;
+            y = g.c[1];
+            z = g.c[2];
+        }
+    } else {
+        double p[3] = {x, y, z};
+        double best = x - g.lo[0];
+        int face = 0;
+        const double cand[5] = {g.hi[0] - x, y - g.lo[1], g.hi[1] - y, z - g.lo[2], g.hi[2] - z};
+#pragma unroll
+        for (int f = 1; f < 6; ++f)
+            if (cand[f - 1] < best) {
+                best = cand[f - 1];
+                face = f;
+            }
+        int hole = -1;
+        if constexpr (KIND == DTN_BOX_MINUS_BOXES) {
+            for (int i = 0; i < g.n_holes; ++i) {
+                const double *h = g.hole_ce + 6 * i;
+                const double qx = fmax(fabs(x - h[0]) - h[3], 0.0);
+                const double qy = fmax(fabs(y - h[1]) - h[4], 0.0);
+                const double qz = fmax(fabs(z - h[2]) - h[5], 0.0);
+                const double d = sqrt(qx * qx + qy * qy + qz * qz);
+                if (d < best) {
+                    best = d;
+                    hole = i;
+                }
+            }
+        }
+        if (hole < 0) {
+            const int k = face >> 1;
+            p[k] = (face & 1) ? g.hi[k] : g.lo[k];
+        } else {
+            const double *b = g.hole_box + 6 * hole;
+            bool inside = true;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if (p[k] < b[k]) {
+                    p[k] = b[k];
+                    inside = false;
+                } else if (p[k] > b[3 + k]) {
+                    p[k] = b[3 + k];
+                    inside = false;
+                }
+            }
+            if (inside) {  // rounding left the point inside the hole
+                double bd = p[0] - b[0];
+                int bf = 0;
+                const double c2[5] = {b[3] - p[0], p[1] - b[1], b[4] - p[1], p[2] - b[2], b[5] - p[2]};
+#pragma unroll
+                for (int f = 1; f < 6; ++f)
+                    if (c2[f - 1] < bd) {
+                        bd = c2[f - 1];
+                        bf = f;
+                    }
+                const int k = bf >> 1;
+                p[k] = (bf & 1) ? b[3 + k] : b[k];
+            }
+        }
+        x = p[0];
+        y = p[1];
+        z = p[2];
+    }
+}
+
+// ------------------------------------------------------- compensated sums
+// Neumaier's variant of Kahan summation.
+struct KSum {
+    double s, c;
+};
+__device__ __forceinline__ void kadd(KSum &a, double v)
+{
+    const double t = a.s + v;
+    if (fabs(a.s) >= fabs(v))
+        a.c += (a.s - t) + v;
+    else
+        a.c += (v - t) + a.s;
+    a.s = t;
+}
+// Error-free combination of two compensated sums.
+__device__ __forceinline__ KSum kmerge(KSum a, KSum b)
+{
+    KSum r = a;
+    kadd(r, b.s);
+    r.c += b.c;
+    return r;
+}
+
+__device__ __forceinline__ KSum wave_ksum(KSum a)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        KSum o;
+        o.s = __shfl_xor(a.s, off, kWave);
+        o.c = __shfl_xor(a.c, off, kWave);
+        a = kmerge(a, o);
+    }
+    return a;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Rank of this lane among the lanes set in `mask` below it.
+__device__ __forceinline__ int rank_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+}
+
+}  // namespace dtn

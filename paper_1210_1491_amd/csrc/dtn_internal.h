@@ -1,0 +1,112 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dtn.h"
+
+namespace dtn {
+
+// Geometry as the kernels see it: passed by value (lands in SGPRs), with the
+// holes and sources in device memory read at wave-uniform addresses.
+struct DevGeom {
+    int32_t kind;
+    int32_t data_kind;
+    double c[3];
+    double r;
+    double lo[3];
+    double hi[3];
+    int32_t n_holes;
+    int32_t n_src;
+    const double *hole_ce;  // [n_holes][6]: centre xyz, half-extent xyz
+    const double *hole_box; // [n_holes][6]: lo xyz, hi xyz
+    const double *src;      // [n_src][4]
+    double quad[10];
+    double eps;
+    int64_t max_steps;
+};
+
+// Per-class operators on the device.  A class is a set of congruent patches
+// (same layout and same curvature relative to h); K scales with h.
+struct DevClass {
+    int32_t n_theta, n_phi, n_rings, n_sectors;
+    int32_t n_nodes, n_panels;
+    int32_t curved;       // patch on a sphere (double-layer term present)
+    int32_t n_dl;         // double-layer quadrature points per panel row
+    double rr;            // R / h for curved classes, 0 for plane ones
+    const double *node_tab;   // [n_theta*n_phi][3]: local node offsets / h
+    const double *col_tab;    // [n_panels][3]: local collocation points / h
+    const double *K;          // [n_panels][n_panels] at h = 1, row-major
+    const double *LU;         // [n_panels][n_panels] FP64 LU of K (row-major)
+    const int32_t *piv;       // [n_panels] row permutation of the LU
+    float *LU32;              // [n_panels][n_panels] FP32 LU (device-built)
+    int32_t *piv32;           // [n_panels]
+    const double *QI;         // [n_panels][n_nodes]
+    const double *A2;         // [n_panels][n_nodes]: (K^-1 QI)^2 at h = 1
+    const double *dl_pts;     // [n_panels][n_dl][3] local points / h
+    const double *dl_w;       // [n_panels][n_dl] weights (kernel x area) at h = 1
+    const double *fit;        // [16][n_panels] tile fit (flat classes)
+    const double *tile_gl;    // [16][3]: (xi, eta, weight) on [-1,1]^2
+};
+
+struct Geometry {
+    DevGeom dev{};
+    dtn_geometry_desc desc{};
+    std::vector<double> holes, src;
+    double *d_hole_ce = nullptr, *d_hole_box = nullptr, *d_src = nullptr;
+    int device = 0;
+};
+
+struct PlanClassHost {
+    DevClass dev{};
+    std::vector<void *> allocations;
+};
+
+struct Plan {
+    Geometry *geom = nullptr;
+    std::vector<dtn_patch> patches;
+    std::vector<int32_t> patch_class;
+    std::vector<int64_t> node_off, panel_off;
+    int64_t n_nodes = 0, n_panels = 0;
+    std::vector<PlanClassHost> classes;
+    DevClass *d_classes = nullptr;     // [n_classes]
+    dtn_patch *d_patches = nullptr;    // [n_patches]
+    int32_t *d_patch_class = nullptr;  // [n_patches]
+    int64_t *d_node_off = nullptr;     // [n_patches+1]
+    int64_t *d_panel_off = nullptr;    // [n_patches+1]
+    bool tiles_ok = false;             // every patch is a square tile of a box face
+    int device = 0;
+};
+
+// Error reporting (thread-local last message).
+void set_error(const std::string &msg);
+dtn_status fail(dtn_status s, const std::string &msg);
+
+// Kernel launchers (dtn_wos.hip).
+dtn_status launch_wos(const Geometry &g, const double *pts, int64_t n, const int64_t *walks,
+                      const int64_t *walk_begin, uint64_t seed, const uint32_t *stream_id,
+                      int precision, double *stats, int64_t *capped, hipStream_t stream);
+
+// Kernel launchers (dtn_patch.hip).
+dtn_status launch_nodes(const Plan &p, double *nodes, hipStream_t stream);
+dtn_status launch_solve(const Plan &p, const double *node_stats, int precision, double *neumann,
+                        double *neumann_se, hipStream_t stream);
+dtn_status launch_potential(const Plan &p, const double *neumann, const double *targets, int64_t m,
+                            double *u_out, hipStream_t stream);
+dtn_status launch_lu32(const Plan &p, hipStream_t stream);
+
+// Host operator construction (dtn_operators.cpp).
+struct ClassOps {
+    int n_theta, n_phi, n_rings, n_sectors;
+    double rr;  // R/h (0 = plane)
+    std::vector<double> node_tab, col_tab, K, LU, QI, A2, dl_pts, dl_w, fit, tile_gl;
+    std::vector<int32_t> piv;
+    int n_dl = 0;
+};
+bool build_class_ops(ClassOps &ops, std::string &err);
+
+}  // namespace dtn

@@ -1,0 +1,425 @@
+// Walk-on-spheres kernels: step 1 of the BIE-WOS method.
+//
+// u(y) = E[phi(X_tau)] (Sec. 2, eq. bw13), sampled by walk on spheres with an
+// epsilon absorbing shell (Sec. 2, after Fig. fig_wos): from x jump to a
+// uniform point of the sphere of radius dist(x, boundary); stop once the
+// distance is below eps and record phi at the closest boundary point.  The
+// node estimate is the mean of the recorded values (Sec. 5.1.2, eq. bw87);
+// the kernels also keep the sum of squares for the standard error.
+//
+// Work decomposition (all on the device, no host round trip):
+//   k_wos_plan      one workgroup: total walks -> chunk size C, per-point
+//                   chunk counts and their exclusive scan (chunk offsets)
+//   k_wos_walk      one wave per chunk (point, walk range of <= C walks); the
+//                   wave runs its walks with refill: a lane whose walk ends takes
+//                   the next walk of the chunk, so lanes do not idle behind
+//                   long walks.  Exit points are queued in LDS and scored 64
+//                   at a time by the whole wave, so the scoring code runs
+//                   with full lanes.  Per-lane compensated FP64 sums are
+//                   reduced across the wave and written per chunk.
+//   k_wos_finalize  per point: merge its chunks in chunk order (fixed
+//                   order, so results do not depend on which wave ran which
+//                   chunk), write (count, mean, M2, steps) and capped count.
+//
+// Randomness: walk k of a point with stream id s draws Philox4x32-10 block
+// (k lo, k hi, j, s) for its steps 2j and 2j+1 (words 0,1 then 2,3).  New
+// walks start on even wave iterations only, so every live lane is at the
+// same step parity and the Philox call is wave-uniform (no divergence).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+
+#include "dtn_device.h"
+#include "dtn_internal.h"
+
+namespace dtn {
+
+struct ChunkPartial {
+    double s1, c1, s2, c2;
+    unsigned long long steps, capped;
+};
+
+constexpr int kPlanThreads = 1024;
+constexpr int kWalkBlock = 256;  // 4 waves
+constexpr int kQueue = 128;      // exit-point queue slots per wave
+
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// ----------------------------------------------------------------- planning
+// meta[0] = chunk size C, meta[1] = total chunks.
+__global__ __launch_bounds__(kPlanThreads) void k_wos_plan(const int64_t *__restrict__ walks, int64_t n,
+                                                           int64_t target_chunks, int64_t c_min,
+                                                           int64_t *__restrict__ chunk_off,
+                                                           int64_t *__restrict__ meta)
+{
+    __shared__ int64_t red[kPlanThreads];
+    const int t = threadIdx.x;
+    int64_t tot = 0;
+    for (int64_t i = t; i < n; i += kPlanThreads) tot += max(walks[i], (int64_t)0);
+    red[t] = tot;
+    __syncthreads();
+    for (int s = kPlanThreads / 2; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    const int64_t total_walks = red[0];
+    __syncthreads();
+    const int64_t C = max(c_min, (total_walks + target_chunks - 1) / target_chunks);
+    // contiguous segments per thread, then a block scan of segment sums
+    const int64_t L = (n + kPlanThreads - 1) / kPlanThreads;
+    const int64_t b = min(n, (int64_t)t * L), e = min(n, b + L);
+    int64_t seg = 0;
+    for (int64_t i = b; i < e; ++i) seg += (max(walks[i], (int64_t)0) + C - 1) / C;
+    red[t] = seg;
+    __syncthreads();
+    for (int s = 1; s < kPlanThreads; s <<= 1) {  // Hillis-Steele inclusive scan
+        const int64_t v = (t >= s) ? red[t - s] : 0;
+        __syncthreads();
+        red[t] += v;
+        __syncthreads();
+    }
+    int64_t run = red[t] - seg;
+    for (int64_t i = b; i < e; ++i) {
+        chunk_off[i] = run;
+        run += (max(walks[i], (int64_t)0) + C - 1) / C;
+    }
+    if (t == kPlanThreads - 1) {
+        chunk_off[n] = red[t];
+        meta[0] = C;
+        meta[1] = red[t];
+    }
+}
+
+// ---------------------------------------------------------------- the walks
+
+template <int KIND, int DATA, int PREC>
+__global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double *__restrict__ pts,
+                                                         const int64_t *__restrict__ walks,
+                                                         const int64_t *__restrict__ walk_begin,
+                                                         const uint32_t *__restrict__ stream_id, uint64_t seed,
+                                                         const int64_t *__restrict__ chunk_off,
+                                                         const int64_t *__restrict__ meta, int64_t n,
+                                                         float fp32_margin, ChunkPartial *__restrict__ out)
+{
+    __shared__ double queue[kWalkBlock / kWave][kQueue * 3];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    double *q = queue[wave];
+    const int lane = lane_id();
+    // one chunk per wave; chunk size and count are wave-uniform (SGPRs)
+    const int64_t C = uniform64(meta[0]);
+    const int64_t total = uniform64(meta[1]);
+    const int64_t chunk = (int64_t)blockIdx.x * (kWalkBlock / kWave) + wave;
+    if (chunk >= total) return;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const double eps = g.eps;
+    const float tau = (float)eps + 2.0f * fp32_margin;
+    {
+        // point owning this chunk: largest i with chunk_off[i] <= chunk
+        int64_t lo = 0, hi = n;
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (chunk_off[mid] <= chunk) lo = mid; else hi = mid;
+        }
+        const int64_t node = lo;
+        const int64_t wnode = max(walks[node], (int64_t)0);
+        const int64_t w_lo = (chunk - chunk_off[node]) * C;
+        const int64_t w_hi = min(wnode, w_lo + C);
+        const int64_t wb = walk_begin ? walk_begin[node] : 0;
+        const uint32_t sid = stream_id ? stream_id[node] : (uint32_t)node;
+        const double y0 = pts[3 * node], y1 = pts[3 * node + 1], y2 = pts[3 * node + 2];
+        double sx = y0, sy = y1, sz = y2;
+        project_f64<KIND>(g, sx, sy, sz);
+        const double shift = phi_eval<DATA>(g, sx, sy, sz);
+
+        // lane state
+        bool walking = false;
+        uint64_t walk = 0;
+        double x = y0, y = y1, z = y2;
+        uint32_t nstep = 0;
+        uint32_t r2 = 0, r3 = 0;
+        KSum s1{0.0, 0.0}, s2{0.0, 0.0};
+        unsigned long long steps = 0, capped = 0;
+        int64_t next = w_lo;  // wave-uniform: next walk to hand out
+        int qn = 0;           // wave-uniform: queued exit points
+        // Hard bound on wave iterations: every walk ends within max_steps + 2
+        // iterations of its start and a lane runs at most ceil(C/64) walks.
+        const uint64_t it_max = ((uint64_t)g.max_steps + 4u) * 2u * (uint64_t)((w_hi - w_lo + kWave - 1) / kWave + 1);
+
+        for (uint64_t it = 0; it < it_max; ++it) {
+            float u1f, u2f;
+            double u1d = 0.0, u2d = 0.0;
+            if ((it & 1ull) == 0ull) {
+                const uint64_t want = __ballot(!walking);
+                if (want) {
+                    const int64_t mine = next + rank_below(want);
+                    if (!walking && mine < w_hi) {
+                        walking = true;
+                        walk = (uint64_t)(wb + mine);
+                        x = y0;
+                        y = y1;
+                        z = y2;
+                        nstep = 0;
+                    }
+                    next += __popcll(want);
+                }
+                if (!__any(walking)) break;
+                const Philox4 r = philox4x32_10((uint32_t)walk, (uint32_t)(walk >> 32), nstep >> 1, sid, k0, k1);
+                if constexpr (PREC == DTN_FP64) {
+                    u1d = u01_f64(r.x);
+                    u2d = u01_f64(r.y);
+                } else {
+                    u1f = u01_f32(r.x);
+                    u2f = u01_f32(r.y);
+                }
+                r2 = r.z;
+                r3 = r.w;
+            } else {
+                if constexpr (PREC == DTN_FP64) {
+                    u1d = u01_f64(r2);
+                    u2d = u01_f64(r3);
+                } else {
+                    u1f = u01_f32(r2);
+                    u2f = u01_f32(r3);
+                }
+            }
+            bool fin = false;
+            if (walking) {
+                if constexpr (PREC == DTN_FP64) {
+                    const double d = dist_f64<KIND>(g, x, y, z);
+                    if (d < eps || (int64_t)nstep >= g.max_steps) {
+                        fin = true;
+                        capped += (d >= eps) ? 1ull : 0ull;
+                    } else {
+                        const double cz = 1.0 - 2.0 * u1d;
+                        const double sr = 2.0 * sqrt(u1d * (1.0 - u1d));
+                        double sn, cs;
+                        sincos(2.0 * M_PI * u2d, &sn, &cs);
+                        x += d * (sr * cs);
+                        y += d * (sr * sn);
+                        z += d * cz;
+                        ++nstep;
+                    }
+                } else {
+                    // FP32 distance; FP64 recheck inside the shell margin.
+                    double d = (double)(dist_f32<KIND>(g, (float)x, (float)y, (float)z) - fp32_margin);
+                    bool stop = false;
+                    if (d < (double)tau - (double)fp32_margin) {
+                        d = dist_f64<KIND>(g, x, y, z);
+                        stop = d < eps;
+                    }
+                    if (stop || (int64_t)nstep >= g.max_steps) {
+                        fin = true;
+                        capped += stop ? 0ull : 1ull;
+                    } else {
+                        const float cz = 1.0f - 2.0f * u1f;
+                        const float sr = 2.0f * __builtin_sqrtf(u1f * (1.0f - u1f));
+                        const float cs = __builtin_amdgcn_cosf(u2f);  // cos(2 pi u2)
+                        const float sn = __builtin_amdgcn_sinf(u2f);  // sin(2 pi u2)
+                        x += d * (double)(sr * cs);
+                        y += d * (double)(sr * sn);
+                        z += d * (double)cz;
+                        ++nstep;
+                    }
+                }
+            }
+            const uint64_t fm = __ballot(fin);
+            if (fm) {
+                if (fin) {
+                    project_f64<KIND>(g, x, y, z);
+                    const int slot = qn + rank_below(fm);
+                    q[3 * slot] = x;
+                    q[3 * slot + 1] = y;
+                    q[3 * slot + 2] = z;
+                    steps += nstep;
+                    walking = false;
+                }
+                qn += __popcll(fm);
+                if (qn >= kWave) {
+                    wave_sync();
+                    const double v = phi_eval<DATA>(g, q[3 * lane], q[3 * lane + 1], q[3 * lane + 2]) - shift;
+                    kadd(s1, v);
+                    kadd(s2, v * v);
+                    const int rest = qn - kWave;
+                    double a0 = 0, a1 = 0, a2 = 0;
+                    if (lane < rest) {
+                        a0 = q[3 * (kWave + lane)];
+                        a1 = q[3 * (kWave + lane) + 1];
+                        a2 = q[3 * (kWave + lane) + 2];
+                    }
+                    wave_sync();
+                    if (lane < rest) {
+                        q[3 * lane] = a0;
+                        q[3 * lane + 1] = a1;
+                        q[3 * lane + 2] = a2;
+                    }
+                    wave_sync();
+                    qn = rest;
+                }
+            }
+        }
+        // score what is left in the queue
+        wave_sync();
+        if (lane < qn) {
+            const double v = phi_eval<DATA>(g, q[3 * lane], q[3 * lane + 1], q[3 * lane + 2]) - shift;
+            kadd(s1, v);
+            kadd(s2, v * v);
+        }
+        wave_sync();
+        const KSum t1 = wave_ksum(s1);
+        const KSum t2 = wave_ksum(s2);
+        const unsigned long long ts = wave_sum_u64(steps);
+        const unsigned long long tc = wave_sum_u64(capped);
+        if (lane == 0) {
+            ChunkPartial p;
+            p.s1 = t1.s;
+            p.c1 = t1.c;
+            p.s2 = t2.s;
+            p.c2 = t2.c;
+            p.steps = ts;
+            p.capped = tc;
+            out[chunk] = p;
+        }
+    }
+}
+
+// --------------------------------------------------------------- finalize
+
+template <int KIND, int DATA>
+__global__ __launch_bounds__(256) void k_wos_finalize(DevGeom g, const double *__restrict__ pts,
+                                                      const int64_t *__restrict__ walks, int64_t n,
+                                                      const int64_t *__restrict__ chunk_off,
+                                                      const ChunkPartial *__restrict__ part,
+                                                      double *__restrict__ stats, int64_t *__restrict__ capped)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    KSum s1{0.0, 0.0}, s2{0.0, 0.0};
+    unsigned long long st = 0, cp = 0;
+    for (int64_t c = chunk_off[i]; c < chunk_off[i + 1]; ++c) {
+        const ChunkPartial p = part[c];
+        s1 = kmerge(s1, KSum{p.s1, p.c1});
+        s2 = kmerge(s2, KSum{p.s2, p.c2});
+        st += p.steps;
+        cp += p.capped;
+    }
+    const int64_t w = max(walks[i], (int64_t)0);
+    double sx = pts[3 * i], sy = pts[3 * i + 1], sz = pts[3 * i + 2];
+    project_f64<KIND>(g, sx, sy, sz);
+    const double shift = phi_eval<DATA>(g, sx, sy, sz);
+    const double cnt = (double)w;
+    const double S1 = s1.s + s1.c, S2 = s2.s + s2.c;
+    double mean = 0.0, m2 = 0.0;
+    if (w > 0) {
+        mean = shift + S1 / cnt;
+        m2 = S2 - S1 * S1 / cnt;
+        if (m2 < 0.0) m2 = 0.0;
+    }
+    stats[4 * i] = cnt;
+    stats[4 * i + 1] = mean;
+    stats[4 * i + 2] = m2;
+    stats[4 * i + 3] = (double)st;
+    if (capped) capped[i] = (int64_t)cp;
+}
+
+// ----------------------------------------------------------------- launch
+
+namespace {
+
+int device_cus()
+{
+    static thread_local int cached_dev = -1, cached_cus = 0;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev != cached_dev) {
+        hipDeviceProp_t prop;
+        cached_cus = hipGetDeviceProperties(&prop, dev) == hipSuccess ? prop.multiProcessorCount : 256;
+        cached_dev = dev;
+    }
+    return cached_cus > 0 ? cached_cus : 256;
+}
+
+template <int KIND, int DATA, int PREC>
+hipError_t run(const Geometry &g, const double *pts, int64_t n, const int64_t *walks, const int64_t *walk_begin,
+               uint64_t seed, const uint32_t *stream_id, double *stats, int64_t *capped, hipStream_t s)
+{
+    // Aim for several chunks per resident wave (4 SIMDs x 8 waves per CU).
+    const int64_t target_chunks = (int64_t)device_cus() * 4 * 8 * 4;
+    const int64_t c_min = 512;
+    // total chunks <= sum(walks)/C + n <= target_chunks + n
+    const int64_t max_chunks = n + target_chunks + 1;
+    hipError_t e;
+    const size_t bytes = sizeof(int64_t) * (size_t)(n + 1) + 64 + 16 + sizeof(ChunkPartial) * (size_t)max_chunks;
+    char *scratch = nullptr;
+    if ((e = hipMallocAsync((void **)&scratch, bytes, s)) != hipSuccess) return e;
+    int64_t *meta = (int64_t *)scratch;
+    int64_t *chunk_off = (int64_t *)(scratch + 64);
+    ChunkPartial *part = (ChunkPartial *)(scratch + 64 + sizeof(int64_t) * (size_t)(n + 1));
+    if (((uintptr_t)part & 15u) != 0) part = (ChunkPartial *)(((uintptr_t)part + 15u) & ~(uintptr_t)15u);
+    hipLaunchKernelGGL(k_wos_plan, dim3(1), dim3(kPlanThreads), 0, s, walks, n, target_chunks, c_min, chunk_off,
+                       meta);
+    // FP32 distance error bound: a few ulps of the largest coordinate.
+    double L = 1.0;
+    if (KIND == DTN_BALL) {
+        L = g.dev.r + std::max({fabs(g.dev.c[0]), fabs(g.dev.c[1]), fabs(g.dev.c[2])});
+    } else {
+        for (int k = 0; k < 3; ++k) L = std::max({L, fabs(g.dev.lo[k]), fabs(g.dev.hi[k])});
+    }
+    const float margin = (float)(32.0 * L * 0x1p-24);
+    const int64_t waves_per_block = kWalkBlock / kWave;
+    const int64_t blocks = (max_chunks + waves_per_block - 1) / waves_per_block;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_wos_walk<KIND, DATA, PREC>), dim3((unsigned)blocks), dim3(kWalkBlock), 0, s, g.dev, pts,
+                       walks, walk_begin, stream_id, seed, chunk_off, meta, n, margin, part);
+    hipLaunchKernelGGL((k_wos_finalize<KIND, DATA>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g.dev, pts,
+                       walks, n, chunk_off, part, stats, capped);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return hipFreeAsync(scratch, s);
+}
+
+template <int PREC>
+hipError_t dispatch(const Geometry &g, const double *pts, int64_t n, const int64_t *walks, const int64_t *wb,
+                    uint64_t seed, const uint32_t *sid, double *stats, int64_t *capped, hipStream_t s)
+{
+    const bool src = g.dev.data_kind == DTN_DATA_POINT_SOURCES;
+    switch (g.dev.kind) {
+    case DTN_BALL:
+        return src ? run<DTN_BALL, DTN_DATA_POINT_SOURCES, PREC>(g, pts, n, walks, wb, seed, sid, stats, capped, s)
+                   : run<DTN_BALL, DTN_DATA_HARMONIC_QUADRATIC, PREC>(g, pts, n, walks, wb, seed, sid, stats, capped, s);
+    case DTN_BOX:
+        return src ? run<DTN_BOX, DTN_DATA_POINT_SOURCES, PREC>(g, pts, n, walks, wb, seed, sid, stats, capped, s)
+                   : run<DTN_BOX, DTN_DATA_HARMONIC_QUADRATIC, PREC>(g, pts, n, walks, wb, seed, sid, stats, capped, s);
+    default:
+        return src ? run<DTN_BOX_MINUS_BOXES, DTN_DATA_POINT_SOURCES, PREC>(g, pts, n, walks, wb, seed, sid, stats,
+                                                                            capped, s)
+                   : run<DTN_BOX_MINUS_BOXES, DTN_DATA_HARMONIC_QUADRATIC, PREC>(g, pts, n, walks, wb, seed, sid,
+                                                                                 stats, capped, s);
+    }
+}
+
+}  // namespace
+
+dtn_status launch_wos(const Geometry &g, const double *pts, int64_t n, const int64_t *walks,
+                      const int64_t *walk_begin, uint64_t seed, const uint32_t *stream_id, int precision,
+                      double *stats, int64_t *capped, hipStream_t stream)
+{
+    if (n == 0) return DTN_OK;
+    hipError_t e = precision == DTN_FP64
+                       ? dispatch<DTN_FP64>(g, pts, n, walks, walk_begin, seed, stream_id, stats, capped, stream)
+                       : dispatch<DTN_FP32_MIXED>(g, pts, n, walks, walk_begin, seed, stream_id, stats, capped, stream);
+    if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_wos_eval: ") + hipGetErrorString(e));
+    return DTN_OK;
+}
+
+}  // namespace dtn

@@ -1,0 +1,240 @@
+"""Python binding of libdtn (the HIP library for the local DtN method).
+
+Argument marshalling only: every step runs in the library's HIP kernels, on
+torch's current HIP stream, with device memory owned by torch tensors.  The
+library must have been built (``paper_1210_1491_amd.build``); importing this
+module fails loudly when it has not.  There is no CPU fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdtn.so")
+
+DTN_OK = 0
+STATUS = {0: "DTN_OK", -1: "DTN_E_ARG", -2: "DTN_E_DEVICE", -3: "DTN_E_OOM", -4: "DTN_E_UNSUPPORTED",
+          -5: "DTN_E_NOCONV", -6: "DTN_E_MAXSTEPS"}
+KIND = {"ball": 0, "box": 1, "box_minus_boxes": 2}
+DATA = {"quadratic": 0, "sources": 1}
+PRECISION = {"fp64": 0, "fp32": 1, "fp32_mixed": 1}
+
+
+class DtnError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class GeometryDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("data_kind", C.c_int32), ("ball_c", C.c_double * 3),
+                ("ball_r", C.c_double), ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
+                ("n_holes", C.c_int32), ("n_src", C.c_int32), ("holes", C.POINTER(C.c_double)),
+                ("src", C.POINTER(C.c_double)), ("quad_coef", C.c_double * 10), ("eps", C.c_double),
+                ("max_steps", C.c_int64)]
+
+
+class PatchDesc(C.Structure):
+    _fields_ = [("c", C.c_double * 3), ("n", C.c_double * 3), ("t1", C.c_double * 3), ("h", C.c_double),
+                ("n_theta", C.c_int32), ("n_phi", C.c_int32), ("n_rings", C.c_int32), ("n_sectors", C.c_int32)]
+
+
+assert C.sizeof(PatchDesc) == 96
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it first (python -c "
+                              "'import __graft_entry__ as g; g.build()')")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.dtn_last_error.restype = C.c_char_p
+        L.dtn_version.restype = C.c_char_p
+        L.dtn_create_geometry.argtypes = [C.POINTER(GeometryDesc), C.POINTER(vp)]
+        L.dtn_destroy_geometry.argtypes = [vp]
+        L.dtn_destroy_geometry.restype = None
+        L.dtn_wos_eval.argtypes = [vp, vp, C.c_int64, vp, vp, C.c_uint64, vp, C.c_int32, vp, vp, vp]
+        L.dtn_create_plan.argtypes = [vp, C.POINTER(PatchDesc), C.c_int64, C.POINTER(vp)]
+        L.dtn_destroy_plan.argtypes = [vp]
+        L.dtn_destroy_plan.restype = None
+        L.dtn_plan_num_nodes.argtypes = [vp]
+        L.dtn_plan_num_nodes.restype = C.c_int64
+        L.dtn_plan_num_panels.argtypes = [vp]
+        L.dtn_plan_num_panels.restype = C.c_int64
+        L.dtn_patch_nodes.argtypes = [vp, vp, vp]
+        L.dtn_patch_solve.argtypes = [vp, vp, C.c_int32, vp, vp, vp]
+        L.dtn_potential.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
+        dp = C.POINTER(C.c_double)
+        L.dtn_class_operators.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                          dp, dp, dp, dp, dp, dp]
+        for f in ("dtn_create_geometry", "dtn_wos_eval", "dtn_create_plan", "dtn_patch_nodes",
+                  "dtn_patch_solve", "dtn_potential", "dtn_class_operators"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status, what):
+    if status != DTN_OK:
+        raise DtnError(status, f"{what}: {lib().dtn_last_error().decode()}")
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev_tensor(t, dtype, shape=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def version():
+    return lib().dtn_version().decode()
+
+
+class Geometry:
+    """Domain, Dirichlet data, eps and step cap on the current device."""
+
+    def __init__(self, desc):
+        d = GeometryDesc()
+        d.kind = KIND[desc["kind"]]
+        d.data_kind = DATA[desc["data_kind"]]
+        for k in range(3):
+            d.ball_c[k] = float(desc.get("ball_c", (0, 0, 0))[k])
+            d.box_lo[k] = float(desc.get("box_lo", (0, 0, 0))[k])
+            d.box_hi[k] = float(desc.get("box_hi", (1, 1, 1))[k])
+        d.ball_r = float(desc.get("ball_r", 1.0))
+        self._holes = np.ascontiguousarray(np.asarray(desc.get("holes", np.zeros((0, 6))), np.float64).reshape(-1, 6))
+        self._src = np.ascontiguousarray(np.asarray(desc.get("src", np.zeros((0, 4))), np.float64).reshape(-1, 4))
+        d.n_holes = self._holes.shape[0]
+        d.n_src = self._src.shape[0]
+        d.holes = self._holes.ctypes.data_as(C.POINTER(C.c_double))
+        d.src = self._src.ctypes.data_as(C.POINTER(C.c_double))
+        for k, v in enumerate(desc.get("quad", [0.0] * 10)):
+            d.quad_coef[k] = float(v)
+        d.eps = float(desc["eps"])
+        d.max_steps = int(desc["max_steps"])
+        self.desc = desc
+        self.handle = C.c_void_p()
+        _check(lib().dtn_create_geometry(C.byref(d), C.byref(self.handle)), "dtn_create_geometry")
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.dtn_destroy_geometry(h)
+            self.handle = None
+
+
+def wos_eval(geom, pts, walks, seed, walk_begin=None, stream_id=None, precision="fp64", stats=None,
+             capped=None):
+    """Step 1: node statistics (count, mean, M2, steps) from WOS walks.
+
+    pts [n,3] f64, walks [n] int64, walk_begin [n] int64 or None,
+    stream_id [n] int32 (bit pattern of uint32) or None; all on the device.
+    Returns (stats [n,4] f64, capped [n] int64)."""
+    n = pts.shape[0]
+    _dev_tensor(pts, torch.float64, (n, 3))
+    _dev_tensor(walks, torch.int64, (n,))
+    if walk_begin is not None:
+        _dev_tensor(walk_begin, torch.int64, (n,))
+    if stream_id is not None:
+        _dev_tensor(stream_id, torch.int32, (n,))
+    if stats is None:
+        stats = torch.empty((n, 4), dtype=torch.float64, device=pts.device)
+    if capped is None:
+        capped = torch.empty((n,), dtype=torch.int64, device=pts.device)
+    _check(lib().dtn_wos_eval(geom.handle, _ptr(pts), n, _ptr(walks), _ptr(walk_begin),
+                              C.c_uint64(int(seed) & (2 ** 64 - 1)), _ptr(stream_id), PRECISION[precision],
+                              _ptr(stats), _ptr(capped), _stream()), "dtn_wos_eval")
+    return stats, capped
+
+
+def patches_struct(pdesc):
+    P = len(pdesc["h"])
+    arr = (PatchDesc * P)()
+    for i in range(P):
+        for k in range(3):
+            arr[i].c[k] = float(pdesc["c"][i][k])
+            arr[i].n[k] = float(pdesc["n"][i][k])
+            arr[i].t1[k] = float(pdesc["t1"][i][k])
+        arr[i].h = float(pdesc["h"][i])
+        arr[i].n_theta = int(pdesc["n_theta"][i])
+        arr[i].n_phi = int(pdesc["n_phi"][i])
+        arr[i].n_rings = int(pdesc["n_rings"][i])
+        arr[i].n_sectors = int(pdesc["n_sectors"][i])
+    return arr
+
+
+class Plan:
+    """The patches of a DtN request with their class operators (device)."""
+
+    def __init__(self, geom, pdesc):
+        self.geom = geom
+        arr = patches_struct(pdesc)
+        self.n_patches = len(arr)
+        self.handle = C.c_void_p()
+        _check(lib().dtn_create_plan(geom.handle, arr, len(arr), C.byref(self.handle)), "dtn_create_plan")
+        self.num_nodes = int(lib().dtn_plan_num_nodes(self.handle))
+        self.num_panels = int(lib().dtn_plan_num_panels(self.handle))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.dtn_destroy_plan(h)
+            self.handle = None
+
+    def nodes(self, out=None, device="cuda"):
+        if out is None:
+            out = torch.empty((self.num_nodes, 3), dtype=torch.float64, device=device)
+        _dev_tensor(out, torch.float64, (self.num_nodes, 3))
+        _check(lib().dtn_patch_nodes(self.handle, _ptr(out), _stream()), "dtn_patch_nodes")
+        return out
+
+    def solve(self, node_stats, precision="fp64", neumann=None, neumann_se=None):
+        _dev_tensor(node_stats, torch.float64, (self.num_nodes, 4))
+        dev = node_stats.device
+        if neumann is None:
+            neumann = torch.empty(self.num_panels, dtype=torch.float64, device=dev)
+        if neumann_se is None:
+            neumann_se = torch.empty(self.num_panels, dtype=torch.float64, device=dev)
+        _check(lib().dtn_patch_solve(self.handle, _ptr(node_stats), PRECISION[precision], _ptr(neumann),
+                                     _ptr(neumann_se), _stream()), "dtn_patch_solve")
+        return neumann, neumann_se
+
+    def potential(self, neumann, targets, out=None):
+        m = targets.shape[0]
+        _dev_tensor(neumann, torch.float64, (self.num_panels,))
+        _dev_tensor(targets, torch.float64, (m, 3))
+        if out is None:
+            out = torch.empty(m, dtype=torch.float64, device=targets.device)
+        _check(lib().dtn_potential(self.handle, _ptr(neumann), _ptr(targets), m, _ptr(out), _stream()),
+               "dtn_potential")
+        return out
+
+
+def class_operators(n_theta, n_phi, n_rings, n_sectors, rr=0.0):
+    """Host diagnostic: the class operators the library builds (no device)."""
+    Nn, Np = n_theta * n_phi, n_rings * n_sectors
+    out = {"node_tab": np.empty((Nn, 3)), "col_tab": np.empty((Np, 3)), "K": np.empty((Np, Np)),
+           "QI": np.empty((Np, Nn)), "A2": np.empty((Np, Nn)), "fit": np.empty((16, Np))}
+    dp = C.POINTER(C.c_double)
+    args = [out[k].ctypes.data_as(dp) for k in ("node_tab", "col_tab", "K", "QI", "A2", "fit")]
+    _check(lib().dtn_class_operators(n_theta, n_phi, n_rings, n_sectors, float(rr), *args), "dtn_class_operators")
+    return out

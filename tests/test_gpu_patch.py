@@ -1,0 +1,153 @@
+"""GPU parity of step 2 (collocation solve), the nodes and the potential.
+
+Inputs to both sides come from the oracle or the input generators: node
+values are the exact harmonic u at the oracle's nodes, or the oracle's own
+walk statistics; Neumann data for the potential is the exact du/dn.  The
+deterministic parts then agree to rounding (1e-10 of the data scale); the
+end-to-end Monte Carlo results agree within the propagated standard errors.
+"""
+import numpy as np
+import pytest
+import torch
+
+import dtn_inputs as I
+from oracle import patch as OP
+from oracle import potential as OPOT
+from oracle import wos as OW
+
+pytestmark = pytest.mark.gpu
+
+
+def _dtn():
+    from paper_1210_1491_amd import dtn
+    return dtn
+
+
+CASES = {
+    "ball": (I.geometry_ball_quadratic, I.patches_ball_pole, None),
+    "cube": (I.geometry_cube_sources, I.patches_cube_tiles, I.cube_tile_subset()),
+}
+
+
+def _setup(which):
+    gfun, pfun, sub = CASES[which]
+    gd = gfun()
+    pd = pfun() if sub is None else I.subset_patches(pfun(), sub)
+    return gd, pd, OP.patches_from_desc(pd, gd)
+
+
+@pytest.mark.parametrize("which", ["ball", "cube"])
+def test_nodes_match_oracle(which):
+    dtn = _dtn()
+    gd, pd, ps = _setup(which)
+    print(f"[gpu] nodes {which}", flush=True)
+    plan = dtn.Plan(dtn.Geometry(gd), pd)
+    got = plan.nodes().cpu().numpy()
+    ref = np.concatenate([OP.nodes_global(p)[0] for p in ps])
+    assert got.shape == ref.shape
+    assert np.max(np.abs(got - ref)) < 1e-14
+
+
+def _stats_from_values(u, count, se):
+    """Node statistics rows (count, mean, M2, steps) carrying a given mean and SE."""
+    m2 = se ** 2 * (count - 1) * count
+    return np.column_stack([np.full_like(u, count), u, m2, np.zeros_like(u)])
+
+
+@pytest.mark.parametrize("which", ["ball", "cube"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_solve_matches_oracle_on_exact_node_values(which, precision):
+    dtn = _dtn()
+    gd, pd, ps = _setup(which)
+    og = OW.Geometry(gd)
+    rows, ref_s, ref_se = [], [], []
+    for k, p in enumerate(ps):
+        nodes, _ = OP.nodes_global(p)
+        u = og.phi(nodes)
+        se = 1e-3 * (1.0 + 0.5 * np.sin(np.arange(len(u)) + k))
+        rows.append(_stats_from_values(u, 1e4, se))
+        r = OP.patch_solve(p, og, u, se)
+        ref_s.append(r["sigma"])
+        ref_se.append(r["se"])
+    print(f"[gpu] solve {which} {precision}", flush=True)
+    plan = dtn.Plan(dtn.Geometry(gd), pd)
+    st = torch.tensor(np.concatenate(rows), device="cuda")
+    sig, se = plan.solve(st, precision=precision)
+    torch.cuda.synchronize()
+    sig, se = sig.cpu().numpy(), se.cpu().numpy()
+    ref_s, ref_se = np.concatenate(ref_s), np.concatenate(ref_se)
+    # Both sides integrate the terms of b to ~1e-12 (adaptive rules checked
+    # against refinement); the solve amplifies a difference db by at most
+    # ||K^-1||_inf, so the bar is ||K^-1||_inf * 1e-11.
+    K = OP.single_layer_matrix(ps[0].h, ps[0].R, ps[0].n_rings, ps[0].n_sectors)
+    bar = np.abs(np.linalg.inv(K)).sum(1).max() * 1e-11
+    assert np.max(np.abs(sig - ref_s)) < bar
+    np.testing.assert_allclose(se, ref_se, rtol=1e-8)
+
+
+def test_full_pipeline_ball_matches_oracle_and_exact():
+    dtn = _dtn()
+    gd, pd, ps = _setup("ball")
+    p = ps[0]
+    walks = 10_000
+    print("[gpu] pipeline ball", flush=True)
+    g = dtn.Geometry(gd)
+    plan = dtn.Plan(g, pd)
+    nodes = plan.nodes()
+    W = torch.full((plan.num_nodes,), walks, dtype=torch.int64, device="cuda")
+    stats, _ = dtn.wos_eval(g, nodes, W, seed=1)
+    sig, se = plan.solve(stats)
+    torch.cuda.synchronize()
+    sig, se = sig.cpu().numpy(), se.cpu().numpy()
+    og = OW.Geometry(gd)
+    on, _ = OP.nodes_global(p)
+    orr = OW.wos_nodes(og, on, walks, seed=1)
+    ref = OP.patch_solve(p, og, orr["mean"], orr["se"])
+    # same counters: equal to rounding of the walks
+    assert np.max(np.abs(sig - ref["sigma"])) < 1e-3 * np.max(ref["se"])
+    np.testing.assert_allclose(se, ref["se"], rtol=1e-6)
+    ex = OP.exact_neumann(gd, ref["x"], ref["normal"])
+    trusted = ref["r"] < 0.7 * OP.s_max(p.h, p.R) * p.R
+    err = OP.rel_l2(sig, ex, ref["area"], trusted)
+    assert err < 5e-2, err
+
+
+def test_potential_matches_oracle():
+    dtn = _dtn()
+    gd = I.geometry_cube_sources()
+    pd = I.patches_cube_tiles()
+    ps = OP.patches_from_desc(pd, gd)
+    sig = []
+    for p in ps:
+        xg, ng, _, _ = OP.collocation_points(p)
+        sig.append(OP.exact_neumann(gd, xg, ng))
+    tg = I.cube_targets(500, seed=4)
+    ref = OPOT.potential(ps, sig, OW.Geometry(gd), tg)
+    print("[gpu] potential", flush=True)
+    plan = dtn.Plan(dtn.Geometry(gd), pd)
+    u = plan.potential(torch.tensor(np.concatenate(sig), device="cuda"), torch.tensor(tg, device="cuda"))
+    torch.cuda.synchronize()
+    u = u.cpu().numpy()
+    np.testing.assert_allclose(u, ref, rtol=1e-10, atol=1e-12 * np.max(np.abs(ref)))
+
+
+def test_plan_rejects_bad_patches_and_unsupported_potential():
+    dtn = _dtn()
+    gd = I.geometry_cube_sources()
+    g = dtn.Geometry(gd)
+    pd = I.subset_patches(I.patches_cube_tiles(), [0])
+    bad = {k: v.copy() for k, v in pd.items()}
+    bad["h"][0] = 0.2  # hemisphere leaves the cube face
+    with pytest.raises(dtn.DtnError) as e:
+        dtn.Plan(g, bad)
+    assert e.value.status == -1
+    bad = {k: v.copy() for k, v in pd.items()}
+    bad["n_phi"][0] = 7
+    with pytest.raises(dtn.DtnError):
+        dtn.Plan(g, bad)
+    gb = dtn.Geometry(I.geometry_ball_quadratic())
+    plan = dtn.Plan(gb, I.patches_ball_pole())
+    with pytest.raises(dtn.DtnError) as e:
+        plan.potential(torch.zeros(plan.num_panels, dtype=torch.float64, device="cuda"),
+                       torch.zeros((4, 3), dtype=torch.float64, device="cuda"))
+    assert e.value.status == -4

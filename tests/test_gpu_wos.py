@@ -1,0 +1,159 @@
+"""GPU parity of step 1 (walk on spheres) against the oracle, through the C-ABI.
+
+The same Philox counters drive both sides, so the FP64 path follows the
+oracle walk for walk: node means agree far inside the statistical bar (the
+bar itself is 4 combined standard errors per node), step counts agree as
+integers.  The FP32-mixed path draws the same counters but rounds its
+directions and jumps differently, so only the statistical bar applies.
+"""
+import numpy as np
+import pytest
+import torch
+
+import dtn_inputs as I
+from oracle import patch as OP
+from oracle import wos as OW
+
+pytestmark = pytest.mark.gpu
+
+
+def _dtn():
+    from paper_1210_1491_amd import dtn
+    return dtn
+
+
+def _gpu_wos(desc, pts, walks, seed, precision="fp64", walk_begin=None, stream_id=None):
+    dtn = _dtn()
+    g = dtn.Geometry(desc)
+    dev = torch.device("cuda:0")
+    n = len(pts)
+    P = torch.tensor(np.asarray(pts, np.float64).reshape(n, 3), device=dev)
+    W = torch.tensor(np.broadcast_to(np.asarray(walks, np.int64), (n,)).copy(), device=dev)
+    B = None if walk_begin is None else torch.tensor(np.broadcast_to(np.asarray(walk_begin, np.int64), (n,)).copy(), device=dev)
+    S = None if stream_id is None else torch.tensor(np.asarray(stream_id, np.uint32).view(np.int32), device=dev)
+    print(f"[gpu] wos n={n} seed={seed} precision={precision}", flush=True)
+    stats, capped = dtn.wos_eval(g, P, W, seed, walk_begin=B, stream_id=S, precision=precision)
+    torch.cuda.synchronize()
+    st = stats.cpu().numpy()
+    return {"count": st[:, 0], "mean": st[:, 1], "m2": st[:, 2], "steps": st[:, 3].astype(np.int64),
+            "capped": capped.cpu().numpy()}
+
+
+def _se(r):
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return np.sqrt(r["m2"] / (r["count"] - 1) / r["count"])
+
+
+def _compare(gpu, ora, exact_walks=True):
+    diff = np.abs(gpu["mean"] - ora["mean"])
+    se = np.sqrt(_se(gpu) ** 2 + ora["se"] ** 2)
+    # a point already inside the shell has zero spread on both sides: then
+    # the two means must be equal outright
+    z = np.where(se > 0, diff / np.where(se > 0, se, 1.0), np.where(diff == 0, 0.0, np.inf))
+    assert np.all(z < 4.0), f"max z {z.max()}"
+    np.testing.assert_array_equal(gpu["count"], ora["count"])
+    if exact_walks:
+        # walk-for-walk agreement: means to rounding, steps as integers
+        rel = np.abs(gpu["mean"] - ora["mean"]) / np.maximum(np.abs(ora["mean"]), 1e-300)
+        assert np.median(rel) < 1e-12, np.median(rel)
+        assert np.mean(gpu["steps"] == ora["steps"]) >= 0.99
+    return z
+
+
+def test_fp64_parity_ball_patch_nodes():
+    gd = I.geometry_ball_quadratic()
+    p = OP.patches_from_desc(I.patches_ball_pole(), gd)[0]
+    nodes, _ = OP.nodes_global(p)
+    walks = 10_000
+    gpu = _gpu_wos(gd, nodes, walks, seed=1)
+    ora = OW.wos_nodes(OW.Geometry(gd), nodes, walks, seed=1)
+    _compare(gpu, ora)
+    assert np.all(gpu["capped"] == 0)
+
+
+def test_fp64_parity_cube_sources_ragged():
+    gd = I.geometry_cube_sources()
+    pts = I.interior_points_box(300, 7)
+    walks = np.random.default_rng(3).integers(1, 3000, size=300)  # ragged chunks
+    gpu = _gpu_wos(gd, pts, walks, seed=11)
+    ora = OW.wos_nodes(OW.Geometry(gd), pts, walks, seed=11)
+    _compare(gpu, ora)
+
+
+def test_fp64_parity_box_minus_holes():
+    holes = np.array([[0.2, 0.2, 0.2, 0.45, 0.5, 0.4], [0.6, 0.55, 0.5, 0.8, 0.75, 0.9]])
+    gd = dict(I.geometry_cube_sources(), kind="box_minus_boxes", holes=holes)
+    rng = np.random.default_rng(4)
+    x = rng.random((2000, 3))
+    keep = np.ones(len(x), bool)
+    for h in holes:
+        keep &= ~np.all((x >= h[:3]) & (x <= h[3:]), axis=1)
+    pts = x[keep][:200]
+    gpu = _gpu_wos(gd, pts, 2000, seed=12)
+    ora = OW.wos_nodes(OW.Geometry(gd), pts, 2000, seed=12)
+    _compare(gpu, ora)
+
+
+@pytest.mark.parametrize("which", ["ball", "cube"])
+def test_fp32_mixed_parity(which):
+    if which == "ball":
+        gd = I.geometry_ball_quadratic()
+        pts = I.interior_points_ball(128, 5, r_max=0.97)
+    else:
+        gd = I.geometry_cube_sources()
+        pts = I.interior_points_box(128, 5)
+    gpu = _gpu_wos(gd, pts, 20_000, seed=3, precision="fp32")
+    ora = OW.wos_nodes(OW.Geometry(gd), pts, 20_000, seed=3)
+    _compare(gpu, ora, exact_walks=False)
+    # same number of walks, similar walk lengths
+    assert abs(gpu["steps"].sum() / ora["steps"].sum() - 1) < 0.02
+
+
+def test_edge_cases_empty_zero_walks_shell_and_one_walk():
+    gd = I.geometry_ball_quadratic(eps=1e-3)
+    pts = np.array([[0.0, 0.0, 1.0 - 5e-4], [0.0, 0.5, 0.0], [0.2, 0.0, 0.1], [0.1, 0.1, 0.1]])
+    walks = np.array([10, 0, 1, 65])
+    gpu = _gpu_wos(gd, pts, walks, seed=1)
+    ora = OW.wos_nodes(OW.Geometry(gd), pts, walks, seed=1)
+    np.testing.assert_array_equal(gpu["count"], walks)
+    np.testing.assert_array_equal(gpu["steps"], ora["steps"])
+    assert gpu["steps"][0] == 0 and gpu["m2"][0] == 0.0
+    assert gpu["mean"][1] == 0.0 and gpu["m2"][1] == 0.0
+    assert gpu["m2"][2] == 0.0
+    np.testing.assert_allclose(gpu["mean"], ora["mean"], rtol=1e-12, atol=1e-14)
+    # n = 0 is a no-op
+    dtn = _dtn()
+    g = dtn.Geometry(gd)
+    e = torch.empty((0, 3), dtype=torch.float64, device="cuda")
+    s, c = dtn.wos_eval(g, e, torch.empty(0, dtype=torch.int64, device="cuda"), 1)
+    assert s.shape == (0, 4)
+
+
+def test_step_cap_counts_match_oracle_exactly():
+    gd = I.geometry_cube_sources(max_steps=3)
+    pts = I.interior_points_box(64, 9)
+    gpu = _gpu_wos(gd, pts, 500, seed=2)
+    ora = OW.wos_nodes(OW.Geometry(gd), pts, 500, seed=2)
+    np.testing.assert_array_equal(gpu["capped"], ora["capped"])
+    np.testing.assert_array_equal(gpu["steps"], ora["steps"])
+    assert gpu["capped"].sum() > 0
+
+
+def test_walk_ranges_compose_and_runs_are_deterministic():
+    gd = I.geometry_cube_sources()
+    pts = I.interior_points_box(40, 13)
+    full = _gpu_wos(gd, pts, 4000, seed=5)
+    again = _gpu_wos(gd, pts, 4000, seed=5)
+    for k in ("count", "mean", "m2", "steps"):
+        np.testing.assert_array_equal(full[k], again[k])
+    a = _gpu_wos(gd, pts, 1500, seed=5)
+    b = _gpu_wos(gd, pts, 2500, seed=5, walk_begin=1500)
+    n = a["count"] + b["count"]
+    mean = (a["count"] * a["mean"] + b["count"] * b["mean"]) / n
+    np.testing.assert_allclose(mean, full["mean"], rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(a["steps"] + b["steps"], full["steps"])
+    # a different batch (so a different chunking) gives the same walks
+    big = np.concatenate([pts, I.interior_points_box(3000, 14)])
+    mixed = _gpu_wos(gd, big, 4000, seed=5, stream_id=np.arange(len(big)))
+    np.testing.assert_allclose(mixed["mean"][:40], full["mean"], rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(mixed["steps"][:40], full["steps"])
