@@ -1,0 +1,189 @@
+"""Benchmark of the local DtN hot path on one MI355X.
+
+One step is one pass of the whole path over the unit-cube workload: the
+hemisphere nodes of all 6 x 16 x 16 = 1536 patches (h = 1/32, 16 x 32 nodes
+each, 786,432 nodes), 1e5 walk-on-spheres walks per node (eps = 1e-5, eight
+exterior point sources), the collocation solve for the Neumann data on 64
+panels per patch with propagated standard errors, and the potential at 1e4
+interior targets from the integral representation.
+
+Prints one JSON line.  `value` is walks per second of the whole step; the
+line also carries DtN patches/s, the Neumann error against the exact data
+(which fixes the error level the throughput is quoted at), the ALU roofline
+of the walk kernel and the oracle's CPU throughput on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Full-rate lane-op slots of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+ALU_PEAK = 256 * 4 * 16 * 2.4e9
+# Algorithmic work, in full-rate lane-op slots (a quarter-rate op such as a
+# 32x32->64 multiply or a square root counts 4), per walk step and per walk,
+# for the box domain with point-source data.  The table behind these numbers
+# is in the design notes; it counts what the step definition requires, not
+# what the compiler emits.
+SLOTS_PER_STEP = {"fp64": 111, "fp32": 87}
+SLOTS_PER_WALK = 150
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--walks", type=int, default=100_000)
+    ap.add_argument("--tiles", type=int, default=16, help="tiles per cube edge (16 -> 1536 patches)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-walks", type=int, default=4000, help="walks per node in the CPU sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(gd, pd_all, walks_per_node):
+    """The oracle on a bounded sample: the 16-tile subset of the cube tiling
+    (face centres, edges, corners, 4 seeded tiles), walks_per_node each."""
+    import dtn_inputs as I
+    from oracle import patch as OP
+    from oracle import wos as OW
+
+    sub = I.cube_tile_subset()
+    pd = I.subset_patches(pd_all, sub)
+    ps = OP.patches_from_desc(pd, gd)
+    nodes = np.concatenate([OP.nodes_global(p)[0] for p in ps])
+    g = OW.Geometry(gd)
+    t0 = time.perf_counter()
+    r = OW.wos_nodes(g, nodes, walks_per_node, seed=2)
+    dt = time.perf_counter() - t0
+    walks = float(r["count"].sum())
+    return {"value": walks / dt, "unit": "walks/s", "cores": OW.max_threads(), "kind": "oracle",
+            "sample": f"{len(sub)} tiles x {nodes.shape[0] // len(sub)} nodes x {walks_per_node} walks "
+                      f"({int(walks)} walks, {int(r['steps'].sum())} steps) in {dt:.1f} s",
+            "steps_per_s": float(r["steps"].sum()) / dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the patches are independent; see the design notes for how the path would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import dtn_inputs as I
+    from paper_1210_1491_amd import dtn
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    gd = I.geometry_cube_sources()
+    pd = I.patches_cube_tiles(m=args.tiles)
+    g = dtn.Geometry(gd)
+    plan = dtn.Plan(g, pd)
+    N, Pn = plan.num_nodes, plan.num_panels
+    walks = torch.full((N,), args.walks, dtype=torch.int64, device=dev)
+    targets = torch.tensor(I.cube_targets(), device=dev)
+    nodes = torch.empty((N, 3), dtype=torch.float64, device=dev)
+    stats = torch.empty((N, 4), dtype=torch.float64, device=dev)
+    capped = torch.empty((N,), dtype=torch.int64, device=dev)
+    neumann = torch.empty(Pn, dtype=torch.float64, device=dev)
+    neumann_se = torch.empty(Pn, dtype=torch.float64, device=dev)
+    u = torch.empty(targets.shape[0], dtype=torch.float64, device=dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wos_ms = []
+
+    def step(record):
+        plan.nodes(out=nodes)
+        if record:
+            ev0.record()
+        dtn.wos_eval(g, nodes, walks, seed=2, precision=args.precision, stats=stats, capped=capped)
+        if record:
+            ev1.record()
+        plan.solve(stats, precision=args.precision, neumann=neumann, neumann_se=neumann_se)
+        plan.potential(neumann, targets, out=u)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+        torch.cuda.synchronize()
+        wos_ms.append(ev0.elapsed_time(ev1))
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+
+    st = stats.cpu().numpy()
+    total_walks = float(st[:, 0].sum())
+    total_steps = float(st[:, 3].sum())
+    n_capped = int(capped.sum().item())
+
+    # Neumann error against the exact data (global, area-weighted, panels
+    # within 0.7 h of their patch centre) and the potential error
+    from oracle import patch as OP  # exact data and panel geometry only
+
+    ps = OP.patches_from_desc(pd, gd)
+    sig = neumann.cpu().numpy()
+    sig_se = neumann_se.cpu().numpy()
+    ex, area, trusted = [], [], []
+    for p in ps:
+        xg, ng, ar, r = OP.collocation_points(p)
+        ex.append(OP.exact_neumann(gd, xg, ng))
+        area.append(ar)
+        trusted.append(r < 0.7 * p.h)
+    ex, area, trusted = map(np.concatenate, (ex, area, trusted))
+    rel_l2 = OP.rel_l2(sig, ex, area, trusted)
+    tg = targets.cpu().numpy()
+    from oracle import wos as OW
+
+    u_ex = OW.Geometry(gd).phi(tg)
+    far = np.min(np.minimum(tg, 1 - tg), axis=1) >= 1.0 / 8
+    pot_err = float(np.max(np.abs(u.cpu().numpy()[far] - u_ex[far])) / np.sqrt(np.mean(u_ex ** 2)))
+
+    wos_s = float(np.mean(wos_ms)) / 1e3
+    slots = SLOTS_PER_STEP[args.precision] * total_steps + SLOTS_PER_WALK * total_walks
+    achieved = slots / wos_s
+    value = total_walks / (ms_per_step / 1e3)
+    line = {
+        "metric": "WOS walks/s + DtN patches/s at fixed Neumann error; p50/p99 query latency",
+        "value": value,
+        "unit": "walks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"unit cube, {6 * args.tiles ** 2} patches x {N // len(ps)} nodes x {args.walks} walks, "
+                               f"eps 1e-5, 8 point sources, 64 panels, 1e4 potential targets",
+                   "patches": len(ps), "nodes": N, "walks_per_node": args.walks, "precision": args.precision},
+        "patches_per_s": len(ps) / (ms_per_step / 1e3),
+        "neumann_rel_l2_vs_exact": rel_l2,
+        "neumann_se_median": float(np.median(sig_se)),
+        "potential_max_err_far": pot_err,
+        "steps_per_walk": total_steps / total_walks,
+        "walk_steps_per_s": total_steps / (ms_per_step / 1e3),
+        "capped_walks": n_capped,
+        "wos_kernel_ms": float(np.mean(wos_ms)),
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK / 1e12,
+                     "unit": "TOP/s (full-rate lane-op slots)", "frac": achieved / ALU_PEAK,
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(gd, pd, args.cpu_walks)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -105,8 +105,11 @@ def test_fp32_mixed_parity(which):
     gpu = _gpu_wos(gd, pts, 20_000, seed=3, precision="fp32")
     ora = OW.wos_nodes(OW.Geometry(gd), pts, 20_000, seed=3)
     _compare(gpu, ora, exact_walks=False)
-    # same number of walks, similar walk lengths
-    assert abs(gpu["steps"].sum() / ora["steps"].sum() - 1) < 0.02
+    # same number of walks; the FP32 path shrinks each jump by the FP32
+    # distance error bound (so a walk never leaves the domain), which costs a
+    # few extra steps near the boundary but keeps the estimate unbiased
+    ratio = gpu["steps"].sum() / ora["steps"].sum()
+    assert 1.0 <= ratio < 1.06, ratio
 
 
 def test_edge_cases_empty_zero_walks_shell_and_one_walk():
