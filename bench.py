@@ -31,8 +31,8 @@ ALU_PEAK = 256 * 4 * 16 * 2.4e9
 # for the box domain with point-source data.  The table behind these numbers
 # is in the design notes; it counts what the step definition requires, not
 # what the compiler emits.
-SLOTS_PER_STEP = {"fp64": 111, "fp32": 87}
-SLOTS_PER_WALK = 150
+SLOTS_PER_STEP = {"fp64": 108, "fp32": 87}
+SLOTS_PER_WALK = 158
 
 
 def parse():
@@ -44,7 +44,9 @@ def parse():
     ap.add_argument("--walks", type=int, default=100_000)
     ap.add_argument("--tiles", type=int, default=16, help="tiles per cube edge (16 -> 1536 patches)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-walks", type=int, default=4000, help="walks per node in the CPU sample")
+    ap.add_argument("--cpu-walks", type=int, default=40000, help="walks per node in the CPU sample")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run a plain device copy of this size first (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -110,6 +112,12 @@ def main():
         plan.solve(stats, precision=args.precision, neumann=neumann, neumann_se=neumann_se)
         plan.potential(neumann, targets, out=u)
 
+    if args.copy_probe_mib > 0:
+        a = torch.empty(args.copy_probe_mib * 2 ** 17, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
