@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--walks", type=int, default=100_000)
     ap.add_argument("--tiles", type=int, default=16, help="tiles per cube edge (16 -> 1536 patches)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the other precision's run")
     ap.add_argument("--cpu-walks", type=int, default=40000, help="walks per node in the CPU sample")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (reference for HBM counters)")
@@ -99,48 +100,10 @@ def main():
     neumann = torch.empty(Pn, dtype=torch.float64, device=dev)
     neumann_se = torch.empty(Pn, dtype=torch.float64, device=dev)
     u = torch.empty(targets.shape[0], dtype=torch.float64, device=dev)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    wos_ms = []
-
-    def step(record):
-        plan.nodes(out=nodes)
-        if record:
-            ev0.record()
-        dtn.wos_eval(g, nodes, walks, seed=2, precision=args.precision, stats=stats, capped=capped)
-        if record:
-            ev1.record()
-        plan.solve(stats, precision=args.precision, neumann=neumann, neumann_se=neumann_se)
-        plan.potential(neumann, targets, out=u)
-
-    if args.copy_probe_mib > 0:
-        a = torch.empty(args.copy_probe_mib * 2 ** 17, dtype=torch.float64, device=dev).fill_(1.0)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(True)
-        torch.cuda.synchronize()
-        wos_ms.append(ev0.elapsed_time(ev1))
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-
-    st = stats.cpu().numpy()
-    total_walks = float(st[:, 0].sum())
-    total_steps = float(st[:, 3].sum())
-    n_capped = int(capped.sum().item())
-
-    # Neumann error against the exact data (global, area-weighted, panels
-    # within 0.7 h of their patch centre) and the potential error
     from oracle import patch as OP  # exact data and panel geometry only
+    from oracle import wos as OW
 
     ps = OP.patches_from_desc(pd, gd)
-    sig = neumann.cpu().numpy()
-    sig_se = neumann_se.cpu().numpy()
     ex, area, trusted = [], [], []
     for p in ps:
         xg, ng, ar, r = OP.collocation_points(p)
@@ -148,18 +111,65 @@ def main():
         area.append(ar)
         trusted.append(r < 0.7 * p.h)
     ex, area, trusted = map(np.concatenate, (ex, area, trusted))
-    rel_l2 = OP.rel_l2(sig, ex, area, trusted)
     tg = targets.cpu().numpy()
-    from oracle import wos as OW
-
     u_ex = OW.Geometry(gd).phi(tg)
     far = np.min(np.minimum(tg, 1 - tg), axis=1) >= 1.0 / 8
-    pot_err = float(np.max(np.abs(u.cpu().numpy()[far] - u_ex[far])) / np.sqrt(np.mean(u_ex ** 2)))
 
-    wos_s = float(np.mean(wos_ms)) / 1e3
-    slots = SLOTS_PER_STEP[args.precision] * total_steps + SLOTS_PER_WALK * total_walks
-    achieved = slots / wos_s
-    value = total_walks / (ms_per_step / 1e3)
+    if args.copy_probe_mib > 0:
+        a = torch.empty(args.copy_probe_mib * 2 ** 17, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    def measure(precision, steps, warmup):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        wos_ms = []
+
+        def step(record):
+            plan.nodes(out=nodes)
+            if record:
+                ev0.record()
+            dtn.wos_eval(g, nodes, walks, seed=2, precision=precision, stats=stats, capped=capped)
+            if record:
+                ev1.record()
+            plan.solve(stats, precision=precision, neumann=neumann, neumann_se=neumann_se)
+            plan.potential(neumann, targets, out=u)
+
+        for _ in range(warmup):
+            step(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(True)
+            torch.cuda.synchronize()
+            wos_ms.append(ev0.elapsed_time(ev1))
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        st = stats.cpu().numpy()
+        walks_n, steps_n = float(st[:, 0].sum()), float(st[:, 3].sum())
+        wos_s = float(np.mean(wos_ms)) / 1e3
+        slots = SLOTS_PER_STEP[precision] * steps_n + SLOTS_PER_WALK * walks_n
+        sig = neumann.cpu().numpy()
+        return {"ms_per_step": ms, "walks_per_s": walks_n / (ms / 1e3), "patches_per_s": len(ps) / (ms / 1e3),
+                "neumann_rel_l2_vs_exact": OP.rel_l2(sig, ex, area, trusted),
+                "neumann_se_median": float(np.median(neumann_se.cpu().numpy())),
+                "potential_max_err_far": float(np.max(np.abs(u.cpu().numpy()[far] - u_ex[far]))
+                                               / np.sqrt(np.mean(u_ex ** 2))),
+                "steps_per_walk": steps_n / walks_n, "walk_steps_per_s": steps_n / (ms / 1e3),
+                "capped_walks": int(capped.sum().item()), "wos_kernel_ms": float(np.mean(wos_ms)),
+                "alu_achieved": slots / wos_s, "total_walks": walks_n}
+
+    m = measure(args.precision, args.steps, args.warmup)
+    variants = {}
+    if not args.no_variants:
+        other = "fp32" if args.precision == "fp64" else "fp64"
+        v = measure(other, 1, 0)
+        variants[other] = {k: v[k] for k in ("walks_per_s", "patches_per_s", "neumann_rel_l2_vs_exact",
+                                              "neumann_se_median", "steps_per_walk", "wos_kernel_ms")}
+        variants[other]["alu_frac"] = v["alu_achieved"] / ALU_PEAK
+    ms_per_step = m["ms_per_step"]
+    achieved = m["alu_achieved"]
+    value = m["walks_per_s"]
     line = {
         "metric": "WOS walks/s + DtN patches/s at fixed Neumann error; p50/p99 query latency",
         "value": value,
@@ -176,17 +186,18 @@ def main():
         "config": {"workload": f"unit cube, {6 * args.tiles ** 2} patches x {N // len(ps)} nodes x {args.walks} walks, "
                                f"eps 1e-5, 8 point sources, 64 panels, 1e4 potential targets",
                    "patches": len(ps), "nodes": N, "walks_per_node": args.walks, "precision": args.precision},
-        "patches_per_s": len(ps) / (ms_per_step / 1e3),
-        "neumann_rel_l2_vs_exact": rel_l2,
-        "neumann_se_median": float(np.median(sig_se)),
-        "potential_max_err_far": pot_err,
-        "steps_per_walk": total_steps / total_walks,
-        "walk_steps_per_s": total_steps / (ms_per_step / 1e3),
-        "capped_walks": n_capped,
-        "wos_kernel_ms": float(np.mean(wos_ms)),
+        "patches_per_s": m["patches_per_s"],
+        "neumann_rel_l2_vs_exact": m["neumann_rel_l2_vs_exact"],
+        "neumann_se_median": m["neumann_se_median"],
+        "potential_max_err_far": m["potential_max_err_far"],
+        "steps_per_walk": m["steps_per_walk"],
+        "walk_steps_per_s": m["walk_steps_per_s"],
+        "capped_walks": m["capped_walks"],
+        "wos_kernel_ms": m["wos_kernel_ms"],
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK / 1e12,
                      "unit": "TOP/s (full-rate lane-op slots)", "frac": achieved / ALU_PEAK,
                      "traffic": None},
+        "variants": variants,
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(gd, pd, args.cpu_walks)

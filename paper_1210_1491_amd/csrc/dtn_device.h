@@ -20,6 +20,13 @@ struct Philox4 {
     uint32_t x, y, z, w;
 };
 
+// Three-input XOR in one VALU op: v_bitop3_b32 with truth table 0x96
+// (a ^ b ^ c); the compiler does not form it from C xors here.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                  uint32_t k0, uint32_t k1)
 {
@@ -27,8 +34,8 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -44,6 +51,64 @@ __device__ __forceinline__ double u01_f64(uint32_t k) { return fma((double)k, 0x
 // FP32 uniform in (0,1): ((k >> 8) + 1/2) 2^-24, exact.
 __device__ __forceinline__ float u01_f32(uint32_t k) { return fmaf((float)(k >> 8), 0x1p-24f, 0x1p-25f); }
 
+// ---------------------------------------------------------------- sin, cos
+// sin and cos of 2 pi u for u in (0,1).  The quarter-turn reduction is done
+// on 4u, where it is exact (q = nearest integer, f = 4u - q in [-1/2, 1/2]),
+// so no large-argument path is needed; sin and cos of r = f pi/2 in
+// [-pi/4, pi/4] come from their Taylor series to degree 17 and 18 (the first
+// omitted terms are below 1e-19), evaluated by Horner's rule in r^2.
+__device__ __forceinline__ void sincos_2pi_f64(double u, double &s, double &c)
+{
+    const double t = 4.0 * u;
+    const double q = floor(t + 0.5);
+    const double r = (t - q) * 1.5707963267948966;
+    const double x2 = r * r;
+    double ps = 1.0 / 355687428096000.0;
+    ps = fma(ps, x2, -1.0 / 1307674368000.0);
+    ps = fma(ps, x2, 1.0 / 6227020800.0);
+    ps = fma(ps, x2, -1.0 / 39916800.0);
+    ps = fma(ps, x2, 1.0 / 362880.0);
+    ps = fma(ps, x2, -1.0 / 5040.0);
+    ps = fma(ps, x2, 1.0 / 120.0);
+    ps = fma(ps, x2, -1.0 / 6.0);
+    const double sr = fma(ps * x2, r, r);
+    double pc = 1.0 / 6402373705728000.0;
+    pc = fma(pc, x2, -1.0 / 20922789888000.0);
+    pc = fma(pc, x2, 1.0 / 87178291200.0);
+    pc = fma(pc, x2, -1.0 / 479001600.0);
+    pc = fma(pc, x2, 1.0 / 3628800.0);
+    pc = fma(pc, x2, -1.0 / 40320.0);
+    pc = fma(pc, x2, 1.0 / 720.0);
+    pc = fma(pc, x2, -1.0 / 24.0);
+    pc = fma(pc, x2, 0.5);
+    const double cr = fma(-pc, x2, 1.0);
+    const int qi = (int)q & 3;
+    const double a = (qi & 1) ? cr : sr;
+    const double b = (qi & 1) ? sr : cr;
+    s = (qi & 2) ? -a : a;
+    c = ((qi + 1) & 2) ? -b : b;
+}
+
+// --------------------------------------------------- square roots (FP64)
+// 1/sqrt(x) and sqrt(x) for normal positive x: the hardware reciprocal
+// square root refined by two Newton steps (quadratic convergence), and
+// sqrt(x) = x/sqrt(x) with one residual correction.  Within 1-2 ulp, about
+// half the instructions of the correctly rounded library sqrt.
+__device__ __forceinline__ double rsqrt_f64(double x)
+{
+    double r = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    r = fma(r, fma(-hx * r, r, 0.5), r);
+    r = fma(r, fma(-hx * r, r, 0.5), r);
+    return r;
+}
+__device__ __forceinline__ double sqrt_f64(double x)
+{
+    const double r = rsqrt_f64(x);
+    const double y = x * r;
+    return fma(fma(-y, y, x), 0.5 * r, y);
+}
+
 // ------------------------------------------------------------- Dirichlet data
 
 template <int DATA>
@@ -58,7 +123,7 @@ __device__ __forceinline__ double phi_eval(const DevGeom &g, double x, double y,
         for (int k = 0; k < g.n_src; ++k) {
             const double *q = g.src + 4 * k;
             const double dx = x - q[0], dy = y - q[1], dz = z - q[2];
-            s += q[3] / sqrt(dx * dx + dy * dy + dz * dz);
+            s = fma(q[3], rsqrt_f64(dx * dx + dy * dy + dz * dz), s);
         }
         return s;
     }
@@ -73,7 +138,7 @@ __device__ __forceinline__ double dist_f64(const DevGeom &g, double x, double y,
 {
     if constexpr (KIND == DTN_BALL) {
         const double dx = x - g.c[0], dy = y - g.c[1], dz = z - g.c[2];
-        return g.r - sqrt(dx * dx + dy * dy + dz * dz);
+        return g.r - sqrt_f64(dx * dx + dy * dy + dz * dz);
     } else {
         double d = fmin(fmin(fmin(x - g.lo[0], g.hi[0] - x), fmin(y - g.lo[1], g.hi[1] - y)),
                         fmin(z - g.lo[2], g.hi[2] - z));
@@ -95,7 +160,7 @@ __device__ __forceinline__ float dist_f32(const DevGeom &g, float x, float y, fl
 {
     if constexpr (KIND == DTN_BALL) {
         const float dx = x - (float)g.c[0], dy = y - (float)g.c[1], dz = z - (float)g.c[2];
-        return (float)g.r - sqrtf(dx * dx + dy * dy + dz * dz);
+        return (float)g.r - __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
     } else {
         float d = fminf(fminf(fminf(x - (float)g.lo[0], (float)g.hi[0] - x),
                               fminf(y - (float)g.lo[1], (float)g.hi[1] - y)),
@@ -106,7 +171,7 @@ __device__ __forceinline__ float dist_f32(const DevGeom &g, float x, float y, fl
                 const float qx = fmaxf(fabsf(x - (float)h[0]) - (float)h[3], 0.0f);
                 const float qy = fmaxf(fabsf(y - (float)h[1]) - (float)h[4], 0.0f);
                 const float qz = fmaxf(fabsf(z - (float)h[2]) - (float)h[5], 0.0f);
-                d = fminf(d, sqrtf(qx * qx + qy * qy + qz * qz));
+                d = fminf(d, __builtin_amdgcn_sqrtf(qx * qx + qy * qy + qz * qz));
             }
         }
         return d;

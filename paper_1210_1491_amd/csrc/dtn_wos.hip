@@ -203,9 +203,9 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                         capped += (d >= eps) ? 1ull : 0ull;
                     } else {
                         const double cz = 1.0 - 2.0 * u1d;
-                        const double sr = 2.0 * sqrt(u1d * (1.0 - u1d));
+                        const double sr = 2.0 * sqrt_f64(u1d * (1.0 - u1d));
                         double sn, cs;
-                        sincos(2.0 * M_PI * u2d, &sn, &cs);
+                        sincos_2pi_f64(u2d, sn, cs);
                         x += d * (sr * cs);
                         y += d * (sr * sn);
                         z += d * cz;
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                         capped += stop ? 0ull : 1ull;
                     } else {
                         const float cz = 1.0f - 2.0f * u1f;
-                        const float sr = 2.0f * __builtin_sqrtf(u1f * (1.0f - u1f));
+                        const float sr = 2.0f * __builtin_amdgcn_sqrtf(u1f * (1.0f - u1f));
                         const float cs = __builtin_amdgcn_cosf(u2f);  // cos(2 pi u2)
                         const float sn = __builtin_amdgcn_sinf(u2f);  // sin(2 pi u2)
                         x += d * (double)(sr * cs);
