@@ -13,9 +13,9 @@
 //   k_wos_walk      one wave per chunk (point, walk range of <= C walks); the
 //                   wave runs its walks with refill: a lane whose walk ends takes
 //                   the next walk of the chunk, so lanes do not idle behind
-//                   long walks.  Exit points are queued in LDS and scored 64
-//                   at a time by the whole wave, so the scoring code runs
-//                   with full lanes.  Per-lane compensated FP64 sums are
+//                   long walks.  Absorbed positions are queued in LDS and
+//                   projected and scored 64 at a time by the whole wave, so
+//                   that code runs with full lanes.  Per-lane compensated FP64 sums are
 //                   reduced across the wave and written per chunk.
 //   k_wos_finalize  per point: merge its chunks in chunk order (fixed
 //                   order, so results do not depend on which wave ran which
@@ -237,7 +237,6 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
             const uint64_t fm = __ballot(fin);
             if (fm) {
                 if (fin) {
-                    project_f64<KIND>(g, x, y, z);
                     const int slot = qn + rank_below(fm);
                     q[3 * slot] = x;
                     q[3 * slot + 1] = y;
@@ -248,7 +247,9 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                 qn += __popcll(fm);
                 if (qn >= kWave) {
                     wave_sync();
-                    const double v = phi_eval<DATA>(g, q[3 * lane], q[3 * lane + 1], q[3 * lane + 2]) - shift;
+                    double px = q[3 * lane], py = q[3 * lane + 1], pz = q[3 * lane + 2];
+                    project_f64<KIND>(g, px, py, pz);
+                    const double v = phi_eval<DATA>(g, px, py, pz) - shift;
                     kadd(s1, v);
                     kadd(s2, v * v);
                     const int rest = qn - kWave;
@@ -272,7 +273,9 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
         // score what is left in the queue
         wave_sync();
         if (lane < qn) {
-            const double v = phi_eval<DATA>(g, q[3 * lane], q[3 * lane + 1], q[3 * lane + 2]) - shift;
+            double px = q[3 * lane], py = q[3 * lane + 1], pz = q[3 * lane + 2];
+            project_f64<KIND>(g, px, py, pz);
+            const double v = phi_eval<DATA>(g, px, py, pz) - shift;
             kadd(s1, v);
             kadd(s2, v * v);
         }
