@@ -145,6 +145,133 @@ def cube_targets(n=10_000, seed=2):
     return rng.random((n, 3))
 
 
+# ----------------------------------------------- box minus holes (uneven batches)
+
+
+def box_holes(seed=4, n_holes=20, size=4.0, side=(0.2, 0.8), gap=0.1, max_tries=100_000):
+    """Axis-aligned holes in the box [0,size]^3: independent sides ~U(side),
+    placed by rejection at least `gap` from the outer box and separated from
+    every other hole by at least `gap` along some axis.  Rows are
+    (lo x,y,z, hi x,y,z)."""
+    rng = np.random.default_rng(seed)
+    holes = []
+    tries = 0
+    while len(holes) < n_holes:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("could not place the holes")
+        e = rng.uniform(side[0], side[1], size=3)
+        lo = gap + rng.random(3) * (size - 2 * gap - e)
+        hi = lo + e
+        ok = True
+        for h in holes:
+            if not (np.any(lo >= h[3:] + gap) or np.any(hi <= h[:3] - gap)):
+                ok = False
+                break
+        if ok:
+            holes.append(np.concatenate([lo, hi]))
+    return np.array(holes)
+
+
+def hole_sources(holes, seed=4):
+    """One source per hole, uniform in the hole's central half (a quarter of
+    each side inset), charge ~N(0,1).  Rows are (x, y, z, q)."""
+    rng = np.random.default_rng([seed, 7])
+    lo, hi = holes[:, :3], holes[:, 3:]
+    s = lo + (hi - lo) * (0.25 + 0.5 * rng.random(lo.shape))
+    q = rng.standard_normal(len(holes))
+    return np.ascontiguousarray(np.column_stack([s, q]))
+
+
+def geometry_box_holes(seed=4, eps=1e-5, max_steps=1_000_000):
+    """[0,4]^3 minus 20 holes, u = sum_i q_i / |x - s_i|, one source in each hole."""
+    holes = box_holes(seed)
+    return {"kind": "box_minus_boxes", "box_lo": (0.0, 0.0, 0.0), "box_hi": (4.0, 4.0, 4.0),
+            "data_kind": "sources", "quad": [0.0] * 10, "src": hole_sources(holes, seed),
+            "holes": holes, "eps": eps, "max_steps": max_steps}
+
+
+# panel classes: panels -> (n_theta, n_phi, n_rings, n_sectors)
+PANEL_CLASSES = {8: (4, 8, 2, 4), 16: (6, 12, 2, 8), 32: (8, 16, 4, 8), 64: (16, 32, 4, 16), 128: (16, 32, 8, 16)}
+
+
+def _box_point_dist(c, lo, hi):
+    q = np.maximum(np.maximum(lo - c, 0.0), c - hi)
+    return float(np.sqrt(np.sum(q * q)))
+
+
+def patches_box_holes(gd, alpha=0.145, panels_per_area=4000.0):
+    """Tiles over every face of the outer box and of the holes, one patch per
+    tile.  Patch sizes follow the face areas: a face of sides a x b is split
+    into round(a/s) x round(b/s) tiles with s = alpha sqrt(ab), so small hole
+    faces get small patches and the large outer faces large ones.  Each patch
+    is centred on its tile with h = the smallest of half the shorter tile
+    side, the distance to the face's edges and the clearance to every other
+    surface (so each half ball stays in the domain).  Panels follow the tile
+    area (panels_per_area per unit area), rounded to a class in
+    {8, 16, 32, 64, 128}."""
+    lo_b, hi_b = np.asarray(gd["box_lo"], float), np.asarray(gd["box_hi"], float)
+    holes = np.asarray(gd["holes"], float).reshape(-1, 6)
+    faces = []  # (axis, plane, sign of the outward normal of the domain, rect lo, rect hi, owner)
+    for k in range(3):
+        for sgn, plane in ((-1.0, lo_b[k]), (1.0, hi_b[k])):
+            faces.append((k, plane, sgn, lo_b, hi_b, -1))
+    for i, h in enumerate(holes):
+        for k in range(3):
+            # the domain lies outside the hole: its outward normal points into the hole
+            faces.append((k, h[k], 1.0, h[:3], h[3:], i))
+            faces.append((k, h[3 + k], -1.0, h[:3], h[3:], i))
+    rows = []
+    classes = np.array(sorted(PANEL_CLASSES))
+    for (k, plane, sgn, rlo, rhi, owner) in faces:
+        a, b = (k + 1) % 3, (k + 2) % 3
+        la, lb = rhi[a] - rlo[a], rhi[b] - rlo[b]
+        tile = alpha * np.sqrt(la * lb)
+        na, nb = max(1, int(round(la / tile))), max(1, int(round(lb / tile)))
+        da, db = la / na, lb / nb
+        for i in range(na):
+            for j in range(nb):
+                c = np.zeros(3)
+                c[k] = plane
+                c[a] = rlo[a] + (i + 0.5) * da
+                c[b] = rlo[b] + (j + 0.5) * db
+                edge = min(c[a] - rlo[a], rhi[a] - c[a], c[b] - rlo[b], rhi[b] - c[b])
+                clear = np.inf
+                for k2 in range(3):
+                    for p2 in (lo_b[k2], hi_b[k2]):
+                        if owner == -1 and k2 == k and p2 == plane:
+                            continue
+                        clear = min(clear, abs(c[k2] - p2))
+                for i2, h2 in enumerate(holes):
+                    if i2 != owner:
+                        clear = min(clear, _box_point_dist(c, h2[:3], h2[3:]))
+                h = min(0.5 * min(da, db), edge, clear)
+                want = panels_per_area * da * db
+                P = int(classes[np.argmin(np.abs(np.log(classes / want)))])
+                n = np.zeros(3)
+                n[k] = sgn
+                t1 = np.zeros(3)
+                t1[a] = 1.0
+                rows.append((c, n, t1, h, P))
+    p = _empty_patches(len(rows))
+    for idx, (c, n, t1, h, P) in enumerate(rows):
+        p["c"][idx], p["n"][idx], p["t1"][idx], p["h"][idx] = c, n, t1, h
+        p["n_theta"][idx], p["n_phi"][idx], p["n_rings"][idx], p["n_sectors"][idx] = PANEL_CLASSES[P]
+    return p
+
+
+def box_holes_sample(pd, per_class=2, seed=4):
+    """Seeded sample of patch indices, ``per_class`` from every panel class
+    present (for tests that compare against the oracle)."""
+    rng = np.random.default_rng([seed, 11])
+    P = np.asarray(pd["n_rings"]) * np.asarray(pd["n_sectors"])
+    out = []
+    for c in sorted(set(P.tolist())):
+        idx = np.flatnonzero(P == c)
+        out.extend(rng.choice(idx, min(per_class, len(idx)), replace=False).tolist())
+    return np.array(sorted(out), dtype=np.int64)
+
+
 # ----------------------------------------------------------------- configs
 
 CONFIGS = {
@@ -153,6 +280,15 @@ CONFIGS = {
         "patches": patches_ball_pole,
         "walks": 10_000,
         "seed": 1,
+    },
+    "box_holes": {  # [0,4]^3 minus 20 holes, ~6000 uneven patches, adaptive walks
+        "geometry": geometry_box_holes,
+        "patches": patches_box_holes,
+        "se_target": 1e-3,
+        "pilot_walks": 1000,
+        "min_walks": 1000,
+        "max_walks": 200_000,
+        "seed": 4,
     },
     "cube_1536": {  # unit cube, 6 x 16 x 16 patches, FP64
         "geometry": geometry_cube_sources,

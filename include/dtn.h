@@ -149,6 +149,60 @@ dtn_status dtn_wos_eval(dtn_geometry g, const double *pts, int64_t n, const int6
                         const int64_t *walk_begin, uint64_t seed, const uint32_t *stream_id,
                         int32_t precision, double *stats, int64_t *capped, void *stream);
 
+/* Work schedule of the walk kernels.  The walks of all points form one work
+ * list of chunks (point, first walk, walk count), one wave per chunk, in a
+ * single launch; the chunk size is C = max(min_chunk, ceil(total walks /
+ * (resident waves x oversub))), so a launch has at most n + resident waves x
+ * oversub chunks.  Results do not depend on the schedule except for the
+ * rounding of the sums (a walk's path is fixed by its counter).
+ *   min_chunk  smallest chunk, >= 1 (default 512)
+ *   oversub    chunks per resident wave slot, 1..64 (default 4)
+ *   reserved   must be 0 */
+typedef struct {
+    int64_t min_chunk;
+    int32_t oversub;
+    int32_t reserved;
+} dtn_schedule;
+
+/* Adaptive walk budget per point: a pilot of pilot_walks walks estimates the
+ * variance s^2 of the scores; the point then gets clamp(ceil(s^2 /
+ * se_target^2), min_walks, max_walks) walks in all (never fewer than the
+ * pilot), so that its standard error sqrt(s^2 / n) (the error of the node
+ * estimate of eq. bw87) meets se_target where the clamp allows.
+ *   pilot_walks >= 2; 1 <= min_walks <= max_walks <= 2^40; se_target > 0 */
+typedef struct {
+    int64_t pilot_walks;
+    int64_t min_walks;
+    int64_t max_walks;
+    double se_target;
+} dtn_adaptive;
+
+/* Step 1 with adaptive walk counts (see dtn_adaptive), all on the device:
+ * the pilot walks of every point in one launch, the budgets, then the
+ * remaining walks of every point in one launch over the uneven work list
+ * (walks [pilot, total) of each point), and a merge of the two statistics.
+ * The result equals dtn_wos_eval over walks [0, walks_used) up to rounding.
+ *   sched      NULL for the default schedule
+ *   stats      device [n][4] out as for dtn_wos_eval, over all walks
+ *   walks_used device [n] out (int64): total walks of each point
+ *   capped     device [n] out (int64) or NULL
+ * Other arguments as for dtn_wos_eval.  Errors: DTN_E_ARG for a budget or
+ * schedule outside the ranges above, and as dtn_wos_eval. */
+dtn_status dtn_wos_adaptive(dtn_geometry g, const double *pts, int64_t n, const dtn_adaptive *budget,
+                            uint64_t seed, const uint32_t *stream_id, int32_t precision,
+                            const dtn_schedule *sched, double *stats, int64_t *walks_used, int64_t *capped,
+                            void *stream);
+
+/* Autotuning support: runs dtn_wos_eval's work (same arguments) once per
+ * candidate schedule, `reps` times each after one untimed run, and writes the
+ * mean device time per run in milliseconds to ms_out[n_cands] (host).  Blocks
+ * until the stream has finished.  stats receives the last run's result.
+ * Errors: DTN_E_ARG for n_cands < 1, reps < 1 or an invalid candidate. */
+dtn_status dtn_wos_time_schedules(dtn_geometry g, const double *pts, int64_t n, const int64_t *walks,
+                                  const int64_t *walk_begin, uint64_t seed, const uint32_t *stream_id,
+                                  int32_t precision, const dtn_schedule *cands, int32_t n_cands, int32_t reps,
+                                  double *stats, float *ms_out, void *stream);
+
 /* A plan holds the patches of a DtN request and, per class of congruent
  * patches, the collocation operators of step 2: the single-layer matrix K
  * (eq. bw50) and its LU factors, the Gamma operator (Poisson kernel against

@@ -159,6 +159,34 @@ def wos_nodes(geom, pts, walks, seed, stream_id=None, walk_begin=None, threads=0
     return {"count": count, "mean": mean, "m2": m2, "steps": steps, "capped": capped, "se": se}
 
 
+def wos_adaptive(geom, pts, pilot_walks, min_walks, max_walks, se_target, seed, stream_id=None, threads=0):
+    """Node statistics with an adaptive walk count per node.
+
+    The standard error of the node estimate (eq. bw87) is sqrt(var / n).  A
+    pilot of ``pilot_walks`` walks estimates var (unbiased); the node then
+    gets n = clamp(ceil(var / se_target^2), min_walks, max_walks) walks in
+    all, never fewer than the pilot, and the statistics are those of walks
+    [0, n) of the node, in one pass.  Returns wos_nodes' dict plus
+    ``walks_used``.
+    """
+    pts = np.ascontiguousarray(np.asarray(pts, dtype=np.float64).reshape(-1, 3))
+    pilot = wos_nodes(geom, pts, pilot_walks, seed, stream_id=stream_id, threads=threads)
+    var = np.where(pilot["count"] > 1, pilot["m2"] / (pilot["count"] - 1.0), 0.0)
+    want = np.ceil(var / (float(se_target) * float(se_target)))
+    total = np.empty(pts.shape[0], dtype=np.int64)
+    for i, w in enumerate(want):
+        if not (w < max_walks):
+            total[i] = max_walks
+        elif w <= min_walks:
+            total[i] = min_walks
+        else:
+            total[i] = int(w)
+    total = np.maximum(total, int(pilot_walks))
+    r = wos_nodes(geom, pts, total, seed, stream_id=stream_id, threads=threads)
+    r["walks_used"] = total
+    return r
+
+
 def wos_scores(geom, y, seed, stream_id, walk_begin, n_walks):
     """Per-walk recorded phi and step counts from one start point."""
     y = np.ascontiguousarray(np.asarray(y, dtype=np.float64).reshape(3))

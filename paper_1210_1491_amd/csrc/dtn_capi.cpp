@@ -260,16 +260,21 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
                 ce[6 * i + 3 + k] = 0.5 * (h[3 + k] - h[k]);
             }
         }
+        std::vector<float> ce32(8 * (size_t)nh, 0.0f);
+        for (int i = 0; i < nh; ++i)
+            for (int k = 0; k < 6; ++k) ce32[8 * i + k] = (float)ce[6 * i + k];
         const int ns = d.data_kind == DTN_DATA_POINT_SOURCES ? d.n_src : 0;
         g.dev.n_src = ns;
         if (ns) g.src.assign(d.src, d.src + 4 * ns);
         hipError_t e = hipGetDevice(&g.device);
         if (e == hipSuccess) e = upload(ce, &g.d_hole_ce);
         if (e == hipSuccess) e = upload(g.holes, &g.d_hole_box);
+        if (e == hipSuccess) e = upload(ce32, &g.d_hole_f32);
         if (e == hipSuccess) e = upload(g.src, &g.d_src);
         if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_create_geometry: ") + hipGetErrorString(e));
         g.dev.hole_ce = g.d_hole_ce;
         g.dev.hole_box = g.d_hole_box;
+        g.dev.hole_f32 = g.d_hole_f32;
         g.dev.src = g.d_src;
         // keep stream-ordered scratch in the pool between calls
         hipMemPool_t pool;
@@ -289,6 +294,7 @@ void dtn_destroy_geometry(dtn_geometry g)
     if (!g) return;
     hipFree(g->g.d_hole_ce);
     hipFree(g->g.d_hole_box);
+    hipFree(g->g.d_hole_f32);
     hipFree(g->g.d_src);
     delete g;
 }
@@ -304,10 +310,109 @@ dtn_status dtn_wos_eval(dtn_geometry g, const double *pts, int64_t n, const int6
             return fail(DTN_E_ARG, "dtn_wos_eval: unknown precision");
         if (n > 0 && (!pts || !walks || !stats)) return fail(DTN_E_ARG, "dtn_wos_eval: NULL array");
         if (n > ((int64_t)1 << 40)) return fail(DTN_E_ARG, "dtn_wos_eval: n too large");
-        return launch_wos(g->g, pts, n, walks, walk_begin, seed, stream_id, precision, stats, capped,
+        return launch_wos(g->g, pts, n, walks, walk_begin, seed, stream_id, precision, stats, capped, Schedule{},
                           (hipStream_t)stream);
     } catch (...) {
         return fail(DTN_E_DEVICE, "dtn_wos_eval: exception");
+    }
+}
+
+static bool schedule_from(const dtn_schedule *in, Schedule &out, std::string &why)
+{
+    out = Schedule{};
+    if (!in) return true;
+    if (in->min_chunk < 1 || in->min_chunk > ((int64_t)1 << 40)) {
+        why = "min_chunk outside [1, 2^40]";
+        return false;
+    }
+    if (in->oversub < 1 || in->oversub > 64) {
+        why = "oversub outside [1, 64]";
+        return false;
+    }
+    if (in->reserved != 0) {
+        why = "reserved field is not 0";
+        return false;
+    }
+    out.min_chunk = in->min_chunk;
+    out.oversub = in->oversub;
+    return true;
+}
+
+dtn_status dtn_wos_adaptive(dtn_geometry g, const double *pts, int64_t n, const dtn_adaptive *budget,
+                            uint64_t seed, const uint32_t *stream_id, int32_t precision,
+                            const dtn_schedule *sched, double *stats, int64_t *walks_used, int64_t *capped,
+                            void *stream)
+{
+    try {
+        const std::string at = "dtn_wos_adaptive: ";
+        if (!g || !budget) return fail(DTN_E_ARG, at + "NULL geometry or budget");
+        if (n < 0 || n > ((int64_t)1 << 40)) return fail(DTN_E_ARG, at + "n outside [0, 2^40]");
+        if (precision != DTN_FP64 && precision != DTN_FP32_MIXED) return fail(DTN_E_ARG, at + "unknown precision");
+        if (n > 0 && (!pts || !stats || !walks_used)) return fail(DTN_E_ARG, at + "NULL array");
+        const dtn_adaptive &b = *budget;
+        if (b.pilot_walks < 2 || b.pilot_walks > ((int64_t)1 << 40))
+            return fail(DTN_E_ARG, at + "pilot_walks outside [2, 2^40]");
+        if (b.min_walks < 1 || b.min_walks > b.max_walks || b.max_walks > ((int64_t)1 << 40))
+            return fail(DTN_E_ARG, at + "need 1 <= min_walks <= max_walks <= 2^40");
+        if (!(b.se_target > 0.0) || !std::isfinite(b.se_target) || !std::isfinite(b.se_target * b.se_target) ||
+            !(b.se_target * b.se_target > 0.0))
+            return fail(DTN_E_ARG, at + "se_target must be positive and finite (with a normal square)");
+        Schedule sc;
+        std::string why;
+        if (!schedule_from(sched, sc, why)) return fail(DTN_E_ARG, at + why);
+        const Adaptive a{b.pilot_walks, b.min_walks, b.max_walks, b.se_target};
+        return launch_wos_adaptive(g->g, pts, n, a, seed, stream_id, precision, stats, walks_used, capped, sc,
+                                   (hipStream_t)stream);
+    } catch (...) {
+        return fail(DTN_E_DEVICE, "dtn_wos_adaptive: exception");
+    }
+}
+
+dtn_status dtn_wos_time_schedules(dtn_geometry g, const double *pts, int64_t n, const int64_t *walks,
+                                  const int64_t *walk_begin, uint64_t seed, const uint32_t *stream_id,
+                                  int32_t precision, const dtn_schedule *cands, int32_t n_cands, int32_t reps,
+                                  double *stats, float *ms_out, void *stream)
+{
+    const std::string at = "dtn_wos_time_schedules: ";
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto done = [&](dtn_status st) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return st;
+    };
+    try {
+        if (!g || !cands || !ms_out) return fail(DTN_E_ARG, at + "NULL geometry, candidates or output");
+        if (n < 1 || n > ((int64_t)1 << 40)) return fail(DTN_E_ARG, at + "n outside [1, 2^40]");
+        if (n_cands < 1 || reps < 1) return fail(DTN_E_ARG, at + "n_cands and reps must be >= 1");
+        if (precision != DTN_FP64 && precision != DTN_FP32_MIXED) return fail(DTN_E_ARG, at + "unknown precision");
+        if (!pts || !walks || !stats) return fail(DTN_E_ARG, at + "NULL array");
+        std::vector<Schedule> sc(n_cands);
+        std::string why;
+        for (int c = 0; c < n_cands; ++c)
+            if (!schedule_from(&cands[c], sc[c], why))
+                return fail(DTN_E_ARG, at + "candidate " + std::to_string(c) + ": " + why);
+        hipStream_t s = (hipStream_t)stream;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+            return done(fail(DTN_E_DEVICE, at + "hipEventCreate failed"));
+        for (int c = 0; c < n_cands; ++c) {
+            dtn_status st = launch_wos(g->g, pts, n, walks, walk_begin, seed, stream_id, precision, stats, nullptr,
+                                       sc[c], s);
+            if (st != DTN_OK) return done(st);
+            hipError_t e = hipEventRecord(e0, s);
+            for (int r = 0; r < reps && e == hipSuccess && st == DTN_OK; ++r)
+                st = launch_wos(g->g, pts, n, walks, walk_begin, seed, stream_id, precision, stats, nullptr, sc[c],
+                                s);
+            if (st != DTN_OK) return done(st);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) return done(fail(DTN_E_DEVICE, at + hipGetErrorString(e)));
+            ms_out[c] = ms / (float)reps;
+        }
+        return done(DTN_OK);
+    } catch (...) {
+        return done(fail(DTN_E_DEVICE, at + "exception"));
     }
 }
 

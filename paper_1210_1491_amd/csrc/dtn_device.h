@@ -109,6 +109,14 @@ __device__ __forceinline__ double sqrt_f64(double x)
     return fma(fma(-y, y, x), 0.5 * r, y);
 }
 
+// Geometry tables (holes, sources) are read at wave-uniform addresses through
+// the constant address space: the loads become scalar loads into SGPRs,
+// shared by the wave, instead of one vector load per lane.
+typedef const __attribute__((address_space(4))) double cdouble;
+typedef const __attribute__((address_space(4))) float cfloat;
+__device__ __forceinline__ cdouble *as_const(const double *p) { return (cdouble *)p; }
+__device__ __forceinline__ cfloat *as_const(const float *p) { return (cfloat *)p; }
+
 // ------------------------------------------------------------- Dirichlet data
 
 template <int DATA>
@@ -120,8 +128,8 @@ __device__ __forceinline__ double phi_eval(const DevGeom &g, double x, double y,
                c[7] * x * y + c[8] * y * z + c[9] * x * z;
     } else {
         double s = 0.0;
-        for (int k = 0; k < g.n_src; ++k) {
-            const double *q = g.src + 4 * k;
+        cdouble *q = as_const(g.src);
+        for (int k = 0; k < g.n_src; ++k, q += 4) {
             const double dx = x - q[0], dy = y - q[1], dz = z - q[2];
             s = fma(q[3], rsqrt_f64(dx * dx + dy * dy + dz * dz), s);
         }
@@ -143,13 +151,19 @@ __device__ __forceinline__ double dist_f64(const DevGeom &g, double x, double y,
         double d = fmin(fmin(fmin(x - g.lo[0], g.hi[0] - x), fmin(y - g.lo[1], g.hi[1] - y)),
                         fmin(z - g.lo[2], g.hi[2] - z));
         if constexpr (KIND == DTN_BOX_MINUS_BOXES) {
-            for (int i = 0; i < g.n_holes; ++i) {
-                const double *h = g.hole_ce + 6 * i;
+            // nearest hole by squared distance, one square root at the end
+            // (sqrt is correctly rounded, hence monotone: same result as the
+            // minimum of the per-hole distances)
+            double q2 = __builtin_inf();
+            cdouble *h = as_const(g.hole_ce);
+#pragma unroll 4
+            for (int i = 0; i < g.n_holes; ++i, h += 6) {
                 const double qx = fmax(fabs(x - h[0]) - h[3], 0.0);
                 const double qy = fmax(fabs(y - h[1]) - h[4], 0.0);
                 const double qz = fmax(fabs(z - h[2]) - h[5], 0.0);
-                d = fmin(d, sqrt(qx * qx + qy * qy + qz * qz));
+                q2 = fmin(q2, qx * qx + qy * qy + qz * qz);
             }
+            d = fmin(d, sqrt(q2));
         }
         return d;
     }
@@ -166,13 +180,16 @@ __device__ __forceinline__ float dist_f32(const DevGeom &g, float x, float y, fl
                               fminf(y - (float)g.lo[1], (float)g.hi[1] - y)),
                         fminf(z - (float)g.lo[2], (float)g.hi[2] - z));
         if constexpr (KIND == DTN_BOX_MINUS_BOXES) {
-            for (int i = 0; i < g.n_holes; ++i) {
-                const double *h = g.hole_ce + 6 * i;
-                const float qx = fmaxf(fabsf(x - (float)h[0]) - (float)h[3], 0.0f);
-                const float qy = fmaxf(fabsf(y - (float)h[1]) - (float)h[4], 0.0f);
-                const float qz = fmaxf(fabsf(z - (float)h[2]) - (float)h[5], 0.0f);
-                d = fminf(d, __builtin_amdgcn_sqrtf(qx * qx + qy * qy + qz * qz));
+            float q2 = __builtin_inff();
+            cfloat *h = as_const(g.hole_f32);
+#pragma unroll 4
+            for (int i = 0; i < g.n_holes; ++i, h += 8) {
+                const float qx = fmaxf(fabsf(x - h[0]) - h[3], 0.0f);
+                const float qy = fmaxf(fabsf(y - h[1]) - h[4], 0.0f);
+                const float qz = fmaxf(fabsf(z - h[2]) - h[5], 0.0f);
+                q2 = fminf(q2, qx * qx + qy * qy + qz * qz);
             }
+            d = fminf(d, __builtin_amdgcn_sqrtf(q2));
         }
         return d;
     }
@@ -207,8 +224,8 @@ __device__ __forceinline__ void project_f64(const DevGeom &g, double &x, double 
             }
         int hole = -1;
         if constexpr (KIND == DTN_BOX_MINUS_BOXES) {
-            for (int i = 0; i < g.n_holes; ++i) {
-                const double *h = g.hole_ce + 6 * i;
+            cdouble *h = as_const(g.hole_ce);
+            for (int i = 0; i < g.n_holes; ++i, h += 6) {
                 const double qx = fmax(fabs(x - h[0]) - h[3], 0.0);
                 const double qy = fmax(fabs(y - h[1]) - h[4], 0.0);
                 const double qz = fmax(fabs(z - h[2]) - h[5], 0.0);
@@ -223,7 +240,7 @@ __device__ __forceinline__ void project_f64(const DevGeom &g, double &x, double 
             const int k = face >> 1;
             p[k] = (face & 1) ? g.hi[k] : g.lo[k];
         } else {
-            const double *b = g.hole_box + 6 * hole;
+            cdouble *b = as_const(g.hole_box) + 6 * hole;
             bool inside = true;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {

@@ -24,6 +24,7 @@ struct DevGeom {
     int32_t n_src;
     const double *hole_ce;  // [n_holes][6]: centre xyz, half-extent xyz
     const double *hole_box; // [n_holes][6]: lo xyz, hi xyz
+    const float *hole_f32;  // [n_holes][8]: centre xyz, half-extent xyz, 0, 0 (FP32)
     const double *src;      // [n_src][4]
     double quad[10];
     double eps;
@@ -58,6 +59,7 @@ struct Geometry {
     dtn_geometry_desc desc{};
     std::vector<double> holes, src;
     double *d_hole_ce = nullptr, *d_hole_box = nullptr, *d_src = nullptr;
+    float *d_hole_f32 = nullptr;
     int device = 0;
 };
 
@@ -86,10 +88,25 @@ struct Plan {
 void set_error(const std::string &msg);
 dtn_status fail(dtn_status s, const std::string &msg);
 
+// Walk schedule: chunks per resident wave and the smallest chunk (walks).
+struct Schedule {
+    int64_t min_chunk = 512;
+    int32_t oversub = 4;
+};
+
+// Adaptive walk budget: pilot walks, clamp of the total, target standard error.
+struct Adaptive {
+    int64_t pilot, w_min, w_max;
+    double se;
+};
+
 // Kernel launchers (dtn_wos.hip).
 dtn_status launch_wos(const Geometry &g, const double *pts, int64_t n, const int64_t *walks,
                       const int64_t *walk_begin, uint64_t seed, const uint32_t *stream_id,
-                      int precision, double *stats, int64_t *capped, hipStream_t stream);
+                      int precision, double *stats, int64_t *capped, const Schedule &sc, hipStream_t stream);
+dtn_status launch_wos_adaptive(const Geometry &g, const double *pts, int64_t n, const Adaptive &a, uint64_t seed,
+                               const uint32_t *stream_id, int precision, double *stats, int64_t *walks_used,
+                               int64_t *capped, const Schedule &sc, hipStream_t stream);
 
 // Kernel launchers (dtn_patch.hip).
 dtn_status launch_nodes(const Plan &p, double *nodes, hipStream_t stream);

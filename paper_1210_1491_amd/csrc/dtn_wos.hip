@@ -355,11 +355,13 @@ int device_cus()
 
 template <int KIND, int DATA, int PREC>
 hipError_t run(const Geometry &g, const double *pts, int64_t n, const int64_t *walks, const int64_t *walk_begin,
-               uint64_t seed, const uint32_t *stream_id, double *stats, int64_t *capped, hipStream_t s)
+               uint64_t seed, const uint32_t *stream_id, double *stats, int64_t *capped, const Schedule &sc,
+               hipStream_t s)
 {
-    // Aim for several chunks per resident wave (4 SIMDs x 8 waves per CU).
-    const int64_t target_chunks = (int64_t)device_cus() * 4 * 8 * 4;
-    const int64_t c_min = 512;
+    // Aim for `oversub` chunks per resident wave (4 SIMDs x 8 waves per CU);
+    // chunks hold at least `min_chunk` walks.
+    const int64_t target_chunks = (int64_t)device_cus() * 4 * 8 * sc.oversub;
+    const int64_t c_min = sc.min_chunk;
     // total chunks <= sum(walks)/C + n <= target_chunks + n
     const int64_t max_chunks = n + target_chunks + 1;
     hipError_t e;
@@ -393,35 +395,129 @@ hipError_t run(const Geometry &g, const double *pts, int64_t n, const int64_t *w
 
 template <int PREC>
 hipError_t dispatch(const Geometry &g, const double *pts, int64_t n, const int64_t *walks, const int64_t *wb,
-                    uint64_t seed, const uint32_t *sid, double *stats, int64_t *capped, hipStream_t s)
+                    uint64_t seed, const uint32_t *sid, double *stats, int64_t *capped, const Schedule &sc,
+                    hipStream_t s)
 {
     const bool src = g.dev.data_kind == DTN_DATA_POINT_SOURCES;
+    constexpr int Q = DTN_DATA_HARMONIC_QUADRATIC, P = DTN_DATA_POINT_SOURCES;
     switch (g.dev.kind) {
     case DTN_BALL:
-        return src ? run<DTN_BALL, DTN_DATA_POINT_SOURCES, PREC>(g, pts, n, walks, wb, seed, sid, stats, capped, s)
-                   : run<DTN_BALL, DTN_DATA_HARMONIC_QUADRATIC, PREC>(g, pts, n, walks, wb, seed, sid, stats, capped, s);
+        return src ? run<DTN_BALL, P, PREC>(g, pts, n, walks, wb, seed, sid, stats, capped, sc, s)
+                   : run<DTN_BALL, Q, PREC>(g, pts, n, walks, wb, seed, sid, stats, capped, sc, s);
     case DTN_BOX:
-        return src ? run<DTN_BOX, DTN_DATA_POINT_SOURCES, PREC>(g, pts, n, walks, wb, seed, sid, stats, capped, s)
-                   : run<DTN_BOX, DTN_DATA_HARMONIC_QUADRATIC, PREC>(g, pts, n, walks, wb, seed, sid, stats, capped, s);
+        return src ? run<DTN_BOX, P, PREC>(g, pts, n, walks, wb, seed, sid, stats, capped, sc, s)
+                   : run<DTN_BOX, Q, PREC>(g, pts, n, walks, wb, seed, sid, stats, capped, sc, s);
     default:
-        return src ? run<DTN_BOX_MINUS_BOXES, DTN_DATA_POINT_SOURCES, PREC>(g, pts, n, walks, wb, seed, sid, stats,
-                                                                            capped, s)
-                   : run<DTN_BOX_MINUS_BOXES, DTN_DATA_HARMONIC_QUADRATIC, PREC>(g, pts, n, walks, wb, seed, sid,
-                                                                                 stats, capped, s);
+        return src ? run<DTN_BOX_MINUS_BOXES, P, PREC>(g, pts, n, walks, wb, seed, sid, stats, capped, sc, s)
+                   : run<DTN_BOX_MINUS_BOXES, Q, PREC>(g, pts, n, walks, wb, seed, sid, stats, capped, sc, s);
     }
+}
+
+hipError_t walk_all(const Geometry &g, const double *pts, int64_t n, const int64_t *walks, const int64_t *walk_begin,
+                    uint64_t seed, const uint32_t *stream_id, int precision, double *stats, int64_t *capped,
+                    const Schedule &sc, hipStream_t stream)
+{
+    return precision == DTN_FP64
+               ? dispatch<DTN_FP64>(g, pts, n, walks, walk_begin, seed, stream_id, stats, capped, sc, stream)
+               : dispatch<DTN_FP32_MIXED>(g, pts, n, walks, walk_begin, seed, stream_id, stats, capped, sc, stream);
+}
+
+// ------------------------------------------------------- adaptive budgets
+
+__global__ __launch_bounds__(256) void k_fill_i64(int64_t *__restrict__ a, int64_t n, int64_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+// Per point: total walks = clamp(ceil(var / se^2), w_min, w_max), never fewer
+// than the pilot; the remainder continues at walk index `pilot`.
+__global__ __launch_bounds__(256) void k_budget(const double *__restrict__ pilot_stats, int64_t n, int64_t pilot,
+                                                int64_t w_min, int64_t w_max, double se2,
+                                                int64_t *__restrict__ rem, int64_t *__restrict__ wb,
+                                                int64_t *__restrict__ used)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double cnt = pilot_stats[4 * i], m2 = pilot_stats[4 * i + 2];
+    const double var = cnt > 1.0 ? m2 / (cnt - 1.0) : 0.0;
+    const double want = ceil(var / se2);
+    int64_t tot;
+    if (!(want < (double)w_max)) tot = w_max;  // also catches NaN
+    else if (want <= (double)w_min) tot = w_min;
+    else tot = (int64_t)want;
+    tot = max(tot, pilot);
+    rem[i] = tot - pilot;
+    wb[i] = pilot;
+    used[i] = tot;
+}
+
+// Merge the pilot statistics with the remainder's (Chan, Golub & LeVeque's
+// pairwise update of count, mean and sum of squared deviations).
+__global__ __launch_bounds__(256) void k_merge(const double *__restrict__ ps, const int64_t *__restrict__ pcap,
+                                               const int64_t *__restrict__ rcap, double *__restrict__ stats,
+                                               int64_t *__restrict__ capped, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double n1 = ps[4 * i], m1 = ps[4 * i + 1], M1 = ps[4 * i + 2], t1 = ps[4 * i + 3];
+    const double n2 = stats[4 * i], m2 = stats[4 * i + 1], M2 = stats[4 * i + 2], t2 = stats[4 * i + 3];
+    double cnt = n1, mean = m1, msq = M1;
+    if (n2 > 0.0) {
+        cnt = n1 + n2;
+        const double d = m2 - m1;
+        mean = m1 + d * (n2 / cnt);
+        msq = M1 + M2 + d * d * (n1 * (n2 / cnt));
+    }
+    stats[4 * i] = cnt;
+    stats[4 * i + 1] = mean;
+    stats[4 * i + 2] = msq;
+    stats[4 * i + 3] = t1 + t2;
+    if (capped) capped[i] = pcap[i] + rcap[i];
 }
 
 }  // namespace
 
 dtn_status launch_wos(const Geometry &g, const double *pts, int64_t n, const int64_t *walks,
                       const int64_t *walk_begin, uint64_t seed, const uint32_t *stream_id, int precision,
-                      double *stats, int64_t *capped, hipStream_t stream)
+                      double *stats, int64_t *capped, const Schedule &sc, hipStream_t stream)
 {
     if (n == 0) return DTN_OK;
-    hipError_t e = precision == DTN_FP64
-                       ? dispatch<DTN_FP64>(g, pts, n, walks, walk_begin, seed, stream_id, stats, capped, stream)
-                       : dispatch<DTN_FP32_MIXED>(g, pts, n, walks, walk_begin, seed, stream_id, stats, capped, stream);
+    hipError_t e = walk_all(g, pts, n, walks, walk_begin, seed, stream_id, precision, stats, capped, sc, stream);
     if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_wos_eval: ") + hipGetErrorString(e));
+    return DTN_OK;
+}
+
+dtn_status launch_wos_adaptive(const Geometry &g, const double *pts, int64_t n, const Adaptive &a, uint64_t seed,
+                               const uint32_t *stream_id, int precision, double *stats, int64_t *walks_used,
+                               int64_t *capped, const Schedule &sc, hipStream_t s)
+{
+    if (n == 0) return DTN_OK;
+    const char *where = "dtn_wos_adaptive: ";
+    // scratch: pilot stats [n][4] doubles, then pilot walks, remainder walks,
+    // remainder first walk, pilot capped, remainder capped ([n] int64 each)
+    char *scratch = nullptr;
+    const size_t bytes = (size_t)n * (4 * sizeof(double) + 5 * sizeof(int64_t));
+    hipError_t e = hipMallocAsync((void **)&scratch, bytes, s);
+    if (e != hipSuccess) return fail(DTN_E_OOM, std::string(where) + hipGetErrorString(e));
+    double *pstats = (double *)scratch;
+    int64_t *pw = (int64_t *)(scratch + (size_t)n * 4 * sizeof(double));
+    int64_t *rw = pw + n, *wb = rw + n, *pcap = wb + n, *rcap = pcap + n;
+    const unsigned grid = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_fill_i64, dim3(grid), dim3(256), 0, s, pw, n, a.pilot);
+    e = walk_all(g, pts, n, pw, nullptr, seed, stream_id, precision, pstats, pcap, sc, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_budget, dim3(grid), dim3(256), 0, s, pstats, n, a.pilot, a.w_min, a.w_max,
+                           a.se * a.se, rw, wb, walks_used);
+        e = walk_all(g, pts, n, rw, wb, seed, stream_id, precision, stats, rcap, sc, s);
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, s, pstats, pcap, rcap, stats, capped, n);
+        e = hipGetLastError();
+    }
+    const hipError_t ef = hipFreeAsync(scratch, s);
+    if (e == hipSuccess) e = ef;
+    if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string(where) + hipGetErrorString(e));
     return DTN_OK;
 }
 

@@ -43,6 +43,23 @@ class PatchDesc(C.Structure):
 
 assert C.sizeof(PatchDesc) == 96
 
+
+class ScheduleDesc(C.Structure):
+    _fields_ = [("min_chunk", C.c_int64), ("oversub", C.c_int32), ("reserved", C.c_int32)]
+
+
+class AdaptiveDesc(C.Structure):
+    _fields_ = [("pilot_walks", C.c_int64), ("min_walks", C.c_int64), ("max_walks", C.c_int64),
+                ("se_target", C.c_double)]
+
+
+def schedule_struct(sched):
+    """dict(min_chunk=..., oversub=...) (or None) -> ScheduleDesc (or None)."""
+    if sched is None:
+        return None
+    return ScheduleDesc(int(sched.get("min_chunk", 512)), int(sched.get("oversub", 4)), 0)
+
+
 _lib = None
 
 
@@ -60,6 +77,11 @@ def lib():
         L.dtn_destroy_geometry.argtypes = [vp]
         L.dtn_destroy_geometry.restype = None
         L.dtn_wos_eval.argtypes = [vp, vp, C.c_int64, vp, vp, C.c_uint64, vp, C.c_int32, vp, vp, vp]
+        L.dtn_wos_adaptive.argtypes = [vp, vp, C.c_int64, C.POINTER(AdaptiveDesc), C.c_uint64, vp, C.c_int32,
+                                       C.POINTER(ScheduleDesc), vp, vp, vp, vp]
+        L.dtn_wos_time_schedules.argtypes = [vp, vp, C.c_int64, vp, vp, C.c_uint64, vp, C.c_int32,
+                                             C.POINTER(ScheduleDesc), C.c_int32, C.c_int32, vp,
+                                             C.POINTER(C.c_float), vp]
         L.dtn_create_plan.argtypes = [vp, C.POINTER(PatchDesc), C.c_int64, C.POINTER(vp)]
         L.dtn_destroy_plan.argtypes = [vp]
         L.dtn_destroy_plan.restype = None
@@ -73,7 +95,8 @@ def lib():
         dp = C.POINTER(C.c_double)
         L.dtn_class_operators.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
                                           dp, dp, dp, dp, dp, dp]
-        for f in ("dtn_create_geometry", "dtn_wos_eval", "dtn_create_plan", "dtn_patch_nodes",
+        for f in ("dtn_create_geometry", "dtn_wos_eval", "dtn_wos_adaptive", "dtn_wos_time_schedules",
+                  "dtn_create_plan", "dtn_patch_nodes",
                   "dtn_patch_solve", "dtn_potential", "dtn_class_operators"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -164,6 +187,56 @@ def wos_eval(geom, pts, walks, seed, walk_begin=None, stream_id=None, precision=
                               C.c_uint64(int(seed) & (2 ** 64 - 1)), _ptr(stream_id), PRECISION[precision],
                               _ptr(stats), _ptr(capped), _stream()), "dtn_wos_eval")
     return stats, capped
+
+
+def wos_adaptive(geom, pts, seed, pilot_walks, min_walks, max_walks, se_target, stream_id=None,
+                 precision="fp64", schedule=None, stats=None, walks_used=None, capped=None):
+    """Step 1 with adaptive walk counts: pilot, per-point budget
+    clamp(ceil(var / se_target^2), min_walks, max_walks), remainder, merge.
+
+    Returns (stats [n,4] f64, walks_used [n] int64, capped [n] int64)."""
+    n = pts.shape[0]
+    _dev_tensor(pts, torch.float64, (n, 3))
+    if stream_id is not None:
+        _dev_tensor(stream_id, torch.int32, (n,))
+    dev = pts.device
+    if stats is None:
+        stats = torch.empty((n, 4), dtype=torch.float64, device=dev)
+    if walks_used is None:
+        walks_used = torch.empty((n,), dtype=torch.int64, device=dev)
+    if capped is None:
+        capped = torch.empty((n,), dtype=torch.int64, device=dev)
+    _dev_tensor(stats, torch.float64, (n, 4))
+    _dev_tensor(walks_used, torch.int64, (n,))
+    _dev_tensor(capped, torch.int64, (n,))
+    b = AdaptiveDesc(int(pilot_walks), int(min_walks), int(max_walks), float(se_target))
+    sc = schedule_struct(schedule)
+    _check(lib().dtn_wos_adaptive(geom.handle, _ptr(pts), n, C.byref(b), C.c_uint64(int(seed) & (2 ** 64 - 1)),
+                                  _ptr(stream_id), PRECISION[precision], None if sc is None else C.byref(sc),
+                                  _ptr(stats), _ptr(walks_used), _ptr(capped), _stream()), "dtn_wos_adaptive")
+    return stats, walks_used, capped
+
+
+def time_schedules(geom, pts, walks, seed, schedules, reps=1, walk_begin=None, stream_id=None,
+                   precision="fp64", stats=None):
+    """Mean device milliseconds of dtn_wos_eval's work under each schedule
+    (list of dicts); blocks until done.  Returns (ms list, stats)."""
+    n = pts.shape[0]
+    _dev_tensor(pts, torch.float64, (n, 3))
+    _dev_tensor(walks, torch.int64, (n,))
+    if walk_begin is not None:
+        _dev_tensor(walk_begin, torch.int64, (n,))
+    if stream_id is not None:
+        _dev_tensor(stream_id, torch.int32, (n,))
+    if stats is None:
+        stats = torch.empty((n, 4), dtype=torch.float64, device=pts.device)
+    cands = (ScheduleDesc * len(schedules))(*[schedule_struct(s) for s in schedules])
+    ms = (C.c_float * len(schedules))()
+    _check(lib().dtn_wos_time_schedules(geom.handle, _ptr(pts), n, _ptr(walks), _ptr(walk_begin),
+                                        C.c_uint64(int(seed) & (2 ** 64 - 1)), _ptr(stream_id),
+                                        PRECISION[precision], cands, len(schedules), int(reps), _ptr(stats), ms,
+                                        _stream()), "dtn_wos_time_schedules")
+    return [float(v) for v in ms], stats
 
 
 def patches_struct(pdesc):

@@ -178,3 +178,42 @@ def test_edge_cases_start_in_shell_cap_and_empty():
     capd = wos.Geometry(dict(desc, max_steps=2))
     rc = wos.wos_nodes(capd, y[1:2], 100, seed=1)
     assert rc["capped"][0] > 50 and rc["steps"][0] <= 200
+
+
+def test_adaptive_budget_follows_the_exit_variance():
+    """From the centre of the unit ball the first jump lands on the sphere
+    and its end point is uniform there (the harmonic measure seen from the
+    centre), so with phi = z every walk takes one step and the scores have
+    variance E[z^2] = 1/3.  The budget must then be close to 1/(3 se^2) and
+    the final standard error close to se."""
+    desc = dict(I.geometry_ball_quadratic(eps=1e-6), quad=[0.0, 0.0, 0.0, 1.0] + [0.0] * 6)
+    g = wos.Geometry(desc)
+    x = np.zeros((8, 3))
+    se = 0.01
+    r = wos.wos_adaptive(g, x, 1000, 100, 10 ** 6, se, seed=3, stream_id=np.arange(8))
+    expect = 1.0 / (3.0 * se * se)
+    # sd of the pilot variance of z^2, z uniform on [-1,1]: sqrt((1/5 - 1/9) / 1000)
+    sd = expect * np.sqrt((1 / 5 - 1 / 9) / 1000) * 3.0
+    assert np.all(np.abs(r["walks_used"] - expect) < 5 * sd), r["walks_used"]
+    np.testing.assert_array_equal(r["count"], r["walks_used"])
+    np.testing.assert_array_equal(r["steps"], r["walks_used"])  # one step per walk
+    assert np.all(np.abs(r["se"] / se - 1.0) < 0.1), r["se"]
+    assert np.all(np.abs(r["mean"]) < 5 * r["se"])
+
+
+def test_adaptive_clamps_and_prefix():
+    """A point inside the shell has zero spread: it gets min_walks (or the
+    pilot if larger); a tiny target hits max_walks; the statistics are those
+    of the first walks_used walks of each point."""
+    desc = I.geometry_ball_quadratic(eps=1e-3)
+    g = wos.Geometry(desc)
+    y = np.array([[0.0, 0.0, 1.0 - 5e-4], [0.0, 0.5, 0.0], [0.2, 0.0, 0.1]])
+    r = wos.wos_adaptive(g, y, 300, 1500, 4000, 1e-6, seed=2)
+    assert list(r["walks_used"]) == [1500, 4000, 4000]
+    r2 = wos.wos_adaptive(g, y, 300, 100, 4000, 1e-6, seed=2)
+    assert r2["walks_used"][0] == 300  # never fewer than the pilot
+    loose = wos.wos_adaptive(g, y, 300, 100, 4000, 10.0, seed=2)
+    assert list(loose["walks_used"]) == [300, 300, 300]
+    plain = wos.wos_nodes(g, y, r["walks_used"], seed=2)
+    for k in ("count", "mean", "m2", "steps"):
+        np.testing.assert_array_equal(r[k], plain[k])
