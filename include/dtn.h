@@ -149,6 +149,16 @@ dtn_status dtn_wos_eval(dtn_geometry g, const double *pts, int64_t n, const int6
                         const int64_t *walk_begin, uint64_t seed, const uint32_t *stream_id,
                         int32_t precision, double *stats, int64_t *capped, void *stream);
 
+/* Distance from n points inside Omega to its boundary, computed as the walk
+ * kernels compute it (the radius of the largest ball of a walk step, Sec. 2):
+ * DTN_FP64 in FP64; DTN_FP32_MIXED the FP32 distance of the mixed path (whose
+ * jumps subtract a rounding margin from it).  For a box minus holes the walk
+ * kernels look up, per grid cell, the holes that can be nearest; this call
+ * lets a caller check that lookup against a plain minimum over all surfaces.
+ *   pts device [n][3]; dist device [n] out.  Errors: DTN_E_ARG. */
+dtn_status dtn_boundary_distance(dtn_geometry g, const double *pts, int64_t n, int32_t precision, double *dist,
+                                 void *stream);
+
 /* Work schedule of the walk kernels.  The walks of all points form one work
  * list of chunks (point, first walk, walk count), one wave per chunk, in a
  * single launch; the chunk size is C = max(min_chunk, ceil(total walks /

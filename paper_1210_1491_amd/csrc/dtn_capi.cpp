@@ -119,6 +119,64 @@ double box_dist(const double *x, const double *lo, const double *hi)
     return std::sqrt(s);
 }
 
+// Candidate-hole grid.  The box is split into about 32^3 cells.  For a cell
+// C, expanded by a small margin so that rounding in the lookup cannot put a
+// point outside the cell it is looked up in, U bounds the distance to the
+// boundary from above for every point of C: the interior distance to the
+// outer box is at most min_k min(hi_C,k - lo_k, hi_k - lo_C,k), and the
+// distance to hole j is a convex function, so at most its largest value at
+// the corners of C.  A hole j whose distance to C exceeds U can never be the
+// nearest surface of a point of C and is left out of the cell's list; the
+// minimum over the listed holes (and the outer faces) is then exactly the
+// minimum over all of them.
+void build_cell_grid(const double lo[3], const double hi[3], const double *holes, int n_holes,
+                     std::vector<uint32_t> &mask, int32_t n[3], float clo[3], float inv[3])
+{
+    const double L[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
+    const double side = std::cbrt(L[0] * L[1] * L[2] / 32768.0);
+    for (int k = 0; k < 3; ++k) {
+        n[k] = (int32_t)std::min(256.0, std::max(1.0, std::ceil(L[k] / side)));
+        clo[k] = (float)lo[k];
+        inv[k] = (float)(n[k] / L[k]);
+    }
+    mask.assign((size_t)n[0] * n[1] * n[2], 0u);
+    const double scale = 1.0 + std::max({std::fabs(lo[0]), std::fabs(lo[1]), std::fabs(lo[2]), std::fabs(hi[0]),
+                                         std::fabs(hi[1]), std::fabs(hi[2])});
+    const double tol = 1e-9 * scale;
+    for (int i = 0; i < n[0]; ++i)
+        for (int j = 0; j < n[1]; ++j)
+            for (int l = 0; l < n[2]; ++l) {
+                const int ijk[3] = {i, j, l};
+                double a[3], b[3];
+                for (int k = 0; k < 3; ++k) {
+                    const double w = L[k] / n[k], margin = 1e-3 * w;
+                    a[k] = lo[k] + w * ijk[k] - margin;
+                    b[k] = lo[k] + w * (ijk[k] + 1) + margin;
+                }
+                double U = std::min({b[0] - lo[0], hi[0] - a[0], b[1] - lo[1], hi[1] - a[1], b[2] - lo[2],
+                                     hi[2] - a[2]});
+                for (int h = 0; h < n_holes; ++h) {
+                    double far = 0.0;
+                    for (int c = 0; c < 8; ++c) {
+                        const double x[3] = {(c & 1) ? b[0] : a[0], (c & 2) ? b[1] : a[1], (c & 4) ? b[2] : a[2]};
+                        far = std::max(far, box_dist(x, holes + 6 * h, holes + 6 * h + 3));
+                    }
+                    U = std::min(U, far);
+                }
+                uint32_t m = 0;
+                for (int h = 0; h < n_holes; ++h) {
+                    const double *hl = holes + 6 * h, *hh = hl + 3;
+                    double s2 = 0.0;
+                    for (int k = 0; k < 3; ++k) {
+                        const double gap = std::max({hl[k] - b[k], 0.0, a[k] - hh[k]});
+                        s2 += gap * gap;
+                    }
+                    if (std::sqrt(s2) <= U + tol) m |= 1u << h;
+                }
+                mask[((size_t)i * n[1] + j) * n[2] + l] = m;
+            }
+}
+
 // Check that a plane patch lies on a face of the box or of a hole, that S
 // fits inside that face and that the half ball over it stays in Omega.
 bool check_plane_patch(const Geometry &g, const dtn_patch &p, std::string &why)
@@ -270,11 +328,17 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
         if (e == hipSuccess) e = upload(ce, &g.d_hole_ce);
         if (e == hipSuccess) e = upload(g.holes, &g.d_hole_box);
         if (e == hipSuccess) e = upload(ce32, &g.d_hole_f32);
+        if (nh >= 1 && nh <= 32) {
+            build_cell_grid(d.box_lo, d.box_hi, g.holes.data(), nh, g.cell_mask, g.dev.cell_n, g.dev.cell_lo,
+                            g.dev.cell_inv);
+            if (e == hipSuccess) e = upload(g.cell_mask, &g.d_cell_mask);
+        }
         if (e == hipSuccess) e = upload(g.src, &g.d_src);
         if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_create_geometry: ") + hipGetErrorString(e));
         g.dev.hole_ce = g.d_hole_ce;
         g.dev.hole_box = g.d_hole_box;
         g.dev.hole_f32 = g.d_hole_f32;
+        g.dev.cell_mask = g.d_cell_mask;
         g.dev.src = g.d_src;
         // keep stream-ordered scratch in the pool between calls
         hipMemPool_t pool;
@@ -295,6 +359,7 @@ void dtn_destroy_geometry(dtn_geometry g)
     hipFree(g->g.d_hole_ce);
     hipFree(g->g.d_hole_box);
     hipFree(g->g.d_hole_f32);
+    hipFree(g->g.d_cell_mask);
     hipFree(g->g.d_src);
     delete g;
 }
@@ -314,6 +379,21 @@ dtn_status dtn_wos_eval(dtn_geometry g, const double *pts, int64_t n, const int6
                           (hipStream_t)stream);
     } catch (...) {
         return fail(DTN_E_DEVICE, "dtn_wos_eval: exception");
+    }
+}
+
+dtn_status dtn_boundary_distance(dtn_geometry g, const double *pts, int64_t n, int32_t precision, double *dist,
+                                 void *stream)
+{
+    try {
+        if (!g) return fail(DTN_E_ARG, "dtn_boundary_distance: NULL geometry");
+        if (n < 0 || n > ((int64_t)1 << 40)) return fail(DTN_E_ARG, "dtn_boundary_distance: n outside [0, 2^40]");
+        if (precision != DTN_FP64 && precision != DTN_FP32_MIXED)
+            return fail(DTN_E_ARG, "dtn_boundary_distance: unknown precision");
+        if (n > 0 && (!pts || !dist)) return fail(DTN_E_ARG, "dtn_boundary_distance: NULL array");
+        return launch_distance(g->g, pts, n, precision, dist, (hipStream_t)stream);
+    } catch (...) {
+        return fail(DTN_E_DEVICE, "dtn_boundary_distance: exception");
     }
 }
 

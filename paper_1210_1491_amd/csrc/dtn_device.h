@@ -117,6 +117,33 @@ typedef const __attribute__((address_space(4))) float cfloat;
 __device__ __forceinline__ cdouble *as_const(const double *p) { return (cdouble *)p; }
 __device__ __forceinline__ cfloat *as_const(const float *p) { return (cfloat *)p; }
 
+// OR of a value over the lanes of the wave (device library reduction, DPP
+// based); the result is wave-uniform.  Its DPP steps read neighbouring lanes'
+// registers whether those lanes are active or not, so it is only called where
+// every lane of the wave is active, with a zero from lanes that do not take
+// part.
+extern "C" __device__ uint32_t __ockl_wfred_or_u32(uint32_t);
+
+// Candidate holes of the grid cell holding (x, y, z): bit i set when hole i
+// can be the nearest surface for some point of the (slightly expanded) cell.
+__device__ __forceinline__ uint32_t cell_candidates(const DevGeom &g, float x, float y, float z)
+{
+    const int ix = min(max((int)((x - g.cell_lo[0]) * g.cell_inv[0]), 0), g.cell_n[0] - 1);
+    const int iy = min(max((int)((y - g.cell_lo[1]) * g.cell_inv[1]), 0), g.cell_n[1] - 1);
+    const int iz = min(max((int)((z - g.cell_lo[2]) * g.cell_inv[2]), 0), g.cell_n[2] - 1);
+    return g.cell_mask[(ix * g.cell_n[1] + iy) * g.cell_n[2] + iz];
+}
+
+// Holes the distance query must visit for the lanes with `take` set: the
+// union of their cells' candidate lists (wave-uniform).  Call with the whole
+// wave active.  Without a grid every hole is visited.
+__device__ __forceinline__ uint32_t hole_candidates(const DevGeom &g, bool take, double x, double y, double z)
+{
+    if (!g.cell_mask) return 0xffffffffu;
+    const uint32_t mine = take ? cell_candidates(g, (float)x, (float)y, (float)z) : 0u;
+    return __ockl_wfred_or_u32(mine);
+}
+
 // ------------------------------------------------------------- Dirichlet data
 
 template <int DATA>
@@ -142,7 +169,7 @@ __device__ __forceinline__ double phi_eval(const DevGeom &g, double x, double y,
 // surface go to the lowest index: outer faces -x,+x,-y,+y,-z,+z, then holes.
 
 template <int KIND>
-__device__ __forceinline__ double dist_f64(const DevGeom &g, double x, double y, double z)
+__device__ __forceinline__ double dist_f64(const DevGeom &g, double x, double y, double z, uint32_t cand)
 {
     if constexpr (KIND == DTN_BALL) {
         const double dx = x - g.c[0], dy = y - g.c[1], dz = z - g.c[2];
@@ -155,13 +182,26 @@ __device__ __forceinline__ double dist_f64(const DevGeom &g, double x, double y,
             // (sqrt is correctly rounded, hence monotone: same result as the
             // minimum of the per-hole distances)
             double q2 = __builtin_inf();
-            cdouble *h = as_const(g.hole_ce);
-#pragma unroll 4
-            for (int i = 0; i < g.n_holes; ++i, h += 6) {
+            auto hole = [&](cdouble *h) {
                 const double qx = fmax(fabs(x - h[0]) - h[3], 0.0);
                 const double qy = fmax(fabs(y - h[1]) - h[4], 0.0);
                 const double qz = fmax(fabs(z - h[2]) - h[5], 0.0);
                 q2 = fmin(q2, qx * qx + qy * qy + qz * qz);
+            };
+            if (g.cell_mask) {
+                // only the holes listed for some lane's cell (`cand`, from
+                // hole_candidates): the others are farther than the boundary
+                // from every point of those cells
+                uint32_t m = cand;
+                while (m) {
+                    const int i = __builtin_ctz(m);
+                    m &= m - 1u;
+                    hole(as_const(g.hole_ce) + 6 * i);
+                }
+            } else {
+                cdouble *h = as_const(g.hole_ce);
+#pragma unroll 4
+                for (int i = 0; i < g.n_holes; ++i, h += 6) hole(h);
             }
             d = fmin(d, sqrt(q2));
         }
@@ -170,7 +210,7 @@ __device__ __forceinline__ double dist_f64(const DevGeom &g, double x, double y,
 }
 
 template <int KIND>
-__device__ __forceinline__ float dist_f32(const DevGeom &g, float x, float y, float z)
+__device__ __forceinline__ float dist_f32(const DevGeom &g, float x, float y, float z, uint32_t cand)
 {
     if constexpr (KIND == DTN_BALL) {
         const float dx = x - (float)g.c[0], dy = y - (float)g.c[1], dz = z - (float)g.c[2];
@@ -181,13 +221,23 @@ __device__ __forceinline__ float dist_f32(const DevGeom &g, float x, float y, fl
                         fminf(z - (float)g.lo[2], (float)g.hi[2] - z));
         if constexpr (KIND == DTN_BOX_MINUS_BOXES) {
             float q2 = __builtin_inff();
-            cfloat *h = as_const(g.hole_f32);
-#pragma unroll 4
-            for (int i = 0; i < g.n_holes; ++i, h += 8) {
+            auto hole = [&](cfloat *h) {
                 const float qx = fmaxf(fabsf(x - h[0]) - h[3], 0.0f);
                 const float qy = fmaxf(fabsf(y - h[1]) - h[4], 0.0f);
                 const float qz = fmaxf(fabsf(z - h[2]) - h[5], 0.0f);
                 q2 = fminf(q2, qx * qx + qy * qy + qz * qz);
+            };
+            if (g.cell_mask) {
+                uint32_t m = cand;
+                while (m) {
+                    const int i = __builtin_ctz(m);
+                    m &= m - 1u;
+                    hole(as_const(g.hole_f32) + 8 * i);
+                }
+            } else {
+                cfloat *h = as_const(g.hole_f32);
+#pragma unroll 4
+                for (int i = 0; i < g.n_holes; ++i, h += 8) hole(h);
             }
             d = fminf(d, __builtin_amdgcn_sqrtf(q2));
         }

@@ -25,6 +25,11 @@ struct DevGeom {
     const double *hole_ce;  // [n_holes][6]: centre xyz, half-extent xyz
     const double *hole_box; // [n_holes][6]: lo xyz, hi xyz
     const float *hole_f32;  // [n_holes][8]: centre xyz, half-extent xyz, 0, 0 (FP32)
+    // Grid over the box listing, per cell, the holes that can be nearest
+    // (bit i = hole i); NULL when not built (more than 32 holes).
+    const uint32_t *cell_mask;  // [cell_n0][cell_n1][cell_n2]
+    float cell_lo[3], cell_inv[3];
+    int32_t cell_n[3];
     const double *src;      // [n_src][4]
     double quad[10];
     double eps;
@@ -60,6 +65,8 @@ struct Geometry {
     std::vector<double> holes, src;
     double *d_hole_ce = nullptr, *d_hole_box = nullptr, *d_src = nullptr;
     float *d_hole_f32 = nullptr;
+    uint32_t *d_cell_mask = nullptr;
+    std::vector<uint32_t> cell_mask;
     int device = 0;
 };
 
@@ -104,6 +111,8 @@ struct Adaptive {
 dtn_status launch_wos(const Geometry &g, const double *pts, int64_t n, const int64_t *walks,
                       const int64_t *walk_begin, uint64_t seed, const uint32_t *stream_id,
                       int precision, double *stats, int64_t *capped, const Schedule &sc, hipStream_t stream);
+dtn_status launch_distance(const Geometry &g, const double *pts, int64_t n, int precision, double *dist,
+                           hipStream_t stream);
 dtn_status launch_wos_adaptive(const Geometry &g, const double *pts, int64_t n, const Adaptive &a, uint64_t seed,
                                const uint32_t *stream_id, int precision, double *stats, int64_t *walks_used,
                                int64_t *capped, const Schedule &sc, hipStream_t stream);

@@ -194,10 +194,13 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                     u2f = u01_f32(r3);
                 }
             }
+            // candidate holes of the walking lanes' cells (whole wave active here)
+            uint32_t cand = 0;
+            if constexpr (KIND == DTN_BOX_MINUS_BOXES) cand = hole_candidates(g, walking, x, y, z);
             bool fin = false;
             if (walking) {
                 if constexpr (PREC == DTN_FP64) {
-                    const double d = dist_f64<KIND>(g, x, y, z);
+                    const double d = dist_f64<KIND>(g, x, y, z, cand);
                     if (d < eps || (int64_t)nstep >= g.max_steps) {
                         fin = true;
                         capped += (d >= eps) ? 1ull : 0ull;
@@ -213,10 +216,10 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                     }
                 } else {
                     // FP32 distance; FP64 recheck inside the shell margin.
-                    double d = (double)(dist_f32<KIND>(g, (float)x, (float)y, (float)z) - fp32_margin);
+                    double d = (double)(dist_f32<KIND>(g, (float)x, (float)y, (float)z, cand) - fp32_margin);
                     bool stop = false;
                     if (d < (double)tau - (double)fp32_margin) {
-                        d = dist_f64<KIND>(g, x, y, z);
+                        d = dist_f64<KIND>(g, x, y, z, cand);
                         stop = d < eps;
                     }
                     if (stop || (int64_t)nstep >= g.max_steps) {
@@ -422,6 +425,34 @@ hipError_t walk_all(const Geometry &g, const double *pts, int64_t n, const int64
                : dispatch<DTN_FP32_MIXED>(g, pts, n, walks, walk_begin, seed, stream_id, stats, capped, sc, stream);
 }
 
+// ------------------------------------------------- distance (diagnostic)
+
+template <int KIND, int PREC>
+__global__ __launch_bounds__(256) void k_distance(DevGeom g, const double *__restrict__ pts, int64_t n,
+                                                  double *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = i < n;
+    const double x = live ? pts[3 * i] : 0.0, y = live ? pts[3 * i + 1] : 0.0, z = live ? pts[3 * i + 2] : 0.0;
+    uint32_t cand = 0;
+    if constexpr (KIND == DTN_BOX_MINUS_BOXES) cand = hole_candidates(g, live, x, y, z);
+    if (!live) return;
+    if constexpr (PREC == DTN_FP64) out[i] = dist_f64<KIND>(g, x, y, z, cand);
+    else out[i] = (double)dist_f32<KIND>(g, (float)x, (float)y, (float)z, cand);
+}
+
+template <int PREC>
+void distance_kind(const Geometry &g, const double *pts, int64_t n, double *out, hipStream_t s)
+{
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    switch (g.dev.kind) {
+    case DTN_BALL: hipLaunchKernelGGL((k_distance<DTN_BALL, PREC>), grid, block, 0, s, g.dev, pts, n, out); break;
+    case DTN_BOX: hipLaunchKernelGGL((k_distance<DTN_BOX, PREC>), grid, block, 0, s, g.dev, pts, n, out); break;
+    default:
+        hipLaunchKernelGGL((k_distance<DTN_BOX_MINUS_BOXES, PREC>), grid, block, 0, s, g.dev, pts, n, out);
+    }
+}
+
 // ------------------------------------------------------- adaptive budgets
 
 __global__ __launch_bounds__(256) void k_fill_i64(int64_t *__restrict__ a, int64_t n, int64_t v)
@@ -485,6 +516,17 @@ dtn_status launch_wos(const Geometry &g, const double *pts, int64_t n, const int
     if (n == 0) return DTN_OK;
     hipError_t e = walk_all(g, pts, n, walks, walk_begin, seed, stream_id, precision, stats, capped, sc, stream);
     if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_wos_eval: ") + hipGetErrorString(e));
+    return DTN_OK;
+}
+
+dtn_status launch_distance(const Geometry &g, const double *pts, int64_t n, int precision, double *dist,
+                           hipStream_t stream)
+{
+    if (n == 0) return DTN_OK;
+    if (precision == DTN_FP64) distance_kind<DTN_FP64>(g, pts, n, dist, stream);
+    else distance_kind<DTN_FP32_MIXED>(g, pts, n, dist, stream);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_boundary_distance: ") + hipGetErrorString(e));
     return DTN_OK;
 }
 

@@ -82,6 +82,7 @@ def lib():
         L.dtn_wos_time_schedules.argtypes = [vp, vp, C.c_int64, vp, vp, C.c_uint64, vp, C.c_int32,
                                              C.POINTER(ScheduleDesc), C.c_int32, C.c_int32, vp,
                                              C.POINTER(C.c_float), vp]
+        L.dtn_boundary_distance.argtypes = [vp, vp, C.c_int64, C.c_int32, vp, vp]
         L.dtn_create_plan.argtypes = [vp, C.POINTER(PatchDesc), C.c_int64, C.POINTER(vp)]
         L.dtn_destroy_plan.argtypes = [vp]
         L.dtn_destroy_plan.restype = None
@@ -96,6 +97,7 @@ def lib():
         L.dtn_class_operators.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
                                           dp, dp, dp, dp, dp, dp]
         for f in ("dtn_create_geometry", "dtn_wos_eval", "dtn_wos_adaptive", "dtn_wos_time_schedules",
+                  "dtn_boundary_distance",
                   "dtn_create_plan", "dtn_patch_nodes",
                   "dtn_patch_solve", "dtn_potential", "dtn_class_operators"):
             getattr(L, f).restype = C.c_int
@@ -187,6 +189,18 @@ def wos_eval(geom, pts, walks, seed, walk_begin=None, stream_id=None, precision=
                               C.c_uint64(int(seed) & (2 ** 64 - 1)), _ptr(stream_id), PRECISION[precision],
                               _ptr(stats), _ptr(capped), _stream()), "dtn_wos_eval")
     return stats, capped
+
+
+def boundary_distance(geom, pts, precision="fp64", out=None):
+    """Distance to the boundary as the walk kernels compute it (device [n])."""
+    n = pts.shape[0]
+    _dev_tensor(pts, torch.float64, (n, 3))
+    if out is None:
+        out = torch.empty((n,), dtype=torch.float64, device=pts.device)
+    _dev_tensor(out, torch.float64, (n,))
+    _check(lib().dtn_boundary_distance(geom.handle, _ptr(pts), n, PRECISION[precision], _ptr(out), _stream()),
+           "dtn_boundary_distance")
+    return out
 
 
 def wos_adaptive(geom, pts, seed, pilot_walks, min_walks, max_walks, se_target, stream_id=None,

@@ -160,3 +160,42 @@ def test_walk_ranges_compose_and_runs_are_deterministic():
     mixed = _gpu_wos(gd, big, 4000, seed=5, stream_id=np.arange(len(big)))
     np.testing.assert_allclose(mixed["mean"][:40], full["mean"], rtol=0, atol=1e-12)
     np.testing.assert_array_equal(mixed["steps"][:40], full["steps"])
+
+
+def test_boundary_distance_with_hole_grid_matches_oracle():
+    """The walk kernels find the nearest hole through a per-cell candidate
+    list; the distance must equal the plain minimum over all surfaces (to a
+    few ulps in FP64, within the FP32 path's rounding margin in FP32), also
+    on cell faces and next to hole faces, edges and corners."""
+    dtn = _dtn()
+    gd = I.geometry_box_holes()
+    holes = np.asarray(gd["holes"]).reshape(-1, 6)
+    rng = np.random.default_rng(12)
+    pts = [rng.uniform(0.0, 4.0, (20000, 3))]
+    grid = np.arange(1, 32) * 0.125  # cell faces of the 32^3 grid
+    q = rng.uniform(0.0, 4.0, (6000, 3))
+    k = rng.integers(0, 3, 6000)
+    q[np.arange(6000), k] = rng.choice(grid, 6000) + rng.choice([-1e-7, 0.0, 1e-7], 6000)
+    pts.append(q)
+    for h in holes:  # next to faces, edges and corners of every hole
+        lo, hi = h[:3], h[3:]
+        c = rng.uniform(lo, hi, (300, 3))
+        for m in range(300):
+            ax = rng.permutation(3)[: 1 + m % 3]
+            for a in ax:
+                c[m, a] = (lo[a] - 10 ** rng.uniform(-9, -1)) if rng.random() < 0.5 else (hi[a] + 10 ** rng.uniform(-9, -1))
+        pts.append(c)
+    pts = np.concatenate(pts)
+    inside = np.zeros(len(pts), bool)
+    for h in holes:
+        inside |= np.all((pts > h[:3]) & (pts < h[3:]), axis=1)
+    pts = pts[~inside & np.all((pts > 0) & (pts < 4), axis=1)]
+    d_ora, _ = OW.Geometry(gd).dist_proj(pts)
+    g = dtn.Geometry(gd)
+    P = torch.tensor(pts, device="cuda:0")
+    print(f"[gpu] boundary distance n={len(pts)}", flush=True)
+    d64 = dtn.boundary_distance(g, P, "fp64").cpu().numpy()
+    d32 = dtn.boundary_distance(g, P, "fp32").cpu().numpy()
+    assert np.max(np.abs(d64 - d_ora) / np.maximum(d_ora, 1e-300)) < 1e-14
+    margin = 32 * 4.0 * 2.0 ** -24  # the FP32 path's jump margin for this box
+    assert np.max(np.abs(d32 - d_ora)) < margin / 4
