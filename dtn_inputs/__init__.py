@@ -272,6 +272,59 @@ def box_holes_sample(pd, per_class=2, seed=4):
     return np.array(sorted(out), dtype=np.int64)
 
 
+def boundary_faces(gd):
+    """Faces of a box (with holes): rows (axis, plane, outward normal sign of
+    the domain, rect lo [3], rect hi [3])."""
+    lo_b, hi_b = np.asarray(gd["box_lo"], float), np.asarray(gd["box_hi"], float)
+    faces = []
+    for k in range(3):
+        faces.append((k, lo_b[k], -1.0, lo_b, hi_b))
+        faces.append((k, hi_b[k], 1.0, lo_b, hi_b))
+    for h in np.asarray(gd.get("holes", np.zeros((0, 6))), float).reshape(-1, 6):
+        for k in range(3):
+            faces.append((k, h[k], 1.0, h[:3], h[3:]))
+            faces.append((k, h[3 + k], -1.0, h[:3], h[3:]))
+    return faces
+
+
+def boundary_points(gd, n, rng, edge_gap=1e-4):
+    """n points uniform by area on the boundary of a box (with holes), with
+    their outward normals; points within edge_gap of a face edge are redrawn."""
+    faces = boundary_faces(gd)
+    area = np.array([(f[4][(f[0] + 1) % 3] - f[3][(f[0] + 1) % 3]) * (f[4][(f[0] + 2) % 3] - f[3][(f[0] + 2) % 3])
+                     for f in faces])
+    pts = np.empty((n, 3))
+    nrm = np.zeros((n, 3))
+    fi = rng.choice(len(faces), n, p=area / area.sum())
+    for i, f in enumerate(fi):
+        k, plane, sgn, lo, hi = faces[f]
+        a, b = (k + 1) % 3, (k + 2) % 3
+        while True:
+            u = rng.random(2)
+            pa = lo[a] + u[0] * (hi[a] - lo[a])
+            pb = lo[b] + u[1] * (hi[b] - lo[b])
+            if min(pa - lo[a], hi[a] - pa, pb - lo[b], hi[b] - pb) > edge_gap:
+                break
+        pts[i, k], pts[i, a], pts[i, b] = plane, pa, pb
+        nrm[i, k] = sgn
+    return pts, nrm
+
+
+def serving_queries(gd, n_queries=600, rate=200.0, seed=5, max_points=4096):
+    """Poisson arrivals at ``rate`` queries/s; each query has a point count
+    log-uniform on [1, max_points] and points uniform by area on the
+    boundary.  Returns a list of dicts (t, pts, normals, seed)."""
+    rng = np.random.default_rng([seed, 13])
+    t = np.cumsum(rng.exponential(1.0 / rate, n_queries))
+    out = []
+    for i in range(n_queries):
+        m = int(np.floor(np.exp(rng.random() * np.log(max_points + 1))))
+        m = min(max(m, 1), max_points)
+        pts, nrm = boundary_points(gd, m, rng)
+        out.append({"t": float(t[i]), "pts": pts, "normals": nrm, "seed": int(seed) * 1_000_003 + i})
+    return out
+
+
 # ----------------------------------------------------------------- configs
 
 CONFIGS = {
@@ -289,6 +342,21 @@ CONFIGS = {
         "min_walks": 1000,
         "max_walks": 200_000,
         "seed": 4,
+    },
+    "serving": {  # box_holes geometry resident, Poisson query arrivals
+        "geometry": geometry_box_holes,
+        "queries": serving_queries,
+        "rate": 200.0,
+        "n_queries": 600,
+        "se_target": 1e-3,
+        "pilot_walks": 100,
+        "min_walks": 100,
+        "max_walks": 1_000_000,
+        "h_max": 0.25,
+        "ladder": 16,
+        "layout": (8, 16, 4, 8),
+        "hbm_budget": 2 << 30,
+        "seed": 5,
     },
     "cube_1536": {  # unit cube, 6 x 16 x 16 patches, FP64
         "geometry": geometry_cube_sources,

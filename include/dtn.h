@@ -255,6 +255,70 @@ dtn_status dtn_patch_solve(dtn_plan p, const double *node_stats, int32_t precisi
 dtn_status dtn_potential(dtn_plan p, const double *neumann, const double *targets, int64_t m,
                          double *u_out, void *stream);
 
+/* ------------------------------------------------------------ serving
+ * A query server answers Neumann queries at boundary points: for every point
+ * of a query it places a patch centred on the point (step 2's layout below,
+ * h = h_max 2^-j for the smallest j that keeps the patch and its half ball
+ * inside Omega), runs step 1 with adaptive walks (dtn_adaptive with the
+ * query's se_target) and step 2, and answers with du/dn averaged over the
+ * patch's central ring of panels (the disk of radius h / n_rings), its
+ * standard error, the walks spent and h.  Queries run concurrently on
+ * several HIP streams of the current device (continuous batching: a query
+ * starts as soon as a stream is free and its device memory fits the budget;
+ * admission is first come, first served).  A query's walks are a function of
+ * its seed and its nodes only (stream id = node index within the query), so
+ * its answer does not depend on what else is in flight.
+ * Only box domains (with or without holes) are served: every point must lie
+ * on a face, with the face's outward normal. */
+typedef struct dtn_server_s *dtn_server; /* opaque, library-owned */
+
+typedef struct {
+    int32_t n_streams;   /* queries in flight at once, 1..16 */
+    int32_t precision;   /* DTN_FP64 or DTN_FP32_MIXED (walks and solve) */
+    int64_t hbm_budget;  /* bytes of device memory the queries in flight may hold */
+    int64_t pilot_walks, min_walks, max_walks; /* adaptive budget (dtn_adaptive) */
+    double h_max;        /* largest patch radius of the ladder, > 0 */
+    int32_t ladder;      /* number of rungs h_max 2^-j, j = 0..ladder-1, 1..40 */
+    int32_t n_theta, n_phi, n_rings, n_sectors; /* patch layout (as dtn_patch) */
+    int64_t max_points;  /* largest query, 1..2^20 (sizes pinned staging) */
+} dtn_server_config;
+
+/* Completion record of a query; times in seconds on the server's clock. */
+typedef struct {
+    uint64_t query_id;
+    int32_t status;      /* DTN_OK or the error that ended the query */
+    int32_t reserved;
+    int64_t n_points;
+    double t_submit, t_start, t_done;
+} dtn_query_done;
+
+/* Create / destroy a server on the current device.  Builds the patch class
+ * once.  Destroy waits for the queries in flight; queued ones are dropped.
+ * Errors: DTN_E_ARG for an invalid configuration or a geometry other than a
+ * box or a box with holes. */
+dtn_status dtn_server_create(dtn_geometry g, const dtn_server_config *cfg, dtn_server *out);
+void dtn_server_destroy(dtn_server s);
+
+/* Device bytes a query of n_points reserves under this configuration. */
+int64_t dtn_server_footprint(const dtn_server_config *cfg, int64_t n_points);
+
+/* Seconds since the server was created (the clock of dtn_query_done). */
+double dtn_server_clock(dtn_server s);
+
+/* Queue a query.  pts, normals: host [n][3] (copied); out: host [n][4]
+ * (value, standard error, walks, h per point), written when the query
+ * completes and owned by the caller, who keeps it allocated until then.
+ * Errors (synchronous, nothing queued): DTN_E_ARG for n outside [1, max_points],
+ * se_target <= 0, a point not on a face with that outward normal, or a point
+ * so close to an edge or another surface that no rung fits; DTN_E_OOM when
+ * the query alone exceeds the budget. */
+dtn_status dtn_server_submit(dtn_server s, uint64_t query_id, const double *pts, const double *normals,
+                             int64_t n, double se_target, uint64_t seed, double *out);
+
+/* Wait up to timeout_s seconds (< 0: forever) for completions and return up
+ * to max_n of them in completion order; *n_out = 0 on timeout. */
+dtn_status dtn_server_wait(dtn_server s, int64_t max_n, double timeout_s, dtn_query_done *done, int64_t *n_out);
+
 /* Diagnostic, host only (no device needed): the class operators that
  * dtn_create_plan builds for patches with this layout and curvature, in local
  * coordinates scaled by 1/h (rr = R/h on a sphere of radius R, 0 on a plane).

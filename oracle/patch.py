@@ -424,6 +424,21 @@ def patch_solve(p, geom, u_nodes, se_nodes=None, dl=None):
     return {"sigma": sigma, "se": se, "b": b, "x": xg, "normal": ng, "area": area, "r": r, "dl": DL}
 
 
+def central_disk_answer(p, geom, u_nodes, se_nodes):
+    """du/dn averaged over the ring-0 panels of a plane patch (the central
+    disk of radius h / n_rings, whose sectors have equal areas) and its
+    standard error, propagated through the same linear map as sigma
+    (Sec. 4, eqs. bw49-bw51; node errors independent)."""
+    r = patch_solve(p, geom, u_nodes)
+    K = single_layer_matrix(p.h, p.R, p.n_rings, p.n_sectors)
+    QI = gamma_operator(p.h, p.R, p.n_theta, p.n_phi, p.n_rings, p.n_sectors)
+    A = np.linalg.solve(K, QI)
+    row = A[: p.n_sectors].mean(axis=0)
+    value = float(r["sigma"][: p.n_sectors].mean())
+    se = float(np.sqrt(np.sum(row ** 2 * np.asarray(se_nodes, dtype=np.float64) ** 2)))
+    return value, se
+
+
 # ----------------------------------------------------------------- exact data
 
 

@@ -6,7 +6,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdtn.so")
-SOURCES = ["dtn_wos.hip", "dtn_patch.hip", "dtn_operators.cpp", "dtn_capi.cpp"]
+SOURCES = ["dtn_wos.hip", "dtn_patch.hip", "dtn_operators.cpp", "dtn_capi.cpp", "dtn_server.cpp"]
 
 
 def hipcc():
@@ -19,7 +19,7 @@ def hipcc():
 def build(verbose: bool = False, arch: str = "gfx950", extra=()) -> str:
     cmd = [hipcc(), f"--offload-arch={arch}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-command-line-argument",
+           "-Wno-unused-command-line-argument", "-pthread",
            *[os.path.join(CSRC, s) for s in SOURCES], "-o", LIB + ".tmp", *extra]
     if verbose:
         print(" ".join(cmd), flush=True)

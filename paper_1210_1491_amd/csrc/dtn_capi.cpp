@@ -92,6 +92,7 @@ dtn_status get_class(const ClassKey &key, int device, DevClass &out, bool &fresh
     UP(dl_w, dl_w)
     UP(fit, fit)
     UP(tile_gl, tile_gl)
+    UP(ans_row, ans_row)
 #undef UP
     if (e == hipSuccess) {
         e = upload(ops.piv, &ip);
@@ -242,6 +243,32 @@ bool check_plane_patch(const Geometry &g, const dtn_patch &p, std::string &why)
 
 }  // namespace
 
+bool plane_patch_ok(const Geometry &g, const dtn_patch &p, std::string &why) { return check_plane_patch(g, p, why); }
+
+dtn_status plane_class(int nt, int nf, int nr, int ns, DevClass &out)
+{
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("plane_class: ") + hipGetErrorString(e));
+    bool fresh = false;
+    const dtn_status st = get_class(ClassKey{nt, nf, nr, ns, 0.0}, device, out, fresh);
+    if (st != DTN_OK || !fresh) return st;
+    // FP32 LU factors of the new class on the device
+    std::lock_guard<std::mutex> lk(g_class_mu);
+    Plan tmp;
+    tmp.classes.resize(1);
+    tmp.classes[0].dev = out;
+    std::vector<DevClass> one{out};
+    e = upload(one, &tmp.d_classes);
+    if (e != hipSuccess) return fail(DTN_E_OOM, std::string("plane_class: ") + hipGetErrorString(e));
+    dtn_status s2 = launch_lu32(tmp, nullptr);
+    e = hipStreamSynchronize(nullptr);
+    (void)hipFree(tmp.d_classes);
+    if (s2 != DTN_OK) return s2;
+    if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("plane_class: ") + hipGetErrorString(e));
+    return DTN_OK;
+}
+
 void set_error(const std::string &msg) { g_last_error = msg; }
 dtn_status fail(dtn_status s, const std::string &msg)
 {
@@ -255,12 +282,6 @@ using namespace dtn;
 
 extern "C" {
 
-struct dtn_geometry_s {
-    Geometry g;
-};
-struct dtn_plan_s {
-    Plan p;
-};
 
 const char *dtn_last_error(void) { return g_last_error.c_str(); }
 const char *dtn_version(void) { return "dtn-wos-mi355x 0.1 (gfx950)"; }

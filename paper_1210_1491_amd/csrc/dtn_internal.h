@@ -57,6 +57,7 @@ struct DevClass {
     const double *dl_w;       // [n_panels][n_dl] weights (kernel x area) at h = 1
     const double *fit;        // [16][n_panels] tile fit (flat classes)
     const double *tile_gl;    // [16][3]: (xi, eta, weight) on [-1,1]^2
+    const double *ans_row;    // [n_nodes]: ring-0 mean of the rows of K^-1 QI at h = 1
 };
 
 struct Geometry {
@@ -125,14 +126,31 @@ dtn_status launch_potential(const Plan &p, const double *neumann, const double *
                             double *u_out, hipStream_t stream);
 dtn_status launch_lu32(const Plan &p, hipStream_t stream);
 
+// Plan helpers shared with the query server (dtn_capi.cpp).
+bool plane_patch_ok(const Geometry &g, const dtn_patch &p, std::string &why);
+dtn_status plane_class(int nt, int nf, int nr, int ns, DevClass &out);  // cached, FP32 LU included
+
+// Central-disk answer per patch (dtn_patch.hip): mean of the ring-0 panels'
+// sigma, its standard error, the walks spent on the patch and h.
+dtn_status launch_answer(const Plan &p, const double *neumann, const double *node_stats, const int64_t *walks_used,
+                         double *ans, hipStream_t stream);
+
 // Host operator construction (dtn_operators.cpp).
 struct ClassOps {
     int n_theta, n_phi, n_rings, n_sectors;
     double rr;  // R/h (0 = plane)
-    std::vector<double> node_tab, col_tab, K, LU, QI, A2, dl_pts, dl_w, fit, tile_gl;
+    std::vector<double> node_tab, col_tab, K, LU, QI, A2, dl_pts, dl_w, fit, tile_gl, ans_row;
     std::vector<int32_t> piv;
     int n_dl = 0;
 };
 bool build_class_ops(ClassOps &ops, std::string &err);
 
 }  // namespace dtn
+
+// The opaque handles of the C-ABI.
+struct dtn_geometry_s {
+    dtn::Geometry g;
+};
+struct dtn_plan_s {
+    dtn::Plan p;
+};

@@ -15,6 +15,8 @@
 //             sphere (the double-layer term of b, weakly singular there)
 //   LU, A2    LU factors of K (partial pivoting), and (K^-1 Q.I)^2 for the
 //             propagation of the node standard errors
+//   ans_row   mean over the ring-0 panels of the rows of K^-1 Q.I (standard
+//             error of the central-disk mean of sigma)
 //   fit       tile fit used by the potential (least-squares quadratic through
 //             the panels within 0.7 of the centre, at 4x4 Gauss points)
 //
@@ -438,13 +440,18 @@ bool build_class_ops(ClassOps &ops, std::string &err)
             }
     }
 
-    // ---- A2 = (K^-1 Q.I)^2
+    // ---- A2 = (K^-1 Q.I)^2, and the ring-0 row: the mean over the central
+    // ring's panels (equal areas on a plane patch) of K^-1 Q.I
     ops.A2.assign((size_t)Np * Nn, 0.0);
+    ops.ans_row.assign((size_t)Nn, 0.0);
     std::vector<double> col(Np);
     for (int k = 0; k < Nn; ++k) {
         for (int i = 0; i < Np; ++i) col[i] = ops.QI[(size_t)i * Nn + k];
         lu_solve(Np, ops.LU, ops.piv, col.data());
         for (int i = 0; i < Np; ++i) ops.A2[(size_t)i * Nn + k] = col[i] * col[i];
+        double r = 0.0;
+        for (int i = 0; i < ops.n_sectors; ++i) r += col[i];
+        ops.ans_row[k] = r / ops.n_sectors;
     }
 
     // ---- double-layer rows (curved patches only)

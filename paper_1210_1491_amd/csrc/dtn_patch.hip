@@ -449,6 +449,59 @@ dtn_status launch_solve(const Plan &p, const double *node_stats, int precision, 
     return DTN_OK;
 }
 
+// One wave per patch: sigma averaged over the ring-0 panels (the central
+// disk, equal panel areas on a plane patch); its standard error from the
+// node standard errors through the class's ring-0 row of K^-1 QI (scaled by
+// 1/h like sigma); the walks spent on the patch; h.  ans [n][4].
+__global__ __launch_bounds__(256) void k_answer(const dtn_patch *__restrict__ patches,
+                                                const int32_t *__restrict__ pclass,
+                                                const DevClass *__restrict__ classes,
+                                                const int64_t *__restrict__ node_off,
+                                                const int64_t *__restrict__ panel_off,
+                                                const double *__restrict__ neumann,
+                                                const double *__restrict__ node_stats,
+                                                const int64_t *__restrict__ walks_used, int64_t n,
+                                                double *__restrict__ ans)
+{
+    const int64_t pi = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (pi >= n) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const DevClass &cl = classes[pclass[pi]];
+    const double h = patches[pi].h;
+    const int64_t nb = node_off[pi], pb = panel_off[pi];
+    double v = 0.0, w = 0.0;
+    for (int k = lane; k < cl.n_nodes; k += kWave) {
+        const double *st = node_stats + 4 * (nb + k);
+        const double se2 = st[0] > 1.0 ? st[2] / ((st[0] - 1.0) * st[0]) : 0.0;
+        const double a = cl.ans_row[k];
+        v += a * a * se2;
+        w += (double)walks_used[nb + k];
+    }
+    double m = 0.0;
+    for (int i = lane; i < cl.n_sectors; i += kWave) m += neumann[pb + i];
+    v = wave_sum(v);
+    w = wave_sum(w);
+    m = wave_sum(m);
+    if (lane == 0) {
+        ans[4 * pi] = m / cl.n_sectors;
+        ans[4 * pi + 1] = sqrt(v) / h;
+        ans[4 * pi + 2] = w;
+        ans[4 * pi + 3] = h;
+    }
+}
+
+dtn_status launch_answer(const Plan &p, const double *neumann, const double *node_stats, const int64_t *walks_used,
+                         double *ans, hipStream_t s)
+{
+    const int64_t n = (int64_t)p.patches.size();
+    if (n == 0) return DTN_OK;
+    hipLaunchKernelGGL(k_answer, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, p.d_patches, p.d_patch_class,
+                       p.d_classes, p.d_node_off, p.d_panel_off, neumann, node_stats, walks_used, n, ans);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("answer: ") + hipGetErrorString(e));
+    return DTN_OK;
+}
+
 dtn_status launch_lu32(const Plan &p, hipStream_t s)
 {
     hipLaunchKernelGGL(k_lu32, dim3((unsigned)p.classes.size()), dim3(kLuBlock), 0, s, p.d_classes);

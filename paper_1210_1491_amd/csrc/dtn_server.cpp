@@ -1,0 +1,492 @@
+// Query server: continuous batching of Neumann queries over HIP streams.
+//
+// A query is a set of boundary points.  Each point gets a patch centred on
+// it (one patch class for the whole server, h from a ladder h_max 2^-j), and
+// the query runs the whole path on one stream: nodes, adaptive walks (pilot,
+// budgets, remainder, merge), the collocation solve, the central-disk answer
+// and the copy back, all stream-ordered, with its device memory taken from
+// the stream-ordered pool.  A dispatcher thread admits queued queries first
+// come, first served, whenever a stream is free and the query's device
+// memory fits under the budget next to the queries in flight; a host
+// function enqueued behind the query's work records its completion, copies
+// the answers out of pinned staging and releases the stream and the memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "dtn_internal.h"
+
+namespace dtn {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Query {
+    uint64_t id = 0;
+    std::vector<dtn_patch> patches;
+    double se = 0.0;
+    uint64_t seed = 0;
+    double *out = nullptr;
+    int64_t bytes = 0;
+    double t_submit = 0.0, t_start = 0.0;
+    int slot = -1;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    dtn_patch *h_patches = nullptr;  // pinned staging, [max_points]
+    double *h_ans = nullptr;         // pinned staging, [max_points][4]
+    bool busy = false;
+};
+
+// Offsets of one query's arrays inside its single device allocation.
+struct Layout {
+    size_t patches, nodes, stats, used, capped, neu, nse, ans, total;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+Layout layout(int64_t n, int64_t nn, int64_t np)
+{
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += align256(bytes);
+        return at;
+    };
+    L.patches = take(sizeof(dtn_patch) * (size_t)n);
+    L.nodes = take(sizeof(double) * 3 * (size_t)(n * nn));
+    L.stats = take(sizeof(double) * 4 * (size_t)(n * nn));
+    L.used = take(sizeof(int64_t) * (size_t)(n * nn));
+    L.capped = take(sizeof(int64_t) * (size_t)(n * nn));
+    L.neu = take(sizeof(double) * (size_t)(n * np));
+    L.nse = take(sizeof(double) * (size_t)(n * np));
+    L.ans = take(sizeof(double) * 4 * (size_t)n);
+    L.total = o;
+    return L;
+}
+
+// Device bytes of a query: its arrays plus the walk kernels' stream-ordered
+// scratch (adaptive statistics and budgets; chunk table and partials for up
+// to nodes + 256 CUs x 32 waves x 4 chunks, the default schedule on MI355X).
+int64_t footprint(const dtn_server_config &c, int64_t n)
+{
+    const int64_t nn = (int64_t)c.n_theta * c.n_phi, np = (int64_t)c.n_rings * c.n_sectors;
+    const int64_t nodes = n * nn;
+    const int64_t adaptive = nodes * (4 * 8 + 5 * 8);
+    const int64_t walk = 8 * (nodes + 1) + 80 + 48 * (nodes + 256 * 32 * 4 + 1);
+    return (int64_t)layout(n, nn, np).total + adaptive + walk;
+}
+
+double box_distance(const double *x, const double *lo, const double *hi)
+{
+    double s = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double q = std::max({lo[k] - x[k], 0.0, x[k] - hi[k]});
+        s += q * q;
+    }
+    return std::sqrt(s);
+}
+
+bool valid_config(const dtn_server_config &c, std::string &why)
+{
+    if (c.n_streams < 1 || c.n_streams > 16) why = "n_streams outside [1, 16]";
+    else if (c.precision != DTN_FP64 && c.precision != DTN_FP32_MIXED) why = "unknown precision";
+    else if (c.hbm_budget <= 0) why = "hbm_budget must be positive";
+    else if (c.pilot_walks < 2 || c.min_walks < 1 || c.min_walks > c.max_walks || c.max_walks > ((int64_t)1 << 40))
+        why = "need pilot_walks >= 2 and 1 <= min_walks <= max_walks <= 2^40";
+    else if (!(c.h_max > 0.0) || !std::isfinite(c.h_max)) why = "h_max must be positive";
+    else if (c.ladder < 1 || c.ladder > 40) why = "ladder outside [1, 40]";
+    else if (c.n_theta < 2 || c.n_theta > 32 || c.n_phi < 4 || c.n_phi > 64 || (c.n_phi & 1) || c.n_rings < 1 ||
+             c.n_rings > 16 || c.n_sectors < 2 || c.n_sectors > 32 || c.n_rings * c.n_sectors > 128)
+        why = "unsupported patch layout";
+    else if (c.max_points < 1 || c.max_points > ((int64_t)1 << 20)) why = "max_points outside [1, 2^20]";
+    else return true;
+    return false;
+}
+
+}  // namespace
+}  // namespace dtn
+
+using namespace dtn;
+
+struct dtn_server_s {
+    Geometry *g = nullptr;
+    dtn_server_config cfg{};
+    int device = 0;
+    DevClass *d_class = nullptr;     // the patch class, [1]
+    int32_t *d_zero = nullptr;       // class index of every patch, [max_points]
+    int64_t *d_node_off = nullptr;   // i * nodes per patch, [max_points + 1]
+    int64_t *d_panel_off = nullptr;  // i * panels per patch, [max_points + 1]
+    int64_t nn = 0, np = 0;
+    std::vector<Slot> slots;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Query *> pending;
+    std::deque<dtn_query_done> done;
+    int64_t in_use = 0;
+    int busy = 0;
+    bool stop = false;
+    std::thread dispatcher;
+    Clock::time_point t0;
+
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+};
+
+namespace {
+
+struct Completion {
+    dtn_server_s *S;
+    Query *q;
+};
+
+// Finish a query (lock held): release its stream and memory, record it.
+void finish_locked(dtn_server_s *S, Query *q, int status)
+{
+    dtn_query_done d{};
+    d.query_id = q->id;
+    d.status = status;
+    d.n_points = (int64_t)q->patches.size();
+    d.t_submit = q->t_submit;
+    d.t_start = q->t_start;
+    d.t_done = S->now();
+    S->in_use -= q->bytes;
+    if (q->slot >= 0) {
+        S->slots[q->slot].busy = false;
+        --S->busy;
+    }
+    S->done.push_back(d);
+    delete q;
+    S->cv.notify_all();
+}
+
+// Host function behind a query's work on its stream (no HIP calls here).
+void on_done(void *arg)
+{
+    std::unique_ptr<Completion> c((Completion *)arg);
+    dtn_server_s *S = c->S;
+    Query *q = c->q;
+    std::memcpy(q->out, S->slots[q->slot].h_ans, sizeof(double) * 4 * q->patches.size());
+    std::lock_guard<std::mutex> lk(S->mu);
+    finish_locked(S, q, DTN_OK);
+}
+
+dtn_status enqueue(dtn_server_s *S, Query *q)
+{
+    Slot &sl = S->slots[q->slot];
+    hipStream_t s = sl.stream;
+    const int64_t n = (int64_t)q->patches.size();
+    const Layout L = layout(n, S->nn, S->np);
+    std::memcpy(sl.h_patches, q->patches.data(), sizeof(dtn_patch) * n);
+    char *buf = nullptr;
+    hipError_t e = hipMallocAsync((void **)&buf, L.total, s);
+    if (e != hipSuccess) return fail(DTN_E_OOM, std::string("server: ") + hipGetErrorString(e));
+    Plan P;
+    P.geom = S->g;
+    P.patches.resize(n);  // launch sizes only; the descriptors are on the device
+    P.d_patches = (dtn_patch *)(buf + L.patches);
+    P.d_patch_class = S->d_zero;
+    P.d_classes = S->d_class;
+    P.d_node_off = S->d_node_off;
+    P.d_panel_off = S->d_panel_off;
+    double *nodes = (double *)(buf + L.nodes), *stats = (double *)(buf + L.stats);
+    int64_t *used = (int64_t *)(buf + L.used), *capped = (int64_t *)(buf + L.capped);
+    double *neu = (double *)(buf + L.neu), *nse = (double *)(buf + L.nse), *ans = (double *)(buf + L.ans);
+    dtn_status st = DTN_OK;
+    e = hipMemcpyAsync(P.d_patches, sl.h_patches, sizeof(dtn_patch) * n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) st = fail(DTN_E_DEVICE, std::string("server: ") + hipGetErrorString(e));
+    if (st == DTN_OK) st = launch_nodes(P, nodes, s);
+    if (st == DTN_OK) {
+        const Adaptive a{S->cfg.pilot_walks, S->cfg.min_walks, S->cfg.max_walks, q->se};
+        st = launch_wos_adaptive(*S->g, nodes, n * S->nn, a, q->seed, nullptr, S->cfg.precision, stats, used, capped,
+                                 Schedule{}, s);
+    }
+    if (st == DTN_OK) st = launch_solve(P, stats, S->cfg.precision, neu, nse, s);
+    if (st == DTN_OK) st = launch_answer(P, neu, stats, used, ans, s);
+    if (st == DTN_OK) {
+        e = hipMemcpyAsync(sl.h_ans, ans, sizeof(double) * 4 * n, hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) st = fail(DTN_E_DEVICE, std::string("server: ") + hipGetErrorString(e));
+    }
+    const hipError_t ef = hipFreeAsync(buf, s);
+    if (st == DTN_OK && ef != hipSuccess) st = fail(DTN_E_DEVICE, std::string("server: ") + hipGetErrorString(ef));
+    if (st != DTN_OK) return st;
+    Completion *c = new Completion{S, q};
+    e = hipLaunchHostFunc(s, on_done, c);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(DTN_E_DEVICE, std::string("server: ") + hipGetErrorString(e));
+    }
+    return DTN_OK;
+}
+
+void dispatch_loop(dtn_server_s *S)
+{
+    (void)hipSetDevice(S->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    const int ns = (int)S->slots.size();
+    for (;;) {
+        S->cv.wait(lk, [&] {
+            return S->stop || (!S->pending.empty() && S->busy < ns &&
+                               S->in_use + S->pending.front()->bytes <= S->cfg.hbm_budget);
+        });
+        if (S->stop) return;
+        Query *q = S->pending.front();
+        S->pending.pop_front();
+        int slot = 0;
+        while (S->slots[slot].busy) ++slot;
+        S->slots[slot].busy = true;
+        ++S->busy;
+        S->in_use += q->bytes;
+        q->slot = slot;
+        q->t_start = S->now();
+        lk.unlock();
+        const dtn_status st = enqueue(S, q);
+        lk.lock();
+        if (st != DTN_OK) finish_locked(S, q, st);
+    }
+}
+
+// Patch centred on a boundary point; false with a reason when none fits.
+bool place_patch(const dtn_server_s *S, const double *x, const double *nrm, dtn_patch &p, std::string &why)
+{
+    const Geometry &G = *S->g;
+    int k = -1;
+    for (int a = 0; a < 3; ++a)
+        if (std::fabs(std::fabs(nrm[a]) - 1.0) < 1e-12) k = a;
+    if (k < 0 || std::fabs(nrm[(k + 1) % 3]) > 1e-12 || std::fabs(nrm[(k + 2) % 3]) > 1e-12) {
+        why = "normal is not an axis direction";
+        return false;
+    }
+    const double sgn = nrm[k] > 0 ? 1.0 : -1.0;
+    const int a = (k + 1) % 3, b = (k + 2) % 3;
+    const double *lo = G.dev.lo, *hi = G.dev.hi;
+    const double scale = 1.0 + std::max({std::fabs(lo[0]), std::fabs(lo[1]), std::fabs(lo[2]), std::fabs(hi[0]),
+                                         std::fabs(hi[1]), std::fabs(hi[2])});
+    const double tol = 1e-9 * scale;
+    auto within = [&](const double *rlo, const double *rhi) {
+        return x[a] >= rlo[a] - tol && x[a] <= rhi[a] + tol && x[b] >= rlo[b] - tol && x[b] <= rhi[b] + tol;
+    };
+    int own = -2;
+    double plane = 0.0;
+    const double *rlo = nullptr, *rhi = nullptr;
+    const double outer = sgn < 0 ? lo[k] : hi[k];
+    if (std::fabs(x[k] - outer) <= tol && within(lo, hi)) {
+        own = -1;
+        plane = outer;
+        rlo = lo;
+        rhi = hi;
+    }
+    for (int i = 0; i < G.dev.n_holes && own == -2; ++i) {
+        const double *hl = &G.holes[6 * i], *hh = hl + 3;
+        const double hp = sgn > 0 ? hl[k] : hh[k];  // the outward normal of Omega points into the hole
+        if (std::fabs(x[k] - hp) <= tol && within(hl, hh)) {
+            own = i;
+            plane = hp;
+            rlo = hl;
+            rhi = hh;
+        }
+    }
+    if (own == -2) {
+        why = "point is not on a face with this outward normal";
+        return false;
+    }
+    double c[3] = {x[0], x[1], x[2]};
+    c[k] = plane;
+    double cap = std::min({c[a] - rlo[a], rhi[a] - c[a], c[b] - rlo[b], rhi[b] - c[b]});
+    for (int k2 = 0; k2 < 3; ++k2) {
+        if (!(own == -1 && k2 == k && sgn < 0)) cap = std::min(cap, std::fabs(c[k2] - lo[k2]));
+        if (!(own == -1 && k2 == k && sgn > 0)) cap = std::min(cap, std::fabs(hi[k2] - c[k2]));
+    }
+    for (int i = 0; i < G.dev.n_holes; ++i)
+        if (i != own) cap = std::min(cap, box_distance(c, &G.holes[6 * i], &G.holes[6 * i + 3]));
+    double h = S->cfg.h_max;
+    int j = 0;
+    while (j < S->cfg.ladder && !(h <= cap * (1.0 - 1e-9))) {
+        h *= 0.5;
+        ++j;
+    }
+    if (j == S->cfg.ladder) {
+        why = "too close to an edge or another surface for the smallest patch of the ladder";
+        return false;
+    }
+    for (int q = 0; q < 3; ++q) {
+        p.c[q] = c[q];
+        p.n[q] = q == k ? sgn : 0.0;
+        p.t1[q] = q == a ? 1.0 : 0.0;
+    }
+    p.h = h;
+    p.n_theta = S->cfg.n_theta;
+    p.n_phi = S->cfg.n_phi;
+    p.n_rings = S->cfg.n_rings;
+    p.n_sectors = S->cfg.n_sectors;
+    return plane_patch_ok(G, p, why);
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t dtn_server_footprint(const dtn_server_config *cfg, int64_t n_points)
+{
+    std::string why;
+    if (!cfg || n_points < 0 || !valid_config(*cfg, why)) return -1;
+    return footprint(*cfg, n_points);
+}
+
+dtn_status dtn_server_create(dtn_geometry g, const dtn_server_config *cfg, dtn_server *out)
+{
+    const std::string at = "dtn_server_create: ";
+    try {
+        if (!g || !cfg || !out) return fail(DTN_E_ARG, at + "NULL argument");
+        *out = nullptr;
+        std::string why;
+        if (!valid_config(*cfg, why)) return fail(DTN_E_ARG, at + why);
+        Geometry *G = &g->g;
+        if (G->dev.kind == DTN_BALL) return fail(DTN_E_ARG, at + "only box domains (with or without holes) are served");
+        std::unique_ptr<dtn_server_s> S(new dtn_server_s());
+        S->g = G;
+        S->cfg = *cfg;
+        S->nn = (int64_t)cfg->n_theta * cfg->n_phi;
+        S->np = (int64_t)cfg->n_rings * cfg->n_sectors;
+        hipError_t e = hipGetDevice(&S->device);
+        if (e != hipSuccess) return fail(DTN_E_DEVICE, at + hipGetErrorString(e));
+        DevClass cls{};
+        dtn_status st = plane_class(cfg->n_theta, cfg->n_phi, cfg->n_rings, cfg->n_sectors, cls);
+        if (st != DTN_OK) return st;
+        const int64_t mp = cfg->max_points;
+        std::vector<int64_t> noff(mp + 1), poff(mp + 1);
+        for (int64_t i = 0; i <= mp; ++i) {
+            noff[i] = i * S->nn;
+            poff[i] = i * S->np;
+        }
+        auto cleanup = [&]() {
+            (void)hipFree(S->d_class);
+            (void)hipFree(S->d_zero);
+            (void)hipFree(S->d_node_off);
+            (void)hipFree(S->d_panel_off);
+            for (Slot &sl : S->slots) {
+                if (sl.stream) (void)hipStreamDestroy(sl.stream);
+                if (sl.h_patches) (void)hipHostFree(sl.h_patches);
+                if (sl.h_ans) (void)hipHostFree(sl.h_ans);
+            }
+        };
+        e = hipMalloc((void **)&S->d_class, sizeof(DevClass));
+        if (e == hipSuccess) e = hipMemcpy(S->d_class, &cls, sizeof(DevClass), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMalloc((void **)&S->d_zero, sizeof(int32_t) * mp);
+        if (e == hipSuccess) e = hipMemset(S->d_zero, 0, sizeof(int32_t) * mp);
+        if (e == hipSuccess) e = hipMalloc((void **)&S->d_node_off, sizeof(int64_t) * (mp + 1));
+        if (e == hipSuccess)
+            e = hipMemcpy(S->d_node_off, noff.data(), sizeof(int64_t) * (mp + 1), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMalloc((void **)&S->d_panel_off, sizeof(int64_t) * (mp + 1));
+        if (e == hipSuccess)
+            e = hipMemcpy(S->d_panel_off, poff.data(), sizeof(int64_t) * (mp + 1), hipMemcpyHostToDevice);
+        S->slots.resize(cfg->n_streams);
+        for (Slot &sl : S->slots) {
+            if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipHostMalloc((void **)&sl.h_patches, sizeof(dtn_patch) * mp);
+            if (e == hipSuccess) e = hipHostMalloc((void **)&sl.h_ans, sizeof(double) * 4 * mp);
+        }
+        if (e != hipSuccess) {
+            cleanup();
+            return fail(DTN_E_OOM, at + hipGetErrorString(e));
+        }
+        S->t0 = Clock::now();
+        dtn_server_s *raw = S.get();
+        S->dispatcher = std::thread(dispatch_loop, raw);
+        *out = S.release();
+        return DTN_OK;
+    } catch (...) {
+        return fail(DTN_E_OOM, at + "exception");
+    }
+}
+
+void dtn_server_destroy(dtn_server s)
+{
+    if (!s) return;
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv.notify_all();
+    }
+    if (s->dispatcher.joinable()) s->dispatcher.join();
+    {
+        // queries in flight still complete through their host functions
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv.wait(lk, [&] { return s->busy == 0; });
+        for (Query *q : s->pending) delete q;
+        s->pending.clear();
+    }
+    for (Slot &sl : s->slots) {
+        (void)hipStreamSynchronize(sl.stream);
+        (void)hipStreamDestroy(sl.stream);
+        (void)hipHostFree(sl.h_patches);
+        (void)hipHostFree(sl.h_ans);
+    }
+    (void)hipFree(s->d_class);
+    (void)hipFree(s->d_zero);
+    (void)hipFree(s->d_node_off);
+    (void)hipFree(s->d_panel_off);
+    delete s;
+}
+
+double dtn_server_clock(dtn_server s) { return s ? s->now() : -1.0; }
+
+dtn_status dtn_server_submit(dtn_server s, uint64_t query_id, const double *pts, const double *normals, int64_t n,
+                             double se_target, uint64_t seed, double *out)
+{
+    const std::string at = "dtn_server_submit: ";
+    try {
+        if (!s || !pts || !normals || !out) return fail(DTN_E_ARG, at + "NULL argument");
+        if (n < 1 || n > s->cfg.max_points) return fail(DTN_E_ARG, at + "n outside [1, max_points]");
+        if (!(se_target > 0.0) || !std::isfinite(se_target) || !(se_target * se_target > 0.0))
+            return fail(DTN_E_ARG, at + "se_target must be positive and finite");
+        std::unique_ptr<Query> q(new Query());
+        q->id = query_id;
+        q->se = se_target;
+        q->seed = seed;
+        q->out = out;
+        q->patches.resize(n);
+        std::string why;
+        for (int64_t i = 0; i < n; ++i)
+            if (!place_patch(s, pts + 3 * i, normals + 3 * i, q->patches[i], why))
+                return fail(DTN_E_ARG, at + "point " + std::to_string(i) + ": " + why);
+        q->bytes = footprint(s->cfg, n);
+        if (q->bytes > s->cfg.hbm_budget) return fail(DTN_E_OOM, at + "query exceeds the device memory budget");
+        std::lock_guard<std::mutex> lk(s->mu);
+        q->t_submit = s->now();
+        s->pending.push_back(q.release());
+        s->cv.notify_all();
+        return DTN_OK;
+    } catch (...) {
+        return fail(DTN_E_OOM, at + "exception");
+    }
+}
+
+dtn_status dtn_server_wait(dtn_server s, int64_t max_n, double timeout_s, dtn_query_done *done, int64_t *n_out)
+{
+    if (!s || !done || !n_out || max_n < 1) return fail(DTN_E_ARG, "dtn_server_wait: bad argument");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto ready = [&] { return !s->done.empty(); };
+    if (timeout_s < 0) s->cv.wait(lk, ready);
+    else s->cv.wait_for(lk, std::chrono::duration<double>(timeout_s), ready);
+    int64_t k = 0;
+    while (k < max_n && !s->done.empty()) {
+        done[k++] = s->done.front();
+        s->done.pop_front();
+    }
+    *n_out = k;
+    return DTN_OK;
+}
+
+}  // extern "C"

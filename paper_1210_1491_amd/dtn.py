@@ -53,6 +53,19 @@ class AdaptiveDesc(C.Structure):
                 ("se_target", C.c_double)]
 
 
+class ServerConfigDesc(C.Structure):
+    _fields_ = [("n_streams", C.c_int32), ("precision", C.c_int32), ("hbm_budget", C.c_int64),
+                ("pilot_walks", C.c_int64), ("min_walks", C.c_int64), ("max_walks", C.c_int64),
+                ("h_max", C.c_double), ("ladder", C.c_int32), ("n_theta", C.c_int32), ("n_phi", C.c_int32),
+                ("n_rings", C.c_int32), ("n_sectors", C.c_int32), ("max_points", C.c_int64)]
+
+
+class QueryDoneDesc(C.Structure):
+    _fields_ = [("query_id", C.c_uint64), ("status", C.c_int32), ("reserved", C.c_int32),
+                ("n_points", C.c_int64), ("t_submit", C.c_double), ("t_start", C.c_double),
+                ("t_done", C.c_double)]
+
+
 def schedule_struct(sched):
     """dict(min_chunk=..., oversub=...) (or None) -> ScheduleDesc (or None)."""
     if sched is None:
@@ -83,6 +96,15 @@ def lib():
                                              C.POINTER(ScheduleDesc), C.c_int32, C.c_int32, vp,
                                              C.POINTER(C.c_float), vp]
         L.dtn_boundary_distance.argtypes = [vp, vp, C.c_int64, C.c_int32, vp, vp]
+        L.dtn_server_create.argtypes = [vp, C.POINTER(ServerConfigDesc), C.POINTER(vp)]
+        L.dtn_server_destroy.argtypes = [vp]
+        L.dtn_server_destroy.restype = None
+        L.dtn_server_footprint.argtypes = [C.POINTER(ServerConfigDesc), C.c_int64]
+        L.dtn_server_footprint.restype = C.c_int64
+        L.dtn_server_clock.argtypes = [vp]
+        L.dtn_server_clock.restype = C.c_double
+        L.dtn_server_submit.argtypes = [vp, C.c_uint64, vp, vp, C.c_int64, C.c_double, C.c_uint64, vp]
+        L.dtn_server_wait.argtypes = [vp, C.c_int64, C.c_double, C.POINTER(QueryDoneDesc), C.POINTER(C.c_int64)]
         L.dtn_create_plan.argtypes = [vp, C.POINTER(PatchDesc), C.c_int64, C.POINTER(vp)]
         L.dtn_destroy_plan.argtypes = [vp]
         L.dtn_destroy_plan.restype = None
@@ -97,7 +119,7 @@ def lib():
         L.dtn_class_operators.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
                                           dp, dp, dp, dp, dp, dp]
         for f in ("dtn_create_geometry", "dtn_wos_eval", "dtn_wos_adaptive", "dtn_wos_time_schedules",
-                  "dtn_boundary_distance",
+                  "dtn_boundary_distance", "dtn_server_create", "dtn_server_submit", "dtn_server_wait",
                   "dtn_create_plan", "dtn_patch_nodes",
                   "dtn_patch_solve", "dtn_potential", "dtn_class_operators"):
             getattr(L, f).restype = C.c_int
@@ -325,3 +347,70 @@ def class_operators(n_theta, n_phi, n_rings, n_sectors, rr=0.0):
     args = [out[k].ctypes.data_as(dp) for k in ("node_tab", "col_tab", "K", "QI", "A2", "fit")]
     _check(lib().dtn_class_operators(n_theta, n_phi, n_rings, n_sectors, float(rr), *args), "dtn_class_operators")
     return out
+
+
+class Server:
+    """Query server (continuous batching over HIP streams, native dispatcher).
+
+    Each query is a set of boundary points; the answer per point is du/dn
+    averaged over the central ring of panels of a patch centred on it, with
+    its standard error, the walks spent and the patch radius h."""
+
+    def __init__(self, geom, n_streams=4, precision="fp64", hbm_budget=2 << 30, pilot_walks=100, min_walks=100,
+                 max_walks=1_000_000, h_max=0.25, ladder=16, layout=(8, 16, 4, 8), max_points=4096):
+        self.geom = geom
+        self.cfg = ServerConfigDesc(int(n_streams), PRECISION[precision], int(hbm_budget), int(pilot_walks),
+                                    int(min_walks), int(max_walks), float(h_max), int(ladder), *map(int, layout),
+                                    int(max_points))
+        self.handle = C.c_void_p()
+        _check(lib().dtn_server_create(geom.handle, C.byref(self.cfg), C.byref(self.handle)), "dtn_server_create")
+        self._out = {}
+
+    def footprint(self, n_points):
+        return int(lib().dtn_server_footprint(C.byref(self.cfg), int(n_points)))
+
+    def clock(self):
+        return float(lib().dtn_server_clock(self.handle))
+
+    def submit(self, query_id, pts, normals, se_target, seed):
+        pts = np.ascontiguousarray(np.asarray(pts, np.float64).reshape(-1, 3))
+        nrm = np.ascontiguousarray(np.asarray(normals, np.float64).reshape(-1, 3))
+        if nrm.shape != pts.shape:
+            raise ValueError("pts and normals must have the same shape")
+        out = np.full((pts.shape[0], 4), np.nan)
+        qid = int(query_id)
+        if qid in self._out:
+            raise ValueError(f"query id {qid} is still in flight")
+        self._out[qid] = (out, pts, nrm)
+        st = lib().dtn_server_submit(self.handle, C.c_uint64(qid), pts.ctypes.data, nrm.ctypes.data,
+                                     pts.shape[0], float(se_target), C.c_uint64(int(seed) & (2 ** 64 - 1)),
+                                     out.ctypes.data)
+        if st != DTN_OK:
+            del self._out[qid]
+            _check(st, "dtn_server_submit")
+        return out
+
+    def wait(self, max_n=64, timeout=-1.0):
+        """Completed queries (up to max_n), each a dict with the answers."""
+        buf = (QueryDoneDesc * int(max_n))()
+        n = C.c_int64(0)
+        _check(lib().dtn_server_wait(self.handle, int(max_n), float(timeout), buf, C.byref(n)), "dtn_server_wait")
+        res = []
+        for i in range(n.value):
+            d = buf[i]
+            out, _, _ = self._out.pop(int(d.query_id))
+            res.append({"id": int(d.query_id), "status": int(d.status), "n_points": int(d.n_points),
+                        "t_submit": d.t_submit, "t_start": d.t_start, "t_done": d.t_done, "answer": out})
+        return res
+
+    def in_flight(self):
+        return len(self._out)
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.dtn_server_destroy(h)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
