@@ -48,7 +48,120 @@ def parse():
     ap.add_argument("--cpu-walks", type=int, default=40000, help="walks per node in the CPU sample")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (reference for HBM counters)")
+    ap.add_argument("--no-box-holes", action="store_true", help="skip the uneven-batching workload")
+    ap.add_argument("--no-serving", action="store_true", help="skip the query-serving workload")
+    ap.add_argument("--serving-window", type=int, default=200, help="arrivals in the serving window")
+    ap.add_argument("--serving-se", type=float, default=1e-2, help="required standard error per node (serving)")
+    ap.add_argument("--serving-rate", type=float, default=200.0, help="offered load, queries/s")
+    ap.add_argument("--only", choices=["cube", "box_holes", "serving"], default=None,
+                    help="run one workload only (for profiling)")
     return ap.parse_args()
+
+
+def box_holes(precision, steps):
+    """Uneven batching: the box [0,4]^3 minus 20 holes, 5994 patches in five
+    panel classes (8..128 panels), adaptive walks 1e3..2e5 per node at a
+    target standard error of 1e-3, all in one adaptive call (pilot launch,
+    budgets, one launch over the uneven remainder, merge), then the solve.
+    The walk schedule comes from the autotuner (timed on a sample of the
+    previous step's work list)."""
+    import torch
+
+    import dtn_inputs as I
+    from paper_1210_1491_amd import autotune, dtn
+
+    cfg = I.CONFIGS["box_holes"]
+    gd = cfg["geometry"]()
+    pd = cfg["patches"](gd)
+    g = dtn.Geometry(gd)
+    plan = dtn.Plan(g, pd)
+    nodes = plan.nodes()
+    N = plan.num_nodes
+    stats = torch.empty((N, 4), dtype=torch.float64, device="cuda")
+    used = torch.empty(N, dtype=torch.int64, device="cuda")
+    capped = torch.empty(N, dtype=torch.int64, device="cuda")
+    budget = (cfg["pilot_walks"], cfg["min_walks"], cfg["max_walks"], cfg["se_target"])
+    # the tuner times a sample of the remainder's work list, estimated from a
+    # pilot (the library recomputes the budgets itself in the timed steps)
+    pw = torch.full((N,), cfg["pilot_walks"], dtype=torch.int64, device="cuda")
+    ps, _ = dtn.wos_eval(g, nodes, pw, cfg["seed"], precision=precision)
+    p = ps.cpu().numpy()
+    var = p[:, 2] / (p[:, 0] - 1)
+    tot = np.clip(np.ceil(var / cfg["se_target"] ** 2), cfg["min_walks"], cfg["max_walks"]).astype(np.int64)
+    rem = torch.tensor(np.maximum(tot - cfg["pilot_walks"], 0), device="cuda")
+    wb = torch.full_like(rem, cfg["pilot_walks"])
+    sched, table = autotune.tune(g, nodes, rem, precision=precision, seed=cfg["seed"], walk_begin=wb)
+    print(f"[bench] box_holes schedule {sched}", file=sys.stderr, flush=True)
+    times = []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dtn.wos_adaptive(g, nodes, cfg["seed"], *budget, precision=precision, schedule=sched, stats=stats,
+                         walks_used=used, capped=capped)
+        neu, nse = plan.solve(stats, precision=precision)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        print(f"[bench] box_holes step {times[-1]:.2f} s", file=sys.stderr, flush=True)
+    st = stats.cpu().numpy()
+    u = used.cpu().numpy()
+    se = np.sqrt(st[:, 2] / np.maximum(st[:, 0] - 1, 1) / st[:, 0])
+    free = (u > cfg["min_walks"]) & (u < cfg["max_walks"])
+    sec = float(np.mean(times))
+    return {"workload": f"box [0,4]^3 minus 20 holes, {len(pd['h'])} patches (8..128 panels), {N} nodes, "
+                        f"adaptive {cfg['min_walks']}..{cfg['max_walks']} walks/node at SE {cfg['se_target']}",
+            "precision": precision, "seconds_per_step": sec, "walks": float(u.sum()),
+            "walks_per_s": float(u.sum()) / sec, "patches_per_s": len(pd["h"]) / sec,
+            "walk_steps_per_s": float(st[:, 3].sum()) / sec, "steps_per_walk": float(st[:, 3].sum() / u.sum()),
+            "share_at_max_walks": float(np.mean(u == cfg["max_walks"])),
+            "median_se_unclamped_nodes": float(np.median(se[free])) if free.any() else None,
+            "capped_walks": int(capped.sum().item()), "schedule": sched, "schedule_ms": table}
+
+
+def serving(precision, window, rate, se_target, sweep_fraction=0.5, sweep_window=60):
+    """Query serving on the box-with-holes geometry: Poisson arrivals, each
+    query 1..4096 boundary points (log-uniform), one patch per point, adaptive
+    walks at the required standard error per node, continuous batching over 4
+    streams under a 2 GB budget.  Latency = completion - arrival.  A second,
+    shorter run offers a fraction of the measured capacity (a stable rate)."""
+    import dtn_inputs as I
+    from paper_1210_1491_amd import dtn
+
+    cfg = I.CONFIGS["serving"]
+    gd = cfg["geometry"]()
+    g = dtn.Geometry(gd)
+
+    def run(rate_qps, n):
+        qs = I.serving_queries(gd, n_queries=n, rate=rate_qps, seed=cfg["seed"])
+        S = dtn.Server(g, n_streams=4, precision=precision, hbm_budget=cfg["hbm_budget"],
+                       pilot_walks=cfg["pilot_walks"], min_walks=cfg["min_walks"], max_walks=cfg["max_walks"],
+                       h_max=cfg["h_max"], ladder=cfg["ladder"], layout=cfg["layout"])
+        t0 = S.clock()
+        done = []
+        for i, q in enumerate(qs):
+            while S.clock() - t0 < q["t"]:
+                done.extend(S.wait(timeout=max(0.0, q["t"] - (S.clock() - t0))))
+            S.submit(i, q["pts"], q["normals"], se_target, q["seed"])
+        while len(done) < n:
+            done.extend(S.wait(timeout=60.0))
+        S.close()
+        lat = np.array([d["t_done"] - (t0 + qs[d["id"]]["t"]) for d in done])
+        walks = sum(float(d["answer"][:, 2].sum()) for d in done)
+        busy = max(d["t_done"] for d in done) - t0
+        assert all(d["status"] == 0 for d in done)
+        return {"rate_qps": rate_qps, "queries": n, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_points": float(np.mean([len(q["pts"]) for q in qs])),
+                "walks": walks, "makespan_s": busy, "served_qps": n / busy, "walks_per_s": walks / busy}
+
+    main = run(rate, window)
+    print(f"[bench] serving at {rate} q/s: p50 {main['p50_ms']:.0f} ms p99 {main['p99_ms']:.0f} ms", file=sys.stderr,
+          flush=True)
+    stable = run(sweep_fraction * main["served_qps"], sweep_window)
+    print(f"[bench] serving at {stable['rate_qps']:.2f} q/s: p50 {stable['p50_ms']:.0f} ms", file=sys.stderr,
+          flush=True)
+    return {"workload": f"box_holes geometry resident; Poisson arrivals; 1..4096 points per query (log-uniform); "
+                        f"patch per point (h = 0.25 * 2^-j, 8x16 nodes, 32 panels); adaptive walks "
+                        f"{cfg['min_walks']}..{cfg['max_walks']} at SE {se_target} per node; 4 streams, 2 GB budget",
+            "precision": precision, "offered": main, "stable": stable}
 
 
 def cpu_baseline(gd, pd_all, walks_per_node):
@@ -159,6 +272,13 @@ def main():
                 "capped_walks": int(capped.sum().item()), "wos_kernel_ms": float(np.mean(wos_ms)),
                 "alu_achieved": slots / wos_s, "total_walks": walks_n}
 
+    if args.only == "box_holes":
+        print(json.dumps({"box_holes": box_holes("fp32", args.steps)}), flush=True)
+        return
+    if args.only == "serving":
+        print(json.dumps({"serving": serving("fp32", args.serving_window, args.serving_rate, args.serving_se)}),
+              flush=True)
+        return
     m = measure(args.precision, args.steps, args.warmup)
     variants = {}
     if not args.no_variants:
@@ -199,6 +319,12 @@ def main():
                      "traffic": None},
         "variants": variants,
     }
+    if args.only is None and not args.no_box_holes:
+        line["box_holes"] = box_holes("fp32", 1)
+    if args.only is None and not args.no_serving:
+        line["serving"] = serving("fp32", args.serving_window, args.serving_rate, args.serving_se)
+        line["p50_latency_ms"] = line["serving"]["offered"]["p50_ms"]
+        line["p99_latency_ms"] = line["serving"]["offered"]["p99_ms"]
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(gd, pd, args.cpu_walks)
     print(json.dumps(line), flush=True)
