@@ -24,15 +24,66 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Full-rate lane-op slots of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+# ALU roofline.  Peak: one lane-op slot per lane per cycle, 256 CUs x 4 SIMDs
+# x 16 lanes x 2.4 GHz.  Each instruction kind costs the slots measured for it
+# by the issue-rate microbenchmarks (``--calibrate``): a kind issued at one
+# lane-op per lane per cycle costs 1.
 ALU_PEAK = 256 * 4 * 16 * 2.4e9
-# Algorithmic work, in full-rate lane-op slots (a quarter-rate op such as a
-# 32x32->64 multiply or a square root counts 4), per walk step and per walk,
-# for the box domain with point-source data.  The table behind these numbers
-# is in the design notes; it counts what the step definition requires, not
-# what the compiler emits.
-SLOTS_PER_STEP = {"fp64": 108, "fp32": 87}
-SLOTS_PER_WALK = 158
+SLOT_COST = {
+    "f64": 1.10,     # v_add/mul/min/max/cmp_f64
+    "f64fma": 1.17,  # v_fma_f64
+    "f32": 0.69,     # v_fma/add/mul/min/max_f32
+    "i32": 1.05,     # 32-bit integer and bit operations (v_bitop3_b32, v_mul_hi_u32)
+    "mad64": 0.96,   # v_mad_u64_u32 (32x32->64)
+    "cvt": 1.02,     # conversions between f32, f64 and u32
+    "trans32": 2.10,  # v_sin_f32, v_cos_f32, v_sqrt_f32
+    "rsq64": 4.06,   # v_rsq_f64
+}
+# Algorithmic work (operation counts by kind) of one walk step and of one walk
+# for the box domain with point-source data, counted from what the step
+# definition requires, not from what the compiler emits.
+STEP_OPS = {
+    # distance (11), eps test (1), x2 (1), u(1-u) (2), sin/cos reduction, scale (6), s cos / s sin (2)
+    "fp64": {"f64": 23,
+             # uniforms (2), z (1), sqrt refinement (4), sin/cos polynomials (17), jump (3)
+             "f64fma": 27,
+             # cap test, Philox xors (half block: 10), counter word, quadrant selects (6), step counter
+             "i32": 19, "mad64": 10, "cvt": 2, "rsq64": 1},
+    # FP32 direction, distance and jump size; FP64 position update and eps pretest
+    "fp32": {"cvt": 9, "f32": 20, "f64": 1, "f64fma": 3, "i32": 15, "mad64": 10, "trans32": 3},
+}
+# projection, 8 sources (sub, FMA, rsq + two Newton steps each), shift,
+# two compensated adds, square, counters
+WALK_OPS = {"f64": 52, "f64fma": 72, "rsq64": 8, "i32": 8}
+
+
+def slots(ops):
+    return sum(SLOT_COST[k] * n for k, n in ops.items())
+
+
+SLOTS_PER_STEP = {k: slots(v) for k, v in STEP_OPS.items()}
+SLOTS_PER_WALK = slots(WALK_OPS)
+
+# HBM traffic of the walk kernel on the unit-cube workload, from rocprofv3
+# FETCH_SIZE / WRITE_SIZE runs, each scaled by the same counter on a plain
+# 256 MiB device copy in the same run (fetch 2.00, write 1.00).  Valid only for
+# the kernel sources it was measured on (SHA-256 of these files).
+TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_amd/csrc/dtn_device.h",
+                     "paper_1210_1491_amd/csrc/dtn_internal.h"],
+           "sha256": ["b3d3580a86b01bfc9cf90b22da45f5e52910d24b141d99a83681770f61ef145f",
+                      "af41727590874b2e00acf879b1ecbd0e79f349e067ca4b21a2d8af6909b490a8",
+                      "440dc9b508ae94ff738dd3b5e127533e365f606ef42f0f08ae155f3bb94cf9ba"],
+           "fetch_bytes": 71745.6 * 1024 * 2.00, "write_bytes": 43008.0 * 1024 * 1.00}
+
+
+def traffic_if_current():
+    import hashlib
+
+    for f, h in zip(TRAFFIC["files"], TRAFFIC["sha256"]):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != h:
+                return None
+    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
 
 
 def parse():
@@ -55,10 +106,46 @@ def parse():
     ap.add_argument("--serving-rate", type=float, default=200.0, help="offered load, queries/s")
     ap.add_argument("--only", choices=["cube", "box_holes", "serving"], default=None,
                     help="run one workload only (for profiling)")
+    ap.add_argument("--box-holes-se", type=float, default=None,
+                    help="target standard error of the uneven-batching workload (default: its 1e-3)")
+    ap.add_argument("--no-tune", action="store_true", help="default walk schedule, no autotuning")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="measure the issue cost of the instruction kinds the roofline table charges")
     return ap.parse_args()
 
 
-def box_holes(precision, steps):
+# Instruction kinds of the issue-rate microbenchmarks (paper_1210_1491_amd/
+# csrc/calib.hip), in library order, with the instructions one chain step issues.
+CALIB_KINDS = [("v_fma_f32", 1), ("v_fma_f64", 1), ("v_mad_u64_u32 + v_xor_b32", 2),
+               ("v_sqrt_f32 + v_mul_f32", 2), ("v_sin_f32", 1), ("v_rsq_f64", 1),
+               ("v_cvt_f64_f32 + v_cvt_f32_f64", 2), ("v_bitop3_b32", 1), ("v_fma_f32 | v_sin_f32 (two chains)", 2),
+               ("v_fma_f64 | v_fma_f32 (two chains)", 2), ("v_min_f64 + 2 v_max_f64", 3), ("v_cos_f32", 1),
+               ("v_sqrt_f32", 1), ("v_add_f64", 1), ("v_mad_u64_u32", 1), ("v_mul_hi_u32", 1)]
+
+
+def calibrate():
+    """Issue slots per instruction kind: the full-rate lane-slot rate of the
+    chip divided by the measured rate of chain steps, per instruction."""
+    import ctypes as C
+
+    from paper_1210_1491_amd import build as B
+
+    L = C.CDLL(B.CALIB)
+    L.dtn_calib_rate.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_float)]
+    rows = {}
+    for op, (name, n_instr) in enumerate(CALIB_KINDS):
+        rate, ms = C.c_double(), C.c_float()
+        st = L.dtn_calib_rate(op, 8192, 16384, C.byref(rate), C.byref(ms))
+        if st != 0:
+            raise RuntimeError(f"calibration kernel {name} failed: {st}")
+        slots_per_step = ALU_PEAK / rate.value
+        rows[name] = {"ms": ms.value, "steps_per_s": rate.value, "slots_per_step": slots_per_step,
+                      "slots_per_instruction": slots_per_step / n_instr}
+        print(f"[calib] {name:40s} {ms.value:8.2f} ms  {slots_per_step:6.2f} slots/step", file=sys.stderr, flush=True)
+    return rows
+
+
+def box_holes(precision, steps, with_cpu=True, se_target=None, tune=True):
     """Uneven batching: the box [0,4]^3 minus 20 holes, 5994 patches in five
     panel classes (8..128 panels), adaptive walks 1e3..2e5 per node at a
     target standard error of 1e-3, all in one adaptive call (pilot launch,
@@ -80,17 +167,21 @@ def box_holes(precision, steps):
     stats = torch.empty((N, 4), dtype=torch.float64, device="cuda")
     used = torch.empty(N, dtype=torch.int64, device="cuda")
     capped = torch.empty(N, dtype=torch.int64, device="cuda")
-    budget = (cfg["pilot_walks"], cfg["min_walks"], cfg["max_walks"], cfg["se_target"])
+    se_t = cfg["se_target"] if se_target is None else float(se_target)
+    budget = (cfg["pilot_walks"], cfg["min_walks"], cfg["max_walks"], se_t)
     # the tuner times a sample of the remainder's work list, estimated from a
     # pilot (the library recomputes the budgets itself in the timed steps)
     pw = torch.full((N,), cfg["pilot_walks"], dtype=torch.int64, device="cuda")
     ps, _ = dtn.wos_eval(g, nodes, pw, cfg["seed"], precision=precision)
     p = ps.cpu().numpy()
     var = p[:, 2] / (p[:, 0] - 1)
-    tot = np.clip(np.ceil(var / cfg["se_target"] ** 2), cfg["min_walks"], cfg["max_walks"]).astype(np.int64)
+    tot = np.clip(np.ceil(var / se_t ** 2), cfg["min_walks"], cfg["max_walks"]).astype(np.int64)
     rem = torch.tensor(np.maximum(tot - cfg["pilot_walks"], 0), device="cuda")
     wb = torch.full_like(rem, cfg["pilot_walks"])
-    sched, table = autotune.tune(g, nodes, rem, precision=precision, seed=cfg["seed"], walk_begin=wb)
+    if tune:
+        sched, table = autotune.tune(g, nodes, rem, precision=precision, seed=cfg["seed"], walk_begin=wb)
+    else:
+        sched, table = dict(autotune.DEFAULT), {}
     print(f"[bench] box_holes schedule {sched}", file=sys.stderr, flush=True)
     times = []
     for _ in range(steps):
@@ -107,14 +198,29 @@ def box_holes(precision, steps):
     se = np.sqrt(st[:, 2] / np.maximum(st[:, 0] - 1, 1) / st[:, 0])
     free = (u > cfg["min_walks"]) & (u < cfg["max_walks"])
     sec = float(np.mean(times))
+    cpu = None
+    if with_cpu:
+        # the oracle's adaptive walks (FP64) on 64 seeded nodes of patches of every class
+        from oracle import patch as OP
+        from oracle import wos as OW
+        idx = I.box_holes_sample(pd, per_class=2, seed=cfg["seed"])
+        X = np.concatenate([OP.nodes_global(q)[0] for q in OP.patches_from_desc(I.subset_patches(pd, idx), gd)])
+        X = X[np.random.default_rng(cfg["seed"]).choice(len(X), 64, replace=False)]
+        t0 = time.perf_counter()
+        r = OW.wos_adaptive(OW.Geometry(gd), X, *budget[:3], budget[3], seed=cfg["seed"])
+        dt = time.perf_counter() - t0
+        cpu = {"value": float(r["count"].sum()) / dt, "unit": "walks/s", "cores": OW.max_threads(), "kind": "oracle",
+               "sample": f"64 nodes of {len(idx)} patches (2 per panel class), adaptive walks "
+                         f"({int(r['count'].sum())} walks, {int(r['steps'].sum())} steps) in {dt:.1f} s"}
     return {"workload": f"box [0,4]^3 minus 20 holes, {len(pd['h'])} patches (8..128 panels), {N} nodes, "
-                        f"adaptive {cfg['min_walks']}..{cfg['max_walks']} walks/node at SE {cfg['se_target']}",
+                        f"adaptive {cfg['min_walks']}..{cfg['max_walks']} walks/node at SE {se_t}",
             "precision": precision, "seconds_per_step": sec, "walks": float(u.sum()),
             "walks_per_s": float(u.sum()) / sec, "patches_per_s": len(pd["h"]) / sec,
             "walk_steps_per_s": float(st[:, 3].sum()) / sec, "steps_per_walk": float(st[:, 3].sum() / u.sum()),
             "share_at_max_walks": float(np.mean(u == cfg["max_walks"])),
             "median_se_unclamped_nodes": float(np.median(se[free])) if free.any() else None,
-            "capped_walks": int(capped.sum().item()), "schedule": sched, "schedule_ms": table}
+            "capped_walks": int(capped.sum().item()), "schedule": sched, "schedule_ms": table,
+            "cpu_baseline": cpu}
 
 
 def serving(precision, window, rate, se_target, sweep_fraction=0.5, sweep_window=60):
@@ -272,8 +378,12 @@ def main():
                 "capped_walks": int(capped.sum().item()), "wos_kernel_ms": float(np.mean(wos_ms)),
                 "alu_achieved": slots / wos_s, "total_walks": walks_n}
 
+    if args.calibrate:
+        print(json.dumps({"calibration": calibrate(), "peak_lane_slots_per_s": ALU_PEAK}), flush=True)
+        return
     if args.only == "box_holes":
-        print(json.dumps({"box_holes": box_holes("fp32", args.steps)}), flush=True)
+        print(json.dumps({"box_holes": box_holes("fp32", args.steps, not args.no_cpu_baseline, args.box_holes_se,
+                                                 not args.no_tune)}), flush=True)
         return
     if args.only == "serving":
         print(json.dumps({"serving": serving("fp32", args.serving_window, args.serving_rate, args.serving_se)}),
@@ -315,12 +425,13 @@ def main():
         "capped_walks": m["capped_walks"],
         "wos_kernel_ms": m["wos_kernel_ms"],
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK / 1e12,
-                     "unit": "TOP/s (full-rate lane-op slots)", "frac": achieved / ALU_PEAK,
-                     "traffic": None},
+                     "unit": "T lane-op slots/s", "frac": achieved / ALU_PEAK,
+                     "traffic": traffic_if_current() if args.walks == 100_000 and args.tiles == 16 else None,
+                     "slots_per_step": SLOTS_PER_STEP[args.precision], "slots_per_walk": SLOTS_PER_WALK},
         "variants": variants,
     }
     if args.only is None and not args.no_box_holes:
-        line["box_holes"] = box_holes("fp32", 1)
+        line["box_holes"] = box_holes("fp32", 1, not args.no_cpu_baseline)
     if args.only is None and not args.no_serving:
         line["serving"] = serving("fp32", args.serving_window, args.serving_rate, args.serving_se)
         line["p50_latency_ms"] = line["serving"]["offered"]["p50_ms"]

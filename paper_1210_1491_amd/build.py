@@ -16,6 +16,21 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
+CALIB = os.path.join(HERE, "libdtn_calib.so")
+
+
+def build_calib(verbose: bool = False, arch: str = "gfx950") -> str:
+    """The issue-rate microbenchmarks (measurement support, own library)."""
+    cmd = [hipcc(), f"--offload-arch={arch}", "-O3", "-std=c++17", "-fPIC", "-shared",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument",
+           os.path.join(CSRC, "calib.hip"), "-o", CALIB + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(CALIB + ".tmp", CALIB)
+    return CALIB
+
+
 def build(verbose: bool = False, arch: str = "gfx950", extra=()) -> str:
     cmd = [hipcc(), f"--offload-arch={arch}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -30,3 +45,4 @@ def build(verbose: bool = False, arch: str = "gfx950", extra=()) -> str:
 
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_calib(verbose=True))
