@@ -121,8 +121,9 @@ double box_dist(const double *x, const double *lo, const double *hi)
 }
 
 // Candidate-hole grid.  The box is split into about 32^3 cells.  For a cell
-// C, expanded by a small margin so that rounding in the lookup cannot put a
-// point outside the cell it is looked up in, U bounds the distance to the
+// C, expanded by 1e-3 of its width so that the FP32 rounding of the lookup
+// (position, one FMA, truncation: a few 1e-7 of a cell) cannot put a point
+// outside the cell it is looked up in, U bounds the distance to the
 // boundary from above for every point of C: the interior distance to the
 // outer box is at most min_k min(hi_C,k - lo_k, hi_k - lo_C,k), and the
 // distance to hole j is a convex function, so at most its largest value at
@@ -131,15 +132,19 @@ double box_dist(const double *x, const double *lo, const double *hi)
 // minimum over the listed holes (and the outer faces) is then exactly the
 // minimum over all of them.
 void build_cell_grid(const double lo[3], const double hi[3], const double *holes, int n_holes,
-                     std::vector<uint32_t> &mask, int32_t n[3], float clo[3], float inv[3])
+                     std::vector<uint32_t> &mask, DevGeom &dg)
 {
     const double L[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
     const double side = std::cbrt(L[0] * L[1] * L[2] / 32768.0);
+    int32_t n[3];
     for (int k = 0; k < 3; ++k) {
         n[k] = (int32_t)std::min(256.0, std::max(1.0, std::ceil(L[k] / side)));
-        clo[k] = (float)lo[k];
-        inv[k] = (float)(n[k] / L[k]);
+        dg.cell_inv[k] = (float)(n[k] / L[k]);
+        dg.cell_off[k] = (float)(-lo[k] * (n[k] / L[k]));
+        dg.cell_top[k] = (float)n[k] - 0.5f;
     }
+    dg.cell_stride[0] = n[1] * n[2];
+    dg.cell_stride[1] = n[2];
     mask.assign((size_t)n[0] * n[1] * n[2], 0u);
     const double scale = 1.0 + std::max({std::fabs(lo[0]), std::fabs(lo[1]), std::fabs(lo[2]), std::fabs(hi[0]),
                                          std::fabs(hi[1]), std::fabs(hi[2])});
@@ -349,9 +354,18 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
         if (e == hipSuccess) e = upload(ce, &g.d_hole_ce);
         if (e == hipSuccess) e = upload(g.holes, &g.d_hole_box);
         if (e == hipSuccess) e = upload(ce32, &g.d_hole_f32);
+        {
+            // (sin, cos) of 2 pi j / 256, evaluated in extended precision and rounded once
+            std::vector<double> tab(512);
+            for (int j = 0; j < 256; ++j) {
+                const long double a = 2.0L * 3.141592653589793238462643383279502884L * (long double)j / 256.0L;
+                tab[2 * j] = (double)std::sin(a);
+                tab[2 * j + 1] = (double)std::cos(a);
+            }
+            if (e == hipSuccess) e = upload(tab, &g.d_sincos);
+        }
         if (nh >= 1 && nh <= 32) {
-            build_cell_grid(d.box_lo, d.box_hi, g.holes.data(), nh, g.cell_mask, g.dev.cell_n, g.dev.cell_lo,
-                            g.dev.cell_inv);
+            build_cell_grid(d.box_lo, d.box_hi, g.holes.data(), nh, g.cell_mask, g.dev);
             if (e == hipSuccess) e = upload(g.cell_mask, &g.d_cell_mask);
         }
         if (e == hipSuccess) e = upload(g.src, &g.d_src);
@@ -359,6 +373,7 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
         g.dev.hole_ce = g.d_hole_ce;
         g.dev.hole_box = g.d_hole_box;
         g.dev.hole_f32 = g.d_hole_f32;
+        g.dev.sincos = g.d_sincos;
         g.dev.cell_mask = g.d_cell_mask;
         g.dev.src = g.d_src;
         // keep stream-ordered scratch in the pool between calls
@@ -380,6 +395,7 @@ void dtn_destroy_geometry(dtn_geometry g)
     hipFree(g->g.d_hole_ce);
     hipFree(g->g.d_hole_box);
     hipFree(g->g.d_hole_f32);
+    hipFree(g->g.d_sincos);
     hipFree(g->g.d_cell_mask);
     hipFree(g->g.d_src);
     delete g;

@@ -30,6 +30,11 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
 __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                  uint32_t k0, uint32_t k1)
 {
+    // The keys are wave-uniform.  The empty statement makes them look new at
+    // every call, so the ten round keys are recomputed by scalar adds here
+    // instead of being kept live in 20 SGPRs across the walk loop (which
+    // spills SGPRs into VGPR lanes and costs a v_readlane per use).
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
@@ -47,11 +52,32 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
 }
 
 // FP64 uniform in (0,1): (k + 1/2) 2^-32, exact.
-__device__ __forceinline__ double u01_f64(uint32_t k) { return fma((double)k, 0x1p-32, 0x1p-33); }
+__device__ __forceinline__ double u01_f64(uint32_t k) { return __builtin_amdgcn_ldexp((double)k + 0.5, -32); }
 // FP32 uniform in (0,1): ((k >> 8) + 1/2) 2^-24, exact.
 __device__ __forceinline__ float u01_f32(uint32_t k) { return fmaf((float)(k >> 8), 0x1p-24f, 0x1p-25f); }
 
 // ---------------------------------------------------------------- sin, cos
+// sin and cos of the angle 2 pi (k + 1/2) 2^-32 of a 32-bit random word k.
+// The angle is split at the nearest multiple of 2 pi / 256: j = the top 8
+// bits of k + 2^23 (mod 2^32, so the last half-interval wraps to j = 0), and
+// the remainder x = 2 pi (r + 1/2) 2^-32 with r = the low 24 bits minus 2^23,
+// |x| <= pi / 256, both exact in integer arithmetic.  tab[j] holds
+// (sin, cos)(2 pi j / 256); sin x and cos x come from their Taylor series to
+// x^7 and x^6 (first omitted terms below 2e-20 relative); the angle-addition
+// formulas combine them.
+__device__ __forceinline__ void sincos_2pi_word(uint32_t k, double tsin, double tcos, double &s, double &c)
+{
+    const uint32_t kk = k + 0x800000u;
+    const int32_t r = (int32_t)(kk & 0xFFFFFFu) - 0x800000;
+    const double x = fma((double)r, 0x1.921fb54442d18p-30, 0x1.921fb54442d18p-31);
+    const double x2 = x * x;
+    const double sx = fma(x * x2, fma(x2, fma(x2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), x);
+    const double cx = fma(x2, fma(x2, fma(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+    s = fma(tsin, cx, tcos * sx);
+    c = fma(tcos, cx, -(tsin * sx));
+}
+__device__ __forceinline__ uint32_t sincos_index(uint32_t k) { return (k + 0x800000u) >> 24; }
+
 // sin and cos of 2 pi u for u in (0,1).  The quarter-turn reduction is done
 // on 4u, where it is exact (q = nearest integer, f = 4u - q in [-1/2, 1/2]),
 // so no large-argument path is needed; sin and cos of r = f pi/2 in
@@ -128,19 +154,23 @@ extern "C" __device__ uint32_t __ockl_wfred_or_u32(uint32_t);
 // can be the nearest surface for some point of the (slightly expanded) cell.
 __device__ __forceinline__ uint32_t cell_candidates(const DevGeom &g, float x, float y, float z)
 {
-    const int ix = min(max((int)((x - g.cell_lo[0]) * g.cell_inv[0]), 0), g.cell_n[0] - 1);
-    const int iy = min(max((int)((y - g.cell_lo[1]) * g.cell_inv[1]), 0), g.cell_n[1] - 1);
-    const int iz = min(max((int)((z - g.cell_lo[2]) * g.cell_inv[2]), 0), g.cell_n[2] - 1);
-    return g.cell_mask[(ix * g.cell_n[1] + iy) * g.cell_n[2] + iz];
+    // cell coordinate (x - lo) / width as one FMA, clamped to [0, n - 1/2]
+    // before truncation (v_med3_f32), linear index in 24-bit multiplies
+    const float fx = __builtin_amdgcn_fmed3f(fmaf(x, g.cell_inv[0], g.cell_off[0]), 0.0f, g.cell_top[0]);
+    const float fy = __builtin_amdgcn_fmed3f(fmaf(y, g.cell_inv[1], g.cell_off[1]), 0.0f, g.cell_top[1]);
+    const float fz = __builtin_amdgcn_fmed3f(fmaf(z, g.cell_inv[2], g.cell_off[2]), 0.0f, g.cell_top[2]);
+    const uint32_t idx = __umul24((uint32_t)fx, (uint32_t)g.cell_stride[0]) +
+                         __umul24((uint32_t)fy, (uint32_t)g.cell_stride[1]) + (uint32_t)fz;
+    return g.cell_mask[idx];
 }
 
 // Holes the distance query must visit for the lanes with `take` set: the
 // union of their cells' candidate lists (wave-uniform).  Call with the whole
 // wave active.  Without a grid every hole is visited.
-__device__ __forceinline__ uint32_t hole_candidates(const DevGeom &g, bool take, double x, double y, double z)
+__device__ __forceinline__ uint32_t hole_candidates(const DevGeom &g, bool take, float x, float y, float z)
 {
     if (!g.cell_mask) return 0xffffffffu;
-    const uint32_t mine = take ? cell_candidates(g, (float)x, (float)y, (float)z) : 0u;
+    const uint32_t mine = take ? cell_candidates(g, x, y, z) : 0u;
     return __ockl_wfred_or_u32(mine);
 }
 

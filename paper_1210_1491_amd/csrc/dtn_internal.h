@@ -25,11 +25,14 @@ struct DevGeom {
     const double *hole_ce;  // [n_holes][6]: centre xyz, half-extent xyz
     const double *hole_box; // [n_holes][6]: lo xyz, hi xyz
     const float *hole_f32;  // [n_holes][8]: centre xyz, half-extent xyz, 0, 0 (FP32)
+    const double *sincos;   // [256][2]: sin, cos of 2 pi j / 256
     // Grid over the box listing, per cell, the holes that can be nearest
     // (bit i = hole i); NULL when not built (more than 32 holes).
     const uint32_t *cell_mask;  // [cell_n0][cell_n1][cell_n2]
-    float cell_lo[3], cell_inv[3];
-    int32_t cell_n[3];
+    float cell_inv[3];          // cells per unit length
+    float cell_off[3];          // -lo * cell_inv
+    float cell_top[3];          // cell_n - 1/2 (clamp before truncation)
+    int32_t cell_stride[2];     // cell_n1 * cell_n2, cell_n2
     const double *src;      // [n_src][4]
     double quad[10];
     double eps;
@@ -66,6 +69,7 @@ struct Geometry {
     std::vector<double> holes, src;
     double *d_hole_ce = nullptr, *d_hole_box = nullptr, *d_src = nullptr;
     float *d_hole_f32 = nullptr;
+    double *d_sincos = nullptr;
     uint32_t *d_cell_mask = nullptr;
     std::vector<uint32_t> cell_mask;
     int device = 0;

@@ -114,6 +114,11 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                                                          float fp32_margin, ChunkPartial *__restrict__ out)
 {
     __shared__ double queue[kWalkBlock / kWave][kQueue * 3];
+    __shared__ double sc_tab[256][2];  // (sin, cos) of 2 pi j / 256, FP64 path
+    if constexpr (PREC == DTN_FP64) {
+        for (int i = threadIdx.x; i < 512; i += kWalkBlock) (&sc_tab[0][0])[i] = g.sincos[i];
+        __syncthreads();
+    }
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     double *q = queue[wave];
     const int lane = lane_id();
@@ -158,8 +163,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
         const uint64_t it_max = ((uint64_t)g.max_steps + 4u) * 2u * (uint64_t)((w_hi - w_lo + kWave - 1) / kWave + 1);
 
         for (uint64_t it = 0; it < it_max; ++it) {
-            float u1f, u2f;
-            double u1d = 0.0, u2d = 0.0;
+            uint32_t w1, w2;  // this step's two random words
             if ((it & 1ull) == 0ull) {
                 const uint64_t want = __ballot(!walking);
                 if (want) {
@@ -176,27 +180,18 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                 }
                 if (!__any(walking)) break;
                 const Philox4 r = philox4x32_10((uint32_t)walk, (uint32_t)(walk >> 32), nstep >> 1, sid, k0, k1);
-                if constexpr (PREC == DTN_FP64) {
-                    u1d = u01_f64(r.x);
-                    u2d = u01_f64(r.y);
-                } else {
-                    u1f = u01_f32(r.x);
-                    u2f = u01_f32(r.y);
-                }
+                w1 = r.x;
+                w2 = r.y;
                 r2 = r.z;
                 r3 = r.w;
             } else {
-                if constexpr (PREC == DTN_FP64) {
-                    u1d = u01_f64(r2);
-                    u2d = u01_f64(r3);
-                } else {
-                    u1f = u01_f32(r2);
-                    u2f = u01_f32(r3);
-                }
+                w1 = r2;
+                w2 = r3;
             }
             // candidate holes of the walking lanes' cells (whole wave active here)
+            const float xf = (float)x, yf = (float)y, zf = (float)z;
             uint32_t cand = 0;
-            if constexpr (KIND == DTN_BOX_MINUS_BOXES) cand = hole_candidates(g, walking, x, y, z);
+            if constexpr (KIND == DTN_BOX_MINUS_BOXES) cand = hole_candidates(g, walking, xf, yf, zf);
             bool fin = false;
             if (walking) {
                 if constexpr (PREC == DTN_FP64) {
@@ -205,10 +200,12 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                         fin = true;
                         capped += (d >= eps) ? 1ull : 0ull;
                     } else {
+                        const double u1d = u01_f64(w1);
                         const double cz = 1.0 - 2.0 * u1d;
                         const double sr = 2.0 * sqrt_f64(u1d * (1.0 - u1d));
+                        const uint32_t j = sincos_index(w2);
                         double sn, cs;
-                        sincos_2pi_f64(u2d, sn, cs);
+                        sincos_2pi_word(w2, sc_tab[j][0], sc_tab[j][1], sn, cs);
                         x += d * (sr * cs);
                         y += d * (sr * sn);
                         z += d * cz;
@@ -216,7 +213,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                     }
                 } else {
                     // FP32 distance; FP64 recheck inside the shell margin.
-                    double d = (double)(dist_f32<KIND>(g, (float)x, (float)y, (float)z, cand) - fp32_margin);
+                    double d = (double)(dist_f32<KIND>(g, xf, yf, zf, cand) - fp32_margin);
                     bool stop = false;
                     if (d < (double)tau - (double)fp32_margin) {
                         d = dist_f64<KIND>(g, x, y, z, cand);
@@ -226,6 +223,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                         fin = true;
                         capped += stop ? 0ull : 1ull;
                     } else {
+                        const float u1f = u01_f32(w1), u2f = u01_f32(w2);
                         const float cz = 1.0f - 2.0f * u1f;
                         const float sr = 2.0f * __builtin_amdgcn_sqrtf(u1f * (1.0f - u1f));
                         const float cs = __builtin_amdgcn_cosf(u2f);  // cos(2 pi u2)
@@ -435,7 +433,7 @@ __global__ __launch_bounds__(256) void k_distance(DevGeom g, const double *__res
     const bool live = i < n;
     const double x = live ? pts[3 * i] : 0.0, y = live ? pts[3 * i + 1] : 0.0, z = live ? pts[3 * i + 2] : 0.0;
     uint32_t cand = 0;
-    if constexpr (KIND == DTN_BOX_MINUS_BOXES) cand = hole_candidates(g, live, x, y, z);
+    if constexpr (KIND == DTN_BOX_MINUS_BOXES) cand = hole_candidates(g, live, (float)x, (float)y, (float)z);
     if (!live) return;
     if constexpr (PREC == DTN_FP64) out[i] = dist_f64<KIND>(g, x, y, z, cand);
     else out[i] = (double)dist_f32<KIND>(g, (float)x, (float)y, (float)z, cand);
