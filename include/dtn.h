@@ -136,9 +136,9 @@ void dtn_destroy_geometry(dtn_geometry g);
  *              (lets a caller extend an estimate: walks [b, b+walks))
  *   seed       Philox key
  *   stream_id  device [n] per-point stream ids, or NULL for the point index
- *   precision  DTN_FP64 (all in FP64) or DTN_FP32_MIXED (direction, distance
- *              and jump in FP32; position, epsilon test, projection, scores
- *              and sums in FP64)
+ *   precision  DTN_FP64 (all in FP64) or DTN_FP32_MIXED (the direction in
+ *              FP32: uniforms, square root, sin and cos; distance, epsilon
+ *              test, jump, position, projection, scores and sums in FP64)
  *   stats      device [n][4] out: (count, mean, M2, steps), M2 = sum of
  *              squared deviations from the mean; count = 0 gives zeros
  *   capped     device [n] out (int64): walks ended by max_steps, or NULL
@@ -150,11 +150,10 @@ dtn_status dtn_wos_eval(dtn_geometry g, const double *pts, int64_t n, const int6
                         int32_t precision, double *stats, int64_t *capped, void *stream);
 
 /* Distance from n points inside Omega to its boundary, computed as the walk
- * kernels compute it (the radius of the largest ball of a walk step, Sec. 2):
- * DTN_FP64 in FP64; DTN_FP32_MIXED the FP32 distance of the mixed path (whose
- * jumps subtract a rounding margin from it).  For a box minus holes the walk
- * kernels look up, per grid cell, the holes that can be nearest; this call
- * lets a caller check that lookup against a plain minimum over all surfaces.
+ * kernels compute it (the radius of the largest ball of a walk step, Sec. 2),
+ * in FP64 for both precisions.  For a box minus holes the walk kernels look
+ * up, per grid cell, the holes that can be nearest; this call lets a caller
+ * check that lookup against a plain minimum over all surfaces.
  *   pts device [n][3]; dist device [n] out.  Errors: DTN_E_ARG. */
 dtn_status dtn_boundary_distance(dtn_geometry g, const double *pts, int64_t n, int32_t precision, double *dist,
                                  void *stream);

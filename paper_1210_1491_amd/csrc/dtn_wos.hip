@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                                                          const uint32_t *__restrict__ stream_id, uint64_t seed,
                                                          const int64_t *__restrict__ chunk_off,
                                                          const int64_t *__restrict__ meta, int64_t n,
-                                                         float fp32_margin, ChunkPartial *__restrict__ out)
+                                                         ChunkPartial *__restrict__ out)
 {
     __shared__ double queue[kWalkBlock / kWave][kQueue * 3];
     __shared__ double sc_tab[256][2];  // (sin, cos) of 2 pi j / 256, FP64 path
@@ -129,7 +129,6 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
     if (chunk >= total) return;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const double eps = g.eps;
-    const float tau = (float)eps + 2.0f * fp32_margin;
     {
         // point owning this chunk: largest i with chunk_off[i] <= chunk
         int64_t lo = 0, hi = n;
@@ -189,17 +188,21 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                 w2 = r3;
             }
             // candidate holes of the walking lanes' cells (whole wave active here)
-            const float xf = (float)x, yf = (float)y, zf = (float)z;
             uint32_t cand = 0;
-            if constexpr (KIND == DTN_BOX_MINUS_BOXES) cand = hole_candidates(g, walking, xf, yf, zf);
+            if constexpr (KIND == DTN_BOX_MINUS_BOXES)
+                cand = hole_candidates(g, walking, (float)x, (float)y, (float)z);
             bool fin = false;
             if (walking) {
-                if constexpr (PREC == DTN_FP64) {
-                    const double d = dist_f64<KIND>(g, x, y, z, cand);
-                    if (d < eps || (int64_t)nstep >= g.max_steps) {
-                        fin = true;
-                        capped += (d >= eps) ? 1ull : 0ull;
-                    } else {
+                // distance and epsilon test in FP64 on both paths (an FP32
+                // distance would need an FP64 recheck inside a rounding band
+                // around the shell, which some lane of a wave needs at almost
+                // every step, and a shrunken jump everywhere)
+                const double d = dist_f64<KIND>(g, x, y, z, cand);
+                if (d < eps || (int64_t)nstep >= g.max_steps) {
+                    fin = true;
+                    capped += (d >= eps) ? 1ull : 0ull;
+                } else {
+                    if constexpr (PREC == DTN_FP64) {
                         const double u1d = u01_f64(w1);
                         const double cz = 1.0 - 2.0 * u1d;
                         const double sr = 2.0 * sqrt_f64(u1d * (1.0 - u1d));
@@ -209,30 +212,22 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                         x += d * (sr * cs);
                         y += d * (sr * sn);
                         z += d * cz;
-                        ++nstep;
-                    }
-                } else {
-                    // FP32 distance; FP64 recheck inside the shell margin.
-                    double d = (double)(dist_f32<KIND>(g, xf, yf, zf, cand) - fp32_margin);
-                    bool stop = false;
-                    if (d < (double)tau - (double)fp32_margin) {
-                        d = dist_f64<KIND>(g, x, y, z, cand);
-                        stop = d < eps;
-                    }
-                    if (stop || (int64_t)nstep >= g.max_steps) {
-                        fin = true;
-                        capped += stop ? 0ull : 1ull;
                     } else {
+                        // FP32 direction: uniforms, square root and the
+                        // hardware sin/cos (revolution input); |omega| = 1
+                        // within three FP32 roundings, so the jump is
+                        // shortened by 2^-22 to stay inside the ball
                         const float u1f = u01_f32(w1), u2f = u01_f32(w2);
                         const float cz = 1.0f - 2.0f * u1f;
                         const float sr = 2.0f * __builtin_amdgcn_sqrtf(u1f * (1.0f - u1f));
                         const float cs = __builtin_amdgcn_cosf(u2f);  // cos(2 pi u2)
                         const float sn = __builtin_amdgcn_sinf(u2f);  // sin(2 pi u2)
-                        x += d * (double)(sr * cs);
-                        y += d * (double)(sr * sn);
-                        z += d * (double)cz;
-                        ++nstep;
+                        const double dj = d * (1.0 - 0x1p-22);
+                        x += dj * (double)(sr * cs);
+                        y += dj * (double)(sr * sn);
+                        z += dj * (double)cz;
                     }
+                    ++nstep;
                 }
             }
             const uint64_t fm = __ballot(fin);
@@ -375,19 +370,11 @@ hipError_t run(const Geometry &g, const double *pts, int64_t n, const int64_t *w
     if (((uintptr_t)part & 15u) != 0) part = (ChunkPartial *)(((uintptr_t)part + 15u) & ~(uintptr_t)15u);
     hipLaunchKernelGGL(k_wos_plan, dim3(1), dim3(kPlanThreads), 0, s, walks, n, target_chunks, c_min, chunk_off,
                        meta);
-    // FP32 distance error bound: a few ulps of the largest coordinate.
-    double L = 1.0;
-    if (KIND == DTN_BALL) {
-        L = g.dev.r + std::max({fabs(g.dev.c[0]), fabs(g.dev.c[1]), fabs(g.dev.c[2])});
-    } else {
-        for (int k = 0; k < 3; ++k) L = std::max({L, fabs(g.dev.lo[k]), fabs(g.dev.hi[k])});
-    }
-    const float margin = (float)(32.0 * L * 0x1p-24);
     const int64_t waves_per_block = kWalkBlock / kWave;
     const int64_t blocks = (max_chunks + waves_per_block - 1) / waves_per_block;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_wos_walk<KIND, DATA, PREC>), dim3((unsigned)blocks), dim3(kWalkBlock), 0, s, g.dev, pts,
-                       walks, walk_begin, stream_id, seed, chunk_off, meta, n, margin, part);
+                       walks, walk_begin, stream_id, seed, chunk_off, meta, n, part);
     hipLaunchKernelGGL((k_wos_finalize<KIND, DATA>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g.dev, pts,
                        walks, n, chunk_off, part, stats, capped);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -425,7 +412,7 @@ hipError_t walk_all(const Geometry &g, const double *pts, int64_t n, const int64
 
 // ------------------------------------------------- distance (diagnostic)
 
-template <int KIND, int PREC>
+template <int KIND>
 __global__ __launch_bounds__(256) void k_distance(DevGeom g, const double *__restrict__ pts, int64_t n,
                                                   double *__restrict__ out)
 {
@@ -435,19 +422,16 @@ __global__ __launch_bounds__(256) void k_distance(DevGeom g, const double *__res
     uint32_t cand = 0;
     if constexpr (KIND == DTN_BOX_MINUS_BOXES) cand = hole_candidates(g, live, (float)x, (float)y, (float)z);
     if (!live) return;
-    if constexpr (PREC == DTN_FP64) out[i] = dist_f64<KIND>(g, x, y, z, cand);
-    else out[i] = (double)dist_f32<KIND>(g, (float)x, (float)y, (float)z, cand);
+    out[i] = dist_f64<KIND>(g, x, y, z, cand);
 }
 
-template <int PREC>
 void distance_kind(const Geometry &g, const double *pts, int64_t n, double *out, hipStream_t s)
 {
     const dim3 grid((unsigned)((n + 255) / 256)), block(256);
     switch (g.dev.kind) {
-    case DTN_BALL: hipLaunchKernelGGL((k_distance<DTN_BALL, PREC>), grid, block, 0, s, g.dev, pts, n, out); break;
-    case DTN_BOX: hipLaunchKernelGGL((k_distance<DTN_BOX, PREC>), grid, block, 0, s, g.dev, pts, n, out); break;
-    default:
-        hipLaunchKernelGGL((k_distance<DTN_BOX_MINUS_BOXES, PREC>), grid, block, 0, s, g.dev, pts, n, out);
+    case DTN_BALL: hipLaunchKernelGGL((k_distance<DTN_BALL>), grid, block, 0, s, g.dev, pts, n, out); break;
+    case DTN_BOX: hipLaunchKernelGGL((k_distance<DTN_BOX>), grid, block, 0, s, g.dev, pts, n, out); break;
+    default: hipLaunchKernelGGL((k_distance<DTN_BOX_MINUS_BOXES>), grid, block, 0, s, g.dev, pts, n, out);
     }
 }
 
@@ -520,9 +504,9 @@ dtn_status launch_wos(const Geometry &g, const double *pts, int64_t n, const int
 dtn_status launch_distance(const Geometry &g, const double *pts, int64_t n, int precision, double *dist,
                            hipStream_t stream)
 {
+    (void)precision;  // both paths measure distances in FP64
     if (n == 0) return DTN_OK;
-    if (precision == DTN_FP64) distance_kind<DTN_FP64>(g, pts, n, dist, stream);
-    else distance_kind<DTN_FP32_MIXED>(g, pts, n, dist, stream);
+    distance_kind(g, pts, n, dist, stream);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_boundary_distance: ") + hipGetErrorString(e));
     return DTN_OK;
