@@ -239,9 +239,18 @@ __device__ __forceinline__ double dist_f64(const DevGeom &g, double x, double y,
     }
 }
 
-// Closest boundary point of an interior point (FP64).
+// All holes as a candidate mask (for callers without a per-cell list).
+__device__ __forceinline__ uint32_t all_holes(const DevGeom &g)
+{
+    return g.n_holes >= 32 ? 0xffffffffu : ((1u << g.n_holes) - 1u);
+}
+
+// Closest boundary point of an interior point (FP64).  With the hole grid,
+// only the holes in `cand` are visited (a superset of the holes that can be
+// nearest, from hole_candidates or all_holes), in increasing index, so ties
+// still go to the lowest index.
 template <int KIND>
-__device__ __forceinline__ void project_f64(const DevGeom &g, double &x, double &y, double &z)
+__device__ __forceinline__ void project_f64(const DevGeom &g, double &x, double &y, double &z, uint32_t cand)
 {
     if constexpr (KIND == DTN_BALL) {
         const double dx = x - g.c[0], dy = y - g.c[1], dz = z - g.c[2];
@@ -259,17 +268,17 @@ __device__ __forceinline__ void project_f64(const DevGeom &g, double &x, double 
         double p[3] = {x, y, z};
         double best = x - g.lo[0];
         int face = 0;
-        const double cand[5] = {g.hi[0] - x, y - g.lo[1], g.hi[1] - y, z - g.lo[2], g.hi[2] - z};
+        const double face_d[5] = {g.hi[0] - x, y - g.lo[1], g.hi[1] - y, z - g.lo[2], g.hi[2] - z};
 #pragma unroll
         for (int f = 1; f < 6; ++f)
-            if (cand[f - 1] < best) {
-                best = cand[f - 1];
+            if (face_d[f - 1] < best) {
+                best = face_d[f - 1];
                 face = f;
             }
         int hole = -1;
         if constexpr (KIND == DTN_BOX_MINUS_BOXES) {
-            cdouble *h = as_const(g.hole_ce);
-            for (int i = 0; i < g.n_holes; ++i, h += 6) {
+            auto visit = [&](int i) {
+                cdouble *h = as_const(g.hole_ce) + 6 * i;
                 const double qx = fmax(fabs(x - h[0]) - h[3], 0.0);
                 const double qy = fmax(fabs(y - h[1]) - h[4], 0.0);
                 const double qz = fmax(fabs(z - h[2]) - h[5], 0.0);
@@ -278,6 +287,17 @@ __device__ __forceinline__ void project_f64(const DevGeom &g, double &x, double 
                     best = d;
                     hole = i;
                 }
+            };
+            if (g.cell_mask) {
+                uint32_t m = cand;
+                while (m) {
+                    const int i = __builtin_ctz(m);
+                    m &= m - 1u;
+                    visit(i);
+                }
+            } else {
+#pragma unroll 1
+                for (int i = 0; i < g.n_holes; ++i) visit(i);
             }
         }
         if (hole < 0) {

@@ -144,7 +144,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
         const uint32_t sid = stream_id ? stream_id[node] : (uint32_t)node;
         const double y0 = pts[3 * node], y1 = pts[3 * node + 1], y2 = pts[3 * node + 2];
         double sx = y0, sy = y1, sz = y2;
-        project_f64<KIND>(g, sx, sy, sz);
+        project_f64<KIND>(g, sx, sy, sz, all_holes(g));
         const double shift = phi_eval<DATA>(g, sx, sy, sz);
 
         // lane state
@@ -244,7 +244,10 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                 if (qn >= kWave) {
                     wave_sync();
                     double px = q[3 * lane], py = q[3 * lane + 1], pz = q[3 * lane + 2];
-                    project_f64<KIND>(g, px, py, pz);
+                    uint32_t pc = 0;  // candidate holes of the 64 queued points (whole wave active)
+                    if constexpr (KIND == DTN_BOX_MINUS_BOXES)
+                        pc = hole_candidates(g, true, (float)px, (float)py, (float)pz);
+                    project_f64<KIND>(g, px, py, pz, pc);
                     const double v = phi_eval<DATA>(g, px, py, pz) - shift;
                     kadd(s1, v);
                     kadd(s2, v * v);
@@ -268,12 +271,18 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
         }
         // score what is left in the queue
         wave_sync();
-        if (lane < qn) {
-            double px = q[3 * lane], py = q[3 * lane + 1], pz = q[3 * lane + 2];
-            project_f64<KIND>(g, px, py, pz);
-            const double v = phi_eval<DATA>(g, px, py, pz) - shift;
-            kadd(s1, v);
-            kadd(s2, v * v);
+        {
+            const bool has = lane < qn;
+            double px = has ? q[3 * lane] : 0.0, py = has ? q[3 * lane + 1] : 0.0, pz = has ? q[3 * lane + 2] : 0.0;
+            uint32_t pc = 0;
+            if constexpr (KIND == DTN_BOX_MINUS_BOXES)
+                pc = hole_candidates(g, has, (float)px, (float)py, (float)pz);
+            if (has) {
+                project_f64<KIND>(g, px, py, pz, pc);
+                const double v = phi_eval<DATA>(g, px, py, pz) - shift;
+                kadd(s1, v);
+                kadd(s2, v * v);
+            }
         }
         wave_sync();
         const KSum t1 = wave_ksum(s1);
@@ -315,7 +324,7 @@ __global__ __launch_bounds__(256) void k_wos_finalize(DevGeom g, const double *_
     }
     const int64_t w = max(walks[i], (int64_t)0);
     double sx = pts[3 * i], sy = pts[3 * i + 1], sz = pts[3 * i + 2];
-    project_f64<KIND>(g, sx, sy, sz);
+    project_f64<KIND>(g, sx, sy, sz, all_holes(g));
     const double shift = phi_eval<DATA>(g, sx, sy, sz);
     const double cnt = (double)w;
     const double S1 = s1.s + s1.c, S2 = s2.s + s2.c;
