@@ -49,8 +49,10 @@ STEP_OPS = {
              "f64fma": 27,
              # cap test, Philox xors (half block: 10), counter word, quadrant selects (6), step counter
              "i32": 19, "mad64": 10, "cvt": 2, "rsq64": 1},
-    # FP32 direction, distance and jump size; FP64 position update and eps pretest
-    "fp32": {"cvt": 9, "f32": 20, "f64": 1, "f64fma": 3, "i32": 15, "mad64": 10, "trans32": 3},
+    # FP64 distance (11), eps test (1), jump shortening (1); FP32 uniforms (2 FMA), z (1),
+    # u(1-u) (2), x2 (1), s cos / s sin (2); sqrt, sin, cos on the transcendental unit;
+    # conversions: 2 uniforms, 3 direction components; 3 FP64 FMAs of the jump
+    "fp32": {"f64": 13, "f64fma": 3, "f32": 8, "trans32": 3, "cvt": 5, "i32": 15, "mad64": 10},
 }
 # projection, 8 sources (sub, FMA, rsq + two Newton steps each), shift,
 # two compensated adds, square, counters

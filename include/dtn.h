@@ -261,25 +261,28 @@ dtn_status dtn_potential(dtn_plan p, const double *neumann, const double *target
  * inside Omega), runs step 1 with adaptive walks (dtn_adaptive with the
  * query's se_target) and step 2, and answers with du/dn averaged over the
  * patch's central ring of panels (the disk of radius h / n_rings), its
- * standard error, the walks spent and h.  Queries run concurrently on
- * several HIP streams of the current device (continuous batching: a query
- * starts as soon as a stream is free and its device memory fits the budget;
- * admission is first come, first served).  A query's walks are a function of
- * its seed and its nodes only (stream id = node index within the query), so
- * its answer does not depend on what else is in flight.
+ * standard error, the walks spent and h.  Continuous batching: a
+ * dispatcher thread joins the queued queries, first come, first served, into
+ * a batch of at most max_points points whose device memory fits under the
+ * budget next to the batches in flight, and runs it on a free HIP stream of
+ * the current device as single launches over all its patches; up to
+ * n_streams batches are in flight.  A query's walks are a function of its
+ * seed and its nodes only (Philox key = its seed, stream id = node index
+ * within the query), so its walk set does not depend on what it is batched
+ * with (its sums may round differently).
  * Only box domains (with or without holes) are served: every point must lie
  * on a face, with the face's outward normal. */
 typedef struct dtn_server_s *dtn_server; /* opaque, library-owned */
 
 typedef struct {
-    int32_t n_streams;   /* queries in flight at once, 1..16 */
+    int32_t n_streams;   /* batches in flight at once, 1..16 */
     int32_t precision;   /* DTN_FP64 or DTN_FP32_MIXED (walks and solve) */
-    int64_t hbm_budget;  /* bytes of device memory the queries in flight may hold */
+    int64_t hbm_budget;  /* bytes of device memory the batches in flight may hold */
     int64_t pilot_walks, min_walks, max_walks; /* adaptive budget (dtn_adaptive) */
     double h_max;        /* largest patch radius of the ladder, > 0 */
     int32_t ladder;      /* number of rungs h_max 2^-j, j = 0..ladder-1, 1..40 */
     int32_t n_theta, n_phi, n_rings, n_sectors; /* patch layout (as dtn_patch) */
-    int64_t max_points;  /* largest query, 1..2^20 (sizes pinned staging) */
+    int64_t max_points;  /* largest query and batch (points), 1..2^20; sizes pinned staging */
 } dtn_server_config;
 
 /* Completion record of a query; times in seconds on the server's clock. */
@@ -298,7 +301,7 @@ typedef struct {
 dtn_status dtn_server_create(dtn_geometry g, const dtn_server_config *cfg, dtn_server *out);
 void dtn_server_destroy(dtn_server s);
 
-/* Device bytes a query of n_points reserves under this configuration. */
+/* Device bytes a batch of n_points reserves under this configuration. */
 int64_t dtn_server_footprint(const dtn_server_config *cfg, int64_t n_points);
 
 /* Seconds since the server was created (the clock of dtn_query_done). */

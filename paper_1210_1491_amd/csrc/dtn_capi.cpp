@@ -478,8 +478,8 @@ dtn_status dtn_wos_adaptive(dtn_geometry g, const double *pts, int64_t n, const 
         std::string why;
         if (!schedule_from(sched, sc, why)) return fail(DTN_E_ARG, at + why);
         const Adaptive a{b.pilot_walks, b.min_walks, b.max_walks, b.se_target};
-        return launch_wos_adaptive(g->g, pts, n, a, seed, stream_id, precision, stats, walks_used, capped, sc,
-                                   (hipStream_t)stream);
+        return launch_wos_adaptive(g->g, pts, n, a, seed, nullptr, stream_id, precision, stats, walks_used, capped,
+                                   sc, (hipStream_t)stream);
     } catch (...) {
         return fail(DTN_E_DEVICE, "dtn_wos_adaptive: exception");
     }

@@ -106,10 +106,12 @@ struct Schedule {
     int32_t oversub = 4;
 };
 
-// Adaptive walk budget: pilot walks, clamp of the total, target standard error.
+// Adaptive walk budget: pilot walks, clamp of the total, target standard
+// error (or per-point squared targets, device [n], when node_se2 is set).
 struct Adaptive {
     int64_t pilot, w_min, w_max;
     double se;
+    const double *node_se2 = nullptr;
 };
 
 // Kernel launchers (dtn_wos.hip).
@@ -118,9 +120,10 @@ dtn_status launch_wos(const Geometry &g, const double *pts, int64_t n, const int
                       int precision, double *stats, int64_t *capped, const Schedule &sc, hipStream_t stream);
 dtn_status launch_distance(const Geometry &g, const double *pts, int64_t n, int precision, double *dist,
                            hipStream_t stream);
+// node_seed: per-point Philox keys (device [n]) or NULL for `seed` everywhere.
 dtn_status launch_wos_adaptive(const Geometry &g, const double *pts, int64_t n, const Adaptive &a, uint64_t seed,
-                               const uint32_t *stream_id, int precision, double *stats, int64_t *walks_used,
-                               int64_t *capped, const Schedule &sc, hipStream_t stream);
+                               const uint64_t *node_seed, const uint32_t *stream_id, int precision, double *stats,
+                               int64_t *walks_used, int64_t *capped, const Schedule &sc, hipStream_t stream);
 
 // Kernel launchers (dtn_patch.hip).
 dtn_status launch_nodes(const Plan &p, double *nodes, hipStream_t stream);
@@ -138,6 +141,11 @@ dtn_status plane_class(int nt, int nf, int nr, int ns, DevClass &out);  // cache
 // sigma, its standard error, the walks spent on the patch and h.
 dtn_status launch_answer(const Plan &p, const double *neumann, const double *node_stats, const int64_t *walks_used,
                          double *ans, hipStream_t stream);
+
+// Per-node Philox keys, stream ids and squared SE targets of a batch of
+// queries from per-patch values (dtn_patch.hip).
+dtn_status launch_node_ids(int64_t n_patches, int nn, const uint64_t *pseed, const uint32_t *psid0,
+                           const double *pse2, uint64_t *nseed, uint32_t *nsid, double *nse2, hipStream_t stream);
 
 // Host operator construction (dtn_operators.cpp).
 struct ClassOps {

@@ -502,6 +502,34 @@ dtn_status launch_answer(const Plan &p, const double *neumann, const double *nod
     return DTN_OK;
 }
 
+// Per-node walk identity of a batch of queries: every node of patch p gets
+// its query's Philox key and squared SE target, and stream id = its index
+// within the query (sid0[p] + node index in the patch).
+__global__ __launch_bounds__(256) void k_node_ids(int64_t n_patches, int nn, const uint64_t *__restrict__ pseed,
+                                                  const uint32_t *__restrict__ psid0,
+                                                  const double *__restrict__ pse2, uint64_t *__restrict__ nseed,
+                                                  uint32_t *__restrict__ nsid, double *__restrict__ nse2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_patches * nn) return;
+    const int64_t p = i / nn;
+    nseed[i] = pseed[p];
+    nsid[i] = psid0[p] + (uint32_t)(i - p * nn);
+    nse2[i] = pse2[p];
+}
+
+dtn_status launch_node_ids(int64_t n_patches, int nn, const uint64_t *pseed, const uint32_t *psid0,
+                           const double *pse2, uint64_t *nseed, uint32_t *nsid, double *nse2, hipStream_t s)
+{
+    const int64_t n = n_patches * nn;
+    if (n == 0) return DTN_OK;
+    hipLaunchKernelGGL(k_node_ids, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n_patches, nn, pseed, psid0,
+                       pse2, nseed, nsid, nse2);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("node ids: ") + hipGetErrorString(e));
+    return DTN_OK;
+}
+
 dtn_status launch_lu32(const Plan &p, hipStream_t s)
 {
     hipLaunchKernelGGL(k_lu32, dim3((unsigned)p.classes.size()), dim3(kLuBlock), 0, s, p.d_classes);

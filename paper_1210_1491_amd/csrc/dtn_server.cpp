@@ -1,15 +1,18 @@
 // Query server: continuous batching of Neumann queries over HIP streams.
 //
 // A query is a set of boundary points.  Each point gets a patch centred on
-// it (one patch class for the whole server, h from a ladder h_max 2^-j), and
-// the query runs the whole path on one stream: nodes, adaptive walks (pilot,
-// budgets, remainder, merge), the collocation solve, the central-disk answer
-// and the copy back, all stream-ordered, with its device memory taken from
-// the stream-ordered pool.  A dispatcher thread admits queued queries first
-// come, first served, whenever a stream is free and the query's device
-// memory fits under the budget next to the queries in flight; a host
-// function enqueued behind the query's work records its completion, copies
-// the answers out of pinned staging and releases the stream and the memory.
+// it (one patch class for the whole server, h from a ladder h_max 2^-j).  A
+// dispatcher thread forms a batch from the queued queries, first come, first
+// served: as many as fit in the largest batch (max_points points) and, with
+// the batches in flight, under the device-memory budget.  A batch runs the
+// whole path on one stream as single launches over all its patches: nodes,
+// per-node walk identities (each query's seed, node index within the query,
+// SE target), adaptive walks (pilot, budgets, remainder, merge), the
+// collocation solve, the central-disk answers and the copy back, all
+// stream-ordered, with its device memory from the stream-ordered pool.  A
+// host function enqueued behind the batch copies each query's answers out of
+// pinned staging, records the completions and releases the stream and the
+// memory, so the next batch can start while others are still in flight.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,21 +40,30 @@ struct Query {
     double se = 0.0;
     uint64_t seed = 0;
     double *out = nullptr;
-    int64_t bytes = 0;
     double t_submit = 0.0, t_start = 0.0;
+};
+
+struct Batch {
+    std::vector<Query *> qs;
+    int64_t n = 0;      // points (patches)
+    int64_t bytes = 0;  // device memory reserved
     int slot = -1;
 };
 
+// Pinned staging of one stream, sized for the largest batch.
 struct Slot {
     hipStream_t stream = nullptr;
-    dtn_patch *h_patches = nullptr;  // pinned staging, [max_points]
-    double *h_ans = nullptr;         // pinned staging, [max_points][4]
+    dtn_patch *h_patches = nullptr;  // [max_points]
+    uint64_t *h_seed = nullptr;      // [max_points] Philox key per patch
+    uint32_t *h_sid0 = nullptr;      // [max_points] query-local index of the patch's first node
+    double *h_se2 = nullptr;         // [max_points] squared SE target per patch
+    double *h_ans = nullptr;         // [max_points][4]
     bool busy = false;
 };
 
-// Offsets of one query's arrays inside its single device allocation.
+// Offsets of one batch's arrays inside its single device allocation.
 struct Layout {
-    size_t patches, nodes, stats, used, capped, neu, nse, ans, total;
+    size_t patches, pseed, psid0, pse2, nodes, nseed, nsid, nse2, stats, used, capped, neu, nse, ans, total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -65,11 +77,18 @@ Layout layout(int64_t n, int64_t nn, int64_t np)
         o += align256(bytes);
         return at;
     };
+    const size_t nodes = (size_t)(n * nn);
     L.patches = take(sizeof(dtn_patch) * (size_t)n);
-    L.nodes = take(sizeof(double) * 3 * (size_t)(n * nn));
-    L.stats = take(sizeof(double) * 4 * (size_t)(n * nn));
-    L.used = take(sizeof(int64_t) * (size_t)(n * nn));
-    L.capped = take(sizeof(int64_t) * (size_t)(n * nn));
+    L.pseed = take(sizeof(uint64_t) * (size_t)n);
+    L.psid0 = take(sizeof(uint32_t) * (size_t)n);
+    L.pse2 = take(sizeof(double) * (size_t)n);
+    L.nodes = take(sizeof(double) * 3 * nodes);
+    L.nseed = take(sizeof(uint64_t) * nodes);
+    L.nsid = take(sizeof(uint32_t) * nodes);
+    L.nse2 = take(sizeof(double) * nodes);
+    L.stats = take(sizeof(double) * 4 * nodes);
+    L.used = take(sizeof(int64_t) * nodes);
+    L.capped = take(sizeof(int64_t) * nodes);
     L.neu = take(sizeof(double) * (size_t)(n * np));
     L.nse = take(sizeof(double) * (size_t)(n * np));
     L.ans = take(sizeof(double) * 4 * (size_t)n);
@@ -77,9 +96,10 @@ Layout layout(int64_t n, int64_t nn, int64_t np)
     return L;
 }
 
-// Device bytes of a query: its arrays plus the walk kernels' stream-ordered
-// scratch (adaptive statistics and budgets; chunk table and partials for up
-// to nodes + 256 CUs x 32 waves x 4 chunks, the default schedule on MI355X).
+// Device bytes of a batch of n points: its arrays plus the walk kernels'
+// stream-ordered scratch (adaptive statistics and budgets; chunk table and
+// partials for up to nodes + 256 CUs x 32 waves x 4 chunks, the default
+// schedule on MI355X).
 int64_t footprint(const dtn_server_config &c, int64_t n)
 {
     const int64_t nn = (int64_t)c.n_theta * c.n_phi, np = (int64_t)c.n_rings * c.n_sectors;
@@ -148,47 +168,68 @@ namespace {
 
 struct Completion {
     dtn_server_s *S;
-    Query *q;
+    Batch *b;
 };
 
-// Finish a query (lock held): release its stream and memory, record it.
-void finish_locked(dtn_server_s *S, Query *q, int status)
+// Finish a batch (lock held): record each query, release the stream and the
+// memory.
+void finish_locked(dtn_server_s *S, Batch *b, int status)
 {
-    dtn_query_done d{};
-    d.query_id = q->id;
-    d.status = status;
-    d.n_points = (int64_t)q->patches.size();
-    d.t_submit = q->t_submit;
-    d.t_start = q->t_start;
-    d.t_done = S->now();
-    S->in_use -= q->bytes;
-    if (q->slot >= 0) {
-        S->slots[q->slot].busy = false;
+    const double t = S->now();
+    for (Query *q : b->qs) {
+        dtn_query_done d{};
+        d.query_id = q->id;
+        d.status = status;
+        d.n_points = (int64_t)q->patches.size();
+        d.t_submit = q->t_submit;
+        d.t_start = q->t_start;
+        d.t_done = t;
+        S->done.push_back(d);
+        delete q;
+    }
+    S->in_use -= b->bytes;
+    if (b->slot >= 0) {
+        S->slots[b->slot].busy = false;
         --S->busy;
     }
-    S->done.push_back(d);
-    delete q;
+    delete b;
     S->cv.notify_all();
 }
 
-// Host function behind a query's work on its stream (no HIP calls here).
+// Host function behind a batch's work on its stream (no HIP calls here).
 void on_done(void *arg)
 {
     std::unique_ptr<Completion> c((Completion *)arg);
     dtn_server_s *S = c->S;
-    Query *q = c->q;
-    std::memcpy(q->out, S->slots[q->slot].h_ans, sizeof(double) * 4 * q->patches.size());
+    Batch *b = c->b;
+    const double *ans = S->slots[b->slot].h_ans;
+    for (Query *q : b->qs) {
+        std::memcpy(q->out, ans, sizeof(double) * 4 * q->patches.size());
+        ans += 4 * q->patches.size();
+    }
     std::lock_guard<std::mutex> lk(S->mu);
-    finish_locked(S, q, DTN_OK);
+    finish_locked(S, b, DTN_OK);
 }
 
-dtn_status enqueue(dtn_server_s *S, Query *q)
+dtn_status enqueue(dtn_server_s *S, Batch *b)
 {
-    Slot &sl = S->slots[q->slot];
+    Slot &sl = S->slots[b->slot];
     hipStream_t s = sl.stream;
-    const int64_t n = (int64_t)q->patches.size();
+    const int64_t n = b->n;
     const Layout L = layout(n, S->nn, S->np);
-    std::memcpy(sl.h_patches, q->patches.data(), sizeof(dtn_patch) * n);
+    {
+        int64_t at = 0;
+        for (const Query *q : b->qs) {
+            const int64_t m = (int64_t)q->patches.size();
+            std::memcpy(sl.h_patches + at, q->patches.data(), sizeof(dtn_patch) * m);
+            for (int64_t i = 0; i < m; ++i) {
+                sl.h_seed[at + i] = q->seed;
+                sl.h_sid0[at + i] = (uint32_t)(i * S->nn);
+                sl.h_se2[at + i] = q->se * q->se;
+            }
+            at += m;
+        }
+    }
     char *buf = nullptr;
     hipError_t e = hipMallocAsync((void **)&buf, L.total, s);
     if (e != hipSuccess) return fail(DTN_E_OOM, std::string("server: ") + hipGetErrorString(e));
@@ -203,13 +244,25 @@ dtn_status enqueue(dtn_server_s *S, Query *q)
     double *nodes = (double *)(buf + L.nodes), *stats = (double *)(buf + L.stats);
     int64_t *used = (int64_t *)(buf + L.used), *capped = (int64_t *)(buf + L.capped);
     double *neu = (double *)(buf + L.neu), *nse = (double *)(buf + L.nse), *ans = (double *)(buf + L.ans);
+    uint64_t *pseed = (uint64_t *)(buf + L.pseed), *nseed = (uint64_t *)(buf + L.nseed);
+    uint32_t *psid0 = (uint32_t *)(buf + L.psid0), *nsid = (uint32_t *)(buf + L.nsid);
+    double *pse2 = (double *)(buf + L.pse2), *nse2 = (double *)(buf + L.nse2);
     dtn_status st = DTN_OK;
-    e = hipMemcpyAsync(P.d_patches, sl.h_patches, sizeof(dtn_patch) * n, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) st = fail(DTN_E_DEVICE, std::string("server: ") + hipGetErrorString(e));
+    auto copy_in = [&](void *dst, const void *src, size_t bytes) {
+        if (st != DTN_OK) return;
+        const hipError_t ec = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+        if (ec != hipSuccess) st = fail(DTN_E_DEVICE, std::string("server: ") + hipGetErrorString(ec));
+    };
+    copy_in(P.d_patches, sl.h_patches, sizeof(dtn_patch) * n);
+    copy_in(pseed, sl.h_seed, sizeof(uint64_t) * n);
+    copy_in(psid0, sl.h_sid0, sizeof(uint32_t) * n);
+    copy_in(pse2, sl.h_se2, sizeof(double) * n);
     if (st == DTN_OK) st = launch_nodes(P, nodes, s);
+    if (st == DTN_OK) st = launch_node_ids(n, (int)S->nn, pseed, psid0, pse2, nseed, nsid, nse2, s);
     if (st == DTN_OK) {
-        const Adaptive a{S->cfg.pilot_walks, S->cfg.min_walks, S->cfg.max_walks, q->se};
-        st = launch_wos_adaptive(*S->g, nodes, n * S->nn, a, q->seed, nullptr, S->cfg.precision, stats, used, capped,
+        Adaptive a{S->cfg.pilot_walks, S->cfg.min_walks, S->cfg.max_walks, 1.0};
+        a.node_se2 = nse2;
+        st = launch_wos_adaptive(*S->g, nodes, n * S->nn, a, 0, nseed, nsid, S->cfg.precision, stats, used, capped,
                                  Schedule{}, s);
     }
     if (st == DTN_OK) st = launch_solve(P, stats, S->cfg.precision, neu, nse, s);
@@ -221,7 +274,7 @@ dtn_status enqueue(dtn_server_s *S, Query *q)
     const hipError_t ef = hipFreeAsync(buf, s);
     if (st == DTN_OK && ef != hipSuccess) st = fail(DTN_E_DEVICE, std::string("server: ") + hipGetErrorString(ef));
     if (st != DTN_OK) return st;
-    Completion *c = new Completion{S, q};
+    Completion *c = new Completion{S, b};
     e = hipLaunchHostFunc(s, on_done, c);
     if (e != hipSuccess) {
         delete c;
@@ -235,25 +288,37 @@ void dispatch_loop(dtn_server_s *S)
     (void)hipSetDevice(S->device);
     std::unique_lock<std::mutex> lk(S->mu);
     const int ns = (int)S->slots.size();
+    auto fits = [&](int64_t points) { return S->in_use + footprint(S->cfg, points) <= S->cfg.hbm_budget; };
     for (;;) {
         S->cv.wait(lk, [&] {
-            return S->stop || (!S->pending.empty() && S->busy < ns &&
-                               S->in_use + S->pending.front()->bytes <= S->cfg.hbm_budget);
+            return S->stop ||
+                   (!S->pending.empty() && S->busy < ns && fits((int64_t)S->pending.front()->patches.size()));
         });
         if (S->stop) return;
-        Query *q = S->pending.front();
-        S->pending.pop_front();
+        // first come, first served: the head, then the queries behind it while
+        // the batch stays within max_points and the budget
+        Batch *b = new Batch();
+        const double t = S->now();
+        while (!S->pending.empty()) {
+            Query *q = S->pending.front();
+            const int64_t m = (int64_t)q->patches.size();
+            if (!b->qs.empty() && (b->n + m > S->cfg.max_points || !fits(b->n + m))) break;
+            S->pending.pop_front();
+            q->t_start = t;
+            b->qs.push_back(q);
+            b->n += m;
+        }
+        b->bytes = footprint(S->cfg, b->n);
         int slot = 0;
         while (S->slots[slot].busy) ++slot;
         S->slots[slot].busy = true;
         ++S->busy;
-        S->in_use += q->bytes;
-        q->slot = slot;
-        q->t_start = S->now();
+        S->in_use += b->bytes;
+        b->slot = slot;
         lk.unlock();
-        const dtn_status st = enqueue(S, q);
+        const dtn_status st = enqueue(S, b);
         lk.lock();
-        if (st != DTN_OK) finish_locked(S, q, st);
+        if (st != DTN_OK) finish_locked(S, b, st);
     }
 }
 
@@ -378,6 +443,9 @@ dtn_status dtn_server_create(dtn_geometry g, const dtn_server_config *cfg, dtn_s
             for (Slot &sl : S->slots) {
                 if (sl.stream) (void)hipStreamDestroy(sl.stream);
                 if (sl.h_patches) (void)hipHostFree(sl.h_patches);
+                if (sl.h_seed) (void)hipHostFree(sl.h_seed);
+                if (sl.h_sid0) (void)hipHostFree(sl.h_sid0);
+                if (sl.h_se2) (void)hipHostFree(sl.h_se2);
                 if (sl.h_ans) (void)hipHostFree(sl.h_ans);
             }
         };
@@ -395,6 +463,9 @@ dtn_status dtn_server_create(dtn_geometry g, const dtn_server_config *cfg, dtn_s
         for (Slot &sl : S->slots) {
             if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
             if (e == hipSuccess) e = hipHostMalloc((void **)&sl.h_patches, sizeof(dtn_patch) * mp);
+            if (e == hipSuccess) e = hipHostMalloc((void **)&sl.h_seed, sizeof(uint64_t) * mp);
+            if (e == hipSuccess) e = hipHostMalloc((void **)&sl.h_sid0, sizeof(uint32_t) * mp);
+            if (e == hipSuccess) e = hipHostMalloc((void **)&sl.h_se2, sizeof(double) * mp);
             if (e == hipSuccess) e = hipHostMalloc((void **)&sl.h_ans, sizeof(double) * 4 * mp);
         }
         if (e != hipSuccess) {
@@ -431,6 +502,9 @@ void dtn_server_destroy(dtn_server s)
         (void)hipStreamSynchronize(sl.stream);
         (void)hipStreamDestroy(sl.stream);
         (void)hipHostFree(sl.h_patches);
+        (void)hipHostFree(sl.h_seed);
+        (void)hipHostFree(sl.h_sid0);
+        (void)hipHostFree(sl.h_se2);
         (void)hipHostFree(sl.h_ans);
     }
     (void)hipFree(s->d_class);
@@ -461,8 +535,8 @@ dtn_status dtn_server_submit(dtn_server s, uint64_t query_id, const double *pts,
         for (int64_t i = 0; i < n; ++i)
             if (!place_patch(s, pts + 3 * i, normals + 3 * i, q->patches[i], why))
                 return fail(DTN_E_ARG, at + "point " + std::to_string(i) + ": " + why);
-        q->bytes = footprint(s->cfg, n);
-        if (q->bytes > s->cfg.hbm_budget) return fail(DTN_E_OOM, at + "query exceeds the device memory budget");
+        if (footprint(s->cfg, n) > s->cfg.hbm_budget)
+            return fail(DTN_E_OOM, at + "query exceeds the device memory budget");
         std::lock_guard<std::mutex> lk(s->mu);
         q->t_submit = s->now();
         s->pending.push_back(q.release());

@@ -109,6 +109,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                                                          const int64_t *__restrict__ walks,
                                                          const int64_t *__restrict__ walk_begin,
                                                          const uint32_t *__restrict__ stream_id, uint64_t seed,
+                                                         const uint64_t *__restrict__ node_seed,
                                                          const int64_t *__restrict__ chunk_off,
                                                          const int64_t *__restrict__ meta, int64_t n,
                                                          ChunkPartial *__restrict__ out)
@@ -127,7 +128,6 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
     const int64_t total = uniform64(meta[1]);
     const int64_t chunk = (int64_t)blockIdx.x * (kWalkBlock / kWave) + wave;
     if (chunk >= total) return;
-    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const double eps = g.eps;
     {
         // point owning this chunk: largest i with chunk_off[i] <= chunk
@@ -142,6 +142,8 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
         const int64_t w_hi = min(wnode, w_lo + C);
         const int64_t wb = walk_begin ? walk_begin[node] : 0;
         const uint32_t sid = stream_id ? stream_id[node] : (uint32_t)node;
+        const uint64_t key = node_seed ? (uint64_t)uniform64((int64_t)node_seed[node]) : seed;
+        const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
         const double y0 = pts[3 * node], y1 = pts[3 * node + 1], y2 = pts[3 * node + 2];
         double sx = y0, sy = y1, sz = y2;
         project_f64<KIND>(g, sx, sy, sz, all_holes(g));
@@ -360,7 +362,8 @@ int device_cus()
 
 template <int KIND, int DATA, int PREC>
 hipError_t run(const Geometry &g, const double *pts, int64_t n, const int64_t *walks, const int64_t *walk_begin,
-               uint64_t seed, const uint32_t *stream_id, double *stats, int64_t *capped, const Schedule &sc,
+               uint64_t seed, const uint64_t *node_seed, const uint32_t *stream_id, double *stats, int64_t *capped,
+               const Schedule &sc,
                hipStream_t s)
 {
     // Aim for `oversub` chunks per resident wave (4 SIMDs x 8 waves per CU);
@@ -383,7 +386,7 @@ hipError_t run(const Geometry &g, const double *pts, int64_t n, const int64_t *w
     const int64_t blocks = (max_chunks + waves_per_block - 1) / waves_per_block;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_wos_walk<KIND, DATA, PREC>), dim3((unsigned)blocks), dim3(kWalkBlock), 0, s, g.dev, pts,
-                       walks, walk_begin, stream_id, seed, chunk_off, meta, n, part);
+                       walks, walk_begin, stream_id, seed, node_seed, chunk_off, meta, n, part);
     hipLaunchKernelGGL((k_wos_finalize<KIND, DATA>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g.dev, pts,
                        walks, n, chunk_off, part, stats, capped);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -392,31 +395,35 @@ hipError_t run(const Geometry &g, const double *pts, int64_t n, const int64_t *w
 
 template <int PREC>
 hipError_t dispatch(const Geometry &g, const double *pts, int64_t n, const int64_t *walks, const int64_t *wb,
-                    uint64_t seed, const uint32_t *sid, double *stats, int64_t *capped, const Schedule &sc,
+                    uint64_t seed, const uint64_t *ns, const uint32_t *sid, double *stats, int64_t *capped,
+                    const Schedule &sc,
                     hipStream_t s)
 {
     const bool src = g.dev.data_kind == DTN_DATA_POINT_SOURCES;
     constexpr int Q = DTN_DATA_HARMONIC_QUADRATIC, P = DTN_DATA_POINT_SOURCES;
     switch (g.dev.kind) {
     case DTN_BALL:
-        return src ? run<DTN_BALL, P, PREC>(g, pts, n, walks, wb, seed, sid, stats, capped, sc, s)
-                   : run<DTN_BALL, Q, PREC>(g, pts, n, walks, wb, seed, sid, stats, capped, sc, s);
+        return src ? run<DTN_BALL, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
+                   : run<DTN_BALL, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
     case DTN_BOX:
-        return src ? run<DTN_BOX, P, PREC>(g, pts, n, walks, wb, seed, sid, stats, capped, sc, s)
-                   : run<DTN_BOX, Q, PREC>(g, pts, n, walks, wb, seed, sid, stats, capped, sc, s);
+        return src ? run<DTN_BOX, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
+                   : run<DTN_BOX, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
     default:
-        return src ? run<DTN_BOX_MINUS_BOXES, P, PREC>(g, pts, n, walks, wb, seed, sid, stats, capped, sc, s)
-                   : run<DTN_BOX_MINUS_BOXES, Q, PREC>(g, pts, n, walks, wb, seed, sid, stats, capped, sc, s);
+        return src ? run<DTN_BOX_MINUS_BOXES, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
+                   : run<DTN_BOX_MINUS_BOXES, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
     }
 }
 
 hipError_t walk_all(const Geometry &g, const double *pts, int64_t n, const int64_t *walks, const int64_t *walk_begin,
-                    uint64_t seed, const uint32_t *stream_id, int precision, double *stats, int64_t *capped,
+                    uint64_t seed, const uint64_t *node_seed, const uint32_t *stream_id, int precision,
+                    double *stats, int64_t *capped,
                     const Schedule &sc, hipStream_t stream)
 {
     return precision == DTN_FP64
-               ? dispatch<DTN_FP64>(g, pts, n, walks, walk_begin, seed, stream_id, stats, capped, sc, stream)
-               : dispatch<DTN_FP32_MIXED>(g, pts, n, walks, walk_begin, seed, stream_id, stats, capped, sc, stream);
+               ? dispatch<DTN_FP64>(g, pts, n, walks, walk_begin, seed, node_seed, stream_id, stats, capped, sc,
+                                    stream)
+               : dispatch<DTN_FP32_MIXED>(g, pts, n, walks, walk_begin, seed, node_seed, stream_id, stats, capped,
+                                          sc, stream);
 }
 
 // ------------------------------------------------- distance (diagnostic)
@@ -455,12 +462,14 @@ __global__ __launch_bounds__(256) void k_fill_i64(int64_t *__restrict__ a, int64
 // Per point: total walks = clamp(ceil(var / se^2), w_min, w_max), never fewer
 // than the pilot; the remainder continues at walk index `pilot`.
 __global__ __launch_bounds__(256) void k_budget(const double *__restrict__ pilot_stats, int64_t n, int64_t pilot,
-                                                int64_t w_min, int64_t w_max, double se2,
+                                                int64_t w_min, int64_t w_max, double se2_all,
+                                                const double *__restrict__ node_se2,
                                                 int64_t *__restrict__ rem, int64_t *__restrict__ wb,
                                                 int64_t *__restrict__ used)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const double se2 = node_se2 ? node_se2[i] : se2_all;
     const double cnt = pilot_stats[4 * i], m2 = pilot_stats[4 * i + 2];
     const double var = cnt > 1.0 ? m2 / (cnt - 1.0) : 0.0;
     const double want = ceil(var / se2);
@@ -505,7 +514,8 @@ dtn_status launch_wos(const Geometry &g, const double *pts, int64_t n, const int
                       double *stats, int64_t *capped, const Schedule &sc, hipStream_t stream)
 {
     if (n == 0) return DTN_OK;
-    hipError_t e = walk_all(g, pts, n, walks, walk_begin, seed, stream_id, precision, stats, capped, sc, stream);
+    hipError_t e =
+        walk_all(g, pts, n, walks, walk_begin, seed, nullptr, stream_id, precision, stats, capped, sc, stream);
     if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_wos_eval: ") + hipGetErrorString(e));
     return DTN_OK;
 }
@@ -522,6 +532,7 @@ dtn_status launch_distance(const Geometry &g, const double *pts, int64_t n, int 
 }
 
 dtn_status launch_wos_adaptive(const Geometry &g, const double *pts, int64_t n, const Adaptive &a, uint64_t seed,
+                               const uint64_t *node_seed,
                                const uint32_t *stream_id, int precision, double *stats, int64_t *walks_used,
                                int64_t *capped, const Schedule &sc, hipStream_t s)
 {
@@ -538,11 +549,11 @@ dtn_status launch_wos_adaptive(const Geometry &g, const double *pts, int64_t n, 
     int64_t *rw = pw + n, *wb = rw + n, *pcap = wb + n, *rcap = pcap + n;
     const unsigned grid = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_fill_i64, dim3(grid), dim3(256), 0, s, pw, n, a.pilot);
-    e = walk_all(g, pts, n, pw, nullptr, seed, stream_id, precision, pstats, pcap, sc, s);
+    e = walk_all(g, pts, n, pw, nullptr, seed, node_seed, stream_id, precision, pstats, pcap, sc, s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_budget, dim3(grid), dim3(256), 0, s, pstats, n, a.pilot, a.w_min, a.w_max,
-                           a.se * a.se, rw, wb, walks_used);
-        e = walk_all(g, pts, n, rw, wb, seed, stream_id, precision, stats, rcap, sc, s);
+                           a.se * a.se, a.node_se2, rw, wb, walks_used);
+        e = walk_all(g, pts, n, rw, wb, seed, node_seed, stream_id, precision, stats, rcap, sc, s);
     }
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_merge, dim3(grid), dim3(256), 0, s, pstats, pcap, rcap, stats, capped, n);

@@ -2,9 +2,9 @@
 
 Each answer is checked against the oracle run on the same patch (centred on
 the query point, h from the same ladder, which the test recomputes on its
-own), the same seed and the same per-node stream ids; a query's answer must
-not depend on the other queries in flight; admission must hold the device
-memory of the queries in flight under the budget.
+own), the same seed and the same per-node stream ids; a query's walks must
+not depend on the queries it is batched with; admission must hold the
+device memory of the batches in flight under the budget.
 """
 import numpy as np
 import pytest
@@ -117,7 +117,12 @@ def test_answer_does_not_depend_on_the_batch():
     print("[gpu] server mix", flush=True)
     res = _run(mix, qs)
     mix.close()
-    np.testing.assert_array_equal(res[12]["answer"], a)
+    # the same walks (the pilot walks fit in one chunk per node either way,
+    # so the budgets agree exactly); the remainder's chunks depend on the
+    # batch, so the sums may round differently
+    b = res[12]["answer"]
+    np.testing.assert_array_equal(b[:, 2:], a[:, 2:])  # walks and h
+    np.testing.assert_allclose(b[:, :2], a[:, :2], rtol=1e-11, atol=1e-14)
     for d in res.values():
         assert np.all(np.isfinite(d["answer"]))
 
