@@ -72,10 +72,10 @@ SLOTS_PER_WALK = slots(WALK_OPS)
 # the kernel sources it was measured on (SHA-256 of these files).
 TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_amd/csrc/dtn_device.h",
                      "paper_1210_1491_amd/csrc/dtn_internal.h"],
-           "sha256": ["b3d3580a86b01bfc9cf90b22da45f5e52910d24b141d99a83681770f61ef145f",
-                      "af41727590874b2e00acf879b1ecbd0e79f349e067ca4b21a2d8af6909b490a8",
-                      "440dc9b508ae94ff738dd3b5e127533e365f606ef42f0f08ae155f3bb94cf9ba"],
-           "fetch_bytes": 71745.6 * 1024 * 2.00, "write_bytes": 43008.0 * 1024 * 1.00}
+           "sha256": ["57b473a8c183ed71ee6c977478a5a14118b8fcf17edc334d544ade50a8def51d",
+                      "86c969e96388662da42ed1099a2a8e613c01b29605d22dfcc5adb36afbf165b7",
+                      "41540727d59b3bb2be75175c57bfb792ec48c4fe0d61e3f72fd3a7aed8ac15fc"],
+           "fetch_bytes": 71760.6 * 1024 * 2.00, "write_bytes": 43008.0 * 1024 * 1.00}
 
 
 def traffic_if_current():
