@@ -43,12 +43,15 @@ SLOT_COST = {
 # for the box domain with point-source data, counted from what the step
 # definition requires, not from what the compiler emits.
 STEP_OPS = {
-    # distance (11), eps test (1), x2 (1), u(1-u) (2), sin/cos reduction, scale (6), s cos / s sin (2)
+    # distance (11), eps test (1), u1 = ldexp(k + 1/2, -32) (2), u(1-u) (2), x2 (1),
+    # sin/cos: x^2, x^3 and the two products of the angle addition (4), s cos / s sin (2)
     "fp64": {"f64": 23,
-             # uniforms (2), z (1), sqrt refinement (4), sin/cos polynomials (17), jump (3)
-             "f64fma": 27,
-             # cap test, Philox xors (half block: 10), counter word, quadrant selects (6), step counter
-             "i32": 19, "mad64": 10, "cvt": 2, "rsq64": 1},
+             # z (1), square root refinement and residual (6), sin/cos: remainder scaling (1),
+             # Taylor series (6), angle addition (2); jump (3)
+             "f64fma": 19,
+             # cap test, Philox xors (half block: 10), counter word, table index and
+             # remainder bits (3), step counter
+             "i32": 16, "mad64": 10, "cvt": 2, "rsq64": 1},
     # FP64 distance (11), eps test (1), jump shortening (1); FP32 uniforms (2 FMA), z (1),
     # u(1-u) (2), x2 (1), s cos / s sin (2); sqrt, sin, cos on the transcendental unit;
     # conversions: 2 uniforms, 3 direction components; 3 FP64 FMAs of the jump
