@@ -76,7 +76,7 @@ SLOTS_PER_WALK = slots(WALK_OPS)
 TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_amd/csrc/dtn_device.h",
                      "paper_1210_1491_amd/csrc/dtn_internal.h"],
            "sha256": ["57b473a8c183ed71ee6c977478a5a14118b8fcf17edc334d544ade50a8def51d",
-                      "86c969e96388662da42ed1099a2a8e613c01b29605d22dfcc5adb36afbf165b7",
+                      "a0fe30b20f6f6e9cd321396262d1d2d22704ada523cae1f48e667ff122259dd2",
                       "41540727d59b3bb2be75175c57bfb792ec48c4fe0d61e3f72fd3a7aed8ac15fc"],
            "fetch_bytes": 71760.6 * 1024 * 2.00, "write_bytes": 43008.0 * 1024 * 1.00}
 

@@ -78,43 +78,6 @@ __device__ __forceinline__ void sincos_2pi_word(uint32_t k, double tsin, double 
 }
 __device__ __forceinline__ uint32_t sincos_index(uint32_t k) { return (k + 0x800000u) >> 24; }
 
-// sin and cos of 2 pi u for u in (0,1).  The quarter-turn reduction is done
-// on 4u, where it is exact (q = nearest integer, f = 4u - q in [-1/2, 1/2]),
-// so no large-argument path is needed; sin and cos of r = f pi/2 in
-// [-pi/4, pi/4] come from their Taylor series to degree 17 and 18 (the first
-// omitted terms are below 1e-19), evaluated by Horner's rule in r^2.
-__device__ __forceinline__ void sincos_2pi_f64(double u, double &s, double &c)
-{
-    const double t = 4.0 * u;
-    const double q = floor(t + 0.5);
-    const double r = (t - q) * 1.5707963267948966;
-    const double x2 = r * r;
-    double ps = 1.0 / 355687428096000.0;
-    ps = fma(ps, x2, -1.0 / 1307674368000.0);
-    ps = fma(ps, x2, 1.0 / 6227020800.0);
-    ps = fma(ps, x2, -1.0 / 39916800.0);
-    ps = fma(ps, x2, 1.0 / 362880.0);
-    ps = fma(ps, x2, -1.0 / 5040.0);
-    ps = fma(ps, x2, 1.0 / 120.0);
-    ps = fma(ps, x2, -1.0 / 6.0);
-    const double sr = fma(ps * x2, r, r);
-    double pc = 1.0 / 6402373705728000.0;
-    pc = fma(pc, x2, -1.0 / 20922789888000.0);
-    pc = fma(pc, x2, 1.0 / 87178291200.0);
-    pc = fma(pc, x2, -1.0 / 479001600.0);
-    pc = fma(pc, x2, 1.0 / 3628800.0);
-    pc = fma(pc, x2, -1.0 / 40320.0);
-    pc = fma(pc, x2, 1.0 / 720.0);
-    pc = fma(pc, x2, -1.0 / 24.0);
-    pc = fma(pc, x2, 0.5);
-    const double cr = fma(-pc, x2, 1.0);
-    const int qi = (int)q & 3;
-    const double a = (qi & 1) ? cr : sr;
-    const double b = (qi & 1) ? sr : cr;
-    s = (qi & 2) ? -a : a;
-    c = ((qi + 1) & 2) ? -b : b;
-}
-
 // --------------------------------------------------- square roots (FP64)
 // 1/sqrt(x) and sqrt(x) for normal positive x: the hardware reciprocal
 // square root refined by two Newton steps (quadratic convergence), and
