@@ -34,6 +34,11 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// Walk schedule of a batch: small chunks (down to one walk per lane) so that
+// a small batch still spreads over many waves and finishes quickly; large
+// batches get chunks of total / (resident waves x 8) walks anyway.
+const Schedule kBatchSchedule{64, 8};
+
 struct Query {
     uint64_t id = 0;
     std::vector<dtn_patch> patches;
@@ -98,14 +103,13 @@ Layout layout(int64_t n, int64_t nn, int64_t np)
 
 // Device bytes of a batch of n points: its arrays plus the walk kernels'
 // stream-ordered scratch (adaptive statistics and budgets; chunk table and
-// partials for up to nodes + 256 CUs x 32 waves x 4 chunks, the default
-// schedule on MI355X).
+// partials for up to nodes + 256 CUs x 32 waves x oversub chunks, MI355X).
 int64_t footprint(const dtn_server_config &c, int64_t n)
 {
     const int64_t nn = (int64_t)c.n_theta * c.n_phi, np = (int64_t)c.n_rings * c.n_sectors;
     const int64_t nodes = n * nn;
     const int64_t adaptive = nodes * (4 * 8 + 5 * 8);
-    const int64_t walk = 8 * (nodes + 1) + 80 + 48 * (nodes + 256 * 32 * 4 + 1);
+    const int64_t walk = 8 * (nodes + 1) + 80 + 48 * (nodes + 256 * 32 * (int64_t)kBatchSchedule.oversub + 1);
     return (int64_t)layout(n, nn, np).total + adaptive + walk;
 }
 
@@ -263,7 +267,7 @@ dtn_status enqueue(dtn_server_s *S, Batch *b)
         Adaptive a{S->cfg.pilot_walks, S->cfg.min_walks, S->cfg.max_walks, 1.0};
         a.node_se2 = nse2;
         st = launch_wos_adaptive(*S->g, nodes, n * S->nn, a, 0, nseed, nsid, S->cfg.precision, stats, used, capped,
-                                 Schedule{}, s);
+                                 kBatchSchedule, s);
     }
     if (st == DTN_OK) st = launch_solve(P, stats, S->cfg.precision, neu, nse, s);
     if (st == DTN_OK) st = launch_answer(P, neu, stats, used, ans, s);

@@ -50,3 +50,24 @@ def test_host_operator_arguments_are_checked():
         dtn.class_operators(1, 16, 4, 8)
     with pytest.raises(dtn.DtnError):
         dtn.class_operators(8, 15, 4, 8)
+
+
+def test_server_footprint_is_host_side_and_checked():
+    """The device footprint the server's admission uses is a host function:
+    affine in the number of points (per-node arrays plus a fixed walk
+    scratch), at least the bytes of the batch's own arrays, and -1 for an
+    invalid configuration."""
+    from paper_1210_1491_amd import dtn
+    L = dtn.lib()
+    cfg = dtn.ServerConfigDesc(4, 1, 2 << 30, 100, 100, 1_000_000, 0.25, 16, 8, 16, 4, 8, 4096)
+    f = [L.dtn_server_footprint(ctypes.byref(cfg), n) for n in (1, 2, 100, 4096)]
+    nodes = 8 * 16
+    per_point = f[2] - f[1]
+    assert per_point > 0 and abs((f[3] - f[2]) - 3996 * per_point / 98) <= 4096 * 256
+    # the per-node arrays alone: nodes (24 B), stats (32), budgets and counts (8 + 8),
+    # walk identities (8 + 4 + 8); panels: Neumann data and SE (2 x 8 x 32)
+    assert per_point >= nodes * (24 + 32 + 16 + 20) + 32 * 16
+    bad = dtn.ServerConfigDesc(0, 1, 2 << 30, 100, 100, 1_000_000, 0.25, 16, 8, 16, 4, 8, 4096)
+    assert L.dtn_server_footprint(ctypes.byref(bad), 10) == -1
+    bad = dtn.ServerConfigDesc(4, 1, 2 << 30, 1, 100, 1_000_000, 0.25, 16, 8, 16, 4, 8, 4096)
+    assert L.dtn_server_footprint(ctypes.byref(bad), 10) == -1

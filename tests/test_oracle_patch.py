@@ -241,3 +241,52 @@ def test_propagated_se_matches_spread_over_seeds():
     z2 = ((np.array(sig) - np.mean(sig, axis=0)) / prop) ** 2
     dof = z2.size - z2.shape[1]
     assert 0.7 < z2.sum() / dof < 1.4
+
+
+def _point_patch(gd, x, nrm, h, layout=(8, 16, 4, 8)):
+    k = int(np.argmax(np.abs(nrm)))
+    t1 = np.zeros(3)
+    t1[(k + 1) % 3] = 1.0
+    return P.Patch(x, nrm, t1, h, *layout)
+
+
+def test_central_disk_answer_matches_exact_neumann():
+    """With exact node values the central-disk answer is the exact du/dn at
+    the patch centre up to the collocation error and the average over the
+    disk of radius h/4, both second order in h."""
+    gd = I.geometry_box_holes()
+    g = wos.Geometry(gd)
+    rng = np.random.default_rng(3)
+    pts, nrm = I.boundary_points(gd, 6, rng, edge_gap=0.1)
+    for x, n in zip(pts, nrm):
+        ex = P.exact_neumann(gd, x[None], n[None])[0]
+        scale = np.max(np.abs(P.grad_phi(gd, x[None])))
+        err = []
+        for h in (0.04, 0.02):
+            p = _point_patch(gd, x, n, h)
+            Y, _ = P.nodes_global(p)
+            v, _ = P.central_disk_answer(p, g, g.phi(Y), np.zeros(len(Y)))
+            err.append(abs(v - ex) / scale)
+        assert err[1] < 2e-5, err
+        # second order: halving h divides the error by about 4
+        assert err[1] < 1e-9 or 0.15 < err[1] / err[0] < 0.35, err
+
+
+def test_central_disk_answer_se_matches_noise_spread():
+    """Gaussian noise of known standard deviation on the node values: the
+    spread of the answer over draws matches the propagated standard error."""
+    gd = I.geometry_box_holes()
+    g = wos.Geometry(gd)
+    x, n = I.boundary_points(gd, 1, np.random.default_rng(5), edge_gap=0.1)
+    p = _point_patch(gd, x[0], n[0], 0.05)
+    Y, _ = P.nodes_global(p)
+    u = g.phi(Y)
+    rng = np.random.default_rng(6)
+    sd = 1e-3 * (1.0 + rng.random(len(Y)))
+    vals = []
+    for _ in range(300):
+        v, se = P.central_disk_answer(p, g, u + sd * rng.standard_normal(len(Y)), sd)
+        vals.append(v)
+    spread = np.std(vals, ddof=1)
+    # sd of a sample sd over 300 draws is about 4 %
+    assert abs(spread / se - 1.0) < 0.15, (spread, se)
