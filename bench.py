@@ -75,8 +75,8 @@ SLOTS_PER_WALK = slots(WALK_OPS)
 # the kernel sources it was measured on (SHA-256 of these files).
 TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_amd/csrc/dtn_device.h",
                      "paper_1210_1491_amd/csrc/dtn_internal.h"],
-           "sha256": ["57b473a8c183ed71ee6c977478a5a14118b8fcf17edc334d544ade50a8def51d",
-                      "a0fe30b20f6f6e9cd321396262d1d2d22704ada523cae1f48e667ff122259dd2",
+           "sha256": ["f9cc806745e33697bb37458aa8b98eb33d1cf9887a15b67e1737d3e32df28d9a",
+                      "40b228f48b5dd299308485a89c904d2d70c5a1b9a848fd6f1c826d1a1e855ae1",
                       "41540727d59b3bb2be75175c57bfb792ec48c4fe0d61e3f72fd3a7aed8ac15fc"],
            "fetch_bytes": 71760.6 * 1024 * 2.00, "write_bytes": 43008.0 * 1024 * 1.00}
 

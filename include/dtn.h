@@ -150,10 +150,13 @@ dtn_status dtn_wos_eval(dtn_geometry g, const double *pts, int64_t n, const int6
                         int32_t precision, double *stats, int64_t *capped, void *stream);
 
 /* Distance from n points inside Omega to its boundary, computed as the walk
- * kernels compute it (the radius of the largest ball of a walk step, Sec. 2),
- * in FP64 for both precisions.  For a box minus holes the walk kernels look
- * up, per grid cell, the holes that can be nearest; this call lets a caller
- * check that lookup against a plain minimum over all surfaces.
+ * kernels of `precision` compute it (the radius of the largest ball of a walk
+ * step, Sec. 2): in FP64 for both; the FP32-mixed walks take the distance to
+ * a hole as q * rsq(q^2) without refinement (relative error below 6e-8, less
+ * than the 2^-22 by which their jumps are shortened).  For a box minus holes
+ * the walk kernels look up, per grid cell, the holes that can be nearest;
+ * this call lets a caller check that lookup against a plain minimum over all
+ * surfaces.
  *   pts device [n][3]; dist device [n] out.  Errors: DTN_E_ARG. */
 dtn_status dtn_boundary_distance(dtn_geometry g, const double *pts, int64_t n, int32_t precision, double *dist,
                                  void *stream);

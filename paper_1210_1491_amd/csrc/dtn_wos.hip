@@ -199,7 +199,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                 // distance would need an FP64 recheck inside a rounding band
                 // around the shell, which some lane of a wave needs at almost
                 // every step, and a shrunken jump everywhere)
-                const double d = dist_f64<KIND>(g, x, y, z, cand);
+                const double d = dist_f64<KIND, PREC != DTN_FP64>(g, x, y, z, cand);
                 if (d < eps || (int64_t)nstep >= g.max_steps) {
                     fin = true;
                     capped += (d >= eps) ? 1ull : 0ull;
@@ -428,7 +428,7 @@ hipError_t walk_all(const Geometry &g, const double *pts, int64_t n, const int64
 
 // ------------------------------------------------- distance (diagnostic)
 
-template <int KIND>
+template <int KIND, bool FAST>
 __global__ __launch_bounds__(256) void k_distance(DevGeom g, const double *__restrict__ pts, int64_t n,
                                                   double *__restrict__ out)
 {
@@ -438,16 +438,17 @@ __global__ __launch_bounds__(256) void k_distance(DevGeom g, const double *__res
     uint32_t cand = 0;
     if constexpr (KIND == DTN_BOX_MINUS_BOXES) cand = hole_candidates(g, live, (float)x, (float)y, (float)z);
     if (!live) return;
-    out[i] = dist_f64<KIND>(g, x, y, z, cand);
+    out[i] = dist_f64<KIND, FAST>(g, x, y, z, cand);
 }
 
+template <bool FAST>
 void distance_kind(const Geometry &g, const double *pts, int64_t n, double *out, hipStream_t s)
 {
     const dim3 grid((unsigned)((n + 255) / 256)), block(256);
     switch (g.dev.kind) {
-    case DTN_BALL: hipLaunchKernelGGL((k_distance<DTN_BALL>), grid, block, 0, s, g.dev, pts, n, out); break;
-    case DTN_BOX: hipLaunchKernelGGL((k_distance<DTN_BOX>), grid, block, 0, s, g.dev, pts, n, out); break;
-    default: hipLaunchKernelGGL((k_distance<DTN_BOX_MINUS_BOXES>), grid, block, 0, s, g.dev, pts, n, out);
+    case DTN_BALL: hipLaunchKernelGGL((k_distance<DTN_BALL, FAST>), grid, block, 0, s, g.dev, pts, n, out); break;
+    case DTN_BOX: hipLaunchKernelGGL((k_distance<DTN_BOX, FAST>), grid, block, 0, s, g.dev, pts, n, out); break;
+    default: hipLaunchKernelGGL((k_distance<DTN_BOX_MINUS_BOXES, FAST>), grid, block, 0, s, g.dev, pts, n, out);
     }
 }
 
@@ -523,9 +524,9 @@ dtn_status launch_wos(const Geometry &g, const double *pts, int64_t n, const int
 dtn_status launch_distance(const Geometry &g, const double *pts, int64_t n, int precision, double *dist,
                            hipStream_t stream)
 {
-    (void)precision;  // both paths measure distances in FP64
     if (n == 0) return DTN_OK;
-    distance_kind(g, pts, n, dist, stream);
+    if (precision == DTN_FP64) distance_kind<false>(g, pts, n, dist, stream);
+    else distance_kind<true>(g, pts, n, dist, stream);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_boundary_distance: ") + hipGetErrorString(e));
     return DTN_OK;

@@ -196,4 +196,7 @@ def test_boundary_distance_with_hole_grid_matches_oracle():
     d64 = dtn.boundary_distance(g, P, "fp64").cpu().numpy()
     d32 = dtn.boundary_distance(g, P, "fp32").cpu().numpy()
     assert np.max(np.abs(d64 - d_ora) / np.maximum(d_ora, 1e-300)) < 1e-14
-    np.testing.assert_array_equal(d32, d64)  # both paths measure distances in FP64
+    # the FP32-mixed walks use an unrefined rsq for hole distances: within
+    # 6e-8 relative, below the 2^-22 by which their jumps are shortened
+    assert np.max(np.abs(d32 - d64) / d64) < 6e-8
+    assert np.all(d32 <= d64 * (1.0 + 2.0 ** -22))
