@@ -136,6 +136,7 @@ void dtn_destroy_geometry(dtn_geometry g);
  *              (lets a caller extend an estimate: walks [b, b+walks))
  *   seed       Philox key
  *   stream_id  device [n] per-point stream ids, or NULL for the point index
+ *              (then n <= 2^32, so that no two points share a stream)
  *   precision  DTN_FP64 (all in FP64) or DTN_FP32_MIXED (the direction in
  *              FP32: uniforms, square root, sin and cos; distance, epsilon
  *              test, jump, position, projection, scores and sums in FP64)

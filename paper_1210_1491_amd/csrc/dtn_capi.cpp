@@ -412,6 +412,8 @@ dtn_status dtn_wos_eval(dtn_geometry g, const double *pts, int64_t n, const int6
             return fail(DTN_E_ARG, "dtn_wos_eval: unknown precision");
         if (n > 0 && (!pts || !walks || !stats)) return fail(DTN_E_ARG, "dtn_wos_eval: NULL array");
         if (n > ((int64_t)1 << 40)) return fail(DTN_E_ARG, "dtn_wos_eval: n too large");
+        if (!stream_id && n > ((int64_t)1 << 32))
+            return fail(DTN_E_ARG, "dtn_wos_eval: more than 2^32 points need explicit stream ids");
         return launch_wos(g->g, pts, n, walks, walk_begin, seed, stream_id, precision, stats, capped, Schedule{},
                           (hipStream_t)stream);
     } catch (...) {
@@ -466,6 +468,8 @@ dtn_status dtn_wos_adaptive(dtn_geometry g, const double *pts, int64_t n, const 
         if (n < 0 || n > ((int64_t)1 << 40)) return fail(DTN_E_ARG, at + "n outside [0, 2^40]");
         if (precision != DTN_FP64 && precision != DTN_FP32_MIXED) return fail(DTN_E_ARG, at + "unknown precision");
         if (n > 0 && (!pts || !stats || !walks_used)) return fail(DTN_E_ARG, at + "NULL array");
+        if (!stream_id && n > ((int64_t)1 << 32))
+            return fail(DTN_E_ARG, at + "more than 2^32 points need explicit stream ids");
         const dtn_adaptive &b = *budget;
         if (b.pilot_walks < 2 || b.pilot_walks > ((int64_t)1 << 40))
             return fail(DTN_E_ARG, at + "pilot_walks outside [2, 2^40]");
