@@ -61,6 +61,45 @@ def test_cube_1536_full_size():
     assert np.max(np.abs(u[far] - ue[far])) < 1e-3 * np.sqrt(np.mean(ue ** 2))
 
 
+@pytest.mark.timeout(600)
+def test_cube_1536_full_size_fp32_mixed():
+    """The same workload through the FP32-mixed walks and the FP32-MFMA LU
+    solve with FP64 refinement (the benchmark's second variant): sampled nodes
+    within 4 combined SE of the oracle's FP64 walks, the same number of steps
+    to within 1 %, and the same Neumann accuracy against the exact data."""
+    from paper_1210_1491_amd import dtn
+    gd = I.geometry_cube_sources()
+    pd = I.patches_cube_tiles()
+    print("[gpu] full cube workload, FP32-mixed", flush=True)
+    g = dtn.Geometry(gd)
+    plan = dtn.Plan(g, pd)
+    nodes = plan.nodes()
+    W = torch.full((plan.num_nodes,), 100_000, dtype=torch.int64, device="cuda")
+    stats, capped = dtn.wos_eval(g, nodes, W, seed=2, precision="fp32")
+    sig, se = plan.solve(stats, precision="fp32")
+    torch.cuda.synchronize()
+    st, sig = stats.cpu().numpy(), sig.cpu().numpy()
+    assert int(capped.sum()) == 0
+    ps = OP.patches_from_desc(pd, gd)
+    rng = np.random.default_rng(18)
+    sample = np.sort(rng.choice(plan.num_nodes, 16, replace=False))
+    on = nodes.cpu().numpy()[sample]
+    o = OW.wos_nodes(OW.Geometry(gd), on, 100_000, seed=2, stream_id=sample.astype(np.uint32))
+    gse = np.sqrt(st[sample, 2] / (st[sample, 0] - 1) / st[sample, 0])
+    z = np.abs(st[sample, 1] - o["mean"]) / np.sqrt(gse ** 2 + o["se"] ** 2)
+    assert np.all(z < 4), z
+    assert abs(st[sample, 3].sum() / o["steps"].sum() - 1.0) < 0.01
+    ex, area, tr = [], [], []
+    for p in ps:
+        xg, ng, ar, r = OP.collocation_points(p)
+        ex.append(OP.exact_neumann(gd, xg, ng))
+        area.append(ar)
+        tr.append(r < 0.7 * p.h)
+    err = OP.rel_l2(sig, *map(np.concatenate, (ex, area, tr)))
+    print(f"[gpu] neumann rel-L2 vs exact (FP32-mixed) {err:.3e}", flush=True)
+    assert err < 2e-2
+
+
 @pytest.mark.timeout(900)
 def test_box_holes_full_size():
     """The uneven-batching workload at full size (5994 patches, 931104 nodes,
