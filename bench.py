@@ -241,9 +241,9 @@ def serving(precision, window, rate, se_target, sweep_fraction=0.5, sweep_window
     gd = cfg["geometry"]()
     g = dtn.Geometry(gd)
 
-    def run(rate_qps, n):
+    def run(rate_qps, n, prec=precision):
         qs = I.serving_queries(gd, n_queries=n, rate=rate_qps, seed=cfg["seed"])
-        S = dtn.Server(g, n_streams=4, precision=precision, hbm_budget=cfg["hbm_budget"],
+        S = dtn.Server(g, n_streams=4, precision=prec, hbm_budget=cfg["hbm_budget"],
                        pilot_walks=cfg["pilot_walks"], min_walks=cfg["min_walks"], max_walks=cfg["max_walks"],
                        h_max=cfg["h_max"], ladder=cfg["ladder"], layout=cfg["layout"])
         t0 = S.clock()
@@ -269,10 +269,16 @@ def serving(precision, window, rate, se_target, sweep_fraction=0.5, sweep_window
     stable = run(sweep_fraction * main["served_qps"], sweep_window)
     print(f"[bench] serving at {stable['rate_qps']:.2f} q/s: p50 {stable['p50_ms']:.0f} ms", file=sys.stderr,
           flush=True)
+    low = run(0.5 * sweep_fraction * main["served_qps"], sweep_window // 2)
+    print(f"[bench] serving at {low['rate_qps']:.2f} q/s: p50 {low['p50_ms']:.0f} ms", file=sys.stderr, flush=True)
+    # the plain FP64 walks and solve on the same arrival trace as the stable run
+    stable64 = run(sweep_fraction * main["served_qps"], sweep_window, prec="fp64")
+    print(f"[bench] serving FP64 at {stable64['rate_qps']:.2f} q/s: p50 {stable64['p50_ms']:.0f} ms",
+          file=sys.stderr, flush=True)
     return {"workload": f"box_holes geometry resident; Poisson arrivals; 1..4096 points per query (log-uniform); "
                         f"patch per point (h = 0.25 * 2^-j, 8x16 nodes, 32 panels); adaptive walks "
                         f"{cfg['min_walks']}..{cfg['max_walks']} at SE {se_target} per node; 4 streams, 2 GB budget",
-            "precision": precision, "offered": main, "stable": stable}
+            "precision": precision, "offered": main, "stable": stable, "low": low, "stable_fp64": stable64}
 
 
 def cpu_baseline(gd, pd_all, walks_per_node):
