@@ -154,9 +154,10 @@ def box_holes(precision, steps, with_cpu=True, se_target=None, tune=True):
     """Uneven batching: the box [0,4]^3 minus 20 holes, 5994 patches in five
     panel classes (8..128 panels), adaptive walks 1e3..2e5 per node at a
     target standard error of 1e-3, all in one adaptive call (pilot launch,
-    budgets, one launch over the uneven remainder, merge), then the solve.
-    The walk schedule comes from the autotuner (timed on a sample of the
-    previous step's work list)."""
+    budgets, one launch over the uneven remainder, merge), then the solve,
+    captured in a HIP graph and replayed per step.  The walk schedule comes
+    from the autotuner (timed on a sample of the remainder's work list as a
+    pilot estimates it)."""
     import torch
 
     import dtn_inputs as I
@@ -188,13 +189,22 @@ def box_holes(precision, steps, with_cpu=True, se_target=None, tune=True):
     else:
         sched, table = dict(autotune.DEFAULT), {}
     print(f"[bench] box_holes schedule {sched}", file=sys.stderr, flush=True)
+    # one step (adaptive walks over all patches + solve) captured once in a
+    # HIP graph and replayed per timed step
+    neu = torch.empty(plan.num_panels, dtype=torch.float64, device="cuda")
+    nse = torch.empty(plan.num_panels, dtype=torch.float64, device="cuda")
+    cap_stream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=cap_stream):
+        dtn.wos_adaptive(g, nodes, cfg["seed"], *budget, precision=precision, schedule=sched, stats=stats,
+                         walks_used=used, capped=capped)
+        plan.solve(stats, precision=precision, neumann=neu, neumann_se=nse)
+    torch.cuda.synchronize()
     times = []
     for _ in range(steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        dtn.wos_adaptive(g, nodes, cfg["seed"], *budget, precision=precision, schedule=sched, stats=stats,
-                         walks_used=used, capped=capped)
-        neu, nse = plan.solve(stats, precision=precision)
+        graph.replay()
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         print(f"[bench] box_holes step {times[-1]:.2f} s", file=sys.stderr, flush=True)
