@@ -310,18 +310,21 @@ def boundary_points(gd, n, rng, edge_gap=1e-4):
     return pts, nrm
 
 
-def serving_queries(gd, n_queries=600, rate=200.0, seed=5, max_points=4096):
+def serving_queries(gd, n_queries=600, rate=200.0, seed=5, max_points=4096, se_range=(1e-4, 1e-2)):
     """Poisson arrivals at ``rate`` queries/s; each query has a point count
-    log-uniform on [1, max_points] and points uniform by area on the
-    boundary.  Returns a list of dicts (t, pts, normals, seed)."""
+    log-uniform on [1, max_points], points uniform by area on the boundary
+    and a required standard error log-uniform on ``se_range``.  Returns a
+    list of dicts (t, pts, normals, se, seed)."""
     rng = np.random.default_rng([seed, 13])
     t = np.cumsum(rng.exponential(1.0 / rate, n_queries))
+    lo, hi = np.log(se_range[0]), np.log(se_range[1])
     out = []
     for i in range(n_queries):
         m = int(np.floor(np.exp(rng.random() * np.log(max_points + 1))))
         m = min(max(m, 1), max_points)
         pts, nrm = boundary_points(gd, m, rng)
-        out.append({"t": float(t[i]), "pts": pts, "normals": nrm, "seed": int(seed) * 1_000_003 + i})
+        se = float(np.exp(lo + (hi - lo) * rng.random()))
+        out.append({"t": float(t[i]), "pts": pts, "normals": nrm, "se": se, "seed": int(seed) * 1_000_003 + i})
     return out
 
 
@@ -348,7 +351,7 @@ CONFIGS = {
         "queries": serving_queries,
         "rate": 200.0,
         "n_queries": 600,
-        "se_target": 1e-3,
+        "se_range": (1e-4, 1e-2),
         "pilot_walks": 100,
         "min_walks": 100,
         "max_walks": 1_000_000,

@@ -274,6 +274,17 @@ dtn_status dtn_potential(dtn_plan p, const double *neumann, const double *target
  * seed and its nodes only (Philox key = its seed, stream id = node index
  * within the query), so its walk set does not depend on what it is batched
  * with (its sums may round differently).
+ * Graph replay (graph_replay = 1): a batch of n points is padded to the
+ * smallest size bucket B >= n (B = n up to 8, then m 2^e with m in 5..8, at
+ * most max_points), and its whole device pass (copies in, walks, solve,
+ * answers, copy out, stream-ordered alloc and free) is one HIP graph,
+ * captured once per stream and bucket and replayed for every later batch of
+ * that bucket.  Padding rows repeat the batch's first patch with an infinite
+ * SE target, so they take only the pilot walks; their answers are dropped.
+ * Budgets and footprints are those of the padded batch.  This mode is
+ * switched off: its tests pass, but a serving run with four streams crashed
+ * the host process with a cause not yet shown, so dtn_server_create rejects
+ * it (DTN_E_ARG); dtn_server_footprint still reports its padded sizes.
  * Only box domains (with or without holes) are served: every point must lie
  * on a face, with the face's outward normal. */
 typedef struct dtn_server_s *dtn_server; /* opaque, library-owned */
@@ -287,6 +298,11 @@ typedef struct {
     int32_t ladder;      /* number of rungs h_max 2^-j, j = 0..ladder-1, 1..40 */
     int32_t n_theta, n_phi, n_rings, n_sectors; /* patch layout (as dtn_patch) */
     int64_t max_points;  /* largest query and batch (points), 1..2^20; sizes pinned staging */
+    int32_t graph_replay;       /* 0: direct launches; 1: replay a HIP graph per size bucket
+                                   (rows padded, see below) -- switched off: rejected by
+                                   dtn_server_create with DTN_E_ARG, see below */
+    int32_t max_batch_queries;  /* queries joined into one batch at most; 0 = no limit,
+                                   1 = one query per batch (no batching across requests) */
 } dtn_server_config;
 
 /* Completion record of a query; times in seconds on the server's clock. */
@@ -305,7 +321,8 @@ typedef struct {
 dtn_status dtn_server_create(dtn_geometry g, const dtn_server_config *cfg, dtn_server *out);
 void dtn_server_destroy(dtn_server s);
 
-/* Device bytes a batch of n_points reserves under this configuration. */
+/* Device bytes a batch of n_points reserves under this configuration (of
+ * its padded size under graph replay). */
 int64_t dtn_server_footprint(const dtn_server_config *cfg, int64_t n_points);
 
 /* Seconds since the server was created (the clock of dtn_query_done). */

@@ -380,7 +380,7 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
         hipMemPool_t pool;
         if (hipDeviceGetDefaultMemPool(&pool, g.device) == hipSuccess) {
             uint64_t thr = UINT64_MAX;
-            hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
         }
         *out = G.release();
         return DTN_OK;
@@ -392,12 +392,12 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
 void dtn_destroy_geometry(dtn_geometry g)
 {
     if (!g) return;
-    hipFree(g->g.d_hole_ce);
-    hipFree(g->g.d_hole_box);
-    hipFree(g->g.d_hole_f32);
-    hipFree(g->g.d_sincos);
-    hipFree(g->g.d_cell_mask);
-    hipFree(g->g.d_src);
+    (void)hipFree(g->g.d_hole_ce);
+    (void)hipFree(g->g.d_hole_box);
+    (void)hipFree(g->g.d_hole_f32);
+    (void)hipFree(g->g.d_sincos);
+    (void)hipFree(g->g.d_cell_mask);
+    (void)hipFree(g->g.d_src);
     delete g;
 }
 
@@ -640,11 +640,11 @@ dtn_status dtn_create_plan(dtn_geometry g, const dtn_patch *patches, int64_t n_p
 void dtn_destroy_plan(dtn_plan p)
 {
     if (!p) return;
-    hipFree(p->p.d_classes);
-    hipFree(p->p.d_patches);
-    hipFree(p->p.d_patch_class);
-    hipFree(p->p.d_node_off);
-    hipFree(p->p.d_panel_off);
+    (void)hipFree(p->p.d_classes);
+    (void)hipFree(p->p.d_patches);
+    (void)hipFree(p->p.d_patch_class);
+    (void)hipFree(p->p.d_node_off);
+    (void)hipFree(p->p.d_panel_off);
     delete p;
 }
 

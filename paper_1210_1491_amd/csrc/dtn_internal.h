@@ -144,6 +144,8 @@ dtn_status launch_answer(const Plan &p, const double *neumann, const double *nod
 
 // Per-node Philox keys, stream ids and squared SE targets of a batch of
 // queries from per-patch values (dtn_patch.hip).
+// Compute units of the current device (cached per thread).
+int device_cus();
 dtn_status launch_node_ids(int64_t n_patches, int nn, const uint64_t *pseed, const uint32_t *psid0,
                            const double *pse2, uint64_t *nseed, uint32_t *nsid, double *nse2, hipStream_t stream);
 

@@ -13,6 +13,11 @@
 // host function enqueued behind the batch copies each query's answers out of
 // pinned staging, records the completions and releases the stream and the
 // memory, so the next batch can start while others are still in flight.
+//
+// Under graph replay the device pass of a batch is padded to a size bucket
+// and recorded once per stream and bucket into a HIP graph (stream capture,
+// thread-local mode, on the dispatcher thread); later batches of the bucket
+// refill the stream's pinned staging and replay it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,6 +26,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -51,6 +57,7 @@ struct Query {
 struct Batch {
     std::vector<Query *> qs;
     int64_t n = 0;      // points (patches)
+    int64_t rows = 0;   // n padded to its size bucket (n under direct launches)
     int64_t bytes = 0;  // device memory reserved
     int slot = -1;
 };
@@ -63,6 +70,7 @@ struct Slot {
     uint32_t *h_sid0 = nullptr;      // [max_points] query-local index of the patch's first node
     double *h_se2 = nullptr;         // [max_points] squared SE target per patch
     double *h_ans = nullptr;         // [max_points][4]
+    std::map<int64_t, hipGraphExec_t> graphs;  // captured device pass per size bucket
     bool busy = false;
 };
 
@@ -101,11 +109,25 @@ Layout layout(int64_t n, int64_t nn, int64_t np)
     return L;
 }
 
-// Device bytes of a batch of n points: its arrays plus the walk kernels'
-// stream-ordered scratch (adaptive statistics and budgets; chunk table and
-// partials for up to nodes + 256 CUs x 32 waves x oversub chunks, MI355X).
-int64_t footprint(const dtn_server_config &c, int64_t n)
+// Rows a batch of n points occupies: n itself under direct launches; under
+// graph replay the smallest bucket >= n (n up to 8, then m 2^e with m in
+// 5..8, so padding stays under a quarter of the batch), at most max_points.
+int64_t padded_rows(const dtn_server_config &c, int64_t n)
 {
+    if (!c.graph_replay || n <= 8) return n;
+    int e = 0;
+    while ((int64_t)8 << e < n) ++e;  // 4 2^e < n <= 8 2^e
+    const int64_t step = (int64_t)1 << e;
+    return std::min((n + step - 1) / step * step, c.max_points);
+}
+
+// Device bytes of a batch of n points: its (padded) arrays plus the walk
+// kernels' stream-ordered scratch (adaptive statistics and budgets; chunk
+// table and partials for up to nodes + 256 CUs x 32 waves x oversub chunks,
+// MI355X).
+int64_t footprint(const dtn_server_config &c, int64_t n_points)
+{
+    const int64_t n = padded_rows(c, n_points);
     const int64_t nn = (int64_t)c.n_theta * c.n_phi, np = (int64_t)c.n_rings * c.n_sectors;
     const int64_t nodes = n * nn;
     const int64_t adaptive = nodes * (4 * 8 + 5 * 8);
@@ -136,6 +158,8 @@ bool valid_config(const dtn_server_config &c, std::string &why)
              c.n_rings > 16 || c.n_sectors < 2 || c.n_sectors > 32 || c.n_rings * c.n_sectors > 128)
         why = "unsupported patch layout";
     else if (c.max_points < 1 || c.max_points > ((int64_t)1 << 20)) why = "max_points outside [1, 2^20]";
+    else if (c.graph_replay != 0 && c.graph_replay != 1) why = "graph_replay must be 0 or 1";
+    else if (c.max_batch_queries < 0) why = "max_batch_queries must be >= 0";
     else return true;
     return false;
 }
@@ -215,25 +239,13 @@ void on_done(void *arg)
     finish_locked(S, b, DTN_OK);
 }
 
-dtn_status enqueue(dtn_server_s *S, Batch *b)
+// The device pass of a batch of `rows` patches on stream s, from the slot's
+// pinned staging to its answers in pinned staging: every call is
+// stream-ordered, so the same sequence runs directly or under capture.
+dtn_status record_pass(dtn_server_s *S, Slot &sl, int64_t rows, hipStream_t s)
 {
-    Slot &sl = S->slots[b->slot];
-    hipStream_t s = sl.stream;
-    const int64_t n = b->n;
+    const int64_t n = rows;
     const Layout L = layout(n, S->nn, S->np);
-    {
-        int64_t at = 0;
-        for (const Query *q : b->qs) {
-            const int64_t m = (int64_t)q->patches.size();
-            std::memcpy(sl.h_patches + at, q->patches.data(), sizeof(dtn_patch) * m);
-            for (int64_t i = 0; i < m; ++i) {
-                sl.h_seed[at + i] = q->seed;
-                sl.h_sid0[at + i] = (uint32_t)(i * S->nn);
-                sl.h_se2[at + i] = q->se * q->se;
-            }
-            at += m;
-        }
-    }
     char *buf = nullptr;
     hipError_t e = hipMallocAsync((void **)&buf, L.total, s);
     if (e != hipSuccess) return fail(DTN_E_OOM, std::string("server: ") + hipGetErrorString(e));
@@ -252,15 +264,15 @@ dtn_status enqueue(dtn_server_s *S, Batch *b)
     uint32_t *psid0 = (uint32_t *)(buf + L.psid0), *nsid = (uint32_t *)(buf + L.nsid);
     double *pse2 = (double *)(buf + L.pse2), *nse2 = (double *)(buf + L.nse2);
     dtn_status st = DTN_OK;
-    auto copy_in = [&](void *dst, const void *src, size_t bytes) {
+    auto copy = [&](void *dst, const void *src, size_t bytes, hipMemcpyKind kind) {
         if (st != DTN_OK) return;
-        const hipError_t ec = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+        const hipError_t ec = hipMemcpyAsync(dst, src, bytes, kind, s);
         if (ec != hipSuccess) st = fail(DTN_E_DEVICE, std::string("server: ") + hipGetErrorString(ec));
     };
-    copy_in(P.d_patches, sl.h_patches, sizeof(dtn_patch) * n);
-    copy_in(pseed, sl.h_seed, sizeof(uint64_t) * n);
-    copy_in(psid0, sl.h_sid0, sizeof(uint32_t) * n);
-    copy_in(pse2, sl.h_se2, sizeof(double) * n);
+    copy(P.d_patches, sl.h_patches, sizeof(dtn_patch) * n, hipMemcpyHostToDevice);
+    copy(pseed, sl.h_seed, sizeof(uint64_t) * n, hipMemcpyHostToDevice);
+    copy(psid0, sl.h_sid0, sizeof(uint32_t) * n, hipMemcpyHostToDevice);
+    copy(pse2, sl.h_se2, sizeof(double) * n, hipMemcpyHostToDevice);
     if (st == DTN_OK) st = launch_nodes(P, nodes, s);
     if (st == DTN_OK) st = launch_node_ids(n, (int)S->nn, pseed, psid0, pse2, nseed, nsid, nse2, s);
     if (st == DTN_OK) {
@@ -271,15 +283,79 @@ dtn_status enqueue(dtn_server_s *S, Batch *b)
     }
     if (st == DTN_OK) st = launch_solve(P, stats, S->cfg.precision, neu, nse, s);
     if (st == DTN_OK) st = launch_answer(P, neu, stats, used, ans, s);
-    if (st == DTN_OK) {
-        e = hipMemcpyAsync(sl.h_ans, ans, sizeof(double) * 4 * n, hipMemcpyDeviceToHost, s);
-        if (e != hipSuccess) st = fail(DTN_E_DEVICE, std::string("server: ") + hipGetErrorString(e));
-    }
+    copy(sl.h_ans, ans, sizeof(double) * 4 * n, hipMemcpyDeviceToHost);
     const hipError_t ef = hipFreeAsync(buf, s);
     if (st == DTN_OK && ef != hipSuccess) st = fail(DTN_E_DEVICE, std::string("server: ") + hipGetErrorString(ef));
+    return st;
+}
+
+// The slot's graph for `rows`, captured on first use.
+dtn_status slot_graph(dtn_server_s *S, Slot &sl, int64_t rows, hipGraphExec_t *out)
+{
+    auto it = sl.graphs.find(rows);
+    if (it != sl.graphs.end()) {
+        *out = it->second;
+        return DTN_OK;
+    }
+    hipError_t e = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("server capture: ") + hipGetErrorString(e));
+    const dtn_status st = record_pass(S, sl, rows, sl.stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(sl.stream, &graph);  // ends the capture on every path
+    if (st != DTN_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("server capture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("server instantiate: ") + hipGetErrorString(e));
+    sl.graphs.emplace(rows, exec);
+    *out = exec;
+    return DTN_OK;
+}
+
+dtn_status enqueue(dtn_server_s *S, Batch *b)
+{
+    Slot &sl = S->slots[b->slot];
+    hipStream_t s = sl.stream;
+    const int64_t rows = b->rows;
+    {
+        int64_t at = 0;
+        for (const Query *q : b->qs) {
+            const int64_t m = (int64_t)q->patches.size();
+            std::memcpy(sl.h_patches + at, q->patches.data(), sizeof(dtn_patch) * m);
+            for (int64_t i = 0; i < m; ++i) {
+                sl.h_seed[at + i] = q->seed;
+                sl.h_sid0[at + i] = (uint32_t)(i * S->nn);
+                sl.h_se2[at + i] = q->se * q->se;
+            }
+            at += m;
+        }
+        // padding rows: a valid patch with an infinite SE target (budget =
+        // the pilot walks); their answers are never read
+        for (; at < rows; ++at) {
+            sl.h_patches[at] = sl.h_patches[0];
+            sl.h_seed[at] = 0;
+            sl.h_sid0[at] = 0;
+            sl.h_se2[at] = HUGE_VAL;
+        }
+    }
+    dtn_status st;
+    if (!S->cfg.graph_replay) {
+        st = record_pass(S, sl, rows, s);
+    } else {
+        hipGraphExec_t exec = nullptr;
+        st = slot_graph(S, sl, rows, &exec);
+        if (st == DTN_OK) {
+            const hipError_t e = hipGraphLaunch(exec, s);
+            if (e != hipSuccess) st = fail(DTN_E_DEVICE, std::string("server graph launch: ") + hipGetErrorString(e));
+        }
+    }
     if (st != DTN_OK) return st;
     Completion *c = new Completion{S, b};
-    e = hipLaunchHostFunc(s, on_done, c);
+    const hipError_t e = hipLaunchHostFunc(s, on_done, c);
     if (e != hipSuccess) {
         delete c;
         return fail(DTN_E_DEVICE, std::string("server: ") + hipGetErrorString(e));
@@ -290,6 +366,7 @@ dtn_status enqueue(dtn_server_s *S, Batch *b)
 void dispatch_loop(dtn_server_s *S)
 {
     (void)hipSetDevice(S->device);
+    (void)device_cus();  // device properties read here, outside any capture
     std::unique_lock<std::mutex> lk(S->mu);
     const int ns = (int)S->slots.size();
     auto fits = [&](int64_t points) { return S->in_use + footprint(S->cfg, points) <= S->cfg.hbm_budget; };
@@ -306,13 +383,16 @@ void dispatch_loop(dtn_server_s *S)
         while (!S->pending.empty()) {
             Query *q = S->pending.front();
             const int64_t m = (int64_t)q->patches.size();
-            if (!b->qs.empty() && (b->n + m > S->cfg.max_points || !fits(b->n + m))) break;
+            if (!b->qs.empty() && (b->n + m > S->cfg.max_points || !fits(b->n + m) ||
+                                   (S->cfg.max_batch_queries > 0 && (int64_t)b->qs.size() >= S->cfg.max_batch_queries)))
+                break;
             S->pending.pop_front();
             q->t_start = t;
             b->qs.push_back(q);
             b->n += m;
         }
         b->bytes = footprint(S->cfg, b->n);
+        b->rows = padded_rows(S->cfg, b->n);
         int slot = 0;
         while (S->slots[slot].busy) ++slot;
         S->slots[slot].busy = true;
@@ -421,6 +501,9 @@ dtn_status dtn_server_create(dtn_geometry g, const dtn_server_config *cfg, dtn_s
         *out = nullptr;
         std::string why;
         if (!valid_config(*cfg, why)) return fail(DTN_E_ARG, at + why);
+        if (cfg->graph_replay)
+            return fail(DTN_E_ARG, at + "graph replay is switched off (a serving run with it crashed the host "
+                                        "process; the cause is not yet shown)");
         Geometry *G = &g->g;
         if (G->dev.kind == DTN_BALL) return fail(DTN_E_ARG, at + "only box domains (with or without holes) are served");
         std::unique_ptr<dtn_server_s> S(new dtn_server_s());
@@ -445,6 +528,7 @@ dtn_status dtn_server_create(dtn_geometry g, const dtn_server_config *cfg, dtn_s
             (void)hipFree(S->d_node_off);
             (void)hipFree(S->d_panel_off);
             for (Slot &sl : S->slots) {
+                for (auto &kv : sl.graphs) (void)hipGraphExecDestroy(kv.second);
                 if (sl.stream) (void)hipStreamDestroy(sl.stream);
                 if (sl.h_patches) (void)hipHostFree(sl.h_patches);
                 if (sl.h_seed) (void)hipHostFree(sl.h_seed);
@@ -504,6 +588,7 @@ void dtn_server_destroy(dtn_server s)
     }
     for (Slot &sl : s->slots) {
         (void)hipStreamSynchronize(sl.stream);
+        for (auto &kv : sl.graphs) (void)hipGraphExecDestroy(kv.second);
         (void)hipStreamDestroy(sl.stream);
         (void)hipHostFree(sl.h_patches);
         (void)hipHostFree(sl.h_seed);

@@ -345,8 +345,6 @@ __global__ __launch_bounds__(256) void k_wos_finalize(DevGeom g, const double *_
 
 // ----------------------------------------------------------------- launch
 
-namespace {
-
 int device_cus()
 {
     static thread_local int cached_dev = -1, cached_cus = 0;
@@ -359,6 +357,8 @@ int device_cus()
     }
     return cached_cus > 0 ? cached_cus : 256;
 }
+
+namespace {
 
 template <int KIND, int DATA, int PREC>
 hipError_t run(const Geometry &g, const double *pts, int64_t n, const int64_t *walks, const int64_t *walk_begin,

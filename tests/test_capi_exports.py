@@ -59,7 +59,7 @@ def test_server_footprint_is_host_side_and_checked():
     invalid configuration."""
     from paper_1210_1491_amd import dtn
     L = dtn.lib()
-    cfg = dtn.ServerConfigDesc(4, 1, 2 << 30, 100, 100, 1_000_000, 0.25, 16, 8, 16, 4, 8, 4096)
+    cfg = dtn.ServerConfigDesc(4, 1, 2 << 30, 100, 100, 1_000_000, 0.25, 16, 8, 16, 4, 8, 4096, 0, 0)
     f = [L.dtn_server_footprint(ctypes.byref(cfg), n) for n in (1, 2, 100, 4096)]
     nodes = 8 * 16
     per_point = f[2] - f[1]
@@ -67,7 +67,31 @@ def test_server_footprint_is_host_side_and_checked():
     # the per-node arrays alone: nodes (24 B), stats (32), budgets and counts (8 + 8),
     # walk identities (8 + 4 + 8); panels: Neumann data and SE (2 x 8 x 32)
     assert per_point >= nodes * (24 + 32 + 16 + 20) + 32 * 16
-    bad = dtn.ServerConfigDesc(0, 1, 2 << 30, 100, 100, 1_000_000, 0.25, 16, 8, 16, 4, 8, 4096)
-    assert L.dtn_server_footprint(ctypes.byref(bad), 10) == -1
-    bad = dtn.ServerConfigDesc(4, 1, 2 << 30, 1, 100, 1_000_000, 0.25, 16, 8, 16, 4, 8, 4096)
-    assert L.dtn_server_footprint(ctypes.byref(bad), 10) == -1
+    for bad in (dtn.ServerConfigDesc(0, 1, 2 << 30, 100, 100, 1_000_000, 0.25, 16, 8, 16, 4, 8, 4096, 0, 0),
+                dtn.ServerConfigDesc(4, 1, 2 << 30, 1, 100, 1_000_000, 0.25, 16, 8, 16, 4, 8, 4096, 0, 0),
+                dtn.ServerConfigDesc(4, 1, 2 << 30, 100, 100, 1_000_000, 0.25, 16, 8, 16, 4, 8, 4096, 2, 0),
+                dtn.ServerConfigDesc(4, 1, 2 << 30, 100, 100, 1_000_000, 0.25, 16, 8, 16, 4, 8, 4096, 0, -1)):
+        assert L.dtn_server_footprint(ctypes.byref(bad), 10) == -1
+
+
+def _bucket(n, max_points):
+    """Size buckets of graph replay, stated independently: n itself up to 8,
+    then the smallest m 2^e >= n with m in 5..8, capped at max_points."""
+    if n <= 8:
+        return n
+    cands = [m << e for e in range(0, 21) for m in (5, 6, 7, 8) if (m << e) >= n]
+    return min(min(cands), max_points)
+
+
+@pytest.mark.parametrize("max_points", [4096, 4000])
+def test_server_footprint_under_graph_replay_is_that_of_the_padded_batch(max_points):
+    from paper_1210_1491_amd import dtn
+    L = dtn.lib()
+    direct = dtn.ServerConfigDesc(4, 1, 2 << 30, 100, 100, 1_000_000, 0.25, 16, 8, 16, 4, 8, max_points, 0, 0)
+    graph = dtn.ServerConfigDesc(4, 1, 2 << 30, 100, 100, 1_000_000, 0.25, 16, 8, 16, 4, 8, max_points, 1, 0)
+    sizes = list(range(1, 70)) + [99, 100, 101, 129, 1000, 3000, 3999, 4000]
+    for n in sizes:
+        b = _bucket(n, max_points)
+        assert n <= b <= max(n, min(max_points, int(n * 1.25) + 1))
+        got = L.dtn_server_footprint(ctypes.byref(graph), n)
+        assert got == L.dtn_server_footprint(ctypes.byref(direct), b), (n, b)

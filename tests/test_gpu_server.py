@@ -178,3 +178,68 @@ def test_server_rejects_bad_queries():
         dtn.Server(g, n_streams=0)
     with pytest.raises(dtn.DtnError):
         dtn.Server(dtn.Geometry(I.geometry_ball_quadratic()))
+
+
+def test_one_query_per_batch_matches_batching_across_requests():
+    """The per-query mode (one query per batch, one stream) gives the walks
+    and answers of batching across requests, and runs the queries one after
+    another."""
+    dtn = _dtn()
+    gd = I.geometry_box_holes()
+    rng = np.random.default_rng(25)
+    qs = {}
+    for qid, m in zip(range(30, 35), (9, 10, 3, 17, 10)):
+        p, n = I.boundary_points(gd, m, rng)
+        qs[qid] = (p, n, 0.05, 500 + qid)
+    g = dtn.Geometry(gd)
+    kw = dict(precision="fp32", pilot_walks=64, min_walks=64, max_walks=3000, layout=LAYOUT)
+    res = {}
+    for name, extra in (("per_query", dict(n_streams=1, max_batch_queries=1)), ("batched", dict(n_streams=2))):
+        S = dtn.Server(g, **kw, **extra)
+        print(f"[gpu] server {name}", flush=True)
+        res[name] = _run(S, qs)
+        S.close()
+    for qid in qs:
+        a, b = res["per_query"][qid]["answer"], res["batched"][qid]["answer"]
+        np.testing.assert_array_equal(b[:, 2:], a[:, 2:])  # walks and h
+        np.testing.assert_allclose(b[:, :2], a[:, :2], rtol=1e-11, atol=1e-14)
+    per = sorted(res["per_query"].values(), key=lambda d: d["t_start"])
+    for prev, nxt in zip(per, per[1:]):
+        assert nxt["t_start"] >= prev["t_done"]
+
+
+def test_graph_replay_is_rejected_while_switched_off():
+    dtn = _dtn()
+    g = dtn.Geometry(I.geometry_box_holes())
+    with pytest.raises(dtn.DtnError, match="graph replay"):
+        dtn.Server(g, graphs=True, layout=LAYOUT)
+
+
+@pytest.mark.skip(reason="server graph replay is switched off: a four-stream serving run with it ended in a host "
+                         "segmentation fault whose cause is not yet shown; the server rejects the mode")
+def test_graph_replay_matches_direct_launches():
+    """Batches replayed from captured graphs (padded to their size bucket)
+    give the direct launches' walks and answers; a bucket's graph replayed
+    for a later batch reads that batch's own staging."""
+    dtn = _dtn()
+    gd = I.geometry_box_holes()
+    rng = np.random.default_rng(25)
+    qs = {}
+    # 9 and 10 share the 10-row bucket (captured once, replayed for the
+    # later one); 17 pads to 20; 3 is unpadded
+    for qid, m in zip(range(30, 35), (9, 10, 3, 17, 10)):
+        p, n = I.boundary_points(gd, m, rng)
+        qs[qid] = (p, n, 0.05, 500 + qid)
+    g = dtn.Geometry(gd)
+    kw = dict(precision="fp32", pilot_walks=64, min_walks=64, max_walks=3000, layout=LAYOUT)
+    res = {}
+    for name, extra in (("direct", dict(graphs=False, n_streams=1, max_batch_queries=1)),
+                        ("graph", dict(graphs=True, n_streams=1, max_batch_queries=1))):
+        S = dtn.Server(g, **kw, **extra)
+        print(f"[gpu] server {name}", flush=True)
+        res[name] = _run(S, qs)
+        S.close()
+    for qid in qs:
+        a, b = res["direct"][qid]["answer"], res["graph"][qid]["answer"]
+        np.testing.assert_array_equal(b[:, 2:], a[:, 2:])  # walks and h
+        np.testing.assert_allclose(b[:, :2], a[:, :2], rtol=1e-11, atol=1e-14)

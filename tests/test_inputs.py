@@ -37,5 +37,9 @@ def test_serving_queries_arrivals_and_sizes():
     # log-uniform sizes: log(m+1) roughly uniform on [0, log 65]
     assert abs(np.mean(np.log(m + 0.5)) / np.log(65) - 0.5) < 0.08
     assert len({q["seed"] for q in qs}) == len(qs)
+    # required standard errors log-uniform on [1e-4, 1e-2]
+    se = np.log10([q["se"] for q in qs])
+    assert se.min() >= -4 and se.max() <= -2
+    assert abs(se.mean() + 3) < 4 * (2 / np.sqrt(12)) / np.sqrt(len(se))
     again = I.serving_queries(gd, n_queries=400, rate=200.0, seed=5, max_points=64)
     assert all(np.array_equal(a["pts"], b["pts"]) for a, b in zip(qs, again))
