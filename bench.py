@@ -301,26 +301,61 @@ def serving(precision, window, rate, se_range, sweep_fraction=0.5, sweep_window=
             "stable": stable, "low": low}
 
 
-def cpu_baseline(gd, pd_all, walks_per_node):
+def cpu_baseline(gd, pd_all, walks_per_node, g, full_walks):
     """The oracle on a bounded sample: the 16-tile subset of the cube tiling
-    (face centres, edges, corners, 4 seeded tiles), walks_per_node each."""
+    (face centres, edges, corners, 4 seeded tiles), walks_per_node each.
+    The FP64 GPU path then runs the identical sample (its own nodes, the
+    same seed and stream ids) for a like-for-like rate and per-node parity:
+    z = |mean_gpu - mean_oracle| / sqrt(se_gpu^2 + se_oracle^2)."""
+    import torch
+
     import dtn_inputs as I
     from oracle import patch as OP
     from oracle import wos as OW
+    from paper_1210_1491_amd import dtn
 
     sub = I.cube_tile_subset()
     pd = I.subset_patches(pd_all, sub)
     ps = OP.patches_from_desc(pd, gd)
     nodes = np.concatenate([OP.nodes_global(p)[0] for p in ps])
-    g = OW.Geometry(gd)
+    og = OW.Geometry(gd)
     t0 = time.perf_counter()
-    r = OW.wos_nodes(g, nodes, walks_per_node, seed=2)
+    r = OW.wos_nodes(og, nodes, walks_per_node, seed=2)
     dt = time.perf_counter() - t0
     walks = float(r["count"].sum())
-    return {"value": walks / dt, "unit": "walks/s", "cores": OW.max_threads(), "kind": "oracle",
+    cores = OW.max_threads()
+    # the GPU on the same sample
+    plan = dtn.Plan(g, pd)
+    nd = plan.nodes()
+    n = plan.num_nodes
+    w = torch.full((n,), walks_per_node, dtype=torch.int64, device=nd.device)
+    st = torch.empty((n, 4), dtype=torch.float64, device=nd.device)
+    dtn.wos_eval(g, nd, w, seed=2, precision="fp64", stats=st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dtn.wos_eval(g, nd, w, seed=2, precision="fp64", stats=st)
+    torch.cuda.synchronize()
+    dt_gpu = time.perf_counter() - t1
+    sg = st.cpu().numpy()
+    se_g = np.sqrt(sg[:, 2] / (sg[:, 0] - 1) / sg[:, 0])
+    se = np.sqrt(se_g ** 2 + r["se"] ** 2)
+    diff = np.abs(sg[:, 1] - r["mean"])
+    # nodes that start inside the shell: every walk ends at once, no spread on
+    # either side; the means differ only by the rounding of the data there
+    flat = se == 0
+    z = diff[~flat] / se[~flat]
+    rel_flat = diff[flat] / np.maximum(np.abs(r["mean"][flat]), 1e-300)
+    return {"value": walks / dt, "unit": "walks/s", "cores": cores, "kind": "oracle",
             "sample": f"{len(sub)} tiles x {nodes.shape[0] // len(sub)} nodes x {walks_per_node} walks "
                       f"({int(walks)} walks, {int(r['steps'].sum())} steps) in {dt:.1f} s",
-            "steps_per_s": float(r["steps"].sum()) / dt}
+            "steps_per_s": float(r["steps"].sum()) / dt, "walks_per_s_per_core": walks / dt / cores,
+            "extrapolated_full_workload_s": full_walks / (walks / dt),
+            "gpu_same_sample": {"walks_per_s": walks / dt_gpu, "seconds": dt_gpu,
+                                "ratio_gpu_over_oracle": dt / dt_gpu, "parity_max_z": float(z.max()),
+                                "nodes_over_4_sigma": int((z > 4).sum()),
+                                "nodes_in_shell": int(flat.sum()),
+                                "in_shell_max_rel_diff": float(rel_flat.max()) if flat.any() else 0.0,
+                                "identical_node_means": int((sg[:, 1] == r["mean"]).sum()), "nodes": int(n)}}
 
 
 def main():
@@ -400,7 +435,14 @@ def main():
         wos_s = float(np.mean(wos_ms)) / 1e3
         slots = SLOTS_PER_STEP[precision] * steps_n + SLOTS_PER_WALK * walks_n
         sig = neumann.cpu().numpy()
-        return {"ms_per_step": ms, "walks_per_s": walks_n / (ms / 1e3), "patches_per_s": len(ps) / (ms / 1e3),
+        # the other solve precision on the same node statistics (walks x solve matrix)
+        other = "fp32" if precision == "fp64" else "fp64"
+        n2, s2 = torch.empty_like(neumann), torch.empty_like(neumann_se)
+        plan.solve(stats, precision=other, neumann=n2, neumann_se=s2)
+        sig2 = n2.cpu().numpy()
+        solves = {precision: OP.rel_l2(sig, ex, area, trusted), other: OP.rel_l2(sig2, ex, area, trusted),
+                  "max_abs_diff_fp32_vs_fp64_solve": float(np.max(np.abs(sig2 - sig)))}
+        return {"ms_per_step": ms, "rel_l2_by_solve_precision": solves, "walks_per_s": walks_n / (ms / 1e3), "patches_per_s": len(ps) / (ms / 1e3),
                 "neumann_rel_l2_vs_exact": OP.rel_l2(sig, ex, area, trusted),
                 "neumann_se_median": float(np.median(neumann_se.cpu().numpy())),
                 "potential_max_err_far": float(np.max(np.abs(u.cpu().numpy()[far] - u_ex[far]))
@@ -426,8 +468,25 @@ def main():
         other = "fp32" if args.precision == "fp64" else "fp64"
         v = measure(other, 1, 0)
         variants[other] = {k: v[k] for k in ("walks_per_s", "patches_per_s", "neumann_rel_l2_vs_exact",
-                                              "neumann_se_median", "steps_per_walk", "wos_kernel_ms")}
+                                              "neumann_se_median", "steps_per_walk", "wos_kernel_ms",
+                                              "rel_l2_by_solve_precision")}
         variants[other]["alu_frac"] = v["alu_achieved"] / ALU_PEAK
+    curve = None
+    if not args.no_variants:
+        # Neumann error against the walk budget, both walk precisions (each
+        # with its own solve); the last point is the timed run's
+        full = {args.precision: m["neumann_rel_l2_vs_exact"], other: v["neumann_rel_l2_vs_exact"]}
+        budgets = [b for b in (1000, 10000) if b < args.walks] + [args.walks]
+        curve = {"walks_per_node": budgets, "fp64": [], "fp32": []}
+        for prec in ("fp64", "fp32"):
+            for b in budgets[:-1]:
+                walks.fill_(b)
+                plan.nodes(out=nodes)
+                dtn.wos_eval(g, nodes, walks, seed=2, precision=prec, stats=stats, capped=capped)
+                plan.solve(stats, precision=prec, neumann=neumann, neumann_se=neumann_se)
+                curve[prec].append(OP.rel_l2(neumann.cpu().numpy(), ex, area, trusted))
+            curve[prec].append(full[prec])
+        walks.fill_(args.walks)
     ms_per_step = m["ms_per_step"]
     achieved = m["alu_achieved"]
     value = m["walks_per_s"]
@@ -449,6 +508,7 @@ def main():
                    "patches": len(ps), "nodes": N, "walks_per_node": args.walks, "precision": args.precision},
         "patches_per_s": m["patches_per_s"],
         "neumann_rel_l2_vs_exact": m["neumann_rel_l2_vs_exact"],
+        "rel_l2_by_solve_precision": m["rel_l2_by_solve_precision"],
         "neumann_se_median": m["neumann_se_median"],
         "potential_max_err_far": m["potential_max_err_far"],
         "steps_per_walk": m["steps_per_walk"],
@@ -460,6 +520,7 @@ def main():
                      "traffic": traffic_if_current() if args.walks == 100_000 and args.tiles == 16 else None,
                      "slots_per_step": SLOTS_PER_STEP[args.precision], "slots_per_walk": SLOTS_PER_WALK},
         "variants": variants,
+        "error_vs_walks": curve,
     }
     if args.only is None and not args.no_box_holes:
         line["box_holes"] = box_holes("fp32", 1, not args.no_cpu_baseline)
@@ -468,7 +529,7 @@ def main():
         line["p50_latency_ms"] = line["serving"]["served"]["p50_ms"]
         line["p99_latency_ms"] = line["serving"]["served"]["p99_ms"]
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(gd, pd, args.cpu_walks)
+        line["cpu_baseline"] = cpu_baseline(gd, pd, args.cpu_walks, g, float(N) * args.walks)
     print(json.dumps(line), flush=True)
 
 

@@ -65,14 +65,32 @@ __device__ __forceinline__ float u01_f32(uint32_t k) { return fmaf((float)(k >> 
 // (sin, cos)(2 pi j / 256); sin x and cos x come from their Taylor series to
 // x^7 and x^6 (first omitted terms below 2e-20 relative); the angle-addition
 // formulas combine them.
+// a * b + c as one three-address FMA: a and c in vector registers, b in a
+// scalar register (fma_vsv), or a and b in vector registers and c in a scalar
+// register (fma_vvs).  With a constant addend the compiler otherwise picks
+// the two-address form and copies the addend into the destination at every
+// use.  Same rounding as fma().
+__device__ __forceinline__ double fma_vsv(double a, double b, double c)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
+__device__ __forceinline__ double fma_vvs(double a, double b, double c)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
+
 __device__ __forceinline__ void sincos_2pi_word(uint32_t k, double tsin, double tcos, double &s, double &c)
 {
     const uint32_t kk = k + 0x800000u;
     const int32_t r = (int32_t)(kk & 0xFFFFFFu) - 0x800000;
-    const double x = fma((double)r, 0x1.921fb54442d18p-30, 0x1.921fb54442d18p-31);
+    const double x = fma_vsv((double)r, 0x1.921fb54442d18p-30, 0x1.921fb54442d18p-31);
     const double x2 = x * x;
-    const double sx = fma(x * x2, fma(x2, fma(x2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), x);
-    const double cx = fma(x2, fma(x2, fma(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+    const double sx = fma(x * x2, fma_vvs(x2, fma_vsv(x2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), x);
+    const double cx = fma(x2, fma(x2, fma_vsv(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
     s = fma(tsin, cx, tcos * sx);
     c = fma(tcos, cx, -(tsin * sx));
 }
@@ -115,25 +133,46 @@ extern "C" __device__ uint32_t __ockl_wfred_or_u32(uint32_t);
 
 // Candidate holes of the grid cell holding (x, y, z): bit i set when hole i
 // can be the nearest surface for some point of the (slightly expanded) cell.
-__device__ __forceinline__ uint32_t cell_candidates(const DevGeom &g, float x, float y, float z)
+__device__ __forceinline__ float fmaf_vsv(float a, float b, float c)
 {
-    // cell coordinate (x - lo) / width as one FMA, clamped to [0, n - 1/2]
-    // before truncation (v_med3_f32), linear index in 24-bit multiplies
-    const float fx = __builtin_amdgcn_fmed3f(fmaf(x, g.cell_inv[0], g.cell_off[0]), 0.0f, g.cell_top[0]);
-    const float fy = __builtin_amdgcn_fmed3f(fmaf(y, g.cell_inv[1], g.cell_off[1]), 0.0f, g.cell_top[1]);
-    const float fz = __builtin_amdgcn_fmed3f(fmaf(z, g.cell_inv[2], g.cell_off[2]), 0.0f, g.cell_top[2]);
+    float r;
+    asm("v_fma_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
+
+// The grid's cell offsets held in vector registers for a whole kernel (the
+// empty asm makes each a per-lane value, so the compiler keeps it there
+// instead of copying it from a scalar register at every lookup).
+struct CellOff {
+    float o[3];
+};
+__device__ __forceinline__ CellOff cell_offsets(const DevGeom &g)
+{
+    CellOff c;
+    for (int k = 0; k < 3; ++k) {
+        c.o[k] = g.cell_off[k];
+        asm volatile("" : "+v"(c.o[k]));
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint32_t cell_candidates(const DevGeom &g, const CellOff &co, float x, float y, float z)
+{
+    // cell coordinate (x - lo) / width as one FMA (three-address, the offset
+    // read in place from a vector register), clamped to [0, n - 1/2] before
+    // truncation (v_med3_f32), linear index in 24-bit multiplies
+    const float fx = __builtin_amdgcn_fmed3f(fmaf_vsv(x, g.cell_inv[0], co.o[0]), 0.0f, g.cell_top[0]);
+    const float fy = __builtin_amdgcn_fmed3f(fmaf_vsv(y, g.cell_inv[1], co.o[1]), 0.0f, g.cell_top[1]);
+    const float fz = __builtin_amdgcn_fmed3f(fmaf_vsv(z, g.cell_inv[2], co.o[2]), 0.0f, g.cell_top[2]);
     const uint32_t idx = __umul24((uint32_t)fx, (uint32_t)g.cell_stride[0]) +
                          __umul24((uint32_t)fy, (uint32_t)g.cell_stride[1]) + (uint32_t)fz;
     return g.cell_mask[idx];
 }
-
-// Holes the distance query must visit for the lanes with `take` set: the
-// union of their cells' candidate lists (wave-uniform).  Call with the whole
-// wave active.  Without a grid every hole is visited.
-__device__ __forceinline__ uint32_t hole_candidates(const DevGeom &g, bool take, float x, float y, float z)
+__device__ __forceinline__ uint32_t hole_candidates(const DevGeom &g, const CellOff &co, bool take, float x, float y,
+                                                    float z)
 {
     if (!g.cell_mask) return 0xffffffffu;
-    const uint32_t mine = take ? cell_candidates(g, x, y, z) : 0u;
+    const uint32_t mine = take ? cell_candidates(g, co, x, y, z) : 0u;
     return __ockl_wfred_or_u32(mine);
 }
 
@@ -348,6 +387,10 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 // Rank of this lane among the lanes set in `mask` below it.
+// Is this lane's bit set in a wave-uniform mask (the mask becomes the
+// execution mask directly; no vector instruction)?
+__device__ __forceinline__ bool lane_in(uint64_t mask) { return __builtin_amdgcn_inverse_ballot_w64(mask); }
+
 __device__ __forceinline__ int rank_below(uint64_t mask)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));

@@ -149,8 +149,11 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
         project_f64<KIND>(g, sx, sy, sz, all_holes(g));
         const double shift = phi_eval<DATA>(g, sx, sy, sz);
 
-        // lane state
-        bool walking = false;
+        const CellOff co = KIND == DTN_BOX_MINUS_BOXES ? cell_offsets(g) : CellOff{};
+        // lane state; which lanes hold a walk is the wave-uniform mask
+        // `wmask` (scalar registers): lane predicates come from it with no
+        // vector instruction, and ballots of compares fold into it
+        uint64_t wmask = 0;
         uint64_t walk = 0;
         double x = y0, y = y1, z = y2;
         uint32_t nstep = 0;
@@ -159,6 +162,8 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
         unsigned long long steps = 0, capped = 0;
         int64_t next = w_lo;  // wave-uniform: next walk to hand out
         int qn = 0;           // wave-uniform: queued exit points
+        // step cap as a 32-bit bound (a walk's step count is 32-bit)
+        const uint32_t cap = (uint32_t)min(g.max_steps, (int64_t)0xffffffff);
         // Hard bound on wave iterations: every walk ends within max_steps + 2
         // iterations of its start and a lane runs at most ceil(C/64) walks.
         const uint64_t it_max = ((uint64_t)g.max_steps + 4u) * 2u * (uint64_t)((w_hi - w_lo + kWave - 1) / kWave + 1);
@@ -166,20 +171,22 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
         for (uint64_t it = 0; it < it_max; ++it) {
             uint32_t w1, w2;  // this step's two random words
             if ((it & 1ull) == 0ull) {
-                const uint64_t want = __ballot(!walking);
+                const uint64_t want = ~wmask;
                 if (want) {
                     const int64_t mine = next + rank_below(want);
-                    if (!walking && mine < w_hi) {
-                        walking = true;
+                    // ballot of the plain compare, masked in scalar registers
+                    const uint64_t sm = want & __builtin_amdgcn_ballot_w64(mine < w_hi);
+                    if (lane_in(sm)) {
                         walk = (uint64_t)(wb + mine);
                         x = y0;
                         y = y1;
                         z = y2;
                         nstep = 0;
                     }
+                    wmask |= sm;
                     next += __popcll(want);
                 }
-                if (!__any(walking)) break;
+                if (wmask == 0) break;
                 const Philox4 r = philox4x32_10((uint32_t)walk, (uint32_t)(walk >> 32), nstep >> 1, sid, k0, k1);
                 w1 = r.x;
                 w2 = r.y;
@@ -189,66 +196,65 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                 w1 = r2;
                 w2 = r3;
             }
+            const bool walking = lane_in(wmask);
             // candidate holes of the walking lanes' cells (whole wave active here)
             uint32_t cand = 0;
             if constexpr (KIND == DTN_BOX_MINUS_BOXES)
-                cand = hole_candidates(g, walking, (float)x, (float)y, (float)z);
-            bool fin = false;
-            if (walking) {
-                // distance and epsilon test in FP64 on both paths (an FP32
-                // distance would need an FP64 recheck inside a rounding band
-                // around the shell, which some lane of a wave needs at almost
-                // every step, and a shrunken jump everywhere)
-                const double d = dist_f64<KIND, PREC != DTN_FP64>(g, x, y, z, cand);
-                if (d < eps || (int64_t)nstep >= g.max_steps) {
-                    fin = true;
-                    capped += (d >= eps) ? 1ull : 0ull;
+                cand = hole_candidates(g, co, walking, (float)x, (float)y, (float)z);
+            // distance and epsilon test in FP64 on both paths (an FP32
+            // distance would need an FP64 recheck inside a rounding band
+            // around the shell, which some lane of a wave needs at almost
+            // every step, and a shrunken jump everywhere).  Every lane
+            // computes it (an idle lane's point is its last one, inside the
+            // domain); only the walking lanes' results are used.
+            const double d = dist_f64<KIND, PREC != DTN_FP64>(g, x, y, z, cand);
+            const uint64_t fm =
+                wmask & (__builtin_amdgcn_ballot_w64(d < eps) | __builtin_amdgcn_ballot_w64(nstep >= cap));
+            if (lane_in(wmask & ~fm)) {
+                if constexpr (PREC == DTN_FP64) {
+                    const double u1d = u01_f64(w1);
+                    const double cz = 1.0 - 2.0 * u1d;
+                    const double sr = 2.0 * sqrt_f64(u1d * (1.0 - u1d));
+                    const uint32_t j = sincos_index(w2);
+                    double sn, cs;
+                    sincos_2pi_word(w2, sc_tab[j][0], sc_tab[j][1], sn, cs);
+                    x += d * (sr * cs);
+                    y += d * (sr * sn);
+                    z += d * cz;
                 } else {
-                    if constexpr (PREC == DTN_FP64) {
-                        const double u1d = u01_f64(w1);
-                        const double cz = 1.0 - 2.0 * u1d;
-                        const double sr = 2.0 * sqrt_f64(u1d * (1.0 - u1d));
-                        const uint32_t j = sincos_index(w2);
-                        double sn, cs;
-                        sincos_2pi_word(w2, sc_tab[j][0], sc_tab[j][1], sn, cs);
-                        x += d * (sr * cs);
-                        y += d * (sr * sn);
-                        z += d * cz;
-                    } else {
-                        // FP32 direction: uniforms, square root and the
-                        // hardware sin/cos (revolution input); |omega| = 1
-                        // within three FP32 roundings, so the jump is
-                        // shortened by 2^-22 to stay inside the ball
-                        const float u1f = u01_f32(w1), u2f = u01_f32(w2);
-                        const float cz = 1.0f - 2.0f * u1f;
-                        const float sr = 2.0f * __builtin_amdgcn_sqrtf(u1f * (1.0f - u1f));
-                        const float cs = __builtin_amdgcn_cosf(u2f);  // cos(2 pi u2)
-                        const float sn = __builtin_amdgcn_sinf(u2f);  // sin(2 pi u2)
-                        const double dj = d * (1.0 - 0x1p-22);
-                        x += dj * (double)(sr * cs);
-                        y += dj * (double)(sr * sn);
-                        z += dj * (double)cz;
-                    }
-                    ++nstep;
+                    // FP32 direction: uniforms, square root and the
+                    // hardware sin/cos (revolution input); |omega| = 1
+                    // within three FP32 roundings, so the jump is
+                    // shortened by 2^-22 to stay inside the ball
+                    const float u1f = u01_f32(w1), u2f = u01_f32(w2);
+                    const float cz = 1.0f - 2.0f * u1f;
+                    const float sr = 2.0f * __builtin_amdgcn_sqrtf(u1f * (1.0f - u1f));
+                    const float cs = __builtin_amdgcn_cosf(u2f);  // cos(2 pi u2)
+                    const float sn = __builtin_amdgcn_sinf(u2f);  // sin(2 pi u2)
+                    const double dj = d * (1.0 - 0x1p-22);
+                    x += dj * (double)(sr * cs);
+                    y += dj * (double)(sr * sn);
+                    z += dj * (double)cz;
                 }
+                ++nstep;
             }
-            const uint64_t fm = __ballot(fin);
             if (fm) {
-                if (fin) {
+                if (lane_in(fm)) {
                     const int slot = qn + rank_below(fm);
                     q[3 * slot] = x;
                     q[3 * slot + 1] = y;
                     q[3 * slot + 2] = z;
                     steps += nstep;
-                    walking = false;
+                    capped += (d >= eps) ? 1ull : 0ull;
                 }
+                wmask &= ~fm;
                 qn += __popcll(fm);
                 if (qn >= kWave) {
                     wave_sync();
                     double px = q[3 * lane], py = q[3 * lane + 1], pz = q[3 * lane + 2];
                     uint32_t pc = 0;  // candidate holes of the 64 queued points (whole wave active)
                     if constexpr (KIND == DTN_BOX_MINUS_BOXES)
-                        pc = hole_candidates(g, true, (float)px, (float)py, (float)pz);
+                        pc = hole_candidates(g, co, true, (float)px, (float)py, (float)pz);
                     project_f64<KIND>(g, px, py, pz, pc);
                     const double v = phi_eval<DATA>(g, px, py, pz) - shift;
                     kadd(s1, v);
@@ -278,7 +284,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
             double px = has ? q[3 * lane] : 0.0, py = has ? q[3 * lane + 1] : 0.0, pz = has ? q[3 * lane + 2] : 0.0;
             uint32_t pc = 0;
             if constexpr (KIND == DTN_BOX_MINUS_BOXES)
-                pc = hole_candidates(g, has, (float)px, (float)py, (float)pz);
+                pc = hole_candidates(g, co, has, (float)px, (float)py, (float)pz);
             if (has) {
                 project_f64<KIND>(g, px, py, pz, pc);
                 const double v = phi_eval<DATA>(g, px, py, pz) - shift;
@@ -436,7 +442,7 @@ __global__ __launch_bounds__(256) void k_distance(DevGeom g, const double *__res
     const bool live = i < n;
     const double x = live ? pts[3 * i] : 0.0, y = live ? pts[3 * i + 1] : 0.0, z = live ? pts[3 * i + 2] : 0.0;
     uint32_t cand = 0;
-    if constexpr (KIND == DTN_BOX_MINUS_BOXES) cand = hole_candidates(g, live, (float)x, (float)y, (float)z);
+    if constexpr (KIND == DTN_BOX_MINUS_BOXES) cand = hole_candidates(g, cell_offsets(g), live, (float)x, (float)y, (float)z);
     if (!live) return;
     out[i] = dist_f64<KIND, FAST>(g, x, y, z, cand);
 }
