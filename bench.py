@@ -75,10 +75,10 @@ SLOTS_PER_WALK = slots(WALK_OPS)
 # the kernel sources it was measured on (SHA-256 of these files).
 TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_amd/csrc/dtn_device.h",
                      "paper_1210_1491_amd/csrc/dtn_internal.h"],
-           "sha256": ["8e1e5d9e1b6103edcb4a30dd468bac7434c4be7af0849932f088e3589cf35757",
-                      "40b228f48b5dd299308485a89c904d2d70c5a1b9a848fd6f1c826d1a1e855ae1",
+           "sha256": ["5c5b790c488bd917c72b8f627b3122c61c5e3ed02d15afff442832bcf68dd4d9",
+                      "474f2e5d94bdf822d887f169aed51598f260bd316d958cc8f1c12a7938e84a86",
                       "0eb5bfa94f8b9bc0c04b0ca22c7c7b33abc91770a9c5511a852c88858976a8fa"],
-           "fetch_bytes": 71760.6 * 1024 * 2.00, "write_bytes": 43008.0 * 1024 * 1.00}
+           "fetch_bytes": 71761.2 * 1024 * (262144 / 131090.0), "write_bytes": 43008.0 * 1024 * 1.00}
 
 
 def traffic_if_current():
