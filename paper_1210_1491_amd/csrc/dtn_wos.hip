@@ -159,7 +159,10 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
         uint32_t nstep = 0;
         uint32_t r2 = 0, r3 = 0;
         KSum s1{0.0, 0.0}, s2{0.0, 0.0};
-        unsigned long long steps = 0, capped = 0;
+        // jumps and capped walks of the chunk, counted from the masks
+        // (wave-uniform): a lane jumps when it walks and does not stop, a
+        // stopping lane is capped when it is not inside the shell
+        uint64_t steps = 0, capped = 0;
         int64_t next = w_lo;  // wave-uniform: next walk to hand out
         int qn = 0;           // wave-uniform: queued exit points
         // step cap as a 32-bit bound (a walk's step count is 32-bit)
@@ -173,8 +176,10 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
             if ((it & 1ull) == 0ull) {
                 const uint64_t want = ~wmask;
                 if (want) {
+                    // the idle lanes take the next walks in lane order while
+                    // any are left (ballot of the plain compare, masked in
+                    // scalar registers)
                     const int64_t mine = next + rank_below(want);
-                    // ballot of the plain compare, masked in scalar registers
                     const uint64_t sm = want & __builtin_amdgcn_ballot_w64(mine < w_hi);
                     if (lane_in(sm)) {
                         walk = (uint64_t)(wb + mine);
@@ -208,8 +213,10 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
             // computes it (an idle lane's point is its last one, inside the
             // domain); only the walking lanes' results are used.
             const double d = dist_f64<KIND, PREC != DTN_FP64>(g, x, y, z, cand);
-            const uint64_t fm =
-                wmask & (__builtin_amdgcn_ballot_w64(d < eps) | __builtin_amdgcn_ballot_w64(nstep >= cap));
+            const uint64_t in_shell = __builtin_amdgcn_ballot_w64(d < eps);
+            const uint64_t fm = wmask & (in_shell | __builtin_amdgcn_ballot_w64(nstep >= cap));
+            steps += (uint64_t)__popcll(wmask & ~fm);
+            capped += (uint64_t)__popcll(fm & ~in_shell);
             if (lane_in(wmask & ~fm)) {
                 if constexpr (PREC == DTN_FP64) {
                     const double u1d = u01_f64(w1);
@@ -244,8 +251,6 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                     q[3 * slot] = x;
                     q[3 * slot + 1] = y;
                     q[3 * slot + 2] = z;
-                    steps += nstep;
-                    capped += (d >= eps) ? 1ull : 0ull;
                 }
                 wmask &= ~fm;
                 qn += __popcll(fm);
@@ -295,8 +300,8 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
         wave_sync();
         const KSum t1 = wave_ksum(s1);
         const KSum t2 = wave_ksum(s2);
-        const unsigned long long ts = wave_sum_u64(steps);
-        const unsigned long long tc = wave_sum_u64(capped);
+        const unsigned long long ts = steps;
+        const unsigned long long tc = capped;
         if (lane == 0) {
             ChunkPartial p;
             p.s1 = t1.s;
