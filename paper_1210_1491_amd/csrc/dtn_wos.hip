@@ -247,10 +247,11 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
             }
             if (fm) {
                 if (lane_in(fm)) {
-                    const int slot = qn + rank_below(fm);
-                    q[3 * slot] = x;
-                    q[3 * slot + 1] = y;
-                    q[3 * slot + 2] = z;
+                    // 32-bit LDS address: lane rank x 24 B onto a scalar base
+                    lds_double *e = lds_slot(q, (uint32_t)qn, (uint32_t)rank_below(fm));
+                    e[0] = x;
+                    e[1] = y;
+                    e[2] = z;
                 }
                 wmask &= ~fm;
                 qn += __popcll(fm);
