@@ -44,11 +44,12 @@ SLOT_COST = {
 # definition requires, not from what the compiler emits.
 STEP_OPS = {
     # distance (11), eps test (1), u1 = ldexp(k + 1/2, -32) (2), u(1-u) (2), x2 (1),
-    # sin/cos: x^2, x^3 and the two products of the angle addition (4), s cos / s sin (2)
-    "fp64": {"f64": 23,
-             # z (1), square root refinement and residual (6), sin/cos: remainder scaling (1),
-             # Taylor series (6), angle addition (2); jump (3)
-             "f64fma": 19,
+    # square root: -x/2, and three more products (4), sin/cos: x^2, x^3 and the two
+    # products of the angle addition (4), s cos / s sin (2)
+    "fp64": {"f64": 27,
+             # z (1), square root: one Newton step and the residual correction (4),
+             # sin/cos: remainder scaling (1), Taylor series (6), angle addition (2); jump (3)
+             "f64fma": 17,
              # cap test, Philox xors (half block: 10), counter word, table index and
              # remainder bits (3), step counter
              "i32": 16, "mad64": 10, "cvt": 2, "rsq64": 1},
@@ -75,10 +76,10 @@ SLOTS_PER_WALK = slots(WALK_OPS)
 # the kernel sources it was measured on (SHA-256 of these files).
 TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_amd/csrc/dtn_device.h",
                      "paper_1210_1491_amd/csrc/dtn_internal.h"],
-           "sha256": ["5c5b790c488bd917c72b8f627b3122c61c5e3ed02d15afff442832bcf68dd4d9",
-                      "474f2e5d94bdf822d887f169aed51598f260bd316d958cc8f1c12a7938e84a86",
+           "sha256": ["78b66e4b0a60d581f0082d4d15a7a88633981b5e44ac82b892ff8665f3ed104f",
+                      "9d7f8603a187c1d1865c1be11c6644ba692350c88a379e465a92dd7a8bb6839b",
                       "0eb5bfa94f8b9bc0c04b0ca22c7c7b33abc91770a9c5511a852c88858976a8fa"],
-           "fetch_bytes": 71761.2 * 1024 * (262144 / 131090.0), "write_bytes": 43008.0 * 1024 * 1.00}
+           "fetch_bytes": 71757.25 * 1024 * (262144 / 131089.625), "write_bytes": 43008.0 * 1024 * 1.00}
 
 
 def traffic_if_current():
