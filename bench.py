@@ -107,10 +107,11 @@ def parse():
                     help="run a plain device copy of this size first (reference for HBM counters)")
     ap.add_argument("--no-box-holes", action="store_true", help="skip the uneven-batching workload")
     ap.add_argument("--no-serving", action="store_true", help="skip the query-serving workload")
-    ap.add_argument("--serving-window", type=int, default=30, help="arrivals in the serving window")
-    ap.add_argument("--serving-se-range", type=float, nargs=2, default=[1e-3, 1e-1],
-                    help="range of the per-query required node standard error (log-uniform); the workload's "
-                         "own range is 1e-4 1e-2")
+    ap.add_argument("--serving-window", type=int, default=12, help="arrivals in the serving window")
+    ap.add_argument("--serving-sweep-window", type=int, default=6,
+                    help="arrivals of the half-capacity run (half as many at a quarter); 0 skips both")
+    ap.add_argument("--serving-se-range", type=float, nargs=2, default=[1e-4, 1e-2],
+                    help="range of the per-query required node standard error (log-uniform)")
     ap.add_argument("--serving-rate", type=float, default=200.0, help="offered load, queries/s")
     ap.add_argument("--only", choices=["cube", "box_holes", "serving"], default=None,
                     help="run one workload only (for profiling)")
@@ -153,14 +154,18 @@ def calibrate():
     return rows
 
 
-def box_holes(precision, steps, with_cpu=True, se_target=None, tune=True):
+def box_holes(precision, steps, with_cpu=True, se_target=None, tune=True, with_fp64=False):
     """Uneven batching: the box [0,4]^3 minus 20 holes, 5994 patches in five
     panel classes (8..128 panels), adaptive walks 1e3..2e5 per node at a
     target standard error of 1e-3, all in one adaptive call (pilot launch,
     budgets, one launch over the uneven remainder, merge), then the solve,
     captured in a HIP graph and replayed per step.  The walk schedule comes
     from the autotuner (timed on a sample of the remainder's work list as a
-    pilot estimates it)."""
+    pilot estimates it).  The Neumann data are checked against the exact data
+    (global area-weighted relative L2 over the trusted panels, beside the
+    same norm of the propagated standard errors).  with_fp64: one more step
+    of the plain FP64 path (eager, same budgets rule) for the comparison at
+    equal error."""
     import torch
 
     import dtn_inputs as I
@@ -216,6 +221,39 @@ def box_holes(precision, steps, with_cpu=True, se_target=None, tune=True):
     se = np.sqrt(st[:, 2] / np.maximum(st[:, 0] - 1, 1) / st[:, 0])
     free = (u > cfg["min_walks"]) & (u < cfg["max_walks"])
     sec = float(np.mean(times))
+    # exact Neumann data at the collocation points (sources inside the holes)
+    from oracle import patch as OP
+    ex, area, tr = [], [], []
+    for q in OP.patches_from_desc(pd, gd):
+        xg, ng, ar, r = OP.collocation_points(q)
+        ex.append(OP.exact_neumann(gd, xg, ng))
+        area.append(ar)
+        tr.append(r < 0.7 * q.h)
+    ex, area, tr = map(np.concatenate, (ex, area, tr))
+
+    def errors(neumann, neumann_se):
+        sig, sse = neumann.cpu().numpy(), neumann_se.cpu().numpy()
+        noise = float(np.sqrt(np.sum(area[tr] * sse[tr] ** 2) / np.sum(area[tr] * ex[tr] ** 2)))
+        return OP.rel_l2(sig, ex, area, tr), noise
+
+    err, noise = errors(neu, nse)
+    fp64 = None
+    if with_fp64:
+        stats64, used64 = torch.empty_like(stats), torch.empty_like(used)
+        n64, s64 = torch.empty_like(neu), torch.empty_like(nse)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dtn.wos_adaptive(g, nodes, cfg["seed"], *budget, precision="fp64", schedule=sched, stats=stats64,
+                         walks_used=used64, capped=capped)
+        plan.solve(stats64, precision="fp64", neumann=n64, neumann_se=s64)
+        torch.cuda.synchronize()
+        sec64 = time.perf_counter() - t0
+        print(f"[bench] box_holes plain FP64 step {sec64:.2f} s", file=sys.stderr, flush=True)
+        e64, noise64 = errors(n64, s64)
+        w64 = float(used64.sum().item())
+        fp64 = {"seconds_per_step": sec64, "walks": w64, "walks_per_s": w64 / sec64,
+                "patches_per_s": len(pd["h"]) / sec64, "neumann_rel_l2_vs_exact": e64,
+                "propagated_noise_rel_l2": noise64, "patches_per_s_ratio": sec64 / sec}
     cpu = None
     if with_cpu:
         # the oracle's adaptive walks (FP64) on 64 seeded nodes of patches of every class
@@ -237,11 +275,12 @@ def box_holes(precision, steps, with_cpu=True, se_target=None, tune=True):
             "walk_steps_per_s": float(st[:, 3].sum()) / sec, "steps_per_walk": float(st[:, 3].sum() / u.sum()),
             "share_at_max_walks": float(np.mean(u == cfg["max_walks"])),
             "median_se_unclamped_nodes": float(np.median(se[free])) if free.any() else None,
+            "neumann_rel_l2_vs_exact": err, "propagated_noise_rel_l2": noise,
             "capped_walks": int(capped.sum().item()), "schedule": sched, "schedule_ms": table,
-            "cpu_baseline": cpu}
+            "plain_fp64": fp64, "cpu_baseline": cpu}
 
 
-def serving(precision, window, rate, se_range, sweep_fraction=0.5, sweep_window=16):
+def serving(precision, window, rate, se_range, sweep_fraction=0.5, sweep_window=6):
     """Query serving on the box-with-holes geometry: Poisson arrivals, each
     query 1..4096 boundary points (log-uniform) with a required standard
     error per node log-uniform on se_range, one patch per point, adaptive
@@ -291,8 +330,8 @@ def serving(precision, window, rate, se_range, sweep_fraction=0.5, sweep_window=
 
     main = run(rate, window)
     plain = run(rate, window, prec="fp64", plain=True)
-    stable = run(sweep_fraction * main["served_qps"], sweep_window)
-    low = run(0.5 * sweep_fraction * main["served_qps"], sweep_window // 2)
+    stable = run(sweep_fraction * main["served_qps"], sweep_window) if sweep_window > 0 else None
+    low = run(0.5 * sweep_fraction * main["served_qps"], max(sweep_window // 2, 1)) if sweep_window > 0 else None
     return {"workload": f"box_holes geometry resident; Poisson arrivals at {rate:g} q/s; 1..4096 points per query "
                         f"(log-uniform); patch per point (h = 0.25 * 2^-j, 8x16 nodes, 32 panels); adaptive walks "
                         f"{cfg['min_walks']}..{cfg['max_walks']} at a per-query node SE log-uniform on "
@@ -457,11 +496,11 @@ def main():
         return
     if args.only == "box_holes":
         print(json.dumps({"box_holes": box_holes("fp32", args.steps, not args.no_cpu_baseline, args.box_holes_se,
-                                                 not args.no_tune)}), flush=True)
+                                                 not args.no_tune, not args.no_variants)}), flush=True)
         return
     if args.only == "serving":
-        print(json.dumps({"serving": serving("fp32", args.serving_window, args.serving_rate, args.serving_se_range)}),
-              flush=True)
+        print(json.dumps({"serving": serving("fp32", args.serving_window, args.serving_rate, args.serving_se_range,
+                                             sweep_window=args.serving_sweep_window)}), flush=True)
         return
     m = measure(args.precision, args.steps, args.warmup)
     variants = {}
@@ -524,9 +563,10 @@ def main():
         "error_vs_walks": curve,
     }
     if args.only is None and not args.no_box_holes:
-        line["box_holes"] = box_holes("fp32", 1, not args.no_cpu_baseline)
+        line["box_holes"] = box_holes("fp32", 1, not args.no_cpu_baseline, with_fp64=not args.no_variants)
     if args.only is None and not args.no_serving:
-        line["serving"] = serving("fp32", args.serving_window, args.serving_rate, args.serving_se_range)
+        line["serving"] = serving("fp32", args.serving_window, args.serving_rate, args.serving_se_range,
+                                  sweep_window=args.serving_sweep_window)
         line["p50_latency_ms"] = line["serving"]["served"]["p50_ms"]
         line["p99_latency_ms"] = line["serving"]["served"]["p99_ms"]
     if not args.no_cpu_baseline:
