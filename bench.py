@@ -76,8 +76,8 @@ SLOTS_PER_WALK = slots(WALK_OPS)
 # the kernel sources it was measured on (SHA-256 of these files).
 TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_amd/csrc/dtn_device.h",
                      "paper_1210_1491_amd/csrc/dtn_internal.h"],
-           "sha256": ["78b66e4b0a60d581f0082d4d15a7a88633981b5e44ac82b892ff8665f3ed104f",
-                      "9d7f8603a187c1d1865c1be11c6644ba692350c88a379e465a92dd7a8bb6839b",
+           "sha256": ["2af1e844ca5d6b9d2dfca04f9c6919ae9a34493c39c0886157f07fbd1e9d2f08",
+                      "5bf5ae5c210289f948a9f4def70e7938a0ad60e4c0771c4c633da8100cea1ed6",
                       "0eb5bfa94f8b9bc0c04b0ca22c7c7b33abc91770a9c5511a852c88858976a8fa"],
            "fetch_bytes": 71757.25 * 1024 * (262144 / 131089.625), "write_bytes": 43008.0 * 1024 * 1.00}
 

@@ -381,16 +381,8 @@ __device__ __forceinline__ KSum wave_ksum(KSum a)
     return a;
 }
 
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
-}
-
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
-// Rank of this lane among the lanes set in `mask` below it.
 // Exit-point queue entry (3 doubles) `first + rank` of a queue in LDS,
 // addressed in 32 bits: rank x 24 B (one 24-bit multiply-add) onto the
 // wave-uniform byte offset of entry `first`.
@@ -406,6 +398,7 @@ __device__ __forceinline__ lds_double *lds_slot(double *queue, uint32_t first, u
 // execution mask directly; no vector instruction)?
 __device__ __forceinline__ bool lane_in(uint64_t mask) { return __builtin_amdgcn_inverse_ballot_w64(mask); }
 
+// Rank of this lane among the lanes set in `mask` below it.
 __device__ __forceinline__ int rank_below(uint64_t mask)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));

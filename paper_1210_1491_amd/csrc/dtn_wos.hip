@@ -15,8 +15,10 @@
 //                   the next walk of the chunk, so lanes do not idle behind
 //                   long walks.  Absorbed positions are queued in LDS and
 //                   projected and scored 64 at a time by the whole wave, so
-//                   that code runs with full lanes.  Per-lane compensated FP64 sums are
-//                   reduced across the wave and written per chunk.
+//                   that code runs with full lanes.  Which lanes hold a walk is
+//                   a wave-uniform mask; jumps and capped walks are counted
+//                   from it on the scalar unit.  Per-lane compensated FP64
+//                   sums are reduced across the wave and written per chunk.
 //   k_wos_finalize  per point: merge its chunks in chunk order (fixed
 //                   order, so results do not depend on which wave ran which
 //                   chunk), write (count, mean, M2, steps) and capped count.
