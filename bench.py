@@ -53,10 +53,11 @@ STEP_OPS = {
              # cap test, Philox xors (half block: 10), counter word, table index and
              # remainder bits (3), step counter
              "i32": 16, "mad64": 10, "cvt": 2, "rsq64": 1},
-    # FP64 distance (11), eps test (1), jump shortening (1); FP32 uniforms (2 FMA), z (1),
-    # u(1-u) (2), x2 (1), s cos / s sin (2); sqrt, sin, cos on the transcendental unit;
-    # conversions: 2 uniforms, 3 direction components; 3 FP64 FMAs of the jump
-    "fp32": {"f64": 13, "f64fma": 3, "f32": 8, "trans32": 3, "cvt": 5, "i32": 15, "mad64": 10},
+    # FP64 distance (11), eps test (1), jump shortening (1); FP32 uniforms (2 subtractions
+    # after a bit alignment each, counted in i32), z (1), u(1-u) (2), x2 (1), s cos / s sin
+    # (2); sqrt, sin, cos on the transcendental unit; conversions: 3 direction components;
+    # 3 FP64 FMAs of the jump
+    "fp32": {"f64": 13, "f64fma": 3, "f32": 8, "trans32": 3, "cvt": 3, "i32": 15, "mad64": 10},
 }
 # projection, 8 sources (sub, FMA, rsq + two Newton steps each), shift,
 # two compensated adds, square, counters
@@ -77,7 +78,7 @@ SLOTS_PER_WALK = slots(WALK_OPS)
 TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_amd/csrc/dtn_device.h",
                      "paper_1210_1491_amd/csrc/dtn_internal.h"],
            "sha256": ["2af1e844ca5d6b9d2dfca04f9c6919ae9a34493c39c0886157f07fbd1e9d2f08",
-                      "5bf5ae5c210289f948a9f4def70e7938a0ad60e4c0771c4c633da8100cea1ed6",
+                      "c69df2588ef5e7b8c4033c2ff0c89e80d5f70816bbcef1cb462d8fa5d8064f15",
                       "0eb5bfa94f8b9bc0c04b0ca22c7c7b33abc91770a9c5511a852c88858976a8fa"],
            "fetch_bytes": 71757.25 * 1024 * (262144 / 131089.625), "write_bytes": 43008.0 * 1024 * 1.00}
 

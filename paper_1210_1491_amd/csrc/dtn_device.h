@@ -53,8 +53,13 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
 
 // FP64 uniform in (0,1): (k + 1/2) 2^-32, exact.
 __device__ __forceinline__ double u01_f64(uint32_t k) { return __builtin_amdgcn_ldexp((double)k + 0.5, -32); }
-// FP32 uniform in (0,1): ((k >> 8) + 1/2) 2^-24, exact.
-__device__ __forceinline__ float u01_f32(uint32_t k) { return fmaf((float)(k >> 8), 0x1p-24f, 0x1p-25f); }
+// FP32 uniform in (0,1): (m + 1/2) 2^-23 with m = k >> 9, exact.  One
+// v_alignbit_b32 shifts the exponent bits of 1.0 in above m, giving the float
+// 1 + m 2^-23; subtracting 1 - 2^-24 is exact (Sterbenz) and centres the bins.
+__device__ __forceinline__ float u01_f32(uint32_t k)
+{
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, k, 9)) - 0x1.fffffep-1f;
+}
 
 // ---------------------------------------------------------------- sin, cos
 // sin and cos of the angle 2 pi (k + 1/2) 2^-32 of a 32-bit random word k.
