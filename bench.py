@@ -78,7 +78,7 @@ SLOTS_PER_WALK = slots(WALK_OPS)
 TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_amd/csrc/dtn_device.h",
                      "paper_1210_1491_amd/csrc/dtn_internal.h"],
            "sha256": ["2af1e844ca5d6b9d2dfca04f9c6919ae9a34493c39c0886157f07fbd1e9d2f08",
-                      "c69df2588ef5e7b8c4033c2ff0c89e80d5f70816bbcef1cb462d8fa5d8064f15",
+                      "f08b594356e1de72579b89237edae8f77fa981deb2f56b0c84db5699ce9a9030",
                       "0eb5bfa94f8b9bc0c04b0ca22c7c7b33abc91770a9c5511a852c88858976a8fa"],
            "fetch_bytes": 71757.25 * 1024 * (262144 / 131089.625), "write_bytes": 43008.0 * 1024 * 1.00}
 

@@ -70,6 +70,15 @@ __device__ __forceinline__ float u01_f32(uint32_t k)
 // (sin, cos)(2 pi j / 256); sin x and cos x come from their Taylor series to
 // x^7 and x^6 (first omitted terms below 2e-20 relative); the angle-addition
 // formulas combine them.
+// min(a, b) of two non-NaN values as one v_min_f64 (fmin() of a loop-carried
+// value costs a canonicalizing v_max_f64 per use).
+__device__ __forceinline__ double min_f64(double a, double b)
+{
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 // a * b + c as one three-address FMA: a and c in vector registers, b in a
 // scalar register (fma_vsv), or a and b in vector registers and c in a scalar
 // register (fma_vvs).  With a constant addend the compiler otherwise picks
@@ -228,7 +237,7 @@ __device__ __forceinline__ double dist_f64(const DevGeom &g, double x, double y,
                 const double qx = fmax(fabs(x - h[0]) - h[3], 0.0);
                 const double qy = fmax(fabs(y - h[1]) - h[4], 0.0);
                 const double qz = fmax(fabs(z - h[2]) - h[5], 0.0);
-                q2 = fmin(q2, qx * qx + qy * qy + qz * qz);
+                q2 = min_f64(q2, qx * qx + qy * qy + qz * qz);
             };
             if (g.cell_mask) {
                 // only the holes listed for some lane's cell (`cand`, from
