@@ -77,8 +77,8 @@ SLOTS_PER_WALK = slots(WALK_OPS)
 # the kernel sources it was measured on (SHA-256 of these files).
 TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_amd/csrc/dtn_device.h",
                      "paper_1210_1491_amd/csrc/dtn_internal.h"],
-           "sha256": ["2af1e844ca5d6b9d2dfca04f9c6919ae9a34493c39c0886157f07fbd1e9d2f08",
-                      "f08b594356e1de72579b89237edae8f77fa981deb2f56b0c84db5699ce9a9030",
+           "sha256": ["26d8366947baede436435ebd9a74e5ad8b185f434be47fa8ae15b5f1ba2c8ffc",
+                      "d0793623423aca1a2d8bfcfdc217a0b0eab8e418fc5287f0eb62e2b0185e07a9",
                       "0eb5bfa94f8b9bc0c04b0ca22c7c7b33abc91770a9c5511a852c88858976a8fa"],
            "fetch_bytes": 71757.25 * 1024 * (262144 / 131089.625), "write_bytes": 43008.0 * 1024 * 1.00}
 

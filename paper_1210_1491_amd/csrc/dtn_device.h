@@ -70,12 +70,20 @@ __device__ __forceinline__ float u01_f32(uint32_t k)
 // (sin, cos)(2 pi j / 256); sin x and cos x come from their Taylor series to
 // x^7 and x^6 (first omitted terms below 2e-20 relative); the angle-addition
 // formulas combine them.
-// min(a, b) of two non-NaN values as one v_min_f64 (fmin() of a loop-carried
-// value costs a canonicalizing v_max_f64 per use).
+// min(a, b) and max(a, b) of non-NaN values as one v_min_f64 / v_max_f64
+// (fmin() and fmax() of a loop-carried value cost a canonicalizing v_max_f64
+// per use).
 __device__ __forceinline__ double min_f64(double a, double b)
 {
     double r;
     asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+__device__ __forceinline__ double max_f64(double a, double b)
+{
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
     return r;
 }
 
@@ -186,10 +194,18 @@ __device__ __forceinline__ uint32_t cell_candidates(const DevGeom &g, const Cell
                          __umul24((uint32_t)fy, (uint32_t)g.cell_stride[1]) + (uint32_t)fz;
     return g.cell_mask[idx];
 }
+// Box minus boxes comes in two kernel kinds: DTN_BOX_MINUS_BOXES with the
+// candidate grid (up to 32 holes, the grid masks are 32-bit) and
+// kHolesNoGrid, which visits every hole.  The host picks by the grid's
+// presence, so neither kind tests it at run time.
+constexpr int kHolesNoGrid = 3;
+constexpr bool has_holes(int kind) { return kind == DTN_BOX_MINUS_BOXES || kind == kHolesNoGrid; }
+
+// Union over the wave of the candidate holes of the cells of the lanes that
+// `take` (grid kind only).
 __device__ __forceinline__ uint32_t hole_candidates(const DevGeom &g, const CellOff &co, bool take, float x, float y,
                                                     float z)
 {
-    if (!g.cell_mask) return 0xffffffffu;
     const uint32_t mine = take ? cell_candidates(g, co, x, y, z) : 0u;
     return __ockl_wfred_or_u32(mine);
 }
@@ -230,33 +246,38 @@ __device__ __forceinline__ double dist_f64(const DevGeom &g, double x, double y,
     } else {
         double d = fmin(fmin(fmin(x - g.lo[0], g.hi[0] - x), fmin(y - g.lo[1], g.hi[1] - y)),
                         fmin(z - g.lo[2], g.hi[2] - z));
-        if constexpr (KIND == DTN_BOX_MINUS_BOXES) {
+        if constexpr (has_holes(KIND)) {
             // nearest hole by squared distance, one square root at the end
-            double q2 = __builtin_inf();
-            auto hole = [&](cdouble *h) {
+            auto hole_q2 = [&](cdouble *h) {
                 const double qx = fmax(fabs(x - h[0]) - h[3], 0.0);
                 const double qy = fmax(fabs(y - h[1]) - h[4], 0.0);
                 const double qz = fmax(fabs(z - h[2]) - h[5], 0.0);
-                q2 = min_f64(q2, qx * qx + qy * qy + qz * qz);
+                return qx * qx + qy * qy + qz * qz;
             };
-            if (g.cell_mask) {
-                // only the holes listed for some lane's cell (`cand`, from
-                // hole_candidates): the others are farther than the boundary
-                // from every point of those cells
-                uint32_t m = cand;
-                while (m) {
-                    const int i = __builtin_ctz(m);
-                    m &= m - 1u;
-                    hole(as_const(g.hole_ce) + 6 * i);
-                }
-            } else {
-                cdouble *h = as_const(g.hole_ce);
+            // the holes listed for some lane's cell (`cand`, from
+            // hole_candidates: the others are farther than the boundary from
+            // every point of those cells), or every hole without the grid; the
+            // branch is wave-uniform, and inside it q2 is finite
+            if (KIND == DTN_BOX_MINUS_BOXES ? cand != 0u : g.n_holes > 0) {
+                double q2 = __builtin_inf();
+                if constexpr (KIND == DTN_BOX_MINUS_BOXES) {
+                    uint32_t m = cand;
+                    while (m) {
+                        const int i = __builtin_ctz(m);
+                        m &= m - 1u;
+                        q2 = min_f64(q2, hole_q2(as_const(g.hole_ce) + 6 * i));
+                    }
+                } else {
+                    cdouble *h = as_const(g.hole_ce);
 #pragma unroll 1
-                for (int i = 0; i < g.n_holes; ++i, h += 6) hole(h);
-            }
-            if (q2 < __builtin_inf()) {
-                const double dh = FAST ? q2 * __builtin_amdgcn_rsq(q2) : sqrt_f64(q2);
-                d = fmin(d, q2 > 0.0 ? dh : 0.0);
+                    for (int i = 0; i < g.n_holes; ++i, h += 6) q2 = min_f64(q2, hole_q2(h));
+                }
+                // a point on a hole (q2 = 0) must still give a distance inside
+                // any shell: the root's argument is clamped at 2^-1000 instead
+                // of a test (identical for every q2 above it)
+                const double qs = max_f64(q2, 0x1p-1000);
+                const double dh = FAST ? q2 * __builtin_amdgcn_rsq(qs) : sqrt_f64(qs);
+                d = min_f64(d, dh);
             }
         }
         return d;
@@ -300,7 +321,7 @@ __device__ __forceinline__ void project_f64(const DevGeom &g, double &x, double 
                 face = f;
             }
         int hole = -1;
-        if constexpr (KIND == DTN_BOX_MINUS_BOXES) {
+        if constexpr (has_holes(KIND)) {
             auto visit = [&](int i) {
                 cdouble *h = as_const(g.hole_ce) + 6 * i;
                 const double qx = fmax(fabs(x - h[0]) - h[3], 0.0);
@@ -312,7 +333,7 @@ __device__ __forceinline__ void project_f64(const DevGeom &g, double &x, double 
                     hole = i;
                 }
             };
-            if (g.cell_mask) {
+            if constexpr (KIND == DTN_BOX_MINUS_BOXES) {
                 uint32_t m = cand;
                 while (m) {
                     const int i = __builtin_ctz(m);

@@ -423,6 +423,9 @@ hipError_t dispatch(const Geometry &g, const double *pts, int64_t n, const int64
         return src ? run<DTN_BOX, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
                    : run<DTN_BOX, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
     default:
+        if (!g.dev.cell_mask)
+            return src ? run<kHolesNoGrid, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
+                       : run<kHolesNoGrid, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
         return src ? run<DTN_BOX_MINUS_BOXES, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
                    : run<DTN_BOX_MINUS_BOXES, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
     }
@@ -462,7 +465,11 @@ void distance_kind(const Geometry &g, const double *pts, int64_t n, double *out,
     switch (g.dev.kind) {
     case DTN_BALL: hipLaunchKernelGGL((k_distance<DTN_BALL, FAST>), grid, block, 0, s, g.dev, pts, n, out); break;
     case DTN_BOX: hipLaunchKernelGGL((k_distance<DTN_BOX, FAST>), grid, block, 0, s, g.dev, pts, n, out); break;
-    default: hipLaunchKernelGGL((k_distance<DTN_BOX_MINUS_BOXES, FAST>), grid, block, 0, s, g.dev, pts, n, out);
+    default:
+        if (g.dev.cell_mask)
+            hipLaunchKernelGGL((k_distance<DTN_BOX_MINUS_BOXES, FAST>), grid, block, 0, s, g.dev, pts, n, out);
+        else
+            hipLaunchKernelGGL((k_distance<kHolesNoGrid, FAST>), grid, block, 0, s, g.dev, pts, n, out);
     }
 }
 

@@ -200,3 +200,46 @@ def test_boundary_distance_with_hole_grid_matches_oracle():
     # 6e-8 relative, below the 2^-22 by which their jumps are shortened
     assert np.max(np.abs(d32 - d64) / d64) < 6e-8
     assert np.all(d32 <= d64 * (1.0 + 2.0 ** -22))
+
+
+def _lattice_holes():
+    """40 cubes of side 0.3 on a 5 x 4 x 2 lattice in [0,4]^3: more holes than
+    the candidate grid's 32-bit masks hold, so the kernels visit every hole."""
+    cs = [(x, y, z) for x in (0.5, 1.25, 2.0, 2.75, 3.5) for y in (0.6, 1.55, 2.45, 3.4) for z in (1.3, 2.7)]
+    return np.array([[x - 0.15, y - 0.15, z - 0.15, x + 0.15, y + 0.15, z + 0.15] for x, y, z in cs])
+
+
+def test_many_holes_without_grid_match_oracle():
+    dtn = _dtn()
+    holes = _lattice_holes()
+    assert len(holes) > 32
+    rng = np.random.default_rng(14)
+    src = np.column_stack([(holes[:, :3] + holes[:, 3:]) / 2, rng.normal(size=len(holes))])
+    gd = dict(I.geometry_box_holes(), holes=holes, src=src)
+    # distances: uniform points and points next to faces, edges and corners
+    pts = [rng.uniform(0.0, 4.0, (4000, 3))]
+    for h in holes[::4]:
+        c = rng.uniform(h[:3], h[3:], (100, 3))
+        for m in range(100):
+            for a in rng.permutation(3)[: 1 + m % 3]:
+                c[m, a] = (h[a] - 10 ** rng.uniform(-9, -1)) if rng.random() < 0.5 else (h[3 + a] + 10 ** rng.uniform(-9, -1))
+        pts.append(c)
+    pts = np.concatenate(pts)
+    inside = np.zeros(len(pts), bool)
+    for h in holes:
+        inside |= np.all((pts > h[:3]) & (pts < h[3:]), axis=1)
+    pts = pts[~inside & np.all((pts > 0) & (pts < 4), axis=1)]
+    d_ora, _ = OW.Geometry(gd).dist_proj(pts)
+    g = dtn.Geometry(gd)
+    P = torch.tensor(pts, device="cuda:0")
+    print(f"[gpu] many holes: distance n={len(pts)}", flush=True)
+    d64 = dtn.boundary_distance(g, P, "fp64").cpu().numpy()
+    d32 = dtn.boundary_distance(g, P, "fp32").cpu().numpy()
+    assert np.max(np.abs(d64 - d_ora) / np.maximum(d_ora, 1e-300)) < 1e-14
+    assert np.max(np.abs(d32 - d64) / d64) < 6e-8
+    # walks, walk for walk against the oracle
+    wp = pts[:150]
+    print(f"[gpu] many holes: walks n={len(wp)}", flush=True)
+    gpu = _gpu_wos(gd, wp, 1500, seed=15)
+    ora = OW.wos_nodes(OW.Geometry(gd), wp, 1500, seed=15)
+    _compare(gpu, ora)
