@@ -40,7 +40,10 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
         const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
-        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
+        // in the first round c3 (the stream id) and k1 are both wave-uniform:
+        // their XOR is one scalar op and the vector side a two-input XOR
+        // (a three-input one could read only one of them from a scalar register)
+        const uint32_t n2 = r == 0 ? (uint32_t)(p0 >> 32) ^ (c3 ^ k1) : xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
