@@ -78,9 +78,9 @@ SLOTS_PER_WALK = slots(WALK_OPS)
 TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_amd/csrc/dtn_device.h",
                      "paper_1210_1491_amd/csrc/dtn_internal.h"],
            "sha256": ["26d8366947baede436435ebd9a74e5ad8b185f434be47fa8ae15b5f1ba2c8ffc",
-                      "d0793623423aca1a2d8bfcfdc217a0b0eab8e418fc5287f0eb62e2b0185e07a9",
+                      "636be46c3c3fa5e81b358641ad3e7a82ad3a084e4f03e4dd0cd47bee3fc3ee35",
                       "0eb5bfa94f8b9bc0c04b0ca22c7c7b33abc91770a9c5511a852c88858976a8fa"],
-           "fetch_bytes": 71757.25 * 1024 * (262144 / 131089.625), "write_bytes": 43008.0 * 1024 * 1.00}
+           "fetch_bytes": 71757.75 * 1024 * (262144 / 131089.625), "write_bytes": 43008.0 * 1024 * 1.00}
 
 
 def traffic_if_current():
