@@ -50,6 +50,32 @@ def geometry_cube_sources(seed=2, eps=1e-5, max_steps=1_000_000):
             "holes": np.zeros((0, 6)), "eps": eps, "max_steps": max_steps}
 
 
+def geometry_halfspace_charge(h=1.0, trunc_r=1e5, eps=1e-5, max_steps=1_000_000):
+    """Half space z > 0 over a unit charge at (0, 0, -h): u = 1 / |x - s|
+    (Sec. 5.1.3, Test 1, eq. bw89 with q'/(4 pi eps0) = 1 and h = 1, the
+    constants that give the printed analytic 0.71554).  Walks that reach the
+    sphere |x| = trunc_r count as gone to infinity (u = 0 there)."""
+    return {"kind": "half_space", "ball_c": (0.0, 0.0, 0.0), "ball_r": float(trunc_r),
+            "data_kind": "sources", "quad": [0.0] * 10, "src": np.array([[0.0, 0.0, -float(h), 1.0]]),
+            "holes": np.zeros((0, 6)), "eps": eps, "max_steps": max_steps}
+
+
+def halfspace_points(n, seed=6, radii=(0.1, 0.2, 0.5, 0.7, 1.0), extent=2.0):
+    """Single-point queries on the plane z = 0: points uniform in the disk of
+    radius ``extent`` around the origin, hemisphere radius cycling through
+    ``radii`` (Table 1's), tangent at a uniform angle.  Rows: x [n,3],
+    outward normal [n,3] = (0, 0, -1), t1 [n,3], a [n]."""
+    rng = np.random.default_rng([seed, 17])
+    r = extent * np.sqrt(rng.random(n))
+    ang = 2 * np.pi * rng.random(n)
+    x = np.column_stack([r * np.cos(ang), r * np.sin(ang), np.zeros(n)])
+    nrm = np.tile([0.0, 0.0, -1.0], (n, 1))
+    b = 2 * np.pi * rng.random(n)
+    t1 = np.column_stack([np.cos(b), np.sin(b), np.zeros(n)])
+    a = np.asarray(radii, float)[np.arange(n) % len(radii)]
+    return x, nrm, t1, a
+
+
 # ----------------------------------------------------------------- patches
 
 
@@ -331,6 +357,16 @@ def serving_queries(gd, n_queries=600, rate=200.0, seed=5, max_points=4096, se_r
 # ----------------------------------------------------------------- configs
 
 CONFIGS = {
+    "halfspace_points": {  # Test 1 scaled to many points: 20x20 nodes, 1e3 walks each
+        "geometry": geometry_halfspace_charge,
+        "points": halfspace_points,
+        "n_points": 4096,
+        "n_g1": 20,
+        "n_g2": 20,
+        "delta_rel": 1e-6,
+        "walks": 1000,
+        "seed": 6,
+    },
     "ball_pole": {  # unit ball, one patch, FP64
         "geometry": geometry_ball_quadratic,
         "patches": patches_ball_pole,

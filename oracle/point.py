@@ -1,0 +1,125 @@
+"""Oracle for the single-point BIE-WOS estimate on a flat boundary.
+
+TEST INFRASTRUCTURE ONLY: plain numpy statement of what the GPU path
+computes; only the test suite, the smoke check and the benchmark's CPU
+baseline may import it.  It shares nothing with the HIP library.
+
+Yan, Cai & Zeng, Sec. 5.1 ("Finding Neumann data at one point on a flat
+boundary").  For a point x on a flat part of the boundary, the hemisphere
+Gamma of radius a centred at x over the disk S_a (Sec. 3, eq. bw20) gives
+
+    du/dn(x) = Sigma1' + Sigma2'                                   (eq. bw64)
+
+    Sigma1' = - int_Gamma h(x, y) (u(y) - phi(x)) ds_y,            (eq. bw65)
+              h = 3 cos(theta) / (2 pi a^3)                         (eq. bw33)
+    Sigma2' = - 1/(2 pi) int_{S_a minus Lambda_delta}
+                 (1/rho^3 - 1/a^3) (phi(y) - phi(x)) ds_y           (eqs. bw68, bw82)
+
+where theta is the polar angle of y seen from x about the inward normal, rho
+= |y - x| and Lambda_delta the disk of radius delta around x (the O(delta)
+error of eq. bw81).  Sigma1' is the N_g1 x N_g1 Gauss rule of eq. bw83 over
+the nodes of eq. bw85 (theta in (0, pi/2), azimuth in (0, 2 pi)), with u at
+the nodes from walk on spheres (eq. bw87).  Sigma2' is an N_g2 x N_g2 Gauss
+rule on the ring (rho in [delta, a] with the Jacobian rho, angle in
+[0, 2 pi]).
+
+Readings (where the paper leaves a choice):
+  - n is the outward normal of the domain in which the walks run (Test 1's
+    analytic value is -d/dz u at (0.5, 0, 0) for walks in z > 0);
+  - Sigma2' keeps both terms of eq. bw68 (the 1/a^3 term is bounded; with
+    it the N_g2 = 20, delta/a = 1e-6 rule gives Table 1's Sigma2' column);
+  - the hemisphere node of polar angle theta and azimuth psi is
+    y = x + a (sin theta cos psi t1 + sin theta sin psi t2 - cos theta n),
+    t2 = n x t1 (the Gauss azimuths are symmetric about pi, so the node set
+    does not depend on the handedness); the ring points likewise in the
+    plane spanned by t1, t2;
+  - the standard error of the estimate propagates the node variances:
+    se^2 = sum_ij W_ij^2 var_ij / count_ij (Sigma2' is deterministic).
+"""
+import numpy as np
+
+
+def gauss_legendre(n):
+    """Gauss-Legendre abscissae and weights on [-1, 1] (library routine)."""
+    return np.polynomial.legendre.leggauss(int(n))
+
+
+def _frame(n, t1):
+    n = np.asarray(n, dtype=np.float64)
+    t1 = np.asarray(t1, dtype=np.float64)
+    t2 = np.cross(n, t1)
+    return n, t1, t2
+
+
+def hemisphere_rule(x, n, t1, a, n_g1):
+    """Nodes y_ij of eq. bw85 and the weights W_ij of eq. bw83.
+
+    Returns (nodes [n_g1*n_g1][3], W [n_g1*n_g1]) with theta-major order;
+    Sigma1' = -sum_ij W_ij (u(y_ij) - phi(x)).
+    W_ij = (pi/4 w_i)(pi w_j) a^2 sin(theta_i) * 3 cos(theta_i) / (2 pi a^3).
+    """
+    xi, w = gauss_legendre(n_g1)
+    theta = np.pi / 4.0 * (xi + 1.0)
+    psi = np.pi * (xi + 1.0)
+    wt = np.pi / 4.0 * w
+    wp = np.pi * w
+    n, t1, t2 = _frame(n, t1)
+    x = np.asarray(x, dtype=np.float64)
+    T, P = np.meshgrid(theta, psi, indexing="ij")
+    nodes = (x[None, None, :]
+             + a * (np.sin(T)[..., None] * np.cos(P)[..., None] * t1
+                    + np.sin(T)[..., None] * np.sin(P)[..., None] * t2
+                    - np.cos(T)[..., None] * n))
+    area = np.outer(wt, wp) * a * a * np.sin(T)            # surface element
+    kern = 3.0 * np.cos(T) / (2.0 * np.pi * a ** 3)        # eq. bw33
+    return nodes.reshape(-1, 3), (area * kern).reshape(-1)
+
+
+def ring_rule(x, n, t1, a, n_g2, delta_rel):
+    """Points and weights of the ring quadrature over S_a minus Lambda_delta.
+
+    Returns (points [n_g2*n_g2][3], weights [n_g2*n_g2], rho [n_g2*n_g2]) with
+    rho-major order; the weights include the Jacobian rho.
+    """
+    xi, w = gauss_legendre(n_g2)
+    d = delta_rel * a
+    rho = 0.5 * (a - d) * xi + 0.5 * (a + d)
+    wr = 0.5 * (a - d) * w
+    psi = np.pi * (xi + 1.0)
+    wp = np.pi * w
+    n, t1, t2 = _frame(n, t1)
+    x = np.asarray(x, dtype=np.float64)
+    R, P = np.meshgrid(rho, psi, indexing="ij")
+    pts = x[None, None, :] + R[..., None] * (np.cos(P)[..., None] * t1 + np.sin(P)[..., None] * t2)
+    W = np.outer(wr, wp) * R
+    return pts.reshape(-1, 3), W.reshape(-1), R.reshape(-1)
+
+
+def sigma2(phi, x, n, t1, a, n_g2, delta_rel):
+    """Sigma2' of eqs. bw68 / bw82 by the ring rule; phi maps [m][3] -> [m]."""
+    pts, W, rho = ring_rule(x, n, t1, a, n_g2, delta_rel)
+    fx = phi(np.asarray(x, dtype=np.float64)[None, :])[0]
+    f = phi(pts) - fx
+    return -np.sum(W * (1.0 / rho ** 3 - 1.0 / a ** 3) * f) / (2.0 * np.pi)
+
+
+def sigma1(phi_x, W, node_mean):
+    """Sigma1' of eq. bw83 from the node means of u."""
+    return -np.sum(W * (np.asarray(node_mean) - phi_x))
+
+
+def point_neumann(phi, x, n, t1, a, n_g1, n_g2, delta_rel, node_stats):
+    """du/dn at x from walk statistics at the hemisphere nodes.
+
+    node_stats: [n_g1*n_g1][4] (count, mean, M2, steps) in the node order of
+    hemisphere_rule.  Returns (value, se, sigma1', sigma2').
+    """
+    _, W = hemisphere_rule(x, n, t1, a, n_g1)
+    st = np.asarray(node_stats, dtype=np.float64)
+    fx = phi(np.asarray(x, dtype=np.float64)[None, :])[0]
+    s1 = sigma1(fx, W, st[:, 1])
+    s2 = sigma2(phi, x, n, t1, a, n_g2, delta_rel)
+    cnt = st[:, 0]
+    var = np.where(cnt > 1, st[:, 2] / np.maximum(cnt - 1, 1), 0.0)
+    se = np.sqrt(np.sum(W * W * np.where(cnt > 0, var / np.maximum(cnt, 1), 0.0)))
+    return s1 + s2, se, s1, s2

@@ -54,7 +54,7 @@ class OgGeom(C.Structure):
     ]
 
 
-KIND = {"ball": 0, "box": 1, "box_minus_boxes": 2}
+KIND = {"ball": 0, "box": 1, "box_minus_boxes": 2, "half_space": 3}
 
 
 def _dptr(a):

@@ -31,7 +31,14 @@
  *   - a walk that reaches max_steps is scored at its closest boundary point
  *     and counted as capped;
  *   - the node statistics are shifted sums (shift = phi at the node's closest
- *     boundary point) accumulated with Neumaier's compensated summation.
+ *     boundary point) accumulated with Neumaier's compensated summation;
+ *   - half space z > 0 (the exterior domain of the flat-boundary tests of
+ *     Sec. 5.1.3): the distance to the boundary is z; a walk that reaches the
+ *     large truncation sphere |x - ball_c| >= ball_r is taken to have gone to
+ *     infinity (Sec. 5.1.3, the sphere of radius 1e5) and scores u = 0 there,
+ *     the limit of data that decay at infinity.  The sphere is tested first at
+ *     every position (start and after every jump), then the shell, then the
+ *     step cap.
  *
  * Build: gcc -O2 -fopenmp -fPIC -shared wos_oracle.c -lm (see build.py).
  */
@@ -44,7 +51,7 @@
 
 /* ---------------------------------------------------------------- geometry */
 
-enum { OG_BALL = 0, OG_BOX = 1, OG_BOX_MINUS_BOXES = 2 };
+enum { OG_BALL = 0, OG_BOX = 1, OG_BOX_MINUS_BOXES = 2, OG_HALF_SPACE = 3 };
 enum { OG_DATA_QUADRATIC = 0, OG_DATA_SOURCES = 1 };
 
 typedef struct {
@@ -89,6 +96,10 @@ double og_phi(const og_geom *g, const double x[3])
  * outer faces -x,+x,-y,+y,-z,+z, then holes in input order. */
 double og_dist_proj(const og_geom *g, const double x[3], double p[3])
 {
+    if (g->kind == OG_HALF_SPACE) {
+        if (p) { p[0] = x[0]; p[1] = x[1]; p[2] = 0.0; }
+        return x[2];
+    }
     if (g->kind == OG_BALL) {
         double v[3] = {x[0] - g->ball_c[0], x[1] - g->ball_c[1], x[2] - g->ball_c[2]};
         double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
@@ -197,8 +208,17 @@ void og_direction(double u1, double u2, double w[3])
 
 /* --------------------------------------------------------------------- WOS */
 
-/* One walk from x0.  Returns the recorded phi; *steps and *capped report the
- * walk length and whether the step cap ended it. */
+/* Has x left the truncation sphere of a half space (gone to infinity)? */
+static int og_escaped(const og_geom *g, const double x[3])
+{
+    if (g->kind != OG_HALF_SPACE) return 0;
+    double dx = x[0] - g->ball_c[0], dy = x[1] - g->ball_c[1], dz = x[2] - g->ball_c[2];
+    return dx * dx + dy * dy + dz * dz >= g->ball_r * g->ball_r;
+}
+
+/* One walk from x0.  Returns the recorded phi (0 for a walk gone to
+ * infinity); *steps and *capped report the walk length and whether the step
+ * cap ended it. */
 double og_walk(const og_geom *g, const double x0[3], uint64_t seed, uint32_t stream_id,
                uint64_t walk, int64_t *steps, int *capped)
 {
@@ -209,6 +229,7 @@ double og_walk(const og_geom *g, const double x0[3], uint64_t seed, uint32_t str
     int64_t n = 0;
     *capped = 0;
     for (;;) {
+        if (og_escaped(g, x)) { *steps = n; return 0.0; }
         double d = og_dist_proj(g, x, p);
         if (d < g->eps) break;
         if (n >= g->max_steps) { *capped = 1; break; }
