@@ -14,6 +14,10 @@
  *   step 2  collocation solve of the local first-kind BIE K sigma = b on the
  *           patch (eqs. bw49-bw51; Sec. 5.2)                 -> dtn_patch_solve
  *   then    u at arbitrary points from eq. bw03              -> dtn_potential
+ * and the single-point variant on a flat boundary (Sec. 5.1): du/dn at one
+ * point from the regularised hypersingular identity, no solve
+ *           hemisphere nodes (eq. bw85)                      -> dtn_points_nodes
+ *           Sigma1' + Sigma2' (eqs. bw64, bw83, bw68/bw82)   -> dtn_points_neumann
  *
  * Conventions
  *   - Bulk arrays are DEVICE pointers owned by the caller (e.g. the data_ptr
@@ -56,8 +60,8 @@ typedef enum {
     DTN_E_MAXSTEPS = -6     /* reserved: walks capped (see dtn_wos_eval)  */
 } dtn_status;
 
-/* Domain kinds (all interior: walks run inside Omega). */
-enum { DTN_BALL = 0, DTN_BOX = 1, DTN_BOX_MINUS_BOXES = 2 };
+/* Domain kinds (walks run inside Omega). */
+enum { DTN_BALL = 0, DTN_BOX = 1, DTN_BOX_MINUS_BOXES = 2, DTN_HALF_SPACE = 3 };
 /* Dirichlet data kinds. */
 enum { DTN_DATA_HARMONIC_QUADRATIC = 0, DTN_DATA_POINT_SOURCES = 1 };
 /* Arithmetic of the walks and of the collocation solve. */
@@ -72,13 +76,22 @@ typedef struct dtn_plan_s *dtn_plan;         /* opaque, library-owned */
  *   kind DTN_BOX_MINUS_BOXES: the box minus n_holes closed axis-aligned
  *                             boxes holes[i] = (lo x,y,z, hi x,y,z), which
  *                             must lie inside it and not overlap.
+ *   kind DTN_HALF_SPACE:      z > 0, boundary the plane z = 0 (the exterior
+ *                             domain of Sec. 5.1.3).  A walk that reaches
+ *                             the truncation sphere |x - ball_c| >= ball_r
+ *                             (tested at its start and after every jump,
+ *                             before the shell) has gone to infinity and
+ *                             scores 0, the limit of data that vanish there
+ *                             (Sec. 5.1.3 uses ball_r = 1e5).  Point sources
+ *                             must lie in z < 0.
  *   data DTN_DATA_HARMONIC_QUADRATIC: phi = q0 + q1 x + q2 y + q3 z + q4 x^2
  *        + q5 y^2 + q6 z^2 + q7 xy + q8 yz + q9 xz, harmonic (q4+q5+q6 = 0).
  *   data DTN_DATA_POINT_SOURCES: phi = sum_k src[k].q / |x - src[k].xyz|,
  *        src rows (x, y, z, q), every source outside the closed domain.
  *   eps: width of the absorbing shell (Sec. 2, epsilon-shell WOS), > 0.
  *   max_steps: a walk still alive after max_steps steps is scored at its
- *        closest boundary point and counted as capped. */
+ *        closest boundary point and counted as capped (a walk gone to
+ *        infinity is neither capped nor absorbed). */
 typedef struct {
     int32_t kind;
     int32_t data_kind;
@@ -257,6 +270,56 @@ dtn_status dtn_patch_solve(dtn_plan p, const double *node_stats, int32_t precisi
  *   neumann device [num_panels]; targets device [m][3]; u_out device [m] */
 dtn_status dtn_potential(dtn_plan p, const double *neumann, const double *targets, int64_t m,
                          double *u_out, void *stream);
+
+/* ------------------------------------------------ single point (Sec. 5.1)
+ * du/dn at a point x of a flat part of the boundary with no collocation
+ * solve.  Over the hemisphere Gamma of radius a centred at x (Sec. 3,
+ * eq. bw20; its Green's function by three images, eq. bw26, gives the kernel
+ * 3 cos(theta) / (2 pi a^3) of eq. bw33),
+ *   du/dn(x) = Sigma1' + Sigma2'                                     (eq. bw64)
+ *   Sigma1' = - sum_ij W_ij (u(y_ij) - phi(x))                       (eq. bw83)
+ *     y_ij = x + a (sin th_i cos ps_j t1 + sin th_i sin ps_j t2 - cos th_i n),
+ *     th_i = pi/4 (xi_i + 1), ps_j = pi (xi_j + 1)  (eq. bw85, N_g1 Gauss
+ *     points xi, weights w), W_ij = (pi/4 w_i)(pi w_j) a^2 sin th_i
+ *     3 cos th_i / (2 pi a^3); u(y_ij) from the walks (eq. bw87);
+ *   Sigma2' = -1/(2 pi) int over S_a minus the disk of radius
+ *     delta = delta_rel a of (1/rho^3 - 1/a^3)(phi(y) - phi(x))
+ *     (eqs. bw68, bw82), by an N_g2 x N_g2 Gauss rule in rho on [delta, a]
+ *     (Jacobian rho) and angle on [0, 2 pi].
+ * The standard error propagates the node variances:
+ * se^2 = sum_ij W_ij^2 var_ij / count_ij. */
+typedef struct dtn_points_s *dtn_points; /* opaque, library-owned */
+
+/* One query point: x on the boundary, n the outward unit normal there, t1 a
+ * unit tangent (t2 = n x t1), a the hemisphere radius.  80 bytes. */
+typedef struct {
+    double c[3];
+    double n[3];
+    double t1[3];
+    double a;
+} dtn_point;
+
+/* Create / destroy a set of query points (host array, copied).
+ * Supported: a half space (n = (0,0,-1), c on z = 0, the hemisphere inside
+ * the truncation sphere) or a face of a box / box minus boxes with the disk
+ * inside the face and the half ball inside Omega (as for plane patches).
+ * n_g1, n_g2 in [1, 64]; delta_rel in (0, 1).  Errors: DTN_E_ARG (n < 1,
+ * bad rule sizes, a point off a flat face, a ball domain). */
+dtn_status dtn_create_points(dtn_geometry g, const dtn_point *pts, int64_t n, int32_t n_g1, int32_t n_g2,
+                             double delta_rel, dtn_points *out);
+void dtn_destroy_points(dtn_points p);
+/* Number of hemisphere nodes: n x n_g1 x n_g1. */
+int64_t dtn_points_num_nodes(dtn_points p);
+
+/* Hemisphere nodes y_ij of every point (device [num_nodes][3] out; point-
+ * major, theta-major, psi-minor), to be walked by dtn_wos_eval. */
+dtn_status dtn_points_nodes(dtn_points p, double *nodes, void *stream);
+
+/* du/dn at every point from the node statistics.
+ *   node_stats device [num_nodes][4] from dtn_wos_eval, node order
+ *   out        device [n][4] out: (Sigma1' + Sigma2', its standard error,
+ *              Sigma1', Sigma2'), all FP64.  Errors: DTN_E_ARG. */
+dtn_status dtn_points_neumann(dtn_points p, const double *node_stats, double *out, void *stream);
 
 /* ------------------------------------------------------------ serving
  * A query server answers Neumann queries at boundary points: for every point

@@ -297,13 +297,14 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
         if (!desc || !out) return fail(DTN_E_ARG, "dtn_create_geometry: NULL argument");
         *out = nullptr;
         const dtn_geometry_desc &d = *desc;
-        if (d.kind < DTN_BALL || d.kind > DTN_BOX_MINUS_BOXES) return fail(DTN_E_ARG, "dtn_create_geometry: bad kind");
+        if (d.kind < DTN_BALL || d.kind > DTN_HALF_SPACE) return fail(DTN_E_ARG, "dtn_create_geometry: bad kind");
         if (d.data_kind != DTN_DATA_HARMONIC_QUADRATIC && d.data_kind != DTN_DATA_POINT_SOURCES)
             return fail(DTN_E_ARG, "dtn_create_geometry: bad data_kind");
         if (!(d.eps > 0.0)) return fail(DTN_E_ARG, "dtn_create_geometry: eps must be > 0");
         if (d.max_steps < 0) return fail(DTN_E_ARG, "dtn_create_geometry: max_steps < 0");
-        if (d.kind == DTN_BALL && !(d.ball_r > 0.0)) return fail(DTN_E_ARG, "dtn_create_geometry: ball_r <= 0");
-        if (d.kind != DTN_BALL)
+        if ((d.kind == DTN_BALL || d.kind == DTN_HALF_SPACE) && !(d.ball_r > 0.0))
+            return fail(DTN_E_ARG, "dtn_create_geometry: ball_r <= 0");
+        if (d.kind == DTN_BOX || d.kind == DTN_BOX_MINUS_BOXES)
             for (int k = 0; k < 3; ++k)
                 if (!(d.box_hi[k] > d.box_lo[k])) return fail(DTN_E_ARG, "dtn_create_geometry: empty box");
         if (d.n_holes < 0 || d.n_src < 0) return fail(DTN_E_ARG, "dtn_create_geometry: negative count");
@@ -311,6 +312,10 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
             return fail(DTN_E_ARG, "dtn_create_geometry: holes is NULL");
         if (d.data_kind == DTN_DATA_POINT_SOURCES && (d.n_src < 1 || !d.src))
             return fail(DTN_E_ARG, "dtn_create_geometry: point-source data needs sources");
+        if (d.kind == DTN_HALF_SPACE && d.data_kind == DTN_DATA_POINT_SOURCES)
+            for (int k = 0; k < d.n_src; ++k)
+                if (!(d.src[4 * k + 2] < 0.0))
+                    return fail(DTN_E_ARG, "dtn_create_geometry: a source of the half space is not in z < 0");
         if (d.data_kind == DTN_DATA_HARMONIC_QUADRATIC &&
             std::fabs(d.quad_coef[4] + d.quad_coef[5] + d.quad_coef[6]) >
                 1e-12 * (1.0 + std::fabs(d.quad_coef[4]) + std::fabs(d.quad_coef[5]) + std::fabs(d.quad_coef[6])))
@@ -554,6 +559,9 @@ dtn_status dtn_create_plan(dtn_geometry g, const dtn_patch *patches, int64_t n_p
         p.patch_class.resize(n_patches);
         std::map<ClassKey, int> local;
         std::vector<ClassKey> keys;
+        if (G.dev.kind == DTN_HALF_SPACE)
+            return fail(DTN_E_ARG, "dtn_create_plan: patch plans need a bounded domain (use dtn_create_points for "
+                                   "the half space)");
         p.tiles_ok = G.dev.kind == DTN_BOX;
         for (int64_t i = 0; i < n_patches; ++i) {
             const dtn_patch &q = p.patches[i];

@@ -201,7 +201,7 @@ __device__ __forceinline__ uint32_t cell_candidates(const DevGeom &g, const Cell
 // candidate grid (up to 32 holes, the grid masks are 32-bit) and
 // kHolesNoGrid, which visits every hole.  The host picks by the grid's
 // presence, so neither kind tests it at run time.
-constexpr int kHolesNoGrid = 3;
+constexpr int kHolesNoGrid = 16;  // internal kind, apart from the public ones
 constexpr bool has_holes(int kind) { return kind == DTN_BOX_MINUS_BOXES || kind == kHolesNoGrid; }
 
 // Union over the wave of the candidate holes of the cells of the lanes that
@@ -243,7 +243,9 @@ __device__ __forceinline__ double phi_eval(const DevGeom &g, double x, double y,
 template <int KIND, bool FAST = false>
 __device__ __forceinline__ double dist_f64(const DevGeom &g, double x, double y, double z, uint32_t cand)
 {
-    if constexpr (KIND == DTN_BALL) {
+    if constexpr (KIND == DTN_HALF_SPACE) {
+        return z;  // the plane z = 0 (the truncation sphere is no surface)
+    } else if constexpr (KIND == DTN_BALL) {
         const double dx = x - g.c[0], dy = y - g.c[1], dz = z - g.c[2];
         return g.r - sqrt_f64(dx * dx + dy * dy + dz * dz);
     } else {
@@ -300,7 +302,9 @@ __device__ __forceinline__ uint32_t all_holes(const DevGeom &g)
 template <int KIND>
 __device__ __forceinline__ void project_f64(const DevGeom &g, double &x, double &y, double &z, uint32_t cand)
 {
-    if constexpr (KIND == DTN_BALL) {
+    if constexpr (KIND == DTN_HALF_SPACE) {
+        z = 0.0;
+    } else if constexpr (KIND == DTN_BALL) {
         const double dx = x - g.c[0], dy = y - g.c[1], dz = z - g.c[2];
         const double r = sqrt(dx * dx + dy * dy + dz * dz);
         if (r > 0.0) {

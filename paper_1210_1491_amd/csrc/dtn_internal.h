@@ -158,6 +158,8 @@ struct ClassOps {
     int n_dl = 0;
 };
 bool build_class_ops(ClassOps &ops, std::string &err);
+// Gauss-Legendre abscissae and weights on [-1, 1] (Newton on the recurrence).
+void gauss_legendre_rule(int n, std::vector<double> &x, std::vector<double> &w);
 
 }  // namespace dtn
 

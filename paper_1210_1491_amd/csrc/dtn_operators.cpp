@@ -555,4 +555,6 @@ bool build_class_ops(ClassOps &ops, std::string &err)
     return true;
 }
 
+void gauss_legendre_rule(int n, std::vector<double> &x, std::vector<double> &w) { gauss_legendre(n, x, w); }
+
 }  // namespace dtn

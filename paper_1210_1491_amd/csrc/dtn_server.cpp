@@ -505,7 +505,8 @@ dtn_status dtn_server_create(dtn_geometry g, const dtn_server_config *cfg, dtn_s
             return fail(DTN_E_ARG, at + "graph replay is switched off (a serving run with it crashed the host "
                                         "process; the cause is not yet shown)");
         Geometry *G = &g->g;
-        if (G->dev.kind == DTN_BALL) return fail(DTN_E_ARG, at + "only box domains (with or without holes) are served");
+        if (G->dev.kind != DTN_BOX && G->dev.kind != DTN_BOX_MINUS_BOXES)
+            return fail(DTN_E_ARG, at + "only box domains (with or without holes) are served");
         std::unique_ptr<dtn_server_s> S(new dtn_server_s());
         S->g = G;
         S->cfg = *cfg;

@@ -23,6 +23,10 @@
 //                   order, so results do not depend on which wave ran which
 //                   chunk), write (count, mean, M2, steps) and capped count.
 //
+// Half space (z > 0): a walk that reaches the truncation sphere has gone to
+// infinity and scores 0 (Sec. 5.1.3); the sphere is tested before the shell.
+// Such a walk is queued with z = -1 (every other queued position has z >= 0).
+//
 // Randomness: walk k of a point with stream id s draws Philox4x32-10 block
 // (k lo, k hi, j, s) for its steps 2j and 2j+1 (words 0,1 then 2,3).  New
 // walks start on even wave iterations only, so every live lane is at the
@@ -105,6 +109,17 @@ __global__ __launch_bounds__(kPlanThreads) void k_wos_plan(const int64_t *__rest
 }
 
 // ---------------------------------------------------------------- the walks
+
+// Score of a queued exit position: phi at its closest boundary point, or 0
+// for a half-space walk gone to infinity (queued with z < 0).
+template <int KIND, int DATA>
+__device__ __forceinline__ double exit_score(const DevGeom &g, double px, double py, double pz, uint32_t pc)
+{
+    const bool gone = KIND == DTN_HALF_SPACE && pz < 0.0;
+    project_f64<KIND>(g, px, py, pz, pc);
+    const double f = phi_eval<DATA>(g, px, py, pz);
+    return gone ? 0.0 : f;
+}
 
 template <int KIND, int DATA, int PREC>
 __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double *__restrict__ pts,
@@ -216,9 +231,14 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
             // domain); only the walking lanes' results are used.
             const double d = dist_f64<KIND, PREC != DTN_FP64>(g, x, y, z, cand);
             const uint64_t in_shell = __builtin_amdgcn_ballot_w64(d < eps);
-            const uint64_t fm = wmask & (in_shell | __builtin_amdgcn_ballot_w64(nstep >= cap));
+            uint64_t gone = 0;  // half space: lanes at or beyond the truncation sphere
+            if constexpr (KIND == DTN_HALF_SPACE) {
+                const double ex = x - g.c[0], ey = y - g.c[1], ez = z - g.c[2];
+                gone = __builtin_amdgcn_ballot_w64(ex * ex + ey * ey + ez * ez >= g.r * g.r);
+            }
+            const uint64_t fm = wmask & (in_shell | gone | __builtin_amdgcn_ballot_w64(nstep >= cap));
             steps += (uint64_t)__popcll(wmask & ~fm);
-            capped += (uint64_t)__popcll(fm & ~in_shell);
+            capped += (uint64_t)__popcll(fm & ~(in_shell | gone));
             if (lane_in(wmask & ~fm)) {
                 if constexpr (PREC == DTN_FP64) {
                     const double u1d = u01_f64(w1);
@@ -253,7 +273,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                     lds_double *e = lds_slot(q, (uint32_t)qn, (uint32_t)rank_below(fm));
                     e[0] = x;
                     e[1] = y;
-                    e[2] = z;
+                    e[2] = (KIND == DTN_HALF_SPACE && lane_in(gone)) ? -1.0 : z;
                 }
                 wmask &= ~fm;
                 qn += __popcll(fm);
@@ -263,8 +283,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                     uint32_t pc = 0;  // candidate holes of the 64 queued points (whole wave active)
                     if constexpr (KIND == DTN_BOX_MINUS_BOXES)
                         pc = hole_candidates(g, co, true, (float)px, (float)py, (float)pz);
-                    project_f64<KIND>(g, px, py, pz, pc);
-                    const double v = phi_eval<DATA>(g, px, py, pz) - shift;
+                    const double v = exit_score<KIND, DATA>(g, px, py, pz, pc) - shift;
                     kadd(s1, v);
                     kadd(s2, v * v);
                     const int rest = qn - kWave;
@@ -294,8 +313,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
             if constexpr (KIND == DTN_BOX_MINUS_BOXES)
                 pc = hole_candidates(g, co, has, (float)px, (float)py, (float)pz);
             if (has) {
-                project_f64<KIND>(g, px, py, pz, pc);
-                const double v = phi_eval<DATA>(g, px, py, pz) - shift;
+                const double v = exit_score<KIND, DATA>(g, px, py, pz, pc) - shift;
                 kadd(s1, v);
                 kadd(s2, v * v);
             }
@@ -422,6 +440,9 @@ hipError_t dispatch(const Geometry &g, const double *pts, int64_t n, const int64
     case DTN_BOX:
         return src ? run<DTN_BOX, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
                    : run<DTN_BOX, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
+    case DTN_HALF_SPACE:
+        return src ? run<DTN_HALF_SPACE, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
+                   : run<DTN_HALF_SPACE, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
     default:
         if (!g.dev.cell_mask)
             return src ? run<kHolesNoGrid, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
@@ -465,6 +486,9 @@ void distance_kind(const Geometry &g, const double *pts, int64_t n, double *out,
     switch (g.dev.kind) {
     case DTN_BALL: hipLaunchKernelGGL((k_distance<DTN_BALL, FAST>), grid, block, 0, s, g.dev, pts, n, out); break;
     case DTN_BOX: hipLaunchKernelGGL((k_distance<DTN_BOX, FAST>), grid, block, 0, s, g.dev, pts, n, out); break;
+    case DTN_HALF_SPACE:
+        hipLaunchKernelGGL((k_distance<DTN_HALF_SPACE, FAST>), grid, block, 0, s, g.dev, pts, n, out);
+        break;
     default:
         if (g.dev.cell_mask)
             hipLaunchKernelGGL((k_distance<DTN_BOX_MINUS_BOXES, FAST>), grid, block, 0, s, g.dev, pts, n, out);

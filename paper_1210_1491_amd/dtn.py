@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libdtn.so")
 DTN_OK = 0
 STATUS = {0: "DTN_OK", -1: "DTN_E_ARG", -2: "DTN_E_DEVICE", -3: "DTN_E_OOM", -4: "DTN_E_UNSUPPORTED",
           -5: "DTN_E_NOCONV", -6: "DTN_E_MAXSTEPS"}
-KIND = {"ball": 0, "box": 1, "box_minus_boxes": 2}
+KIND = {"ball": 0, "box": 1, "box_minus_boxes": 2, "half_space": 3}
 DATA = {"quadratic": 0, "sources": 1}
 PRECISION = {"fp64": 0, "fp32": 1, "fp32_mixed": 1}
 
@@ -42,6 +42,10 @@ class PatchDesc(C.Structure):
 
 
 assert C.sizeof(PatchDesc) == 96
+
+
+class PointDesc(C.Structure):
+    _fields_ = [("c", C.c_double * 3), ("n", C.c_double * 3), ("t1", C.c_double * 3), ("a", C.c_double)]
 
 
 class ScheduleDesc(C.Structure):
@@ -116,13 +120,22 @@ def lib():
         L.dtn_patch_nodes.argtypes = [vp, vp, vp]
         L.dtn_patch_solve.argtypes = [vp, vp, C.c_int32, vp, vp, vp]
         L.dtn_potential.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
+        L.dtn_create_points.argtypes = [vp, C.POINTER(PointDesc), C.c_int64, C.c_int32, C.c_int32, C.c_double,
+                                        C.POINTER(vp)]
+        L.dtn_destroy_points.argtypes = [vp]
+        L.dtn_destroy_points.restype = None
+        L.dtn_points_num_nodes.argtypes = [vp]
+        L.dtn_points_num_nodes.restype = C.c_int64
+        L.dtn_points_nodes.argtypes = [vp, vp, vp]
+        L.dtn_points_neumann.argtypes = [vp, vp, vp, vp]
         dp = C.POINTER(C.c_double)
         L.dtn_class_operators.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
                                           dp, dp, dp, dp, dp, dp]
         for f in ("dtn_create_geometry", "dtn_wos_eval", "dtn_wos_adaptive", "dtn_wos_time_schedules",
                   "dtn_boundary_distance", "dtn_server_create", "dtn_server_submit", "dtn_server_wait",
                   "dtn_create_plan", "dtn_patch_nodes",
-                  "dtn_patch_solve", "dtn_potential", "dtn_class_operators"):
+                  "dtn_patch_solve", "dtn_potential", "dtn_class_operators", "dtn_create_points",
+                  "dtn_points_nodes", "dtn_points_neumann"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -336,6 +349,52 @@ class Plan:
             out = torch.empty(m, dtype=torch.float64, device=targets.device)
         _check(lib().dtn_potential(self.handle, _ptr(neumann), _ptr(targets), m, _ptr(out), _stream()),
                "dtn_potential")
+        return out
+
+
+class Points:
+    """Single-point queries on a flat boundary (Sec. 5.1): hemisphere nodes
+    and du/dn = Sigma1' + Sigma2' from the node statistics."""
+
+    def __init__(self, geom, x, normals, t1, a, n_g1=20, n_g2=20, delta_rel=1e-6):
+        self.geom = geom
+        x = np.asarray(x, np.float64).reshape(-1, 3)
+        normals = np.asarray(normals, np.float64).reshape(-1, 3)
+        t1 = np.asarray(t1, np.float64).reshape(-1, 3)
+        a = np.broadcast_to(np.asarray(a, np.float64), (x.shape[0],))
+        self.n = x.shape[0]
+        arr = (PointDesc * max(self.n, 1))()
+        for i in range(self.n):
+            for k in range(3):
+                arr[i].c[k] = float(x[i, k])
+                arr[i].n[k] = float(normals[i, k])
+                arr[i].t1[k] = float(t1[i, k])
+            arr[i].a = float(a[i])
+        self.handle = C.c_void_p()
+        _check(lib().dtn_create_points(geom.handle, arr, self.n, int(n_g1), int(n_g2), float(delta_rel),
+                                       C.byref(self.handle)), "dtn_create_points")
+        self.num_nodes = int(lib().dtn_points_num_nodes(self.handle))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.dtn_destroy_points(h)
+            self.handle = None
+
+    def nodes(self, out=None, device="cuda"):
+        if out is None:
+            out = torch.empty((self.num_nodes, 3), dtype=torch.float64, device=device)
+        _dev_tensor(out, torch.float64, (self.num_nodes, 3))
+        _check(lib().dtn_points_nodes(self.handle, _ptr(out), _stream()), "dtn_points_nodes")
+        return out
+
+    def neumann(self, node_stats, out=None):
+        """(du/dn, standard error, Sigma1', Sigma2') per point, [n][4]."""
+        _dev_tensor(node_stats, torch.float64, (self.num_nodes, 4))
+        if out is None:
+            out = torch.empty((self.n, 4), dtype=torch.float64, device=node_stats.device)
+        _dev_tensor(out, torch.float64, (self.n, 4))
+        _check(lib().dtn_points_neumann(self.handle, _ptr(node_stats), _ptr(out), _stream()), "dtn_points_neumann")
         return out
 
 

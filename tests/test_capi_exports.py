@@ -22,6 +22,7 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(dtn.LIB_PATH)
     names = _declared()
     assert "dtn_wos_eval" in names and "dtn_patch_solve" in names and "dtn_potential" in names
+    assert "dtn_create_points" in names and "dtn_points_neumann" in names
     for n in names:
         assert hasattr(lib, n), n
     assert "gfx950" in dtn.version()
@@ -95,3 +96,15 @@ def test_server_footprint_under_graph_replay_is_that_of_the_padded_batch(max_poi
         assert n <= b <= max(n, min(max_points, int(n * 1.25) + 1))
         got = L.dtn_server_footprint(ctypes.byref(graph), n)
         assert got == L.dtn_server_footprint(ctypes.byref(direct), b), (n, b)
+
+
+def test_points_arguments_are_checked_before_any_device_work():
+    """NULL handles and arrays are refused on the host (no GPU needed)."""
+    from paper_1210_1491_amd import dtn
+    L = dtn.lib()
+    h = ctypes.c_void_p()
+    assert L.dtn_create_points(None, None, 1, 20, 20, 1e-6, ctypes.byref(h)) == -1
+    assert "NULL" in L.dtn_last_error().decode()
+    assert L.dtn_points_nodes(None, None, None) == -1
+    assert L.dtn_points_neumann(None, None, None, None) == -1
+    assert L.dtn_points_num_nodes(None) == -1

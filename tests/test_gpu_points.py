@@ -1,0 +1,216 @@
+"""GPU parity of the single-point flat-boundary path (Sec. 5.1) against the
+oracle, through the C-ABI: half-space walks with the truncation sphere
+(FP64 walk for walk, FP32-mixed statistically), the hemisphere nodes, the
+Sigma1' / Sigma2' reduction, and Table 1 end to end.
+"""
+import numpy as np
+import pytest
+import torch
+
+import dtn_inputs as I
+from oracle import point as OPt
+from oracle import wos as OW
+
+from test_gpu_wos import _compare, _gpu_wos
+
+pytestmark = pytest.mark.gpu
+
+X0 = (0.5, 0.0, 0.0)
+N_DOWN = (0.0, 0.0, -1.0)
+T1 = (1.0, 0.0, 0.0)
+EXACT_T1 = 1.0 / 1.25 ** 1.5
+
+
+def _dtn():
+    from paper_1210_1491_amd import dtn
+    return dtn
+
+
+def _hs(**kw):
+    return dict(I.geometry_halfspace_charge(), **kw)
+
+
+def _above_plane(n, seed, r=0.6):
+    """Seeded start points in the half ball of radius r over (0.5, 0, 0)."""
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    d[:, 2] = np.abs(d[:, 2])
+    return np.asarray(X0) + r * rng.random(n)[:, None] ** (1 / 3) * d
+
+
+def test_halfspace_walks_fp64_parity():
+    gd = _hs()
+    nodes = _above_plane(400, 1)
+    gpu = _gpu_wos(gd, nodes, 2000, seed=7)
+    ora = OW.wos_nodes(OW.Geometry(gd), nodes, 2000, seed=7)
+    _compare(gpu, ora)
+    assert np.all(gpu["capped"] == 0)
+
+
+@pytest.mark.parametrize("data", ["sources", "constant"])
+def test_halfspace_truncation_parity_ragged(data):
+    # a small sphere (radius 3) so that many walks reach it; ragged walk
+    # counts; start points beyond the sphere, inside the shell, and both
+    kw = {"ball_r": 3.0}
+    if data == "constant":
+        kw.update(data_kind="quadratic", quad=[1.0] + [0.0] * 9, src=np.zeros((0, 4)))
+    gd = _hs(**kw)
+    rng = np.random.default_rng(21)
+    pts = np.column_stack([rng.uniform(-1.5, 1.5, (150, 2)), rng.uniform(0.0, 1.5, 150)])
+    pts[0] = (0.0, 0.0, 3.5)          # beyond the sphere
+    pts[1] = (0.3, 0.2, 4e-6)         # in the shell
+    pts[2] = (3.2, 0.0, 4e-6)         # both: the sphere wins
+    pts[3] = (0.0, 0.0, 2.9999)       # just inside
+    walks = rng.integers(1, 1500, size=len(pts))
+    walks[4] = 0
+    gpu = _gpu_wos(gd, pts, walks, seed=13)
+    ora = OW.wos_nodes(OW.Geometry(gd), pts, walks, seed=13)
+    _compare(gpu, ora)
+    np.testing.assert_array_equal(gpu["capped"], ora["capped"])
+    # escaped at once: every walk scores 0 (to the rounding of the shifted
+    # sums); in the shell: phi at the plane point (to the last bit or so)
+    shift = abs(ora["mean"][1]) + 1.0
+    assert abs(gpu["mean"][0]) <= 1e-15 * shift and gpu["steps"][0] == 0
+    assert abs(gpu["mean"][2]) <= 1e-15 * shift and gpu["steps"][2] == 0
+    assert abs(gpu["mean"][1] - ora["mean"][1]) <= 4e-16 * abs(ora["mean"][1])
+    # the sphere does take walks away (constant data: mean = absorbed share)
+    if data == "constant":
+        assert np.mean(gpu["mean"][5:]) < 0.999
+
+
+def test_halfspace_fp32_mixed_statistical():
+    gd = _hs()
+    nodes = _above_plane(64, 2, r=0.2)
+    gpu = _gpu_wos(gd, nodes, 20_000, seed=3, precision="fp32")
+    ora = OW.wos_nodes(OW.Geometry(gd), nodes, 20_000, seed=3)
+    _compare(gpu, ora, exact_walks=False)
+    ratio = gpu["steps"].sum() / ora["steps"].sum()
+    assert 0.99 <= ratio <= 1.01, ratio
+
+
+def _points_case(rng, n):
+    x = np.column_stack([rng.uniform(-2, 2, (n, 2)), np.zeros(n)])
+    ang = rng.uniform(0, 2 * np.pi, n)
+    t1 = np.column_stack([np.cos(ang), np.sin(ang), np.zeros(n)])
+    nrm = np.tile(N_DOWN, (n, 1))
+    a = rng.uniform(0.05, 1.2, n)
+    return x, nrm, t1, a
+
+
+@pytest.mark.parametrize("ng1,ng2,drel", [(20, 20, 1e-6), (7, 13, 1e-3), (1, 1, 0.5), (64, 64, 1e-8)])
+def test_point_nodes_and_reduction_match_oracle(ng1, ng2, drel):
+    dtn = _dtn()
+    gd = _hs(src=np.array([[0.2, -0.1, -0.8, 1.0], [-0.7, 0.4, -1.3, -0.6]]))
+    g = dtn.Geometry(gd)
+    og = OW.Geometry(gd)
+    rng = np.random.default_rng(ng1 * 100 + ng2)
+    x, nrm, t1, a = _points_case(rng, 37)  # ragged over the 4 points per block
+    print(f"[gpu] points n=37 n_g1={ng1} n_g2={ng2}", flush=True)
+    P = dtn.Points(g, x, nrm, t1, a, n_g1=ng1, n_g2=ng2, delta_rel=drel)
+    nodes = P.nodes().cpu().numpy()
+    nn = ng1 * ng1
+    assert P.num_nodes == 37 * nn
+    # synthetic node statistics: counts (with 0 and 1), means, spreads
+    st = np.column_stack([rng.integers(0, 500, 37 * nn).astype(float), rng.normal(size=37 * nn),
+                          rng.uniform(0, 3, 37 * nn), np.zeros(37 * nn)])
+    out = P.neumann(torch.tensor(st, device="cuda")).cpu().numpy()
+    for i in range(37):
+        on, W = OPt.hemisphere_rule(x[i], nrm[i], t1[i], a[i], ng1)
+        np.testing.assert_allclose(nodes[i * nn:(i + 1) * nn], on, rtol=0, atol=1e-14)
+        want = OPt.point_neumann(og.phi, x[i], nrm[i], t1[i], a[i], ng1, ng2, drel, st[i * nn:(i + 1) * nn])
+        scale = np.sum(np.abs(W)) * (1 + np.max(np.abs(st[i * nn:(i + 1) * nn, 1])))
+        for k in range(4):
+            assert abs(out[i, k] - want[k]) <= 1e-12 * max(scale, abs(want[k])), (i, k, out[i, k], want[k])
+
+
+def test_point_on_box_face_with_quadratic_data():
+    dtn = _dtn()
+    gd = I.geometry_ball_quadratic()
+    gd = dict(gd, kind="box", box_lo=(0.0, 0.0, 0.0), box_hi=(1.0, 1.0, 1.0))
+    g = dtn.Geometry(gd)
+    og = OW.Geometry(gd)
+    x = np.array([[0.5, 0.5, 0.0], [0.3, 0.6, 1.0], [0.0, 0.4, 0.5]])
+    nrm = np.array([[0, 0, -1.0], [0, 0, 1.0], [-1.0, 0, 0]])
+    t1 = np.array([[1.0, 0, 0], [0, 1.0, 0], [0, 0, 1.0]])
+    a = np.array([0.2, 0.25, 0.3])
+    P = dtn.Points(g, x, nrm, t1, a, n_g1=12, n_g2=12, delta_rel=1e-6)
+    nodes = P.nodes()
+    W = torch.full((P.num_nodes,), 4000, dtype=torch.int64, device="cuda")
+    stats, capped = dtn.wos_eval(g, nodes, W, 5)
+    out = P.neumann(stats).cpu().numpy()
+    nn = 144
+    # the oracle walks from its own nodes (equal to the GPU's to rounding)
+    onodes = np.concatenate([OPt.hemisphere_rule(x[i], nrm[i], t1[i], a[i], 12)[0] for i in range(3)])
+    np.testing.assert_allclose(nodes.cpu().numpy(), onodes, rtol=0, atol=1e-14)
+    ora = OW.wos_nodes(og, onodes, 4000, seed=5)
+    ost = np.column_stack([ora["count"], ora["mean"], ora["m2"], ora["steps"]])
+    for i in range(3):
+        want = OPt.point_neumann(og.phi, x[i], nrm[i], t1[i], a[i], 12, 12, 1e-6, ost[i * nn:(i + 1) * nn])
+        assert abs(out[i, 0] - want[0]) < 0.2 * want[1] + 1e-12, (i, out[i], want)
+        assert abs(out[i, 3] - want[3]) < 1e-13
+    # exact du/dn of u = z + x^2 - y^2 with the outward normal
+    grad = lambda p: np.array([2 * p[0], -2 * p[1], 1.0])
+    for i in range(3):
+        ex = grad(x[i]) @ nrm[i]
+        assert abs(out[i, 0] - ex) < 4 * out[i, 1] + 2e-3, (i, out[i], ex)
+
+
+def test_table1_on_the_gpu():
+    dtn = _dtn()
+    gd = _hs()
+    g = dtn.Geometry(gd)
+    og = OW.Geometry(gd)
+    radii = np.array([0.1, 0.2, 0.5, 0.7, 1.0])
+    n = len(radii)
+    x = np.tile(X0, (n, 1))
+    P = dtn.Points(g, x, np.tile(N_DOWN, (n, 1)), np.tile(T1, (n, 1)), radii, n_g1=20, n_g2=20, delta_rel=1e-6)
+    nodes = P.nodes()
+    W = torch.full((P.num_nodes,), 1000, dtype=torch.int64, device="cuda")
+    print("[gpu] table 1: 5 points x 400 nodes x 1000 walks", flush=True)
+    stats, capped = dtn.wos_eval(g, nodes, W, 7)
+    out = P.neumann(stats).cpu().numpy()
+    assert int(capped.sum().item()) == 0
+    onodes = np.concatenate([OPt.hemisphere_rule(X0, N_DOWN, T1, a, 20)[0] for a in radii])
+    np.testing.assert_allclose(nodes.cpu().numpy(), onodes, rtol=0, atol=1e-14)
+    ora = OW.wos_nodes(og, onodes, 1000, seed=7)
+    ost = np.column_stack([ora["count"], ora["mean"], ora["m2"], ora["steps"]])
+    table_s2 = [0.018777, 0.037515, 0.093054, 0.128971, 0.179973]
+    for i, a in enumerate(radii):
+        want = OPt.point_neumann(og.phi, X0, N_DOWN, T1, a, 20, 20, 1e-6, ost[i * 400:(i + 1) * 400])
+        # same walks on both sides: far inside the statistical bar
+        assert abs(out[i, 0] - want[0]) < 0.05 * want[1], (a, out[i], want)
+        assert abs(out[i, 1] - want[1]) < 0.05 * want[1]
+        assert abs(out[i, 3] - table_s2[i]) <= 5e-7
+        assert abs(out[i, 0] - EXACT_T1) < 4 * out[i, 1], (a, out[i])
+
+
+def test_points_reject_bad_input():
+    dtn = _dtn()
+    g = dtn.Geometry(_hs())
+    ok = dict(x=[X0], normals=[N_DOWN], t1=[T1], a=[0.5])
+
+    def bad(**kw):
+        d = dict(ok, **kw)
+        with pytest.raises(dtn.DtnError):
+            dtn.Points(g, d["x"], d["normals"], d["t1"], d["a"], **{k: v for k, v in kw.items()
+                                                                    if k in ("n_g1", "n_g2", "delta_rel")})
+
+    bad(x=[(0.5, 0.0, 0.1)])                # off the plane
+    bad(normals=[(0.0, 0.0, 1.0)])          # inward normal
+    bad(t1=[(0.0, 0.0, 1.0)])               # tangent along the normal
+    bad(a=[0.0])
+    bad(x=[(99_999.8, 0.0, 0.0)])           # hemisphere reaches the truncation sphere
+    bad(n_g1=0)
+    bad(n_g2=65)
+    bad(delta_rel=1.0)
+    ball = dtn.Geometry(I.geometry_ball_quadratic())
+    with pytest.raises(dtn.DtnError):
+        dtn.Points(ball, [(0.0, 0.0, 1.0)], [(0.0, 0.0, 1.0)], [T1], [0.2])
+    cube = dtn.Geometry(I.geometry_cube_sources())
+    with pytest.raises(dtn.DtnError):      # disk does not fit in the face
+        dtn.Points(cube, [(0.05, 0.5, 0.0)], [N_DOWN], [T1], [0.2])
+    with pytest.raises(dtn.DtnError):      # patch plans need a bounded domain
+        dtn.Plan(g, I.patches_cube_tiles(m=1))
+    with pytest.raises(dtn.DtnError):      # sources must lie below the plane
+        dtn.Geometry(_hs(src=np.array([[0.0, 0.0, 0.5, 1.0]])))
