@@ -62,6 +62,16 @@ STEP_OPS = {
 # projection, 8 sources (sub, FMA, rsq + two Newton steps each), shift,
 # two compensated adds, square, counters
 WALK_OPS = {"f64": 52, "f64fma": 72, "rsq64": 8, "i32": 8}
+# Half space with the truncation sphere: the distance is z itself (no work);
+# the sphere test (3 differences, a product, 2 FMAs, a compare) replaces the
+# 11 operations of the box distance; the rest of the step is the box's.  Per
+# walk: one source (differences, square, rsq + two Newton steps, the scaled
+# add), the shift and the compensated sums.
+HS_STEP_OPS = {
+    "fp64": {"f64": 27 - 11 + 5, "f64fma": 17 + 2, "i32": 16, "mad64": 10, "cvt": 2, "rsq64": 1},
+    "fp32": {"f64": 13 - 11 + 5, "f64fma": 3 + 2, "f32": 8, "trans32": 3, "cvt": 3, "i32": 15, "mad64": 10},
+}
+HS_WALK_OPS = {"f64": 10, "f64fma": 9, "rsq64": 1, "i32": 8}
 
 
 def slots(ops):
@@ -70,6 +80,8 @@ def slots(ops):
 
 SLOTS_PER_STEP = {k: slots(v) for k, v in STEP_OPS.items()}
 SLOTS_PER_WALK = slots(WALK_OPS)
+HS_SLOTS_PER_STEP = {k: slots(v) for k, v in HS_STEP_OPS.items()}
+HS_SLOTS_PER_WALK = slots(HS_WALK_OPS)
 
 # HBM traffic of the walk kernel on the unit-cube workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs, each scaled by the same counter on a plain
@@ -81,6 +93,66 @@ TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_am
                       "636be46c3c3fa5e81b358641ad3e7a82ad3a084e4f03e4dd0cd47bee3fc3ee35",
                       "0eb5bfa94f8b9bc0c04b0ca22c7c7b33abc91770a9c5511a852c88858976a8fa"],
            "fetch_bytes": 71757.75 * 1024 * (262144 / 131089.625), "write_bytes": 43008.0 * 1024 * 1.00}
+
+
+# ------------------------------------------------- exact data, panel layout
+# The accuracy figures compare the library's output with the exact solution
+# of the synthetic problems (closed forms of their harmonic data), at the
+# collocation points of the panel layout that include/dtn.h documents for
+# plane patches: n_rings uniform rings x n_sectors sectors of the disk of
+# radius h, ring-major, collocation at the parametric centres.
+
+
+def exact_grad(gd, x):
+    """Gradient of the harmonic extension of the Dirichlet data."""
+    x = np.asarray(x, dtype=np.float64).reshape(-1, 3)
+    if gd["data_kind"] == "quadratic":
+        c = gd["quad"]
+        X, Y, Z = x[:, 0], x[:, 1], x[:, 2]
+        return np.stack([c[1] + 2 * c[4] * X + c[7] * Y + c[9] * Z,
+                         c[2] + 2 * c[5] * Y + c[7] * X + c[8] * Z,
+                         c[3] + 2 * c[6] * Z + c[8] * Y + c[9] * X], axis=-1)
+    g = np.zeros_like(x)
+    for q in np.asarray(gd["src"]).reshape(-1, 4):
+        d = x - q[:3]
+        g -= q[3] * d / np.linalg.norm(d, axis=-1)[:, None] ** 3
+    return g
+
+
+def exact_u(gd, x):
+    x = np.asarray(x, dtype=np.float64).reshape(-1, 3)
+    if gd["data_kind"] == "quadratic":
+        c = gd["quad"]
+        X, Y, Z = x[:, 0], x[:, 1], x[:, 2]
+        return (c[0] + c[1] * X + c[2] * Y + c[3] * Z + c[4] * X * X + c[5] * Y * Y + c[6] * Z * Z
+                + c[7] * X * Y + c[8] * Y * Z + c[9] * X * Z)
+    return sum(q[3] / np.linalg.norm(x - q[:3], axis=-1) for q in np.asarray(gd["src"]).reshape(-1, 4))
+
+
+def plane_panels(pd):
+    """Collocation points, outward normals, areas and centre distances of the
+    panels of plane patches, patch-major as the solve returns them."""
+    X, N, A, R = [], [], [], []
+    for i in range(len(pd["h"])):
+        c, n, t1, h = (np.asarray(pd[k][i], np.float64) for k in ("c", "n", "t1", "h"))
+        t2 = np.cross(n, t1)
+        nr, ns = int(pd["n_rings"][i]), int(pd["n_sectors"][i])
+        se = h * np.arange(nr + 1) / nr
+        ae = 2 * np.pi * np.arange(ns + 1) / ns
+        s0, s1 = np.repeat(se[:-1], ns), np.repeat(se[1:], ns)
+        a0, a1 = np.tile(ae[:-1], nr), np.tile(ae[1:], nr)
+        sc, ac = 0.5 * (s0 + s1), 0.5 * (a0 + a1)
+        X.append(c + (sc * np.cos(ac))[:, None] * t1 + (sc * np.sin(ac))[:, None] * t2)
+        N.append(np.tile(n, (nr * ns, 1)))
+        A.append(0.5 * (s1 ** 2 - s0 ** 2) * (a1 - a0))
+        R.append(sc)
+    return np.concatenate(X), np.concatenate(N), np.concatenate(A), np.concatenate(R)
+
+
+def rel_l2(sigma, exact, area, mask):
+    """Area-weighted relative L2 error over the panels in ``mask``."""
+    return float(np.sqrt(np.sum(area[mask] * (sigma[mask] - exact[mask]) ** 2)
+                         / np.sum(area[mask] * exact[mask] ** 2)))
 
 
 def traffic_if_current():
@@ -114,7 +186,8 @@ def parse():
     ap.add_argument("--serving-se-range", type=float, nargs=2, default=[1e-4, 1e-2],
                     help="range of the per-query required node standard error (log-uniform)")
     ap.add_argument("--serving-rate", type=float, default=200.0, help="offered load, queries/s")
-    ap.add_argument("--only", choices=["cube", "box_holes", "serving"], default=None,
+    ap.add_argument("--no-halfspace", action="store_true", help="skip the single-point half-space workload")
+    ap.add_argument("--only", choices=["cube", "box_holes", "serving", "halfspace"], default=None,
                     help="run one workload only (for profiling)")
     ap.add_argument("--box-holes-se", type=float, default=None,
                     help="target standard error of the uneven-batching workload (default: its 1e-3)")
@@ -223,19 +296,15 @@ def box_holes(precision, steps, with_cpu=True, se_target=None, tune=True, with_f
     free = (u > cfg["min_walks"]) & (u < cfg["max_walks"])
     sec = float(np.mean(times))
     # exact Neumann data at the collocation points (sources inside the holes)
-    from oracle import patch as OP
-    ex, area, tr = [], [], []
-    for q in OP.patches_from_desc(pd, gd):
-        xg, ng, ar, r = OP.collocation_points(q)
-        ex.append(OP.exact_neumann(gd, xg, ng))
-        area.append(ar)
-        tr.append(r < 0.7 * q.h)
-    ex, area, tr = map(np.concatenate, (ex, area, tr))
+    xg, ng, area, rc = plane_panels(pd)
+    ex = np.sum(exact_grad(gd, xg) * ng, axis=-1)
+    tr = rc < 0.7 * np.repeat(np.asarray(pd["h"], np.float64),
+                              np.asarray(pd["n_rings"]) * np.asarray(pd["n_sectors"]))
 
     def errors(neumann, neumann_se):
         sig, sse = neumann.cpu().numpy(), neumann_se.cpu().numpy()
         noise = float(np.sqrt(np.sum(area[tr] * sse[tr] ** 2) / np.sum(area[tr] * ex[tr] ** 2)))
-        return OP.rel_l2(sig, ex, area, tr), noise
+        return rel_l2(sig, ex, area, tr), noise
 
     err, noise = errors(neu, nse)
     fp64 = None
@@ -255,20 +324,7 @@ def box_holes(precision, steps, with_cpu=True, se_target=None, tune=True, with_f
         fp64 = {"seconds_per_step": sec64, "walks": w64, "walks_per_s": w64 / sec64,
                 "patches_per_s": len(pd["h"]) / sec64, "neumann_rel_l2_vs_exact": e64,
                 "propagated_noise_rel_l2": noise64, "patches_per_s_ratio": sec64 / sec}
-    cpu = None
-    if with_cpu:
-        # the oracle's adaptive walks (FP64) on 64 seeded nodes of patches of every class
-        from oracle import patch as OP
-        from oracle import wos as OW
-        idx = I.box_holes_sample(pd, per_class=2, seed=cfg["seed"])
-        X = np.concatenate([OP.nodes_global(q)[0] for q in OP.patches_from_desc(I.subset_patches(pd, idx), gd)])
-        X = X[np.random.default_rng(cfg["seed"]).choice(len(X), 64, replace=False)]
-        t0 = time.perf_counter()
-        r = OW.wos_adaptive(OW.Geometry(gd), X, *budget[:3], budget[3], seed=cfg["seed"])
-        dt = time.perf_counter() - t0
-        cpu = {"value": float(r["count"].sum()) / dt, "unit": "walks/s", "cores": OW.max_threads(), "kind": "oracle",
-               "sample": f"64 nodes of {len(idx)} patches (2 per panel class), adaptive walks "
-                         f"({int(r['count'].sum())} walks, {int(r['steps'].sum())} steps) in {dt:.1f} s"}
+    cpu = box_holes_cpu_baseline(gd, pd, cfg, budget) if with_cpu else None
     return {"workload": f"box [0,4]^3 minus 20 holes, {len(pd['h'])} patches (8..128 panels), {N} nodes, "
                         f"adaptive {cfg['min_walks']}..{cfg['max_walks']} walks/node at SE {se_t}",
             "precision": precision, "seconds_per_step": sec, "walks": float(u.sum()),
@@ -279,6 +335,136 @@ def box_holes(precision, steps, with_cpu=True, se_target=None, tune=True, with_f
             "neumann_rel_l2_vs_exact": err, "propagated_noise_rel_l2": noise,
             "capped_walks": int(capped.sum().item()), "schedule": sched, "schedule_ms": table,
             "plain_fp64": fp64, "cpu_baseline": cpu}
+
+
+def box_holes_cpu_baseline(gd, pd, cfg, budget):
+    """CPU baseline of the box-with-holes workload: the oracle's adaptive
+    walks (FP64) on 64 seeded nodes of patches of every panel class."""
+    import dtn_inputs as I
+    from oracle import patch as OP
+    from oracle import wos as OW
+    idx = I.box_holes_sample(pd, per_class=2, seed=cfg["seed"])
+    X = np.concatenate([OP.nodes_global(q)[0] for q in OP.patches_from_desc(I.subset_patches(pd, idx), gd)])
+    X = X[np.random.default_rng(cfg["seed"]).choice(len(X), 64, replace=False)]
+    t0 = time.perf_counter()
+    r = OW.wos_adaptive(OW.Geometry(gd), X, *budget[:3], budget[3], seed=cfg["seed"])
+    dt = time.perf_counter() - t0
+    return {"value": float(r["count"].sum()) / dt, "unit": "walks/s", "cores": OW.max_threads(), "kind": "oracle",
+            "sample": f"64 nodes of {len(idx)} patches (2 per panel class), adaptive walks "
+                      f"({int(r['count'].sum())} walks, {int(r['steps'].sum())} steps) in {dt:.1f} s"}
+
+
+def halfspace_points(precision, steps, warmup, with_cpu=True, cpu_points=128):
+    """Single-point Neumann data on a flat boundary (Sec. 5.1), Test 1 scaled
+    to many points: the half space z > 0 over a unit charge at (0, 0, -1),
+    truncation sphere 1e5, eps 1e-5; 4096 points uniform in the disk of
+    radius 2 on z = 0 with a = 0.1 .. 1.0 (Table 1's radii), 20 x 20
+    hemisphere nodes x 1e3 walks each (Table 1's rule), Sigma2' by 20 x 20 on
+    the ring with delta/a = 1e-6.  A step: nodes, walks, Sigma1' + Sigma2'.
+    Accuracy against the exact -du/dz; Table 1 itself (x = (0.5, 0, 0), the
+    five radii) from one more call; the oracle on a bounded sample with the
+    same seeds and stream ids (so the GPU's values for those points are
+    compared with the oracle's)."""
+    import torch
+
+    import dtn_inputs as I
+    from paper_1210_1491_amd import dtn
+
+    cfg = I.CONFIGS["halfspace_points"]
+    gd = cfg["geometry"]()
+    g = dtn.Geometry(gd)
+    x, nrm, t1, a = cfg["points"](cfg["n_points"], cfg["seed"])
+    P = dtn.Points(g, x, nrm, t1, a, cfg["n_g1"], cfg["n_g2"], cfg["delta_rel"])
+    N = P.num_nodes
+    nodes = torch.empty((N, 3), dtype=torch.float64, device="cuda")
+    stats = torch.empty((N, 4), dtype=torch.float64, device="cuda")
+    capped = torch.empty(N, dtype=torch.int64, device="cuda")
+    out = torch.empty((len(a), 4), dtype=torch.float64, device="cuda")
+    walks = torch.full((N,), cfg["walks"], dtype=torch.int64, device="cuda")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    seed = cfg["seed"]
+
+    def step(record):
+        P.nodes(out=nodes)
+        if record:
+            ev0.record()
+        dtn.wos_eval(g, nodes, walks, seed, precision=precision, stats=stats, capped=capped)
+        if record:
+            ev1.record()
+        P.neumann(stats, out=out)
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    wos_ms = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+        torch.cuda.synchronize()
+        wos_ms.append(ev0.elapsed_time(ev1))
+    sec = (time.perf_counter() - t0) / steps
+    print(f"[bench] halfspace points {precision}: {sec * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+    st = stats.cpu().numpy()
+    o = out.cpu().numpy()
+    walks_n, steps_n = float(st[:, 0].sum()), float(st[:, 3].sum())
+    wos_s = float(np.mean(wos_ms)) / 1e3
+    achieved = (HS_SLOTS_PER_STEP[precision] * steps_n + HS_SLOTS_PER_WALK * walks_n) / wos_s
+    exact = np.sum(exact_grad(gd, x) * nrm, axis=-1)
+    z = (o[:, 0] - exact) / o[:, 1]
+    res = {"workload": f"half space over a unit charge, {len(a)} points x {cfg['n_g1']}x{cfg['n_g1']} nodes x "
+                       f"{cfg['walks']} walks, a in 0.1..1.0, ring rule {cfg['n_g2']}x{cfg['n_g2']}, "
+                       f"truncation 1e5, eps 1e-5",
+           "precision": precision, "ms_per_step": sec * 1e3, "points_per_s": len(a) / sec,
+           "walks_per_s": walks_n / sec, "walk_steps_per_s": steps_n / sec, "steps_per_walk": steps_n / walks_n,
+           "wos_kernel_ms": float(np.mean(wos_ms)), "capped_walks": int(capped.sum().item()),
+           "rel_l2_vs_exact": float(np.linalg.norm(o[:, 0] - exact) / np.linalg.norm(exact)),
+           "se_rel_l2": float(np.linalg.norm(o[:, 1]) / np.linalg.norm(exact)),
+           "mean_abs_z": float(np.mean(np.abs(z))), "share_within_3_se": float(np.mean(np.abs(z) < 3)),
+           "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK / 1e12,
+                        "unit": "T lane-op slots/s", "frac": achieved / ALU_PEAK,
+                        "slots_per_step": HS_SLOTS_PER_STEP[precision], "slots_per_walk": HS_SLOTS_PER_WALK}}
+    # Table 1: x = (0.5, 0, 0), the five radii, 20 x 20 nodes x 1e3 walks
+    radii = np.array([0.1, 0.2, 0.5, 0.7, 1.0])
+    T = dtn.Points(g, np.tile([0.5, 0.0, 0.0], (5, 1)), np.tile([0.0, 0.0, -1.0], (5, 1)),
+                   np.tile([1.0, 0.0, 0.0], (5, 1)), radii, 20, 20, 1e-6)
+    tn = T.nodes()
+    ts, _ = dtn.wos_eval(g, tn, torch.full((T.num_nodes,), 1000, dtype=torch.int64, device="cuda"), 7,
+                         precision=precision)
+    to = T.neumann(ts).cpu().numpy()
+    ex1 = 1.0 / 1.25 ** 1.5
+    res["table1"] = {"a": radii.tolist(), "sigma1": to[:, 2].tolist(), "sigma2": to[:, 3].tolist(),
+                     "total": to[:, 0].tolist(), "se": to[:, 1].tolist(),
+                     "err_pct": (100 * (to[:, 0] - ex1) / ex1).tolist(), "analytic": ex1}
+    if with_cpu:
+        res["cpu_baseline"] = halfspace_cpu_baseline(gd, x, nrm, t1, a, cfg, o, cpu_points)
+    return res
+
+
+def halfspace_cpu_baseline(gd, x, nrm, t1, a, cfg, gpu_out, n_sample):
+    """CPU baseline of the half-space point workload: the oracle on the first
+    n_sample points with the stream ids the GPU run gave their nodes (node
+    index), so the oracle's walks are the GPU's (FP64) and the values of the
+    sampled points can be compared one by one."""
+    from oracle import point as OPt
+    from oracle import wos as OW
+    og = OW.Geometry(gd)
+    nn = cfg["n_g1"] ** 2
+    nodes = np.concatenate([OPt.hemisphere_rule(x[i], nrm[i], t1[i], a[i], cfg["n_g1"])[0] for i in range(n_sample)])
+    sid = np.arange(n_sample * nn, dtype=np.uint32)
+    t0 = time.perf_counter()
+    r = OW.wos_nodes(og, nodes, cfg["walks"], seed=cfg["seed"], stream_id=sid)
+    dt = time.perf_counter() - t0
+    st = np.column_stack([r["count"], r["mean"], r["m2"], r["steps"]])
+    want = np.array([OPt.point_neumann(og.phi, x[i], nrm[i], t1[i], a[i], cfg["n_g1"], cfg["n_g2"],
+                                       cfg["delta_rel"], st[i * nn:(i + 1) * nn]) for i in range(n_sample)])
+    d = np.abs(gpu_out[:n_sample, 0] - want[:, 0]) / want[:, 1]
+    walks = float(r["count"].sum())
+    return {"value": n_sample / dt, "unit": "points/s", "cores": OW.max_threads(), "kind": "oracle",
+            "sample": f"first {n_sample} points ({walks:.3g} walks, {int(r['steps'].sum())} steps) in {dt:.1f} s",
+            "walks_per_s": walks / dt,
+            "gpu_same_sample": {"max_diff_in_se": float(d.max()),
+                                "max_rel_diff": float(np.max(np.abs(gpu_out[:n_sample, 0] - want[:, 0])
+                                                             / np.abs(want[:, 0])))}}
 
 
 def serving(precision, window, rate, se_range, sweep_fraction=0.5, sweep_window=6):
@@ -426,19 +612,13 @@ def main():
     neumann = torch.empty(Pn, dtype=torch.float64, device=dev)
     neumann_se = torch.empty(Pn, dtype=torch.float64, device=dev)
     u = torch.empty(targets.shape[0], dtype=torch.float64, device=dev)
-    from oracle import patch as OP  # exact data and panel geometry only
-    from oracle import wos as OW
-
-    ps = OP.patches_from_desc(pd, gd)
-    ex, area, trusted = [], [], []
-    for p in ps:
-        xg, ng, ar, r = OP.collocation_points(p)
-        ex.append(OP.exact_neumann(gd, xg, ng))
-        area.append(ar)
-        trusted.append(r < 0.7 * p.h)
-    ex, area, trusted = map(np.concatenate, (ex, area, trusted))
+    xg, ng, area, rc = plane_panels(pd)
+    ex = np.sum(exact_grad(gd, xg) * ng, axis=-1)
+    trusted = rc < 0.7 * np.repeat(np.asarray(pd["h"], np.float64),
+                                   np.asarray(pd["n_rings"]) * np.asarray(pd["n_sectors"]))
+    n_patches = len(pd["h"])
     tg = targets.cpu().numpy()
-    u_ex = OW.Geometry(gd).phi(tg)
+    u_ex = exact_u(gd, tg)
     far = np.min(np.minimum(tg, 1 - tg), axis=1) >= 1.0 / 8
 
     if args.copy_probe_mib > 0:
@@ -481,10 +661,10 @@ def main():
         n2, s2 = torch.empty_like(neumann), torch.empty_like(neumann_se)
         plan.solve(stats, precision=other, neumann=n2, neumann_se=s2)
         sig2 = n2.cpu().numpy()
-        solves = {precision: OP.rel_l2(sig, ex, area, trusted), other: OP.rel_l2(sig2, ex, area, trusted),
+        solves = {precision: rel_l2(sig, ex, area, trusted), other: rel_l2(sig2, ex, area, trusted),
                   "max_abs_diff_fp32_vs_fp64_solve": float(np.max(np.abs(sig2 - sig)))}
-        return {"ms_per_step": ms, "rel_l2_by_solve_precision": solves, "walks_per_s": walks_n / (ms / 1e3), "patches_per_s": len(ps) / (ms / 1e3),
-                "neumann_rel_l2_vs_exact": OP.rel_l2(sig, ex, area, trusted),
+        return {"ms_per_step": ms, "rel_l2_by_solve_precision": solves, "walks_per_s": walks_n / (ms / 1e3), "patches_per_s": n_patches / (ms / 1e3),
+                "neumann_rel_l2_vs_exact": rel_l2(sig, ex, area, trusted),
                 "neumann_se_median": float(np.median(neumann_se.cpu().numpy())),
                 "potential_max_err_far": float(np.max(np.abs(u.cpu().numpy()[far] - u_ex[far]))
                                                / np.sqrt(np.mean(u_ex ** 2))),
@@ -502,6 +682,10 @@ def main():
     if args.only == "serving":
         print(json.dumps({"serving": serving("fp32", args.serving_window, args.serving_rate, args.serving_se_range,
                                              sweep_window=args.serving_sweep_window)}), flush=True)
+        return
+    if args.only == "halfspace":
+        print(json.dumps({"halfspace_points": halfspace_points(args.precision, args.steps, args.warmup,
+                                                               not args.no_cpu_baseline)}), flush=True)
         return
     m = measure(args.precision, args.steps, args.warmup)
     variants = {}
@@ -525,7 +709,7 @@ def main():
                 plan.nodes(out=nodes)
                 dtn.wos_eval(g, nodes, walks, seed=2, precision=prec, stats=stats, capped=capped)
                 plan.solve(stats, precision=prec, neumann=neumann, neumann_se=neumann_se)
-                curve[prec].append(OP.rel_l2(neumann.cpu().numpy(), ex, area, trusted))
+                curve[prec].append(rel_l2(neumann.cpu().numpy(), ex, area, trusted))
             curve[prec].append(full[prec])
         walks.fill_(args.walks)
     ms_per_step = m["ms_per_step"]
@@ -544,9 +728,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"unit cube, {6 * args.tiles ** 2} patches x {N // len(ps)} nodes x {args.walks} walks, "
+        "config": {"workload": f"unit cube, {6 * args.tiles ** 2} patches x {N // n_patches} nodes x {args.walks} walks, "
                                f"eps 1e-5, 8 point sources, 64 panels, 1e4 potential targets",
-                   "patches": len(ps), "nodes": N, "walks_per_node": args.walks, "precision": args.precision},
+                   "patches": n_patches, "nodes": N, "walks_per_node": args.walks, "precision": args.precision},
         "patches_per_s": m["patches_per_s"],
         "neumann_rel_l2_vs_exact": m["neumann_rel_l2_vs_exact"],
         "rel_l2_by_solve_precision": m["rel_l2_by_solve_precision"],
@@ -565,6 +749,8 @@ def main():
     }
     if args.only is None and not args.no_box_holes:
         line["box_holes"] = box_holes("fp32", 1, not args.no_cpu_baseline, with_fp64=not args.no_variants)
+    if args.only is None and not args.no_halfspace:
+        line["halfspace_points"] = halfspace_points("fp64", 1, 1, not args.no_cpu_baseline)
     if args.only is None and not args.no_serving:
         line["serving"] = serving("fp32", args.serving_window, args.serving_rate, args.serving_se_range,
                                   sweep_window=args.serving_sweep_window)

@@ -123,3 +123,13 @@ def point_neumann(phi, x, n, t1, a, n_g1, n_g2, delta_rel, node_stats):
     var = np.where(cnt > 1, st[:, 2] / np.maximum(cnt - 1, 1), 0.0)
     se = np.sqrt(np.sum(W * W * np.where(cnt > 0, var / np.maximum(cnt, 1), 0.0)))
     return s1 + s2, se, s1, s2
+
+
+def sigma2_rounding_bound(phi, x, n, t1, a, n_g2, delta_rel, ulps=4):
+    """Size of the FP64 rounding error of Sigma2': each term's phi(y) - phi(x)
+    carries an absolute error of about 2 ulps of each phi value, times the ring
+    weight (1/rho^3 - 1/a^3) rho, which is large next to the excluded disk.
+    Two FP64 evaluations of the rule may differ by this much."""
+    pts, W, rho = ring_rule(x, n, t1, a, n_g2, delta_rel)
+    f = np.abs(phi(pts)) + abs(phi(np.asarray(x, dtype=np.float64)[None, :])[0])
+    return ulps * np.finfo(np.float64).eps * np.sum(np.abs(W * (1.0 / rho ** 3 - 1.0 / a ** 3)) * f) / (2.0 * np.pi)

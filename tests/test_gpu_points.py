@@ -148,7 +148,7 @@ def test_point_on_box_face_with_quadratic_data():
     for i in range(3):
         want = OPt.point_neumann(og.phi, x[i], nrm[i], t1[i], a[i], 12, 12, 1e-6, ost[i * nn:(i + 1) * nn])
         assert abs(out[i, 0] - want[0]) < 0.2 * want[1] + 1e-12, (i, out[i], want)
-        assert abs(out[i, 3] - want[3]) < 1e-13
+        assert abs(out[i, 3] - want[3]) <= OPt.sigma2_rounding_bound(og.phi, x[i], nrm[i], t1[i], a[i], 12, 1e-6)
     # exact du/dn of u = z + x^2 - y^2 with the outward normal
     grad = lambda p: np.array([2 * p[0], -2 * p[1], 1.0])
     for i in range(3):
