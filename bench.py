@@ -89,10 +89,14 @@ HS_SLOTS_PER_WALK = slots(HS_WALK_OPS)
 # the kernel sources it was measured on (SHA-256 of these files).
 TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_amd/csrc/dtn_device.h",
                      "paper_1210_1491_amd/csrc/dtn_internal.h"],
-           "sha256": ["26d8366947baede436435ebd9a74e5ad8b185f434be47fa8ae15b5f1ba2c8ffc",
-                      "636be46c3c3fa5e81b358641ad3e7a82ad3a084e4f03e4dd0cd47bee3fc3ee35",
-                      "0eb5bfa94f8b9bc0c04b0ca22c7c7b33abc91770a9c5511a852c88858976a8fa"],
-           "fetch_bytes": 71757.75 * 1024 * (262144 / 131089.625), "write_bytes": 43008.0 * 1024 * 1.00}
+           "sha256": ["7a3871db29b4d09447a52ac3ab474bebb1d1793c055867bccd516d9bcefecb00",
+                      "09999af31f8be484fd7e3112965b250101a27799e11420efc7bf44e5f1df9f98",
+                      "d85a513da41eda0ddb131a768130f224b4afe53d6af419ad7c4985e12fcec4a6"],
+           "fetch_bytes": 71756.75 * 1024 * (262144 / 131089.125), "write_bytes": 43008.0 * 1024 * 1.00,
+           # the half-space point workload's walk kernel (same sources), scaled
+           # by the copy in its own run (fetch 131086.438 KiB for 262144)
+           "halfspace_fetch_bytes": 156232.625 * 1024 * (262144 / 131086.438),
+           "halfspace_write_bytes": 89600.0 * 1024 * 1.00}
 
 
 # ------------------------------------------------- exact data, panel layout
@@ -163,6 +167,12 @@ def traffic_if_current():
             if hashlib.sha256(fh.read()).hexdigest() != h:
                 return None
     return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+
+
+def halfspace_traffic_if_current():
+    if traffic_if_current() is None:
+        return None
+    return TRAFFIC["halfspace_fetch_bytes"] + TRAFFIC["halfspace_write_bytes"]
 
 
 def parse():
@@ -422,6 +432,7 @@ def halfspace_points(precision, steps, warmup, with_cpu=True, cpu_points=128):
            "mean_abs_z": float(np.mean(np.abs(z))), "share_within_3_se": float(np.mean(np.abs(z) < 3)),
            "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK / 1e12,
                         "unit": "T lane-op slots/s", "frac": achieved / ALU_PEAK,
+                        "traffic": halfspace_traffic_if_current() if precision == "fp64" else None,
                         "slots_per_step": HS_SLOTS_PER_STEP[precision], "slots_per_walk": HS_SLOTS_PER_WALK}}
     # Table 1: x = (0.5, 0, 0), the five radii, 20 x 20 nodes x 1e3 walks
     radii = np.array([0.1, 0.2, 0.5, 0.7, 1.0])
