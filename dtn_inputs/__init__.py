@@ -60,6 +60,21 @@ def geometry_halfspace_charge(h=1.0, trunc_r=1e5, eps=1e-5, max_steps=1_000_000)
             "holes": np.zeros((0, 6)), "eps": eps, "max_steps": max_steps}
 
 
+def geometry_disk(b=1.0, trunc_r=1e5, eps=1e-5, max_steps=1_000_000):
+    """Exterior of a thin conducting disk {z = 0, x^2 + y^2 <= b^2} held at
+    u = 1, with u -> 0 at infinity (Sec. 5.1.3, Test 4, eq. bw95 with Q = 8b);
+    walks that reach the sphere |x| = trunc_r count as gone to infinity."""
+    return {"kind": "disk", "disk_r": float(b), "ball_c": (0.0, 0.0, 0.0), "ball_r": float(trunc_r),
+            "data_kind": "quadratic", "quad": [1.0] + [0.0] * 9, "src": np.zeros((0, 4)),
+            "holes": np.zeros((0, 6)), "eps": eps, "max_steps": max_steps}
+
+
+# Test 4's point and hemisphere (Sec. 5.1.3) and Table 5's three rules:
+# (N_g1, paths per node).
+DISK_POINT = {"x": (-0.5, 0.0, 0.0), "n": (0.0, 0.0, -1.0), "t1": (1.0, 0.0, 0.0), "a": 0.4}
+TABLE5_RULES = [(10, 100), (10, 1000), (20, 1000)]
+
+
 def halfspace_points(n, seed=6, radii=(0.1, 0.2, 0.5, 0.7, 1.0), extent=2.0):
     """Single-point queries on the plane z = 0: points uniform in the disk of
     radius ``extent`` around the origin, hemisphere radius cycling through

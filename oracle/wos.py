@@ -51,10 +51,11 @@ class OgGeom(C.Structure):
         ("quad", C.c_double * 10),
         ("eps", C.c_double),
         ("max_steps", C.c_int64),
+        ("disk_r", C.c_double),
     ]
 
 
-KIND = {"ball": 0, "box": 1, "box_minus_boxes": 2, "half_space": 3}
+KIND = {"ball": 0, "box": 1, "box_minus_boxes": 2, "half_space": 3, "disk": 4}
 
 
 def _dptr(a):
@@ -98,6 +99,7 @@ class Geometry:
             g.quad[k] = float(q[k])
         g.eps = float(desc["eps"])
         g.max_steps = int(desc["max_steps"])
+        g.disk_r = float(desc.get("disk_r", 0.0))
         self.g = g
 
     def ref(self):

@@ -38,7 +38,11 @@
  *     infinity (Sec. 5.1.3, the sphere of radius 1e5) and scores u = 0 there,
  *     the limit of data that decay at infinity.  The sphere is tested first at
  *     every position (start and after every jump), then the shell, then the
- *     step cap.
+ *     step cap;
+ *   - the exterior of a thin disk (Sec. 5.1.3, Test 4): all of space minus
+ *     the closed disk {z = 0, x^2 + y^2 <= disk_r^2}; the distance is that to
+ *     the disk, the closest point its projection, and the truncation sphere
+ *     applies as for the half space.
  *
  * Build: gcc -O2 -fopenmp -fPIC -shared wos_oracle.c -lm (see build.py).
  */
@@ -51,7 +55,7 @@
 
 /* ---------------------------------------------------------------- geometry */
 
-enum { OG_BALL = 0, OG_BOX = 1, OG_BOX_MINUS_BOXES = 2, OG_HALF_SPACE = 3 };
+enum { OG_BALL = 0, OG_BOX = 1, OG_BOX_MINUS_BOXES = 2, OG_HALF_SPACE = 3, OG_DISK = 4 };
 enum { OG_DATA_QUADRATIC = 0, OG_DATA_SOURCES = 1 };
 
 typedef struct {
@@ -68,6 +72,7 @@ typedef struct {
     double quad[10];     /* c0 + c.x + x^T A x, see og_phi  */
     double eps;
     int64_t max_steps;
+    double disk_r;       /* OG_DISK: radius of the disk in z = 0 */
 } og_geom;
 
 /* Dirichlet data phi(x).
@@ -99,6 +104,16 @@ double og_dist_proj(const og_geom *g, const double x[3], double p[3])
     if (g->kind == OG_HALF_SPACE) {
         if (p) { p[0] = x[0]; p[1] = x[1]; p[2] = 0.0; }
         return x[2];
+    }
+    if (g->kind == OG_DISK) {
+        double rho = sqrt(x[0] * x[0] + x[1] * x[1]);
+        if (rho <= g->disk_r) {
+            if (p) { p[0] = x[0]; p[1] = x[1]; p[2] = 0.0; }
+            return fabs(x[2]);
+        }
+        double e = rho - g->disk_r;
+        if (p) { p[0] = x[0] * (g->disk_r / rho); p[1] = x[1] * (g->disk_r / rho); p[2] = 0.0; }
+        return sqrt(e * e + x[2] * x[2]);
     }
     if (g->kind == OG_BALL) {
         double v[3] = {x[0] - g->ball_c[0], x[1] - g->ball_c[1], x[2] - g->ball_c[2]};
@@ -208,10 +223,10 @@ void og_direction(double u1, double u2, double w[3])
 
 /* --------------------------------------------------------------------- WOS */
 
-/* Has x left the truncation sphere of a half space (gone to infinity)? */
+/* Has x left the truncation sphere of an unbounded domain (gone to infinity)? */
 static int og_escaped(const og_geom *g, const double x[3])
 {
-    if (g->kind != OG_HALF_SPACE) return 0;
+    if (g->kind != OG_HALF_SPACE && g->kind != OG_DISK) return 0;
     double dx = x[0] - g->ball_c[0], dy = x[1] - g->ball_c[1], dz = x[2] - g->ball_c[2];
     return dx * dx + dy * dy + dz * dz >= g->ball_r * g->ball_r;
 }

@@ -250,3 +250,76 @@ def test_table1_reproduction_monte_carlo():
         assert abs(tot_paper - exact) < 4 * se, (a, tot_paper, se)
         assert abs(100 * (tot_paper - 0.71554) / 0.71554 - err_paper) < 0.02
         assert int(r["capped"].sum()) == 0
+
+
+# ------------------------------------------- exterior of a thin disk (Test 4)
+
+def _disk_u(x, b=1.0):
+    """Potential of a conducting disk of radius b at u = 1 (closed form in
+    oblate spheroidal coordinates): (2/pi) arcsin(2b / (r_+ + r_-)), r_+/-
+    the distances to the rim in the meridian plane."""
+    x = np.atleast_2d(x)
+    rho = np.hypot(x[:, 0], x[:, 1])
+    rp = np.sqrt((rho + b) ** 2 + x[:, 2] ** 2)
+    rm = np.sqrt((rho - b) ** 2 + x[:, 2] ** 2)
+    return 2.0 / np.pi * np.arcsin(np.minimum(1.0, 2.0 * b / (rp + rm)))
+
+
+def test_disk_potential_closed_form_is_the_disk_potential():
+    # 1 on the disk, ~ (2/pi) b / r far away (total charge 8 b, eq. bw95),
+    # harmonic off the disk (7-point Laplacian)
+    assert abs(_disk_u([[0.3, -0.2, 0.0]])[0] - 1.0) < 1e-15
+    far = np.array([[3e3, 1e3, 2e3]])
+    r = np.linalg.norm(far)
+    assert abs(_disk_u(far)[0] * r / (2.0 / np.pi) - 1.0) < 1e-6
+    h = 1e-3
+    for p in ([0.4, 0.1, 0.3], [1.3, -0.2, 0.05], [0.2, 0.2, -0.7]):
+        p = np.asarray(p)
+        lap = sum(_disk_u(p + h * e)[0] + _disk_u(p - h * e)[0] for e in np.eye(3)) - 6 * _disk_u(p)[0]
+        assert abs(lap / h ** 2) < 1e-4
+    # the density of eq. bw95 is -du/dz on the upper face
+    x0 = np.array([-0.5, 0.0, 0.0])
+    fd = (1.0 - _disk_u(x0 + [0, 0, 1e-6])[0]) / 1e-6
+    assert abs(fd - 8.0 / (4 * np.pi * np.sqrt(0.75))) < 1e-4
+
+
+def test_disk_distance_and_projection_brute_force():
+    g = wos.Geometry(I.geometry_disk())
+    rng = np.random.default_rng(8)
+    x = rng.uniform(-2, 2, (300, 3))
+    x[:50, 2] = rng.uniform(-1e-3, 1e-3, 50)  # next to the faces
+    d, p = g.dist_proj(x)
+    rr, tt = np.meshgrid(np.sqrt(np.linspace(0, 1, 400)), np.linspace(0, 2 * np.pi, 800, endpoint=False))
+    disk = np.column_stack([(rr * np.cos(tt)).ravel(), (rr * np.sin(tt)).ravel(), np.zeros(rr.size)])
+    for i in range(len(x)):
+        bd = np.min(np.linalg.norm(disk - x[i], axis=1))
+        assert d[i] <= bd + 1e-12 and bd - d[i] < 0.01
+        assert abs(np.linalg.norm(x[i] - p[i]) - d[i]) < 1e-13
+        assert p[i, 2] == 0.0 and np.hypot(p[i, 0], p[i, 1]) <= 1.0 + 1e-15
+
+
+def test_disk_walks_match_the_disk_potential():
+    g = wos.Geometry(I.geometry_disk())
+    y = np.array([[-0.5, 0.0, 0.2], [0.9, 0.3, -0.1], [1.5, 0.0, 0.0], [0.0, 0.0, 2.0]])
+    r = wos.wos_nodes(g, y, 40_000, seed=9)
+    z = (r["mean"] - _disk_u(y)) / r["se"]
+    assert np.all(np.abs(z) < 4.5), z
+    assert np.all(r["capped"] == 0)
+
+
+def test_table5_reproduction_monte_carlo():
+    """Test 4 / Table 5: x = (-0.5, 0, 0), a = 0.4, 10x10 x 100, 10x10 x 1000,
+    20x20 x 1000 paths; Sigma2' is 0 for the constant data."""
+    g = wos.Geometry(I.geometry_disk())
+    dp = I.DISK_POINT
+    exact = 8.0 / (4.0 * np.pi * np.sqrt(1.0 - 0.25))
+    assert abs(exact - 0.735105) < 5e-7  # the printed analytic density
+    paper = {(10, 100): 0.68888, (10, 1000): 0.73960, (20, 1000): 0.73441}
+    for ng, npath in I.TABLE5_RULES:
+        nodes, _ = P.hemisphere_rule(dp["x"], dp["n"], dp["t1"], dp["a"], ng)
+        r = wos.wos_nodes(g, nodes, npath, seed=3)
+        st = np.column_stack([r["count"], r["mean"], r["m2"], r["steps"]])
+        v, se, s1, s2 = P.point_neumann(g.phi, dp["x"], dp["n"], dp["t1"], dp["a"], ng, 20, 1e-6, st)
+        assert s2 == 0.0
+        assert abs(v - exact) < 4 * se, (ng, npath, v, se)
+        assert abs(paper[(ng, npath)] - exact) < 4 * se
