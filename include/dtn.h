@@ -61,7 +61,7 @@ typedef enum {
 } dtn_status;
 
 /* Domain kinds (walks run inside Omega). */
-enum { DTN_BALL = 0, DTN_BOX = 1, DTN_BOX_MINUS_BOXES = 2, DTN_HALF_SPACE = 3 };
+enum { DTN_BALL = 0, DTN_BOX = 1, DTN_BOX_MINUS_BOXES = 2, DTN_HALF_SPACE = 3, DTN_DISK = 4 };
 /* Dirichlet data kinds. */
 enum { DTN_DATA_HARMONIC_QUADRATIC = 0, DTN_DATA_POINT_SOURCES = 1 };
 /* Arithmetic of the walks and of the collocation solve. */
@@ -84,6 +84,11 @@ typedef struct dtn_plan_s *dtn_plan;         /* opaque, library-owned */
  *                             scores 0, the limit of data that vanish there
  *                             (Sec. 5.1.3 uses ball_r = 1e5).  Point sources
  *                             must lie in z < 0.
+ *   kind DTN_DISK:            all of space minus the closed thin disk
+ *                             {z = 0, x^2 + y^2 <= disk_r^2} (Sec. 5.1.3,
+ *                             Test 4); the truncation sphere as for the
+ *                             half space, which must enclose the disk.  Point
+ *                             sources must lie off the disk.
  *   data DTN_DATA_HARMONIC_QUADRATIC: phi = q0 + q1 x + q2 y + q3 z + q4 x^2
  *        + q5 y^2 + q6 z^2 + q7 xy + q8 yz + q9 xz, harmonic (q4+q5+q6 = 0).
  *   data DTN_DATA_POINT_SOURCES: phi = sum_k src[k].q / |x - src[k].xyz|,
@@ -106,6 +111,7 @@ typedef struct {
     double quad_coef[10];
     double eps;
     int64_t max_steps;
+    double disk_r; /* DTN_DISK: radius of the disk (other kinds: unused) */
 } dtn_geometry_desc;
 
 /* One boundary patch S with its hemisphere (Sec. 4, Fig. fig_biewos).
@@ -301,8 +307,10 @@ typedef struct {
 
 /* Create / destroy a set of query points (host array, copied).
  * Supported: a half space (n = (0,0,-1), c on z = 0, the hemisphere inside
- * the truncation sphere) or a face of a box / box minus boxes with the disk
- * inside the face and the half ball inside Omega (as for plane patches).
+ * the truncation sphere), either face of a thin disk (n = (0,0,-1) on the
+ * upper face, (0,0,1) on the lower; S_a inside the disk), or a face of a
+ * box / box minus boxes with the disk inside the face and the half ball
+ * inside Omega (as for plane patches).
  * n_g1, n_g2 in [1, 64]; delta_rel in (0, 1).  Errors: DTN_E_ARG (n < 1,
  * bad rule sizes, a point off a flat face, a ball domain). */
 dtn_status dtn_create_points(dtn_geometry g, const dtn_point *pts, int64_t n, int32_t n_g1, int32_t n_g2,

@@ -297,13 +297,20 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
         if (!desc || !out) return fail(DTN_E_ARG, "dtn_create_geometry: NULL argument");
         *out = nullptr;
         const dtn_geometry_desc &d = *desc;
-        if (d.kind < DTN_BALL || d.kind > DTN_HALF_SPACE) return fail(DTN_E_ARG, "dtn_create_geometry: bad kind");
+        if (d.kind < DTN_BALL || d.kind > DTN_DISK) return fail(DTN_E_ARG, "dtn_create_geometry: bad kind");
         if (d.data_kind != DTN_DATA_HARMONIC_QUADRATIC && d.data_kind != DTN_DATA_POINT_SOURCES)
             return fail(DTN_E_ARG, "dtn_create_geometry: bad data_kind");
         if (!(d.eps > 0.0)) return fail(DTN_E_ARG, "dtn_create_geometry: eps must be > 0");
         if (d.max_steps < 0) return fail(DTN_E_ARG, "dtn_create_geometry: max_steps < 0");
-        if ((d.kind == DTN_BALL || d.kind == DTN_HALF_SPACE) && !(d.ball_r > 0.0))
+        if ((d.kind == DTN_BALL || d.kind == DTN_HALF_SPACE || d.kind == DTN_DISK) && !(d.ball_r > 0.0))
             return fail(DTN_E_ARG, "dtn_create_geometry: ball_r <= 0");
+        if (d.kind == DTN_DISK) {
+            if (!(d.disk_r > 0.0)) return fail(DTN_E_ARG, "dtn_create_geometry: disk_r <= 0");
+            const double cc = std::sqrt(d.ball_c[0] * d.ball_c[0] + d.ball_c[1] * d.ball_c[1] +
+                                        d.ball_c[2] * d.ball_c[2]);
+            if (!(cc + d.disk_r < d.ball_r))
+                return fail(DTN_E_ARG, "dtn_create_geometry: the truncation sphere must enclose the disk");
+        }
         if (d.kind == DTN_BOX || d.kind == DTN_BOX_MINUS_BOXES)
             for (int k = 0; k < 3; ++k)
                 if (!(d.box_hi[k] > d.box_lo[k])) return fail(DTN_E_ARG, "dtn_create_geometry: empty box");
@@ -312,6 +319,12 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
             return fail(DTN_E_ARG, "dtn_create_geometry: holes is NULL");
         if (d.data_kind == DTN_DATA_POINT_SOURCES && (d.n_src < 1 || !d.src))
             return fail(DTN_E_ARG, "dtn_create_geometry: point-source data needs sources");
+        if (d.kind == DTN_DISK && d.data_kind == DTN_DATA_POINT_SOURCES)
+            for (int k = 0; k < d.n_src; ++k) {
+                const double *q = d.src + 4 * k;
+                if (q[2] == 0.0 && q[0] * q[0] + q[1] * q[1] <= d.disk_r * d.disk_r)
+                    return fail(DTN_E_ARG, "dtn_create_geometry: a source lies on the disk");
+            }
         if (d.kind == DTN_HALF_SPACE && d.data_kind == DTN_DATA_POINT_SOURCES)
             for (int k = 0; k < d.n_src; ++k)
                 if (!(d.src[4 * k + 2] < 0.0))
@@ -334,6 +347,7 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
         g.dev.r = d.ball_r;
         for (int k = 0; k < 10; ++k) g.dev.quad[k] = d.quad_coef[k];
         g.dev.eps = d.eps;
+        g.dev.disk_r = d.kind == DTN_DISK ? d.disk_r : 0.0;
         g.dev.max_steps = d.max_steps;
         const int nh = d.kind == DTN_BOX_MINUS_BOXES ? d.n_holes : 0;
         g.dev.n_holes = nh;
@@ -559,9 +573,9 @@ dtn_status dtn_create_plan(dtn_geometry g, const dtn_patch *patches, int64_t n_p
         p.patch_class.resize(n_patches);
         std::map<ClassKey, int> local;
         std::vector<ClassKey> keys;
-        if (G.dev.kind == DTN_HALF_SPACE)
+        if (G.dev.kind == DTN_HALF_SPACE || G.dev.kind == DTN_DISK)
             return fail(DTN_E_ARG, "dtn_create_plan: patch plans need a bounded domain (use dtn_create_points for "
-                                   "the half space)");
+                                   "the half space and the disk)");
         p.tiles_ok = G.dev.kind == DTN_BOX;
         for (int64_t i = 0; i < n_patches; ++i) {
             const dtn_patch &q = p.patches[i];

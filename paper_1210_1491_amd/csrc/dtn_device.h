@@ -203,6 +203,9 @@ __device__ __forceinline__ uint32_t cell_candidates(const DevGeom &g, const Cell
 // presence, so neither kind tests it at run time.
 constexpr int kHolesNoGrid = 16;  // internal kind, apart from the public ones
 constexpr bool has_holes(int kind) { return kind == DTN_BOX_MINUS_BOXES || kind == kHolesNoGrid; }
+// Unbounded domains: walks that reach the truncation sphere have gone to
+// infinity (score 0).
+constexpr bool has_truncation(int kind) { return kind == DTN_HALF_SPACE || kind == DTN_DISK; }
 
 // Union over the wave of the candidate holes of the cells of the lanes that
 // `take` (grid kind only).
@@ -245,6 +248,17 @@ __device__ __forceinline__ double dist_f64(const DevGeom &g, double x, double y,
 {
     if constexpr (KIND == DTN_HALF_SPACE) {
         return z;  // the plane z = 0 (the truncation sphere is no surface)
+    } else if constexpr (KIND == DTN_DISK) {
+        // distance to the disk: |z| over it, to its rim beyond; rho from the
+        // correctly rounded root (a rim distance is a small difference of
+        // rho and the radius), its argument kept off 0 on the axis (where
+        // the clamp cannot change the distance); sqrt(0 + z^2) is |z|
+        // exactly.  FAST: the outer root unrefined (relative error below
+        // 6e-8 of the distance itself)
+        const double rho = sqrt_f64(max_f64(x * x + y * y, 0x1p-1000));
+        const double e = max_f64(rho - g.disk_r, 0.0);
+        const double q = max_f64(fma(e, e, z * z), 0x1p-1000);
+        return FAST ? q * __builtin_amdgcn_rsq(q) : sqrt_f64(q);
     } else if constexpr (KIND == DTN_BALL) {
         const double dx = x - g.c[0], dy = y - g.c[1], dz = z - g.c[2];
         return g.r - sqrt_f64(dx * dx + dy * dy + dz * dz);
@@ -303,6 +317,13 @@ template <int KIND>
 __device__ __forceinline__ void project_f64(const DevGeom &g, double &x, double &y, double &z, uint32_t cand)
 {
     if constexpr (KIND == DTN_HALF_SPACE) {
+        z = 0.0;
+    } else if constexpr (KIND == DTN_DISK) {
+        const double rho = sqrt(x * x + y * y);
+        if (rho > g.disk_r) {
+            x *= g.disk_r / rho;
+            y *= g.disk_r / rho;
+        }
         z = 0.0;
     } else if constexpr (KIND == DTN_BALL) {
         const double dx = x - g.c[0], dy = y - g.c[1], dz = z - g.c[2];

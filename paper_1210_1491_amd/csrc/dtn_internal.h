@@ -37,6 +37,7 @@ struct DevGeom {
     double quad[10];
     double eps;
     int64_t max_steps;
+    double disk_r;          // DTN_DISK: radius of the disk
 };
 
 // Per-class operators on the device.  A class is a set of congruent patches

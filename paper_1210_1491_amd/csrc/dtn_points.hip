@@ -152,6 +152,26 @@ bool point_ok(const Geometry &g, const dtn_point &q, std::string &why)
         }
         return true;
     }
+    if (g.dev.kind == DTN_DISK) {
+        if (std::fabs(q.n[0]) > 1e-12 || std::fabs(q.n[1]) > 1e-12 || std::fabs(q.n[2]) < 1.0 - 1e-12) {
+            why = "the disk's outward normals are (0, 0, -1) on its upper face and (0, 0, 1) on its lower";
+            return false;
+        }
+        if (std::fabs(q.c[2]) > 1e-12 * (1.0 + g.dev.disk_r)) {
+            why = "centre is not on the disk's plane z = 0";
+            return false;
+        }
+        if (std::sqrt(q.c[0] * q.c[0] + q.c[1] * q.c[1]) + q.a > g.dev.disk_r * (1.0 + 1e-12)) {
+            why = "S_a leaves the disk";
+            return false;
+        }
+        const double dx = q.c[0] - g.dev.c[0], dy = q.c[1] - g.dev.c[1], dz = q.c[2] - g.dev.c[2];
+        if (std::sqrt(dx * dx + dy * dy + dz * dz) + q.a >= g.dev.r) {
+            why = "hemisphere reaches the truncation sphere";
+            return false;
+        }
+        return true;
+    }
     if (g.dev.kind == DTN_BOX || g.dev.kind == DTN_BOX_MINUS_BOXES) {
         dtn_patch pt{};
         for (int k = 0; k < 3; ++k) {
@@ -162,7 +182,7 @@ bool point_ok(const Geometry &g, const dtn_point &q, std::string &why)
         pt.h = q.a;
         return plane_patch_ok(g, pt, why);
     }
-    why = "the single-point estimate needs a flat boundary (half space or box faces)";
+    why = "the single-point estimate needs a flat boundary (half space, disk or box faces)";
     return false;
 }
 

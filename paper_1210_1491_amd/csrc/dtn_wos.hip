@@ -23,9 +23,10 @@
 //                   order, so results do not depend on which wave ran which
 //                   chunk), write (count, mean, M2, steps) and capped count.
 //
-// Half space (z > 0): a walk that reaches the truncation sphere has gone to
-// infinity and scores 0 (Sec. 5.1.3); the sphere is tested before the shell.
-// Such a walk is queued with z = -1 (every other queued position has z >= 0).
+// Unbounded domains (half space, exterior of a disk): a walk that reaches the
+// truncation sphere has gone to infinity and scores 0 (Sec. 5.1.3); the
+// sphere is tested before the shell.  Such a walk is queued with z = +inf
+// (every other queued position is finite).
 //
 // Randomness: walk k of a point with stream id s draws Philox4x32-10 block
 // (k lo, k hi, j, s) for its steps 2j and 2j+1 (words 0,1 then 2,3).  New
@@ -111,11 +112,11 @@ __global__ __launch_bounds__(kPlanThreads) void k_wos_plan(const int64_t *__rest
 // ---------------------------------------------------------------- the walks
 
 // Score of a queued exit position: phi at its closest boundary point, or 0
-// for a half-space walk gone to infinity (queued with z < 0).
+// for a walk gone to infinity (queued with z = +inf).
 template <int KIND, int DATA>
 __device__ __forceinline__ double exit_score(const DevGeom &g, double px, double py, double pz, uint32_t pc)
 {
-    const bool gone = KIND == DTN_HALF_SPACE && pz < 0.0;
+    const bool gone = has_truncation(KIND) && pz == __builtin_inf();
     project_f64<KIND>(g, px, py, pz, pc);
     const double f = phi_eval<DATA>(g, px, py, pz);
     return gone ? 0.0 : f;
@@ -231,8 +232,8 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
             // domain); only the walking lanes' results are used.
             const double d = dist_f64<KIND, PREC != DTN_FP64>(g, x, y, z, cand);
             const uint64_t in_shell = __builtin_amdgcn_ballot_w64(d < eps);
-            uint64_t gone = 0;  // half space: lanes at or beyond the truncation sphere
-            if constexpr (KIND == DTN_HALF_SPACE) {
+            uint64_t gone = 0;  // lanes at or beyond the truncation sphere
+            if constexpr (has_truncation(KIND)) {
                 const double ex = x - g.c[0], ey = y - g.c[1], ez = z - g.c[2];
                 gone = __builtin_amdgcn_ballot_w64(ex * ex + ey * ey + ez * ez >= g.r * g.r);
             }
@@ -273,7 +274,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                     lds_double *e = lds_slot(q, (uint32_t)qn, (uint32_t)rank_below(fm));
                     e[0] = x;
                     e[1] = y;
-                    e[2] = (KIND == DTN_HALF_SPACE && lane_in(gone)) ? -1.0 : z;
+                    e[2] = (has_truncation(KIND) && lane_in(gone)) ? __builtin_inf() : z;
                 }
                 wmask &= ~fm;
                 qn += __popcll(fm);
@@ -443,6 +444,9 @@ hipError_t dispatch(const Geometry &g, const double *pts, int64_t n, const int64
     case DTN_HALF_SPACE:
         return src ? run<DTN_HALF_SPACE, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
                    : run<DTN_HALF_SPACE, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
+    case DTN_DISK:
+        return src ? run<DTN_DISK, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
+                   : run<DTN_DISK, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
     default:
         if (!g.dev.cell_mask)
             return src ? run<kHolesNoGrid, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
@@ -489,6 +493,7 @@ void distance_kind(const Geometry &g, const double *pts, int64_t n, double *out,
     case DTN_HALF_SPACE:
         hipLaunchKernelGGL((k_distance<DTN_HALF_SPACE, FAST>), grid, block, 0, s, g.dev, pts, n, out);
         break;
+    case DTN_DISK: hipLaunchKernelGGL((k_distance<DTN_DISK, FAST>), grid, block, 0, s, g.dev, pts, n, out); break;
     default:
         if (g.dev.cell_mask)
             hipLaunchKernelGGL((k_distance<DTN_BOX_MINUS_BOXES, FAST>), grid, block, 0, s, g.dev, pts, n, out);

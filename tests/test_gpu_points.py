@@ -214,3 +214,110 @@ def test_points_reject_bad_input():
         dtn.Plan(g, I.patches_cube_tiles(m=1))
     with pytest.raises(dtn.DtnError):      # sources must lie below the plane
         dtn.Geometry(_hs(src=np.array([[0.0, 0.0, 0.5, 1.0]])))
+
+
+# ------------------------------------------- exterior of a thin disk (Test 4)
+
+def _disk(**kw):
+    return dict(I.geometry_disk(), **kw)
+
+
+def _disk_starts(n, seed):
+    rng = np.random.default_rng(seed)
+    p = np.column_stack([rng.uniform(-1.6, 1.6, (n, 2)), rng.uniform(-0.8, 0.8, n)])
+    p[0] = (0.0, 0.0, 2.0)        # on the axis (rho = 0)
+    p[1] = (1.3, 0.0, 0.0)        # in the disk's plane beyond the rim
+    p[2] = (0.2, 0.1, 3e-6)       # in the shell above the disk
+    p[3] = (0.99999, 0.0, -2e-6)  # next to the rim, below
+    return p
+
+
+def test_disk_distance_matches_oracle():
+    dtn = _dtn()
+    gd = _disk()
+    g = dtn.Geometry(gd)
+    x = _disk_starts(2000, 4)
+    d_or, _ = OW.Geometry(gd).dist_proj(x)
+    X = torch.tensor(x, device="cuda")
+    d64 = dtn.boundary_distance(g, X, "fp64").cpu().numpy()
+    d32 = dtn.boundary_distance(g, X, "fp32").cpu().numpy()
+    # beyond the rim the distance starts from rho - b: an ulp of rho (the
+    # sides may round x^2 + y^2 differently, fused or not) is kept in full
+    rho = np.hypot(x[:, 0], x[:, 1])
+    assert np.all(np.abs(d64 - d_or) <= 4.5e-16 * np.maximum(rho, 1.0) + 4.5e-16 * d_or)
+    # the FP32-mixed walks take the outer root unrefined; their jumps are
+    # shortened by 2^-22, far more than this error
+    np.testing.assert_allclose(d32, d_or, rtol=1e-7, atol=0)
+
+
+def test_disk_walks_fp64_parity_ragged():
+    gd = _disk()
+    pts = _disk_starts(200, 5)
+    walks = np.random.default_rng(6).integers(0, 1500, size=len(pts))
+    walks[2] = 100
+    gpu = _gpu_wos(gd, pts, walks, seed=17)
+    ora = OW.wos_nodes(OW.Geometry(gd), pts, walks, seed=17)
+    _compare(gpu, ora)
+    np.testing.assert_array_equal(gpu["capped"], ora["capped"])
+    assert gpu["mean"][2] == 1.0 and gpu["steps"][2] == 0  # in the shell: phi = 1 outright
+
+
+def test_disk_fp32_mixed_statistical():
+    gd = _disk()
+    pts = _disk_starts(64, 7)
+    gpu = _gpu_wos(gd, pts, 20_000, seed=5, precision="fp32")
+    ora = OW.wos_nodes(OW.Geometry(gd), pts, 20_000, seed=5)
+    _compare(gpu, ora, exact_walks=False)
+    ratio = gpu["steps"].sum() / ora["steps"].sum()
+    assert 0.99 <= ratio <= 1.01, ratio
+
+
+def test_table5_on_the_gpu():
+    dtn = _dtn()
+    gd = _disk()
+    g = dtn.Geometry(gd)
+    og = OW.Geometry(gd)
+    dp = I.DISK_POINT
+    exact = 8.0 / (4.0 * np.pi * np.sqrt(0.75))
+    for ng, npath in I.TABLE5_RULES:
+        print(f"[gpu] table 5: {ng}x{ng} nodes x {npath} paths", flush=True)
+        P = dtn.Points(g, [dp["x"]], [dp["n"]], [dp["t1"]], [dp["a"]], n_g1=ng, n_g2=20, delta_rel=1e-6)
+        nodes = P.nodes()
+        W = torch.full((P.num_nodes,), npath, dtype=torch.int64, device="cuda")
+        stats, capped = dtn.wos_eval(g, nodes, W, 3)
+        out = P.neumann(stats).cpu().numpy()[0]
+        on, _ = OPt.hemisphere_rule(dp["x"], dp["n"], dp["t1"], dp["a"], ng)
+        np.testing.assert_allclose(nodes.cpu().numpy(), on, rtol=0, atol=1e-14)
+        r = OW.wos_nodes(og, on, npath, seed=3)
+        want = OPt.point_neumann(og.phi, dp["x"], dp["n"], dp["t1"], dp["a"], ng, 20, 1e-6,
+                                 np.column_stack([r["count"], r["mean"], r["m2"], r["steps"]]))
+        assert out[3] == 0.0  # constant data: Sigma2' vanishes term by term
+        assert abs(out[0] - want[0]) < 0.05 * want[1], (ng, npath, out, want)
+        assert abs(out[0] - exact) < 4 * out[1], (ng, npath, out)
+        assert int(capped.sum().item()) == 0
+
+
+def test_disk_lower_face_and_rejections():
+    dtn = _dtn()
+    g = dtn.Geometry(_disk())
+    # lower face: n = +z, the hemisphere below; the density at rho = 0.36
+    x = (0.3, -0.2, 0.0)
+    P = dtn.Points(g, [x], [(0.0, 0.0, 1.0)], [(0.0, 1.0, 0.0)], [0.3], n_g1=16, n_g2=8)
+    nodes = P.nodes()
+    assert float(nodes[:, 2].max().item()) < 0.0
+    W = torch.full((P.num_nodes,), 20_000, dtype=torch.int64, device="cuda")
+    stats, _ = dtn.wos_eval(g, nodes, W, 11)
+    out = P.neumann(stats).cpu().numpy()[0]
+    exact = 2.0 / (np.pi * np.sqrt(1.0 - (0.3 ** 2 + 0.2 ** 2)))
+    assert abs(out[0] - exact) < 4 * out[1] + 1e-3, (out, exact)
+    for kw in ({"x": [(0.7, 0.0, 0.0)], "a": [0.4]},               # S_a leaves the disk
+               {"normals": [(1.0, 0.0, 0.0)], "t1": [(0.0, 1.0, 0.0)]},  # not a face normal
+               {"x": [(0.0, 0.0, 0.01)]}):                         # off the plane
+        d = dict(x=[(0.0, 0.0, 0.0)], normals=[(0.0, 0.0, -1.0)], t1=[(1.0, 0.0, 0.0)], a=[0.2])
+        d.update(kw)
+        with pytest.raises(dtn.DtnError):
+            dtn.Points(g, d["x"], d["normals"], d["t1"], d["a"])
+    with pytest.raises(dtn.DtnError):      # the sphere must enclose the disk
+        dtn.Geometry(_disk(ball_r=0.5))
+    with pytest.raises(dtn.DtnError):      # no patch plans on unbounded domains
+        dtn.Plan(g, I.patches_cube_tiles(m=1))
