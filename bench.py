@@ -72,6 +72,18 @@ HS_STEP_OPS = {
     "fp32": {"f64": 13 - 11 + 5, "f64fma": 3 + 2, "f32": 8, "trans32": 3, "cvt": 3, "i32": 15, "mad64": 10},
 }
 HS_WALK_OPS = {"f64": 10, "f64fma": 9, "rsq64": 1, "i32": 8}
+# Exterior of a disk: the distance is rho = sqrt(x^2 + y^2) (a product and an
+# FMA, a clamp, the correctly rounded root: 4 f64 + 4 FMA + rsq), e = rho - b
+# and its clamp, e^2 + z^2 (a product, an FMA) and its clamp, and the root
+# again (FP32-mixed: unrefined, a product and rsq); the sphere test as for
+# the half space.  Per walk: the projection onto the disk (root, quotient,
+# two products, compare), the constant data, the shift and the sums.
+DISK_STEP_OPS = {
+    "fp64": {"f64": 27 - 11 + 14 + 5, "f64fma": 17 + 10 + 2, "i32": 16, "mad64": 10, "cvt": 2, "rsq64": 1 + 2},
+    "fp32": {"f64": 13 - 11 + 11 + 5, "f64fma": 3 + 6 + 2, "f32": 8, "trans32": 3, "cvt": 3, "i32": 15,
+             "mad64": 10, "rsq64": 2},
+}
+DISK_WALK_OPS = {"f64": 14, "f64fma": 12, "rsq64": 2, "i32": 8}
 
 
 def slots(ops):
@@ -82,6 +94,8 @@ SLOTS_PER_STEP = {k: slots(v) for k, v in STEP_OPS.items()}
 SLOTS_PER_WALK = slots(WALK_OPS)
 HS_SLOTS_PER_STEP = {k: slots(v) for k, v in HS_STEP_OPS.items()}
 HS_SLOTS_PER_WALK = slots(HS_WALK_OPS)
+DISK_SLOTS_PER_STEP = {k: slots(v) for k, v in DISK_STEP_OPS.items()}
+DISK_SLOTS_PER_WALK = slots(DISK_WALK_OPS)
 
 # HBM traffic of the walk kernel on the unit-cube workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs, each scaled by the same counter on a plain
@@ -197,7 +211,8 @@ def parse():
                     help="range of the per-query required node standard error (log-uniform)")
     ap.add_argument("--serving-rate", type=float, default=200.0, help="offered load, queries/s")
     ap.add_argument("--no-halfspace", action="store_true", help="skip the single-point half-space workload")
-    ap.add_argument("--only", choices=["cube", "box_holes", "serving", "halfspace"], default=None,
+    ap.add_argument("--no-disk", action="store_true", help="skip the thin-disk workload (Table 5)")
+    ap.add_argument("--only", choices=["cube", "box_holes", "serving", "halfspace", "disk"], default=None,
                     help="run one workload only (for profiling)")
     ap.add_argument("--box-holes-se", type=float, default=None,
                     help="target standard error of the uneven-batching workload (default: its 1e-3)")
@@ -451,8 +466,110 @@ def halfspace_points(precision, steps, warmup, with_cpu=True, cpu_points=128):
     return res
 
 
+def disk(precision, steps, warmup, with_cpu=True, cpu_points=64, reps=20):
+    """Exterior of a thin disk (Sec. 5.1.3, Test 4).  Table 5: the density at
+    (-0.5, 0, 0) with a = 0.4 by its three rules (10x10 x 100, 10x10 x 1000,
+    20x20 x 1000 paths), each timed end to end (nodes, walks, Sigma1' +
+    Sigma2') over `reps` calls, beside the paper's CPU times; then 4096
+    points on both faces (20x20 x 1e3 walks) for throughput, accuracy against
+    the exact density 2/(pi sqrt(1 - rho^2)) and the walk kernel's ALU
+    fraction; the oracle on a sample with the GPU's stream ids."""
+    import torch
+
+    import dtn_inputs as I
+    from paper_1210_1491_amd import dtn
+
+    cfg = I.CONFIGS["disk_points"]
+    gd = cfg["geometry"]()
+    g = dtn.Geometry(gd)
+    dp = I.DISK_POINT
+    exact5 = 8.0 / (4.0 * np.pi * np.sqrt(0.75))
+    paper = {(10, 100): (0.68888, 30.0), (10, 1000): (0.73960, 307.0), (20, 1000): (0.73441, 1218.0)}
+    table5 = []
+    for ng, npath in I.TABLE5_RULES:
+        T = dtn.Points(g, [dp["x"]], [dp["n"]], [dp["t1"]], [dp["a"]], ng, 20, 1e-6)
+        tn = torch.empty((T.num_nodes, 3), dtype=torch.float64, device="cuda")
+        ts = torch.empty((T.num_nodes, 4), dtype=torch.float64, device="cuda")
+        to = torch.empty((1, 4), dtype=torch.float64, device="cuda")
+        tw = torch.full((T.num_nodes,), npath, dtype=torch.int64, device="cuda")
+
+        def call(seed):
+            T.nodes(out=tn)
+            dtn.wos_eval(g, tn, tw, seed, precision=precision, stats=ts)
+            T.neumann(ts, out=to)
+
+        call(3)
+        torch.cuda.synchronize()
+        v = to.cpu().numpy()[0]
+        t0 = time.perf_counter()
+        for r in range(reps):
+            call(100 + r)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        pv, pcpu = paper[(ng, npath)]
+        table5.append({"rule": f"{ng}x{ng} x {npath}", "paths": ng * ng * npath, "value": float(v[0]),
+                       "se": float(v[1]), "sigma2": float(v[3]), "err_pct": float(100 * (v[0] - exact5) / exact5),
+                       "gpu_ms": ms, "paper_value": pv, "paper_err_pct": 100 * (pv - exact5) / exact5,
+                       "paper_cpu_s": pcpu, "paper_cpu_s_over_gpu_s": pcpu / (ms / 1e3)})
+        print(f"[bench] table 5 {ng}x{ng} x {npath}: {v[0]:.5f} +- {v[1]:.5f}, {ms:.3f} ms", file=sys.stderr,
+              flush=True)
+    x, nrm, t1, a = cfg["points"](cfg["n_points"], cfg["seed"])
+    P = dtn.Points(g, x, nrm, t1, a, cfg["n_g1"], cfg["n_g2"], cfg["delta_rel"])
+    N = P.num_nodes
+    nodes = torch.empty((N, 3), dtype=torch.float64, device="cuda")
+    stats = torch.empty((N, 4), dtype=torch.float64, device="cuda")
+    capped = torch.empty(N, dtype=torch.int64, device="cuda")
+    out = torch.empty((len(a), 4), dtype=torch.float64, device="cuda")
+    walks = torch.full((N,), cfg["walks"], dtype=torch.int64, device="cuda")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def step(record):
+        P.nodes(out=nodes)
+        if record:
+            ev0.record()
+        dtn.wos_eval(g, nodes, walks, cfg["seed"], precision=precision, stats=stats, capped=capped)
+        if record:
+            ev1.record()
+        P.neumann(stats, out=out)
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    wos_ms = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+        torch.cuda.synchronize()
+        wos_ms.append(ev0.elapsed_time(ev1))
+    sec = (time.perf_counter() - t0) / steps
+    print(f"[bench] disk points {precision}: {sec * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+    st = stats.cpu().numpy()
+    o = out.cpu().numpy()
+    walks_n, steps_n = float(st[:, 0].sum()), float(st[:, 3].sum())
+    wos_s = float(np.mean(wos_ms)) / 1e3
+    achieved = (DISK_SLOTS_PER_STEP[precision] * steps_n + DISK_SLOTS_PER_WALK * walks_n) / wos_s
+    exact = 2.0 / (np.pi * np.sqrt(1.0 - (x[:, 0] ** 2 + x[:, 1] ** 2)))
+    z = (o[:, 0] - exact) / o[:, 1]
+    res = {"workload": f"exterior of a thin disk (b = 1) at u = 1, {len(a)} points on both faces x "
+                       f"{cfg['n_g1']}x{cfg['n_g1']} nodes x {cfg['walks']} walks, a <= 0.4, truncation 1e5, "
+                       f"eps 1e-5",
+           "precision": precision, "ms_per_step": sec * 1e3, "points_per_s": len(a) / sec,
+           "walks_per_s": walks_n / sec, "walk_steps_per_s": steps_n / sec, "steps_per_walk": steps_n / walks_n,
+           "wos_kernel_ms": float(np.mean(wos_ms)), "capped_walks": int(capped.sum().item()),
+           "rel_l2_vs_exact": float(np.linalg.norm(o[:, 0] - exact) / np.linalg.norm(exact)),
+           "se_rel_l2": float(np.linalg.norm(o[:, 1]) / np.linalg.norm(exact)),
+           "mean_abs_z": float(np.mean(np.abs(z))), "share_within_3_se": float(np.mean(np.abs(z) < 3)),
+           "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK / 1e12,
+                        "unit": "T lane-op slots/s", "frac": achieved / ALU_PEAK,
+                        "slots_per_step": DISK_SLOTS_PER_STEP[precision], "slots_per_walk": DISK_SLOTS_PER_WALK},
+           "table5": table5}
+    if with_cpu:
+        res["cpu_baseline"] = halfspace_cpu_baseline(gd, x, nrm, t1, a, cfg, o, cpu_points)
+    return res
+
+
 def halfspace_cpu_baseline(gd, x, nrm, t1, a, cfg, gpu_out, n_sample):
-    """CPU baseline of the half-space point workload: the oracle on the first
+    """CPU baseline of a single-point workload (half space or disk): the oracle on the first
     n_sample points with the stream ids the GPU run gave their nodes (node
     index), so the oracle's walks are the GPU's (FP64) and the values of the
     sampled points can be compared one by one."""
@@ -694,6 +811,10 @@ def main():
         print(json.dumps({"serving": serving("fp32", args.serving_window, args.serving_rate, args.serving_se_range,
                                              sweep_window=args.serving_sweep_window)}), flush=True)
         return
+    if args.only == "disk":
+        print(json.dumps({"disk": disk(args.precision, args.steps, args.warmup, not args.no_cpu_baseline)}),
+              flush=True)
+        return
     if args.only == "halfspace":
         print(json.dumps({"halfspace_points": halfspace_points(args.precision, args.steps, args.warmup,
                                                                not args.no_cpu_baseline)}), flush=True)
@@ -762,6 +883,8 @@ def main():
         line["box_holes"] = box_holes("fp32", 1, not args.no_cpu_baseline, with_fp64=not args.no_variants)
     if args.only is None and not args.no_halfspace:
         line["halfspace_points"] = halfspace_points("fp64", 1, 1, not args.no_cpu_baseline)
+    if args.only is None and not args.no_disk:
+        line["disk"] = disk("fp64", 1, 1, not args.no_cpu_baseline)
     if args.only is None and not args.no_serving:
         line["serving"] = serving("fp32", args.serving_window, args.serving_rate, args.serving_se_range,
                                   sweep_window=args.serving_sweep_window)

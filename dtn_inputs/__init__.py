@@ -75,6 +75,24 @@ DISK_POINT = {"x": (-0.5, 0.0, 0.0), "n": (0.0, 0.0, -1.0), "t1": (1.0, 0.0, 0.0
 TABLE5_RULES = [(10, 100), (10, 1000), (20, 1000)]
 
 
+def disk_points(n, seed=8, b=1.0, rho_max=0.8, a_max=0.4):
+    """Single-point queries on both faces of the disk: centres uniform by area
+    in the disk of radius rho_max*b, alternately on the upper face (outward
+    normal (0, 0, -1)) and the lower one ((0, 0, 1)), tangent at a uniform
+    angle, hemisphere radius a = min(a_max, 0.9 (b - rho)) so that S_a stays
+    on the disk.  Rows: x [n,3], normal [n,3], t1 [n,3], a [n]."""
+    rng = np.random.default_rng([seed, 19])
+    r = rho_max * b * np.sqrt(rng.random(n))
+    ang = 2 * np.pi * rng.random(n)
+    x = np.column_stack([r * np.cos(ang), r * np.sin(ang), np.zeros(n)])
+    nrm = np.zeros((n, 3))
+    nrm[:, 2] = np.where(np.arange(n) % 2 == 0, -1.0, 1.0)
+    c = 2 * np.pi * rng.random(n)
+    t1 = np.column_stack([np.cos(c), np.sin(c), np.zeros(n)])
+    a = np.minimum(a_max, 0.9 * (b - r))
+    return x, nrm, t1, a
+
+
 def halfspace_points(n, seed=6, radii=(0.1, 0.2, 0.5, 0.7, 1.0), extent=2.0):
     """Single-point queries on the plane z = 0: points uniform in the disk of
     radius ``extent`` around the origin, hemisphere radius cycling through
@@ -372,6 +390,16 @@ def serving_queries(gd, n_queries=600, rate=200.0, seed=5, max_points=4096, se_r
 # ----------------------------------------------------------------- configs
 
 CONFIGS = {
+    "disk_points": {  # Test 4 scaled to many points on both faces: 20x20 nodes, 1e3 walks each
+        "geometry": geometry_disk,
+        "points": disk_points,
+        "n_points": 4096,
+        "n_g1": 20,
+        "n_g2": 20,
+        "delta_rel": 1e-6,
+        "walks": 1000,
+        "seed": 8,
+    },
     "halfspace_points": {  # Test 1 scaled to many points: 20x20 nodes, 1e3 walks each
         "geometry": geometry_halfspace_charge,
         "points": halfspace_points,

@@ -227,3 +227,37 @@ def test_halfspace_points_full_size():
     z = (out[:, 0] - exact) / out[:, 1]
     print(f"[gpu] mean |z| {np.mean(np.abs(z)):.3f}, within 3 se {np.mean(np.abs(z) < 3):.4f}", flush=True)
     assert np.mean(np.abs(z)) < 1.0 and np.mean(np.abs(z) < 3) > 0.99
+
+
+@pytest.mark.timeout(300)
+def test_disk_points_full_size():
+    """The thin-disk workload at its full size (4096 points on both faces x
+    20 x 20 nodes x 1e3 walks, the benchmark's launch): sampled points (one
+    per face) recomputed by the oracle with the launch's stream ids; all
+    points meet the exact density within their standard errors."""
+    from oracle import point as OPt
+    from paper_1210_1491_amd import dtn
+    cfg = I.CONFIGS["disk_points"]
+    gd = cfg["geometry"]()
+    x, nrm, t1, a = cfg["points"](cfg["n_points"], cfg["seed"])
+    print("[gpu] full disk point workload", flush=True)
+    g = dtn.Geometry(gd)
+    P = dtn.Points(g, x, nrm, t1, a, cfg["n_g1"], cfg["n_g2"], cfg["delta_rel"])
+    nodes = P.nodes()
+    W = torch.full((P.num_nodes,), cfg["walks"], dtype=torch.int64, device="cuda")
+    stats, capped = dtn.wos_eval(g, nodes, W, cfg["seed"])
+    out = P.neumann(stats).cpu().numpy()
+    assert int(capped.sum()) == 0
+    og = OW.Geometry(gd)
+    nn = cfg["n_g1"] ** 2
+    for i in (10, cfg["n_points"] - 1):
+        on = OPt.hemisphere_rule(x[i], nrm[i], t1[i], a[i], cfg["n_g1"])[0]
+        sid = (i * nn + np.arange(nn)).astype(np.uint32)
+        r = OW.wos_nodes(og, on, cfg["walks"], seed=cfg["seed"], stream_id=sid)
+        st = np.column_stack([r["count"], r["mean"], r["m2"], r["steps"]])
+        want = OPt.point_neumann(og.phi, x[i], nrm[i], t1[i], a[i], cfg["n_g1"], cfg["n_g2"], cfg["delta_rel"], st)
+        assert abs(out[i, 0] - want[0]) < 0.05 * want[1], (i, out[i], want)
+    exact = 2.0 / (np.pi * np.sqrt(1.0 - (x[:, 0] ** 2 + x[:, 1] ** 2)))
+    z = (out[:, 0] - exact) / out[:, 1]
+    print(f"[gpu] mean |z| {np.mean(np.abs(z)):.3f}, within 3 se {np.mean(np.abs(z) < 3):.4f}", flush=True)
+    assert np.mean(np.abs(z)) < 1.0 and np.mean(np.abs(z) < 3) > 0.99
