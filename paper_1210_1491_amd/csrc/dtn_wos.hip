@@ -9,7 +9,9 @@
 //
 // Work decomposition (all on the device, no host round trip):
 //   k_wos_plan      one workgroup: total walks -> chunk size C, per-point
-//                   chunk counts and their exclusive scan (chunk offsets)
+//                   chunk counts and their exclusive scan (chunk offsets);
+//                   for many points the same in three launches over
+//                   segments (k_plan_sum, k_plan_count, k_plan_write)
 //   k_wos_walk      one wave per chunk (point, walk range of <= C walks); the
 //                   wave runs its walks with refill: a lane whose walk ends takes
 //                   the next walk of the chunk, so lanes do not idle behind
@@ -106,6 +108,104 @@ __global__ __launch_bounds__(kPlanThreads) void k_wos_plan(const int64_t *__rest
         chunk_off[n] = red[t];
         meta[0] = C;
         meta[1] = red[t];
+    }
+}
+
+// Multi-block planning (many points): B segments of L consecutive points.
+//   k_plan_sum    per segment: sum of its walk counts -> part[b]
+//   k_plan_count  per segment: C from the sum of part[] (every block
+//                 computes the same value), the segment's chunk count ->
+//                 cnt[b]; block 0 writes meta[0] = C
+//   k_plan_write  per segment: base = sum of cnt[j < b], a block scan of the
+//                 points' chunk counts -> chunk_off; the last block writes
+//                 chunk_off[n] and meta[1]
+// Same integers as k_wos_plan (every value is an exact integer sum).
+constexpr int kSegThreads = 256;
+
+__device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *red)
+{
+    const int t = threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+    for (int s = kSegThreads / 2; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    const int64_t r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kSegThreads) void k_plan_sum(const int64_t *__restrict__ walks, int64_t n, int64_t L,
+                                                          int64_t *__restrict__ part)
+{
+    __shared__ int64_t red[kSegThreads];
+    const int64_t b0 = (int64_t)blockIdx.x * L, b1 = min(n, b0 + L);
+    int64_t s = 0;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += kSegThreads) s += max(walks[i], (int64_t)0);
+    s = block_sum_i64(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__device__ __forceinline__ int64_t plan_chunk(const int64_t *__restrict__ part, int nb, int64_t target_chunks,
+                                              int64_t c_min, int64_t *red)
+{
+    int64_t s = 0;
+    for (int j = threadIdx.x; j < nb; j += kSegThreads) s += part[j];
+    const int64_t total = block_sum_i64(s, red);
+    return max(c_min, (total + target_chunks - 1) / target_chunks);
+}
+
+__global__ __launch_bounds__(kSegThreads) void k_plan_count(const int64_t *__restrict__ walks, int64_t n, int64_t L,
+                                                            const int64_t *__restrict__ part, int nb,
+                                                            int64_t target_chunks, int64_t c_min,
+                                                            int64_t *__restrict__ cnt, int64_t *__restrict__ meta)
+{
+    __shared__ int64_t red[kSegThreads];
+    const int64_t C = plan_chunk(part, nb, target_chunks, c_min, red);
+    const int64_t b0 = (int64_t)blockIdx.x * L, b1 = min(n, b0 + L);
+    int64_t s = 0;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += kSegThreads) s += (max(walks[i], (int64_t)0) + C - 1) / C;
+    s = block_sum_i64(s, red);
+    if (threadIdx.x == 0) {
+        cnt[blockIdx.x] = s;
+        if (blockIdx.x == 0) meta[0] = C;
+    }
+}
+
+__global__ __launch_bounds__(kSegThreads) void k_plan_write(const int64_t *__restrict__ walks, int64_t n, int64_t L,
+                                                            const int64_t *__restrict__ cnt,
+                                                            int64_t *__restrict__ chunk_off,
+                                                            int64_t *__restrict__ meta)
+{
+    __shared__ int64_t red[kSegThreads];
+    const int t = threadIdx.x;
+    const int64_t C = meta[0];
+    int64_t s = 0;
+    for (int j = t; j < (int)blockIdx.x; j += kSegThreads) s += cnt[j];
+    const int64_t base = block_sum_i64(s, red);
+    // contiguous runs per thread, then a scan of the run sums
+    const int64_t b0 = (int64_t)blockIdx.x * L, b1 = min(n, b0 + L);
+    const int64_t R = (b1 - b0 + kSegThreads - 1) / kSegThreads;
+    const int64_t r0 = min(b1, b0 + t * R), r1 = min(b1, r0 + R);
+    int64_t run = 0;
+    for (int64_t i = r0; i < r1; ++i) run += (max(walks[i], (int64_t)0) + C - 1) / C;
+    red[t] = run;
+    __syncthreads();
+    for (int o = 1; o < kSegThreads; o <<= 1) {  // Hillis-Steele inclusive scan
+        const int64_t v = t >= o ? red[t - o] : 0;
+        __syncthreads();
+        red[t] += v;
+        __syncthreads();
+    }
+    int64_t off = base + red[t] - run;
+    for (int64_t i = r0; i < r1; ++i) {
+        chunk_off[i] = off;
+        off += (max(walks[i], (int64_t)0) + C - 1) / C;
+    }
+    if (blockIdx.x == gridDim.x - 1 && t == kSegThreads - 1) {
+        chunk_off[n] = base + red[t];
+        meta[1] = base + red[t];
     }
 }
 
@@ -406,15 +506,32 @@ hipError_t run(const Geometry &g, const double *pts, int64_t n, const int64_t *w
     // total chunks <= sum(walks)/C + n <= target_chunks + n
     const int64_t max_chunks = n + target_chunks + 1;
     hipError_t e;
-    const size_t bytes = sizeof(int64_t) * (size_t)(n + 1) + 64 + 16 + sizeof(ChunkPartial) * (size_t)max_chunks;
+    // many points: the multi-block plan over nb segments of L points
+    constexpr int64_t kSegPoints = 2048, kMaxSegs = 1024;
+    const bool multi = n > 8 * kSegPoints;
+    const int nb = multi ? (int)min(kMaxSegs, (n + kSegPoints - 1) / kSegPoints) : 0;
+    const int64_t L = multi ? (n + nb - 1) / nb : 0;
+    const size_t bytes = sizeof(int64_t) * (size_t)(n + 1) + 64 + 16 + sizeof(ChunkPartial) * (size_t)max_chunks +
+                         2 * sizeof(int64_t) * (size_t)nb;
     char *scratch = nullptr;
     if ((e = hipMallocAsync((void **)&scratch, bytes, s)) != hipSuccess) return e;
     int64_t *meta = (int64_t *)scratch;
     int64_t *chunk_off = (int64_t *)(scratch + 64);
     ChunkPartial *part = (ChunkPartial *)(scratch + 64 + sizeof(int64_t) * (size_t)(n + 1));
     if (((uintptr_t)part & 15u) != 0) part = (ChunkPartial *)(((uintptr_t)part + 15u) & ~(uintptr_t)15u);
-    hipLaunchKernelGGL(k_wos_plan, dim3(1), dim3(kPlanThreads), 0, s, walks, n, target_chunks, c_min, chunk_off,
-                       meta);
+    if (multi) {
+        // segment sums and counts after the partials (the 16 spare bytes
+        // cover the partials' alignment)
+        int64_t *seg_part = (int64_t *)(part + max_chunks);
+        int64_t *seg_cnt = seg_part + nb;
+        hipLaunchKernelGGL(k_plan_sum, dim3(nb), dim3(kSegThreads), 0, s, walks, n, L, seg_part);
+        hipLaunchKernelGGL(k_plan_count, dim3(nb), dim3(kSegThreads), 0, s, walks, n, L, seg_part, nb,
+                           target_chunks, c_min, seg_cnt, meta);
+        hipLaunchKernelGGL(k_plan_write, dim3(nb), dim3(kSegThreads), 0, s, walks, n, L, seg_cnt, chunk_off, meta);
+    } else {
+        hipLaunchKernelGGL(k_wos_plan, dim3(1), dim3(kPlanThreads), 0, s, walks, n, target_chunks, c_min, chunk_off,
+                           meta);
+    }
     const int64_t waves_per_block = kWalkBlock / kWave;
     const int64_t blocks = (max_chunks + waves_per_block - 1) / waves_per_block;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;

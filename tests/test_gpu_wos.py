@@ -243,3 +243,24 @@ def test_many_holes_without_grid_match_oracle():
     gpu = _gpu_wos(gd, wp, 1500, seed=15)
     ora = OW.wos_nodes(OW.Geometry(gd), wp, 1500, seed=15)
     _compare(gpu, ora)
+
+
+def test_many_points_plan_in_segments_matches_oracle():
+    """More than 16384 points take the multi-block plan (segment sums,
+    counts, offsets): ragged walk counts with zeros; every point's count and
+    walks must match the oracle's, as with the one-workgroup plan."""
+    gd = I.geometry_cube_sources()
+    n = 40_000
+    # a margin keeps starts out of the shell (there every walk scores phi at
+    # one boundary point, so the two sides' phi must agree to the bit)
+    pts = I.interior_points_box(n, 31, margin=1e-3)
+    # 0 or at least 2 walks (one walk has no spread on either side, and its
+    # score may differ in the last bit)
+    walks = np.random.default_rng(32).integers(2, 9, size=n)
+    walks[:100] = 0
+    walks[-50:] = 0
+    walks[np.random.default_rng(33).random(n) < 0.1] = 0
+    gpu = _gpu_wos(gd, pts, walks, seed=21)
+    ora = OW.wos_nodes(OW.Geometry(gd), pts, walks, seed=21)
+    np.testing.assert_array_equal(gpu["count"], walks)
+    _compare(gpu, ora)
