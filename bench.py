@@ -103,13 +103,13 @@ DISK_SLOTS_PER_WALK = slots(DISK_WALK_OPS)
 # the kernel sources it was measured on (SHA-256 of these files).
 TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_amd/csrc/dtn_device.h",
                      "paper_1210_1491_amd/csrc/dtn_internal.h"],
-           "sha256": ["7a3871db29b4d09447a52ac3ab474bebb1d1793c055867bccd516d9bcefecb00",
-                      "09999af31f8be484fd7e3112965b250101a27799e11420efc7bf44e5f1df9f98",
-                      "d85a513da41eda0ddb131a768130f224b4afe53d6af419ad7c4985e12fcec4a6"],
-           "fetch_bytes": 71756.75 * 1024 * (262144 / 131089.125), "write_bytes": 43008.0 * 1024 * 1.00,
+           "sha256": ["cfc1fefdaa6c8ff15a725922e90596be36fc14d0046d2456454b7d85751b83e3",
+                      "dea1f750bdeed5412dcfbb6682f2f0ca948c92a965b9a2ae890f32fdeacfc490",
+                      "6027597fc35d2c2a06441b4edb4d7c8fa4f45273c1a688c783f159eb1a0ac103"],
+           "fetch_bytes": 71753.188 * 1024 * (262144 / 131089.938), "write_bytes": 43008.0 * 1024 * 1.00,
            # the half-space point workload's walk kernel (same sources), scaled
-           # by the copy in its own run (fetch 131086.438 KiB for 262144)
-           "halfspace_fetch_bytes": 156232.625 * 1024 * (262144 / 131086.438),
+           # by the copy in its own run (fetch 131086.25 KiB for 262144)
+           "halfspace_fetch_bytes": 156226.125 * 1024 * (262144 / 131086.25),
            "halfspace_write_bytes": 89600.0 * 1024 * 1.00}
 
 
