@@ -55,7 +55,7 @@ def geometry_halfspace_charge(h=1.0, trunc_r=1e5, eps=1e-5, max_steps=1_000_000)
     (Sec. 5.1.3, Test 1, eq. bw89 with q'/(4 pi eps0) = 1 and h = 1, the
     constants that give the printed analytic 0.71554).  Walks that reach the
     sphere |x| = trunc_r count as gone to infinity (u = 0 there)."""
-    return {"kind": "half_space", "ball_c": (0.0, 0.0, 0.0), "ball_r": float(trunc_r),
+    return {"kind": "half_space", "ball_c": (0.0, 0.0, 0.0), "trunc_r": float(trunc_r),
             "data_kind": "sources", "quad": [0.0] * 10, "src": np.array([[0.0, 0.0, -float(h), 1.0]]),
             "holes": np.zeros((0, 6)), "eps": eps, "max_steps": max_steps}
 
@@ -64,7 +64,7 @@ def geometry_disk(b=1.0, trunc_r=1e5, eps=1e-5, max_steps=1_000_000):
     """Exterior of a thin conducting disk {z = 0, x^2 + y^2 <= b^2} held at
     u = 1, with u -> 0 at infinity (Sec. 5.1.3, Test 4, eq. bw95 with Q = 8b);
     walks that reach the sphere |x| = trunc_r count as gone to infinity."""
-    return {"kind": "disk", "disk_r": float(b), "ball_c": (0.0, 0.0, 0.0), "ball_r": float(trunc_r),
+    return {"kind": "disk", "disk_r": float(b), "ball_c": (0.0, 0.0, 0.0), "trunc_r": float(trunc_r),
             "data_kind": "quadratic", "quad": [1.0] + [0.0] * 9, "src": np.zeros((0, 4)),
             "holes": np.zeros((0, 6)), "eps": eps, "max_steps": max_steps}
 
@@ -91,6 +91,50 @@ def disk_points(n, seed=8, b=1.0, rho_max=0.8, a_max=0.4):
     t1 = np.column_stack([np.cos(c), np.sin(c), np.zeros(n)])
     a = np.minimum(a_max, 0.9 * (b - r))
     return x, nrm, t1, a
+
+
+def geometry_ball_exterior(R=3.0, q=1.0, trunc_r=1e5, eps=1e-5, max_steps=1_000_000):
+    """Exterior of the sphere |x| = R with a point charge q at its centre,
+    u = q/|x| (Sec. 5.2, the big sphere: R = 3, q = 1); walks that reach the
+    sphere |x| = trunc_r count as gone to infinity."""
+    return {"kind": "ball_exterior", "ball_c": (0.0, 0.0, 0.0), "ball_r": float(R), "trunc_r": float(trunc_r),
+            "data_kind": "sources", "quad": [0.0] * 10, "src": np.array([[0.0, 0.0, 0.0, float(q)]]),
+            "holes": np.zeros((0, 6)), "eps": eps, "max_steps": max_steps}
+
+
+def patches_big_sphere(R=3.0, h=1.0, n_theta=16, n_phi=32, n_rings=4, n_sectors=16):
+    """Sec. 5.2's patch: centre o = (0, 0, R) on the sphere, a = h = 1; the
+    domain's outward normal there points to the centre."""
+    d = _empty_patches(1)
+    d["c"][0] = (0.0, 0.0, R)
+    d["n"][0] = (0.0, 0.0, -1.0)
+    d["t1"][0] = (1.0, 0.0, 0.0)
+    d["h"][0] = h
+    d["n_theta"][0], d["n_phi"][0], d["n_rings"][0], d["n_sectors"][0] = n_theta, n_phi, n_rings, n_sectors
+    return d
+
+
+def patches_sphere_exterior(n, R=3.0, h=0.5, n_theta=8, n_phi=16, n_rings=4, n_sectors=8, seed=9):
+    """n patches outside the sphere |x| = R at the points of a Fibonacci
+    lattice (near-uniform), each with the domain's outward normal (to the
+    centre) and a tangent at a seeded angle."""
+    rng = np.random.default_rng([seed, 23])
+    k = np.arange(n) + 0.5
+    z = 1.0 - 2.0 * k / n
+    phi = np.pi * (1.0 + 5.0 ** 0.5) * k
+    u = np.column_stack([np.sqrt(1 - z * z) * np.cos(phi), np.sqrt(1 - z * z) * np.sin(phi), z])
+    d = _empty_patches(n)
+    d["c"][:] = R * u
+    d["n"][:] = -u
+    ref = np.where(np.abs(u[:, 2:3]) < 0.9, [[0.0, 0.0, 1.0]], [[1.0, 0.0, 0.0]])
+    e1 = np.cross(ref, u)
+    e1 /= np.linalg.norm(e1, axis=1, keepdims=True)
+    e2 = np.cross(u, e1)
+    ang = 2 * np.pi * rng.random(n)
+    d["t1"][:] = np.cos(ang)[:, None] * e1 + np.sin(ang)[:, None] * e2
+    d["h"][:] = h
+    d["n_theta"][:], d["n_phi"][:], d["n_rings"][:], d["n_sectors"][:] = n_theta, n_phi, n_rings, n_sectors
+    return d
 
 
 def halfspace_points(n, seed=6, radii=(0.1, 0.2, 0.5, 0.7, 1.0), extent=2.0):

@@ -47,8 +47,10 @@ FOUR_PI = 4.0 * np.pi
 class Patch:
     """A patch S of the boundary with its hemisphere.
 
-    ``sphere`` is (C, R) when the boundary near c is the sphere |x - C| = R
-    (then n = (c - C)/R), and None when the boundary is the plane through c
+    ``sphere`` is (C, R) when the boundary near c is the sphere |x - C| = |R|
+    (then n = (c - C)/R): R > 0 when the domain is inside the sphere, R < 0
+    when it is outside (the exterior of a ball, Sec. 5.2's big sphere; n then
+    points to the centre); None when the boundary is the plane through c
     normal to n."""
 
     def __init__(self, c, n, t1, h, n_theta, n_phi, n_rings, n_sectors, sphere=None):
@@ -79,6 +81,8 @@ def patches_from_desc(desc, geom_desc):
     sphere = None
     if geom_desc["kind"] == "ball":
         sphere = (np.asarray(geom_desc["ball_c"], dtype=np.float64), float(geom_desc["ball_r"]))
+    elif geom_desc["kind"] == "ball_exterior":
+        sphere = (np.asarray(geom_desc["ball_c"], dtype=np.float64), -float(geom_desc["ball_r"]))
     out = []
     for i in range(len(desc["h"])):
         out.append(Patch(desc["c"][i], desc["n"][i], desc["t1"][i], desc["h"][i],
@@ -88,12 +92,15 @@ def patches_from_desc(desc, geom_desc):
 
 
 # In local coordinates the patch centre is the origin, n = e_z, t1 = e_x and
-# t2 = e_y; on a sphere of radius R its centre sits at (0, 0, -R).
+# t2 = e_y; on a sphere of signed radius R its centre sits at (0, 0, -R)
+# (below S for a domain inside the sphere, above it for one outside).
 
 
 def theta_max(h, R):
     """Polar extent of Gamma, measured from the inward normal: pi/2 over a
-    plane; arccos(h / 2R) over a sphere of radius R (|c + h v - C| < R)."""
+    plane; arccos(h / 2R) over a sphere of signed radius R (the part of the
+    sphere |v| = h on the domain's side: less than a hemisphere inside a
+    ball, more outside one)."""
     return 0.5 * np.pi if R is None else float(np.arccos(h / (2.0 * R)))
 
 
@@ -124,23 +131,28 @@ def nodes_global(p):
 
 def s_max(h, R):
     """Parametric radius of S: h over a plane; the geodesic angle
-    2 arcsin(h / 2R) over a sphere (|y - c| = h on the rim)."""
-    return h if R is None else 2.0 * np.arcsin(h / (2.0 * R))
+    2 arcsin(h / 2|R|) over a sphere (|y - c| = h on the rim)."""
+    return h if R is None else 2.0 * np.arcsin(h / (2.0 * abs(R)))
 
 
 def surface(s, a, R):
-    """Point, unit normal and area Jacobian of S at parameters (s, a), local
-    coordinates.  Plane: y = s (cos a, sin a, 0), jac = s.  Sphere: y = C + R
-    (sin s cos a, sin s sin a, cos s), C = (0,0,-R), jac = R^2 sin s."""
+    """Point, unit normal (the domain's outward one) and area Jacobian of S at
+    parameters (s, a), local coordinates.  Plane: y = s (cos a, sin a, 0),
+    jac = s.  Sphere of signed radius R, r = |R|, side e = sign(R):
+    y = (r sin s cos a, r sin s sin a, e r (cos s - 1)), normal
+    (e sin s cos a, e sin s sin a, cos s), jac = r^2 sin s; s is the geodesic
+    angle from c, so |y - C| = r with C = (0, 0, -R)."""
     s = np.asarray(s, dtype=np.float64)
     a = np.asarray(a, dtype=np.float64)
     if R is None:
         y = np.stack([s * np.cos(a), s * np.sin(a), np.zeros_like(s)], axis=-1)
         nrm = np.broadcast_to(np.array([0.0, 0.0, 1.0]), y.shape)
         return y, nrm, s
-    u = np.stack([np.sin(s) * np.cos(a), np.sin(s) * np.sin(a), np.cos(s)], axis=-1)
-    y = R * u + np.array([0.0, 0.0, -R])
-    return y, u, R * R * np.sin(s)
+    r, e = abs(R), np.sign(R)
+    ss, cs = np.sin(s), np.cos(s)
+    y = np.stack([r * ss * np.cos(a), r * ss * np.sin(a), e * r * (cs - 1.0)], axis=-1)
+    nrm = np.stack([e * ss * np.cos(a), e * ss * np.sin(a), cs], axis=-1)
+    return y, nrm, r * r * ss
 
 
 def panels(h, R, n_rings, n_sectors):
@@ -239,11 +251,11 @@ def integrate_singular(f, box, R, n=20, tol=1e-14):
     centre) is a singular point of f.  A sub-box around the point that is
     square in physical lengths (metric g_ss, g_aa of the surface) takes the
     Duffy rule; the rest of the panel is regular and takes the adaptive rule.
-    Plane: g_ss = 1, g_aa = s^2.  Sphere of radius R: g_ss = R^2,
+    Plane: g_ss = 1, g_aa = s^2.  Sphere of radius |R|: g_ss = R^2,
     g_aa = R^2 sin^2 s."""
     sc, ac = 0.5 * (box[0] + box[1]), 0.5 * (box[2] + box[3])
-    gs = 1.0 if R is None else R
-    ga = sc if R is None else R * np.sin(sc)
+    gs = 1.0 if R is None else abs(R)
+    ga = sc if R is None else abs(R) * np.sin(sc)
     w = min(0.5 * (box[1] - box[0]) * gs, 0.5 * (box[3] - box[2]) * ga)
     ds, da = w / gs, w / ga
     core = (sc - ds, sc + ds, ac - da, ac + da)

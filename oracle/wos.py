@@ -52,10 +52,11 @@ class OgGeom(C.Structure):
         ("eps", C.c_double),
         ("max_steps", C.c_int64),
         ("disk_r", C.c_double),
+        ("trunc_r", C.c_double),
     ]
 
 
-KIND = {"ball": 0, "box": 1, "box_minus_boxes": 2, "half_space": 3, "disk": 4}
+KIND = {"ball": 0, "box": 1, "box_minus_boxes": 2, "half_space": 3, "disk": 4, "ball_exterior": 5}
 
 
 def _dptr(a):
@@ -100,6 +101,7 @@ class Geometry:
         g.eps = float(desc["eps"])
         g.max_steps = int(desc["max_steps"])
         g.disk_r = float(desc.get("disk_r", 0.0))
+        g.trunc_r = float(desc.get("trunc_r", 0.0))
         self.g = g
 
     def ref(self):

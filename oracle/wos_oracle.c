@@ -34,15 +34,18 @@
  *     boundary point) accumulated with Neumaier's compensated summation;
  *   - half space z > 0 (the exterior domain of the flat-boundary tests of
  *     Sec. 5.1.3): the distance to the boundary is z; a walk that reaches the
- *     large truncation sphere |x - ball_c| >= ball_r is taken to have gone to
- *     infinity (Sec. 5.1.3, the sphere of radius 1e5) and scores u = 0 there,
- *     the limit of data that decay at infinity.  The sphere is tested first at
+ *     large truncation sphere |x - ball_c| >= trunc_r is taken to have gone
+ *     to infinity (Sec. 5.1.3, the sphere of radius 1e5) and scores u = 0
+ *     there, the limit of data that decay at infinity.  The sphere is tested first at
  *     every position (start and after every jump), then the shell, then the
  *     step cap;
  *   - the exterior of a thin disk (Sec. 5.1.3, Test 4): all of space minus
  *     the closed disk {z = 0, x^2 + y^2 <= disk_r^2}; the distance is that to
  *     the disk, the closest point its projection, and the truncation sphere
- *     applies as for the half space.
+ *     applies as for the half space;
+ *   - the exterior of a ball (Sec. 5.2, the big sphere): |x - ball_c| >
+ *     ball_r, distance |x - ball_c| - ball_r, closest point on the sphere,
+ *     the truncation sphere as above.
  *
  * Build: gcc -O2 -fopenmp -fPIC -shared wos_oracle.c -lm (see build.py).
  */
@@ -55,7 +58,7 @@
 
 /* ---------------------------------------------------------------- geometry */
 
-enum { OG_BALL = 0, OG_BOX = 1, OG_BOX_MINUS_BOXES = 2, OG_HALF_SPACE = 3, OG_DISK = 4 };
+enum { OG_BALL = 0, OG_BOX = 1, OG_BOX_MINUS_BOXES = 2, OG_HALF_SPACE = 3, OG_DISK = 4, OG_BALL_EXTERIOR = 5 };
 enum { OG_DATA_QUADRATIC = 0, OG_DATA_SOURCES = 1 };
 
 typedef struct {
@@ -73,6 +76,7 @@ typedef struct {
     double eps;
     int64_t max_steps;
     double disk_r;       /* OG_DISK: radius of the disk in z = 0 */
+    double trunc_r;      /* unbounded kinds: truncation sphere |x - ball_c| = trunc_r */
 } og_geom;
 
 /* Dirichlet data phi(x).
@@ -114,6 +118,13 @@ double og_dist_proj(const og_geom *g, const double x[3], double p[3])
         double e = rho - g->disk_r;
         if (p) { p[0] = x[0] * (g->disk_r / rho); p[1] = x[1] * (g->disk_r / rho); p[2] = 0.0; }
         return sqrt(e * e + x[2] * x[2]);
+    }
+    if (g->kind == OG_BALL_EXTERIOR) {
+        double v[3] = {x[0] - g->ball_c[0], x[1] - g->ball_c[1], x[2] - g->ball_c[2]};
+        double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        if (p)
+            for (int k = 0; k < 3; ++k) p[k] = g->ball_c[k] + g->ball_r * v[k] / r;
+        return r - g->ball_r;
     }
     if (g->kind == OG_BALL) {
         double v[3] = {x[0] - g->ball_c[0], x[1] - g->ball_c[1], x[2] - g->ball_c[2]};
@@ -226,9 +237,9 @@ void og_direction(double u1, double u2, double w[3])
 /* Has x left the truncation sphere of an unbounded domain (gone to infinity)? */
 static int og_escaped(const og_geom *g, const double x[3])
 {
-    if (g->kind != OG_HALF_SPACE && g->kind != OG_DISK) return 0;
+    if (g->kind != OG_HALF_SPACE && g->kind != OG_DISK && g->kind != OG_BALL_EXTERIOR) return 0;
     double dx = x[0] - g->ball_c[0], dy = x[1] - g->ball_c[1], dz = x[2] - g->ball_c[2];
-    return dx * dx + dy * dy + dz * dz >= g->ball_r * g->ball_r;
+    return dx * dx + dy * dy + dz * dz >= g->trunc_r * g->trunc_r;
 }
 
 /* One walk from x0.  Returns the recorded phi (0 for a walk gone to

@@ -52,7 +52,7 @@ def test_halfspace_walks_fp64_parity():
 def test_halfspace_truncation_parity_ragged(data):
     # a small sphere (radius 3) so that many walks reach it; ragged walk
     # counts; start points beyond the sphere, inside the shell, and both
-    kw = {"ball_r": 3.0}
+    kw = {"trunc_r": 3.0}
     if data == "constant":
         kw.update(data_kind="quadratic", quad=[1.0] + [0.0] * 9, src=np.zeros((0, 4)))
     gd = _hs(**kw)
@@ -318,6 +318,6 @@ def test_disk_lower_face_and_rejections():
         with pytest.raises(dtn.DtnError):
             dtn.Points(g, d["x"], d["normals"], d["t1"], d["a"])
     with pytest.raises(dtn.DtnError):      # the sphere must enclose the disk
-        dtn.Geometry(_disk(ball_r=0.5))
+        dtn.Geometry(_disk(trunc_r=0.5))
     with pytest.raises(dtn.DtnError):      # no patch plans on unbounded domains
         dtn.Plan(g, I.patches_cube_tiles(m=1))

@@ -31,6 +31,38 @@ def _ball_patch():
     return P.patches_from_desc(I.patches_ball_pole(), gd)[0], gd
 
 
+def _exterior_patch():
+    gd = I.geometry_ball_exterior()
+    return P.patches_from_desc(I.patches_big_sphere(), gd)[0], gd
+
+
+def test_exterior_patch_geometry():
+    """Outside a ball (signed radius -3): Gamma is more than a hemisphere
+    and outside the ball, S lies on the sphere with the normal pointing to
+    the centre, the panel areas add up to the cap's area."""
+    p, gd = _exterior_patch()
+    assert p.R == -3.0
+    h, R = p.h, p.R
+    tm = P.theta_max(h, R)
+    assert tm == pytest.approx(np.arccos(-1.0 / 6.0)) and tm > 0.5 * np.pi
+    Yg, W = P.nodes_global(p)
+    assert np.all(np.linalg.norm(Yg, axis=1) > 3.0 - 1e-12)
+    np.testing.assert_allclose(np.linalg.norm(Yg - p.c, axis=1), h, rtol=1e-14)
+    assert W.sum() == pytest.approx(2 * np.pi * h * h * (1 - np.cos(tm)), rel=1e-13)
+    boxes, X, N, area = P.panels(h, R, 4, 16)
+    Xg, Ng = p.to_global(X), p.normal_to_global(N)
+    np.testing.assert_allclose(np.linalg.norm(Xg, axis=1), 3.0, rtol=1e-14)
+    np.testing.assert_allclose(Ng, -Xg / 3.0, atol=1e-14)
+    sm = P.s_max(h, R)
+    assert np.all(np.linalg.norm(Xg - p.c, axis=1) <= h)
+    assert area.sum() == pytest.approx(2 * np.pi * 9.0 * (1 - np.cos(sm)), rel=1e-13)
+    # the surface Jacobian integrates to the same area
+    s, ws = np.polynomial.legendre.leggauss(40)
+    s, ws = 0.5 * sm * (s + 1), 0.5 * sm * ws
+    _, _, jac = P.surface(s, 0.0 * s, R)
+    assert np.sum(jac * ws) * 2 * np.pi == pytest.approx(area.sum(), rel=1e-13)
+
+
 def test_node_weights_sum_to_gamma_area():
     for h, R in ((0.2, None), (0.2, 1.0), (0.5, 3.0)):
         _, W, _, _ = P.node_grid(h, R, 8, 16)
@@ -128,9 +160,15 @@ def test_gamma_operator_rows_and_convergence():
     np.testing.assert_allclose(fines, QIs, rtol=0, atol=1e-12)
 
 
-@pytest.mark.parametrize("which", ["flat", "ball"])
+def _which(which, flat_idx):
+    if which == "flat":
+        return _cube_patch(flat_idx)
+    return _ball_patch() if which == "ball" else _exterior_patch()
+
+
+@pytest.mark.parametrize("which", ["flat", "ball", "exterior"])
 def test_constant_data_gives_zero_neumann(which):
-    p, gd = _cube_patch(40) if which == "flat" else _ball_patch()
+    p, gd = _which(which, 40)
     const = dict(gd, data_kind="quadratic", quad=[1.0] + [0.0] * 9)
     g = wos.Geometry(const)
     Y, _ = P.nodes_global(p)
@@ -176,24 +214,27 @@ def _representation(p, gd, x_loc, n=48):
     return gam - dl + sl, g.phi(p.to_global(x_loc[None]))[0]
 
 
-@pytest.mark.parametrize("which", ["flat", "ball"])
+@pytest.mark.parametrize("which", ["flat", "ball", "exterior"])
 def test_local_representation_identity(which):
-    p, gd = _cube_patch(3 * 256 + 100) if which == "flat" else _ball_patch()
+    p, gd = _which(which, 3 * 256 + 100)
     h = p.h
     for x_loc in ([0.1 * h, -0.2 * h, -0.4 * h], [-0.3 * h, 0.25 * h, -0.6 * h]):
         rep, exact = _representation(p, gd, np.array(x_loc))
         assert rep == pytest.approx(exact, abs=1e-10 * max(1.0, abs(exact)))
 
 
-@pytest.mark.parametrize("which", ["flat", "ball"])
+@pytest.mark.parametrize("which", ["flat", "ball", "exterior"])
 def test_exact_node_values_give_accurate_neumann(which):
     """The method's deterministic floor: exact u on Gamma, exact phi on S."""
     if which == "flat":
         gd = I.geometry_cube_sources()
         pd = I.subset_patches(I.patches_cube_tiles(), I.cube_tile_subset()[:6])
         ps, bar = P.patches_from_desc(pd, gd), 1e-4
-    else:
+    elif which == "ball":
         p, gd = _ball_patch()
+        ps, bar = [p], 2e-3
+    else:
+        p, gd = _exterior_patch()
         ps, bar = [p], 2e-3
     g = wos.Geometry(gd)
     sig, exs, area, trusted = [], [], [], []
@@ -203,7 +244,7 @@ def test_exact_node_values_give_accurate_neumann(which):
         sig.append(r["sigma"])
         exs.append(P.exact_neumann(gd, r["x"], r["normal"]))
         area.append(r["area"])
-        trusted.append(r["r"] < 0.7 * P.s_max(p.h, p.R) * (1 if p.R is None else p.R))
+        trusted.append(r["r"] < 0.7 * P.s_max(p.h, p.R) * (1 if p.R is None else abs(p.R)))
     # global (area-weighted, all patches) error: a per-patch relative error is
     # ill-posed on patches where the Neumann data is nearly zero
     err = P.rel_l2(*map(np.concatenate, (sig, exs, area, trusted)))
@@ -290,3 +331,37 @@ def test_central_disk_answer_se_matches_noise_spread():
     spread = np.std(vals, ddof=1)
     # sd of a sample sd over 300 draws is about 4 %
     assert abs(spread / se - 1.0) < 0.15, (spread, se)
+
+
+def test_exterior_ball_walks_match_exact_u():
+    """Walks outside the sphere of radius 3 with the truncation sphere 1e5:
+    the mean is u = 1/|x| of the central charge (a walk gone to infinity
+    scores 0, against u ~ 1e-5 there)."""
+    gd = I.geometry_ball_exterior()
+    g = wos.Geometry(gd)
+    y = np.array([[0.0, 0.0, 3.5], [1.0, 2.0, 2.9], [0.0, 0.0, 10.0], [4.0, 0.0, 0.0]])
+    r = wos.wos_nodes(g, y, 40_000, seed=4)
+    z = (r["mean"] - 1.0 / np.linalg.norm(y, axis=1)) / r["se"]
+    assert np.all(np.abs(z) < 4.5), z
+    d, pr = g.dist_proj(y)
+    np.testing.assert_allclose(d, np.linalg.norm(y, axis=1) - 3.0, rtol=1e-15)
+    np.testing.assert_allclose(np.linalg.norm(pr, axis=1), 3.0, rtol=1e-15)
+
+
+def test_big_sphere_patch_section_5_2():
+    """Sec. 5.2: the patch at (0, 0, 3) outside the sphere of radius 3 with
+    the unit charge at its centre, a = 1, 1e4 walks per node: the maximal
+    relative error over the panels with r < 0.7a is below the paper's 1.25 %
+    and within 4 propagated standard errors of the exact 1/9."""
+    p, gd = _exterior_patch()
+    g = wos.Geometry(gd)
+    Y, _ = P.nodes_global(p)
+    r = wos.wos_nodes(g, Y, 10_000, seed=5)
+    assert int(r["capped"].sum()) == 0
+    res = P.patch_solve(p, g, r["mean"], r["se"])
+    ex = P.exact_neumann(gd, res["x"], res["normal"])
+    np.testing.assert_allclose(ex, 1.0 / 9.0, rtol=1e-14)
+    tr = res["r"] < 0.7 * P.s_max(p.h, p.R) * abs(p.R)
+    rel = np.abs(res["sigma"] - ex) / np.abs(ex)
+    assert rel[tr].max() < 0.0125
+    assert np.all(np.abs(res["sigma"][tr] - ex[tr]) < 4 * res["se"][tr] + 2e-3 * ex[tr])

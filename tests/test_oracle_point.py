@@ -153,7 +153,7 @@ def test_half_space_walks_match_exact_u():
 
 
 def test_half_space_start_cases():
-    g = _geom(ball_r=10.0)
+    g = _geom(trunc_r=10.0)
     # outside the truncation sphere: gone to infinity at once, score 0
     s, st = wos.wos_scores(g, (0.0, 0.0, 10.0), 1, 0, 0, 5)
     np.testing.assert_array_equal(s, 0.0)
@@ -171,7 +171,7 @@ def test_half_space_start_cases():
 def _rewalk(desc, y, seed, sid, walk):
     """Step-by-step half-space walk from the rule alone (tiny inputs)."""
     c = np.asarray(desc["ball_c"], float)
-    R = desc["ball_r"]
+    R = desc["trunc_r"]
     x = np.asarray(y, float).copy()
     n = 0
     words = None
@@ -196,7 +196,7 @@ def _rewalk(desc, y, seed, sid, walk):
 
 
 def test_half_space_rewalk_tiny():
-    desc = dict(I.geometry_halfspace_charge(), ball_r=3.0, max_steps=60)
+    desc = dict(I.geometry_halfspace_charge(), trunc_r=3.0, max_steps=60)
     g = wos.Geometry(desc)
     y = (0.4, 0.1, 0.8)
     s, st = wos.wos_scores(g, y, 9, 3, 0, 300)
@@ -224,7 +224,7 @@ def _half_ball_escape(z0, R, lmax=401):
 
 def test_half_space_escape_probability_bound():
     # constant data 1 on the plane: the walk mean is the absorbed fraction
-    g = _geom(data_kind="quadratic", quad=[1.0] + [0.0] * 9, src=np.zeros((0, 4)), ball_r=5.0)
+    g = _geom(data_kind="quadratic", quad=[1.0] + [0.0] * 9, src=np.zeros((0, 4)), trunc_r=5.0)
     r = wos.wos_nodes(g, [[0.0, 0.0, 0.5]], 200_000, seed=3)
     v = _half_ball_escape(0.5, 5.0)
     assert abs(v - 1.5 * 0.5 / 5.0) < 0.01  # leading dipole term
