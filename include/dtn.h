@@ -61,7 +61,7 @@ typedef enum {
 } dtn_status;
 
 /* Domain kinds (walks run inside Omega). */
-enum { DTN_BALL = 0, DTN_BOX = 1, DTN_BOX_MINUS_BOXES = 2, DTN_HALF_SPACE = 3, DTN_DISK = 4 };
+enum { DTN_BALL = 0, DTN_BOX = 1, DTN_BOX_MINUS_BOXES = 2, DTN_HALF_SPACE = 3, DTN_DISK = 4, DTN_BALL_EXTERIOR = 5 };
 /* Dirichlet data kinds. */
 enum { DTN_DATA_HARMONIC_QUADRATIC = 0, DTN_DATA_POINT_SOURCES = 1 };
 /* Arithmetic of the walks and of the collocation solve. */
@@ -78,17 +78,21 @@ typedef struct dtn_plan_s *dtn_plan;         /* opaque, library-owned */
  *                             must lie inside it and not overlap.
  *   kind DTN_HALF_SPACE:      z > 0, boundary the plane z = 0 (the exterior
  *                             domain of Sec. 5.1.3).  A walk that reaches
- *                             the truncation sphere |x - ball_c| >= ball_r
+ *                             the truncation sphere |x - ball_c| >= trunc_r
  *                             (tested at its start and after every jump,
  *                             before the shell) has gone to infinity and
  *                             scores 0, the limit of data that vanish there
- *                             (Sec. 5.1.3 uses ball_r = 1e5).  Point sources
+ *                             (Sec. 5.1.3 uses trunc_r = 1e5).  Point sources
  *                             must lie in z < 0.
  *   kind DTN_DISK:            all of space minus the closed thin disk
  *                             {z = 0, x^2 + y^2 <= disk_r^2} (Sec. 5.1.3,
  *                             Test 4); the truncation sphere as for the
  *                             half space, which must enclose the disk.  Point
  *                             sources must lie off the disk.
+ *   kind DTN_BALL_EXTERIOR:   |x - ball_c| > ball_r (Sec. 5.2, the big
+ *                             sphere), the truncation sphere as for the half
+ *                             space (trunc_r > ball_r).  Point sources must
+ *                             lie inside the ball.
  *   data DTN_DATA_HARMONIC_QUADRATIC: phi = q0 + q1 x + q2 y + q3 z + q4 x^2
  *        + q5 y^2 + q6 z^2 + q7 xy + q8 yz + q9 xz, harmonic (q4+q5+q6 = 0).
  *   data DTN_DATA_POINT_SOURCES: phi = sum_k src[k].q / |x - src[k].xyz|,
@@ -111,7 +115,9 @@ typedef struct {
     double quad_coef[10];
     double eps;
     int64_t max_steps;
-    double disk_r; /* DTN_DISK: radius of the disk (other kinds: unused) */
+    double disk_r;  /* DTN_DISK: radius of the disk (other kinds: unused) */
+    double trunc_r; /* unbounded kinds: radius of the truncation sphere
+                       (centre ball_c); bounded kinds: unused */
 } dtn_geometry_desc;
 
 /* One boundary patch S with its hemisphere (Sec. 4, Fig. fig_biewos).
@@ -242,9 +248,12 @@ dtn_status dtn_wos_time_schedules(dtn_geometry g, const double *pts, int64_t n, 
  * curved patches, and the tile fit used by dtn_potential.  Built once on the
  * host and uploaded; the FP32 LU factors are computed on the device.
  *   patches  host [n_patches] (copied)
+ * On the sphere of DTN_BALL_EXTERIOR, n points to the centre and Gamma is
+ * the part of the sphere |y - c| = h outside the ball (more than a
+ * hemisphere), which must stay inside the truncation sphere.
  * Errors: DTN_E_ARG for a patch outside the supported layouts, a patch whose
  * hemisphere is not inside Omega's supported shapes (plane faces of a box,
- * or the sphere of a ball), or n_patches < 1. */
+ * or the sphere of a ball, inside or outside), or n_patches < 1. */
 dtn_status dtn_create_plan(dtn_geometry g, const dtn_patch *patches, int64_t n_patches, dtn_plan *out);
 void dtn_destroy_plan(dtn_plan p);
 /* Sizes of a plan: total nodes and total panels over its patches. */
@@ -415,7 +424,8 @@ dtn_status dtn_server_wait(dtn_server s, int64_t max_n, double timeout_s, dtn_qu
 
 /* Diagnostic, host only (no device needed): the class operators that
  * dtn_create_plan builds for patches with this layout and curvature, in local
- * coordinates scaled by 1/h (rr = R/h on a sphere of radius R, 0 on a plane).
+ * coordinates scaled by 1/h (rr = R/h on a sphere of radius R, -R/h outside
+ * a ball, 0 on a plane).
  * Outputs are host arrays (any may be NULL):
  *   node_tab [n_theta*n_phi][3], col_tab [P][3], K [P][P] (at h = 1),
  *   QI [P][n_theta*n_phi], A2 [P][n_theta*n_phi], fit [16][P];

@@ -297,20 +297,31 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
         if (!desc || !out) return fail(DTN_E_ARG, "dtn_create_geometry: NULL argument");
         *out = nullptr;
         const dtn_geometry_desc &d = *desc;
-        if (d.kind < DTN_BALL || d.kind > DTN_DISK) return fail(DTN_E_ARG, "dtn_create_geometry: bad kind");
+        if (d.kind < DTN_BALL || d.kind > DTN_BALL_EXTERIOR) return fail(DTN_E_ARG, "dtn_create_geometry: bad kind");
         if (d.data_kind != DTN_DATA_HARMONIC_QUADRATIC && d.data_kind != DTN_DATA_POINT_SOURCES)
             return fail(DTN_E_ARG, "dtn_create_geometry: bad data_kind");
         if (!(d.eps > 0.0)) return fail(DTN_E_ARG, "dtn_create_geometry: eps must be > 0");
         if (d.max_steps < 0) return fail(DTN_E_ARG, "dtn_create_geometry: max_steps < 0");
-        if ((d.kind == DTN_BALL || d.kind == DTN_HALF_SPACE || d.kind == DTN_DISK) && !(d.ball_r > 0.0))
+        const bool unbounded = d.kind == DTN_HALF_SPACE || d.kind == DTN_DISK || d.kind == DTN_BALL_EXTERIOR;
+        if ((d.kind == DTN_BALL || d.kind == DTN_BALL_EXTERIOR) && !(d.ball_r > 0.0))
             return fail(DTN_E_ARG, "dtn_create_geometry: ball_r <= 0");
+        if (unbounded && !(d.trunc_r > 0.0)) return fail(DTN_E_ARG, "dtn_create_geometry: trunc_r <= 0");
         if (d.kind == DTN_DISK) {
             if (!(d.disk_r > 0.0)) return fail(DTN_E_ARG, "dtn_create_geometry: disk_r <= 0");
             const double cc = std::sqrt(d.ball_c[0] * d.ball_c[0] + d.ball_c[1] * d.ball_c[1] +
                                         d.ball_c[2] * d.ball_c[2]);
-            if (!(cc + d.disk_r < d.ball_r))
+            if (!(cc + d.disk_r < d.trunc_r))
                 return fail(DTN_E_ARG, "dtn_create_geometry: the truncation sphere must enclose the disk");
         }
+        if (d.kind == DTN_BALL_EXTERIOR && !(d.ball_r < d.trunc_r))
+            return fail(DTN_E_ARG, "dtn_create_geometry: the truncation sphere must enclose the ball");
+        if (d.kind == DTN_BALL_EXTERIOR && d.data_kind == DTN_DATA_POINT_SOURCES)
+            for (int k = 0; k < d.n_src; ++k) {
+                const double *q = d.src + 4 * k;
+                const double dx = q[0] - d.ball_c[0], dy = q[1] - d.ball_c[1], dz = q[2] - d.ball_c[2];
+                if (!(dx * dx + dy * dy + dz * dz < d.ball_r * d.ball_r))
+                    return fail(DTN_E_ARG, "dtn_create_geometry: a source lies outside the ball");
+            }
         if (d.kind == DTN_BOX || d.kind == DTN_BOX_MINUS_BOXES)
             for (int k = 0; k < 3; ++k)
                 if (!(d.box_hi[k] > d.box_lo[k])) return fail(DTN_E_ARG, "dtn_create_geometry: empty box");
@@ -348,6 +359,7 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
         for (int k = 0; k < 10; ++k) g.dev.quad[k] = d.quad_coef[k];
         g.dev.eps = d.eps;
         g.dev.disk_r = d.kind == DTN_DISK ? d.disk_r : 0.0;
+        g.dev.trunc_r = unbounded ? d.trunc_r : 0.0;
         g.dev.max_steps = d.max_steps;
         const int nh = d.kind == DTN_BOX_MINUS_BOXES ? d.n_holes : 0;
         g.dev.n_holes = nh;
@@ -587,8 +599,10 @@ dtn_status dtn_create_plan(dtn_geometry g, const dtn_patch *patches, int64_t n_p
                 std::fabs(q.n[0] * q.t1[0] + q.n[1] * q.t1[1] + q.n[2] * q.t1[2]) > 1e-12)
                 return fail(DTN_E_ARG, at + "h <= 0 or frame (n, t1) not orthonormal");
             double rr = 0.0;
-            if (G.dev.kind == DTN_BALL) {
-                const double R = G.dev.r;
+            if (G.dev.kind == DTN_BALL || G.dev.kind == DTN_BALL_EXTERIOR) {
+                // outside the ball the domain's outward normal points to the
+                // centre and the class takes the signed radius -R/h
+                const double R = G.dev.r, e = G.dev.kind == DTN_BALL ? 1.0 : -1.0;
                 double v[3], rv = 0.0;
                 for (int k = 0; k < 3; ++k) {
                     v[k] = q.c[k] - G.dev.c[k];
@@ -597,9 +611,12 @@ dtn_status dtn_create_plan(dtn_geometry g, const dtn_patch *patches, int64_t n_p
                 rv = std::sqrt(rv);
                 if (std::fabs(rv - R) > 1e-12 * R) return fail(DTN_E_ARG, at + "centre is not on the sphere");
                 for (int k = 0; k < 3; ++k)
-                    if (std::fabs(v[k] / rv - q.n[k]) > 1e-12) return fail(DTN_E_ARG, at + "n is not the outward normal");
+                    if (std::fabs(e * v[k] / rv - q.n[k]) > 1e-12)
+                        return fail(DTN_E_ARG, at + "n is not the outward normal of the domain");
                 if (!(q.h <= R)) return fail(DTN_E_ARG, at + "h must not exceed the ball radius");
-                rr = R / q.h;
+                if (e < 0.0 && !(R + q.h < G.dev.trunc_r))
+                    return fail(DTN_E_ARG, at + "the hemisphere reaches the truncation sphere");
+                rr = e * R / q.h;
             } else {
                 std::string why;
                 if (!check_plane_patch(G, q, why)) return fail(DTN_E_ARG, at + why);
@@ -710,7 +727,7 @@ dtn_status dtn_class_operators(int32_t n_theta, int32_t n_phi, int32_t n_rings, 
         ops.n_sectors = n_sectors;
         ops.rr = rr;
         if (n_theta < 2 || n_theta > 32 || n_phi < 4 || n_phi > 64 || (n_phi & 1) || n_rings < 1 || n_rings > 16 ||
-            n_sectors < 2 || n_sectors > 32 || n_rings * n_sectors > 128 || rr < 0.0 || (rr > 0.0 && rr < 1.0))
+            n_sectors < 2 || n_sectors > 32 || n_rings * n_sectors > 128 || (rr != 0.0 && std::fabs(rr) < 1.0))
             return fail(DTN_E_ARG, "dtn_class_operators: unsupported layout");
         std::string err;
         if (!build_class_ops(ops, err)) return fail(DTN_E_ARG, "dtn_class_operators: " + err);

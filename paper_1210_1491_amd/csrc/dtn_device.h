@@ -205,7 +205,10 @@ constexpr int kHolesNoGrid = 16;  // internal kind, apart from the public ones
 constexpr bool has_holes(int kind) { return kind == DTN_BOX_MINUS_BOXES || kind == kHolesNoGrid; }
 // Unbounded domains: walks that reach the truncation sphere have gone to
 // infinity (score 0).
-constexpr bool has_truncation(int kind) { return kind == DTN_HALF_SPACE || kind == DTN_DISK; }
+constexpr bool has_truncation(int kind)
+{
+    return kind == DTN_HALF_SPACE || kind == DTN_DISK || kind == DTN_BALL_EXTERIOR;
+}
 
 // Union over the wave of the candidate holes of the cells of the lanes that
 // `take` (grid kind only).
@@ -259,6 +262,11 @@ __device__ __forceinline__ double dist_f64(const DevGeom &g, double x, double y,
         const double e = max_f64(rho - g.disk_r, 0.0);
         const double q = max_f64(fma(e, e, z * z), 0x1p-1000);
         return FAST ? q * __builtin_amdgcn_rsq(q) : sqrt_f64(q);
+    } else if constexpr (KIND == DTN_BALL_EXTERIOR) {
+        // outside the sphere: |x - c| - r from the correctly rounded root on
+        // both paths (the difference keeps the root's rounding in full)
+        const double dx = x - g.c[0], dy = y - g.c[1], dz = z - g.c[2];
+        return sqrt_f64(dx * dx + dy * dy + dz * dz) - g.r;
     } else if constexpr (KIND == DTN_BALL) {
         const double dx = x - g.c[0], dy = y - g.c[1], dz = z - g.c[2];
         return g.r - sqrt_f64(dx * dx + dy * dy + dz * dz);
@@ -325,7 +333,7 @@ __device__ __forceinline__ void project_f64(const DevGeom &g, double &x, double 
             y *= g.disk_r / rho;
         }
         z = 0.0;
-    } else if constexpr (KIND == DTN_BALL) {
+    } else if constexpr (KIND == DTN_BALL || KIND == DTN_BALL_EXTERIOR) {
         const double dx = x - g.c[0], dy = y - g.c[1], dz = z - g.c[2];
         const double r = sqrt(dx * dx + dy * dy + dz * dz);
         if (r > 0.0) {

@@ -38,6 +38,7 @@ struct DevGeom {
     double eps;
     int64_t max_steps;
     double disk_r;          // DTN_DISK: radius of the disk
+    double trunc_r;         // unbounded kinds: truncation sphere |x - c| = trunc_r
 };
 
 // Per-class operators on the device.  A class is a set of congruent patches

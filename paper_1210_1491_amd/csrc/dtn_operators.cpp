@@ -92,10 +92,16 @@ inline V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
 inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 inline double norm(V3 a) { return std::sqrt(dot(a, a)); }
 
-// Surface of S at parameters (s, a): plane (rr = 0) or sphere radius rr.
+// Surface of S at parameters (s, a): plane (rr = 0) or sphere of signed
+// radius rr (rr > 0: the domain inside the sphere, centre (0, 0, -rr);
+// rr < 0: outside it, centre (0, 0, |rr|)).  On the sphere s is the
+// geodesic angle from the patch centre, so every rule stays positively
+// oriented; n is the domain's outward normal (towards the centre outside).
 struct Surf {
     double rr;
-    double smax() const { return rr == 0.0 ? 1.0 : 2.0 * std::asin(0.5 / rr); }
+    double r() const { return std::fabs(rr); }
+    double side() const { return rr < 0.0 ? -1.0 : 1.0; }
+    double smax() const { return rr == 0.0 ? 1.0 : 2.0 * std::asin(0.5 / r()); }
     void at(double s, double a, V3 &y, V3 &n, double &jac) const
     {
         const double ca = std::cos(a), sa = std::sin(a);
@@ -104,15 +110,15 @@ struct Surf {
             n = {0.0, 0.0, 1.0};
             jac = s;
         } else {
-            const double ss = std::sin(s), cs = std::cos(s);
-            n = {ss * ca, ss * sa, cs};
-            y = {rr * n.x, rr * n.y, rr * n.z - rr};
-            jac = rr * rr * ss;
+            const double ss = std::sin(s), cs = std::cos(s), e = side(), R = r();
+            n = {e * ss * ca, e * ss * sa, cs};
+            y = {R * ss * ca, R * ss * sa, e * R * (cs - 1.0)};
+            jac = R * R * ss;
         }
     }
     // arc-length metric factors along s and a at parameter s
-    double gs() const { return rr == 0.0 ? 1.0 : rr; }
-    double ga(double s) const { return rr == 0.0 ? s : rr * std::sin(s); }
+    double gs() const { return rr == 0.0 ? 1.0 : r(); }
+    double ga(double s) const { return rr == 0.0 ? s : r() * std::sin(s); }
 };
 
 inline double green_ball(V3 x, V3 y)

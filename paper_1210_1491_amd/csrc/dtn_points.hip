@@ -146,7 +146,7 @@ bool point_ok(const Geometry &g, const dtn_point &q, std::string &why)
             return false;
         }
         const double dx = q.c[0] - g.dev.c[0], dy = q.c[1] - g.dev.c[1], dz = q.c[2] - g.dev.c[2];
-        if (std::sqrt(dx * dx + dy * dy + dz * dz) + q.a >= g.dev.r) {
+        if (std::sqrt(dx * dx + dy * dy + dz * dz) + q.a >= g.dev.trunc_r) {
             why = "hemisphere reaches the truncation sphere";
             return false;
         }
@@ -166,7 +166,7 @@ bool point_ok(const Geometry &g, const dtn_point &q, std::string &why)
             return false;
         }
         const double dx = q.c[0] - g.dev.c[0], dy = q.c[1] - g.dev.c[1], dz = q.c[2] - g.dev.c[2];
-        if (std::sqrt(dx * dx + dy * dy + dz * dz) + q.a >= g.dev.r) {
+        if (std::sqrt(dx * dx + dy * dy + dz * dz) + q.a >= g.dev.trunc_r) {
             why = "hemisphere reaches the truncation sphere";
             return false;
         }

@@ -25,7 +25,7 @@
 //                   order, so results do not depend on which wave ran which
 //                   chunk), write (count, mean, M2, steps) and capped count.
 //
-// Unbounded domains (half space, exterior of a disk): a walk that reaches the
+// Unbounded domains (half space, exterior of a disk or a ball): a walk that reaches the
 // truncation sphere has gone to infinity and scores 0 (Sec. 5.1.3); the
 // sphere is tested before the shell.  Such a walk is queued with z = +inf
 // (every other queued position is finite).
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
             uint64_t gone = 0;  // lanes at or beyond the truncation sphere
             if constexpr (has_truncation(KIND)) {
                 const double ex = x - g.c[0], ey = y - g.c[1], ez = z - g.c[2];
-                gone = __builtin_amdgcn_ballot_w64(ex * ex + ey * ey + ez * ez >= g.r * g.r);
+                gone = __builtin_amdgcn_ballot_w64(ex * ex + ey * ey + ez * ez >= g.trunc_r * g.trunc_r);
             }
             const uint64_t fm = wmask & (in_shell | gone | __builtin_amdgcn_ballot_w64(nstep >= cap));
             steps += (uint64_t)__popcll(wmask & ~fm);
@@ -564,6 +564,9 @@ hipError_t dispatch(const Geometry &g, const double *pts, int64_t n, const int64
     case DTN_DISK:
         return src ? run<DTN_DISK, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
                    : run<DTN_DISK, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
+    case DTN_BALL_EXTERIOR:
+        return src ? run<DTN_BALL_EXTERIOR, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
+                   : run<DTN_BALL_EXTERIOR, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
     default:
         if (!g.dev.cell_mask)
             return src ? run<kHolesNoGrid, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
@@ -611,6 +614,9 @@ void distance_kind(const Geometry &g, const double *pts, int64_t n, double *out,
         hipLaunchKernelGGL((k_distance<DTN_HALF_SPACE, FAST>), grid, block, 0, s, g.dev, pts, n, out);
         break;
     case DTN_DISK: hipLaunchKernelGGL((k_distance<DTN_DISK, FAST>), grid, block, 0, s, g.dev, pts, n, out); break;
+    case DTN_BALL_EXTERIOR:
+        hipLaunchKernelGGL((k_distance<DTN_BALL_EXTERIOR, FAST>), grid, block, 0, s, g.dev, pts, n, out);
+        break;
     default:
         if (g.dev.cell_mask)
             hipLaunchKernelGGL((k_distance<DTN_BOX_MINUS_BOXES, FAST>), grid, block, 0, s, g.dev, pts, n, out);

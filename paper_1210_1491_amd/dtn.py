@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libdtn.so")
 DTN_OK = 0
 STATUS = {0: "DTN_OK", -1: "DTN_E_ARG", -2: "DTN_E_DEVICE", -3: "DTN_E_OOM", -4: "DTN_E_UNSUPPORTED",
           -5: "DTN_E_NOCONV", -6: "DTN_E_MAXSTEPS"}
-KIND = {"ball": 0, "box": 1, "box_minus_boxes": 2, "half_space": 3, "disk": 4}
+KIND = {"ball": 0, "box": 1, "box_minus_boxes": 2, "half_space": 3, "disk": 4, "ball_exterior": 5}
 DATA = {"quadratic": 0, "sources": 1}
 PRECISION = {"fp64": 0, "fp32": 1, "fp32_mixed": 1}
 
@@ -33,7 +33,7 @@ class GeometryDesc(C.Structure):
                 ("ball_r", C.c_double), ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
                 ("n_holes", C.c_int32), ("n_src", C.c_int32), ("holes", C.POINTER(C.c_double)),
                 ("src", C.POINTER(C.c_double)), ("quad_coef", C.c_double * 10), ("eps", C.c_double),
-                ("max_steps", C.c_int64), ("disk_r", C.c_double)]
+                ("max_steps", C.c_int64), ("disk_r", C.c_double), ("trunc_r", C.c_double)]
 
 
 class PatchDesc(C.Structure):
@@ -193,6 +193,7 @@ class Geometry:
         d.eps = float(desc["eps"])
         d.max_steps = int(desc["max_steps"])
         d.disk_r = float(desc.get("disk_r", 0.0))
+        d.trunc_r = float(desc.get("trunc_r", 0.0))
         self.desc = desc
         self.handle = C.c_void_p()
         _check(lib().dtn_create_geometry(C.byref(d), C.byref(self.handle)), "dtn_create_geometry")

@@ -28,7 +28,8 @@ def test_library_exports_every_declared_symbol():
     assert "gfx950" in dtn.version()
 
 
-@pytest.mark.parametrize("layout", [(16, 32, 4, 16, 0.0), (8, 16, 4, 8, 5.0), (6, 12, 2, 8, 0.0)])
+@pytest.mark.parametrize("layout", [(16, 32, 4, 16, 0.0), (8, 16, 4, 8, 5.0), (6, 12, 2, 8, 0.0),
+                                    (16, 32, 4, 16, -3.0), (8, 16, 4, 8, -5.0)])
 def test_host_operators_agree_with_oracle(layout):
     from oracle import patch as OP
     from paper_1210_1491_amd import dtn
@@ -43,6 +44,8 @@ def test_host_operators_agree_with_oracle(layout):
     assert np.max(np.abs(ops["node_tab"] * h - Y)) < 1e-15
     A = np.linalg.solve(K, QI) * h
     np.testing.assert_allclose(ops["A2"], A * A, rtol=1e-9, atol=1e-14)
+    _, X, _, _ = OP.panels(h, R, nr, ns)
+    assert np.max(np.abs(ops["col_tab"] * h - X)) < 1e-15
 
 
 def test_host_operator_arguments_are_checked():
@@ -51,6 +54,8 @@ def test_host_operator_arguments_are_checked():
         dtn.class_operators(1, 16, 4, 8)
     with pytest.raises(dtn.DtnError):
         dtn.class_operators(8, 15, 4, 8)
+    with pytest.raises(dtn.DtnError):  # |R| < h on either side of a sphere
+        dtn.class_operators(8, 16, 4, 8, -0.5)
 
 
 def test_server_footprint_is_host_side_and_checked():

@@ -26,6 +26,7 @@ def _dtn():
 CASES = {
     "ball": (I.geometry_ball_quadratic, I.patches_ball_pole, None),
     "cube": (I.geometry_cube_sources, I.patches_cube_tiles, I.cube_tile_subset()),
+    "exterior": (I.geometry_ball_exterior, I.patches_big_sphere, None),
 }
 
 
@@ -36,7 +37,7 @@ def _setup(which):
     return gd, pd, OP.patches_from_desc(pd, gd)
 
 
-@pytest.mark.parametrize("which", ["ball", "cube"])
+@pytest.mark.parametrize("which", ["ball", "cube", "exterior"])
 def test_nodes_match_oracle(which):
     dtn = _dtn()
     gd, pd, ps = _setup(which)
@@ -54,7 +55,7 @@ def _stats_from_values(u, count, se):
     return np.column_stack([np.full_like(u, count), u, m2, np.zeros_like(u)])
 
 
-@pytest.mark.parametrize("which", ["ball", "cube"])
+@pytest.mark.parametrize("which", ["ball", "cube", "exterior"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_solve_matches_oracle_on_exact_node_values(which, precision):
     dtn = _dtn()
@@ -110,6 +111,55 @@ def test_full_pipeline_ball_matches_oracle_and_exact():
     trusted = ref["r"] < 0.7 * OP.s_max(p.h, p.R) * p.R
     err = OP.rel_l2(sig, ex, ref["area"], trusted)
     assert err < 5e-2, err
+
+
+def test_big_sphere_exterior_patch_section_5_2():
+    """Sec. 5.2: the patch at (0, 0, 3) outside the sphere of radius 3 with a
+    unit charge at the centre, a = 1, 1e4 walks per node: walk for walk
+    equal to the oracle's pipeline; the maximal relative error over the
+    panels with r < 0.7a below the paper's 1.25 %."""
+    dtn = _dtn()
+    gd, pd, ps = _setup("exterior")
+    p = ps[0]
+    walks = 10_000
+    print("[gpu] pipeline big sphere (exterior)", flush=True)
+    g = dtn.Geometry(gd)
+    plan = dtn.Plan(g, pd)
+    nodes = plan.nodes()
+    W = torch.full((plan.num_nodes,), walks, dtype=torch.int64, device="cuda")
+    stats, capped = dtn.wos_eval(g, nodes, W, seed=5)
+    sig, se = plan.solve(stats)
+    torch.cuda.synchronize()
+    sig, se = sig.cpu().numpy(), se.cpu().numpy()
+    assert int(capped.sum().item()) == 0
+    og = OW.Geometry(gd)
+    on, _ = OP.nodes_global(p)
+    orr = OW.wos_nodes(og, on, walks, seed=5)
+    ref = OP.patch_solve(p, og, orr["mean"], orr["se"])
+    assert np.max(np.abs(sig - ref["sigma"])) < 1e-2 * np.max(ref["se"])
+    np.testing.assert_allclose(se, ref["se"], rtol=1e-4)
+    ex = OP.exact_neumann(gd, ref["x"], ref["normal"])
+    trusted = ref["r"] < 0.7 * OP.s_max(p.h, p.R) * abs(p.R)
+    assert np.max(np.abs(sig[trusted] - ex[trusted]) / ex[trusted]) < 0.0125
+
+
+def test_exterior_plans_reject_bad_patches():
+    dtn = _dtn()
+    g = dtn.Geometry(I.geometry_ball_exterior())
+    good = I.patches_big_sphere()
+    dtn.Plan(g, good)
+    bad = I.patches_big_sphere()
+    bad["n"][0] = (0.0, 0.0, 1.0)               # the ball's outward normal, not the domain's
+    with pytest.raises(dtn.DtnError):
+        dtn.Plan(g, bad)
+    bad = I.patches_big_sphere(h=3.5)           # h > R
+    with pytest.raises(dtn.DtnError):
+        dtn.Plan(g, bad)
+    near = dtn.Geometry(dict(I.geometry_ball_exterior(), trunc_r=3.8))
+    with pytest.raises(dtn.DtnError):           # Gamma reaches the truncation sphere
+        dtn.Plan(near, I.patches_big_sphere())
+    with pytest.raises(dtn.DtnError):           # a source outside the ball
+        dtn.Geometry(dict(I.geometry_ball_exterior(), src=np.array([[0.0, 0.0, 4.0, 1.0]])))
 
 
 def test_potential_matches_oracle():

@@ -321,3 +321,31 @@ def test_disk_lower_face_and_rejections():
         dtn.Geometry(_disk(trunc_r=0.5))
     with pytest.raises(dtn.DtnError):      # no patch plans on unbounded domains
         dtn.Plan(g, I.patches_cube_tiles(m=1))
+
+
+# ------------------------------------------------ exterior of a ball (Sec. 5.2)
+
+def test_exterior_ball_walks_fp64_parity_and_fp32():
+    gd = I.geometry_ball_exterior()
+    rng = np.random.default_rng(41)
+    d = rng.standard_normal((150, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    pts = d * (3.0 + rng.exponential(0.8, 150))[:, None]
+    pts[0] = (0.0, 0.0, 3.0 + 4e-6)   # in the shell
+    pts[1] = (0.0, 0.0, 1.2e5)        # beyond the truncation sphere
+    walks = rng.integers(2, 1500, size=len(pts))
+    gpu = _gpu_wos(gd, pts, walks, seed=19)
+    ora = OW.wos_nodes(OW.Geometry(gd), pts, walks, seed=19)
+    _compare(gpu, ora)
+    np.testing.assert_array_equal(gpu["capped"], ora["capped"])
+    assert abs(gpu["mean"][1]) <= 1e-15 and gpu["steps"][1] == 0
+    # exact u = 1/|x| of the central charge, where the sample SE is a fair
+    # scale (at least 500 walks: with a handful of walks it is heavy-tailed)
+    se = np.sqrt(gpu["m2"] / np.maximum(gpu["count"] - 1, 1) / np.maximum(gpu["count"], 1))
+    ok = (se > 0) & (gpu["count"] >= 500)
+    z = (gpu["mean"][ok] - 1.0 / np.linalg.norm(pts[ok], axis=1)) / se[ok]
+    assert np.all(np.abs(z) < 4.5)
+    g32 = _gpu_wos(gd, pts[2:66], 20_000, seed=3, precision="fp32")
+    o32 = OW.wos_nodes(OW.Geometry(gd), pts[2:66], 20_000, seed=3)
+    _compare(g32, o32, exact_walks=False)
+
