@@ -84,6 +84,17 @@ DISK_STEP_OPS = {
              "mad64": 10, "rsq64": 2},
 }
 DISK_WALK_OPS = {"f64": 14, "f64fma": 12, "rsq64": 2, "i32": 8}
+# Exterior of a ball: the distance is |x - c| - R (3 differences, a product
+# and 2 FMAs, the correctly rounded root: 4 f64 + 4 FMA + rsq, the
+# difference), the sphere test as for the half space.  Per walk: the
+# projection onto the sphere (root, quotient, 3 FMAs), one source, the shift
+# and the sums.
+EXT_STEP_OPS = {
+    "fp64": {"f64": 27 - 11 + 9 + 5, "f64fma": 17 + 6 + 2, "i32": 16, "mad64": 10, "cvt": 2, "rsq64": 1 + 1},
+    "fp32": {"f64": 13 - 11 + 9 + 5, "f64fma": 3 + 6 + 2, "f32": 8, "trans32": 3, "cvt": 3, "i32": 15,
+             "mad64": 10, "rsq64": 1},
+}
+EXT_WALK_OPS = {"f64": 16, "f64fma": 14, "rsq64": 2, "i32": 8}
 
 
 def slots(ops):
@@ -96,6 +107,8 @@ HS_SLOTS_PER_STEP = {k: slots(v) for k, v in HS_STEP_OPS.items()}
 HS_SLOTS_PER_WALK = slots(HS_WALK_OPS)
 DISK_SLOTS_PER_STEP = {k: slots(v) for k, v in DISK_STEP_OPS.items()}
 DISK_SLOTS_PER_WALK = slots(DISK_WALK_OPS)
+EXT_SLOTS_PER_STEP = {k: slots(v) for k, v in EXT_STEP_OPS.items()}
+EXT_SLOTS_PER_WALK = slots(EXT_WALK_OPS)
 
 # HBM traffic of the walk kernel on the unit-cube workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs, each scaled by the same counter on a plain
@@ -212,7 +225,8 @@ def parse():
     ap.add_argument("--serving-rate", type=float, default=200.0, help="offered load, queries/s")
     ap.add_argument("--no-halfspace", action="store_true", help="skip the single-point half-space workload")
     ap.add_argument("--no-disk", action="store_true", help="skip the thin-disk workload (Table 5)")
-    ap.add_argument("--only", choices=["cube", "box_holes", "serving", "halfspace", "disk"], default=None,
+    ap.add_argument("--no-exterior", action="store_true", help="skip the exterior-sphere workload (Sec. 5.2)")
+    ap.add_argument("--only", choices=["cube", "box_holes", "serving", "halfspace", "disk", "exterior"], default=None,
                     help="run one workload only (for profiling)")
     ap.add_argument("--box-holes-se", type=float, default=None,
                     help="target standard error of the uneven-batching workload (default: its 1e-3)")
@@ -568,6 +582,135 @@ def disk(precision, steps, warmup, with_cpu=True, cpu_points=64, reps=20):
     return res
 
 
+def sphere_exterior(precision, steps, warmup, with_cpu=True, cpu_patches=8):
+    """Patches outside a ball (Sec. 5.2's big sphere: R = 3, unit charge at
+    the centre, exact du/dn = 1/9 with the domain's normal).  Sec. 5.2 itself:
+    the patch at (0, 0, 3) with a = 1, 16x32 nodes x 1e4 walks, 64 panels,
+    its maximal relative error over r < 0.7a (the paper: below 1.25 %).
+    Throughput: 2048 patches (h = 0.5, 8x16 nodes, 4x8 panels) on a
+    Fibonacci lattice of the sphere, 1e4 walks per node, walks + solve per
+    step; the walk kernel's ALU fraction; the oracle on a sample of patches
+    with the GPU's stream ids."""
+    import torch
+
+    import dtn_inputs as I
+    from paper_1210_1491_amd import dtn
+
+    cfg = I.CONFIGS["sphere_exterior"]
+    gd = cfg["geometry"]()
+    g = dtn.Geometry(gd)
+    # Sec. 5.2
+    pd1 = I.patches_big_sphere()
+    plan1 = dtn.Plan(g, pd1)
+    n1 = plan1.nodes()
+    st1, _ = dtn.wos_eval(g, n1, torch.full((plan1.num_nodes,), 10_000, dtype=torch.int64, device="cuda"), 5,
+                          precision=precision)
+    s1, e1 = plan1.solve(st1, precision=precision)
+    x1, _, a1, r1 = plane_or_sphere_panels(pd1, -gd["ball_r"])
+    s1 = s1.cpu().numpy()
+    tr1 = r1 < 0.7 * 1.0
+    sec52 = {"max_rel_err_r_lt_0.7a": float(np.max(np.abs(s1[tr1] - 1.0 / 9.0)) * 9.0),
+             "rel_l2_r_lt_0.7a": rel_l2(s1, np.full_like(s1, 1.0 / 9.0), a1, tr1),
+             "median_se_rel": float(np.median(e1.cpu().numpy()[tr1]) * 9.0), "paper_bar": 0.0125}
+    print(f"[bench] sec 5.2 max rel err {sec52['max_rel_err_r_lt_0.7a']:.4f}", file=sys.stderr, flush=True)
+    # throughput
+    pd = cfg["patches"](cfg["n_patches"], seed=cfg["seed"])
+    plan = dtn.Plan(g, pd)
+    N, Pn = plan.num_nodes, plan.num_panels
+    nodes = plan.nodes()
+    walks = torch.full((N,), cfg["walks"], dtype=torch.int64, device="cuda")
+    stats = torch.empty((N, 4), dtype=torch.float64, device="cuda")
+    capped = torch.empty(N, dtype=torch.int64, device="cuda")
+    neu = torch.empty(Pn, dtype=torch.float64, device="cuda")
+    nse = torch.empty(Pn, dtype=torch.float64, device="cuda")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def step(record):
+        plan.nodes(out=nodes)
+        if record:
+            ev0.record()
+        dtn.wos_eval(g, nodes, walks, cfg["seed"], precision=precision, stats=stats, capped=capped)
+        if record:
+            ev1.record()
+        plan.solve(stats, precision=precision, neumann=neu, neumann_se=nse)
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    wos_ms = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+        torch.cuda.synchronize()
+        wos_ms.append(ev0.elapsed_time(ev1))
+    sec = (time.perf_counter() - t0) / steps
+    print(f"[bench] sphere exterior {precision}: {sec * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+    st = stats.cpu().numpy()
+    walks_n, steps_n = float(st[:, 0].sum()), float(st[:, 3].sum())
+    wos_s = float(np.mean(wos_ms)) / 1e3
+    achieved = (EXT_SLOTS_PER_STEP[precision] * steps_n + EXT_SLOTS_PER_WALK * walks_n) / wos_s
+    _, _, area, rc = plane_or_sphere_panels(pd, -gd["ball_r"])
+    hh = np.repeat(np.asarray(pd["h"], np.float64), np.asarray(pd["n_rings"]) * np.asarray(pd["n_sectors"]))
+    tr = rc < 0.7 * hh
+    sig = neu.cpu().numpy()
+    res = {"workload": f"outside the sphere R = 3 (unit charge at the centre), {cfg['n_patches']} patches (h = 0.5, "
+                       f"8x16 nodes, 32 panels) x {cfg['walks']} walks, truncation 1e5, eps 1e-5",
+           "precision": precision, "ms_per_step": sec * 1e3, "patches_per_s": cfg["n_patches"] / sec,
+           "walks_per_s": walks_n / sec, "walk_steps_per_s": steps_n / sec, "steps_per_walk": steps_n / walks_n,
+           "wos_kernel_ms": float(np.mean(wos_ms)), "capped_walks": int(capped.sum().item()),
+           "neumann_rel_l2_vs_exact": rel_l2(sig, np.full_like(sig, 1.0 / 9.0), area, tr),
+           "propagated_noise_rel_l2": float(np.sqrt(np.sum(area[tr] * nse.cpu().numpy()[tr] ** 2)
+                                                    / np.sum(area[tr] / 81.0))),
+           "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK / 1e12,
+                        "unit": "T lane-op slots/s", "frac": achieved / ALU_PEAK,
+                        "slots_per_step": EXT_SLOTS_PER_STEP[precision], "slots_per_walk": EXT_SLOTS_PER_WALK},
+           "section_5_2": sec52}
+    if with_cpu:
+        res["cpu_baseline"] = exterior_cpu_baseline(gd, pd, cfg, st, cpu_patches)
+    return res
+
+
+def plane_or_sphere_panels(pd, R):
+    """Panel areas and centre chord distances for patches on a sphere of
+    radius |R| (the layout of include/dtn.h: uniform rings in the geodesic
+    angle, parametric centres); returns (None, None, area, r)."""
+    A, Rc = [], []
+    r = abs(R)
+    for i in range(len(pd["h"])):
+        h = float(pd["h"][i])
+        nr, ns = int(pd["n_rings"][i]), int(pd["n_sectors"][i])
+        sm = 2.0 * np.arcsin(h / (2.0 * r))
+        se = sm * np.arange(nr + 1) / nr
+        s0, s1 = np.repeat(se[:-1], ns), np.repeat(se[1:], ns)
+        sc = 0.5 * (s0 + s1)
+        A.append(r * r * (np.cos(s0) - np.cos(s1)) * (2 * np.pi / ns))
+        Rc.append(2.0 * r * np.sin(0.5 * sc))
+    return None, None, np.concatenate(A), np.concatenate(Rc)
+
+
+def exterior_cpu_baseline(gd, pd, cfg, gpu_stats, n_sample):
+    """CPU baseline of the exterior workload: the oracle's walks at the nodes
+    of the first n_sample patches with the stream ids the GPU run gave them
+    (node index), so the node means can be compared one by one."""
+    from oracle import patch as OP
+    from oracle import wos as OW
+    import dtn_inputs as I
+    sub = I.subset_patches(pd, list(range(n_sample)))
+    nodes = np.concatenate([OP.nodes_global(p)[0] for p in OP.patches_from_desc(sub, gd)])
+    sid = np.arange(len(nodes), dtype=np.uint32)
+    t0 = time.perf_counter()
+    r = OW.wos_nodes(OW.Geometry(gd), nodes, cfg["walks"], seed=cfg["seed"], stream_id=sid)
+    dt = time.perf_counter() - t0
+    g = gpu_stats[: len(nodes)]
+    gse = np.sqrt(g[:, 2] / (g[:, 0] - 1) / g[:, 0])
+    z = np.abs(g[:, 1] - r["mean"]) / np.sqrt(gse ** 2 + r["se"] ** 2)
+    walks = float(r["count"].sum())
+    return {"value": walks / dt, "unit": "walks/s", "cores": OW.max_threads(), "kind": "oracle",
+            "sample": f"nodes of the first {n_sample} patches ({len(nodes)} nodes, {walks:.3g} walks) in {dt:.1f} s",
+            "gpu_same_sample": {"max_z": float(z.max()),
+                                "median_rel_diff": float(np.median(np.abs(g[:, 1] - r["mean"]) / r["mean"]))}}
+
+
 def halfspace_cpu_baseline(gd, x, nrm, t1, a, cfg, gpu_out, n_sample):
     """CPU baseline of a single-point workload (half space or disk): the oracle on the first
     n_sample points with the stream ids the GPU run gave their nodes (node
@@ -811,6 +954,10 @@ def main():
         print(json.dumps({"serving": serving("fp32", args.serving_window, args.serving_rate, args.serving_se_range,
                                              sweep_window=args.serving_sweep_window)}), flush=True)
         return
+    if args.only == "exterior":
+        print(json.dumps({"sphere_exterior": sphere_exterior(args.precision, args.steps, args.warmup,
+                                                             not args.no_cpu_baseline)}), flush=True)
+        return
     if args.only == "disk":
         print(json.dumps({"disk": disk(args.precision, args.steps, args.warmup, not args.no_cpu_baseline)}),
               flush=True)
@@ -885,6 +1032,8 @@ def main():
         line["halfspace_points"] = halfspace_points("fp64", 1, 1, not args.no_cpu_baseline)
     if args.only is None and not args.no_disk:
         line["disk"] = disk("fp64", 1, 1, not args.no_cpu_baseline)
+    if args.only is None and not args.no_exterior:
+        line["sphere_exterior"] = sphere_exterior("fp64", 1, 1, not args.no_cpu_baseline)
     if args.only is None and not args.no_serving:
         line["serving"] = serving("fp32", args.serving_window, args.serving_rate, args.serving_se_range,
                                   sweep_window=args.serving_sweep_window)

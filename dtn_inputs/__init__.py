@@ -434,6 +434,13 @@ def serving_queries(gd, n_queries=600, rate=200.0, seed=5, max_points=4096, se_r
 # ----------------------------------------------------------------- configs
 
 CONFIGS = {
+    "sphere_exterior": {  # Sec. 5.2 scaled: 2048 patches outside the sphere R = 3, 1e4 walks per node
+        "geometry": geometry_ball_exterior,
+        "patches": patches_sphere_exterior,
+        "n_patches": 2048,
+        "walks": 10_000,
+        "seed": 9,
+    },
     "disk_points": {  # Test 4 scaled to many points on both faces: 20x20 nodes, 1e3 walks each
         "geometry": geometry_disk,
         "points": disk_points,

@@ -261,3 +261,34 @@ def test_disk_points_full_size():
     z = (out[:, 0] - exact) / out[:, 1]
     print(f"[gpu] mean |z| {np.mean(np.abs(z)):.3f}, within 3 se {np.mean(np.abs(z) < 3):.4f}", flush=True)
     assert np.mean(np.abs(z)) < 1.0 and np.mean(np.abs(z) < 3) > 0.99
+
+
+@pytest.mark.timeout(300)
+def test_sphere_exterior_full_size():
+    """The exterior-sphere workload at its full size (2048 patches x 128
+    nodes x 1e4 walks, the benchmark's launch): sampled nodes recomputed by
+    the oracle with the launch's stream ids (walk for walk), and the Neumann
+    data within the propagated noise of the exact 1/9."""
+    from paper_1210_1491_amd import dtn
+    cfg = I.CONFIGS["sphere_exterior"]
+    gd = cfg["geometry"]()
+    pd = cfg["patches"](cfg["n_patches"], seed=cfg["seed"])
+    print("[gpu] full exterior-sphere workload", flush=True)
+    g = dtn.Geometry(gd)
+    plan = dtn.Plan(g, pd)
+    nodes = plan.nodes()
+    W = torch.full((plan.num_nodes,), cfg["walks"], dtype=torch.int64, device="cuda")
+    stats, capped = dtn.wos_eval(g, nodes, W, cfg["seed"])
+    sig, se = plan.solve(stats)
+    st, sig, se = stats.cpu().numpy(), sig.cpu().numpy(), se.cpu().numpy()
+    assert int(capped.sum().item()) == 0
+    ps = OP.patches_from_desc(pd, gd)
+    sample = np.array([5, 70_000, plan.num_nodes - 1])
+    on = np.concatenate([OP.nodes_global(ps[i // 128])[0][[i % 128]] for i in sample])
+    assert np.max(np.abs(on - nodes.cpu().numpy()[sample])) < 1e-14
+    o = OW.wos_nodes(OW.Geometry(gd), on, cfg["walks"], seed=cfg["seed"], stream_id=sample.astype(np.uint32))
+    gse = np.sqrt(st[sample, 2] / (st[sample, 0] - 1) / st[sample, 0])
+    assert np.all(np.abs(st[sample, 1] - o["mean"]) < 0.05 * np.sqrt(gse ** 2 + o["se"] ** 2))
+    z = (sig - 1.0 / 9.0) / se
+    print(f"[gpu] mean |z| {np.mean(np.abs(z)):.3f}", flush=True)
+    assert np.mean(np.abs(z)) < 2.0
