@@ -116,13 +116,13 @@ EXT_SLOTS_PER_WALK = slots(EXT_WALK_OPS)
 # the kernel sources it was measured on (SHA-256 of these files).
 TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_amd/csrc/dtn_device.h",
                      "paper_1210_1491_amd/csrc/dtn_internal.h"],
-           "sha256": ["cfc1fefdaa6c8ff15a725922e90596be36fc14d0046d2456454b7d85751b83e3",
-                      "dea1f750bdeed5412dcfbb6682f2f0ca948c92a965b9a2ae890f32fdeacfc490",
-                      "6027597fc35d2c2a06441b4edb4d7c8fa4f45273c1a688c783f159eb1a0ac103"],
-           "fetch_bytes": 71753.188 * 1024 * (262144 / 131089.938), "write_bytes": 43008.0 * 1024 * 1.00,
+           "sha256": ["bebedd82506e67d55dcb625cc8c527702c4c0ea179c46fed9c2cb6b488806f73",
+                      "6a1675eaf8869631fee8f9a58747a3423500e1bbb7b205e83c5e42f8e2918dd3",
+                      "0c2fed8fed7ff085b27db5a6564efe0a22145418aa7cb64978a0a8bd3a13ffe0"],
+           "fetch_bytes": 71753.25 * 1024 * (262144 / 131088.938), "write_bytes": 43008.0 * 1024 * 1.00,
            # the half-space point workload's walk kernel (same sources), scaled
-           # by the copy in its own run (fetch 131086.25 KiB for 262144)
-           "halfspace_fetch_bytes": 156226.125 * 1024 * (262144 / 131086.25),
+           # by the copy in its own run (fetch 131086.688 KiB for 262144)
+           "halfspace_fetch_bytes": 156228.875 * 1024 * (262144 / 131086.688),
            "halfspace_write_bytes": 89600.0 * 1024 * 1.00}
 
 
