@@ -475,6 +475,14 @@ def halfspace_points(precision, steps, warmup, with_cpu=True, cpu_points=128):
     res["table1"] = {"a": radii.tolist(), "sigma1": to[:, 2].tolist(), "sigma2": to[:, 3].tolist(),
                      "total": to[:, 0].tolist(), "se": to[:, 1].tolist(),
                      "err_pct": (100 * (to[:, 0] - ex1) / ex1).tolist(), "analytic": ex1}
+    # Table 2: Sigma2' at x = (0.5, 0, 0), a = 0.5, by rule size and delta/a
+    t2 = {}
+    zero = torch.zeros((1, 4), dtype=torch.float64, device="cuda")
+    for drel in (1e-4, 1e-5, 1e-6):
+        t2[f"{drel:g}"] = [float(dtn.Points(g, [[0.5, 0.0, 0.0]], [[0.0, 0.0, -1.0]], [[1.0, 0.0, 0.0]], [0.5], 1,
+                                            ng, drel).neumann(zero).cpu().numpy()[0, 3]) for ng in (4, 6, 10, 20)]
+    res["table2"] = {"n_g2": [4, 6, 10, 20], "sigma2_by_delta_rel": t2,
+                     "paper_1e-6": [0.10087, 0.09338, 0.09306, 0.09305]}
     if with_cpu:
         res["cpu_baseline"] = halfspace_cpu_baseline(gd, x, nrm, t1, a, cfg, o, cpu_points)
     return res

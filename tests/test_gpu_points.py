@@ -349,3 +349,26 @@ def test_exterior_ball_walks_fp64_parity_and_fp32():
     o32 = OW.wos_nodes(OW.Geometry(gd), pts[2:66], 20_000, seed=3)
     _compare(g32, o32, exact_walks=False)
 
+
+
+def test_table2_on_the_gpu():
+    """Table 2: Sigma2' at (0.5, 0, 0), a = 0.5, by the library's ring rule
+    for N_g2 = 4, 6, 10, 20 and delta/a = 1e-4 .. 1e-6, against the printed
+    values (the rows pinned for the oracle) and against the oracle."""
+    import os
+    dtn = _dtn()
+    g = dtn.Geometry(_hs())
+    og = OW.Geometry(_hs())
+    tab = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "table2_sigma2.txt"), comments="#")
+    for row in tab:
+        drel = row[0]
+        if drel > 1e-4:
+            continue
+        for ng, want in zip((4, 6, 10, 20), row[1:]):
+            P = dtn.Points(g, [X0], [N_DOWN], [T1], [0.5], n_g1=1, n_g2=ng, delta_rel=drel)
+            st = torch.tensor([[0.0, 0.0, 0.0, 0.0]], dtype=torch.float64, device="cuda")
+            s2 = float(P.neumann(st).cpu().numpy()[0, 3])
+            tol = 1e-5 if drel <= 1e-5 else 2e-5
+            assert abs(s2 - want) <= tol, (drel, ng, s2, want)
+            ref = OPt.sigma2(og.phi, X0, N_DOWN, T1, 0.5, ng, drel)
+            assert abs(s2 - ref) <= OPt.sigma2_rounding_bound(og.phi, X0, N_DOWN, T1, 0.5, ng, drel)
