@@ -276,6 +276,21 @@ dtn_status dtn_patch_nodes(dtn_plan p, double *nodes, void *stream);
 dtn_status dtn_patch_solve(dtn_plan p, const double *node_stats, int32_t precision, double *neumann,
                            double *neumann_se, void *stream);
 
+/* Step 2 by the second-kind equation (Sec. 4, eqs. bw53-bw59) on plans whose
+ * patches are all flat: there the adjoint double layer D of the ball's
+ * Green's function vanishes, so (1/2 I - D) sigma = b gives sigma = 2b with
+ * no linear solve, at the same collocation points as dtn_patch_solve:
+ *   b(x) = int_Gamma dP/dn_x (u - phi(x)) - int_S d2G/dn_x dn_y (phi - phi(x)),
+ * P the ball's Poisson kernel, u on Gamma the interpolant of the node means,
+ * the hypersingular S integral regularised by the constant solution and taken
+ * outside the disk of radius 1e-6 h around x (eq. bw82's O(delta) error).
+ * SE(sigma) = 2 sqrt(sum_k Q2_ik^2 SE_k^2) / h.  FP64.
+ *   node_stats device [num_nodes][4]; neumann device [num_panels] out;
+ *   neumann_se device [num_panels] out, or NULL.
+ * Errors: DTN_E_ARG (NULL), DTN_E_UNSUPPORTED (a curved patch). */
+dtn_status dtn_patch_solve_second_kind(dtn_plan p, const double *node_stats, double *neumann, double *neumann_se,
+                                       void *stream);
+
 /* u at m targets off the boundary by eq. bw03 (G = 1/(4 pi |x - y|)).
  * Requires every patch to be a square tile [-h,h]^2 of a box face (tiles
  * covering the boundary, as produced by splitting each face into squares):
@@ -432,6 +447,12 @@ dtn_status dtn_server_wait(dtn_server s, int64_t max_n, double timeout_s, dtn_qu
  *   P = n_rings*n_sectors.  Lets a caller inspect or test step 2's operators. */
 dtn_status dtn_class_operators(int32_t n_theta, int32_t n_phi, int32_t n_rings, int32_t n_sectors, double rr,
                                double *node_tab, double *col_tab, double *K, double *QI, double *A2, double *fit);
+
+/* Host diagnostic: the second-kind tables of a flat class at h = 1 (no
+ * device): Q2 [P][N] (the Gamma operator with the kernel dP/dn_x) and c2 [P]
+ * (sum_k Q2_ik minus the sum of the S rule's weights).  Host arrays. */
+dtn_status dtn_class_second_kind(int32_t n_theta, int32_t n_phi, int32_t n_rings, int32_t n_sectors, double *Q2,
+                                 double *c2);
 
 #ifdef __cplusplus
 }

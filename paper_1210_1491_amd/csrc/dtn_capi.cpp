@@ -93,7 +93,12 @@ dtn_status get_class(const ClassKey &key, int device, DevClass &out, bool &fresh
     UP(fit, fit)
     UP(tile_gl, tile_gl)
     UP(ans_row, ans_row)
+    UP(Q2, Q2)
+    UP(s_pts, s_pts)
+    UP(s_w, s_w)
+    UP(c2, c2)
 #undef UP
+    d.n_s = ops.n_s;
     if (e == hipSuccess) {
         e = upload(ops.piv, &ip);
         d.piv = ip;
@@ -705,6 +710,20 @@ dtn_status dtn_patch_solve(dtn_plan p, const double *node_stats, int32_t precisi
     return launch_solve(p->p, node_stats, precision, neumann, neumann_se, (hipStream_t)stream);
 }
 
+dtn_status dtn_patch_solve_second_kind(dtn_plan p, const double *node_stats, double *neumann, double *neumann_se,
+                                       void *stream)
+{
+    try {
+        if (!p || !node_stats || !neumann) return fail(DTN_E_ARG, "dtn_patch_solve_second_kind: NULL argument");
+        for (const PlanClassHost &c : p->p.classes)
+            if (!c.dev.Q2)
+                return fail(DTN_E_UNSUPPORTED, "dtn_patch_solve_second_kind: flat patches only (a patch is curved)");
+        return launch_solve2(p->p, node_stats, neumann, neumann_se, (hipStream_t)stream);
+    } catch (...) {
+        return fail(DTN_E_DEVICE, "dtn_patch_solve_second_kind: exception");
+    }
+}
+
 dtn_status dtn_potential(dtn_plan p, const double *neumann, const double *targets, int64_t m, double *u_out,
                          void *stream)
 {
@@ -747,3 +766,27 @@ dtn_status dtn_class_operators(int32_t n_theta, int32_t n_phi, int32_t n_rings, 
 }
 
 }  // extern "C"
+
+dtn_status dtn_class_second_kind(int32_t n_theta, int32_t n_phi, int32_t n_rings, int32_t n_sectors, double *Q2,
+                                 double *c2)
+{
+    try {
+        if (!Q2 || !c2) return fail(DTN_E_ARG, "dtn_class_second_kind: NULL argument");
+        if (n_theta < 2 || n_theta > 32 || n_phi < 4 || n_phi > 64 || (n_phi & 1) || n_rings < 1 || n_rings > 16 ||
+            n_sectors < 2 || n_sectors > 32 || n_rings * n_sectors > 128)
+            return fail(DTN_E_ARG, "dtn_class_second_kind: unsupported layout");
+        dtn::ClassOps ops;
+        ops.n_theta = n_theta;
+        ops.n_phi = n_phi;
+        ops.n_rings = n_rings;
+        ops.n_sectors = n_sectors;
+        ops.rr = 0.0;
+        std::string err;
+        if (!dtn::build_class_ops(ops, err)) return dtn::fail(DTN_E_ARG, "dtn_class_second_kind: " + err);
+        std::copy(ops.Q2.begin(), ops.Q2.end(), Q2);
+        std::copy(ops.c2.begin(), ops.c2.end(), c2);
+        return DTN_OK;
+    } catch (...) {
+        return dtn::fail(DTN_E_OOM, "dtn_class_second_kind: exception");
+    }
+}

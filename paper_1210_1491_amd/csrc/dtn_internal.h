@@ -63,6 +63,13 @@ struct DevClass {
     const double *fit;        // [16][n_panels] tile fit (flat classes)
     const double *tile_gl;    // [16][3]: (xi, eta, weight) on [-1,1]^2
     const double *ans_row;    // [n_nodes]: ring-0 mean of the rows of K^-1 QI at h = 1
+    // second-kind equation on flat classes (NULL on curved ones), at h = 1
+    // (scale 1/h): sigma_i = 2 (Q2 u - sum_q s_w phi(s_pts) - c2 phi(x_i))
+    const double *Q2;         // [n_panels][n_nodes]: Gamma operator with the kernel dP/dn_x
+    const double *s_pts;      // [n_panels][n_s][3]: local points / h of the regularised S rule
+    const double *s_w;        // [n_panels][n_s]: weights x kernel of that rule
+    const double *c2;         // [n_panels]: sum_k Q2_ik - sum_q s_w_iq
+    int32_t n_s;
 };
 
 struct Geometry {
@@ -134,6 +141,9 @@ dtn_status launch_solve(const Plan &p, const double *node_stats, int precision, 
 dtn_status launch_potential(const Plan &p, const double *neumann, const double *targets, int64_t m,
                             double *u_out, hipStream_t stream);
 dtn_status launch_lu32(const Plan &p, hipStream_t stream);
+// Second-kind equation on flat patches (sigma = 2b, no solve).
+dtn_status launch_solve2(const Plan &p, const double *node_stats, double *neumann, double *neumann_se,
+                         hipStream_t stream);
 
 // Plan helpers shared with the query server (dtn_capi.cpp).
 bool plane_patch_ok(const Geometry &g, const dtn_patch &p, std::string &why);
@@ -156,8 +166,9 @@ struct ClassOps {
     int n_theta, n_phi, n_rings, n_sectors;
     double rr;  // R/h (0 = plane)
     std::vector<double> node_tab, col_tab, K, LU, QI, A2, dl_pts, dl_w, fit, tile_gl, ans_row;
+    std::vector<double> Q2, s_pts, s_w, c2;  // second kind, flat classes only
     std::vector<int32_t> piv;
-    int n_dl = 0;
+    int n_dl = 0, n_s = 0;
 };
 bool build_class_ops(ClassOps &ops, std::string &err);
 // Gauss-Legendre abscissae and weights on [-1, 1] (Newton on the recurrence).

@@ -293,6 +293,79 @@ void lu_solve(int n, const std::vector<double> &LU, const std::vector<int32_t> &
 
 }  // namespace
 
+// ---- second-kind equation on a flat patch (eqs. bw53-bw59), at h = 1.
+// With S in the plane through the ball's centre, dG_B/dn_x vanishes for x, y
+// on S (D = 0), so sigma = 2b.  The Gamma kernel is dP/dn_x =
+// 3 (1 - |x|^2) y.n / (4 pi r^5); the S kernel d2G_B/dn_x dn_y =
+// 1/(4 pi r^3) - 1/(4 pi Dimg^{3/2}), Dimg = |x|^2 |y|^2 - 2 x.y + 1.  The
+// hypersingular S integral is regularised by the constant solution (as in
+// Sec. 5.1, eqs. bw63-bw68) and taken outside the disk of radius
+// kSecondKindDelta around x: Gauss in the angle, and along each ray a
+// logarithmic substitution rho = lo (hi / lo)^tau in two pieces (split at
+// the geometric mean of delta and the rim distance), Gauss in tau, so that
+// the 1/rho part of the integrand is integrated exactly and its angle sum
+// cancels.
+constexpr double kSecondKindDelta = 1e-6;
+constexpr int kSecondKindRule = 20;  // Gauss points in the angle and per piece along a ray
+
+inline double dpoisson_dnx(V3 x, V3 y)
+{
+    const double r = norm(sub(x, y));
+    return 3.0 * (1.0 - dot(x, x)) * y.z / (4.0 * kPi * r * r * r * r * r);
+}
+
+inline double ddgreen_s(V3 x, V3 y)
+{
+    const double r = norm(sub(x, y));
+    const double D = dot(x, x) * dot(y, y) - 2.0 * dot(x, y) + 1.0;
+    return 1.0 / (4.0 * kPi * r * r * r) - 1.0 / (4.0 * kPi * D * std::sqrt(D));
+}
+
+template <class Rows>
+void second_kind_tables(ClassOps &ops, const std::vector<V3> &X, Rows &gamma_rows)
+{
+    const int Np = ops.n_rings * ops.n_sectors, Nn = ops.n_theta * ops.n_phi;
+    gamma_rows([](V3 x, V3 y) { return dpoisson_dnx(x, y); }, ops.Q2);
+    const int n = kSecondKindRule;
+    std::vector<double> gx, gw;
+    gauss_legendre(n, gx, gw);
+    ops.n_s = 2 * n * n;
+    ops.s_pts.assign((size_t)Np * ops.n_s * 3, 0.0);
+    ops.s_w.assign((size_t)Np * ops.n_s, 0.0);
+    ops.c2.assign(Np, 0.0);
+    for (int i = 0; i < Np; ++i) {
+        const V3 x = X[i];
+        double wsum = 0.0;
+        int q = 0;
+        for (int l = 0; l < n; ++l) {
+            const double psi = kPi * (gx[l] + 1.0), wpsi = kPi * gw[l];
+            const double ex = std::cos(psi), ey = std::sin(psi);
+            const double be = ex * x.x + ey * x.y, bb = x.x * x.x + x.y * x.y;
+            const double rmax = -be + std::sqrt(be * be + 1.0 - bb);
+            const double lo0 = kSecondKindDelta, mid = std::sqrt(kSecondKindDelta * rmax);
+            const double los[2] = {lo0, mid}, his[2] = {mid, rmax};
+            for (int piece = 0; piece < 2; ++piece) {
+                const double L = std::log(his[piece] / los[piece]);
+                for (int k = 0; k < n; ++k, ++q) {
+                    const double tau = 0.5 * (gx[k] + 1.0), wtau = 0.5 * gw[k];
+                    const double rho = los[piece] * std::exp(L * tau);
+                    const V3 y{x.x + rho * ex, x.y + rho * ey, 0.0};
+                    const double w = wpsi * wtau * rho * rho * L * ddgreen_s(x, y);
+                    double *o = &ops.s_pts[((size_t)i * ops.n_s + q) * 3];
+                    o[0] = y.x;
+                    o[1] = y.y;
+                    o[2] = 0.0;
+                    ops.s_w[(size_t)i * ops.n_s + q] = w;
+                    wsum += w;
+                }
+            }
+        }
+        double qsum = 0.0;
+        for (int k = 0; k < Nn; ++k) qsum += ops.Q2[(size_t)i * Nn + k];
+        ops.c2[i] = qsum - wsum;
+    }
+}
+
 bool build_class_ops(ClassOps &ops, std::string &err)
 {
     const int Nt = ops.n_theta, Nf = ops.n_phi, Nr = ops.n_rings, Ns = ops.n_sectors;
@@ -417,34 +490,40 @@ bool build_class_ops(ClassOps &ops, std::string &err)
             for (int k = 1; k < Nf / 2; ++k) s += 2.0 * std::cos(k * d);
             Tph[(size_t)b * NA + q] = s / Nf;
         }
-    ops.QI.assign((size_t)Np * Nn, 0.0);
+    // rows of a Gamma operator: int_Gamma kernel(x_i, y) l_k(y) ds_y for the
+    // cardinal functions l_k of the node grid
     std::vector<double> V((size_t)NT * NA), tmp((size_t)Nt * NA);
-    for (int i = 0; i < Np; ++i) {
-        for (int q = 0; q < NT; ++q) {
-            const double st = std::sin(tq[q]), ct = std::cos(tq[q]);
-            for (int p = 0; p < NA; ++p) {
-                const double ph = 2.0 * kPi * p / NA;
-                const V3 y{st * std::cos(ph), st * std::sin(ph), -ct};
-                V[(size_t)q * NA + p] = poisson_ball(X[i], y) * st * twq[q] * (2.0 * kPi / NA);
-            }
-        }
-        std::fill(tmp.begin(), tmp.end(), 0.0);
-        for (int a = 0; a < Nt; ++a)
+    auto gamma_rows = [&](auto kernel, std::vector<double> &out) {
+        out.assign((size_t)Np * Nn, 0.0);
+        for (int i = 0; i < Np; ++i) {
             for (int q = 0; q < NT; ++q) {
-                const double l = Lth[(size_t)a * NT + q];
-                const double *vr = &V[(size_t)q * NA];
-                double *tr = &tmp[(size_t)a * NA];
-                for (int p = 0; p < NA; ++p) tr[p] += l * vr[p];
+                const double st = std::sin(tq[q]), ct = std::cos(tq[q]);
+                for (int p = 0; p < NA; ++p) {
+                    const double ph = 2.0 * kPi * p / NA;
+                    const V3 y{st * std::cos(ph), st * std::sin(ph), -ct};
+                    V[(size_t)q * NA + p] = kernel(X[i], y) * st * twq[q] * (2.0 * kPi / NA);
+                }
             }
-        for (int a = 0; a < Nt; ++a)
-            for (int b = 0; b < Nf; ++b) {
-                double s = 0.0;
-                const double *tr = &tmp[(size_t)a * NA];
-                const double *cr = &Tph[(size_t)b * NA];
-                for (int p = 0; p < NA; ++p) s += tr[p] * cr[p];
-                ops.QI[(size_t)i * Nn + a * Nf + b] = s;
-            }
-    }
+            std::fill(tmp.begin(), tmp.end(), 0.0);
+            for (int a = 0; a < Nt; ++a)
+                for (int q = 0; q < NT; ++q) {
+                    const double l = Lth[(size_t)a * NT + q];
+                    const double *vr = &V[(size_t)q * NA];
+                    double *tr = &tmp[(size_t)a * NA];
+                    for (int p = 0; p < NA; ++p) tr[p] += l * vr[p];
+                }
+            for (int a = 0; a < Nt; ++a)
+                for (int b = 0; b < Nf; ++b) {
+                    double s = 0.0;
+                    const double *tr = &tmp[(size_t)a * NA];
+                    const double *cr = &Tph[(size_t)b * NA];
+                    for (int p = 0; p < NA; ++p) s += tr[p] * cr[p];
+                    out[(size_t)i * Nn + a * Nf + b] = s;
+                }
+        }
+    };
+    gamma_rows([](V3 x, V3 y) { return poisson_ball(x, y); }, ops.QI);
+    if (ops.rr == 0.0) second_kind_tables(ops, X, gamma_rows);
 
     // ---- A2 = (K^-1 Q.I)^2, and the ring-0 row: the mean over the central
     // ring's panels (equal areas on a plane patch) of K^-1 Q.I

@@ -449,6 +449,85 @@ dtn_status launch_solve(const Plan &p, const double *node_stats, int precision, 
     return DTN_OK;
 }
 
+// ------------------------------------------------- second kind (flat)
+// sigma = 2b on a flat patch (eqs. bw53-bw59 with D = 0): one block per
+// patch, one wave per panel row: the Gamma operator Q2 against the node
+// means (and Q2^2 against their squared SE for the propagated SE), phi at
+// the regularised S rule's points, the constant term at the collocation
+// point; all scaled by 1/h.
+template <int DATA>
+__global__ __launch_bounds__(kSolveBlock) void k_solve2(DevGeom g, const dtn_patch *__restrict__ patches,
+                                                        const int32_t *__restrict__ pclass,
+                                                        const DevClass *__restrict__ classes,
+                                                        const int64_t *__restrict__ node_off,
+                                                        const int64_t *__restrict__ panel_off,
+                                                        const double *__restrict__ node_stats,
+                                                        double *__restrict__ neumann, double *__restrict__ neumann_se)
+{
+    __shared__ double u[kMaxNodes];
+    __shared__ double v2[kMaxNodes];
+    const int pi = blockIdx.x;
+    const dtn_patch p = patches[pi];
+    const DevClass &cl = classes[pclass[pi]];
+    const int Np = cl.n_panels, Nn = cl.n_nodes, Ns = cl.n_s;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int nwaves = kSolveBlock / kWave;
+    double t2[3];
+    cross3(p.n, p.t1, t2);
+    const int64_t nb = node_off[pi];
+    for (int k = tid; k < Nn; k += kSolveBlock) {
+        const double *s = node_stats + 4 * (nb + k);
+        const double cnt = s[0];
+        u[k] = s[1];
+        v2[k] = cnt > 1.0 ? s[2] / ((cnt - 1.0) * cnt) : 0.0;
+    }
+    __syncthreads();
+    const double two_over_h = 2.0 / p.h;
+    for (int i = wave; i < Np; i += nwaves) {
+        const double *q2 = cl.Q2 + (size_t)i * Nn;
+        double acc = 0.0, var = 0.0, sp = 0.0;
+        for (int k = lane; k < Nn; k += kWave) {
+            const double w = q2[k];
+            acc += w * u[k];
+            var += w * w * v2[k];
+        }
+        const double *pts = cl.s_pts + (size_t)i * Ns * 3;
+        const double *sw = cl.s_w + (size_t)i * Ns;
+        for (int q = lane; q < Ns; q += kWave) {
+            double gx, gy, gz;
+            to_global(p, t2, pts[3 * q], pts[3 * q + 1], pts[3 * q + 2], gx, gy, gz);
+            sp += sw[q] * phi_eval<DATA>(g, gx, gy, gz);
+        }
+        acc = wave_sum(acc);
+        var = wave_sum(var);
+        sp = wave_sum(sp);
+        if (lane == 0) {
+            double gx, gy, gz;
+            const double *x = cl.col_tab + 3 * i;
+            to_global(p, t2, x[0], x[1], x[2], gx, gy, gz);
+            const double fx = phi_eval<DATA>(g, gx, gy, gz);
+            const int64_t o = panel_off[pi] + i;
+            neumann[o] = two_over_h * (acc - sp - cl.c2[i] * fx);
+            if (neumann_se) neumann_se[o] = two_over_h * sqrt(var);
+        }
+    }
+}
+
+dtn_status launch_solve2(const Plan &p, const double *node_stats, double *neumann, double *neumann_se, hipStream_t s)
+{
+    const dim3 grid((unsigned)p.patches.size());
+    if (p.geom->dev.data_kind == DTN_DATA_POINT_SOURCES)
+        hipLaunchKernelGGL(k_solve2<DTN_DATA_POINT_SOURCES>, grid, dim3(kSolveBlock), 0, s, p.geom->dev, p.d_patches,
+                           p.d_patch_class, p.d_classes, p.d_node_off, p.d_panel_off, node_stats, neumann, neumann_se);
+    else
+        hipLaunchKernelGGL(k_solve2<DTN_DATA_HARMONIC_QUADRATIC>, grid, dim3(kSolveBlock), 0, s, p.geom->dev,
+                           p.d_patches, p.d_patch_class, p.d_classes, p.d_node_off, p.d_panel_off, node_stats, neumann,
+                           neumann_se);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_patch_solve_second_kind: ") + hipGetErrorString(e));
+    return DTN_OK;
+}
+
 // One wave per patch: sigma averaged over the ring-0 panels (the central
 // disk, equal panel areas on a plane patch); its standard error from the
 // node standard errors through the class's ring-0 row of K^-1 QI (scaled by

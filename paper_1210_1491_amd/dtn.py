@@ -120,6 +120,8 @@ def lib():
         L.dtn_patch_nodes.argtypes = [vp, vp, vp]
         L.dtn_patch_solve.argtypes = [vp, vp, C.c_int32, vp, vp, vp]
         L.dtn_potential.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
+        L.dtn_patch_solve_second_kind.argtypes = [vp, vp, vp, vp, vp]
+        L.dtn_class_second_kind.argtypes = [C.c_int32] * 4 + [C.POINTER(C.c_double)] * 2
         L.dtn_create_points.argtypes = [vp, C.POINTER(PointDesc), C.c_int64, C.c_int32, C.c_int32, C.c_double,
                                         C.POINTER(vp)]
         L.dtn_destroy_points.argtypes = [vp]
@@ -134,7 +136,9 @@ def lib():
         for f in ("dtn_create_geometry", "dtn_wos_eval", "dtn_wos_adaptive", "dtn_wos_time_schedules",
                   "dtn_boundary_distance", "dtn_server_create", "dtn_server_submit", "dtn_server_wait",
                   "dtn_create_plan", "dtn_patch_nodes",
-                  "dtn_patch_solve", "dtn_potential", "dtn_class_operators", "dtn_create_points",
+                  "dtn_patch_solve", "dtn_patch_solve_second_kind", "dtn_class_second_kind", "dtn_potential",
+                  "dtn_class_operators",
+                  "dtn_create_points",
                   "dtn_points_nodes", "dtn_points_neumann"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -343,6 +347,18 @@ class Plan:
                                      _ptr(neumann_se), _stream()), "dtn_patch_solve")
         return neumann, neumann_se
 
+    def solve_second_kind(self, node_stats, neumann=None, neumann_se=None):
+        """Neumann data by the second-kind equation (flat patches: sigma = 2b)."""
+        _dev_tensor(node_stats, torch.float64, (self.num_nodes, 4))
+        dev = node_stats.device
+        if neumann is None:
+            neumann = torch.empty(self.num_panels, dtype=torch.float64, device=dev)
+        if neumann_se is None:
+            neumann_se = torch.empty(self.num_panels, dtype=torch.float64, device=dev)
+        _check(lib().dtn_patch_solve_second_kind(self.handle, _ptr(node_stats), _ptr(neumann), _ptr(neumann_se),
+                                                 _stream()), "dtn_patch_solve_second_kind")
+        return neumann, neumann_se
+
     def potential(self, neumann, targets, out=None):
         m = targets.shape[0]
         _dev_tensor(neumann, torch.float64, (self.num_panels,))
@@ -477,3 +493,14 @@ class Server:
 
     def __del__(self):
         self.close()
+
+
+def class_second_kind(n_theta, n_phi, n_rings, n_sectors):
+    """Host diagnostic: the second-kind tables of a flat class at h = 1."""
+    Np, Nn = n_rings * n_sectors, n_theta * n_phi
+    Q2, c2 = np.empty((Np, Nn)), np.empty(Np)
+    dp = C.POINTER(C.c_double)
+    _check(lib().dtn_class_second_kind(n_theta, n_phi, n_rings, n_sectors, Q2.ctypes.data_as(dp),
+                                       c2.ctypes.data_as(dp)), "dtn_class_second_kind")
+    return {"Q2": Q2, "c2": c2}
+

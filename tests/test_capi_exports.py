@@ -113,3 +113,22 @@ def test_points_arguments_are_checked_before_any_device_work():
     assert L.dtn_points_nodes(None, None, None) == -1
     assert L.dtn_points_neumann(None, None, None, None) == -1
     assert L.dtn_points_num_nodes(None) == -1
+
+
+@pytest.mark.parametrize("layout", [(16, 32, 4, 16), (8, 16, 4, 8)])
+def test_second_kind_tables_agree_with_oracle(layout):
+    """The library's second-kind tables of a flat class (Gamma operator with
+    dP/dn_x, and the constant term of the regularised S rule) against the
+    oracle's independent functions."""
+    from oracle import patch as OP
+    from oracle import second_kind as SK
+    from paper_1210_1491_amd import dtn
+    nt, nf, nr, ns = layout
+    t = dtn.class_second_kind(nt, nf, nr, ns)
+    Q2 = SK.gamma_operator_2(1.0, nt, nf, nr, ns)
+    assert np.max(np.abs(t["Q2"] - Q2)) < 1e-10 * np.max(np.abs(Q2))
+    _, X, _, _ = OP.panels(1.0, None, nr, ns)
+    for i in range(len(X)):
+        pts, W = SK.s_rule(X[i], 1.0, 1e-6)
+        wsum = np.sum(W * SK.kernel_s(X[i][None, :], pts, 1.0))
+        assert abs(t["c2"][i] - (Q2[i].sum() - wsum)) < 1e-9 * max(1.0, abs(wsum))

@@ -201,3 +201,83 @@ def test_plan_rejects_bad_patches_and_unsupported_potential():
         plan.potential(torch.zeros(plan.num_panels, dtype=torch.float64, device="cuda"),
                        torch.zeros((4, 3), dtype=torch.float64, device="cuda"))
     assert e.value.status == -4
+
+
+def test_second_kind_matches_oracle_on_exact_node_values():
+    """sigma = 2b on flat patches (eqs. bw53-bw59 with D = 0) through the
+    C-ABI against the oracle on the same node values, for a tiling subset of
+    the cube.  Bar: 1e-8 of each row's term scale (the two sides' tables
+    agree to 1e-10 relative); SE to 1e-6."""
+    from oracle import second_kind as SK
+    dtn = _dtn()
+    gd, pd, ps = _setup("cube")
+    og = OW.Geometry(gd)
+    rows, ref_s, ref_se, scale = [], [], [], []
+    for k, p in enumerate(ps):
+        nodes, _ = OP.nodes_global(p)
+        u = og.phi(nodes)
+        se = 1e-3 * (1.0 + 0.5 * np.sin(np.arange(len(u)) + k))
+        rows.append(_stats_from_values(u, 1e4, se))
+        r = SK.patch_solve_2(p, og, u, se)
+        ref_s.append(r["sigma"])
+        ref_se.append(r["se"])
+        Q2 = SK.gamma_operator_2(p.h, p.n_theta, p.n_phi, p.n_rings, p.n_sectors)
+        _, X, _, _ = OP.panels(p.h, None, p.n_rings, p.n_sectors)
+        for i in range(len(X)):
+            pts, W = SK.s_rule(X[i], p.h, 1e-6)
+            ws = np.abs(W * SK.kernel_s(X[i][None, :], pts, p.h))
+            scale.append(2.0 * (np.abs(Q2[i]) @ np.abs(u) + ws @ np.abs(og.phi(p.to_global(pts)))
+                                + abs(Q2[i].sum() - np.sum(W * SK.kernel_s(X[i][None, :], pts, p.h)))
+                                * np.max(np.abs(u))))
+    print("[gpu] second kind, exact node values", flush=True)
+    plan = dtn.Plan(dtn.Geometry(gd), pd)
+    st = torch.tensor(np.concatenate(rows), device="cuda")
+    sig, se = plan.solve_second_kind(st)
+    sig, se = sig.cpu().numpy(), se.cpu().numpy()
+    ref_s, ref_se = map(np.concatenate, (ref_s, ref_se))
+    scale = np.asarray(scale)
+    assert np.all(np.abs(sig - ref_s) <= 1e-8 * scale), np.max(np.abs(sig - ref_s) / scale)
+    np.testing.assert_allclose(se, ref_se, rtol=1e-6)
+    # the method's floor against the exact data on the trusted panels
+    xg, ng, area, tr = [], [], [], []
+    for p in ps:
+        a, b, c, d = OP.collocation_points(p)
+        xg.append(a)
+        ng.append(b)
+        area.append(c)
+        tr.append(d < 0.7 * p.h)
+    xg, ng, area, tr = map(np.concatenate, (xg, ng, area, tr))
+    assert OP.rel_l2(sig, OP.exact_neumann(gd, xg, ng), area, tr) < 1e-4
+
+
+def test_second_kind_pipeline_and_curved_rejection():
+    dtn = _dtn()
+    gd, pd, ps = _setup("cube")
+    g = dtn.Geometry(gd)
+    plan = dtn.Plan(g, pd)
+    nodes = plan.nodes()
+    W = torch.full((plan.num_nodes,), 20_000, dtype=torch.int64, device="cuda")
+    stats, _ = dtn.wos_eval(g, nodes, W, seed=3)
+    s1, e1 = plan.solve(stats)
+    s2, e2 = plan.solve_second_kind(stats)
+    s1, e1, s2, e2 = (t.cpu().numpy() for t in (s1, e1, s2, e2))
+    xg, ng, area, tr = [], [], [], []
+    for p in ps:
+        a, b, c, d = OP.collocation_points(p)
+        xg.append(a)
+        ng.append(b)
+        area.append(c)
+        tr.append(d < 0.7 * p.h)
+    xg, ng, area, tr = map(np.concatenate, (xg, ng, area, tr))
+    ex = OP.exact_neumann(gd, xg, ng)
+    noise2 = float(np.sqrt(np.sum(area[tr] * e2[tr] ** 2) / np.sum(area[tr] * ex[tr] ** 2)))
+    err2 = OP.rel_l2(s2, ex, area, tr)
+    print(f"[gpu] second kind rel-L2 {err2:.3e} (noise {noise2:.3e}); first kind {OP.rel_l2(s1, ex, area, tr):.3e}",
+          flush=True)
+    assert err2 < 3 * noise2 + 1e-4
+    # per panel within the propagated SE
+    assert np.mean(np.abs(s2[tr] - ex[tr]) < 4 * e2[tr]) > 0.99
+    ball = dtn.Plan(dtn.Geometry(I.geometry_ball_quadratic()), I.patches_ball_pole())
+    st = torch.zeros((ball.num_nodes, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(dtn.DtnError):
+        ball.solve_second_kind(st)
