@@ -942,7 +942,30 @@ def main():
         sig2 = n2.cpu().numpy()
         solves = {precision: rel_l2(sig, ex, area, trusted), other: rel_l2(sig2, ex, area, trusted),
                   "max_abs_diff_fp32_vs_fp64_solve": float(np.max(np.abs(sig2 - sig)))}
-        return {"ms_per_step": ms, "rel_l2_by_solve_precision": solves, "walks_per_s": walks_n / (ms / 1e3), "patches_per_s": n_patches / (ms / 1e3),
+        # the second-kind equation (flat patches: sigma = 2b, no solve) on the
+        # timed run's statistics, timed on the stream beside a first-kind solve
+        second = None
+        if precision == "fp64":
+            n2, s2 = torch.empty_like(neumann), torch.empty_like(neumann_se)
+            n1, s1 = torch.empty_like(neumann), torch.empty_like(neumann_se)
+            plan.solve_second_kind(stats, neumann=n2, neumann_se=s2)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.solve_second_kind(stats, neumann=n2, neumann_se=s2)
+            e1.record()
+            f0.record()
+            plan.solve(stats, precision="fp64", neumann=n1, neumann_se=s1)
+            f1.record()
+            torch.cuda.synchronize()
+            sig2, sse2, sse1 = n2.cpu().numpy(), s2.cpu().numpy(), s1.cpu().numpy()
+            den = np.sum(area[trusted] * ex[trusted] ** 2)
+            second = {"neumann_rel_l2_vs_exact": rel_l2(sig2, ex, area, trusted),
+                      "first_kind_rel_l2_vs_exact": rel_l2(n1.cpu().numpy(), ex, area, trusted),
+                      "propagated_noise_rel_l2": float(np.sqrt(np.sum(area[trusted] * sse2[trusted] ** 2) / den)),
+                      "first_kind_noise_rel_l2": float(np.sqrt(np.sum(area[trusted] * sse1[trusted] ** 2) / den)),
+                      "solve_ms": e0.elapsed_time(e1), "first_kind_solve_ms": f0.elapsed_time(f1)}
+        return {"second_kind": second, "ms_per_step": ms, "rel_l2_by_solve_precision": solves, "walks_per_s": walks_n / (ms / 1e3), "patches_per_s": n_patches / (ms / 1e3),
                 "neumann_rel_l2_vs_exact": rel_l2(sig, ex, area, trusted),
                 "neumann_se_median": float(np.median(neumann_se.cpu().numpy())),
                 "potential_max_err_far": float(np.max(np.abs(u.cpu().numpy()[far] - u_ex[far]))
@@ -1033,6 +1056,7 @@ def main():
                      "slots_per_step": SLOTS_PER_STEP[args.precision], "slots_per_walk": SLOTS_PER_WALK},
         "variants": variants,
         "error_vs_walks": curve,
+        "second_kind": m.get("second_kind"),
     }
     if args.only is None and not args.no_box_holes:
         line["box_holes"] = box_holes("fp32", 1, not args.no_cpu_baseline, with_fp64=not args.no_variants)
