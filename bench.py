@@ -118,11 +118,11 @@ TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_am
                      "paper_1210_1491_amd/csrc/dtn_internal.h"],
            "sha256": ["bebedd82506e67d55dcb625cc8c527702c4c0ea179c46fed9c2cb6b488806f73",
                       "6a1675eaf8869631fee8f9a58747a3423500e1bbb7b205e83c5e42f8e2918dd3",
-                      "0c2fed8fed7ff085b27db5a6564efe0a22145418aa7cb64978a0a8bd3a13ffe0"],
-           "fetch_bytes": 71753.25 * 1024 * (262144 / 131088.938), "write_bytes": 43008.0 * 1024 * 1.00,
+                      "b23804fc69bb8cee50a3a03bc57f72e76198ab978429d666ea06ab9b3e0ec3c9"],
+           "fetch_bytes": 71753.188 * 1024 * (262144 / 131088.875), "write_bytes": 43008.0 * 1024 * 1.00,
            # the half-space point workload's walk kernel (same sources), scaled
-           # by the copy in its own run (fetch 131086.688 KiB for 262144)
-           "halfspace_fetch_bytes": 156228.875 * 1024 * (262144 / 131086.688),
+           # by the copy in its own run (fetch 131086.312 KiB for 262144)
+           "halfspace_fetch_bytes": 156228.688 * 1024 * (262144 / 131086.312),
            "halfspace_write_bytes": 89600.0 * 1024 * 1.00}
 
 
