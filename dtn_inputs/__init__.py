@@ -137,6 +137,34 @@ def patches_sphere_exterior(n, R=3.0, h=0.5, n_theta=8, n_phi=16, n_rings=4, n_s
     return d
 
 
+def box_face_grid(gd, n0, n1):
+    """Grid points of the six faces of a box geometry (-x,+x,-y,+y,-z,+z),
+    face k's axes a = (k+1) mod 3 with n0 nodes and b = (k+2) mod 3 with n1,
+    uniform from lo to hi: [6][n0][n1][3]."""
+    lo, hi = np.asarray(gd["box_lo"], float), np.asarray(gd["box_hi"], float)
+    out = np.zeros((6, n0, n1, 3))
+    for f in range(6):
+        k, a, b = f // 2, (f // 2 + 1) % 3, (f // 2 + 2) % 3
+        A, B = np.meshgrid(np.linspace(lo[a], hi[a], n0), np.linspace(lo[b], hi[b], n1), indexing="ij")
+        out[f, :, :, k] = hi[k] if f % 2 else lo[k]
+        out[f, :, :, a] = A
+        out[f, :, :, b] = B
+    return out
+
+
+def tabulated_cube_sources(n0=257, n1=257, seed=2, eps=1e-5, max_steps=1_000_000):
+    """The unit cube with its 8-source data given as face tables (the
+    potential sampled on each face's grid): Dirichlet data without a closed
+    form for the library, whose harmonic extension approaches the sources'
+    potential as the grid is refined (bilinear interpolation error
+    O(grid spacing^2))."""
+    gd = geometry_cube_sources(seed, eps, max_steps)
+    X = box_face_grid(gd, n0, n1)
+    src = gd["src"]
+    tab = sum(q[3] / np.linalg.norm(X - q[:3], axis=-1) for q in src)
+    return dict(gd, data_kind="table", tab=np.ascontiguousarray(tab))
+
+
 def halfspace_points(n, seed=6, radii=(0.1, 0.2, 0.5, 0.7, 1.0), extent=2.0):
     """Single-point queries on the plane z = 0: points uniform in the disk of
     radius ``extent`` around the origin, hemisphere radius cycling through

@@ -53,6 +53,9 @@ class OgGeom(C.Structure):
         ("max_steps", C.c_int64),
         ("disk_r", C.c_double),
         ("trunc_r", C.c_double),
+        ("tab_n0", C.c_int32),
+        ("tab_n1", C.c_int32),
+        ("tab", C.POINTER(C.c_double)),
     ]
 
 
@@ -83,7 +86,7 @@ class Geometry:
         self.desc = desc
         g = OgGeom()
         g.kind = KIND[desc["kind"]]
-        g.data_kind = 0 if desc["data_kind"] == "quadratic" else 1
+        g.data_kind = {"quadratic": 0, "sources": 1, "table": 2}[desc["data_kind"]]
         for k in range(3):
             g.ball_c[k] = float(desc.get("ball_c", (0, 0, 0))[k])
             g.box_lo[k] = float(desc.get("box_lo", (0, 0, 0))[k])
@@ -102,6 +105,11 @@ class Geometry:
         g.max_steps = int(desc["max_steps"])
         g.disk_r = float(desc.get("disk_r", 0.0))
         g.trunc_r = float(desc.get("trunc_r", 0.0))
+        self._tab = np.ascontiguousarray(np.asarray(desc.get("tab", np.zeros((6, 2, 2))), dtype=np.float64))
+        if self._tab.ndim != 3 or self._tab.shape[0] != 6:
+            raise ValueError("tab must be [6][n0][n1]")
+        g.tab_n0, g.tab_n1 = int(self._tab.shape[1]), int(self._tab.shape[2])
+        g.tab = _dptr(self._tab)
         self.g = g
 
     def ref(self):

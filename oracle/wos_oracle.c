@@ -43,6 +43,12 @@
  *     the closed disk {z = 0, x^2 + y^2 <= disk_r^2}; the distance is that to
  *     the disk, the closest point its projection, and the truncation sphere
  *     applies as for the half space;
+ *   - tabulated Dirichlet data on a box (no closed form): a grid of values on
+ *     each face (-x,+x,-y,+y,-z,+z), uniform in the face's two coordinates
+ *     a = (k+1) mod 3 (tab_n0 nodes) and b = (k+2) mod 3 (tab_n1 nodes),
+ *     bilinear interpolation in the cell holding the point; a point takes the
+ *     nearest face (ties: the lowest index), and the cell index is clamped to
+ *     the grid;
  *   - the exterior of a ball (Sec. 5.2, the big sphere): |x - ball_c| >
  *     ball_r, distance |x - ball_c| - ball_r, closest point on the sphere,
  *     the truncation sphere as above.
@@ -59,7 +65,7 @@
 /* ---------------------------------------------------------------- geometry */
 
 enum { OG_BALL = 0, OG_BOX = 1, OG_BOX_MINUS_BOXES = 2, OG_HALF_SPACE = 3, OG_DISK = 4, OG_BALL_EXTERIOR = 5 };
-enum { OG_DATA_QUADRATIC = 0, OG_DATA_SOURCES = 1 };
+enum { OG_DATA_QUADRATIC = 0, OG_DATA_SOURCES = 1, OG_DATA_TABLE = 2 };
 
 typedef struct {
     int32_t kind;
@@ -77,14 +83,44 @@ typedef struct {
     int64_t max_steps;
     double disk_r;       /* OG_DISK: radius of the disk in z = 0 */
     double trunc_r;      /* unbounded kinds: truncation sphere |x - ball_c| = trunc_r */
+    int32_t tab_n0, tab_n1;
+    const double *tab;   /* OG_DATA_TABLE: [6][tab_n0][tab_n1] */
 } og_geom;
 
 /* Dirichlet data phi(x).
  * Quadratic: c0 + c1 x + c2 y + c3 z + c4 x^2 + c5 y^2 + c6 z^2
  *            + c7 xy + c8 yz + c9 xz   (harmonic when c4 + c5 + c6 = 0).
  * Sources:   sum_k q_k / |x - s_k|. */
+/* Bilinear interpolation of the face tables (see the header). */
+static double og_phi_table(const og_geom *g, const double x[3])
+{
+    int f = 0;
+    double best = INFINITY;
+    for (int k = 0; k < 3; ++k) {
+        double dlo = fabs(x[k] - g->box_lo[k]), dhi = fabs(g->box_hi[k] - x[k]);
+        if (dlo < best) { best = dlo; f = 2 * k; }
+        if (dhi < best) { best = dhi; f = 2 * k + 1; }
+    }
+    const int k = f / 2, a = (k + 1) % 3, b = (k + 2) % 3;
+    const int n0 = g->tab_n0, n1 = g->tab_n1;
+    const double sa = (double)(n0 - 1) / (g->box_hi[a] - g->box_lo[a]);
+    const double sb = (double)(n1 - 1) / (g->box_hi[b] - g->box_lo[b]);
+    const double s = (x[a] - g->box_lo[a]) * sa, t = (x[b] - g->box_lo[b]) * sb;
+    int i = (int)floor(s), j = (int)floor(t);
+    if (i < 0) i = 0;
+    if (i > n0 - 2) i = n0 - 2;
+    if (j < 0) j = 0;
+    if (j > n1 - 2) j = n1 - 2;
+    const double fs = s - i, ft = t - j;
+    const double *T = g->tab + (size_t)f * n0 * n1;
+    const double v00 = T[(size_t)i * n1 + j], v10 = T[(size_t)(i + 1) * n1 + j];
+    const double v01 = T[(size_t)i * n1 + j + 1], v11 = T[(size_t)(i + 1) * n1 + j + 1];
+    return (1.0 - fs) * ((1.0 - ft) * v00 + ft * v01) + fs * ((1.0 - ft) * v10 + ft * v11);
+}
+
 double og_phi(const og_geom *g, const double x[3])
 {
+    if (g->data_kind == OG_DATA_TABLE) return og_phi_table(g, x);
     if (g->data_kind == OG_DATA_QUADRATIC) {
         const double *c = g->quad;
         return c[0] + c[1] * x[0] + c[2] * x[1] + c[3] * x[2] + c[4] * x[0] * x[0] +
