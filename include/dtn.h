@@ -63,7 +63,7 @@ typedef enum {
 /* Domain kinds (walks run inside Omega). */
 enum { DTN_BALL = 0, DTN_BOX = 1, DTN_BOX_MINUS_BOXES = 2, DTN_HALF_SPACE = 3, DTN_DISK = 4, DTN_BALL_EXTERIOR = 5 };
 /* Dirichlet data kinds. */
-enum { DTN_DATA_HARMONIC_QUADRATIC = 0, DTN_DATA_POINT_SOURCES = 1 };
+enum { DTN_DATA_HARMONIC_QUADRATIC = 0, DTN_DATA_POINT_SOURCES = 1, DTN_DATA_TABULATED = 2 };
 /* Arithmetic of the walks and of the collocation solve. */
 enum { DTN_FP64 = 0, DTN_FP32_MIXED = 1 };
 
@@ -97,6 +97,13 @@ typedef struct dtn_plan_s *dtn_plan;         /* opaque, library-owned */
  *        + q5 y^2 + q6 z^2 + q7 xy + q8 yz + q9 xz, harmonic (q4+q5+q6 = 0).
  *   data DTN_DATA_POINT_SOURCES: phi = sum_k src[k].q / |x - src[k].xyz|,
  *        src rows (x, y, z, q), every source outside the closed domain.
+ *   data DTN_DATA_TABULATED (DTN_BOX only): phi given by tables on the six
+ *        faces (order -x,+x,-y,+y,-z,+z), tab host [6][tab_n[0]][tab_n[1]]:
+ *        face k's value (i, j) sits at coordinate a = (k/2+1) mod 3 equal to
+ *        lo_a + i (hi_a - lo_a)/(tab_n[0] - 1) and b = (k/2+2) mod 3 equal to
+ *        lo_b + j (hi_b - lo_b)/(tab_n[1] - 1); phi at a boundary point is
+ *        the bilinear interpolant on the nearest face (ties: the lowest
+ *        face index).  tab_n[0], tab_n[1] in [2, 4096].
  *   eps: width of the absorbing shell (Sec. 2, epsilon-shell WOS), > 0.
  *   max_steps: a walk still alive after max_steps steps is scored at its
  *        closest boundary point and counted as capped (a walk gone to
@@ -118,6 +125,8 @@ typedef struct {
     double disk_r;  /* DTN_DISK: radius of the disk (other kinds: unused) */
     double trunc_r; /* unbounded kinds: radius of the truncation sphere
                        (centre ball_c); bounded kinds: unused */
+    int32_t tab_n[2];  /* DTN_DATA_TABULATED: grid nodes per face axis */
+    const double *tab; /* DTN_DATA_TABULATED: host [6][tab_n[0]][tab_n[1]] */
 } dtn_geometry_desc;
 
 /* One boundary patch S with its hemisphere (Sec. 4, Fig. fig_biewos).

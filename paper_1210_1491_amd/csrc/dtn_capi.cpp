@@ -303,8 +303,18 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
         *out = nullptr;
         const dtn_geometry_desc &d = *desc;
         if (d.kind < DTN_BALL || d.kind > DTN_BALL_EXTERIOR) return fail(DTN_E_ARG, "dtn_create_geometry: bad kind");
-        if (d.data_kind != DTN_DATA_HARMONIC_QUADRATIC && d.data_kind != DTN_DATA_POINT_SOURCES)
+        if (d.data_kind != DTN_DATA_HARMONIC_QUADRATIC && d.data_kind != DTN_DATA_POINT_SOURCES &&
+            d.data_kind != DTN_DATA_TABULATED)
             return fail(DTN_E_ARG, "dtn_create_geometry: bad data_kind");
+        size_t tab_len = 0;
+        if (d.data_kind == DTN_DATA_TABULATED) {
+            if (d.kind != DTN_BOX) return fail(DTN_E_ARG, "dtn_create_geometry: tabulated data needs a box");
+            if (d.tab_n[0] < 2 || d.tab_n[0] > 4096 || d.tab_n[1] < 2 || d.tab_n[1] > 4096 || !d.tab)
+                return fail(DTN_E_ARG, "dtn_create_geometry: tab_n outside [2, 4096] or tab NULL");
+            tab_len = (size_t)6 * d.tab_n[0] * d.tab_n[1];
+            for (size_t q = 0; q < tab_len; ++q)
+                if (!std::isfinite(d.tab[q])) return fail(DTN_E_ARG, "dtn_create_geometry: tab holds a non-finite value");
+        }
         if (!(d.eps > 0.0)) return fail(DTN_E_ARG, "dtn_create_geometry: eps must be > 0");
         if (d.max_steps < 0) return fail(DTN_E_ARG, "dtn_create_geometry: max_steps < 0");
         const bool unbounded = d.kind == DTN_HALF_SPACE || d.kind == DTN_DISK || d.kind == DTN_BALL_EXTERIOR;
@@ -365,6 +375,14 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
         g.dev.eps = d.eps;
         g.dev.disk_r = d.kind == DTN_DISK ? d.disk_r : 0.0;
         g.dev.trunc_r = unbounded ? d.trunc_r : 0.0;
+        if (tab_len) {
+            g.dev.tab_n[0] = d.tab_n[0];
+            g.dev.tab_n[1] = d.tab_n[1];
+            for (int k = 0; k < 3; ++k) {
+                g.dev.tab_sc[k][0] = (double)(d.tab_n[0] - 1) / (d.box_hi[k] - d.box_lo[k]);
+                g.dev.tab_sc[k][1] = (double)(d.tab_n[1] - 1) / (d.box_hi[k] - d.box_lo[k]);
+            }
+        }
         g.dev.max_steps = d.max_steps;
         const int nh = d.kind == DTN_BOX_MINUS_BOXES ? d.n_holes : 0;
         g.dev.n_holes = nh;
@@ -405,6 +423,7 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
             if (e == hipSuccess) e = upload(g.cell_mask, &g.d_cell_mask);
         }
         if (e == hipSuccess) e = upload(g.src, &g.d_src);
+        if (e == hipSuccess && tab_len) e = upload(std::vector<double>(d.tab, d.tab + tab_len), &g.d_tab);
         if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_create_geometry: ") + hipGetErrorString(e));
         g.dev.hole_ce = g.d_hole_ce;
         g.dev.hole_box = g.d_hole_box;
@@ -412,6 +431,7 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
         g.dev.sincos = g.d_sincos;
         g.dev.cell_mask = g.d_cell_mask;
         g.dev.src = g.d_src;
+        g.dev.tab = g.d_tab;
         // keep stream-ordered scratch in the pool between calls
         hipMemPool_t pool;
         if (hipDeviceGetDefaultMemPool(&pool, g.device) == hipSuccess) {
@@ -434,6 +454,7 @@ void dtn_destroy_geometry(dtn_geometry g)
     (void)hipFree(g->g.d_sincos);
     (void)hipFree(g->g.d_cell_mask);
     (void)hipFree(g->g.d_src);
+    (void)hipFree(g->g.d_tab);
     delete g;
 }
 

@@ -224,7 +224,32 @@ __device__ __forceinline__ uint32_t hole_candidates(const DevGeom &g, const Cell
 template <int DATA>
 __device__ __forceinline__ double phi_eval(const DevGeom &g, double x, double y, double z)
 {
-    if constexpr (DATA == DTN_DATA_HARMONIC_QUADRATIC) {
+    if constexpr (DATA == DTN_DATA_TABULATED) {
+        // nearest face (ties: lowest index), bilinear in its cell (clamped)
+        const double p[3] = {x, y, z};
+        int f = 0;
+        double best = __builtin_inf();
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double dlo = fabs(p[k] - g.lo[k]), dhi = fabs(g.hi[k] - p[k]);
+            if (dlo < best) {
+                best = dlo;
+                f = 2 * k;
+            }
+            if (dhi < best) {
+                best = dhi;
+                f = 2 * k + 1;
+            }
+        }
+        const int k = f >> 1, a = k == 2 ? 0 : k + 1, b = k == 0 ? 2 : k - 1;
+        const int n0 = g.tab_n[0], n1 = g.tab_n[1];
+        const double s = (p[a] - g.lo[a]) * g.tab_sc[a][0], t = (p[b] - g.lo[b]) * g.tab_sc[b][1];
+        const int i = min(max((int)floor(s), 0), n0 - 2), j = min(max((int)floor(t), 0), n1 - 2);
+        const double fs = s - i, ft = t - j;
+        const double *T = g.tab + (size_t)f * n0 * n1 + (size_t)i * n1 + j;
+        const double v00 = T[0], v01 = T[1], v10 = T[n1], v11 = T[n1 + 1];
+        return (1.0 - fs) * ((1.0 - ft) * v00 + ft * v01) + fs * ((1.0 - ft) * v10 + ft * v11);
+    } else if constexpr (DATA == DTN_DATA_HARMONIC_QUADRATIC) {
         const double *c = g.quad;
         return c[0] + c[1] * x + c[2] * y + c[3] * z + c[4] * x * x + c[5] * y * y + c[6] * z * z +
                c[7] * x * y + c[8] * y * z + c[9] * x * z;

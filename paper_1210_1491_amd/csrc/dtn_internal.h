@@ -39,6 +39,11 @@ struct DevGeom {
     int64_t max_steps;
     double disk_r;          // DTN_DISK: radius of the disk
     double trunc_r;         // unbounded kinds: truncation sphere |x - c| = trunc_r
+    // DTN_DATA_TABULATED: face tables [6][n0][n1]; tab_sc[k] = (n - 1)/(hi - lo)
+    // along axis k for the first and second grid axis
+    const double *tab;
+    int32_t tab_n[2];
+    double tab_sc[3][2];
 };
 
 // Per-class operators on the device.  A class is a set of congruent patches
@@ -80,6 +85,7 @@ struct Geometry {
     float *d_hole_f32 = nullptr;
     double *d_sincos = nullptr;
     uint32_t *d_cell_mask = nullptr;
+    double *d_tab = nullptr;
     std::vector<uint32_t> cell_mask;
     int device = 0;
 };

@@ -436,7 +436,11 @@ dtn_status launch_solve(const Plan &p, const double *node_stats, int precision, 
 {
     const int mixed = precision == DTN_FP32_MIXED ? 1 : 0;
     const dim3 grid((unsigned)p.patches.size());
-    if (p.geom->dev.data_kind == DTN_DATA_POINT_SOURCES)
+    if (p.geom->dev.data_kind == DTN_DATA_TABULATED)
+        hipLaunchKernelGGL(k_solve<DTN_DATA_TABULATED>, grid, dim3(kSolveBlock), 0, s, p.geom->dev, p.d_patches,
+                           p.d_patch_class, p.d_classes, p.d_node_off, p.d_panel_off, node_stats, mixed, neumann,
+                           neumann_se);
+    else if (p.geom->dev.data_kind == DTN_DATA_POINT_SOURCES)
         hipLaunchKernelGGL(k_solve<DTN_DATA_POINT_SOURCES>, grid, dim3(kSolveBlock), 0, s, p.geom->dev, p.d_patches,
                            p.d_patch_class, p.d_classes, p.d_node_off, p.d_panel_off, node_stats, mixed, neumann,
                            neumann_se);
@@ -516,7 +520,10 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve2(DevGeom g, const dtn_pat
 dtn_status launch_solve2(const Plan &p, const double *node_stats, double *neumann, double *neumann_se, hipStream_t s)
 {
     const dim3 grid((unsigned)p.patches.size());
-    if (p.geom->dev.data_kind == DTN_DATA_POINT_SOURCES)
+    if (p.geom->dev.data_kind == DTN_DATA_TABULATED)
+        hipLaunchKernelGGL(k_solve2<DTN_DATA_TABULATED>, grid, dim3(kSolveBlock), 0, s, p.geom->dev, p.d_patches,
+                           p.d_patch_class, p.d_classes, p.d_node_off, p.d_panel_off, node_stats, neumann, neumann_se);
+    else if (p.geom->dev.data_kind == DTN_DATA_POINT_SOURCES)
         hipLaunchKernelGGL(k_solve2<DTN_DATA_POINT_SOURCES>, grid, dim3(kSolveBlock), 0, s, p.geom->dev, p.d_patches,
                            p.d_patch_class, p.d_classes, p.d_node_off, p.d_panel_off, node_stats, neumann, neumann_se);
     else
@@ -629,7 +636,10 @@ dtn_status launch_potential(const Plan &p, const double *neumann, const double *
     if (e != hipSuccess) return fail(DTN_E_OOM, std::string("dtn_potential: ") + hipGetErrorString(e));
     Src *src = (Src *)scratch;
     double *partial = (double *)(scratch + sizeof(Src) * (size_t)n_src);
-    if (p.geom->dev.data_kind == DTN_DATA_POINT_SOURCES)
+    if (p.geom->dev.data_kind == DTN_DATA_TABULATED)
+        hipLaunchKernelGGL(k_tile_sources<DTN_DATA_TABULATED>, dim3((unsigned)p.patches.size()), dim3(64), 0, s,
+                           p.geom->dev, p.d_patches, p.d_patch_class, p.d_classes, p.d_panel_off, neumann, src);
+    else if (p.geom->dev.data_kind == DTN_DATA_POINT_SOURCES)
         hipLaunchKernelGGL(k_tile_sources<DTN_DATA_POINT_SOURCES>, dim3((unsigned)p.patches.size()), dim3(64), 0, s,
                            p.geom->dev, p.d_patches, p.d_patch_class, p.d_classes, p.d_panel_off, neumann, src);
     else

@@ -312,7 +312,10 @@ dtn_status dtn_points_neumann(dtn_points p, const double *node_stats, double *ou
         const dim3 grid((unsigned)((n + kPointsPerBlock - 1) / kPointsPerBlock)), block(kPointsPerBlock * kWave);
         const hipStream_t s = (hipStream_t)stream;
         const int nn = P.n_g1 * P.n_g1, nr = P.n_g2 * P.n_g2;
-        if (P.geom->dev.data_kind == DTN_DATA_POINT_SOURCES)
+        if (P.geom->dev.data_kind == DTN_DATA_TABULATED)
+            hipLaunchKernelGGL(k_point_neumann<DTN_DATA_TABULATED>, grid, block, 0, s, P.geom->dev, P.d_pts, n,
+                               nn, P.d_hemi, nr, P.d_ring, node_stats, out);
+        else if (P.geom->dev.data_kind == DTN_DATA_POINT_SOURCES)
             hipLaunchKernelGGL(k_point_neumann<DTN_DATA_POINT_SOURCES>, grid, block, 0, s, P.geom->dev, P.d_pts, n,
                                nn, P.d_hemi, nr, P.d_ring, node_stats, out);
         else

@@ -556,6 +556,8 @@ hipError_t dispatch(const Geometry &g, const double *pts, int64_t n, const int64
         return src ? run<DTN_BALL, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
                    : run<DTN_BALL, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
     case DTN_BOX:
+        if (g.dev.data_kind == DTN_DATA_TABULATED)
+            return run<DTN_BOX, DTN_DATA_TABULATED, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
         return src ? run<DTN_BOX, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
                    : run<DTN_BOX, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
     case DTN_HALF_SPACE:

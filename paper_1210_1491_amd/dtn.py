@@ -18,7 +18,7 @@ DTN_OK = 0
 STATUS = {0: "DTN_OK", -1: "DTN_E_ARG", -2: "DTN_E_DEVICE", -3: "DTN_E_OOM", -4: "DTN_E_UNSUPPORTED",
           -5: "DTN_E_NOCONV", -6: "DTN_E_MAXSTEPS"}
 KIND = {"ball": 0, "box": 1, "box_minus_boxes": 2, "half_space": 3, "disk": 4, "ball_exterior": 5}
-DATA = {"quadratic": 0, "sources": 1}
+DATA = {"quadratic": 0, "sources": 1, "table": 2}
 PRECISION = {"fp64": 0, "fp32": 1, "fp32_mixed": 1}
 
 
@@ -33,7 +33,8 @@ class GeometryDesc(C.Structure):
                 ("ball_r", C.c_double), ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
                 ("n_holes", C.c_int32), ("n_src", C.c_int32), ("holes", C.POINTER(C.c_double)),
                 ("src", C.POINTER(C.c_double)), ("quad_coef", C.c_double * 10), ("eps", C.c_double),
-                ("max_steps", C.c_int64), ("disk_r", C.c_double), ("trunc_r", C.c_double)]
+                ("max_steps", C.c_int64), ("disk_r", C.c_double), ("trunc_r", C.c_double),
+                ("tab_n", C.c_int32 * 2), ("tab", C.POINTER(C.c_double))]
 
 
 class PatchDesc(C.Structure):
@@ -198,6 +199,10 @@ class Geometry:
         d.max_steps = int(desc["max_steps"])
         d.disk_r = float(desc.get("disk_r", 0.0))
         d.trunc_r = float(desc.get("trunc_r", 0.0))
+        if desc["data_kind"] == "table":
+            self._tab = np.ascontiguousarray(np.asarray(desc["tab"], np.float64))
+            d.tab_n[0], d.tab_n[1] = int(self._tab.shape[1]), int(self._tab.shape[2])
+            d.tab = self._tab.ctypes.data_as(C.POINTER(C.c_double))
         self.desc = desc
         self.handle = C.c_void_p()
         _check(lib().dtn_create_geometry(C.byref(d), C.byref(self.handle)), "dtn_create_geometry")
