@@ -226,6 +226,7 @@ def parse():
     ap.add_argument("--no-halfspace", action="store_true", help="skip the single-point half-space workload")
     ap.add_argument("--no-disk", action="store_true", help="skip the thin-disk workload (Table 5)")
     ap.add_argument("--no-exterior", action="store_true", help="skip the exterior-sphere workload (Sec. 5.2)")
+    ap.add_argument("--no-tabulated", action="store_true", help="skip the tabulated-data workload")
     ap.add_argument("--only", choices=["cube", "box_holes", "serving", "halfspace", "disk", "exterior"], default=None,
                     help="run one workload only (for profiling)")
     ap.add_argument("--box-holes-se", type=float, default=None,
@@ -678,6 +679,43 @@ def sphere_exterior(precision, steps, warmup, with_cpu=True, cpu_patches=8):
     return res
 
 
+def cube_tabulated(walks_per_node=10_000, n_grid=257):
+    """The unit-cube tiling (1536 patches x 512 nodes) with its data given as
+    257 x 257 face tables (bilinear), against the closed-form data with the
+    same seed (the same walks): walk and solve time, and the Neumann error
+    against the exact data for both (their difference is the interpolation's
+    share)."""
+    import torch
+
+    import dtn_inputs as I
+    from paper_1210_1491_amd import dtn
+
+    pd = I.patches_cube_tiles()
+    xg, ng, area, rc = plane_panels(pd)
+    gd0 = I.geometry_cube_sources()
+    ex = np.sum(exact_grad(gd0, xg) * ng, axis=-1)
+    tr = rc < 0.7 * np.repeat(np.asarray(pd["h"], np.float64), np.asarray(pd["n_rings"]) * np.asarray(pd["n_sectors"]))
+    out = {"workload": f"unit cube, 1536 patches x 512 nodes x {walks_per_node} walks, data as "
+                       f"{n_grid}x{n_grid} face tables vs closed form"}
+    for name, gd in (("tabulated", I.tabulated_cube_sources(n_grid, n_grid)), ("closed_form", gd0)):
+        g = dtn.Geometry(gd)
+        plan = dtn.Plan(g, pd)
+        nodes = plan.nodes()
+        W = torch.full((plan.num_nodes,), walks_per_node, dtype=torch.int64, device="cuda")
+        stats, _ = dtn.wos_eval(g, nodes, W, 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats, _ = dtn.wos_eval(g, nodes, W, 2)
+        sig, se = plan.solve(stats)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        out[name] = {"seconds": sec, "walks_per_s": float(plan.num_nodes) * walks_per_node / sec,
+                     "neumann_rel_l2_vs_exact": rel_l2(sig.cpu().numpy(), ex, area, tr)}
+    print(f"[bench] cube tabulated: {out['tabulated']['seconds']:.3f} s vs closed form "
+          f"{out['closed_form']['seconds']:.3f} s", file=sys.stderr, flush=True)
+    return out
+
+
 def plane_or_sphere_panels(pd, R):
     """Panel areas and centre chord distances for patches on a sphere of
     radius |R| (the layout of include/dtn.h: uniform rings in the geodesic
@@ -1066,6 +1104,8 @@ def main():
         line["disk"] = disk("fp64", 1, 1, not args.no_cpu_baseline)
     if args.only is None and not args.no_exterior:
         line["sphere_exterior"] = sphere_exterior("fp64", 1, 1, not args.no_cpu_baseline)
+    if args.only is None and not args.no_tabulated:
+        line["cube_tabulated"] = cube_tabulated()
     if args.only is None and not args.no_serving:
         line["serving"] = serving("fp32", args.serving_window, args.serving_rate, args.serving_se_range,
                                   sweep_window=args.serving_sweep_window)
