@@ -116,13 +116,13 @@ EXT_SLOTS_PER_WALK = slots(EXT_WALK_OPS)
 # the kernel sources it was measured on (SHA-256 of these files).
 TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_amd/csrc/dtn_device.h",
                      "paper_1210_1491_amd/csrc/dtn_internal.h"],
-           "sha256": ["bebedd82506e67d55dcb625cc8c527702c4c0ea179c46fed9c2cb6b488806f73",
-                      "6a1675eaf8869631fee8f9a58747a3423500e1bbb7b205e83c5e42f8e2918dd3",
-                      "b23804fc69bb8cee50a3a03bc57f72e76198ab978429d666ea06ab9b3e0ec3c9"],
-           "fetch_bytes": 71753.188 * 1024 * (262144 / 131088.875), "write_bytes": 43008.0 * 1024 * 1.00,
+           "sha256": ["5ef310b5c4bb8484fdb70bd2eab9dcb269cb157546e3f306fcc8d3dc3b5aa57e",
+                      "32e1aa880c5fc692e427e9181a9b47d14aeeb1ddc66d47bf4bcf324aa713e4f7",
+                      "484a48b7f92b8e6cf794651f517f0a16c59de700e3f5cffad7a2065c3bbf38bb"],
+           "fetch_bytes": 71753.688 * 1024 * (262144 / 131088.5), "write_bytes": 43008.0 * 1024 * 1.00,
            # the half-space point workload's walk kernel (same sources), scaled
-           # by the copy in its own run (fetch 131086.312 KiB for 262144)
-           "halfspace_fetch_bytes": 156228.688 * 1024 * (262144 / 131086.312),
+           # by the copy in its own run (fetch 131086.438 KiB for 262144)
+           "halfspace_fetch_bytes": 156223.625 * 1024 * (262144 / 131086.438),
            "halfspace_write_bytes": 89600.0 * 1024 * 1.00}
 
 
