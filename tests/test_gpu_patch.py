@@ -281,3 +281,29 @@ def test_second_kind_pipeline_and_curved_rejection():
     st = torch.zeros((ball.num_nodes, 4), dtype=torch.float64, device="cuda")
     with pytest.raises(dtn.DtnError):
         ball.solve_second_kind(st)
+
+
+def test_second_kind_on_several_panel_classes():
+    """A box-with-holes sample: patches of every panel class (8..128 panels)
+    in one plan, the second-kind solve against the oracle on exact node
+    values (same bar as the single-class test)."""
+    from oracle import second_kind as SK
+    dtn = _dtn()
+    gd = I.geometry_box_holes()
+    pd_all = I.patches_box_holes(gd)
+    pd = I.subset_patches(pd_all, I.box_holes_sample(pd_all, per_class=1))
+    og = OW.Geometry(gd)
+    rows, ref, scale = [], [], []
+    for p in OP.patches_from_desc(pd, gd):
+        nodes, _ = OP.nodes_global(p)
+        u = og.phi(nodes)
+        rows.append(_stats_from_values(u, 1e4, np.full(len(u), 1e-3)))
+        ref.append(SK.patch_solve_2(p, og, u)["sigma"])
+        Q2 = SK.gamma_operator_2(p.h, p.n_theta, p.n_phi, p.n_rings, p.n_sectors)
+        scale.append(2.0 * (np.abs(Q2) @ np.abs(u) + np.abs(Q2).sum(1) * np.max(np.abs(u))) / 1.0)
+    print(f"[gpu] second kind, {len(pd['h'])} patches of several classes", flush=True)
+    plan = dtn.Plan(dtn.Geometry(gd), pd)
+    sig, _ = plan.solve_second_kind(torch.tensor(np.concatenate(rows), device="cuda"))
+    sig, ref, scale = sig.cpu().numpy(), np.concatenate(ref), np.concatenate(scale)
+    assert np.all(np.abs(sig - ref) <= 1e-8 * scale + 1e-10 * np.max(np.abs(ref))), np.max(np.abs(sig - ref))
+

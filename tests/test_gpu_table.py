@@ -105,3 +105,45 @@ def test_tabulated_rejections():
     bad[2, 1, 1] = np.nan
     with pytest.raises(dtn.DtnError):
         dtn.Geometry(dict(I.geometry_cube_sources(), data_kind="table", tab=bad))
+
+
+def test_points_and_server_on_tabulated_data():
+    """Single-point queries on box faces and the query server both read the
+    face tables: the points against the oracle's reduction of its own walks,
+    the server's answers against the sampled function's exact du/dn."""
+    from oracle import point as OPt
+    dtn = _dtn()
+    gd = I.tabulated_cube_sources()
+    g = dtn.Geometry(gd)
+    og = OW.Geometry(gd)
+    x = np.array([[0.5, 0.5, 0.0], [0.3, 0.0, 0.6]])
+    nrm = np.array([[0.0, 0.0, -1.0], [0.0, -1.0, 0.0]])
+    t1 = np.array([[1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    a = np.array([0.2, 0.25])
+    P = dtn.Points(g, x, nrm, t1, a, n_g1=10, n_g2=10)
+    nodes = P.nodes()
+    W = torch.full((P.num_nodes,), 2000, dtype=torch.int64, device="cuda")
+    stats, _ = dtn.wos_eval(g, nodes, W, 3)
+    out = P.neumann(stats).cpu().numpy()
+    onodes = np.concatenate([OPt.hemisphere_rule(x[i], nrm[i], t1[i], a[i], 10)[0] for i in range(2)])
+    r = OW.wos_nodes(og, onodes, 2000, seed=3)
+    st = np.column_stack([r["count"], r["mean"], r["m2"], r["steps"]])
+    for i in range(2):
+        want = OPt.point_neumann(og.phi, x[i], nrm[i], t1[i], a[i], 10, 10, 1e-6, st[i * 100:(i + 1) * 100])
+        assert abs(out[i, 0] - want[0]) < 0.05 * want[1], (i, out[i], want)
+    # the server on the tabulated data
+    S = dtn.Server(g, n_streams=2, precision="fp32", pilot_walks=64, min_walks=64, max_walks=20_000,
+                   layout=(8, 16, 4, 8))
+    rng = np.random.default_rng(7)
+    pts, nn = I.boundary_points(I.geometry_cube_sources(), 6, rng)
+    S.submit(1, pts, nn, 0.01, 5)
+    done = []
+    while not done:
+        r = S.wait(timeout=120.0)
+        assert r, "server wait timed out"
+        done.extend(r)
+    S.close()
+    assert done[0]["status"] == 0, done[0]
+    ans = done[0]["answer"]
+    ex = OP.exact_neumann(I.geometry_cube_sources(), pts, nn)
+    assert np.all(np.abs(ans[:, 0] - ex) < 4.5 * ans[:, 1] + 5e-3), (ans, ex)
