@@ -32,8 +32,10 @@
  *     raised while enqueuing is returned as DTN_E_DEVICE.  dtn_last_error()
  *     gives a message for the last failing call on the calling thread.  No
  *     C++ exception crosses this interface.
- *   - Geometries and plans are immutable after creation and may be used from
- *     several streams and threads at once.
+ *   - Geometries, plans and point sets are immutable after creation and may
+ *     be used from several streams and threads at once.  A plan, a point set
+ *     and a server refer to the geometry they were created on: destroy them
+ *     before that geometry.
  *   - Randomness: walk k from a point with stream id s uses Philox4x32-10
  *     (Salmon et al., SC'11) with key = seed and counter = (k lo, k hi, draw,
  *     s); one block feeds two steps.  A walk's path is thus a pure function
