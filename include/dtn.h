@@ -312,6 +312,57 @@ dtn_status dtn_patch_solve_second_kind(dtn_plan p, const double *node_stats, dou
 dtn_status dtn_potential(dtn_plan p, const double *neumann, const double *targets, int64_t m,
                          double *u_out, void *stream);
 
+/* ------------------------------------------------- treecode potential
+ * The same sum as dtn_potential (same sources: the tiles' 4 x 4 Gauss points
+ * with their fitted Neumann and exact Dirichlet weights), evaluated by a
+ * kernel-independent treecode, the fast summation the paper names for this
+ * step (Sec. 6): barycentric Lagrange interpolation on Chebyshev points
+ * (Wang, Krasny & Tlupova 2020).
+ *   tree      clusters split at the midpoint of their tight bounding box
+ *             along every dimension with extent >= the largest / sqrt(2),
+ *             children in octant-code order (bit d: upper half in
+ *             dimension d), down to <= leaf_size sources;
+ *   proxies   per cluster a tensor grid of Chebyshev points of the second
+ *             kind on its box padded by 1e-12 of the root extent, `degree`
+ *             in each dimension whose extent exceeds 1e-9 of the largest
+ *             (one point, the centre, otherwise); charges
+ *             q_k = sum_j L_k(y_j) w_j sigma_j and vectors
+ *             p_k = -sum_j L_k(y_j) w_j phi_j n_j (L_k the tensor Lagrange
+ *             basis), so far away u = sum_k [q_k/r + p_k.(x - s_k)/r^3]/(4 pi);
+ *   traversal a cluster of centre c and radius r (half the padded box's
+ *             diagonal) is taken whole when r < theta |x - c|: by its
+ *             proxies if it has more sources than proxies, else directly;
+ *             otherwise its children are visited (a leaf is summed directly).
+ * The tree is built on the host from the plan's tile geometry and kept with
+ * the handle; the proxies are rebuilt from the Neumann data on every call.
+ * Targets are evaluated in Morton order of their position (sorted on the
+ * device), so a wave's 64 targets share most of their traversal.
+ * Create: degree in [1, 8], leaf_size in [8, 4096].  Errors: DTN_E_ARG,
+ * DTN_E_UNSUPPORTED (a plan dtn_potential rejects), DTN_E_OOM.
+ * The tree refers to the plan: destroy it before the plan. */
+typedef struct dtn_tree_s *dtn_tree; /* opaque, library-owned */
+dtn_status dtn_create_tree(dtn_plan p, int32_t degree, int32_t leaf_size, dtn_tree *out);
+void dtn_destroy_tree(dtn_tree t);
+/* Clusters, clusters with proxies, proxies in total, sources (host ints). */
+dtn_status dtn_tree_info(dtn_tree t, int64_t info[4]);
+/* Host only (no device work): the tree dtn_create_tree builds for these
+ * patches (host array).  nodes [cap][8] out, in depth-first pre-order: first
+ * and end source in tree order, end of the subtree (node index), leaf flag,
+ * degrees per axis, first proxy (-1: none); perm [16 n_patches] out: tree
+ * position -> source index 16 i + 4 a + b (tile i, Gauss point (xi_a, xi_b)
+ * along (t1, n x t1)); n_nodes out.  DTN_E_ARG when cap is too small (n_nodes
+ * is still set). */
+dtn_status dtn_tree_layout(const dtn_patch *patches, int64_t n_patches, int32_t degree, int32_t leaf_size,
+                           int64_t cap, int32_t *nodes, int32_t *perm, int64_t *n_nodes);
+
+/* u at m targets (as dtn_potential) by the treecode with MAC parameter theta
+ * in (0, 1).  counts: device [m][2] out (proxy and direct interactions of
+ * each target), or NULL.  Device scratch is allocated stream-ordered.
+ *   neumann device [num_panels]; targets device [m][3]; u_out device [m].
+ * Errors: DTN_E_ARG (NULL arrays with m > 0, theta out of range), DTN_E_OOM. */
+dtn_status dtn_tree_potential(dtn_tree t, const double *neumann, const double *targets, int64_t m,
+                              double theta, double *u_out, int64_t *counts, void *stream);
+
 /* ------------------------------------------------ single point (Sec. 5.1)
  * du/dn at a point x of a flat part of the boundary with no collocation
  * solve.  Over the hemisphere Gamma of radius a centred at x (Sec. 3,

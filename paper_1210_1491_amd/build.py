@@ -6,7 +6,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdtn.so")
-SOURCES = ["dtn_wos.hip", "dtn_patch.hip", "dtn_points.hip", "dtn_operators.cpp", "dtn_capi.cpp", "dtn_server.cpp"]
+SOURCES = ["dtn_wos.hip", "dtn_patch.hip", "dtn_points.hip", "dtn_tree.hip", "dtn_operators.cpp", "dtn_capi.cpp", "dtn_server.cpp"]
 
 
 def hipcc():

@@ -22,6 +22,7 @@
 
 #include "dtn_device.h"
 #include "dtn_internal.h"
+#include "dtn_potential.h"
 
 namespace dtn {
 
@@ -343,16 +344,14 @@ __global__ __launch_bounds__(kLuBlock) void k_lu32(DevClass *__restrict__ classe
 
 // --------------------------------------------------------------- potential
 
-struct Src {
-    double x, y, z, nx, ny, nz, ws, wf;
-};
-
 template <int DATA>
 __global__ __launch_bounds__(64) void k_tile_sources(DevGeom g, const dtn_patch *__restrict__ patches,
                                                      const int32_t *__restrict__ pclass,
                                                      const DevClass *__restrict__ classes,
                                                      const int64_t *__restrict__ panel_off,
-                                                     const double *__restrict__ neumann, Src *__restrict__ src)
+                                                     const double *__restrict__ neumann,
+                                                     const int32_t *__restrict__ slot,
+                                                     TileSource *__restrict__ src)
 {
     const int pi = blockIdx.x, q = threadIdx.x;
     if (q >= 16) return;
@@ -364,25 +363,26 @@ __global__ __launch_bounds__(64) void k_tile_sources(DevGeom g, const dtn_patch 
     double s = 0.0;
     for (int i = 0; i < cl.n_panels; ++i) s += cl.fit[q * cl.n_panels + i] * sig[i];
     const double xi = cl.tile_gl[3 * q], eta = cl.tile_gl[3 * q + 1], w = cl.tile_gl[3 * q + 2] * p.h * p.h;
-    Src o;
+    TileSource o;
     to_global(p, t2, xi, eta, 0.0, o.x, o.y, o.z);
     o.nx = p.n[0];
     o.ny = p.n[1];
     o.nz = p.n[2];
     o.ws = w * s;
     o.wf = w * phi_eval<DATA>(g, o.x, o.y, o.z);
-    src[(size_t)pi * 16 + q] = o;
+    const int64_t at = (int64_t)pi * 16 + q;
+    src[slot ? (int64_t)slot[at] : at] = o;
 }
 
 constexpr int kPotBlock = 256;
 constexpr int kPotChunk = 2048;
 constexpr int kPotStage = 256;
 
-__global__ __launch_bounds__(kPotBlock) void k_potential_partial(const Src *__restrict__ src, int64_t n_src,
+__global__ __launch_bounds__(kPotBlock) void k_potential_partial(const TileSource *__restrict__ src, int64_t n_src,
                                                                  const double *__restrict__ targets, int64_t m,
                                                                  double *__restrict__ partial)
 {
-    __shared__ Src st[kPotStage];
+    __shared__ TileSource st[kPotStage];
     const int64_t t = (int64_t)blockIdx.x * kPotBlock + threadIdx.x;
     const int64_t s0 = (int64_t)blockIdx.y * kPotChunk;
     const int64_t s1 = min(n_src, s0 + kPotChunk);
@@ -399,7 +399,7 @@ __global__ __launch_bounds__(kPotBlock) void k_potential_partial(const Src *__re
         if (threadIdx.x < cnt) st[threadIdx.x] = src[b + threadIdx.x];
         __syncthreads();
         for (int j = 0; j < cnt; ++j) {
-            const Src &s = st[j];
+            const TileSource &s = st[j];
             const double dx = x - s.x, dy = y - s.y, dz = z - s.z;
             const double r2 = dx * dx + dy * dy + dz * dz;
             const double ir = 1.0 / sqrt(r2);
@@ -624,27 +624,41 @@ dtn_status launch_lu32(const Plan &p, hipStream_t s)
     return DTN_OK;
 }
 
+dtn_status launch_tile_sources(const Plan &p, const double *neumann, const int32_t *slot, TileSource *src,
+                               hipStream_t s)
+{
+    const dim3 grid((unsigned)p.patches.size());
+    if (p.geom->dev.data_kind == DTN_DATA_TABULATED)
+        hipLaunchKernelGGL(k_tile_sources<DTN_DATA_TABULATED>, grid, dim3(64), 0, s, p.geom->dev, p.d_patches,
+                           p.d_patch_class, p.d_classes, p.d_panel_off, neumann, slot, src);
+    else if (p.geom->dev.data_kind == DTN_DATA_POINT_SOURCES)
+        hipLaunchKernelGGL(k_tile_sources<DTN_DATA_POINT_SOURCES>, grid, dim3(64), 0, s, p.geom->dev, p.d_patches,
+                           p.d_patch_class, p.d_classes, p.d_panel_off, neumann, slot, src);
+    else
+        hipLaunchKernelGGL(k_tile_sources<DTN_DATA_HARMONIC_QUADRATIC>, grid, dim3(64), 0, s, p.geom->dev,
+                           p.d_patches, p.d_patch_class, p.d_classes, p.d_panel_off, neumann, slot, src);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("tile sources: ") + hipGetErrorString(e));
+    return DTN_OK;
+}
+
 dtn_status launch_potential(const Plan &p, const double *neumann, const double *targets, int64_t m, double *u_out,
                             hipStream_t s)
 {
     if (m == 0) return DTN_OK;
     const int64_t n_src = (int64_t)p.patches.size() * 16;
     const int nchunks = (int)((n_src + kPotChunk - 1) / kPotChunk);
-    const size_t bytes = sizeof(Src) * (size_t)n_src + sizeof(double) * (size_t)nchunks * (size_t)m;
+    const size_t bytes = sizeof(TileSource) * (size_t)n_src + sizeof(double) * (size_t)nchunks * (size_t)m;
     char *scratch = nullptr;
     hipError_t e = hipMallocAsync((void **)&scratch, bytes, s);
     if (e != hipSuccess) return fail(DTN_E_OOM, std::string("dtn_potential: ") + hipGetErrorString(e));
-    Src *src = (Src *)scratch;
-    double *partial = (double *)(scratch + sizeof(Src) * (size_t)n_src);
-    if (p.geom->dev.data_kind == DTN_DATA_TABULATED)
-        hipLaunchKernelGGL(k_tile_sources<DTN_DATA_TABULATED>, dim3((unsigned)p.patches.size()), dim3(64), 0, s,
-                           p.geom->dev, p.d_patches, p.d_patch_class, p.d_classes, p.d_panel_off, neumann, src);
-    else if (p.geom->dev.data_kind == DTN_DATA_POINT_SOURCES)
-        hipLaunchKernelGGL(k_tile_sources<DTN_DATA_POINT_SOURCES>, dim3((unsigned)p.patches.size()), dim3(64), 0, s,
-                           p.geom->dev, p.d_patches, p.d_patch_class, p.d_classes, p.d_panel_off, neumann, src);
-    else
-        hipLaunchKernelGGL(k_tile_sources<DTN_DATA_HARMONIC_QUADRATIC>, dim3((unsigned)p.patches.size()), dim3(64), 0,
-                           s, p.geom->dev, p.d_patches, p.d_patch_class, p.d_classes, p.d_panel_off, neumann, src);
+    TileSource *src = (TileSource *)scratch;
+    double *partial = (double *)(scratch + sizeof(TileSource) * (size_t)n_src);
+    const dtn_status st = launch_tile_sources(p, neumann, nullptr, src, s);
+    if (st != DTN_OK) {
+        (void)hipFreeAsync(scratch, s);
+        return st;
+    }
     hipLaunchKernelGGL(k_potential_partial, dim3((unsigned)((m + kPotBlock - 1) / kPotBlock), (unsigned)nchunks),
                        dim3(kPotBlock), 0, s, src, n_src, targets, m, partial);
     hipLaunchKernelGGL(k_potential_reduce, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, partial, nchunks, m,

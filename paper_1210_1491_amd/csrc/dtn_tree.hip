@@ -1,0 +1,600 @@
+// Treecode evaluation of the final potential (eq. bw03; the paper names a
+// fast summation as the way to scale this step, Sec. 6).  Kernel-independent
+// treecode with barycentric Lagrange interpolation on Chebyshev points (Wang,
+// Krasny & Tlupova, Commun. Comput. Phys. 28, 2020).  With the tile sources
+// y_j, a_j = w_j sigma_j and b_j = -w_j phi_j n_j,
+//   u(x) = sum_j [a_j / |x - y_j| + b_j . (x - y_j) / |x - y_j|^3] / (4 pi),
+// and a cluster's proxies s_k carry q_k = sum_j L_k(y_j) a_j and
+// p_k = sum_j L_k(y_j) b_j, which interpolate y -> 1/|x - y| and its gradient.
+//
+//   host, per handle       tree over the tile sources in depth-first
+//                          pre-order: node j's subtree is nodes [j, skip_j),
+//                          its sources [b, e) in tree order; proxy grids and
+//                          the proxy pass's work items (cluster, source chunk)
+//   k_tree_proxy_partial   one block per work item: 1-D Lagrange values of 64
+//                          sources at a time in LDS, each thread accumulates
+//                          up to 3 proxies of the cluster
+//   k_tree_proxy_reduce    per cluster: chunk partials summed in order, proxy
+//                          points written beside their charges
+//   k_tree_keys            Morton keys of the targets (10 bits per axis in the
+//                          sources' bounding box, clamped), then a radix sort
+//                          of (key, target) pairs (hipCUB)
+//   k_tree_eval            one wave per 64 consecutive sorted targets: a
+//                          stackless walk of the node list under wave-uniform
+//                          control.  Each lane keeps the node index below
+//                          which it is done (it took an ancestor whole); a
+//                          node is opened when a lane still inside it needs
+//                          it opened, else the walk jumps past its subtree.
+//                          Proxies and sources are read at wave-uniform
+//                          addresses.  All FP64.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dtn_device.h"
+#include "dtn_internal.h"
+#include "dtn_potential.h"
+
+namespace dtn {
+namespace {
+
+constexpr int kMaxDegree = 8;
+constexpr int kProxyChunk = 1024;  // sources per proxy work item
+constexpr int kProxyThreads = 256;
+constexpr int kProxySlots = 3;     // (kMaxDegree + 1)^3 = 729 <= kProxyThreads * kProxySlots
+constexpr double kPadRel = 1e-12;  // box padding, relative to the root extent
+constexpr double kFlatRel = 1e-9;  // extents below this (relative) get degree 0
+
+struct TreeNode {
+    double c[3];   // centre of the padded box
+    double r2;     // squared radius (half the padded box's diagonal)
+    double lo[3];  // padded box: the Chebyshev grid's interval per axis
+    double hi[3];
+    int32_t b, e;     // sources [b, e) in tree order
+    int32_t skip;     // first node after this subtree
+    int32_t leaf;     // 1 for a leaf
+    int32_t proxy;    // first proxy, -1 without proxies
+    int32_t n_proxy;  // (deg0 + 1)(deg1 + 1)(deg2 + 1)
+    int32_t deg[3];
+    int32_t pad[3];
+};
+
+struct Proxy {
+    double x, y, z, q, px, py, pz, pad;
+};
+
+struct Item {      // proxy pass work item: one cluster's sources [b, e)
+    int32_t node, b, e, pad;
+    int64_t part;  // offset of its partials (4 doubles per proxy)
+};
+
+struct ProxyCluster {
+    int32_t node, item_b, item_e, pad;
+};
+
+static_assert(sizeof(TreeNode) == 128, "node layout");
+static_assert((kMaxDegree + 1) * (kMaxDegree + 1) * (kMaxDegree + 1) <= kProxyThreads * kProxySlots, "slots");
+
+struct HostTree {
+    std::vector<TreeNode> nodes;
+    std::vector<int32_t> perm;  // tree position -> source index (16 patch + q)
+    std::vector<int32_t> slot;  // source index -> tree position
+    std::vector<Item> items;
+    std::vector<ProxyCluster> pcl;
+    int64_t n_proxies = 0, part_len = 0;
+    double box_lo[3], box_ext[3];  // tight box of all sources (Morton frame)
+};
+
+// Recursive build of node [b, e) of perm (depth-first pre-order).
+void build_node(const std::vector<double> &pos, int32_t b, int32_t e, int degree, int leaf_size, double pad,
+                HostTree &T, std::vector<int32_t> &tmp)
+{
+    double tlo[3], thi[3];
+    for (int d = 0; d < 3; ++d) {
+        tlo[d] = std::numeric_limits<double>::infinity();
+        thi[d] = -tlo[d];
+    }
+    for (int32_t i = b; i < e; ++i)
+        for (int d = 0; d < 3; ++d) {
+            const double v = pos[3 * (size_t)T.perm[i] + d];
+            tlo[d] = std::min(tlo[d], v);
+            thi[d] = std::max(thi[d], v);
+        }
+    double ext[3], big = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        ext[d] = thi[d] - tlo[d];
+        big = std::max(big, ext[d]);
+    }
+    TreeNode nd{};
+    double diag2 = 0.0;
+    nd.n_proxy = 1;
+    for (int d = 0; d < 3; ++d) {
+        nd.lo[d] = tlo[d] - pad;
+        nd.hi[d] = thi[d] + pad;
+        nd.c[d] = 0.5 * (nd.lo[d] + nd.hi[d]);
+        diag2 += (nd.hi[d] - nd.lo[d]) * (nd.hi[d] - nd.lo[d]);
+        nd.deg[d] = ext[d] > kFlatRel * big ? degree : 0;
+        nd.n_proxy *= nd.deg[d] + 1;
+    }
+    nd.r2 = 0.25 * diag2;
+    nd.b = b;
+    nd.e = e;
+    nd.proxy = -1;
+    const bool split = e - b > leaf_size && big > 0.0;
+    nd.leaf = split ? 0 : 1;
+    const int32_t j = (int32_t)T.nodes.size();
+    T.nodes.push_back(nd);
+    if (split) {
+        double mid[3];
+        bool cut[3];
+        for (int d = 0; d < 3; ++d) {
+            mid[d] = 0.5 * (tlo[d] + thi[d]);
+            cut[d] = ext[d] >= big / std::sqrt(2.0);
+        }
+        // stable counting sort of the sources by octant code
+        int32_t cnt[9] = {0};
+        auto code = [&](int32_t s) {
+            int c = 0;
+            for (int d = 0; d < 3; ++d)
+                if (cut[d] && pos[3 * (size_t)s + d] >= mid[d]) c |= 1 << d;
+            return c;
+        };
+        for (int32_t i = b; i < e; ++i) ++cnt[code(T.perm[i]) + 1];
+        for (int c = 0; c < 8; ++c) cnt[c + 1] += cnt[c];
+        int32_t at[8];
+        for (int c = 0; c < 8; ++c) at[c] = b + cnt[c];
+        for (int32_t i = b; i < e; ++i) tmp[at[code(T.perm[i])]++] = T.perm[i];
+        std::copy(tmp.begin() + b, tmp.begin() + e, T.perm.begin() + b);
+        for (int c = 0; c < 8; ++c)
+            if (cnt[c + 1] > cnt[c]) build_node(pos, b + cnt[c], b + cnt[c + 1], degree, leaf_size, pad, T, tmp);
+    }
+    T.nodes[j].skip = (int32_t)T.nodes.size();
+}
+
+void build_tree(const std::vector<double> &pos, int degree, int leaf_size, HostTree &T)
+{
+    const int32_t n = (int32_t)(pos.size() / 3);
+    double lo[3], hi[3], big = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = std::numeric_limits<double>::infinity();
+        hi[d] = -lo[d];
+    }
+    for (int32_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = std::min(lo[d], pos[3 * (size_t)i + d]);
+            hi[d] = std::max(hi[d], pos[3 * (size_t)i + d]);
+        }
+    for (int d = 0; d < 3; ++d) {
+        T.box_lo[d] = lo[d];
+        T.box_ext[d] = hi[d] - lo[d];
+        big = std::max(big, hi[d] - lo[d]);
+    }
+    T.perm.resize(n);
+    for (int32_t i = 0; i < n; ++i) T.perm[i] = i;
+    std::vector<int32_t> tmp(n);
+    build_node(pos, 0, n, degree, leaf_size, kPadRel * big, T, tmp);
+    T.slot.resize(n);
+    for (int32_t i = 0; i < n; ++i) T.slot[T.perm[i]] = i;
+    // proxies of every cluster holding more sources than proxies, in node order
+    for (int32_t j = 0; j < (int32_t)T.nodes.size(); ++j) {
+        TreeNode &nd = T.nodes[j];
+        if (nd.e - nd.b <= nd.n_proxy) continue;
+        nd.proxy = (int32_t)T.n_proxies;
+        T.n_proxies += nd.n_proxy;
+        ProxyCluster pc{j, (int32_t)T.items.size(), 0, 0};
+        for (int32_t s = nd.b; s < nd.e; s += kProxyChunk) {
+            T.items.push_back(Item{j, s, std::min(nd.e, s + kProxyChunk), 0, T.part_len});
+            T.part_len += 4 * (int64_t)nd.n_proxy;
+        }
+        pc.item_e = (int32_t)T.items.size();
+        T.pcl.push_back(pc);
+    }
+}
+
+// Lagrange basis at y through the Chebyshev points of the second kind on
+// [lo, hi] (degree n; the centre alone for n = 0), second barycentric form;
+// the unit vector when y equals a node.
+__device__ void lagrange_1d(double y, double lo, double hi, int n, double *L)
+{
+    if (n == 0) {
+        L[0] = 1.0;
+        return;
+    }
+    const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+    double sum = 0.0;
+    int hit = -1;
+    for (int k = 0; k <= n; ++k) {
+        const double d = y - (c + h * cos(M_PI * k / n));
+        const double w = ((k & 1) ? -1.0 : 1.0) * ((k == 0 || k == n) ? 0.5 : 1.0);
+        if (d == 0.0) hit = k;
+        const double t = d == 0.0 ? 0.0 : w / d;
+        L[k] = t;
+        sum += t;
+    }
+    for (int k = 0; k <= n; ++k) L[k] = hit >= 0 ? (k == hit ? 1.0 : 0.0) : L[k] / sum;
+}
+
+__device__ __forceinline__ double cheb_point(const TreeNode &nd, int d, int k)
+{
+    if (nd.deg[d] == 0) return 0.5 * (nd.lo[d] + nd.hi[d]);
+    return 0.5 * (nd.lo[d] + nd.hi[d]) + 0.5 * (nd.hi[d] - nd.lo[d]) * cos(M_PI * k / nd.deg[d]);
+}
+
+__global__ __launch_bounds__(kProxyThreads) void k_tree_proxy_partial(const TreeNode *__restrict__ nodes,
+                                                                      const Item *__restrict__ items,
+                                                                      const TileSource *__restrict__ src,
+                                                                      double *__restrict__ part)
+{
+    __shared__ double sl[3][64][kMaxDegree + 1];
+    __shared__ double sw[64][4];
+    const Item it = items[blockIdx.x];
+    const TreeNode &nd = nodes[it.node];
+    const int tid = threadIdx.x;
+    const int n1 = nd.deg[1] + 1, n2 = nd.deg[2] + 1, np = nd.n_proxy;
+    int k0[kProxySlots], k1[kProxySlots], k2[kProxySlots];
+    double acc[kProxySlots][4];
+    for (int s = 0; s < kProxySlots; ++s) {
+        const int k = tid + kProxyThreads * s;
+        k2[s] = k % n2;
+        k1[s] = (k / n2) % n1;
+        k0[s] = k / (n1 * n2);
+        for (int c = 0; c < 4; ++c) acc[s][c] = 0.0;
+    }
+    for (int32_t base = it.b; base < it.e; base += 64) {
+        const int cnt = min(64, it.e - base);
+        __syncthreads();
+        if (tid < cnt) {
+            const TileSource s = src[base + tid];
+            sw[tid][0] = s.ws;
+            sw[tid][1] = -s.wf * s.nx;
+            sw[tid][2] = -s.wf * s.ny;
+            sw[tid][3] = -s.wf * s.nz;
+            lagrange_1d(s.x, nd.lo[0], nd.hi[0], nd.deg[0], sl[0][tid]);
+            lagrange_1d(s.y, nd.lo[1], nd.hi[1], nd.deg[1], sl[1][tid]);
+            lagrange_1d(s.z, nd.lo[2], nd.hi[2], nd.deg[2], sl[2][tid]);
+        }
+        __syncthreads();
+        for (int s = 0; s < kProxySlots; ++s) {
+            if (tid + kProxyThreads * s >= np) break;
+            for (int j = 0; j < cnt; ++j) {
+                const double L = sl[0][j][k0[s]] * sl[1][j][k1[s]] * sl[2][j][k2[s]];
+                for (int c = 0; c < 4; ++c) acc[s][c] += L * sw[j][c];
+            }
+        }
+    }
+    for (int s = 0; s < kProxySlots; ++s) {
+        const int k = tid + kProxyThreads * s;
+        if (k < np)
+            for (int c = 0; c < 4; ++c) part[it.part + 4 * (int64_t)k + c] = acc[s][c];
+    }
+}
+
+__global__ __launch_bounds__(kProxyThreads) void k_tree_proxy_reduce(const TreeNode *__restrict__ nodes,
+                                                                     const ProxyCluster *__restrict__ pcl,
+                                                                     const Item *__restrict__ items,
+                                                                     const double *__restrict__ part,
+                                                                     Proxy *__restrict__ prox)
+{
+    const ProxyCluster pc = pcl[blockIdx.x];
+    const TreeNode &nd = nodes[pc.node];
+    const int n1 = nd.deg[1] + 1, n2 = nd.deg[2] + 1;
+    for (int k = threadIdx.x; k < nd.n_proxy; k += kProxyThreads) {
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int32_t i = pc.item_b; i < pc.item_e; ++i)
+            for (int c = 0; c < 4; ++c) v[c] += part[items[i].part + 4 * (int64_t)k + c];
+        Proxy o;
+        o.x = cheb_point(nd, 0, k / (n1 * n2));
+        o.y = cheb_point(nd, 1, (k / n2) % n1);
+        o.z = cheb_point(nd, 2, k % n2);
+        o.q = v[0];
+        o.px = v[1];
+        o.py = v[2];
+        o.pz = v[3];
+        o.pad = 0.0;
+        prox[nd.proxy + k] = o;
+    }
+}
+
+__device__ __forceinline__ uint32_t spread10(uint32_t v)
+{
+    v &= 1023u;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_tree_keys(const double *__restrict__ targets, int64_t m, double lo0,
+                                                   double lo1, double lo2, double sc0, double sc1, double sc2,
+                                                   uint32_t *__restrict__ keys, uint32_t *__restrict__ ids)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    const double lo[3] = {lo0, lo1, lo2}, sc[3] = {sc0, sc1, sc2};
+    uint32_t key = 0;
+    for (int d = 0; d < 3; ++d) {
+        const double u = fmin(fmax((targets[3 * t + d] - lo[d]) * sc[d], 0.0), 1023.0);
+        key |= spread10((uint32_t)u) << d;
+    }
+    keys[t] = key;
+    ids[t] = (uint32_t)t;
+}
+
+enum : int { kNone = 0, kTakeProxy = 1, kTakeDirect = 2, kOpen = 3 };
+
+__global__ __launch_bounds__(64) void k_tree_eval(const TreeNode *__restrict__ nodes, int32_t n_nodes,
+                                                  const Proxy *__restrict__ prox,
+                                                  const TileSource *__restrict__ src,
+                                                  const double *__restrict__ targets,
+                                                  const uint32_t *__restrict__ order, int64_t m, double theta2,
+                                                  double *__restrict__ u, int64_t *__restrict__ counts)
+{
+    const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const bool valid = t < m;
+    const int64_t id = valid ? (int64_t)order[t] : 0;
+    double x = 0.0, y = 0.0, z = 0.0;
+    if (valid) {
+        x = targets[3 * id];
+        y = targets[3 * id + 1];
+        z = targets[3 * id + 2];
+    }
+    int32_t done_below = valid ? 0 : INT32_MAX;  // the lane is inside node j iff j >= done_below
+    double acc = 0.0;
+    int64_t n_prox = 0, n_dir = 0;
+    int32_t j = 0;
+    while (j < n_nodes) {
+        const TreeNode &nd = nodes[j];
+        const double dx = x - nd.c[0], dy = y - nd.c[1], dz = z - nd.c[2];
+        const double R2 = dx * dx + dy * dy + dz * dz;
+        int act = kNone;
+        if (j >= done_below)
+            act = nd.r2 < theta2 * R2 ? (nd.proxy >= 0 ? kTakeProxy : kTakeDirect) : (nd.leaf ? kTakeDirect : kOpen);
+        if (__any(act == kTakeProxy)) {
+            for (int32_t k = nd.proxy; k < nd.proxy + nd.n_proxy; ++k) {
+                const Proxy &p = prox[k];
+                if (act == kTakeProxy) {
+                    const double ex = x - p.x, ey = y - p.y, ez = z - p.z;
+                    const double ir = 1.0 / sqrt(ex * ex + ey * ey + ez * ez);
+                    acc += p.q * ir + (p.px * ex + p.py * ey + p.pz * ez) * (ir * ir * ir);
+                }
+            }
+            if (act == kTakeProxy) n_prox += nd.n_proxy;
+        }
+        if (__any(act == kTakeDirect)) {
+            for (int32_t k = nd.b; k < nd.e; ++k) {
+                const TileSource &s = src[k];
+                if (act == kTakeDirect) {
+                    const double ex = x - s.x, ey = y - s.y, ez = z - s.z;
+                    const double ir = 1.0 / sqrt(ex * ex + ey * ey + ez * ez);
+                    acc += s.ws * ir - s.wf * (ex * s.nx + ey * s.ny + ez * s.nz) * (ir * ir * ir);
+                }
+            }
+            if (act == kTakeDirect) n_dir += nd.e - nd.b;
+        }
+        if (act == kTakeProxy || act == kTakeDirect) done_below = nd.skip;
+        j = __any(act == kOpen) ? j + 1 : nd.skip;
+    }
+    if (valid) {
+        u[id] = acc * (1.0 / (4.0 * M_PI));
+        if (counts) {
+            counts[2 * id] = n_prox;
+            counts[2 * id + 1] = n_dir;
+        }
+    }
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Tile sources on the host: c + h (xi t1 + eta t2) for the 4 x 4 Gauss points
+// (xi, eta), t2 = n x t1, source 4 a + b of a tile at (xi_a, xi_b).
+std::vector<double> tile_positions(const dtn_patch *patches, int64_t n)
+{
+    std::vector<double> gx, gw;
+    gauss_legendre_rule(4, gx, gw);
+    std::vector<double> pos((size_t)n * 16 * 3);
+    for (int64_t i = 0; i < n; ++i) {
+        const dtn_patch &q = patches[i];
+        const double t2[3] = {q.n[1] * q.t1[2] - q.n[2] * q.t1[1], q.n[2] * q.t1[0] - q.n[0] * q.t1[2],
+                              q.n[0] * q.t1[1] - q.n[1] * q.t1[0]};
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b)
+                for (int d = 0; d < 3; ++d)
+                    pos[3 * (16 * (size_t)i + 4 * a + b) + d] = q.c[d] + q.h * (gx[a] * q.t1[d] + gx[b] * t2[d]);
+    }
+    return pos;
+}
+
+}  // namespace
+
+struct TreeHandle {
+    const Plan *plan = nullptr;
+    HostTree host;
+    TreeNode *d_nodes = nullptr;
+    int32_t *d_slot = nullptr;
+    Item *d_items = nullptr;
+    ProxyCluster *d_pcl = nullptr;
+    int device = 0;
+};
+
+}  // namespace dtn
+
+struct dtn_tree_s {
+    dtn::TreeHandle t;
+};
+
+using namespace dtn;
+
+namespace {
+
+template <class T>
+hipError_t upload_vec(const std::vector<T> &v, T **out)
+{
+    *out = nullptr;
+    if (v.empty()) return hipSuccess;
+    hipError_t e = hipMalloc((void **)out, sizeof(T) * v.size());
+    if (e == hipSuccess) e = hipMemcpy(*out, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
+    return e;
+}
+
+void free_tree(dtn_tree t)
+{
+    (void)hipFree(t->t.d_nodes);
+    (void)hipFree(t->t.d_slot);
+    (void)hipFree(t->t.d_items);
+    (void)hipFree(t->t.d_pcl);
+}
+
+}  // namespace
+
+dtn_status dtn_create_tree(dtn_plan p, int32_t degree, int32_t leaf_size, dtn_tree *out)
+{
+    const std::string at = "dtn_create_tree: ";
+    try {
+        if (!p || !out) return fail(DTN_E_ARG, at + "NULL argument");
+        *out = nullptr;
+        if (degree < 1 || degree > kMaxDegree) return fail(DTN_E_ARG, at + "degree outside [1, 8]");
+        if (leaf_size < 8 || leaf_size > 4096) return fail(DTN_E_ARG, at + "leaf_size outside [8, 4096]");
+        const Plan &P = p->p;
+        if (!P.tiles_ok)
+            return fail(DTN_E_UNSUPPORTED, at + "needs square tiles on the faces of a box domain");
+        if ((int64_t)P.patches.size() * 16 > (int64_t)INT32_MAX / 2) return fail(DTN_E_ARG, at + "too many tiles");
+        const std::vector<double> pos = tile_positions(P.patches.data(), (int64_t)P.patches.size());
+        std::unique_ptr<dtn_tree_s> T(new dtn_tree_s());
+        T->t.plan = &P;
+        build_tree(pos, degree, leaf_size, T->t.host);
+        hipError_t e = hipGetDevice(&T->t.device);
+        if (e == hipSuccess) e = upload_vec(T->t.host.nodes, &T->t.d_nodes);
+        if (e == hipSuccess) e = upload_vec(T->t.host.slot, &T->t.d_slot);
+        if (e == hipSuccess) e = upload_vec(T->t.host.items, &T->t.d_items);
+        if (e == hipSuccess) e = upload_vec(T->t.host.pcl, &T->t.d_pcl);
+        if (e != hipSuccess) {
+            free_tree(T.get());
+            return fail(DTN_E_OOM, at + hipGetErrorString(e));
+        }
+        *out = T.release();
+        return DTN_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(DTN_E_OOM, at + "host allocation failed");
+    } catch (...) {
+        return fail(DTN_E_OOM, at + "exception");
+    }
+}
+
+void dtn_destroy_tree(dtn_tree t)
+{
+    if (!t) return;
+    free_tree(t);
+    delete t;
+}
+
+dtn_status dtn_tree_layout(const dtn_patch *patches, int64_t n_patches, int32_t degree, int32_t leaf_size,
+                           int64_t cap, int32_t *nodes, int32_t *perm, int64_t *n_nodes)
+{
+    const std::string at = "dtn_tree_layout: ";
+    try {
+        if (!patches || !nodes || !perm || !n_nodes) return fail(DTN_E_ARG, at + "NULL argument");
+        if (n_patches < 1 || n_patches * 16 > (int64_t)INT32_MAX / 2) return fail(DTN_E_ARG, at + "bad n_patches");
+        if (degree < 1 || degree > kMaxDegree) return fail(DTN_E_ARG, at + "degree outside [1, 8]");
+        if (leaf_size < 8 || leaf_size > 4096) return fail(DTN_E_ARG, at + "leaf_size outside [8, 4096]");
+        HostTree H;
+        build_tree(tile_positions(patches, n_patches), degree, leaf_size, H);
+        *n_nodes = (int64_t)H.nodes.size();
+        if ((int64_t)H.nodes.size() > cap) return fail(DTN_E_ARG, at + "cap below the number of nodes");
+        for (size_t j = 0; j < H.nodes.size(); ++j) {
+            const TreeNode &nd = H.nodes[j];
+            const int32_t row[8] = {nd.b, nd.e, nd.skip, nd.leaf, nd.deg[0], nd.deg[1], nd.deg[2], nd.proxy};
+            std::copy(row, row + 8, nodes + 8 * j);
+        }
+        std::copy(H.perm.begin(), H.perm.end(), perm);
+        return DTN_OK;
+    } catch (...) {
+        return fail(DTN_E_OOM, at + "exception");
+    }
+}
+
+dtn_status dtn_tree_info(dtn_tree t, int64_t info[4])
+{
+    if (!t || !info) return fail(DTN_E_ARG, "dtn_tree_info: NULL argument");
+    info[0] = (int64_t)t->t.host.nodes.size();
+    info[1] = (int64_t)t->t.host.pcl.size();
+    info[2] = t->t.host.n_proxies;
+    info[3] = (int64_t)t->t.host.perm.size();
+    return DTN_OK;
+}
+
+dtn_status dtn_tree_potential(dtn_tree t, const double *neumann, const double *targets, int64_t m, double theta,
+                              double *u_out, int64_t *counts, void *stream)
+{
+    const std::string at = "dtn_tree_potential: ";
+    try {
+        if (!t) return fail(DTN_E_ARG, at + "NULL tree");
+        if (m < 0 || m > (int64_t)INT32_MAX) return fail(DTN_E_ARG, at + "m outside [0, 2^31)");
+        if (!(theta > 0.0 && theta < 1.0)) return fail(DTN_E_ARG, at + "theta outside (0, 1)");
+        if (m > 0 && (!neumann || !targets || !u_out)) return fail(DTN_E_ARG, at + "NULL array");
+        if (m == 0) return DTN_OK;
+        const hipStream_t s = (hipStream_t)stream;
+        const HostTree &H = t->t.host;
+        const int64_t n_src = (int64_t)H.perm.size();
+        size_t sort_bytes = 0;
+        hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const uint32_t *)nullptr,
+                                                          (uint32_t *)nullptr, (const uint32_t *)nullptr,
+                                                          (uint32_t *)nullptr, (int)m, 0, 30, s);
+        if (e != hipSuccess) return fail(DTN_E_DEVICE, at + hipGetErrorString(e));
+        const size_t o_src = 0;
+        const size_t o_part = o_src + align256(sizeof(TileSource) * (size_t)n_src);
+        const size_t o_prox = o_part + align256(sizeof(double) * (size_t)std::max<int64_t>(H.part_len, 1));
+        const size_t o_keys = o_prox + align256(sizeof(Proxy) * (size_t)std::max<int64_t>(H.n_proxies, 1));
+        const size_t o_sorted = o_keys + align256(sizeof(uint32_t) * (size_t)m);
+        const size_t o_ids = o_sorted + align256(sizeof(uint32_t) * (size_t)m);
+        const size_t o_order = o_ids + align256(sizeof(uint32_t) * (size_t)m);
+        const size_t o_tmp = o_order + align256(sizeof(uint32_t) * (size_t)m);
+        const size_t bytes = o_tmp + align256(std::max<size_t>(sort_bytes, 1));
+        char *w = nullptr;
+        e = hipMallocAsync((void **)&w, bytes, s);
+        if (e != hipSuccess) return fail(DTN_E_OOM, at + hipGetErrorString(e));
+        TileSource *src = (TileSource *)(w + o_src);
+        double *part = (double *)(w + o_part);
+        Proxy *prox = (Proxy *)(w + o_prox);
+        uint32_t *keys = (uint32_t *)(w + o_keys), *sorted = (uint32_t *)(w + o_sorted);
+        uint32_t *ids = (uint32_t *)(w + o_ids), *order = (uint32_t *)(w + o_order);
+        dtn_status st = launch_tile_sources(*t->t.plan, neumann, t->t.d_slot, src, s);
+        if (st != DTN_OK) {
+            (void)hipFreeAsync(w, s);
+            return st;
+        }
+        if (!H.items.empty()) {
+            hipLaunchKernelGGL(k_tree_proxy_partial, dim3((unsigned)H.items.size()), dim3(kProxyThreads), 0, s,
+                               t->t.d_nodes, t->t.d_items, src, part);
+            hipLaunchKernelGGL(k_tree_proxy_reduce, dim3((unsigned)H.pcl.size()), dim3(kProxyThreads), 0, s,
+                               t->t.d_nodes, t->t.d_pcl, t->t.d_items, part, prox);
+        }
+        double sc[3];
+        for (int d = 0; d < 3; ++d) sc[d] = H.box_ext[d] > 0.0 ? 1024.0 / H.box_ext[d] : 0.0;
+        hipLaunchKernelGGL(k_tree_keys, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, targets, m, H.box_lo[0],
+                           H.box_lo[1], H.box_lo[2], sc[0], sc[1], sc[2], keys, ids);
+        e = hipGetLastError();
+        if (e == hipSuccess)
+            e = hipcub::DeviceRadixSort::SortPairs((void *)(w + o_tmp), sort_bytes, keys, sorted, ids, order, (int)m,
+                                                   0, 30, s);
+        if (e == hipSuccess) {
+            const double theta2 = theta * theta;
+            hipLaunchKernelGGL(k_tree_eval, dim3((unsigned)((m + 63) / 64)), dim3(64), 0, s, t->t.d_nodes,
+                               (int32_t)H.nodes.size(), prox, src, targets, order, m, theta2, u_out, counts);
+            e = hipGetLastError();
+        }
+        const hipError_t ef = hipFreeAsync(w, s);
+        if (e == hipSuccess) e = ef;
+        if (e != hipSuccess) return fail(DTN_E_DEVICE, at + hipGetErrorString(e));
+        return DTN_OK;
+    } catch (...) {
+        return fail(DTN_E_OOM, at + "exception");
+    }
+}

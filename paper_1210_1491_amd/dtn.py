@@ -131,6 +131,13 @@ def lib():
         L.dtn_points_num_nodes.restype = C.c_int64
         L.dtn_points_nodes.argtypes = [vp, vp, vp]
         L.dtn_points_neumann.argtypes = [vp, vp, vp, vp]
+        L.dtn_create_tree.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(vp)]
+        L.dtn_destroy_tree.argtypes = [vp]
+        L.dtn_destroy_tree.restype = None
+        L.dtn_tree_info.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.dtn_tree_potential.argtypes = [vp, vp, vp, C.c_int64, C.c_double, vp, vp, vp]
+        L.dtn_tree_layout.argtypes = [C.POINTER(PatchDesc), C.c_int64, C.c_int32, C.c_int32, C.c_int64, vp, vp,
+                                      C.POINTER(C.c_int64)]
         dp = C.POINTER(C.c_double)
         L.dtn_class_operators.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
                                           dp, dp, dp, dp, dp, dp]
@@ -138,6 +145,7 @@ def lib():
                   "dtn_boundary_distance", "dtn_server_create", "dtn_server_submit", "dtn_server_wait",
                   "dtn_create_plan", "dtn_patch_nodes",
                   "dtn_patch_solve", "dtn_patch_solve_second_kind", "dtn_class_second_kind", "dtn_potential",
+                  "dtn_create_tree", "dtn_tree_info", "dtn_tree_potential", "dtn_tree_layout",
                   "dtn_class_operators",
                   "dtn_create_points",
                   "dtn_points_nodes", "dtn_points_neumann"):
@@ -375,6 +383,43 @@ class Plan:
         return out
 
 
+class Tree:
+    """Treecode for the potential of a tile plan (same sum as Plan.potential):
+    the tree over the tile sources is built once; each call rebuilds the
+    Chebyshev proxies from the Neumann data and walks the tree per wave of
+    Morton-sorted targets."""
+
+    def __init__(self, plan, degree=6, leaf_size=64):
+        self.plan = plan
+        self.handle = C.c_void_p()
+        _check(lib().dtn_create_tree(plan.handle, int(degree), int(leaf_size), C.byref(self.handle)),
+               "dtn_create_tree")
+        info = (C.c_int64 * 4)()
+        _check(lib().dtn_tree_info(self.handle, info), "dtn_tree_info")
+        self.n_clusters, self.n_proxy_clusters, self.n_proxies, self.n_sources = (int(v) for v in info)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.dtn_destroy_tree(h)
+            self.handle = None
+
+    def potential(self, neumann, targets, theta=0.5, out=None, counts=None):
+        """u at the targets; counts (int64 [m][2], optional) receives each
+        target's proxy and direct interactions."""
+        m = targets.shape[0]
+        _dev_tensor(neumann, torch.float64, (self.plan.num_panels,))
+        _dev_tensor(targets, torch.float64, (m, 3))
+        if out is None:
+            out = torch.empty(m, dtype=torch.float64, device=targets.device)
+        _dev_tensor(out, torch.float64, (m,))
+        if counts is not None:
+            _dev_tensor(counts, torch.int64, (m, 2))
+        _check(lib().dtn_tree_potential(self.handle, _ptr(neumann), _ptr(targets), m, float(theta), _ptr(out),
+                                        _ptr(counts), _stream()), "dtn_tree_potential")
+        return out
+
+
 class Points:
     """Single-point queries on a flat boundary (Sec. 5.1): hemisphere nodes
     and du/dn = Sigma1' + Sigma2' from the node statistics."""
@@ -419,6 +464,21 @@ class Points:
         _dev_tensor(out, torch.float64, (self.n, 4))
         _check(lib().dtn_points_neumann(self.handle, _ptr(node_stats), _ptr(out), _stream()), "dtn_points_neumann")
         return out
+
+
+def tree_layout(pdesc, degree=6, leaf_size=64):
+    """Host diagnostic: the treecode's tree for these patches (no device):
+    nodes [n][8] (first, end source, subtree end, leaf, degrees, first proxy)
+    and the source permutation."""
+    arr = patches_struct(pdesc)
+    n = len(pdesc["h"])
+    cap = 4 * 16 * n + 16
+    nodes = np.empty((cap, 8), dtype=np.int32)
+    perm = np.empty(16 * n, dtype=np.int32)
+    nn = C.c_int64()
+    _check(lib().dtn_tree_layout(arr, n, int(degree), int(leaf_size), cap, nodes.ctypes.data_as(C.c_void_p),
+                                 perm.ctypes.data_as(C.c_void_p), C.byref(nn)), "dtn_tree_layout")
+    return nodes[: nn.value].copy(), perm
 
 
 def class_operators(n_theta, n_phi, n_rings, n_sectors, rr=0.0):
