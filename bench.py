@@ -227,7 +227,9 @@ def parse():
     ap.add_argument("--no-disk", action="store_true", help="skip the thin-disk workload (Table 5)")
     ap.add_argument("--no-exterior", action="store_true", help="skip the exterior-sphere workload (Sec. 5.2)")
     ap.add_argument("--no-tabulated", action="store_true", help="skip the tabulated-data workload")
-    ap.add_argument("--only", choices=["cube", "box_holes", "serving", "halfspace", "disk", "exterior"], default=None,
+    ap.add_argument("--no-treecode", action="store_true", help="skip the treecode-potential workload")
+    ap.add_argument("--only", choices=["cube", "box_holes", "serving", "halfspace", "disk", "exterior", "treecode"],
+                    default=None,
                     help="run one workload only (for profiling)")
     ap.add_argument("--box-holes-se", type=float, default=None,
                     help="target standard error of the uneven-batching workload (default: its 1e-3)")
@@ -716,6 +718,72 @@ def cube_tabulated(walks_per_node=10_000, n_grid=257):
     return out
 
 
+def treecode_potential(m_tiles=96, n_targets=1_000_000, degree=6, theta=0.5, leaf=64, reps=3):
+    """The potential (eq. bw03) of a finer cube tiling (m_tiles^2 tiles per
+    face, 16 sources each: 884,736 at 96) at 1e6 targets uniform in the cube,
+    by the treecode and by the direct sum, from the exact du/dn at the
+    collocation points (the potential is linear in the Neumann data; this
+    leg measures the summation).  Times of whole calls (tile sources,
+    proxies, target sort and traversal for the treecode), interactions per
+    target, the treecode's error against the direct sum on every target and
+    both sums' error against the exact u at targets at least two tile sides
+    from the boundary."""
+    import torch
+
+    import dtn_inputs as I
+    from paper_1210_1491_amd import dtn
+
+    gd = I.geometry_cube_sources()
+    pd = I.patches_cube_tiles(m_tiles)
+    xg, ng, _, _ = plane_panels(pd)
+    neu = torch.tensor(np.sum(exact_grad(gd, xg) * ng, axis=-1), device="cuda")
+    tg_np = np.random.default_rng([5, m_tiles]).random((n_targets, 3))
+    tg = torch.tensor(tg_np, device="cuda")
+    g = dtn.Geometry(gd)
+    plan = dtn.Plan(g, pd)
+    t0 = time.perf_counter()
+    tree = dtn.Tree(plan, degree, leaf)
+    t_build = time.perf_counter() - t0
+    counts = torch.empty((n_targets, 2), dtype=torch.int64, device="cuda")
+    u_t = tree.potential(neu, tg, theta, counts=counts)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        tree.potential(neu, tg, theta, out=u_t)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms_tree = ev[0].elapsed_time(ev[1]) / reps
+    u_d = plan.potential(neu, tg)
+    torch.cuda.synchronize()
+    ev[0].record()
+    plan.potential(neu, tg, out=u_d)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms_direct = ev[0].elapsed_time(ev[1])
+    u_t, u_d, cnt = u_t.cpu().numpy(), u_d.cpu().numpy(), counts.cpu().numpy()
+    far = np.min(np.minimum(tg_np, 1.0 - tg_np), axis=1) >= 2.0 / m_tiles
+    ex = exact_u(gd, tg_np[far])
+    inter = float(cnt.sum()) / n_targets
+    out = {
+        "workload": f"unit cube, {m_tiles}x{m_tiles} tiles per face ({tree.n_sources} sources), "
+                    f"{n_targets} targets uniform in the cube, exact du/dn",
+        "degree": degree, "theta": theta, "leaf_size": leaf,
+        "clusters": tree.n_clusters, "proxies": tree.n_proxies, "tree_build_s": t_build,
+        "ms_treecode": ms_tree, "ms_direct": ms_direct, "speedup": ms_direct / ms_tree,
+        "interactions_per_target": inter, "direct_pairs_per_target": tree.n_sources,
+        "treecode_interactions_per_s": inter * n_targets / (ms_tree * 1e-3),
+        "direct_pairs_per_s": float(tree.n_sources) * n_targets / (ms_direct * 1e-3),
+        "max_rel_diff_treecode_vs_direct": float(np.max(np.abs(u_t - u_d)) / np.max(np.abs(u_d))),
+        "max_err_vs_exact_treecode": float(np.max(np.abs(u_t[far] - ex))),
+        "max_err_vs_exact_direct": float(np.max(np.abs(u_d[far] - ex))),
+        "targets_vs_exact": int(far.sum()),
+    }
+    print(f"[bench] treecode potential: {ms_tree:.1f} ms vs direct {ms_direct:.1f} ms "
+          f"({out['speedup']:.1f}x), {inter:.0f} interactions per target", file=sys.stderr, flush=True)
+    return out
+
+
 def plane_or_sphere_panels(pd, R):
     """Panel areas and centre chord distances for patches on a sphere of
     radius |R| (the layout of include/dtn.h: uniform rings in the geodesic
@@ -1031,6 +1099,9 @@ def main():
         print(json.dumps({"disk": disk(args.precision, args.steps, args.warmup, not args.no_cpu_baseline)}),
               flush=True)
         return
+    if args.only == "treecode":
+        print(json.dumps({"treecode_potential": treecode_potential()}), flush=True)
+        return
     if args.only == "halfspace":
         print(json.dumps({"halfspace_points": halfspace_points(args.precision, args.steps, args.warmup,
                                                                not args.no_cpu_baseline)}), flush=True)
@@ -1106,6 +1177,8 @@ def main():
         line["sphere_exterior"] = sphere_exterior("fp64", 1, 1, not args.no_cpu_baseline)
     if args.only is None and not args.no_tabulated:
         line["cube_tabulated"] = cube_tabulated()
+    if args.only is None and not args.no_treecode:
+        line["treecode_potential"] = treecode_potential()
     if args.only is None and not args.no_serving:
         line["serving"] = serving("fp32", args.serving_window, args.serving_rate, args.serving_se_range,
                                   sweep_window=args.serving_sweep_window)

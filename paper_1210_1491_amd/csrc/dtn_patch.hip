@@ -402,7 +402,7 @@ __global__ __launch_bounds__(kPotBlock) void k_potential_partial(const TileSourc
             const TileSource &s = st[j];
             const double dx = x - s.x, dy = y - s.y, dz = z - s.z;
             const double r2 = dx * dx + dy * dy + dz * dz;
-            const double ir = 1.0 / sqrt(r2);
+            const double ir = rsqrt(r2);
             const double ir3 = ir * ir * ir;
             acc += s.ws * ir - s.wf * (dx * s.nx + dy * s.ny + dz * s.nz) * ir3;
         }

@@ -362,7 +362,7 @@ __global__ __launch_bounds__(64) void k_tree_eval(const TreeNode *__restrict__ n
                 const Proxy &p = prox[k];
                 if (act == kTakeProxy) {
                     const double ex = x - p.x, ey = y - p.y, ez = z - p.z;
-                    const double ir = 1.0 / sqrt(ex * ex + ey * ey + ez * ez);
+                    const double ir = rsqrt(ex * ex + ey * ey + ez * ez);
                     acc += p.q * ir + (p.px * ex + p.py * ey + p.pz * ez) * (ir * ir * ir);
                 }
             }
@@ -373,7 +373,7 @@ __global__ __launch_bounds__(64) void k_tree_eval(const TreeNode *__restrict__ n
                 const TileSource &s = src[k];
                 if (act == kTakeDirect) {
                     const double ex = x - s.x, ey = y - s.y, ez = z - s.z;
-                    const double ir = 1.0 / sqrt(ex * ex + ey * ey + ez * ez);
+                    const double ir = rsqrt(ex * ex + ey * ey + ez * ez);
                     acc += s.ws * ir - s.wf * (ex * s.nx + ey * s.ny + ez * s.nz) * (ir * ir * ir);
                 }
             }
