@@ -443,7 +443,15 @@ dtn_status dtn_points_neumann(dtn_points p, const double *node_stats, double *ou
  * the host process with a cause not yet shown, so dtn_server_create rejects
  * it (DTN_E_ARG); dtn_server_footprint still reports its padded sizes.
  * Only box domains (with or without holes) are served: every point must lie
- * on a face, with the face's outward normal. */
+ * on a face, with the face's outward normal.
+ * Point mode (n_g1 > 0): the single-point estimate of Sec. 5.1 with no
+ * collocation solve.  Each point gets the hemisphere of radius a = the rung
+ * h chosen as above (the same half ball, so it lies inside Omega), its
+ * n_g1 x n_g1 nodes walked with the adaptive budgets, and the answer
+ * (Sigma1' + Sigma2', its standard error, walks spent, a) as
+ * dtn_points_neumann computes it; stream ids are node indices within the
+ * query (point-major, theta-major, psi-minor).  The patch layout fields must
+ * still be valid; they place nothing in this mode. */
 typedef struct dtn_server_s *dtn_server; /* opaque, library-owned */
 
 typedef struct {
@@ -460,6 +468,8 @@ typedef struct {
                                    dtn_server_create with DTN_E_ARG, see below */
     int32_t max_batch_queries;  /* queries joined into one batch at most; 0 = no limit,
                                    1 = one query per batch (no batching across requests) */
+    int32_t n_g1, n_g2;  /* point mode when n_g1 > 0 (see below): hemisphere and ring rules, [1, 64] */
+    double delta_rel;    /* point mode: excluded disk radius / a, in (0, 1) */
 } dtn_server_config;
 
 /* Completion record of a query; times in seconds on the server's clock. */

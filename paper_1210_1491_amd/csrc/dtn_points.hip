@@ -25,17 +25,15 @@
 
 #include "dtn_device.h"
 #include "dtn_internal.h"
+#include "dtn_point_rule.h"
 
 namespace dtn {
 
 struct Points {
     Geometry *geom = nullptr;
     std::vector<dtn_point> pts;
-    int n_g1 = 0, n_g2 = 0;
-    double delta_rel = 0.0;
+    PointRule rule;
     dtn_point *d_pts = nullptr;
-    double *d_hemi = nullptr;  // [n_g1*n_g1][4]: sin(th) cos(ps), sin(th) sin(ps), cos(th), W at a = 1
-    double *d_ring = nullptr;  // [n_g2*n_g2][4]: rho / a, cos(ps), sin(ps), ring weight at a = 1
     int device = 0;
 };
 
@@ -124,7 +122,19 @@ hipError_t upload_vec(const std::vector<T> &v, T **out)
 
 bool unit3(const double *v) { return std::fabs(std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) - 1.0) < 1e-12; }
 
-// Is the point on a flat part of the boundary with its hemisphere in Omega?
+__global__ __launch_bounds__(256) void k_point_answer(const dtn_point *__restrict__ pts, int64_t n, int nn,
+                                                      const int64_t *__restrict__ used, double *__restrict__ out)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int64_t w = 0;
+    for (int k = 0; k < nn; ++k) w += used[p * nn + k];
+    out[4 * p + 2] = (double)w;
+    out[4 * p + 3] = pts[p].a;
+}
+
+}  // namespace
+
 bool point_ok(const Geometry &g, const dtn_point &q, std::string &why)
 {
     if (!(q.a > 0.0) || !std::isfinite(q.a)) {
@@ -186,7 +196,103 @@ bool point_ok(const Geometry &g, const dtn_point &q, std::string &why)
     return false;
 }
 
-}  // namespace
+dtn_status make_point_rule(int n_g1, int n_g2, double delta_rel, PointRule &r)
+{
+    r = PointRule{};
+    r.n_g1 = n_g1;
+    r.n_g2 = n_g2;
+    r.delta_rel = delta_rel;
+    // hemisphere rule at a = 1 (eqs. bw83, bw85): theta = pi/4 (xi + 1),
+    // psi = pi (xi + 1); W a = (pi/4 w_i)(pi w_j) sin(th) 3 cos(th) / (2 pi)
+    std::vector<double> xi, w;
+    gauss_legendre_rule(n_g1, xi, w);
+    std::vector<double> hemi(4 * (size_t)n_g1 * n_g1);
+    for (int i = 0; i < n_g1; ++i) {
+        const double th = 0.25 * kPi * (xi[i] + 1.0), wt = 0.25 * kPi * w[i];
+        for (int j = 0; j < n_g1; ++j) {
+            const double ps = kPi * (xi[j] + 1.0), wp = kPi * w[j];
+            double *h = &hemi[4 * ((size_t)i * n_g1 + j)];
+            h[0] = std::sin(th) * std::cos(ps);
+            h[1] = std::sin(th) * std::sin(ps);
+            h[2] = std::cos(th);
+            h[3] = wt * wp * std::sin(th) * 3.0 * std::cos(th) / (2.0 * kPi);
+        }
+    }
+    // ring rule at a = 1 (eqs. bw68, bw82): rho / a = r on [delta_rel, 1],
+    // psi on [0, 2 pi]; with rho = a r the term
+    // -1/(2 pi) w_rho w_psi rho (1/rho^3 - 1/a^3) equals (1/a) times
+    // -1/(2 pi) ((1 - delta_rel)/2 w_k)(pi w_l) r (1/r^3 - 1)
+    gauss_legendre_rule(n_g2, xi, w);
+    std::vector<double> ring(4 * (size_t)n_g2 * n_g2);
+    for (int k = 0; k < n_g2; ++k) {
+        const double rr = 0.5 * (1.0 - delta_rel) * xi[k] + 0.5 * (1.0 + delta_rel);
+        const double wr = 0.5 * (1.0 - delta_rel) * w[k];
+        for (int l = 0; l < n_g2; ++l) {
+            const double ps = kPi * (xi[l] + 1.0), wp = kPi * w[l];
+            double *h = &ring[4 * ((size_t)k * n_g2 + l)];
+            h[0] = rr;
+            h[1] = std::cos(ps);
+            h[2] = std::sin(ps);
+            h[3] = -wr * wp * rr * (1.0 / (rr * rr * rr) - 1.0) / (2.0 * kPi);
+        }
+    }
+    hipError_t e = upload_vec(hemi, &r.d_hemi);
+    if (e == hipSuccess) e = upload_vec(ring, &r.d_ring);
+    if (e != hipSuccess) {
+        free_point_rule(r);
+        return fail(DTN_E_DEVICE, std::string("point rule: ") + hipGetErrorString(e));
+    }
+    return DTN_OK;
+}
+
+void free_point_rule(PointRule &r)
+{
+    (void)hipFree(r.d_hemi);
+    (void)hipFree(r.d_ring);
+    r.d_hemi = r.d_ring = nullptr;
+}
+
+dtn_status launch_point_nodes(const dtn_point *pts, int64_t n, const PointRule &r, double *nodes, hipStream_t s)
+{
+    const int nn = r.n_g1 * r.n_g1;
+    const int64_t total = n * nn;
+    if (total == 0) return DTN_OK;
+    hipLaunchKernelGGL(k_point_nodes, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, pts, n, nn, r.d_hemi,
+                       nodes);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("point nodes: ") + hipGetErrorString(e));
+    return DTN_OK;
+}
+
+dtn_status launch_point_neumann(const Geometry &g, const dtn_point *pts, int64_t n, const PointRule &r,
+                                const double *stats, double *out, hipStream_t s)
+{
+    if (n == 0) return DTN_OK;
+    const dim3 grid((unsigned)((n + kPointsPerBlock - 1) / kPointsPerBlock)), block(kPointsPerBlock * kWave);
+    const int nn = r.n_g1 * r.n_g1, nr = r.n_g2 * r.n_g2;
+    if (g.dev.data_kind == DTN_DATA_TABULATED)
+        hipLaunchKernelGGL(k_point_neumann<DTN_DATA_TABULATED>, grid, block, 0, s, g.dev, pts, n, nn, r.d_hemi, nr,
+                           r.d_ring, stats, out);
+    else if (g.dev.data_kind == DTN_DATA_POINT_SOURCES)
+        hipLaunchKernelGGL(k_point_neumann<DTN_DATA_POINT_SOURCES>, grid, block, 0, s, g.dev, pts, n, nn, r.d_hemi,
+                           nr, r.d_ring, stats, out);
+    else
+        hipLaunchKernelGGL(k_point_neumann<DTN_DATA_HARMONIC_QUADRATIC>, grid, block, 0, s, g.dev, pts, n, nn,
+                           r.d_hemi, nr, r.d_ring, stats, out);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("point neumann: ") + hipGetErrorString(e));
+    return DTN_OK;
+}
+
+dtn_status launch_point_answer(const dtn_point *pts, int64_t n, int nn, const int64_t *used, double *out,
+                               hipStream_t s)
+{
+    if (n == 0) return DTN_OK;
+    hipLaunchKernelGGL(k_point_answer, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pts, n, nn, used, out);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("point answer: ") + hipGetErrorString(e));
+    return DTN_OK;
+}
 
 }  // namespace dtn
 
@@ -216,51 +322,13 @@ dtn_status dtn_create_points(dtn_geometry g, const dtn_point *pts, int64_t n, in
         Points &p = P->p;
         p.geom = &g->g;
         p.pts.assign(pts, pts + n);
-        p.n_g1 = n_g1;
-        p.n_g2 = n_g2;
-        p.delta_rel = delta_rel;
-        // hemisphere rule at a = 1 (eqs. bw83, bw85): theta = pi/4 (xi + 1),
-        // psi = pi (xi + 1); W a = (pi/4 w_i)(pi w_j) sin(th) 3 cos(th) / (2 pi)
-        std::vector<double> xi, w;
-        gauss_legendre_rule(n_g1, xi, w);
-        std::vector<double> hemi(4 * (size_t)n_g1 * n_g1);
-        for (int i = 0; i < n_g1; ++i) {
-            const double th = 0.25 * kPi * (xi[i] + 1.0), wt = 0.25 * kPi * w[i];
-            for (int j = 0; j < n_g1; ++j) {
-                const double ps = kPi * (xi[j] + 1.0), wp = kPi * w[j];
-                double *h = &hemi[4 * ((size_t)i * n_g1 + j)];
-                h[0] = std::sin(th) * std::cos(ps);
-                h[1] = std::sin(th) * std::sin(ps);
-                h[2] = std::cos(th);
-                h[3] = wt * wp * std::sin(th) * 3.0 * std::cos(th) / (2.0 * kPi);
-            }
-        }
-        // ring rule at a = 1 (eqs. bw68, bw82): rho / a = r on [delta_rel, 1],
-        // psi on [0, 2 pi]; with rho = a r the term
-        // -1/(2 pi) w_rho w_psi rho (1/rho^3 - 1/a^3) equals (1/a) times
-        // -1/(2 pi) ((1 - delta_rel)/2 w_k)(pi w_l) r (1/r^3 - 1)
-        gauss_legendre_rule(n_g2, xi, w);
-        std::vector<double> ring(4 * (size_t)n_g2 * n_g2);
-        for (int k = 0; k < n_g2; ++k) {
-            const double r = 0.5 * (1.0 - delta_rel) * xi[k] + 0.5 * (1.0 + delta_rel);
-            const double wr = 0.5 * (1.0 - delta_rel) * w[k];
-            for (int l = 0; l < n_g2; ++l) {
-                const double ps = kPi * (xi[l] + 1.0), wp = kPi * w[l];
-                double *h = &ring[4 * ((size_t)k * n_g2 + l)];
-                h[0] = r;
-                h[1] = std::cos(ps);
-                h[2] = std::sin(ps);
-                h[3] = -wr * wp * r * (1.0 / (r * r * r) - 1.0) / (2.0 * kPi);
-            }
-        }
+        dtn_status st = make_point_rule(n_g1, n_g2, delta_rel, p.rule);
+        if (st != DTN_OK) return st;
         hipError_t e = hipGetDevice(&p.device);
         if (e == hipSuccess) e = upload_vec(p.pts, &p.d_pts);
-        if (e == hipSuccess) e = upload_vec(hemi, &p.d_hemi);
-        if (e == hipSuccess) e = upload_vec(ring, &p.d_ring);
         if (e != hipSuccess) {
             (void)hipFree(p.d_pts);
-            (void)hipFree(p.d_hemi);
-            (void)hipFree(p.d_ring);
+            free_point_rule(p.rule);
             return fail(DTN_E_DEVICE, at + hipGetErrorString(e));
         }
         *out = P.release();
@@ -274,15 +342,14 @@ void dtn_destroy_points(dtn_points p)
 {
     if (!p) return;
     (void)hipFree(p->p.d_pts);
-    (void)hipFree(p->p.d_hemi);
-    (void)hipFree(p->p.d_ring);
+    free_point_rule(p->p.rule);
     delete p;
 }
 
 int64_t dtn_points_num_nodes(dtn_points p)
 {
     if (!p) return -1;
-    return (int64_t)p->p.pts.size() * p->p.n_g1 * p->p.n_g1;
+    return (int64_t)p->p.pts.size() * p->p.rule.n_g1 * p->p.rule.n_g1;
 }
 
 dtn_status dtn_points_nodes(dtn_points p, double *nodes, void *stream)
@@ -290,14 +357,7 @@ dtn_status dtn_points_nodes(dtn_points p, double *nodes, void *stream)
     try {
         if (!p || !nodes) return fail(DTN_E_ARG, "dtn_points_nodes: NULL argument");
         const Points &P = p->p;
-        const int64_t n = (int64_t)P.pts.size();
-        const int nn = P.n_g1 * P.n_g1;
-        const int64_t total = n * nn;
-        hipLaunchKernelGGL(k_point_nodes, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
-                           P.d_pts, n, nn, P.d_hemi, nodes);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_points_nodes: ") + hipGetErrorString(e));
-        return DTN_OK;
+        return launch_point_nodes(P.d_pts, (int64_t)P.pts.size(), P.rule, nodes, (hipStream_t)stream);
     } catch (...) {
         return fail(DTN_E_DEVICE, "dtn_points_nodes: exception");
     }
@@ -308,22 +368,8 @@ dtn_status dtn_points_neumann(dtn_points p, const double *node_stats, double *ou
     try {
         if (!p || !node_stats || !out) return fail(DTN_E_ARG, "dtn_points_neumann: NULL argument");
         const Points &P = p->p;
-        const int64_t n = (int64_t)P.pts.size();
-        const dim3 grid((unsigned)((n + kPointsPerBlock - 1) / kPointsPerBlock)), block(kPointsPerBlock * kWave);
-        const hipStream_t s = (hipStream_t)stream;
-        const int nn = P.n_g1 * P.n_g1, nr = P.n_g2 * P.n_g2;
-        if (P.geom->dev.data_kind == DTN_DATA_TABULATED)
-            hipLaunchKernelGGL(k_point_neumann<DTN_DATA_TABULATED>, grid, block, 0, s, P.geom->dev, P.d_pts, n,
-                               nn, P.d_hemi, nr, P.d_ring, node_stats, out);
-        else if (P.geom->dev.data_kind == DTN_DATA_POINT_SOURCES)
-            hipLaunchKernelGGL(k_point_neumann<DTN_DATA_POINT_SOURCES>, grid, block, 0, s, P.geom->dev, P.d_pts, n,
-                               nn, P.d_hemi, nr, P.d_ring, node_stats, out);
-        else
-            hipLaunchKernelGGL(k_point_neumann<DTN_DATA_HARMONIC_QUADRATIC>, grid, block, 0, s, P.geom->dev, P.d_pts,
-                               n, nn, P.d_hemi, nr, P.d_ring, node_stats, out);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_points_neumann: ") + hipGetErrorString(e));
-        return DTN_OK;
+        return launch_point_neumann(*P.geom, P.d_pts, (int64_t)P.pts.size(), P.rule, node_stats, out,
+                                    (hipStream_t)stream);
     } catch (...) {
         return fail(DTN_E_DEVICE, "dtn_points_neumann: exception");
     }

@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "dtn_internal.h"
+#include "dtn_point_rule.h"
 
 namespace dtn {
 namespace {
@@ -128,7 +129,9 @@ int64_t padded_rows(const dtn_server_config &c, int64_t n)
 int64_t footprint(const dtn_server_config &c, int64_t n_points)
 {
     const int64_t n = padded_rows(c, n_points);
-    const int64_t nn = (int64_t)c.n_theta * c.n_phi, np = (int64_t)c.n_rings * c.n_sectors;
+    const bool points = c.n_g1 > 0;
+    const int64_t nn = points ? (int64_t)c.n_g1 * c.n_g1 : (int64_t)c.n_theta * c.n_phi;
+    const int64_t np = points ? 0 : (int64_t)c.n_rings * c.n_sectors;
     const int64_t nodes = n * nn;
     const int64_t adaptive = nodes * (4 * 8 + 5 * 8);
     const int64_t walk = 8 * (nodes + 1) + 80 + 48 * (nodes + 256 * 32 * (int64_t)kBatchSchedule.oversub + 1);
@@ -160,6 +163,9 @@ bool valid_config(const dtn_server_config &c, std::string &why)
     else if (c.max_points < 1 || c.max_points > ((int64_t)1 << 20)) why = "max_points outside [1, 2^20]";
     else if (c.graph_replay != 0 && c.graph_replay != 1) why = "graph_replay must be 0 or 1";
     else if (c.max_batch_queries < 0) why = "max_batch_queries must be >= 0";
+    else if (c.n_g1 != 0 && (c.n_g1 < 1 || c.n_g1 > 64 || c.n_g2 < 1 || c.n_g2 > 64 ||
+                             !(c.delta_rel > 0.0 && c.delta_rel < 1.0)))
+        why = "point mode needs n_g1, n_g2 in [1, 64] and delta_rel in (0, 1)";
     else return true;
     return false;
 }
@@ -177,7 +183,9 @@ struct dtn_server_s {
     int32_t *d_zero = nullptr;       // class index of every patch, [max_points]
     int64_t *d_node_off = nullptr;   // i * nodes per patch, [max_points + 1]
     int64_t *d_panel_off = nullptr;  // i * panels per patch, [max_points + 1]
-    int64_t nn = 0, np = 0;
+    int64_t nn = 0, np = 0;  // nodes and panels per point
+    bool points = false;     // point mode: the single-point estimate, no solve
+    PointRule rule;          // point mode's quadrature tables
     std::vector<Slot> slots;
     std::mutex mu;
     std::condition_variable cv;
@@ -269,11 +277,12 @@ dtn_status record_pass(dtn_server_s *S, Slot &sl, int64_t rows, hipStream_t s)
         const hipError_t ec = hipMemcpyAsync(dst, src, bytes, kind, s);
         if (ec != hipSuccess) st = fail(DTN_E_DEVICE, std::string("server: ") + hipGetErrorString(ec));
     };
-    copy(P.d_patches, sl.h_patches, sizeof(dtn_patch) * n, hipMemcpyHostToDevice);
+    copy(P.d_patches, sl.h_patches, (S->points ? sizeof(dtn_point) : sizeof(dtn_patch)) * n, hipMemcpyHostToDevice);
     copy(pseed, sl.h_seed, sizeof(uint64_t) * n, hipMemcpyHostToDevice);
     copy(psid0, sl.h_sid0, sizeof(uint32_t) * n, hipMemcpyHostToDevice);
     copy(pse2, sl.h_se2, sizeof(double) * n, hipMemcpyHostToDevice);
-    if (st == DTN_OK) st = launch_nodes(P, nodes, s);
+    const dtn_point *d_pts = (const dtn_point *)P.d_patches;
+    if (st == DTN_OK) st = S->points ? launch_point_nodes(d_pts, n, S->rule, nodes, s) : launch_nodes(P, nodes, s);
     if (st == DTN_OK) st = launch_node_ids(n, (int)S->nn, pseed, psid0, pse2, nseed, nsid, nse2, s);
     if (st == DTN_OK) {
         Adaptive a{S->cfg.pilot_walks, S->cfg.min_walks, S->cfg.max_walks, 1.0};
@@ -281,8 +290,13 @@ dtn_status record_pass(dtn_server_s *S, Slot &sl, int64_t rows, hipStream_t s)
         st = launch_wos_adaptive(*S->g, nodes, n * S->nn, a, 0, nseed, nsid, S->cfg.precision, stats, used, capped,
                                  kBatchSchedule, s);
     }
-    if (st == DTN_OK) st = launch_solve(P, stats, S->cfg.precision, neu, nse, s);
-    if (st == DTN_OK) st = launch_answer(P, neu, stats, used, ans, s);
+    if (S->points) {
+        if (st == DTN_OK) st = launch_point_neumann(*S->g, d_pts, n, S->rule, stats, ans, s);
+        if (st == DTN_OK) st = launch_point_answer(d_pts, n, (int)S->nn, used, ans, s);
+    } else {
+        if (st == DTN_OK) st = launch_solve(P, stats, S->cfg.precision, neu, nse, s);
+        if (st == DTN_OK) st = launch_answer(P, neu, stats, used, ans, s);
+    }
     copy(sl.h_ans, ans, sizeof(double) * 4 * n, hipMemcpyDeviceToHost);
     const hipError_t ef = hipFreeAsync(buf, s);
     if (st == DTN_OK && ef != hipSuccess) st = fail(DTN_E_DEVICE, std::string("server: ") + hipGetErrorString(ef));
@@ -325,7 +339,22 @@ dtn_status enqueue(dtn_server_s *S, Batch *b)
         int64_t at = 0;
         for (const Query *q : b->qs) {
             const int64_t m = (int64_t)q->patches.size();
-            std::memcpy(sl.h_patches + at, q->patches.data(), sizeof(dtn_patch) * m);
+            if (S->points) {
+                // the staging holds dtn_point records (80 B < sizeof(dtn_patch))
+                dtn_point *hp = (dtn_point *)sl.h_patches;
+                for (int64_t i = 0; i < m; ++i) {
+                    const dtn_patch &pq = q->patches[i];
+                    dtn_point &o = hp[at + i];
+                    for (int k = 0; k < 3; ++k) {
+                        o.c[k] = pq.c[k];
+                        o.n[k] = pq.n[k];
+                        o.t1[k] = pq.t1[k];
+                    }
+                    o.a = pq.h;
+                }
+            } else {
+                std::memcpy(sl.h_patches + at, q->patches.data(), sizeof(dtn_patch) * m);
+            }
             for (int64_t i = 0; i < m; ++i) {
                 sl.h_seed[at + i] = q->seed;
                 sl.h_sid0[at + i] = (uint32_t)(i * S->nn);
@@ -510,8 +539,9 @@ dtn_status dtn_server_create(dtn_geometry g, const dtn_server_config *cfg, dtn_s
         std::unique_ptr<dtn_server_s> S(new dtn_server_s());
         S->g = G;
         S->cfg = *cfg;
-        S->nn = (int64_t)cfg->n_theta * cfg->n_phi;
-        S->np = (int64_t)cfg->n_rings * cfg->n_sectors;
+        S->points = cfg->n_g1 > 0;
+        S->nn = S->points ? (int64_t)cfg->n_g1 * cfg->n_g1 : (int64_t)cfg->n_theta * cfg->n_phi;
+        S->np = S->points ? 0 : (int64_t)cfg->n_rings * cfg->n_sectors;
         hipError_t e = hipGetDevice(&S->device);
         if (e != hipSuccess) return fail(DTN_E_DEVICE, at + hipGetErrorString(e));
         DevClass cls{};
@@ -524,6 +554,7 @@ dtn_status dtn_server_create(dtn_geometry g, const dtn_server_config *cfg, dtn_s
             poff[i] = i * S->np;
         }
         auto cleanup = [&]() {
+            free_point_rule(S->rule);
             (void)hipFree(S->d_class);
             (void)hipFree(S->d_zero);
             (void)hipFree(S->d_node_off);
@@ -561,6 +592,13 @@ dtn_status dtn_server_create(dtn_geometry g, const dtn_server_config *cfg, dtn_s
             cleanup();
             return fail(DTN_E_OOM, at + hipGetErrorString(e));
         }
+        if (S->points) {
+            st = make_point_rule(cfg->n_g1, cfg->n_g2, cfg->delta_rel, S->rule);
+            if (st != DTN_OK) {
+                cleanup();
+                return st;
+            }
+        }
         S->t0 = Clock::now();
         dtn_server_s *raw = S.get();
         S->dispatcher = std::thread(dispatch_loop, raw);
@@ -597,6 +635,7 @@ void dtn_server_destroy(dtn_server s)
         (void)hipHostFree(sl.h_se2);
         (void)hipHostFree(sl.h_ans);
     }
+    free_point_rule(s->rule);
     (void)hipFree(s->d_class);
     (void)hipFree(s->d_zero);
     (void)hipFree(s->d_node_off);

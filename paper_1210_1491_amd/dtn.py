@@ -63,7 +63,8 @@ class ServerConfigDesc(C.Structure):
                 ("pilot_walks", C.c_int64), ("min_walks", C.c_int64), ("max_walks", C.c_int64),
                 ("h_max", C.c_double), ("ladder", C.c_int32), ("n_theta", C.c_int32), ("n_phi", C.c_int32),
                 ("n_rings", C.c_int32), ("n_sectors", C.c_int32), ("max_points", C.c_int64),
-                ("graph_replay", C.c_int32), ("max_batch_queries", C.c_int32)]
+                ("graph_replay", C.c_int32), ("max_batch_queries", C.c_int32), ("n_g1", C.c_int32),
+                ("n_g2", C.c_int32), ("delta_rel", C.c_double)]
 
 
 class QueryDoneDesc(C.Structure):
@@ -501,11 +502,16 @@ class Server:
 
     def __init__(self, geom, n_streams=4, precision="fp64", hbm_budget=2 << 30, pilot_walks=100, min_walks=100,
                  max_walks=1_000_000, h_max=0.25, ladder=16, layout=(8, 16, 4, 8), max_points=4096, graphs=False,
-                 max_batch_queries=0):
+                 max_batch_queries=0, point_rule=None):
+        """point_rule = (n_g1, n_g2, delta_rel) switches to point mode: the
+        single-point estimate (Sec. 5.1) on the hemisphere of radius a = h,
+        answers (Sigma1' + Sigma2', SE, walks, a), no collocation solve."""
         self.geom = geom
+        g1, g2, dr = (0, 0, 0.0) if point_rule is None else point_rule
         self.cfg = ServerConfigDesc(int(n_streams), PRECISION[precision], int(hbm_budget), int(pilot_walks),
                                     int(min_walks), int(max_walks), float(h_max), int(ladder), *map(int, layout),
-                                    int(max_points), 1 if graphs else 0, int(max_batch_queries))
+                                    int(max_points), 1 if graphs else 0, int(max_batch_queries), int(g1), int(g2),
+                                    float(dr))
         self.handle = C.c_void_p()
         _check(lib().dtn_server_create(geom.handle, C.byref(self.cfg), C.byref(self.handle)), "dtn_server_create")
         self._out = {}

@@ -80,6 +80,24 @@ def test_server_footprint_is_host_side_and_checked():
         assert L.dtn_server_footprint(ctypes.byref(bad), 10) == -1
 
 
+def test_server_footprint_in_point_mode():
+    """Point mode: n_g1^2 nodes per point and no panels; invalid rules give -1."""
+    from paper_1210_1491_amd import dtn
+    L = dtn.lib()
+    base = (4, 1, 2 << 30, 100, 100, 1_000_000, 0.25, 16, 8, 16, 4, 8, 4096, 0, 0)
+    pm = dtn.ServerConfigDesc(*base, 20, 20, 1e-6)
+    f = [L.dtn_server_footprint(ctypes.byref(pm), n) for n in (1, 2, 100)]
+    per_point = f[2] - f[1]
+    assert per_point > 0 and abs((f[2] - f[1]) - 98 * (f[1] - f[0])) <= 98 * 256 * 16
+    assert per_point >= 400 * (24 + 32 + 16 + 20)
+    patch = L.dtn_server_footprint(ctypes.byref(dtn.ServerConfigDesc(*base)), 100)
+    assert patch != f[2]
+    for bad in ((20, 0, 1e-6), (65, 20, 1e-6), (20, 20, 0.0), (20, 20, 1.0), (-1, 20, 1e-6)):
+        assert L.dtn_server_footprint(ctypes.byref(dtn.ServerConfigDesc(*base, *bad)), 10) == -1, bad
+    # n_g1 = 0 is patch mode: the other point fields are not read
+    assert L.dtn_server_footprint(ctypes.byref(dtn.ServerConfigDesc(*base, 0, 0, 0.0)), 100) == patch
+
+
 def _bucket(n, max_points):
     """Size buckets of graph replay, stated independently: n itself up to 8,
     then the smallest m 2^e >= n with m in 5..8, capped at max_points."""

@@ -11,6 +11,7 @@ import pytest
 
 import dtn_inputs as I
 from oracle import patch as OP
+from oracle import point as OPt
 from oracle import wos as OW
 
 pytestmark = pytest.mark.gpu
@@ -96,6 +97,44 @@ def test_server_answers_match_oracle_fp64():
         value, se = OP.central_disk_answer(p, g, r["mean"][s], se_nodes)
         assert abs(out[i, 2] - r["walks_used"][s].sum()) <= 0.001 * out[i, 2]
         assert abs(out[i, 0] - value) < 0.01 * se, (i, out[i], value, se)
+        assert out[i, 1] == pytest.approx(se, rel=1e-3)
+
+
+def test_point_mode_answers_match_oracle_fp64():
+    """Point mode (Sec. 5.1, no solve): every answer against the oracle's
+    single-point estimate on its own hemisphere nodes (a = the ladder's h),
+    walked with the same seed, stream ids and adaptive budgets."""
+    dtn = _dtn()
+    gd = I.geometry_box_holes()
+    rng = np.random.default_rng(31)
+    pts, nrm = I.boundary_points(gd, 6, rng)
+    budget = (64, 64, 4000, 0.05)
+    rule = (8, 12, 1e-6)
+    S = dtn.Server(dtn.Geometry(gd), n_streams=2, precision="fp64", pilot_walks=budget[0], min_walks=budget[1],
+                   max_walks=budget[2], layout=LAYOUT, point_rule=rule)
+    print(f"[gpu] server point mode n={len(pts)}", flush=True)
+    out = _run(S, {9: (pts, nrm, budget[3], 99)})[9]["answer"]
+    S.close()
+    g = OW.Geometry(gd)
+    frames, nodes = [], []
+    for i in range(len(pts)):
+        h = _ladder_h(gd, pts[i], nrm[i])
+        assert out[i, 3] == h
+        k = int(np.argmax(np.abs(nrm[i])))
+        t1 = np.zeros(3)
+        t1[(k + 1) % 3] = 1.0
+        frames.append((pts[i], nrm[i], t1, h))
+        nodes.append(OPt.hemisphere_rule(pts[i], nrm[i], t1, h, rule[0])[0])
+    r = OW.wos_adaptive(g, np.concatenate(nodes), *budget[:3], budget[3], seed=99,
+                        stream_id=np.arange(len(pts) * rule[0] ** 2))
+    nn = rule[0] ** 2
+    for i, (x, n, t1, a) in enumerate(frames):
+        s = slice(i * nn, (i + 1) * nn)
+        st = np.stack([r["count"][s], r["mean"][s], r["m2"][s], r["steps"][s]], axis=-1)
+        value, se, _, _ = OPt.point_neumann(g.phi, x, n, t1, a, rule[0], rule[1], rule[2], st)
+        bound = OPt.sigma2_rounding_bound(g.phi, x, n, t1, a, rule[1], rule[2])
+        assert out[i, 2] == r["walks_used"][s].sum()
+        assert abs(out[i, 0] - value) < 0.01 * se + bound, (i, out[i], value, se)
         assert out[i, 1] == pytest.approx(se, rel=1e-3)
 
 
