@@ -852,6 +852,11 @@ def halfspace_cpu_baseline(gd, x, nrm, t1, a, cfg, gpu_out, n_sample):
                                                              / np.abs(want[:, 0])))}}
 
 
+# Point-mode rule of the serving workload: 8 x 8 hemisphere nodes (half the
+# patch layout's 8 x 16), the 20 x 20 ring rule and delta / a of Table 1.
+POINT_RULE = (8, 20, 1e-6)
+
+
 def serving(precision, window, rate, se_range, sweep_fraction=0.5, sweep_window=6):
     """Query serving on the box-with-holes geometry: Poisson arrivals, each
     query 1..4096 boundary points (log-uniform) with a required standard
@@ -859,7 +864,8 @@ def serving(precision, window, rate, se_range, sweep_fraction=0.5, sweep_window=
     walks.  The served path: FP32-mixed walks, continuous batching across
     requests over 4 streams under a 2 GB budget.  The plain path: FP64, one
     query at a time (one stream, one query per batch), on the same arrival
-    trace.  Latency =
+    trace.  The point mode: the served path answering each point by the
+    single-point estimate (no patch solve), same trace.  Latency =
     completion - arrival; patches/s = points answered / makespan.  Shorter
     runs offer a half and a quarter of the served path's measured capacity."""
     import dtn_inputs as I
@@ -869,9 +875,11 @@ def serving(precision, window, rate, se_range, sweep_fraction=0.5, sweep_window=
     gd = cfg["geometry"]()
     g = dtn.Geometry(gd)
 
-    def run(rate_qps, n, prec=precision, plain=False):
+    def run(rate_qps, n, prec=precision, plain=False, point=False):
         qs = I.serving_queries(gd, n_queries=n, rate=rate_qps, seed=cfg["seed"], se_range=tuple(se_range))
         mode = dict(n_streams=1, max_batch_queries=1) if plain else dict(n_streams=4)
+        if point:
+            mode["point_rule"] = POINT_RULE
         S = dtn.Server(g, precision=prec, hbm_budget=cfg["hbm_budget"], pilot_walks=cfg["pilot_walks"],
                        min_walks=cfg["min_walks"], max_walks=cfg["max_walks"], h_max=cfg["h_max"],
                        ladder=cfg["ladder"], layout=cfg["layout"], **mode)
@@ -895,13 +903,15 @@ def serving(precision, window, rate, se_range, sweep_fraction=0.5, sweep_window=
                "p99_ms": float(np.percentile(lat, 99) * 1e3), "walks": walks, "makespan_s": busy,
                "served_qps": n / busy, "patches_per_s": points / busy, "walks_per_s": walks / busy,
                "median_answer_se_over_target": float(np.median(ratio))}
-        print(f"[bench] serving {'plain fp64' if plain else prec} at {rate_qps:.3g} q/s, {n} queries: "
+        print(f"[bench] serving {'plain fp64' if plain else prec}{' point mode' if point else ''} at "
+              f"{rate_qps:.3g} q/s, {n} queries: "
               f"{out['patches_per_s']:.0f} patches/s, p50 {out['p50_ms']:.0f} ms p99 {out['p99_ms']:.0f} ms",
               file=sys.stderr, flush=True)
         return out
 
     main = run(rate, window)
     plain = run(rate, window, prec="fp64", plain=True)
+    point = run(rate, window, point=True)
     stable = run(sweep_fraction * main["served_qps"], sweep_window) if sweep_window > 0 else None
     low = run(0.5 * sweep_fraction * main["served_qps"], max(sweep_window // 2, 1)) if sweep_window > 0 else None
     return {"workload": f"box_holes geometry resident; Poisson arrivals at {rate:g} q/s; 1..4096 points per query "
@@ -910,6 +920,10 @@ def serving(precision, window, rate, se_range, sweep_fraction=0.5, sweep_window=
                         f"[{se_range[0]:g}, {se_range[1]:g}]; 2 GB budget",
             "precision": precision, "served": main, "plain_fp64_per_query": plain,
             "patches_per_s_vs_plain_fp64": main["patches_per_s"] / plain["patches_per_s"],
+            "point_mode": dict(point, rule={"n_g1": POINT_RULE[0], "n_g2": POINT_RULE[1],
+                                            "delta_rel": POINT_RULE[2]},
+                               answer="du/dn at the point by Sigma1' + Sigma2' (Sec. 5.1), no solve; a = h"),
+            "points_per_s_point_mode_vs_served": point["patches_per_s"] / main["patches_per_s"],
             "stable": stable, "low": low}
 
 
