@@ -138,6 +138,30 @@ def test_point_mode_answers_match_oracle_fp64():
         assert out[i, 1] == pytest.approx(se, rel=1e-3)
 
 
+def test_point_mode_fp32_mixed_agrees_with_fp64():
+    """The serving benchmark's precision: FP32-mixed walks in point mode give
+    answers within 4 sqrt(SE_32^2 + SE_64^2) of the FP64 ones (same seeds and
+    stream ids: the paths differ only where FP32 rounding moves a walk), with
+    the same a and a comparable walk count."""
+    dtn = _dtn()
+    gd = I.geometry_box_holes()
+    rng = np.random.default_rng(32)
+    pts, nrm = I.boundary_points(gd, 40, rng)
+    g = dtn.Geometry(gd)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        S = dtn.Server(g, n_streams=2, precision=prec, pilot_walks=64, min_walks=64, max_walks=20000,
+                       layout=LAYOUT, point_rule=(8, 20, 1e-6))
+        print(f"[gpu] server point mode {prec}", flush=True)
+        res[prec] = _run(S, {5: (pts, nrm, 0.02, 55)})[5]["answer"]
+        S.close()
+    a, b = res["fp64"], res["fp32"]
+    np.testing.assert_array_equal(a[:, 3], b[:, 3])
+    z = np.abs(a[:, 0] - b[:, 0]) / np.sqrt(a[:, 1] ** 2 + b[:, 1] ** 2)
+    assert np.all(z < 4.0), z.max()
+    assert np.all(np.abs(b[:, 2] / a[:, 2] - 1.0) < 0.5)
+
+
 def test_answer_does_not_depend_on_the_batch():
     dtn = _dtn()
     gd = I.geometry_box_holes()
