@@ -761,6 +761,23 @@ def treecode_potential(m_tiles=96, n_targets=1_000_000, degree=6, theta=0.5, lea
     ev[1].record()
     torch.cuda.synchronize()
     ms_direct = ev[0].elapsed_time(ev[1])
+    # speed against accuracy: other degrees and acceptance parameters, the
+    # same targets, error against the direct sum
+    u_dev = u_d
+    sweep = []
+    for deg, th in ((2, 0.7), (4, 0.7), (4, 0.5), (6, 0.7), (8, 0.5)):
+        tr = dtn.Tree(plan, deg, leaf)
+        u_s = tr.potential(neu, tg, th)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            tr.potential(neu, tg, th, out=u_s)
+        ev[1].record()
+        torch.cuda.synchronize()
+        err = float(torch.max(torch.abs(u_s - u_dev)) / torch.max(torch.abs(u_dev)))
+        sweep.append({"degree": deg, "theta": th, "ms": ev[0].elapsed_time(ev[1]) / reps,
+                      "max_rel_diff_vs_direct": err})
+        del tr
     u_t, u_d, cnt = u_t.cpu().numpy(), u_d.cpu().numpy(), counts.cpu().numpy()
     far = np.min(np.minimum(tg_np, 1.0 - tg_np), axis=1) >= 2.0 / m_tiles
     ex = exact_u(gd, tg_np[far])
@@ -778,6 +795,7 @@ def treecode_potential(m_tiles=96, n_targets=1_000_000, degree=6, theta=0.5, lea
         "max_err_vs_exact_treecode": float(np.max(np.abs(u_t[far] - ex))),
         "max_err_vs_exact_direct": float(np.max(np.abs(u_d[far] - ex))),
         "targets_vs_exact": int(far.sum()),
+        "sweep": sweep,
     }
     print(f"[bench] treecode potential: {ms_tree:.1f} ms vs direct {ms_direct:.1f} ms "
           f"({out['speedup']:.1f}x), {inter:.0f} interactions per target", file=sys.stderr, flush=True)
