@@ -72,6 +72,7 @@ struct Slot {
     double *h_se2 = nullptr;         // [max_points] squared SE target per patch
     double *h_ans = nullptr;         // [max_points][4]
     std::map<int64_t, hipGraphExec_t> graphs;  // captured device pass per size bucket
+    hipStream_t capture = nullptr;  // graph replay: records the passes, never runs work
     bool busy = false;
 };
 
@@ -303,7 +304,10 @@ dtn_status record_pass(dtn_server_s *S, Slot &sl, int64_t rows, hipStream_t s)
     return st;
 }
 
-// The slot's graph for `rows`, captured on first use.
+// The slot's graph for `rows`, captured on first use.  The capture records
+// on the slot's own capture stream, which never runs work: the stream that
+// replays the graph may still be finishing the previous batch's host
+// function when the dispatcher gets here.
 dtn_status slot_graph(dtn_server_s *S, Slot &sl, int64_t rows, hipGraphExec_t *out)
 {
     auto it = sl.graphs.find(rows);
@@ -311,11 +315,11 @@ dtn_status slot_graph(dtn_server_s *S, Slot &sl, int64_t rows, hipGraphExec_t *o
         *out = it->second;
         return DTN_OK;
     }
-    hipError_t e = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal);
+    hipError_t e = hipStreamBeginCapture(sl.capture, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("server capture: ") + hipGetErrorString(e));
-    const dtn_status st = record_pass(S, sl, rows, sl.stream);
+    const dtn_status st = record_pass(S, sl, rows, sl.capture);
     hipGraph_t graph = nullptr;
-    e = hipStreamEndCapture(sl.stream, &graph);  // ends the capture on every path
+    e = hipStreamEndCapture(sl.capture, &graph);  // ends the capture on every path
     if (st != DTN_OK) {
         if (graph) (void)hipGraphDestroy(graph);
         return st;
@@ -365,7 +369,12 @@ dtn_status enqueue(dtn_server_s *S, Batch *b)
         // padding rows: a valid patch with an infinite SE target (budget =
         // the pilot walks); their answers are never read
         for (; at < rows; ++at) {
-            sl.h_patches[at] = sl.h_patches[0];
+            if (S->points) {
+                dtn_point *hp = (dtn_point *)sl.h_patches;  // records at the dtn_point stride
+                hp[at] = hp[0];
+            } else {
+                sl.h_patches[at] = sl.h_patches[0];
+            }
             sl.h_seed[at] = 0;
             sl.h_sid0[at] = 0;
             sl.h_se2[at] = HUGE_VAL;
@@ -530,9 +539,11 @@ dtn_status dtn_server_create(dtn_geometry g, const dtn_server_config *cfg, dtn_s
         *out = nullptr;
         std::string why;
         if (!valid_config(*cfg, why)) return fail(DTN_E_ARG, at + why);
+#ifndef DTN_SERVER_GRAPH_REPLAY
         if (cfg->graph_replay)
             return fail(DTN_E_ARG, at + "graph replay is switched off (a serving run with it crashed the host "
                                         "process; the cause is not yet shown)");
+#endif
         Geometry *G = &g->g;
         if (G->dev.kind != DTN_BOX && G->dev.kind != DTN_BOX_MINUS_BOXES)
             return fail(DTN_E_ARG, at + "only box domains (with or without holes) are served");
@@ -562,6 +573,7 @@ dtn_status dtn_server_create(dtn_geometry g, const dtn_server_config *cfg, dtn_s
             for (Slot &sl : S->slots) {
                 for (auto &kv : sl.graphs) (void)hipGraphExecDestroy(kv.second);
                 if (sl.stream) (void)hipStreamDestroy(sl.stream);
+                if (sl.capture) (void)hipStreamDestroy(sl.capture);
                 if (sl.h_patches) (void)hipHostFree(sl.h_patches);
                 if (sl.h_seed) (void)hipHostFree(sl.h_seed);
                 if (sl.h_sid0) (void)hipHostFree(sl.h_sid0);
@@ -582,6 +594,7 @@ dtn_status dtn_server_create(dtn_geometry g, const dtn_server_config *cfg, dtn_s
         S->slots.resize(cfg->n_streams);
         for (Slot &sl : S->slots) {
             if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+            if (e == hipSuccess && cfg->graph_replay) e = hipStreamCreateWithFlags(&sl.capture, hipStreamNonBlocking);
             if (e == hipSuccess) e = hipHostMalloc((void **)&sl.h_patches, sizeof(dtn_patch) * mp);
             if (e == hipSuccess) e = hipHostMalloc((void **)&sl.h_seed, sizeof(uint64_t) * mp);
             if (e == hipSuccess) e = hipHostMalloc((void **)&sl.h_sid0, sizeof(uint32_t) * mp);
@@ -629,6 +642,7 @@ void dtn_server_destroy(dtn_server s)
         (void)hipStreamSynchronize(sl.stream);
         for (auto &kv : sl.graphs) (void)hipGraphExecDestroy(kv.second);
         (void)hipStreamDestroy(sl.stream);
+        if (sl.capture) (void)hipStreamDestroy(sl.capture);
         (void)hipHostFree(sl.h_patches);
         (void)hipHostFree(sl.h_seed);
         (void)hipHostFree(sl.h_sid0);
