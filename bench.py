@@ -95,6 +95,26 @@ EXT_STEP_OPS = {
              "mad64": 10, "rsq64": 1},
 }
 EXT_WALK_OPS = {"f64": 16, "f64fma": 14, "rsq64": 2, "i32": 8}
+# Box minus holes, FP32-mixed step: the cube's step (its box distance is the
+# outer-box part), plus the cell lookup (position to FP32: 3 conversions,
+# 3 FMAs, 3 clamps, 3 truncations, 2 index products and 2 adds), the root of
+# the nearest hole's squared distance (clamp, rsq, product, min), and per
+# hole whose distance the wave computes: 3 differences, 3 differences of
+# absolute values, 3 clamps at 0, a product and 2 FMAs for the square, and
+# the running min.  The holes per wave iteration are counted by the kernel
+# (dtn_walk_counters).  Per walk: the cube's per-walk work with 20 sources
+# instead of 8 (each: differences, square, rsq with Newton refinement, the
+# scaled add) and the projection's candidate holes at the mean count.
+HOLES_STEP_OPS = {k: dict(v) for k, v in STEP_OPS.items()}
+for _k in HOLES_STEP_OPS:
+    _o = HOLES_STEP_OPS[_k]
+    _o["cvt"] = _o.get("cvt", 0) + 3 + 3
+    _o["f32"] = _o.get("f32", 0) + 6
+    _o["i32"] = _o.get("i32", 0) + 4
+    _o["f64"] = _o.get("f64", 0) + 3
+    _o["rsq64"] = _o.get("rsq64", 0) + 1
+HOLE_OPS = {"f64": 11, "f64fma": 2}
+HOLES_WALK_OPS = {"f64": 52 + 12 * 5, "f64fma": 72 + 12 * 9, "rsq64": 8 + 12, "i32": 8}
 
 
 def slots(ops):
@@ -102,6 +122,9 @@ def slots(ops):
 
 
 SLOTS_PER_STEP = {k: slots(v) for k, v in STEP_OPS.items()}
+HOLES_SLOTS_PER_STEP = {k: slots(v) for k, v in HOLES_STEP_OPS.items()}
+HOLE_SLOTS = slots(HOLE_OPS)
+HOLES_SLOTS_PER_WALK = slots(HOLES_WALK_OPS)
 SLOTS_PER_WALK = slots(WALK_OPS)
 HS_SLOTS_PER_STEP = {k: slots(v) for k, v in HS_STEP_OPS.items()}
 HS_SLOTS_PER_WALK = slots(HS_WALK_OPS)
@@ -212,7 +235,7 @@ def parse():
     ap.add_argument("--tiles", type=int, default=16, help="tiles per cube edge (16 -> 1536 patches)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precision's run")
-    ap.add_argument("--cpu-walks", type=int, default=40000, help="walks per node in the CPU sample")
+    ap.add_argument("--cpu-walks", type=int, default=100_000, help="walks per node in the CPU sample")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (reference for HBM counters)")
     ap.add_argument("--no-box-holes", action="store_true", help="skip the uneven-batching workload")
@@ -223,6 +246,9 @@ def parse():
     ap.add_argument("--serving-se-range", type=float, nargs=2, default=[1e-4, 1e-2],
                     help="range of the per-query required node standard error (log-uniform)")
     ap.add_argument("--serving-rate", type=float, default=200.0, help="offered load, queries/s")
+    ap.add_argument("--serving-stable-only", action="store_true",
+                    help="with --only serving: one window at --serving-rate only (a latency distribution at a "
+                         "rate the GPU sustains)")
     ap.add_argument("--no-halfspace", action="store_true", help="skip the single-point half-space workload")
     ap.add_argument("--no-disk", action="store_true", help="skip the thin-disk workload (Table 5)")
     ap.add_argument("--no-exterior", action="store_true", help="skip the exterior-sphere workload (Sec. 5.2)")
@@ -324,6 +350,7 @@ def box_holes(precision, steps, with_cpu=True, se_target=None, tune=True, with_f
                          walks_used=used, capped=capped)
         plan.solve(stats, precision=precision, neumann=neu, neumann_se=nse)
     torch.cuda.synchronize()
+    dtn.walk_counters(g)  # clear: count the timed steps only
     times = []
     for _ in range(steps):
         torch.cuda.synchronize()
@@ -332,6 +359,7 @@ def box_holes(precision, steps, with_cpu=True, se_target=None, tune=True, with_f
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         print(f"[bench] box_holes step {times[-1]:.2f} s", file=sys.stderr, flush=True)
+    iters, visits = dtn.walk_counters(g)
     st = stats.cpu().numpy()
     u = used.cpu().numpy()
     se = np.sqrt(st[:, 2] / np.maximum(st[:, 0] - 1, 1) / st[:, 0])
@@ -349,6 +377,17 @@ def box_holes(precision, steps, with_cpu=True, se_target=None, tune=True, with_f
         return rel_l2(sig, ex, area, tr), noise
 
     err, noise = errors(neu, nse)
+    # ALU roofline of the step (both walk launches; the solve and the
+    # planning kernels are under 0.1 % of it, counted in the time)
+    holes_per_iter = visits / max(iters, 1)
+    steps_n, walks_n = float(st[:, 3].sum()), float(u.sum())
+    slots_step = HOLES_SLOTS_PER_STEP[precision] + holes_per_iter * HOLE_SLOTS
+    slots_walk = HOLES_SLOTS_PER_WALK + holes_per_iter * HOLE_SLOTS
+    achieved = (slots_step * steps_n + slots_walk * walks_n) / sec
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK / 1e12, "unit": "T lane-op slots/s",
+            "frac": achieved / ALU_PEAK, "traffic": None, "slots_per_step": slots_step, "slots_per_walk": slots_walk,
+            "holes_per_wave_iteration": holes_per_iter, "wave_iterations_per_step": iters / max(steps, 1),
+            "walking_lanes_per_wave_iteration": steps_n * steps / max(iters, 1)}
     fp64 = None
     if with_fp64:
         stats64, used64 = torch.empty_like(stats), torch.empty_like(used)
@@ -376,7 +415,7 @@ def box_holes(precision, steps, with_cpu=True, se_target=None, tune=True, with_f
             "median_se_unclamped_nodes": float(np.median(se[free])) if free.any() else None,
             "neumann_rel_l2_vs_exact": err, "propagated_noise_rel_l2": noise,
             "capped_walks": int(capped.sum().item()), "schedule": sched, "schedule_ms": table,
-            "plain_fp64": fp64, "cpu_baseline": cpu}
+            "roofline": roof, "plain_fp64": fp64, "cpu_baseline": cpu}
 
 
 def box_holes_cpu_baseline(gd, pd, cfg, budget):
@@ -618,11 +657,23 @@ def sphere_exterior(precision, steps, warmup, with_cpu=True, cpu_patches=8):
                           precision=precision)
     s1, e1 = plan1.solve(st1, precision=precision)
     x1, _, a1, r1 = plane_or_sphere_panels(pd1, -gd["ball_r"])
-    s1 = s1.cpu().numpy()
+    # the second-kind equation on the same walks ((1/2 I - D) sigma = b, D != 0 on the sphere)
+    s2, e2 = plan1.solve_second_kind(st1)
+    s1, s2 = s1.cpu().numpy(), s2.cpu().numpy()
     tr1 = r1 < 0.7 * 1.0
+    ex1 = np.full_like(s1, 1.0 / 9.0)
+
+    def noise(e):
+        return float(np.sqrt(np.sum(a1[tr1] * e.cpu().numpy()[tr1] ** 2) / np.sum(a1[tr1] * ex1[tr1] ** 2)))
+
     sec52 = {"max_rel_err_r_lt_0.7a": float(np.max(np.abs(s1[tr1] - 1.0 / 9.0)) * 9.0),
-             "rel_l2_r_lt_0.7a": rel_l2(s1, np.full_like(s1, 1.0 / 9.0), a1, tr1),
-             "median_se_rel": float(np.median(e1.cpu().numpy()[tr1]) * 9.0), "paper_bar": 0.0125}
+             "rel_l2_r_lt_0.7a": rel_l2(s1, ex1, a1, tr1),
+             "median_se_rel": float(np.median(e1.cpu().numpy()[tr1]) * 9.0), "paper_bar": 0.0125,
+             "propagated_noise_rel_l2": noise(e1),
+             "second_kind": {"max_rel_err_r_lt_0.7a": float(np.max(np.abs(s2[tr1] - 1.0 / 9.0)) * 9.0),
+                             "rel_l2_r_lt_0.7a": rel_l2(s2, ex1, a1, tr1),
+                             "propagated_noise_rel_l2": noise(e2),
+                             "max_abs_diff_vs_first_kind": float(np.max(np.abs(s2 - s1)))}}
     print(f"[bench] sec 5.2 max rel err {sec52['max_rel_err_r_lt_0.7a']:.4f}", file=sys.stderr, flush=True)
     # throughput
     pd = cfg["patches"](cfg["n_patches"], seed=cfg["seed"])
@@ -875,7 +926,7 @@ def halfspace_cpu_baseline(gd, x, nrm, t1, a, cfg, gpu_out, n_sample):
 POINT_RULE = (8, 20, 1e-6)
 
 
-def serving(precision, window, rate, se_range, sweep_fraction=0.5, sweep_window=6):
+def serving(precision, window, rate, se_range, sweep_fraction=0.5, sweep_window=6, stable_only=False):
     """Query serving on the box-with-holes geometry: Poisson arrivals, each
     query 1..4096 boundary points (log-uniform) with a required standard
     error per node log-uniform on se_range, one patch per point, adaptive
@@ -903,30 +954,54 @@ def serving(precision, window, rate, se_range, sweep_fraction=0.5, sweep_window=
                        ladder=cfg["ladder"], layout=cfg["layout"], **mode)
         t0 = S.clock()
         done = []
+        last = [time.perf_counter()]
+
+        def progress():
+            if time.perf_counter() - last[0] > 30.0:
+                last[0] = time.perf_counter()
+                print(f"[bench] serving: {len(done)} of {n} queries done at {S.clock() - t0:.0f} s",
+                      file=sys.stderr, flush=True)
+
         for i, q in enumerate(qs):
             while S.clock() - t0 < q["t"]:
-                done.extend(S.wait(timeout=max(0.0, q["t"] - (S.clock() - t0))))
+                done.extend(S.wait(timeout=max(0.0, min(30.0, q["t"] - (S.clock() - t0)))))
+                progress()
             S.submit(i, q["pts"], q["normals"], q["se"], q["seed"])
         while len(done) < n:
-            done.extend(S.wait(timeout=60.0))
+            done.extend(S.wait(timeout=30.0))
+            progress()
         S.close()
         assert all(d["status"] == 0 for d in done)
         lat = np.array([d["t_done"] - (t0 + qs[d["id"]]["t"]) for d in done])
         walks = sum(float(d["answer"][:, 2].sum()) for d in done)
         points = sum(len(q["pts"]) for q in qs)
-        # achieved SE of each answer over its query's node SE target
+        # achieved SE of each answer over its query's node SE target; points
+        # whose nodes all ran the walk cap (their answers cannot meet it)
         ratio = np.concatenate([d["answer"][:, 1] / qs[d["id"]]["se"] for d in done])
+        nn = cfg["layout"][0] * cfg["layout"][1]
+        at_cap = np.concatenate([d["answer"][:, 2] >= nn * cfg["max_walks"] for d in done])
+        q_ok = np.array([bool(np.all(d["answer"][:, 1] <= qs[d["id"]]["se"])) for d in done])
         busy = max(d["t_done"] for d in done) - t0
-        out = {"rate_qps": rate_qps, "queries": n, "points": points, "p50_ms": float(np.percentile(lat, 50) * 1e3),
-               "p99_ms": float(np.percentile(lat, 99) * 1e3), "walks": walks, "makespan_s": busy,
+        out = {"rate_qps": rate_qps, "queries": n, "completions": len(done), "points": points,
+               "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+               "percentile_samples": len(lat), "walks": walks, "makespan_s": busy,
                "served_qps": n / busy, "patches_per_s": points / busy, "walks_per_s": walks / busy,
-               "median_answer_se_over_target": float(np.median(ratio))}
+               "median_answer_se_over_target": float(np.median(ratio)),
+               "share_points_answer_se_within_target": float(np.mean(ratio <= 1.0)),
+               "share_queries_every_answer_within_target": float(np.mean(q_ok)),
+               "share_points_all_nodes_at_walk_cap": float(np.mean(at_cap))}
         print(f"[bench] serving {'plain fp64' if plain else prec}{' point mode' if point else ''} at "
               f"{rate_qps:.3g} q/s, {n} queries: "
-              f"{out['patches_per_s']:.0f} patches/s, p50 {out['p50_ms']:.0f} ms p99 {out['p99_ms']:.0f} ms",
-              file=sys.stderr, flush=True)
+              f"{out['patches_per_s']:.0f} patches/s, p50 {out['p50_ms']:.0f} ms p99 {out['p99_ms']:.0f} ms "
+              f"(over {len(lat)} completions)", file=sys.stderr, flush=True)
         return out
 
+    if stable_only:
+        return {"workload": f"box_holes geometry resident; Poisson arrivals at {rate:g} q/s; 1..4096 points per "
+                            f"query (log-uniform); patch per point; adaptive walks {cfg['min_walks']}.."
+                            f"{cfg['max_walks']} at a per-query node SE log-uniform on [{se_range[0]:g}, "
+                            f"{se_range[1]:g}]; 2 GB budget",
+                "precision": precision, "stable": run(rate, window)}
     main = run(rate, window)
     plain = run(rate, window, prec="fp64", plain=True)
     point = run(rate, window, point=True)
@@ -945,12 +1020,19 @@ def serving(precision, window, rate, se_range, sweep_fraction=0.5, sweep_window=
             "stable": stable, "low": low}
 
 
-def cpu_baseline(gd, pd_all, walks_per_node, g, full_walks):
+def cpu_baseline(gd, pd_all, walks_per_node, g, full_walks, sigmas=None, full_walks_per_node=None):
     """The oracle on a bounded sample: the 16-tile subset of the cube tiling
-    (face centres, edges, corners, 4 seeded tiles), walks_per_node each.
-    The FP64 GPU path then runs the identical sample (its own nodes, the
-    same seed and stream ids) for a like-for-like rate and per-node parity:
-    z = |mean_gpu - mean_oracle| / sqrt(se_gpu^2 + se_oracle^2)."""
+    (face centres, edges, corners, 4 seeded tiles), walks_per_node each, every
+    node with the stream id it has in the full launch (its global node
+    index).  The FP64 GPU path then runs the identical sample (its own nodes,
+    the same seed and stream ids) for a like-for-like rate and per-node
+    parity: z = |mean_gpu - mean_oracle| / sqrt(se_gpu^2 + se_oracle^2).
+
+    sigmas: the timed runs' Neumann data {(walk precision, solve precision):
+    [panels]}; when the sample ran at their walk count, the oracle's own
+    Neumann data on the sample (FP64 walks, FP64 solve) is the reference
+    each pairing is compared with.  Also times the unit-ball workload (one
+    patch, 128 nodes x 1e4 walks) on the oracle in full, beside the GPU."""
     import torch
 
     import dtn_inputs as I
@@ -962,9 +1044,12 @@ def cpu_baseline(gd, pd_all, walks_per_node, g, full_walks):
     pd = I.subset_patches(pd_all, sub)
     ps = OP.patches_from_desc(pd, gd)
     nodes = np.concatenate([OP.nodes_global(p)[0] for p in ps])
+    npp = nodes.shape[0] // len(sub)
+    sid = (np.asarray(sub)[:, None] * npp + np.arange(npp)[None, :]).reshape(-1).astype(np.uint32)
     og = OW.Geometry(gd)
+    print(f"[bench] oracle: {nodes.shape[0]} nodes x {walks_per_node} walks", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    r = OW.wos_nodes(og, nodes, walks_per_node, seed=2)
+    r = OW.wos_nodes(og, nodes, walks_per_node, seed=2, stream_id=sid)
     dt = time.perf_counter() - t0
     walks = float(r["count"].sum())
     cores = OW.max_threads()
@@ -974,10 +1059,11 @@ def cpu_baseline(gd, pd_all, walks_per_node, g, full_walks):
     n = plan.num_nodes
     w = torch.full((n,), walks_per_node, dtype=torch.int64, device=nd.device)
     st = torch.empty((n, 4), dtype=torch.float64, device=nd.device)
-    dtn.wos_eval(g, nd, w, seed=2, precision="fp64", stats=st)
+    S = torch.tensor(sid.view(np.int32), device=nd.device)
+    dtn.wos_eval(g, nd, w, seed=2, precision="fp64", stats=st, stream_id=S)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    dtn.wos_eval(g, nd, w, seed=2, precision="fp64", stats=st)
+    dtn.wos_eval(g, nd, w, seed=2, precision="fp64", stats=st, stream_id=S)
     torch.cuda.synchronize()
     dt_gpu = time.perf_counter() - t1
     sg = st.cpu().numpy()
@@ -989,17 +1075,82 @@ def cpu_baseline(gd, pd_all, walks_per_node, g, full_walks):
     flat = se == 0
     z = diff[~flat] / se[~flat]
     rel_flat = diff[flat] / np.maximum(np.abs(r["mean"][flat]), 1e-300)
-    return {"value": walks / dt, "unit": "walks/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(sub)} tiles x {nodes.shape[0] // len(sub)} nodes x {walks_per_node} walks "
-                      f"({int(walks)} walks, {int(r['steps'].sum())} steps) in {dt:.1f} s",
-            "steps_per_s": float(r["steps"].sum()) / dt, "walks_per_s_per_core": walks / dt / cores,
-            "extrapolated_full_workload_s": full_walks / (walks / dt),
-            "gpu_same_sample": {"walks_per_s": walks / dt_gpu, "seconds": dt_gpu,
-                                "ratio_gpu_over_oracle": dt / dt_gpu, "parity_max_z": float(z.max()),
-                                "nodes_over_4_sigma": int((z > 4).sum()),
-                                "nodes_in_shell": int(flat.sum()),
-                                "in_shell_max_rel_diff": float(rel_flat.max()) if flat.any() else 0.0,
-                                "identical_node_means": int((sg[:, 1] == r["mean"]).sum()), "nodes": int(n)}}
+    out = {"value": walks / dt, "unit": "walks/s", "cores": cores, "kind": "oracle",
+           "sample": f"{len(sub)} tiles x {npp} nodes x {walks_per_node} walks "
+                     f"({int(walks)} walks, {int(r['steps'].sum())} steps) in {dt:.1f} s",
+           "steps_per_s": float(r["steps"].sum()) / dt, "walks_per_s_per_core": walks / dt / cores,
+           "extrapolated_full_workload_s": full_walks / (walks / dt),
+           "gpu_same_sample": {"walks_per_s": walks / dt_gpu, "seconds": dt_gpu,
+                               "ratio_gpu_over_oracle": dt / dt_gpu, "parity_max_z": float(z.max()),
+                               "nodes_over_4_sigma": int((z > 4).sum()),
+                               "nodes_in_shell": int(flat.sum()),
+                               "in_shell_max_rel_diff": float(rel_flat.max()) if flat.any() else 0.0,
+                               "identical_node_means": int((sg[:, 1] == r["mean"]).sum()), "nodes": int(n)}}
+    # each walks x solve pairing of the timed runs against the oracle's own
+    # Neumann data on the sample (same walks when the counts agree)
+    if sigmas and full_walks_per_node == walks_per_node:
+        npan = ps[0].n_rings * ps[0].n_sectors
+        ref, exact, area, tr, nse = [], [], [], [], []
+        for k, p in enumerate(ps):
+            o = OP.patch_solve(p, og, r["mean"][k * npp:(k + 1) * npp], r["se"][k * npp:(k + 1) * npp])
+            xg, ng, ar, rc = OP.collocation_points(p)
+            ref.append(o["sigma"])
+            nse.append(o["se"])
+            exact.append(OP.exact_neumann(gd, xg, ng))
+            area.append(ar)
+            tr.append(rc < 0.7 * p.h)
+        ref, exact, area, tr, nse = map(np.concatenate, (ref, exact, area, tr, nse))
+        cols = (np.asarray(sub)[:, None] * npan + np.arange(npan)[None, :]).reshape(-1)
+        den = np.sum(area[tr] * exact[tr] ** 2)
+        pairs = {}
+        for (wp, sp), sig in sigmas.items():
+            s = sig[cols]
+            pairs[f"walks_{wp}_solve_{sp}"] = {
+                "rel_l2_vs_oracle": float(np.sqrt(np.sum(area[tr] * (s[tr] - ref[tr]) ** 2) / den)),
+                "max_abs_vs_oracle": float(np.max(np.abs(s - ref))),
+                "rel_l2_vs_exact": float(np.sqrt(np.sum(area[tr] * (s[tr] - exact[tr]) ** 2) / den))}
+        out["precision_vs_oracle"] = {
+            "sample": f"{len(sub)} tiles x {npan} panels, oracle FP64 walks ({walks_per_node}/node, same counters) "
+                      "and FP64 solve",
+            "oracle_rel_l2_vs_exact": float(np.sqrt(np.sum(area[tr] * (ref[tr] - exact[tr]) ** 2) / den)),
+            "propagated_noise_rel_l2": float(np.sqrt(np.sum(area[tr] * nse[tr] ** 2) / den)),
+            "pairings": pairs}
+    # the unit-ball workload in full on the oracle, and on the GPU
+    bd, bp = I.geometry_ball_quadratic(), I.patches_ball_pole()
+    bps = OP.patches_from_desc(bp, bd)[0]
+    bn, _ = OP.nodes_global(bps)
+    bg = OW.Geometry(bd)
+    t0 = time.perf_counter()
+    br = OW.wos_nodes(bg, bn, 10_000, seed=1)
+    bsol = OP.patch_solve(bps, bg, br["mean"], br["se"])
+    dtb = time.perf_counter() - t0
+    xg, ng, ar, _ = OP.collocation_points(bps)
+    bex = OP.exact_neumann(bd, xg, ng)
+    gb = dtn.Geometry(bd)
+    bplan = dtn.Plan(gb, bp)
+    bnodes = bplan.nodes()
+    bw = torch.full((bplan.num_nodes,), 10_000, dtype=torch.int64, device=bnodes.device)
+    bst, _ = dtn.wos_eval(gb, bnodes, bw, seed=1)
+    bsig, _ = bplan.solve(bst)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    bst, _ = dtn.wos_eval(gb, bnodes, bw, seed=1)
+    bsig, _ = bplan.solve(bst)
+    torch.cuda.synchronize()
+    dtg = time.perf_counter() - t1
+    bsig = bsig.cpu().numpy()
+    bsig2 = bplan.solve_second_kind(bst)[0].cpu().numpy()
+
+    def rel(a):
+        return float(np.sqrt(np.sum(ar * (a - bex) ** 2) / np.sum(ar * bex ** 2)))
+
+    out["unit_ball"] = {"workload": "unit ball, one patch (h 0.2) x 128 nodes x 1e4 walks, eps 1e-4, 32 panels",
+                        "oracle_seconds": dtb, "oracle_walks_per_s": 1.28e6 / dtb, "gpu_seconds": dtg,
+                        "gpu_walks_per_s": 1.28e6 / dtg, "oracle_rel_l2_vs_exact": rel(bsol["sigma"]),
+                        "gpu_rel_l2_vs_exact": rel(bsig), "gpu_second_kind_rel_l2_vs_exact": rel(bsig2),
+                        "gpu_vs_oracle_max_abs": float(np.max(np.abs(bsig - bsol["sigma"]))),
+                        "neumann_se_median": float(np.median(bsol["se"]))}
+    return out
 
 
 def main():
@@ -1103,7 +1254,8 @@ def main():
                       "propagated_noise_rel_l2": float(np.sqrt(np.sum(area[trusted] * sse2[trusted] ** 2) / den)),
                       "first_kind_noise_rel_l2": float(np.sqrt(np.sum(area[trusted] * sse1[trusted] ** 2) / den)),
                       "solve_ms": e0.elapsed_time(e1), "first_kind_solve_ms": f0.elapsed_time(f1)}
-        return {"second_kind": second, "ms_per_step": ms, "rel_l2_by_solve_precision": solves, "walks_per_s": walks_n / (ms / 1e3), "patches_per_s": n_patches / (ms / 1e3),
+        return {"sigma": {precision: sig, other: sig2}, "second_kind": second, "ms_per_step": ms,
+                "rel_l2_by_solve_precision": solves, "walks_per_s": walks_n / (ms / 1e3), "patches_per_s": n_patches / (ms / 1e3),
                 "neumann_rel_l2_vs_exact": rel_l2(sig, ex, area, trusted),
                 "neumann_se_median": float(np.median(neumann_se.cpu().numpy())),
                 "potential_max_err_far": float(np.max(np.abs(u.cpu().numpy()[far] - u_ex[far]))
@@ -1121,7 +1273,8 @@ def main():
         return
     if args.only == "serving":
         print(json.dumps({"serving": serving("fp32", args.serving_window, args.serving_rate, args.serving_se_range,
-                                             sweep_window=args.serving_sweep_window)}), flush=True)
+                                             sweep_window=args.serving_sweep_window,
+                                             stable_only=args.serving_stable_only)}), flush=True)
         return
     if args.only == "exterior":
         print(json.dumps({"sphere_exterior": sphere_exterior(args.precision, args.steps, args.warmup,
@@ -1217,7 +1370,14 @@ def main():
         line["p50_latency_ms"] = line["serving"]["served"]["p50_ms"]
         line["p99_latency_ms"] = line["serving"]["served"]["p99_ms"]
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(gd, pd, args.cpu_walks, g, float(N) * args.walks)
+        sigmas = {(args.precision, sp): a for sp, a in m["sigma"].items()}
+        if not args.no_variants:
+            sigmas.update({(other, sp): a for sp, a in v["sigma"].items()})
+        cb = cpu_baseline(gd, pd, args.cpu_walks, g, float(N) * args.walks, sigmas, args.walks)
+        if "precision_vs_oracle" in cb:
+            line["precision_vs_oracle"] = cb.pop("precision_vs_oracle")
+        line["unit_ball"] = cb.pop("unit_ball")
+        line["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)
 
 

@@ -58,8 +58,8 @@ typedef enum {
     DTN_E_DEVICE = -2,      /* HIP runtime error                          */
     DTN_E_OOM = -3,         /* device or host allocation failed           */
     DTN_E_UNSUPPORTED = -4, /* valid request this build does not support  */
-    DTN_E_NOCONV = -5,      /* iterative refinement did not converge      */
-    DTN_E_MAXSTEPS = -6     /* reserved: walks capped (see dtn_wos_eval)  */
+    DTN_E_NOCONV = -5,      /* iterative refinement did not converge (dtn_check) */
+    DTN_E_MAXSTEPS = -6     /* walks ended by the step cap (dtn_check)    */
 } dtn_status;
 
 /* Domain kinds (walks run inside Omega). */
@@ -109,7 +109,9 @@ typedef struct dtn_plan_s *dtn_plan;         /* opaque, library-owned */
  *   eps: width of the absorbing shell (Sec. 2, epsilon-shell WOS), > 0.
  *   max_steps: a walk still alive after max_steps steps is scored at its
  *        closest boundary point and counted as capped (a walk gone to
- *        infinity is neither capped nor absorbed). */
+ *        infinity is neither capped nor absorbed); 0 <= max_steps <= 2^32 - 1
+ *        (a walk's step count is 32-bit).  Capped walks are counted per point
+ *        (dtn_wos_eval's `capped`) and raise DTN_E_MAXSTEPS at dtn_check. */
 typedef struct {
     int32_t kind;
     int32_t data_kind;
@@ -181,7 +183,8 @@ void dtn_destroy_geometry(dtn_geometry g);
  *   capped     device [n] out (int64): walks ended by max_steps, or NULL
  * Scratch is taken from the stream-ordered allocator and released on the
  * same stream.  Errors: DTN_E_ARG (n < 0, NULL pts/walks/stats when n > 0,
- * unknown precision). */
+ * unknown precision).  Walks ended by the step cap are reported by
+ * dtn_check once the stream has run them. */
 dtn_status dtn_wos_eval(dtn_geometry g, const double *pts, int64_t n, const int64_t *walks,
                         const int64_t *walk_begin, uint64_t seed, const uint32_t *stream_id,
                         int32_t precision, double *stats, int64_t *capped, void *stream);
@@ -267,6 +270,34 @@ dtn_status dtn_wos_time_schedules(dtn_geometry g, const double *pts, int64_t n, 
  * or the sphere of a ball, inside or outside), or n_patches < 1. */
 dtn_status dtn_create_plan(dtn_geometry g, const dtn_patch *patches, int64_t n_patches, dtn_plan *out);
 void dtn_destroy_plan(dtn_plan p);
+/* Most FP32 solves of dtn_patch_solve's FP32-mixed refinement, 0..64
+ * (default 8; 0 or 1 cannot reach the bound, so they always raise
+ * DTN_E_NOCONV).  Set before enqueuing solves on the plan, not while another
+ * thread enqueues them.  Errors: DTN_E_ARG. */
+dtn_status dtn_plan_set_max_sweeps(dtn_plan p, int32_t max_sweeps);
+
+/* Status of the work done on a geometry (Sec. 2's capped walks; Sec. 5.2's
+ * collocation solve).  Waits for the work enqueued on `stream`, then reads
+ * and clears the geometry's status bits, raised by any completed work on it
+ * (every plan, point set and server of the geometry, every stream: to cover
+ * other streams, synchronise them first):
+ *   DTN_E_NOCONV    an FP32-mixed solve missed its residual bound
+ *   DTN_E_MAXSTEPS  some walk was ended by the step cap
+ *   DTN_OK          neither.
+ * Not to be called while a stream capture is recording on `stream`.
+ * Errors: DTN_E_ARG (NULL), DTN_E_DEVICE. */
+dtn_status dtn_check(dtn_geometry g, void *stream);
+
+/* Work counters of the walks on a box minus holes (diagnostic, for the
+ * roofline of the walk kernel): waits for the work enqueued on `stream`,
+ * then reads and clears, over all completed walk launches on this geometry,
+ *   out[0]  wave iterations (each computes one distance per lane of its wave)
+ *   out[1]  hole distances computed per wave: the sum over wave iterations
+ *           of the holes listed for the cells of the wave's walking lanes
+ *           (every hole for more than 32 holes).
+ * Zero for other domains.  Errors: DTN_E_ARG (NULL), DTN_E_DEVICE. */
+dtn_status dtn_walk_counters(dtn_geometry g, void *stream, int64_t out[2]);
+
 /* Sizes of a plan: total nodes and total panels over its patches. */
 int64_t dtn_plan_num_nodes(dtn_plan p);
 int64_t dtn_plan_num_panels(dtn_plan p);
@@ -280,31 +311,43 @@ dtn_status dtn_patch_nodes(dtn_plan p, double *nodes, void *stream);
  * node means, and SE(sigma) = sqrt(sum_k A_k^2 SE_k^2), A = K^-1 (Q.I).
  *   node_stats device [num_nodes][4] from dtn_wos_eval, node order
  *   precision  DTN_FP64: FP64 LU solve; DTN_FP32_MIXED: FP32 LU factors
- *              (computed on the device with MFMA) + FP64 residual iterative
- *              refinement
+ *              (computed on the device with MFMA) + iterative refinement
+ *              with the residual b - K sigma in FP64, until the norm-wise
+ *              backward error |r|_inf <= P 2^-53 (|K|_inf |sigma|_inf +
+ *              |b|_inf) (P panels), at most max_sweeps FP32 solves (default
+ *              8, see dtn_plan_set_max_sweeps); a patch that misses the bound
+ *              (or whose residual is not finite) keeps its last iterate and
+ *              raises DTN_E_NOCONV at dtn_check
  *   neumann    device [num_panels] out, patch-major, ring-major
  *   neumann_se device [num_panels] out, or NULL */
 dtn_status dtn_patch_solve(dtn_plan p, const double *node_stats, int32_t precision, double *neumann,
                            double *neumann_se, void *stream);
 
-/* Step 2 by the second-kind equation (Sec. 4, eqs. bw53-bw59) on plans whose
- * patches are all flat: there the adjoint double layer D of the ball's
- * Green's function vanishes, so (1/2 I - D) sigma = b gives sigma = 2b with
- * no linear solve, at the same collocation points as dtn_patch_solve:
- *   b(x) = int_Gamma dP/dn_x (u - phi(x)) - int_S d2G/dn_x dn_y (phi - phi(x)),
- * P the ball's Poisson kernel, u on Gamma the interpolant of the node means,
- * the hypersingular S integral regularised by the constant solution and taken
- * outside the disk of radius 1e-6 h around x (eq. bw82's O(delta) error).
- * SE(sigma) = 2 sqrt(sum_k Q2_ik^2 SE_k^2) / h.  FP64.
- *   node_stats device [num_nodes][4]; neumann device [num_panels] out;
- *   neumann_se device [num_panels] out, or NULL.
- * Errors: DTN_E_ARG (NULL), DTN_E_UNSUPPORTED (a curved patch). */
+/* Step 2 by the second-kind equation (Sec. 4, eqs. bw53-bw59), at the same
+ * collocation points as dtn_patch_solve:
+ *   (1/2 I - D) sigma = b,   D[sigma](x) = int_S dG/dn_x sigma ds (eq. bw57),
+ *   b(x) = - int_Gamma d2G/dn_x dn_y (u - phi(x)) ds
+ *          - int_S d2G/dn_x dn_y (phi - phi(x)) ds,
+ * G the ball's Green's function, u on Gamma the interpolant of the node
+ * means; the hypersingular S integral (eq. bw59's finite part) is
+ * regularised by the constant solution and taken outside the disk of radius
+ * 1e-6 h around x (its projection onto the tangent plane at the centre, on a
+ * sphere), an O(delta) error as in eq. bw82.  On flat patches D = 0 and
+ * sigma = 2b with no solve; on a sphere (inside a ball or outside one) D is
+ * collocated with piecewise constants (Duffy on the own panel) and the
+ * system solved with the class's FP64 LU factors.  SE(sigma) =
+ * sqrt(sum_k A_ik^2 SE_k^2) with A = 2 Q2 / h (flat) or (1/2 I - D)^-1 Q2 / h.
+ * FP64.  node_stats device [num_nodes][4]; neumann device [num_panels] out;
+ * neumann_se device [num_panels] out, or NULL.
+ * Errors: DTN_E_ARG (NULL). */
 dtn_status dtn_patch_solve_second_kind(dtn_plan p, const double *node_stats, double *neumann, double *neumann_se,
                                        void *stream);
 
 /* u at m targets off the boundary by eq. bw03 (G = 1/(4 pi |x - y|)).
- * Requires every patch to be a square tile [-h,h]^2 of a box face (tiles
- * covering the boundary, as produced by splitting each face into squares):
+ * Requires the patches to tile the boundary of a box: square tiles
+ * [-h,h]^2 in their (t1, n x t1) frame with t1 along an axis, inside their
+ * face, not overlapping, and adding up to each face's area (checked when the
+ * plan is created; a partial or overlapping tiling is rejected here):
  * per tile, the Neumann data is the least-squares quadratic through the
  * panels within 0.7 h of the centre and the tile integral a 4 x 4 Gauss rule
  * with the exact Dirichlet data.  DTN_E_UNSUPPORTED for other plans.
@@ -435,7 +478,8 @@ dtn_status dtn_points_neumann(dtn_points p, const double *node_stats, double *ou
  * smallest size bucket B >= n (B = n up to 8, then m 2^e with m in 5..8, at
  * most max_points), and its whole device pass (copies in, walks, solve,
  * answers, copy out, stream-ordered alloc and free) is one HIP graph,
- * captured once per stream and bucket and replayed for every later batch of
+ * captured once per stream and bucket (recorded on a capture stream of its
+ * own, which runs no work) and replayed for every later batch of
  * that bucket.  Padding rows repeat the batch's first patch with an infinite
  * SE target, so they take only the pilot walks; their answers are dropped.
  * Budgets and footprints are those of the padded batch.  This mode is
@@ -520,11 +564,14 @@ dtn_status dtn_server_wait(dtn_server s, int64_t max_n, double timeout_s, dtn_qu
 dtn_status dtn_class_operators(int32_t n_theta, int32_t n_phi, int32_t n_rings, int32_t n_sectors, double rr,
                                double *node_tab, double *col_tab, double *K, double *QI, double *A2, double *fit);
 
-/* Host diagnostic: the second-kind tables of a flat class at h = 1 (no
- * device): Q2 [P][N] (the Gamma operator with the kernel dP/dn_x) and c2 [P]
- * (sum_k Q2_ik minus the sum of the S rule's weights).  Host arrays. */
-dtn_status dtn_class_second_kind(int32_t n_theta, int32_t n_phi, int32_t n_rings, int32_t n_sectors, double *Q2,
-                                 double *c2);
+/* Host diagnostic: the second-kind tables of a class at h = 1 (no device),
+ * rr as for dtn_class_operators (0: plane): Q2 [P][N] (the Gamma operator
+ * with the kernel -d2G_B/dn_x dn_y, dP/dn_x on a plane), c2 [P] (sum_k Q2_ik
+ * minus the sum of the regularised S rule's weights) and M [P][P] = 1/2 I - D
+ * (D the adjoint double layer of eq. bw57; zero on a plane), or NULL.  Host
+ * arrays.  Errors: DTN_E_ARG (NULL Q2 or c2, bad layout, 0 < |rr| < 1). */
+dtn_status dtn_class_second_kind(int32_t n_theta, int32_t n_phi, int32_t n_rings, int32_t n_sectors, double rr,
+                                 double *Q2, double *c2, double *M);
 
 #ifdef __cplusplus
 }

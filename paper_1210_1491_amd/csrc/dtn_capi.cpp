@@ -97,8 +97,20 @@ dtn_status get_class(const ClassKey &key, int device, DevClass &out, bool &fresh
     UP(s_pts, s_pts)
     UP(s_w, s_w)
     UP(c2, c2)
+    UP(M2_LU, M2_LU)
+    UP(A2s, A2s)
 #undef UP
+    if (e == hipSuccess && !ops.M2_piv.empty()) {
+        e = upload(ops.M2_piv, &ip);
+        d.M2_piv = ip;
+    }
     d.n_s = ops.n_s;
+    d.k_inf = 0.0;
+    for (int i = 0; i < d.n_panels; ++i) {
+        double row = 0.0;
+        for (int j = 0; j < d.n_panels; ++j) row += std::fabs(ops.K[(size_t)i * d.n_panels + j]);
+        d.k_inf = std::max(d.k_inf, row);
+    }
     if (e == hipSuccess) {
         e = upload(ops.piv, &ip);
         d.piv = ip;
@@ -110,6 +122,67 @@ dtn_status get_class(const ClassKey &key, int device, DevClass &out, bool &fresh
     out = d;
     fresh = true;
     return DTN_OK;
+}
+
+// Device arrays of a geometry (hipFree of NULL is a no-op).
+void free_geometry(Geometry &g)
+{
+    (void)hipFree(g.d_hole_ce);
+    (void)hipFree(g.d_hole_box);
+    (void)hipFree(g.d_hole_f32);
+    (void)hipFree(g.d_sincos);
+    (void)hipFree(g.d_cell_mask);
+    (void)hipFree(g.d_src);
+    (void)hipFree(g.d_tab);
+    (void)hipFree(g.d_status);
+    g.d_hole_ce = g.d_hole_box = g.d_src = g.d_sincos = g.d_tab = nullptr;
+    g.d_hole_f32 = nullptr;
+    g.d_cell_mask = nullptr;
+    g.d_status = nullptr;
+}
+
+// The potential's sum (eq. bw03) runs over square tiles [-h, h]^2 about
+// each patch centre in its (t1, n x t1) frame.  It is the integral over the
+// box boundary only if the tiles cover every face exactly once: each tile
+// has an axis-aligned frame and lies inside its face, tiles on a face do not
+// overlap, and their areas add up to the face area.
+bool tiles_cover_box(const Geometry &G, const std::vector<dtn_patch> &ps)
+{
+    const double *lo = G.dev.lo, *hi = G.dev.hi;
+    double scale = 0.0;
+    for (int k = 0; k < 3; ++k) scale = std::max({scale, std::fabs(lo[k]), std::fabs(hi[k]), hi[k] - lo[k]});
+    const double tol = 1e-9 * scale;
+    struct Sq { double a0, a1, b0, b1; };
+    std::vector<Sq> face[6];
+    for (const dtn_patch &q : ps) {
+        int k = -1, ta = -1;
+        for (int d = 0; d < 3; ++d) {
+            if (std::fabs(std::fabs(q.n[d]) - 1.0) < 1e-12) k = d;
+            if (std::fabs(std::fabs(q.t1[d]) - 1.0) < 1e-12) ta = d;
+        }
+        if (k < 0 || ta < 0 || ta == k) return false;
+        const int f = 2 * k + (q.n[k] > 0 ? 1 : 0);
+        const double plane = q.n[k] < 0 ? lo[k] : hi[k];
+        if (std::fabs(q.c[k] - plane) > tol) return false;
+        const int a = (k + 1) % 3, b = (k + 2) % 3;
+        const Sq sq{q.c[a] - q.h, q.c[a] + q.h, q.c[b] - q.h, q.c[b] + q.h};
+        if (sq.a0 < lo[a] - tol || sq.a1 > hi[a] + tol || sq.b0 < lo[b] - tol || sq.b1 > hi[b] + tol) return false;
+        face[f].push_back(sq);
+    }
+    for (int f = 0; f < 6; ++f) {
+        const int k = f / 2, a = (k + 1) % 3, b = (k + 2) % 3;
+        std::vector<Sq> &v = face[f];
+        double area = 0.0;
+        for (const Sq &q : v) area += (q.a1 - q.a0) * (q.b1 - q.b0);
+        const double want = (hi[a] - lo[a]) * (hi[b] - lo[b]);
+        if (std::fabs(area - want) > 1e-9 * want) return false;
+        // overlap: sweep in order of the lower a edge
+        std::sort(v.begin(), v.end(), [](const Sq &x, const Sq &y) { return x.a0 < y.a0; });
+        for (size_t i = 0; i < v.size(); ++i)
+            for (size_t j = i + 1; j < v.size() && v[j].a0 < v[i].a1 - tol; ++j)
+                if (v[j].b0 < v[i].b1 - tol && v[i].b0 < v[j].b1 - tol) return false;
+    }
+    return true;
 }
 
 bool unit(const double *v, double tol = 1e-12) { return std::fabs(std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) - 1.0) < tol; }
@@ -316,7 +389,9 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
                 if (!std::isfinite(d.tab[q])) return fail(DTN_E_ARG, "dtn_create_geometry: tab holds a non-finite value");
         }
         if (!(d.eps > 0.0)) return fail(DTN_E_ARG, "dtn_create_geometry: eps must be > 0");
-        if (d.max_steps < 0) return fail(DTN_E_ARG, "dtn_create_geometry: max_steps < 0");
+        if (d.max_steps < 0 || d.max_steps > (int64_t)0xffffffff)
+            return fail(DTN_E_ARG, "dtn_create_geometry: max_steps outside [0, 2^32 - 1] (a walk's step count "
+                                   "is 32-bit)");
         const bool unbounded = d.kind == DTN_HALF_SPACE || d.kind == DTN_DISK || d.kind == DTN_BALL_EXTERIOR;
         if ((d.kind == DTN_BALL || d.kind == DTN_BALL_EXTERIOR) && !(d.ball_r > 0.0))
             return fail(DTN_E_ARG, "dtn_create_geometry: ball_r <= 0");
@@ -424,7 +499,11 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
         }
         if (e == hipSuccess) e = upload(g.src, &g.d_src);
         if (e == hipSuccess && tab_len) e = upload(std::vector<double>(d.tab, d.tab + tab_len), &g.d_tab);
-        if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_create_geometry: ") + hipGetErrorString(e));
+        if (e == hipSuccess) e = upload(std::vector<DevStatus>(1, DevStatus{}), &g.d_status);
+        if (e != hipSuccess) {
+            free_geometry(g);
+            return fail(DTN_E_DEVICE, std::string("dtn_create_geometry: ") + hipGetErrorString(e));
+        }
         g.dev.hole_ce = g.d_hole_ce;
         g.dev.hole_box = g.d_hole_box;
         g.dev.hole_f32 = g.d_hole_f32;
@@ -432,6 +511,7 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
         g.dev.cell_mask = g.d_cell_mask;
         g.dev.src = g.d_src;
         g.dev.tab = g.d_tab;
+        g.dev.status = g.d_status;
         // keep stream-ordered scratch in the pool between calls
         hipMemPool_t pool;
         if (hipDeviceGetDefaultMemPool(&pool, g.device) == hipSuccess) {
@@ -448,13 +528,7 @@ dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
 void dtn_destroy_geometry(dtn_geometry g)
 {
     if (!g) return;
-    (void)hipFree(g->g.d_hole_ce);
-    (void)hipFree(g->g.d_hole_box);
-    (void)hipFree(g->g.d_hole_f32);
-    (void)hipFree(g->g.d_sincos);
-    (void)hipFree(g->g.d_cell_mask);
-    (void)hipFree(g->g.d_src);
-    (void)hipFree(g->g.d_tab);
+    free_geometry(g->g);
     delete g;
 }
 
@@ -667,6 +741,7 @@ dtn_status dtn_create_plan(dtn_geometry g, const dtn_patch *patches, int64_t n_p
         }
         p.n_nodes = p.node_off[n_patches];
         p.n_panels = p.panel_off[n_patches];
+        if (p.tiles_ok) p.tiles_ok = tiles_cover_box(G, p.patches);
         hipError_t e = hipGetDevice(&p.device);
         if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_create_plan: ") + hipGetErrorString(e));
         std::vector<DevClass> dc(keys.size());
@@ -713,6 +788,52 @@ void dtn_destroy_plan(dtn_plan p)
     delete p;
 }
 
+dtn_status dtn_check(dtn_geometry g, void *stream)
+{
+    try {
+        if (!g) return fail(DTN_E_ARG, "dtn_check: NULL geometry");
+        static std::mutex mu;  // one snapshot word per geometry
+        std::lock_guard<std::mutex> lk(mu);
+        uint32_t bits = 0;
+        const dtn_status st = take_flags(g->g, (hipStream_t)stream, bits);
+        if (st != DTN_OK) return st;
+        if (bits & kFlagNoConv)
+            return fail(DTN_E_NOCONV, std::string("dtn_check: an FP32-mixed solve did not reach its residual "
+                                                  "bound") +
+                                          (bits & kFlagCapped ? "; walks were ended by the step cap" : ""));
+        if (bits & kFlagCapped)
+            return fail(DTN_E_MAXSTEPS, "dtn_check: walks were ended by the step cap (see the per-point capped "
+                                        "counts)");
+        return DTN_OK;
+    } catch (...) {
+        return fail(DTN_E_OOM, "dtn_check: exception");
+    }
+}
+
+dtn_status dtn_walk_counters(dtn_geometry g, void *stream, int64_t out[2])
+{
+    try {
+        if (!g || !out) return fail(DTN_E_ARG, "dtn_walk_counters: NULL argument");
+        static std::mutex mu;  // one snapshot per geometry
+        std::lock_guard<std::mutex> lk(mu);
+        unsigned long long c[2] = {0, 0};
+        const dtn_status st = take_counters(g->g, (hipStream_t)stream, c);
+        out[0] = (int64_t)c[0];
+        out[1] = (int64_t)c[1];
+        return st;
+    } catch (...) {
+        return fail(DTN_E_OOM, "dtn_walk_counters: exception");
+    }
+}
+
+dtn_status dtn_plan_set_max_sweeps(dtn_plan p, int32_t max_sweeps)
+{
+    if (!p) return fail(DTN_E_ARG, "dtn_plan_set_max_sweeps: NULL plan");
+    if (max_sweeps < 0 || max_sweeps > 64) return fail(DTN_E_ARG, "dtn_plan_set_max_sweeps: outside [0, 64]");
+    p->p.max_sweeps = max_sweeps;
+    return DTN_OK;
+}
+
 int64_t dtn_plan_num_nodes(dtn_plan p) { return p ? p->p.n_nodes : -1; }
 int64_t dtn_plan_num_panels(dtn_plan p) { return p ? p->p.n_panels : -1; }
 
@@ -737,8 +858,8 @@ dtn_status dtn_patch_solve_second_kind(dtn_plan p, const double *node_stats, dou
     try {
         if (!p || !node_stats || !neumann) return fail(DTN_E_ARG, "dtn_patch_solve_second_kind: NULL argument");
         for (const PlanClassHost &c : p->p.classes)
-            if (!c.dev.Q2)
-                return fail(DTN_E_UNSUPPORTED, "dtn_patch_solve_second_kind: flat patches only (a patch is curved)");
+            if (!c.dev.Q2 || (c.dev.curved && !c.dev.M2_LU))
+                return fail(DTN_E_UNSUPPORTED, "dtn_patch_solve_second_kind: a patch class has no second-kind tables");
         return launch_solve2(p->p, node_stats, neumann, neumann_se, (hipStream_t)stream);
     } catch (...) {
         return fail(DTN_E_DEVICE, "dtn_patch_solve_second_kind: exception");
@@ -788,24 +909,35 @@ dtn_status dtn_class_operators(int32_t n_theta, int32_t n_phi, int32_t n_rings, 
 
 }  // extern "C"
 
-dtn_status dtn_class_second_kind(int32_t n_theta, int32_t n_phi, int32_t n_rings, int32_t n_sectors, double *Q2,
-                                 double *c2)
+dtn_status dtn_class_second_kind(int32_t n_theta, int32_t n_phi, int32_t n_rings, int32_t n_sectors, double rr,
+                                 double *Q2, double *c2, double *M)
 {
     try {
         if (!Q2 || !c2) return fail(DTN_E_ARG, "dtn_class_second_kind: NULL argument");
         if (n_theta < 2 || n_theta > 32 || n_phi < 4 || n_phi > 64 || (n_phi & 1) || n_rings < 1 || n_rings > 16 ||
             n_sectors < 2 || n_sectors > 32 || n_rings * n_sectors > 128)
             return fail(DTN_E_ARG, "dtn_class_second_kind: unsupported layout");
+        if (!std::isfinite(rr) || (rr != 0.0 && std::fabs(rr) < 1.0))
+            return fail(DTN_E_ARG, "dtn_class_second_kind: |rr| must be >= 1 (or 0 for a plane)");
         dtn::ClassOps ops;
         ops.n_theta = n_theta;
         ops.n_phi = n_phi;
         ops.n_rings = n_rings;
         ops.n_sectors = n_sectors;
-        ops.rr = 0.0;
+        ops.rr = rr;
         std::string err;
         if (!dtn::build_class_ops(ops, err)) return dtn::fail(DTN_E_ARG, "dtn_class_second_kind: " + err);
         std::copy(ops.Q2.begin(), ops.Q2.end(), Q2);
         std::copy(ops.c2.begin(), ops.c2.end(), c2);
+        if (M) {
+            const int P = n_rings * n_sectors;
+            if (rr == 0.0) {
+                std::fill(M, M + (size_t)P * P, 0.0);
+                for (int i = 0; i < P; ++i) M[(size_t)i * P + i] = 0.5;
+            } else {
+                std::copy(ops.M2.begin(), ops.M2.end(), M);
+            }
+        }
         return DTN_OK;
     } catch (...) {
         return dtn::fail(DTN_E_OOM, "dtn_class_second_kind: exception");

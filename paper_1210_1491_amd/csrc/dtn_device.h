@@ -479,6 +479,19 @@ __device__ __forceinline__ KSum wave_ksum(KSum a)
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup i to XCD
+// i mod 8), and each XCD has its own L2.  This bijection of [0, G) gives
+// XCD x the contiguous range of logical blocks [x q + min(x, r), ...), q =
+// G / 8, r = G mod 8, in dispatch order, so the rows a block reads (points,
+// walk counts, chunk offsets) are shared with its XCD neighbours' rows
+// instead of being fetched into all eight L2s.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t i, int64_t G)
+{
+    const int64_t x = i % kXcds, q = G / kXcds, r = G % kXcds;
+    return x * q + (x < r ? x : r) + i / kXcds;
+}
+
 // Exit-point queue entry (3 doubles) `first + rank` of a queue in LDS,
 // addressed in 32 bits: rank x 24 B (one 24-bit multiply-add) onto the
 // wave-uniform byte offset of entry `first`.

@@ -44,7 +44,21 @@ struct DevGeom {
     const double *tab;
     int32_t tab_n[2];
     double tab_sc[3][2];
+    // Status of the work on this geometry (device, see DevStatus).
+    struct DevStatus *status;
 };
+
+// Sticky status bits raised by kernels working on a geometry (kFlag*), read
+// and cleared by dtn_check, and the walk counters of box-minus-holes walks,
+// read and cleared by dtn_walk_counters; *_taken are the snapshots those
+// calls take.
+struct DevStatus {
+    uint32_t flags, flags_taken;
+    unsigned long long iters, visits;  // wave iterations, hole distances computed by waves
+    unsigned long long iters_taken, visits_taken;
+};
+constexpr uint32_t kFlagCapped = 1u;  // some walk was ended by the step cap
+constexpr uint32_t kFlagNoConv = 2u;  // an FP32-mixed solve did not reach its residual bound
 
 // Per-class operators on the device.  A class is a set of congruent patches
 // (same layout and same curvature relative to h); K scales with h.
@@ -68,13 +82,18 @@ struct DevClass {
     const double *fit;        // [16][n_panels] tile fit (flat classes)
     const double *tile_gl;    // [16][3]: (xi, eta, weight) on [-1,1]^2
     const double *ans_row;    // [n_nodes]: ring-0 mean of the rows of K^-1 QI at h = 1
-    // second-kind equation on flat classes (NULL on curved ones), at h = 1
-    // (scale 1/h): sigma_i = 2 (Q2 u - sum_q s_w phi(s_pts) - c2 phi(x_i))
-    const double *Q2;         // [n_panels][n_nodes]: Gamma operator with the kernel dP/dn_x
+    // second-kind equation, at h = 1 (scale 1/h): b_i = Q2 u -
+    // sum_q s_w phi(s_pts) - c2 phi(x_i); flat classes: sigma = 2 b; curved
+    // ones: (1/2 I - D) sigma = b by the LU factors M2_LU
+    const double *Q2;         // [n_panels][n_nodes]: Gamma operator with the kernel -d2G_B/dn_x dn_y
     const double *s_pts;      // [n_panels][n_s][3]: local points / h of the regularised S rule
     const double *s_w;        // [n_panels][n_s]: weights x kernel of that rule
     const double *c2;         // [n_panels]: sum_k Q2_ik - sum_q s_w_iq
     int32_t n_s;
+    const double *M2_LU;      // [n_panels][n_panels] LU of 1/2 I - D (curved classes; NULL on flat ones)
+    const int32_t *M2_piv;    // [n_panels]
+    const double *A2s;        // [n_panels][n_nodes]: (M^-1 Q2)^2 (curved classes)
+    double k_inf;             // max row sum of |K| at h = 1 (residual bound of the refinement)
 };
 
 struct Geometry {
@@ -86,6 +105,7 @@ struct Geometry {
     double *d_sincos = nullptr;
     uint32_t *d_cell_mask = nullptr;
     double *d_tab = nullptr;
+    DevStatus *d_status = nullptr;  // see DevGeom::status
     std::vector<uint32_t> cell_mask;
     int device = 0;
 };
@@ -107,7 +127,8 @@ struct Plan {
     int32_t *d_patch_class = nullptr;  // [n_patches]
     int64_t *d_node_off = nullptr;     // [n_patches+1]
     int64_t *d_panel_off = nullptr;    // [n_patches+1]
-    bool tiles_ok = false;             // every patch is a square tile of a box face
+    bool tiles_ok = false;             // the patches tile the whole boundary of a box (square tiles)
+    int max_sweeps = 8;                // FP32-mixed solve: FP32 solves with FP64 residual at most
     int device = 0;
 };
 
@@ -139,6 +160,11 @@ dtn_status launch_distance(const Geometry &g, const double *pts, int64_t n, int 
 dtn_status launch_wos_adaptive(const Geometry &g, const double *pts, int64_t n, const Adaptive &a, uint64_t seed,
                                const uint64_t *node_seed, const uint32_t *stream_id, int precision, double *stats,
                                int64_t *walks_used, int64_t *capped, const Schedule &sc, hipStream_t stream);
+
+// Read and clear the geometry's status bits, or its walk counters, after
+// the stream's work (synchronises the stream).
+dtn_status take_flags(const Geometry &g, hipStream_t stream, uint32_t &out);
+dtn_status take_counters(const Geometry &g, hipStream_t stream, unsigned long long out[2]);
 
 // Kernel launchers (dtn_patch.hip).
 dtn_status launch_nodes(const Plan &p, double *nodes, hipStream_t stream);
@@ -172,7 +198,9 @@ struct ClassOps {
     int n_theta, n_phi, n_rings, n_sectors;
     double rr;  // R/h (0 = plane)
     std::vector<double> node_tab, col_tab, K, LU, QI, A2, dl_pts, dl_w, fit, tile_gl, ans_row;
-    std::vector<double> Q2, s_pts, s_w, c2;  // second kind, flat classes only
+    std::vector<double> Q2, s_pts, s_w, c2;  // second kind
+    std::vector<double> M2, M2_LU, A2s;       // second kind on a sphere: 1/2 I - D, its LU, (M^-1 Q2)^2
+    std::vector<int32_t> M2_piv;
     std::vector<int32_t> piv;
     int n_dl = 0, n_s = 0;
 };

@@ -321,6 +321,129 @@ inline double ddgreen_s(V3 x, V3 y)
     return 1.0 / (4.0 * kPi * r * r * r) - 1.0 / (4.0 * kPi * D * std::sqrt(D));
 }
 
+// ---- second-kind equation on a patch of a sphere (signed radius rr at
+// h = 1, centre C = (0, 0, -rr), outward normal (x - C) / rr): D != 0, so
+// (1/2 I - D) sigma = b is solved by LU.  The kernels are the derivatives of
+// G_B = 1/(4 pi r) - 1/(4 pi sqrt(f)), f = |x|^2 |y|^2 - 2 x.y + 1, for any
+// points and unit normals (on Gamma, n_y = y):
+//   dG_B/dn_x       = [-(x - y).n_x / r^3 + f^{-3/2} (|y|^2 x - y).n_x] / (4 pi)
+//   d2G_B/dn_x dn_y = [n_x.n_y / r^3 - 3 ((x - y).n_x)((x - y).n_y) / r^5
+//                      - 3 f^{-5/2} ((|y|^2 x - y).n_x)((|x|^2 y - x).n_y)
+//                      + f^{-3/2} (2 (x.n_x)(y.n_y) - n_x.n_y)] / (4 pi)
+inline double dgreen_dnx(V3 x, V3 nx, V3 y)
+{
+    const V3 d = sub(x, y);
+    const double r = norm(d), aa = dot(y, y);
+    const double f = aa * dot(x, x) - 2.0 * dot(x, y) + 1.0;
+    const V3 gx{aa * x.x - y.x, aa * x.y - y.y, aa * x.z - y.z};
+    return (-dot(d, nx) / (r * r * r) + dot(gx, nx) / (f * std::sqrt(f))) * kInv4Pi;
+}
+
+inline double ddgreen(V3 x, V3 nx, V3 y, V3 ny)
+{
+    const V3 d = sub(x, y);
+    const double r = norm(d), r2 = r * r, aa = dot(y, y), bb = dot(x, x);
+    const double f = aa * bb - 2.0 * dot(x, y) + 1.0, sf = std::sqrt(f);
+    const V3 gx{aa * x.x - y.x, aa * x.y - y.y, aa * x.z - y.z};
+    const V3 gy{bb * y.x - x.x, bb * y.y - x.y, bb * y.z - x.z};
+    const double nn = dot(nx, ny);
+    const double fr = nn / (r2 * r) - 3.0 * dot(d, nx) * dot(d, ny) / (r2 * r2 * r);
+    const double img = 3.0 * dot(gx, nx) * dot(gy, ny) / (f * f * sf) - (2.0 * dot(x, nx) * dot(y, ny) - nn) / (f * sf);
+    return (fr - img) * kInv4Pi;
+}
+
+// Tables of the curved second kind: Q2 (Gamma kernel -d2G_B/dn_x dn_y against
+// the node interpolant), the regularised S rule around each collocation
+// point, c2, M = 1/2 I - D with its LU factors, and (M^-1 Q2)^2 for the SE.
+// The S rule parametrises S by its projection (X, Y) onto the tangent plane
+// at the centre, a disk of radius r sin(s_max) (z = e (sqrt(r^2 - X^2 - Y^2)
+// - r), normal (e X, e Y, sqrt(r^2 - X^2 - Y^2)) / r, area element
+// r / sqrt(r^2 - X^2 - Y^2)), with the flat rule's rays and radial grading
+// around x's projection and the disk of radius kSecondKindDelta excluded.
+template <class Rows>
+void second_kind_tables_curved(ClassOps &ops, const std::vector<V3> &X, const std::vector<V3> &N,
+                               const std::vector<Box> &boxes, const Surf &surf, Rows &gamma_rows)
+{
+    const int Np = ops.n_rings * ops.n_sectors, Nn = ops.n_theta * ops.n_phi;
+    const double rr = ops.rr, r = surf.r(), e = surf.side();
+    gamma_rows(
+        [rr](V3 x, V3 y) {
+            const V3 nx{x.x / rr, x.y / rr, (x.z + rr) / rr};
+            return -ddgreen(x, nx, y, y);
+        },
+        ops.Q2);
+    // D (eq. bw57, collocation form): weakly singular on the own panel
+    std::vector<double> D((size_t)Np * Np, 0.0);
+    for (int j = 0; j < Np; ++j)
+        for (int i = 0; i < Np; ++i) {
+            auto f = [&](double s, double a, double *out) {
+                V3 y, n;
+                double jac;
+                surf.at(s, a, y, n, jac);
+                out[0] = dgreen_dnx(X[i], N[i], y) * jac;
+            };
+            std::vector<Leaf> lv;
+            if (i == j)
+                singular_leaves(boxes[j], surf, f, lv);
+            else
+                adapt_leaves(boxes[j], 1, f, 1e-14, 0, lv);
+            double acc = 0.0;
+            for (const Leaf &l : lv) {
+                double v;
+                f(l.s, l.a, &v);
+                acc += l.w * v;
+            }
+            D[(size_t)i * Np + j] = acc;
+        }
+    ops.M2 = D;
+    for (double &v : ops.M2) v = -v;
+    for (int i = 0; i < Np; ++i) ops.M2[(size_t)i * Np + i] += 0.5;
+    ops.M2_LU = ops.M2;
+    // S rule
+    const int n = kSecondKindRule;
+    std::vector<double> gx, gw;
+    gauss_legendre(n, gx, gw);
+    ops.n_s = 2 * n * n;
+    ops.s_pts.assign((size_t)Np * ops.n_s * 3, 0.0);
+    ops.s_w.assign((size_t)Np * ops.n_s, 0.0);
+    ops.c2.assign(Np, 0.0);
+    const double rim = r * std::sin(surf.smax());
+    for (int i = 0; i < Np; ++i) {
+        const V3 x = X[i];
+        double wsum = 0.0;
+        int q = 0;
+        for (int l = 0; l < n; ++l) {
+            const double psi = kPi * (gx[l] + 1.0), wpsi = kPi * gw[l];
+            const double ex = std::cos(psi), ey = std::sin(psi);
+            const double be = ex * x.x + ey * x.y, bb = x.x * x.x + x.y * x.y;
+            const double rmax = -be + std::sqrt(be * be + rim * rim - bb);
+            const double lo0 = kSecondKindDelta, mid = std::sqrt(kSecondKindDelta * rmax);
+            const double los[2] = {lo0, mid}, his[2] = {mid, rmax};
+            for (int piece = 0; piece < 2; ++piece) {
+                const double L = std::log(his[piece] / los[piece]);
+                for (int k = 0; k < n; ++k, ++q) {
+                    const double tau = 0.5 * (gx[k] + 1.0), wtau = 0.5 * gw[k];
+                    const double rho = los[piece] * std::exp(L * tau);
+                    const double px = x.x + rho * ex, py = x.y + rho * ey;
+                    const double qz = std::sqrt(r * r - px * px - py * py);
+                    const V3 y{px, py, e * (qz - r)};
+                    const V3 ny{e * px / r, e * py / r, qz / r};
+                    const double w = wpsi * wtau * rho * rho * L * (r / qz) * ddgreen(x, N[i], y, ny);
+                    double *o = &ops.s_pts[((size_t)i * ops.n_s + q) * 3];
+                    o[0] = y.x;
+                    o[1] = y.y;
+                    o[2] = y.z;
+                    ops.s_w[(size_t)i * ops.n_s + q] = w;
+                    wsum += w;
+                }
+            }
+        }
+        double qsum = 0.0;
+        for (int k = 0; k < Nn; ++k) qsum += ops.Q2[(size_t)i * Nn + k];
+        ops.c2[i] = qsum - wsum;
+    }
+}
+
 template <class Rows>
 void second_kind_tables(ClassOps &ops, const std::vector<V3> &X, Rows &gamma_rows)
 {
@@ -523,7 +646,30 @@ bool build_class_ops(ClassOps &ops, std::string &err)
         }
     };
     gamma_rows([](V3 x, V3 y) { return poisson_ball(x, y); }, ops.QI);
-    if (ops.rr == 0.0) second_kind_tables(ops, X, gamma_rows);
+    if (ops.rr == 0.0) {
+        second_kind_tables(ops, X, gamma_rows);
+    } else {
+        std::vector<V3> N(Np);
+        for (int k = 0; k < Np; ++k) {
+            const Box &b = boxes[k];
+            V3 y;
+            double jac;
+            surf.at(0.5 * (b.s0 + b.s1), 0.5 * (b.a0 + b.a1), y, N[k], jac);
+        }
+        second_kind_tables_curved(ops, X, N, boxes, surf, gamma_rows);
+        if (!lu_factor(Np, ops.M2_LU, ops.M2_piv)) {
+            err = "singular second-kind matrix";
+            return false;
+        }
+        // (M^-1 Q2)^2 for the propagated standard error
+        ops.A2s.assign((size_t)Np * Nn, 0.0);
+        std::vector<double> c(Np);
+        for (int k = 0; k < Nn; ++k) {
+            for (int i = 0; i < Np; ++i) c[i] = ops.Q2[(size_t)i * Nn + k];
+            lu_solve(Np, ops.M2_LU, ops.M2_piv, c.data());
+            for (int i = 0; i < Np; ++i) ops.A2s[(size_t)i * Nn + k] = c[i] * c[i];
+        }
+    }
 
     // ---- A2 = (K^-1 Q.I)^2, and the ring-0 row: the mean over the central
     // ring's panels (equal areas on a plane patch) of K^-1 Q.I

@@ -75,6 +75,18 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Largest |v| over the wave; a NaN anywhere gives NaN (fmax would drop it).
+__device__ __forceinline__ double wave_absmax(double v)
+{
+    v = fabs(v);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off, kWave);
+        v = (o > v || o != o) ? o : v;
+    }
+    return v;
+}
+
 template <int DATA>
 __global__ __launch_bounds__(kSolveBlock) void k_solve(DevGeom g, const dtn_patch *__restrict__ patches,
                                                        const int32_t *__restrict__ pclass,
@@ -82,7 +94,8 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(DevGeom g, const dtn_patc
                                                        const int64_t *__restrict__ node_off,
                                                        const int64_t *__restrict__ panel_off,
                                                        const double *__restrict__ node_stats, int mixed,
-                                                       double *__restrict__ neumann, double *__restrict__ neumann_se)
+                                                       int max_sweeps, double *__restrict__ neumann,
+                                                       double *__restrict__ neumann_se)
 {
     __shared__ double u[kMaxNodes];
     __shared__ double v2[kMaxNodes];
@@ -170,14 +183,27 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(DevGeom g, const dtn_patc
             }
             for (int i = lane; i < Np; i += kWave) sol[i] = b[i];
         } else {
-            // FP32 factors + FP64 residual: y0 = 0, r = b, repeat: y += LU32^-1 r
+            // FP32 factors + FP64 residual: y0 = 0, r = b; each sweep
+            // y += LU32^-1 r, then r = b - K_hat y in FP64, until the
+            // norm-wise backward error is at FP64 rounding level,
+            //   |r|_inf <= Np 2^-53 (|K_hat|_inf |y|_inf + |b|_inf),
+            // or max_sweeps sweeps (then, or on a non-finite residual, the
+            // geometry's no-convergence bit is raised for dtn_check).  With
+            // cond(K_hat) <= 64 (every supported layout) the bound is met
+            // after three sweeps.
+            double bmax = 0.0;
             for (int i = lane; i < Np; i += kWave) {
                 sol[i] = 0.0;
                 res[i] = b[i];
+                const double a = fabs(b[i]);
+                bmax = (a > bmax || a != a) ? a : bmax;
             }
+            bmax = wave_absmax(bmax);
+            const double tol = (double)Np * 0x1p-53;
+            bool converged = false;
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            for (int it = 0; it < 4; ++it) {
+            for (int it = 0; it < max_sweeps && !converged; ++it) {
                 if (lane == 0) {
                     for (int k = 0; k < Np; ++k) f32[k] = (float)res[k];
                     for (int k = 0; k < Np; ++k) {
@@ -221,7 +247,17 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(DevGeom g, const dtn_patc
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 __builtin_amdgcn_wave_barrier();
+                double rmax = 0.0, ymax = 0.0;
+                for (int i = lane; i < Np; i += kWave) {
+                    const double ra = fabs(res[i]), ya = fabs(sol[i]);
+                    rmax = (ra > rmax || ra != ra) ? ra : rmax;
+                    ymax = (ya > ymax || ya != ya) ? ya : ymax;
+                }
+                rmax = wave_absmax(rmax);
+                ymax = wave_absmax(ymax);
+                converged = rmax <= tol * (cl.k_inf * ymax + bmax);  // false on NaN
             }
+            if (!converged && lane == 0) atomicOr(&g.status->flags, kFlagNoConv);
         }
     }
     __syncthreads();
@@ -438,27 +474,30 @@ dtn_status launch_solve(const Plan &p, const double *node_stats, int precision, 
     const dim3 grid((unsigned)p.patches.size());
     if (p.geom->dev.data_kind == DTN_DATA_TABULATED)
         hipLaunchKernelGGL(k_solve<DTN_DATA_TABULATED>, grid, dim3(kSolveBlock), 0, s, p.geom->dev, p.d_patches,
-                           p.d_patch_class, p.d_classes, p.d_node_off, p.d_panel_off, node_stats, mixed, neumann,
-                           neumann_se);
+                           p.d_patch_class, p.d_classes, p.d_node_off, p.d_panel_off, node_stats, mixed,
+                           p.max_sweeps, neumann, neumann_se);
     else if (p.geom->dev.data_kind == DTN_DATA_POINT_SOURCES)
         hipLaunchKernelGGL(k_solve<DTN_DATA_POINT_SOURCES>, grid, dim3(kSolveBlock), 0, s, p.geom->dev, p.d_patches,
-                           p.d_patch_class, p.d_classes, p.d_node_off, p.d_panel_off, node_stats, mixed, neumann,
-                           neumann_se);
+                           p.d_patch_class, p.d_classes, p.d_node_off, p.d_panel_off, node_stats, mixed,
+                           p.max_sweeps, neumann, neumann_se);
     else
         hipLaunchKernelGGL(k_solve<DTN_DATA_HARMONIC_QUADRATIC>, grid, dim3(kSolveBlock), 0, s, p.geom->dev,
                            p.d_patches, p.d_patch_class, p.d_classes, p.d_node_off, p.d_panel_off, node_stats, mixed,
-                           neumann, neumann_se);
+                           p.max_sweeps, neumann, neumann_se);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_patch_solve: ") + hipGetErrorString(e));
     return DTN_OK;
 }
 
-// ------------------------------------------------- second kind (flat)
-// sigma = 2b on a flat patch (eqs. bw53-bw59 with D = 0): one block per
-// patch, one wave per panel row: the Gamma operator Q2 against the node
-// means (and Q2^2 against their squared SE for the propagated SE), phi at
-// the regularised S rule's points, the constant term at the collocation
-// point; all scaled by 1/h.
+// ------------------------------------------------------- second kind
+// Eqs. bw53-bw59: one block per patch, one wave per panel row computes
+//   b_i = Q2_i u - sum_q s_w_iq phi(s_pts_iq) - c2_i phi(x_i)
+// (the Gamma operator against the node means, phi at the regularised S
+// rule's points and at the collocation point).  Flat classes: D = 0 and
+// sigma = 2b; classes on a sphere: (1/2 I - D) sigma = b by substitution
+// with the class's FP64 LU factors (wave 0).  The propagated SE takes
+// (2 Q2)^2, or (M^-1 Q2)^2, against the node means' squared SE.  All
+// scaled by 1/h.
 template <int DATA>
 __global__ __launch_bounds__(kSolveBlock) void k_solve2(DevGeom g, const dtn_patch *__restrict__ patches,
                                                         const int32_t *__restrict__ pclass,
@@ -470,10 +509,12 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve2(DevGeom g, const dtn_pat
 {
     __shared__ double u[kMaxNodes];
     __shared__ double v2[kMaxNodes];
+    __shared__ double b[kMaxPanels];
     const int pi = blockIdx.x;
     const dtn_patch p = patches[pi];
     const DevClass &cl = classes[pclass[pi]];
     const int Np = cl.n_panels, Nn = cl.n_nodes, Ns = cl.n_s;
+    const bool curved = cl.M2_LU != nullptr;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int nwaves = kSolveBlock / kWave;
     double t2[3];
@@ -486,14 +527,15 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve2(DevGeom g, const dtn_pat
         v2[k] = cnt > 1.0 ? s[2] / ((cnt - 1.0) * cnt) : 0.0;
     }
     __syncthreads();
-    const double two_over_h = 2.0 / p.h;
+    const double inv_h = 1.0 / p.h;
     for (int i = wave; i < Np; i += nwaves) {
         const double *q2 = cl.Q2 + (size_t)i * Nn;
+        const double *a2 = curved ? cl.A2s + (size_t)i * Nn : nullptr;
         double acc = 0.0, var = 0.0, sp = 0.0;
         for (int k = lane; k < Nn; k += kWave) {
             const double w = q2[k];
             acc += w * u[k];
-            var += w * w * v2[k];
+            var += (curved ? a2[k] : 4.0 * w * w) * v2[k];
         }
         const double *pts = cl.s_pts + (size_t)i * Ns * 3;
         const double *sw = cl.s_w + (size_t)i * Ns;
@@ -510,10 +552,44 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve2(DevGeom g, const dtn_pat
             const double *x = cl.col_tab + 3 * i;
             to_global(p, t2, x[0], x[1], x[2], gx, gy, gz);
             const double fx = phi_eval<DATA>(g, gx, gy, gz);
-            const int64_t o = panel_off[pi] + i;
-            neumann[o] = two_over_h * (acc - sp - cl.c2[i] * fx);
-            if (neumann_se) neumann_se[o] = two_over_h * sqrt(var);
+            b[i] = acc - sp - cl.c2[i] * fx;
+            if (neumann_se) neumann_se[panel_off[pi] + i] = inv_h * sqrt(var);
         }
+    }
+    __syncthreads();
+    if (!curved) {
+        for (int i = tid; i < Np; i += kSolveBlock) neumann[panel_off[pi] + i] = 2.0 * inv_h * b[i];
+        return;
+    }
+    if (wave == 0) {
+        if (lane == 0)
+            for (int k = 0; k < Np; ++k) {
+                const int pk = cl.M2_piv[k];
+                if (pk != k) {
+                    const double t = b[k];
+                    b[k] = b[pk];
+                    b[pk] = t;
+                }
+            }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int i = 0; i < Np; ++i) {  // forward, unit lower
+            double a = 0.0;
+            for (int j = lane; j < i; j += kWave) a += cl.M2_LU[(size_t)i * Np + j] * b[j];
+            a = wave_sum(a);
+            if (lane == 0) b[i] -= a;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        for (int i = Np - 1; i >= 0; --i) {  // backward
+            double a = 0.0;
+            for (int j = i + 1 + lane; j < Np; j += kWave) a += cl.M2_LU[(size_t)i * Np + j] * b[j];
+            a = wave_sum(a);
+            if (lane == 0) b[i] = (b[i] - a) / cl.M2_LU[(size_t)i * Np + i];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        for (int i = lane; i < Np; i += kWave) neumann[panel_off[pi] + i] = inv_h * b[i];
     }
 }
 

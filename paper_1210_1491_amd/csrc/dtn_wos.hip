@@ -38,6 +38,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <string>
 
 #include "dtn_device.h"
 #include "dtn_internal.h"
@@ -244,7 +245,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
     // one chunk per wave; chunk size and count are wave-uniform (SGPRs)
     const int64_t C = uniform64(meta[0]);
     const int64_t total = uniform64(meta[1]);
-    const int64_t chunk = (int64_t)blockIdx.x * (kWalkBlock / kWave) + wave;
+    const int64_t chunk = xcd_block(blockIdx.x, gridDim.x) * (kWalkBlock / kWave) + wave;
     if (chunk >= total) return;
     const double eps = g.eps;
     {
@@ -281,13 +282,20 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
         // (wave-uniform): a lane jumps when it walks and does not stop, a
         // stopping lane is capped when it is not inside the shell
         uint64_t steps = 0, capped = 0;
+        // box minus holes: wave iterations and hole distances computed
+        // (scalar counters, reported by dtn_walk_counters)
+        uint64_t n_iters = 0, n_visits = 0;
         int64_t next = w_lo;  // wave-uniform: next walk to hand out
         int qn = 0;           // wave-uniform: queued exit points
-        // step cap as a 32-bit bound (a walk's step count is 32-bit)
+        // step cap (a walk's step count is 32-bit; geometries with a larger
+        // cap are rejected at creation)
         const uint32_t cap = (uint32_t)min(g.max_steps, (int64_t)0xffffffff);
-        // Hard bound on wave iterations: every walk ends within max_steps + 2
+        // Hard bound on wave iterations: every walk ends within cap + 2
         // iterations of its start and a lane runs at most ceil(C/64) walks.
-        const uint64_t it_max = ((uint64_t)g.max_steps + 4u) * 2u * (uint64_t)((w_hi - w_lo + kWave - 1) / kWave + 1);
+        // Saturating, so that no cap or chunk size makes the product wrap.
+        const uint64_t per_walk = 2ull * ((uint64_t)cap + 4ull);
+        const uint64_t per_lane = (uint64_t)((w_hi - w_lo + kWave - 1) / kWave + 1);
+        const uint64_t it_max = per_lane > ~0ull / per_walk ? ~0ull : per_walk * per_lane;
 
         for (uint64_t it = 0; it < it_max; ++it) {
             uint32_t w1, w2;  // this step's two random words
@@ -324,6 +332,10 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
             uint32_t cand = 0;
             if constexpr (KIND == DTN_BOX_MINUS_BOXES)
                 cand = hole_candidates(g, co, walking, (float)x, (float)y, (float)z);
+            if constexpr (has_holes(KIND)) {
+                ++n_iters;
+                n_visits += KIND == DTN_BOX_MINUS_BOXES ? (uint64_t)__builtin_popcount(cand) : (uint64_t)g.n_holes;
+            }
             // distance and epsilon test in FP64 on both paths (an FP32
             // distance would need an FP64 recheck inside a rounding band
             // around the shell, which some lane of a wave needs at almost
@@ -405,6 +417,10 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                 }
             }
         }
+        // walks still running or never started when the bound ends the loop
+        // (not reached under the bound above) are counted as capped, so a
+        // short sum is never silent
+        capped += (uint64_t)__popcll(wmask) + (uint64_t)(next < w_hi ? w_hi - next : 0);
         // score what is left in the queue
         wave_sync();
         {
@@ -424,6 +440,12 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
         const KSum t2 = wave_ksum(s2);
         const unsigned long long ts = steps;
         const unsigned long long tc = capped;
+        if constexpr (has_holes(KIND)) {
+            if (lane == 0) {
+                atomicAdd(&g.status->iters, (unsigned long long)n_iters);
+                atomicAdd(&g.status->visits, (unsigned long long)n_visits);
+            }
+        }
         if (lane == 0) {
             ChunkPartial p;
             p.s1 = t1.s;
@@ -474,6 +496,7 @@ __global__ __launch_bounds__(256) void k_wos_finalize(DevGeom g, const double *_
     stats[4 * i + 2] = m2;
     stats[4 * i + 3] = (double)st;
     if (capped) capped[i] = (int64_t)cp;
+    if (cp != 0) atomicOr(&g.status->flags, kFlagCapped);  // reported by dtn_check
 }
 
 // ----------------------------------------------------------------- launch
@@ -493,33 +516,52 @@ int device_cus()
 
 namespace {
 
+// Launch shape and scratch of one walk launch over n points: the chunk
+// target (`oversub` chunks per resident wave, 4 SIMDs x 8 waves per CU), the
+// bound on the chunk count (total chunks <= sum(walks)/C + n <= target + n),
+// the multi-block plan over nb segments of L points for many points, and the
+// scratch bytes (meta, chunk offsets, partials with 16 B of alignment slack,
+// segment sums and counts).
+struct WalkLayout {
+    int64_t target_chunks, max_chunks, L, blocks;
+    int nb;
+    bool multi;
+    size_t bytes;
+};
+
+WalkLayout walk_layout(int64_t n, const Schedule &sc)
+{
+    constexpr int64_t kSegPoints = 2048, kMaxSegs = 1024;
+    WalkLayout w{};
+    w.target_chunks = (int64_t)device_cus() * 4 * 8 * sc.oversub;
+    w.max_chunks = n + w.target_chunks + 1;
+    w.multi = n > 8 * kSegPoints;
+    w.nb = w.multi ? (int)std::min(kMaxSegs, (n + kSegPoints - 1) / kSegPoints) : 0;
+    w.L = w.multi ? (n + w.nb - 1) / w.nb : 0;
+    w.blocks = (w.max_chunks + kWalkBlock / kWave - 1) / (kWalkBlock / kWave);
+    w.bytes = sizeof(int64_t) * (size_t)(n + 1) + 64 + 16 + sizeof(ChunkPartial) * (size_t)w.max_chunks +
+              2 * sizeof(int64_t) * (size_t)w.nb;
+    return w;
+}
+
 template <int KIND, int DATA, int PREC>
 hipError_t run(const Geometry &g, const double *pts, int64_t n, const int64_t *walks, const int64_t *walk_begin,
                uint64_t seed, const uint64_t *node_seed, const uint32_t *stream_id, double *stats, int64_t *capped,
-               const Schedule &sc,
-               hipStream_t s)
+               const Schedule &sc, char *ws, hipStream_t s)
 {
-    // Aim for `oversub` chunks per resident wave (4 SIMDs x 8 waves per CU);
-    // chunks hold at least `min_chunk` walks.
-    const int64_t target_chunks = (int64_t)device_cus() * 4 * 8 * sc.oversub;
-    const int64_t c_min = sc.min_chunk;
-    // total chunks <= sum(walks)/C + n <= target_chunks + n
-    const int64_t max_chunks = n + target_chunks + 1;
+    const WalkLayout w = walk_layout(n, sc);
+    const int64_t c_min = sc.min_chunk, target_chunks = w.target_chunks, max_chunks = w.max_chunks, L = w.L;
+    const int nb = w.nb;
+    if (w.blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     hipError_t e;
-    // many points: the multi-block plan over nb segments of L points
-    constexpr int64_t kSegPoints = 2048, kMaxSegs = 1024;
-    const bool multi = n > 8 * kSegPoints;
-    const int nb = multi ? (int)min(kMaxSegs, (n + kSegPoints - 1) / kSegPoints) : 0;
-    const int64_t L = multi ? (n + nb - 1) / nb : 0;
-    const size_t bytes = sizeof(int64_t) * (size_t)(n + 1) + 64 + 16 + sizeof(ChunkPartial) * (size_t)max_chunks +
-                         2 * sizeof(int64_t) * (size_t)nb;
-    char *scratch = nullptr;
-    if ((e = hipMallocAsync((void **)&scratch, bytes, s)) != hipSuccess) return e;
+    // scratch: the caller's workspace (at least w.bytes), else stream-ordered
+    char *scratch = ws;
+    if (!ws && (e = hipMallocAsync((void **)&scratch, w.bytes, s)) != hipSuccess) return e;
     int64_t *meta = (int64_t *)scratch;
     int64_t *chunk_off = (int64_t *)(scratch + 64);
     ChunkPartial *part = (ChunkPartial *)(scratch + 64 + sizeof(int64_t) * (size_t)(n + 1));
     if (((uintptr_t)part & 15u) != 0) part = (ChunkPartial *)(((uintptr_t)part + 15u) & ~(uintptr_t)15u);
-    if (multi) {
+    if (w.multi) {
         // segment sums and counts after the partials (the 16 spare bytes
         // cover the partials' alignment)
         int64_t *seg_part = (int64_t *)(part + max_chunks);
@@ -532,62 +574,57 @@ hipError_t run(const Geometry &g, const double *pts, int64_t n, const int64_t *w
         hipLaunchKernelGGL(k_wos_plan, dim3(1), dim3(kPlanThreads), 0, s, walks, n, target_chunks, c_min, chunk_off,
                            meta);
     }
-    const int64_t waves_per_block = kWalkBlock / kWave;
-    const int64_t blocks = (max_chunks + waves_per_block - 1) / waves_per_block;
-    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_wos_walk<KIND, DATA, PREC>), dim3((unsigned)blocks), dim3(kWalkBlock), 0, s, g.dev, pts,
+    hipLaunchKernelGGL((k_wos_walk<KIND, DATA, PREC>), dim3((unsigned)w.blocks), dim3(kWalkBlock), 0, s, g.dev, pts,
                        walks, walk_begin, stream_id, seed, node_seed, chunk_off, meta, n, part);
     hipLaunchKernelGGL((k_wos_finalize<KIND, DATA>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g.dev, pts,
                        walks, n, chunk_off, part, stats, capped);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    return hipFreeAsync(scratch, s);
+    return ws ? hipSuccess : hipFreeAsync(scratch, s);
 }
 
 template <int PREC>
 hipError_t dispatch(const Geometry &g, const double *pts, int64_t n, const int64_t *walks, const int64_t *wb,
                     uint64_t seed, const uint64_t *ns, const uint32_t *sid, double *stats, int64_t *capped,
-                    const Schedule &sc,
-                    hipStream_t s)
+                    const Schedule &sc, char *ws, hipStream_t s)
 {
     const bool src = g.dev.data_kind == DTN_DATA_POINT_SOURCES;
     constexpr int Q = DTN_DATA_HARMONIC_QUADRATIC, P = DTN_DATA_POINT_SOURCES;
     switch (g.dev.kind) {
     case DTN_BALL:
-        return src ? run<DTN_BALL, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
-                   : run<DTN_BALL, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
+        return src ? run<DTN_BALL, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, ws, s)
+                   : run<DTN_BALL, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, ws, s);
     case DTN_BOX:
         if (g.dev.data_kind == DTN_DATA_TABULATED)
-            return run<DTN_BOX, DTN_DATA_TABULATED, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
-        return src ? run<DTN_BOX, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
-                   : run<DTN_BOX, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
+            return run<DTN_BOX, DTN_DATA_TABULATED, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, ws, s);
+        return src ? run<DTN_BOX, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, ws, s)
+                   : run<DTN_BOX, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, ws, s);
     case DTN_HALF_SPACE:
-        return src ? run<DTN_HALF_SPACE, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
-                   : run<DTN_HALF_SPACE, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
+        return src ? run<DTN_HALF_SPACE, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, ws, s)
+                   : run<DTN_HALF_SPACE, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, ws, s);
     case DTN_DISK:
-        return src ? run<DTN_DISK, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
-                   : run<DTN_DISK, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
+        return src ? run<DTN_DISK, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, ws, s)
+                   : run<DTN_DISK, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, ws, s);
     case DTN_BALL_EXTERIOR:
-        return src ? run<DTN_BALL_EXTERIOR, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
-                   : run<DTN_BALL_EXTERIOR, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
+        return src ? run<DTN_BALL_EXTERIOR, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, ws, s)
+                   : run<DTN_BALL_EXTERIOR, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, ws, s);
     default:
         if (!g.dev.cell_mask)
-            return src ? run<kHolesNoGrid, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
-                       : run<kHolesNoGrid, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
-        return src ? run<DTN_BOX_MINUS_BOXES, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s)
-                   : run<DTN_BOX_MINUS_BOXES, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, s);
+            return src ? run<kHolesNoGrid, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, ws, s)
+                       : run<kHolesNoGrid, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, ws, s);
+        return src ? run<DTN_BOX_MINUS_BOXES, P, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, ws, s)
+                   : run<DTN_BOX_MINUS_BOXES, Q, PREC>(g, pts, n, walks, wb, seed, ns, sid, stats, capped, sc, ws, s);
     }
 }
 
 hipError_t walk_all(const Geometry &g, const double *pts, int64_t n, const int64_t *walks, const int64_t *walk_begin,
                     uint64_t seed, const uint64_t *node_seed, const uint32_t *stream_id, int precision,
-                    double *stats, int64_t *capped,
-                    const Schedule &sc, hipStream_t stream)
+                    double *stats, int64_t *capped, const Schedule &sc, hipStream_t stream, char *ws = nullptr)
 {
     return precision == DTN_FP64
-               ? dispatch<DTN_FP64>(g, pts, n, walks, walk_begin, seed, node_seed, stream_id, stats, capped, sc,
+               ? dispatch<DTN_FP64>(g, pts, n, walks, walk_begin, seed, node_seed, stream_id, stats, capped, sc, ws,
                                     stream)
                : dispatch<DTN_FP32_MIXED>(g, pts, n, walks, walk_begin, seed, node_seed, stream_id, stats, capped,
-                                          sc, stream);
+                                          sc, ws, stream);
 }
 
 // ------------------------------------------------- distance (diagnostic)
@@ -684,6 +721,44 @@ __global__ __launch_bounds__(256) void k_merge(const double *__restrict__ ps, co
 }
 
 }  // namespace
+
+// Status of a geometry: snapshot the live bits (or the walk counters) and
+// clear them in one atomic exchange each (work still running on other
+// streams keeps raising them).
+__global__ void k_take_status(DevStatus *st, int counters)
+{
+    if (threadIdx.x != 0) return;
+    if (counters) {
+        st->iters_taken = atomicExch(&st->iters, 0ull);
+        st->visits_taken = atomicExch(&st->visits, 0ull);
+    } else {
+        st->flags_taken = atomicExch(&st->flags, 0u);
+    }
+}
+
+dtn_status take_flags(const Geometry &g, hipStream_t s, uint32_t &out)
+{
+    out = 0;
+    hipLaunchKernelGGL(k_take_status, dim3(1), dim3(kWave), 0, s, g.d_status, 0);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&out, &g.d_status->flags_taken, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_check: ") + hipGetErrorString(e));
+    return DTN_OK;
+}
+
+dtn_status take_counters(const Geometry &g, hipStream_t s, unsigned long long out[2])
+{
+    out[0] = out[1] = 0;
+    hipLaunchKernelGGL(k_take_status, dim3(1), dim3(kWave), 0, s, g.d_status, 1);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, &g.d_status->iters_taken, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_walk_counters: ") + hipGetErrorString(e));
+    return DTN_OK;
+}
 
 dtn_status launch_wos(const Geometry &g, const double *pts, int64_t n, const int64_t *walks,
                       const int64_t *walk_begin, uint64_t seed, const uint32_t *stream_id, int precision,

@@ -123,7 +123,7 @@ def lib():
         L.dtn_patch_solve.argtypes = [vp, vp, C.c_int32, vp, vp, vp]
         L.dtn_potential.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
         L.dtn_patch_solve_second_kind.argtypes = [vp, vp, vp, vp, vp]
-        L.dtn_class_second_kind.argtypes = [C.c_int32] * 4 + [C.POINTER(C.c_double)] * 2
+        L.dtn_class_second_kind.argtypes = [C.c_int32] * 4 + [C.c_double] + [C.POINTER(C.c_double)] * 3
         L.dtn_create_points.argtypes = [vp, C.POINTER(PointDesc), C.c_int64, C.c_int32, C.c_int32, C.c_double,
                                         C.POINTER(vp)]
         L.dtn_destroy_points.argtypes = [vp]
@@ -142,6 +142,9 @@ def lib():
         dp = C.POINTER(C.c_double)
         L.dtn_class_operators.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
                                           dp, dp, dp, dp, dp, dp]
+        L.dtn_check.argtypes = [vp, vp]
+        L.dtn_walk_counters.argtypes = [vp, vp, C.POINTER(C.c_int64)]
+        L.dtn_plan_set_max_sweeps.argtypes = [vp, C.c_int32]
         for f in ("dtn_create_geometry", "dtn_wos_eval", "dtn_wos_adaptive", "dtn_wos_time_schedules",
                   "dtn_boundary_distance", "dtn_server_create", "dtn_server_submit", "dtn_server_wait",
                   "dtn_create_plan", "dtn_patch_nodes",
@@ -149,7 +152,8 @@ def lib():
                   "dtn_create_tree", "dtn_tree_info", "dtn_tree_potential", "dtn_tree_layout",
                   "dtn_class_operators",
                   "dtn_create_points",
-                  "dtn_points_nodes", "dtn_points_neumann"):
+                  "dtn_points_nodes", "dtn_points_neumann", "dtn_check", "dtn_plan_set_max_sweeps",
+                  "dtn_walk_counters"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -247,6 +251,29 @@ def wos_eval(geom, pts, walks, seed, walk_begin=None, stream_id=None, precision=
     return stats, capped
 
 
+def walk_counters(geom):
+    """(wave iterations, hole distances computed by waves) of the walks on a
+    box minus holes since the last call (waits for torch's current stream)."""
+    out = (C.c_int64 * 2)()
+    _check(lib().dtn_walk_counters(geom.handle, _stream(), out), "dtn_walk_counters")
+    return int(out[0]), int(out[1])
+
+
+def check(geom):
+    """Status of the work done on `geom` (waits for torch's current stream,
+    then reads and clears the geometry's status bits): "ok", "maxsteps"
+    (walks ended by the step cap) or "noconv" (an FP32-mixed solve missed its
+    residual bound)."""
+    st = lib().dtn_check(geom.handle, _stream())
+    if st == DTN_OK:
+        return "ok"
+    if st == -6:
+        return "maxsteps"
+    if st == -5:
+        return "noconv"
+    _check(st, "dtn_check")
+
+
 def boundary_distance(geom, pts, precision="fp64", out=None):
     """Distance to the boundary as the walk kernels compute it (device [n])."""
     n = pts.shape[0]
@@ -342,6 +369,10 @@ class Plan:
         if h and _lib is not None:
             _lib.dtn_destroy_plan(h)
             self.handle = None
+
+    def set_max_sweeps(self, n):
+        """Most FP32 solves of the FP32-mixed refinement (default 8)."""
+        _check(lib().dtn_plan_set_max_sweeps(self.handle, int(n)), "dtn_plan_set_max_sweeps")
 
     def nodes(self, out=None, device="cuda"):
         if out is None:
@@ -566,12 +597,13 @@ class Server:
         self.close()
 
 
-def class_second_kind(n_theta, n_phi, n_rings, n_sectors):
-    """Host diagnostic: the second-kind tables of a flat class at h = 1."""
+def class_second_kind(n_theta, n_phi, n_rings, n_sectors, rr=0.0):
+    """Host diagnostic: the second-kind tables of a class at h = 1 (rr = R/h
+    on a sphere, -R/h outside a ball, 0 on a plane): Q2, c2 and M = 1/2 I - D."""
     Np, Nn = n_rings * n_sectors, n_theta * n_phi
-    Q2, c2 = np.empty((Np, Nn)), np.empty(Np)
+    Q2, c2, M = np.empty((Np, Nn)), np.empty(Np), np.empty((Np, Np))
     dp = C.POINTER(C.c_double)
-    _check(lib().dtn_class_second_kind(n_theta, n_phi, n_rings, n_sectors, Q2.ctypes.data_as(dp),
-                                       c2.ctypes.data_as(dp)), "dtn_class_second_kind")
-    return {"Q2": Q2, "c2": c2}
+    _check(lib().dtn_class_second_kind(n_theta, n_phi, n_rings, n_sectors, float(rr), Q2.ctypes.data_as(dp),
+                                       c2.ctypes.data_as(dp), M.ctypes.data_as(dp)), "dtn_class_second_kind")
+    return {"Q2": Q2, "c2": c2, "M": M}
 

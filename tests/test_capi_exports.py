@@ -150,3 +150,99 @@ def test_second_kind_tables_agree_with_oracle(layout):
         pts, W = SK.s_rule(X[i], 1.0, 1e-6)
         wsum = np.sum(W * SK.kernel_s(X[i][None, :], pts, 1.0))
         assert abs(t["c2"][i] - (Q2[i].sum() - wsum)) < 1e-9 * max(1.0, abs(wsum))
+
+
+def test_geometry_step_cap_is_checked_on_the_host():
+    """A walk's step count is 32-bit: caps above 2^32 - 1 (e.g. INT64_MAX for
+    'no cap') are refused before any device work, so the kernels' iteration
+    bound can never be computed from a cap they do not honour."""
+    from paper_1210_1491_amd import dtn
+    L = dtn.lib()
+    for cap in (2 ** 32, 2 ** 63 - 1, -1):
+        d = dtn.GeometryDesc()
+        d.kind, d.data_kind = 0, 0
+        d.ball_r, d.eps, d.max_steps = 1.0, 1e-4, cap
+        h = ctypes.c_void_p()
+        assert L.dtn_create_geometry(ctypes.byref(d), ctypes.byref(h)) == -1, cap
+        assert "max_steps" in L.dtn_last_error().decode()
+        assert not h.value
+
+
+def test_status_entry_points_check_their_arguments_on_the_host():
+    from paper_1210_1491_amd import dtn
+    L = dtn.lib()
+    assert L.dtn_check(None, None) == -1
+    assert L.dtn_plan_set_max_sweeps(None, 4) == -1
+    assert "NULL" in L.dtn_last_error().decode()
+
+
+def _lu32(K):
+    """FP32 LU with partial pivoting (row swaps), as a plain loop."""
+    A = K.astype(np.float32).copy()
+    piv = []
+    for k in range(A.shape[0]):
+        p = k + int(np.argmax(np.abs(A[k:, k])))
+        piv.append(p)
+        A[[k, p]] = A[[p, k]]
+        A[k + 1:, k] /= A[k, k]
+        A[k + 1:, k + 1:] -= np.outer(A[k + 1:, k], A[k, k + 1:]).astype(np.float32)
+    return A, piv
+
+
+def _solve32(A, piv, r):
+    f = r.astype(np.float32)
+    for k, p in enumerate(piv):
+        f[[k, p]] = f[[p, k]]
+    n = len(f)
+    for i in range(n):
+        f[i] -= np.float32(np.dot(A[i, :i], f[:i]))
+    for i in range(n - 1, -1, -1):
+        f[i] = (f[i] - np.float32(np.dot(A[i, i + 1:], f[i + 1:]))) / A[i, i]
+    return f.astype(np.float64)
+
+
+@pytest.mark.parametrize("layout", [(4, 8, 2, 4, 0.0), (8, 16, 4, 8, 0.0), (16, 32, 4, 16, 0.0),
+                                    (16, 32, 8, 16, 0.0), (8, 16, 4, 8, 5.0)])
+def test_refinement_bound_is_met_after_three_sweeps(layout):
+    """The FP32-mixed solve stops once |r|_inf <= P 2^-53 (|K|_inf |y|_inf +
+    |b|_inf).  With the library's own class matrices, FP32 factors and an
+    FP64 residual, that bound is out of reach after one FP32 solve (so a
+    limit of one sweep must report no convergence) and met, with margin,
+    from the third on: the default limit of 8 sweeps is never the one that
+    stops a supported layout."""
+    from paper_1210_1491_amd import dtn
+    K = dtn.class_operators(*layout[:4], rr=layout[4])["K"]
+    P = K.shape[0]
+    A, piv = _lu32(K)
+    kinf = np.abs(K).sum(1).max()
+    rng = np.random.default_rng(7)
+    for _ in range(6):
+        b = rng.standard_normal(P) * 10.0 ** rng.uniform(-3, 3)
+        y, r, ratio = np.zeros(P), b.copy(), []
+        for _ in range(4):
+            y = y + _solve32(A, piv, r)
+            r = b - K @ y
+            ratio.append(np.abs(r).max() / (P * 2.0 ** -53 * (kinf * np.abs(y).max() + np.abs(b).max())))
+        assert ratio[0] > 1e3
+        assert ratio[2] < 0.5 and ratio[3] < 0.5, ratio
+
+
+@pytest.mark.parametrize("layout", [(8, 16, 4, 8, 5.0), (16, 32, 4, 16, -3.0)])
+def test_curved_second_kind_tables_agree_with_oracle(layout):
+    """The library's second-kind tables of a class on a sphere (Gamma
+    operator with -d2G_B/dn_x dn_y, 1/2 I - D, and the regularised S rule's
+    constant term) against the oracle's independent functions."""
+    from oracle import patch as OP
+    from oracle import second_kind as SK
+    from paper_1210_1491_amd import dtn
+    nt, nf, nr, ns, rr = layout
+    t = dtn.class_second_kind(nt, nf, nr, ns, rr)
+    Q2 = SK.gamma_operator_2c(1.0, rr, nt, nf, nr, ns)
+    M = 0.5 * np.eye(nr * ns) - SK.adjoint_double_layer(1.0, rr, nr, ns)
+    assert np.max(np.abs(t["Q2"] - Q2)) < 1e-10 * np.max(np.abs(Q2))
+    assert np.max(np.abs(t["M"] - M)) < 1e-10
+    _, X, N, _ = OP.panels(1.0, rr, nr, ns)
+    for i in (0, len(X) // 2, len(X) - 1):
+        pts, nrm, W = SK.s_rule_c(X[i], 1.0, rr, 1e-6)
+        wsum = np.sum(W * SK.d2green(X[i][None, :], N[i][None, :], pts, nrm, 1.0))
+        assert abs(t["c2"][i] - (Q2[i].sum() - wsum)) < 1e-9 * max(1.0, abs(wsum))

@@ -94,13 +94,38 @@ def test_adaptive_equals_plain_walks_over_the_budget(box_holes):
         np.testing.assert_allclose(a["m2"], st[:, 2], rtol=1e-9, atol=1e-13)
 
 
+def _gpu_plain(desc, pts, walks, seed, precision):
+    dtn = _dtn()
+    g = dtn.Geometry(desc)
+    P = torch.tensor(np.asarray(pts, np.float64).reshape(-1, 3), device="cuda:0")
+    W = torch.tensor(np.asarray(walks, np.int64), device="cuda:0")
+    print(f"[gpu] plain walks n={len(P)} seed={seed} precision={precision}", flush=True)
+    stats, capped = dtn.wos_eval(g, P, W, seed, precision=precision)
+    torch.cuda.synchronize()
+    st = stats.cpu().numpy()
+    return {"count": st[:, 0], "mean": st[:, 1], "m2": st[:, 2], "steps": st[:, 3].astype(np.int64),
+            "capped": capped.cpu().numpy()}
+
+
 def test_adaptive_fp32_mixed_statistical(box_holes):
+    """FP32-mixed adaptive walks against the oracle's FP64 adaptive walks.
+
+    The two sides decide their budgets from different pilots (FP32 against
+    FP64 directions), so their walk sets differ; the 4-SE bar is applied to
+    the same walk set: the GPU's FP32-mixed walks over the oracle's own
+    budgets (walks [0, budget) per node, the walks the adaptive path runs;
+    that the adaptive path equals plain walks over its budget is tested
+    above).  The budgets themselves are compared separately."""
     gd, pd = box_holes
     pts = _nodes_of(gd, pd, I.box_holes_sample(pd, per_class=1, seed=7))[::3]
     budget = (500, 500, 50_000, 0.01)
     gpu = _gpu_adaptive(gd, pts, budget, seed=8, precision="fp32")
     ora = OW.wos_adaptive(OW.Geometry(gd), pts, *budget, seed=8)
-    assert np.all(_z(gpu, ora) < 4.5)
+    same = _gpu_plain(gd, pts, ora["walks_used"], 8, "fp32")
+    np.testing.assert_array_equal(same["count"], ora["walks_used"])
+    z = _z(same, ora)
+    print(f"[gpu] fp32 vs oracle on the oracle's budgets: max z {z.max():.2f}", flush=True)
+    assert np.all(z < 4.0), z.max()
     # The FP32 walks follow the FP64 ones closely (same counters), so most
     # budgets agree; the pilot variance is heavy-tailed (scores near a source
     # are large), so a walk that ends differently can move a budget a lot.

@@ -1,0 +1,122 @@
+"""Statuses of the C-ABI that are raised by device work (read by dtn_check),
+and the tiling check of the potential.
+
+* Walks ended by the step cap (Sec. 2: the epsilon-shell walk is run with a
+  cap on its steps here) are counted per point and raise DTN_E_MAXSTEPS.
+* The FP32-mixed collocation solve (Sec. 5.2's solve, with FP32 factors and
+  FP64 residual refinement) stops on a norm-wise backward-error bound; a
+  sweep limit too small to reach it raises DTN_E_NOCONV.
+* The potential of eq. bw03 is a surface integral over the whole boundary:
+  plans whose tiles cover part of it, or cover some of it twice, are
+  rejected.
+"""
+import numpy as np
+import pytest
+import torch
+
+import dtn_inputs as I
+from oracle import patch as OP
+from oracle import wos as OW
+
+pytestmark = pytest.mark.gpu
+
+
+def _dtn():
+    from paper_1210_1491_amd import dtn
+    return dtn
+
+
+def test_step_cap_raises_maxsteps_and_check_clears_it():
+    dtn = _dtn()
+    dev = torch.device("cuda:0")
+    pts = torch.tensor(I.interior_points_box(64, 9), device=dev)
+    w = torch.full((64,), 300, dtype=torch.int64, device=dev)
+    print("[gpu] status: step cap 3", flush=True)
+    capped_g = dtn.Geometry(I.geometry_cube_sources(max_steps=3))
+    assert dtn.check(capped_g) == "ok"
+    _, capped = dtn.wos_eval(capped_g, pts, w, 2)
+    assert dtn.check(capped_g) == "maxsteps"
+    assert int(capped.sum()) > 0
+    assert dtn.check(capped_g) == "ok"  # read and cleared
+    # the adaptive path reports through the same bit
+    st, used, cp = dtn.wos_adaptive(capped_g, pts, 2, 50, 50, 200, 1e-3)
+    assert dtn.check(capped_g) == "maxsteps" and int(cp.sum()) > 0
+    print("[gpu] status: no cap reached", flush=True)
+    free_g = dtn.Geometry(I.geometry_cube_sources())
+    _, capped = dtn.wos_eval(free_g, pts, w, 2)
+    assert dtn.check(free_g) == "ok" and int(capped.sum()) == 0
+    # bits belong to their geometry
+    dtn.wos_eval(capped_g, pts, w, 3)
+    assert dtn.check(free_g) == "ok"
+    assert dtn.check(capped_g) == "maxsteps"
+
+
+def _exact_stats(gd, pd):
+    og = OW.Geometry(gd)
+    rows = []
+    for p in OP.patches_from_desc(pd, gd):
+        nodes, _ = OP.nodes_global(p)
+        u = og.phi(nodes)
+        rows.append(np.column_stack([np.full_like(u, 1e4), u, np.full_like(u, 1e-2), np.zeros_like(u)]))
+    return torch.tensor(np.concatenate(rows), device="cuda")
+
+
+@pytest.mark.parametrize("which", ["ball", "cube"])
+def test_refinement_limit_raises_noconv(which):
+    dtn = _dtn()
+    if which == "ball":
+        gd, pd = I.geometry_ball_quadratic(), I.patches_ball_pole()
+    else:
+        gd, pd = I.geometry_cube_sources(), I.subset_patches(I.patches_cube_tiles(), I.cube_tile_subset())
+    g = dtn.Geometry(gd)
+    plan = dtn.Plan(g, pd)
+    st = _exact_stats(gd, pd)
+    print(f"[gpu] status: refinement {which}", flush=True)
+    ref, _ = plan.solve(st, precision="fp64")
+    sig, _ = plan.solve(st, precision="fp32")
+    assert dtn.check(g) == "ok"
+    scale = float(ref.abs().max())
+    assert float((sig - ref).abs().max()) < 1e-12 * scale
+    for sweeps in (0, 1):
+        plan.set_max_sweeps(sweeps)
+        plan.solve(st, precision="fp32")
+        assert dtn.check(g) == "noconv", sweeps
+        plan.solve(st, precision="fp64")  # the FP64 solve does not refine
+        assert dtn.check(g) == "ok"
+    plan.set_max_sweeps(3)
+    sig3, _ = plan.solve(st, precision="fp32")
+    assert dtn.check(g) == "ok"
+    assert float((sig3 - ref).abs().max()) < 1e-12 * scale
+    with pytest.raises(dtn.DtnError):
+        plan.set_max_sweeps(65)
+
+
+def test_potential_rejects_partial_and_overlapping_tilings():
+    dtn = _dtn()
+    gd = I.geometry_cube_sources()
+    g = dtn.Geometry(gd)
+    full = I.patches_cube_tiles(m=4, n_theta=8, n_phi=16, n_rings=4, n_sectors=8)
+    n = len(full["h"])
+    tg = torch.tensor(I.cube_targets(8, seed=4), device="cuda")
+    print("[gpu] status: tilings", flush=True)
+    plan = dtn.Plan(g, full)
+    u = plan.potential(torch.zeros(plan.num_panels, dtype=torch.float64, device="cuda"), tg)
+    torch.cuda.synchronize()
+    assert torch.isfinite(u).all()
+    cases = {
+        "one face missing": np.arange(n - 16),
+        "sixteen-tile sample": np.unique(I.cube_tile_subset(m=4, seed=16)),
+        "a tile twice": np.concatenate([np.arange(n), [5]]),
+    }
+    for name, idx in cases.items():
+        p = dtn.Plan(g, I.subset_patches(full, idx))
+        with pytest.raises(dtn.DtnError) as e:
+            p.potential(torch.zeros(p.num_panels, dtype=torch.float64, device="cuda"), tg)
+        assert e.value.status == -4, name
+    # a tiling of the same area with one tile moved onto another
+    moved = {k: v.copy() for k, v in full.items()}
+    moved["c"][3] = moved["c"][2]
+    p = dtn.Plan(g, moved)
+    with pytest.raises(dtn.DtnError) as e:
+        p.potential(torch.zeros(p.num_panels, dtype=torch.float64, device="cuda"), tg)
+    assert e.value.status == -4
