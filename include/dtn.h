@@ -189,6 +189,24 @@ dtn_status dtn_wos_eval(dtn_geometry g, const double *pts, int64_t n, const int6
                         const int64_t *walk_begin, uint64_t seed, const uint32_t *stream_id,
                         int32_t precision, double *stats, int64_t *capped, void *stream);
 
+/* dtn_wos_eval for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, same kernels, same default schedule and the same results
+ * bit for bit, but the walk kernels' scratch (chunk offsets, chunk partials,
+ * plan segments) lives in a static workspace of the library, 64 MiB per
+ * device, held from the first call on a device until the process ends.  The
+ * call allocates nothing (no hipMalloc, hipMallocAsync or hipFree); the
+ * caller still owns every input and output.  The workspace is shared by every
+ * call on the device: calls whose work overlaps on one device (two streams,
+ * or two threads) race on it and must be serialised by the caller.  Nothing
+ * in it needs to start at zero.
+ * Errors: DTN_E_ARG as dtn_wos_eval, and when n needs more workspace than
+ * 64 MiB (on a 256-CU MI355X: n > 1,170,119 points); DTN_E_DEVICE when the
+ * workspace's address cannot be taken. */
+dtn_status dtn_wos_eval_noalloc(dtn_geometry g, const double *pts, int64_t n, const int64_t *walks,
+                                const int64_t *walk_begin, uint64_t seed, const uint32_t *stream_id,
+                                int32_t precision, double *stats, int64_t *capped, void *stream);
+
 /* Distance from n points inside Omega to its boundary, computed as the walk
  * kernels of `precision` compute it (the radius of the largest ball of a walk
  * step, Sec. 2): in FP64 for both; the FP32-mixed walks take the distance to

@@ -552,6 +552,25 @@ dtn_status dtn_wos_eval(dtn_geometry g, const double *pts, int64_t n, const int6
     }
 }
 
+dtn_status dtn_wos_eval_noalloc(dtn_geometry g, const double *pts, int64_t n, const int64_t *walks,
+                                const int64_t *walk_begin, uint64_t seed, const uint32_t *stream_id,
+                                int32_t precision, double *stats, int64_t *capped, void *stream)
+{
+    try {
+        if (!g) return fail(DTN_E_ARG, "dtn_wos_eval_noalloc: NULL geometry");
+        if (n < 0) return fail(DTN_E_ARG, "dtn_wos_eval_noalloc: n < 0");
+        if (precision != DTN_FP64 && precision != DTN_FP32_MIXED)
+            return fail(DTN_E_ARG, "dtn_wos_eval_noalloc: unknown precision");
+        if (n > 0 && (!pts || !walks || !stats)) return fail(DTN_E_ARG, "dtn_wos_eval_noalloc: NULL array");
+        if (!stream_id && n > ((int64_t)1 << 32))
+            return fail(DTN_E_ARG, "dtn_wos_eval_noalloc: more than 2^32 points need explicit stream ids");
+        return launch_wos_noalloc(g->g, pts, n, walks, walk_begin, seed, stream_id, precision, stats, capped,
+                                  (hipStream_t)stream);
+    } catch (...) {
+        return fail(DTN_E_DEVICE, "dtn_wos_eval_noalloc: exception");
+    }
+}
+
 dtn_status dtn_boundary_distance(dtn_geometry g, const double *pts, int64_t n, int32_t precision, double *dist,
                                  void *stream)
 {

@@ -156,6 +156,13 @@ dtn_status launch_wos(const Geometry &g, const double *pts, int64_t n, const int
                       int precision, double *stats, int64_t *capped, const Schedule &sc, hipStream_t stream);
 dtn_status launch_distance(const Geometry &g, const double *pts, int64_t n, int precision, double *dist,
                            hipStream_t stream);
+// launch_wos with the default schedule, its scratch in the library's static
+// per-device workspace (no allocation); DTN_E_ARG when n needs more.
+dtn_status launch_wos_noalloc(const Geometry &g, const double *pts, int64_t n, const int64_t *walks,
+                              const int64_t *walk_begin, uint64_t seed, const uint32_t *stream_id, int precision,
+                              double *stats, int64_t *capped, hipStream_t stream);
+size_t noalloc_workspace_bytes();
+size_t noalloc_bytes(int64_t n);  // workspace bytes of a launch over n points (default schedule)
 // node_seed: per-point Philox keys (device [n]) or NULL for `seed` everywhere.
 dtn_status launch_wos_adaptive(const Geometry &g, const double *pts, int64_t n, const Adaptive &a, uint64_t seed,
                                const uint64_t *node_seed, const uint32_t *stream_id, int precision, double *stats,

@@ -38,6 +38,8 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <map>
+#include <mutex>
 #include <string>
 
 #include "dtn_device.h"
@@ -768,6 +770,64 @@ dtn_status launch_wos(const Geometry &g, const double *pts, int64_t n, const int
     hipError_t e =
         walk_all(g, pts, n, walks, walk_begin, seed, nullptr, stream_id, precision, stats, capped, sc, stream);
     if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_wos_eval: ") + hipGetErrorString(e));
+    return DTN_OK;
+}
+
+// Workspace of the walk launches of dtn_wos_eval_noalloc: one copy per
+// device, held until the process ends.  Host code never passes the array's
+// name to a kernel (on the host it is a stand-in, not a device address): it
+// takes the device's address once, with that device current, and passes
+// that.  Nothing in it needs clearing: every word a launch reads (chunk
+// offsets, meta, partials, segment sums) is written earlier in the same
+// launch sequence.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, char *> g_scratch_ptr;  // device -> address of its `scratch`
+
+dtn_status device_scratch(char **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_wos_eval_noalloc: ") + hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(DTN_E_DEVICE, std::string("dtn_wos_eval_noalloc: workspace address: ") +
+                                          hipGetErrorString(e));
+        it = g_scratch_ptr.emplace(dev, (char *)ptr).first;
+    }
+    *out = it->second;
+    return DTN_OK;
+}
+
+}  // namespace
+
+size_t noalloc_workspace_bytes() { return kNoAllocBytes; }
+size_t noalloc_bytes(int64_t n) { return walk_layout(n, Schedule{}).bytes; }
+
+dtn_status launch_wos_noalloc(const Geometry &g, const double *pts, int64_t n, const int64_t *walks,
+                              const int64_t *walk_begin, uint64_t seed, const uint32_t *stream_id, int precision,
+                              double *stats, int64_t *capped, hipStream_t stream)
+{
+    if (n == 0) return DTN_OK;
+    const Schedule sc;
+    const size_t need = walk_layout(n, sc).bytes;
+    if (need > kNoAllocBytes)
+        return fail(DTN_E_ARG, "dtn_wos_eval_noalloc: " + std::to_string(n) + " points need " + std::to_string(need) +
+                                   " bytes of workspace, more than its " + std::to_string(kNoAllocBytes));
+    char *ptr = nullptr;
+    const dtn_status st = device_scratch(&ptr);
+    if (st != DTN_OK) return st;
+    const hipError_t e =
+        walk_all(g, pts, n, walks, walk_begin, seed, nullptr, stream_id, precision, stats, capped, sc, stream, ptr);
+    if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("dtn_wos_eval_noalloc: ") + hipGetErrorString(e));
     return DTN_OK;
 }
 

@@ -144,6 +144,7 @@ def lib():
                                           dp, dp, dp, dp, dp, dp]
         L.dtn_check.argtypes = [vp, vp]
         L.dtn_walk_counters.argtypes = [vp, vp, C.POINTER(C.c_int64)]
+        L.dtn_wos_eval_noalloc.argtypes = [vp, vp, C.c_int64, vp, vp, C.c_uint64, vp, C.c_int32, vp, vp, vp]
         L.dtn_plan_set_max_sweeps.argtypes = [vp, C.c_int32]
         for f in ("dtn_create_geometry", "dtn_wos_eval", "dtn_wos_adaptive", "dtn_wos_time_schedules",
                   "dtn_boundary_distance", "dtn_server_create", "dtn_server_submit", "dtn_server_wait",
@@ -152,8 +153,8 @@ def lib():
                   "dtn_create_tree", "dtn_tree_info", "dtn_tree_potential", "dtn_tree_layout",
                   "dtn_class_operators",
                   "dtn_create_points",
-                  "dtn_points_nodes", "dtn_points_neumann", "dtn_check", "dtn_plan_set_max_sweeps",
-                  "dtn_walk_counters"):
+                  "dtn_points_nodes", "dtn_points_neumann", "dtn_check", "dtn_plan_set_max_sweeps", "dtn_walk_counters",
+                  "dtn_wos_eval_noalloc"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -248,6 +249,24 @@ def wos_eval(geom, pts, walks, seed, walk_begin=None, stream_id=None, precision=
     _check(lib().dtn_wos_eval(geom.handle, _ptr(pts), n, _ptr(walks), _ptr(walk_begin),
                               C.c_uint64(int(seed) & (2 ** 64 - 1)), _ptr(stream_id), PRECISION[precision],
                               _ptr(stats), _ptr(capped), _stream()), "dtn_wos_eval")
+    return stats, capped
+
+
+def wos_eval_noalloc(geom, pts, walks, seed, stats, capped, walk_begin=None, stream_id=None, precision="fp64"):
+    """wos_eval with the library's static workspace: allocates nothing, so the
+    caller passes the outputs (stats [n,4] f64, capped [n] int64)."""
+    n = pts.shape[0]
+    _dev_tensor(pts, torch.float64, (n, 3))
+    _dev_tensor(walks, torch.int64, (n,))
+    _dev_tensor(stats, torch.float64, (n, 4))
+    _dev_tensor(capped, torch.int64, (n,))
+    if walk_begin is not None:
+        _dev_tensor(walk_begin, torch.int64, (n,))
+    if stream_id is not None:
+        _dev_tensor(stream_id, torch.int32, (n,))
+    _check(lib().dtn_wos_eval_noalloc(geom.handle, _ptr(pts), n, _ptr(walks), _ptr(walk_begin),
+                                      C.c_uint64(int(seed) & (2 ** 64 - 1)), _ptr(stream_id), PRECISION[precision],
+                                      _ptr(stats), _ptr(capped), _stream()), "dtn_wos_eval_noalloc")
     return stats, capped
 
 
