@@ -1228,9 +1228,9 @@ def main():
         other = "fp32" if precision == "fp64" else "fp64"
         n2, s2 = torch.empty_like(neumann), torch.empty_like(neumann_se)
         plan.solve(stats, precision=other, neumann=n2, neumann_se=s2)
-        sig2 = n2.cpu().numpy()
-        solves = {precision: rel_l2(sig, ex, area, trusted), other: rel_l2(sig2, ex, area, trusted),
-                  "max_abs_diff_fp32_vs_fp64_solve": float(np.max(np.abs(sig2 - sig)))}
+        sig_other = n2.cpu().numpy()
+        solves = {precision: rel_l2(sig, ex, area, trusted), other: rel_l2(sig_other, ex, area, trusted),
+                  "max_abs_diff_fp32_vs_fp64_solve": float(np.max(np.abs(sig_other - sig)))}
         # the second-kind equation (flat patches: sigma = 2b, no solve) on the
         # timed run's statistics, timed on the stream beside a first-kind solve
         second = None
@@ -1254,7 +1254,7 @@ def main():
                       "propagated_noise_rel_l2": float(np.sqrt(np.sum(area[trusted] * sse2[trusted] ** 2) / den)),
                       "first_kind_noise_rel_l2": float(np.sqrt(np.sum(area[trusted] * sse1[trusted] ** 2) / den)),
                       "solve_ms": e0.elapsed_time(e1), "first_kind_solve_ms": f0.elapsed_time(f1)}
-        return {"sigma": {precision: sig, other: sig2}, "second_kind": second, "ms_per_step": ms,
+        return {"sigma": {precision: sig, other: sig_other}, "second_kind": second, "ms_per_step": ms,
                 "rel_l2_by_solve_precision": solves, "walks_per_s": walks_n / (ms / 1e3), "patches_per_s": n_patches / (ms / 1e3),
                 "neumann_rel_l2_vs_exact": rel_l2(sig, ex, area, trusted),
                 "neumann_se_median": float(np.median(neumann_se.cpu().numpy())),

@@ -397,7 +397,10 @@ dtn_status dtn_potential(dtn_plan p, const double *neumann, const double *target
  * The tree is built on the host from the plan's tile geometry and kept with
  * the handle; the proxies are rebuilt from the Neumann data on every call.
  * Targets are evaluated in Morton order of their position (sorted on the
- * device), so a wave's 64 targets share most of their traversal.
+ * device), so a wave's 64 targets share most of their traversal; a node that
+ * at most 32 of a wave's targets take is evaluated by the whole wave
+ * repacked, 64/k lanes per taking target, so a target's sum depends on its
+ * wave companions only through rounding.
  * Create: degree in [1, 8], leaf_size in [8, 4096].  Errors: DTN_E_ARG,
  * DTN_E_UNSUPPORTED (a plan dtn_potential rejects), DTN_E_OOM.
  * The tree refers to the plan: destroy it before the plan. */

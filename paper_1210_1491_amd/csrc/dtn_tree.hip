@@ -330,6 +330,63 @@ __global__ __launch_bounds__(256) void k_tree_keys(const double *__restrict__ ta
 
 enum : int { kNone = 0, kTakeProxy = 1, kTakeDirect = 2, kOpen = 3 };
 
+__device__ __forceinline__ double proxy_term(double x, double y, double z, const Proxy &p)
+{
+    const double ex = x - p.x, ey = y - p.y, ez = z - p.z;
+    const double ir = rsqrt(ex * ex + ey * ey + ez * ez);
+    return p.q * ir + (p.px * ex + p.py * ey + p.pz * ez) * (ir * ir * ir);
+}
+
+__device__ __forceinline__ double source_term(double x, double y, double z, const TileSource &s)
+{
+    const double ex = x - s.x, ey = y - s.y, ez = z - s.z;
+    const double ir = rsqrt(ex * ex + ey * ey + ez * ez);
+    return s.ws * ir - s.wf * (ex * s.nx + ey * s.ny + ez * s.nz) * (ir * ir * ir);
+}
+
+__device__ __forceinline__ void tree_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Entries [base, base + count) of a node taken by the k <= 32 lanes of
+// `mask`: the wave is repacked so that g = 64 / k lanes work on each taking
+// lane's target (lane l on the target of rank l / g, entries l mod g, l mod g
+// + g, ...), each reading its own entries; the g partial sums of a target
+// are then added, in lane order, to its lane's sum.  With k > 32 the whole
+// wave walks the entries together instead (wave-uniform loads).
+template <class Entry, class Term>
+__device__ __forceinline__ void packed_sum(uint64_t mask, int32_t base, int32_t count, const Entry *__restrict__ E,
+                                           double x, double y, double z, double &acc, Term term, double *lx,
+                                           double *ly, double *lz, double *part)
+{
+    const int lane = __lane_id();
+    const int k = __popcll(mask), g = 64 / k;
+    const bool mine = (mask >> lane) & 1ull;
+    const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+    if (mine) {
+        lx[rank] = x;
+        ly[rank] = y;
+        lz[rank] = z;
+    }
+    tree_wave_sync();
+    const int t = lane / g, sub = lane - t * g;
+    double a = 0.0;
+    if (t < k) {
+        const double px = lx[t], py = ly[t], pz = lz[t];
+        for (int32_t e = sub; e < count; e += g) a += term(px, py, pz, E[base + e]);
+    }
+    part[lane] = a;
+    tree_wave_sync();
+    if (mine) {
+        double sum = 0.0;
+        for (int q = 0; q < g; ++q) sum += part[rank * g + q];
+        acc += sum;
+    }
+    tree_wave_sync();
+}
+
 __global__ __launch_bounds__(64) void k_tree_eval(const TreeNode *__restrict__ nodes, int32_t n_nodes,
                                                   const Proxy *__restrict__ prox,
                                                   const TileSource *__restrict__ src,
@@ -337,6 +394,7 @@ __global__ __launch_bounds__(64) void k_tree_eval(const TreeNode *__restrict__ n
                                                   const uint32_t *__restrict__ order, int64_t m, double theta2,
                                                   double *__restrict__ u, int64_t *__restrict__ counts)
 {
+    __shared__ double lx[64], ly[64], lz[64], part[64];
     const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
     const bool valid = t < m;
     const int64_t id = valid ? (int64_t)order[t] : 0;
@@ -350,6 +408,8 @@ __global__ __launch_bounds__(64) void k_tree_eval(const TreeNode *__restrict__ n
     double acc = 0.0;
     int64_t n_prox = 0, n_dir = 0;
     int32_t j = 0;
+    const auto pterm = [](double a, double b, double c, const Proxy &p) { return proxy_term(a, b, c, p); };
+    const auto sterm = [](double a, double b, double c, const TileSource &q) { return source_term(a, b, c, q); };
     while (j < n_nodes) {
         const TreeNode &nd = nodes[j];
         const double dx = x - nd.c[0], dy = y - nd.c[1], dz = z - nd.c[2];
@@ -357,25 +417,26 @@ __global__ __launch_bounds__(64) void k_tree_eval(const TreeNode *__restrict__ n
         int act = kNone;
         if (j >= done_below)
             act = nd.r2 < theta2 * R2 ? (nd.proxy >= 0 ? kTakeProxy : kTakeDirect) : (nd.leaf ? kTakeDirect : kOpen);
-        if (__any(act == kTakeProxy)) {
-            for (int32_t k = nd.proxy; k < nd.proxy + nd.n_proxy; ++k) {
-                const Proxy &p = prox[k];
-                if (act == kTakeProxy) {
-                    const double ex = x - p.x, ey = y - p.y, ez = z - p.z;
-                    const double ir = rsqrt(ex * ex + ey * ey + ez * ez);
-                    acc += p.q * ir + (p.px * ex + p.py * ey + p.pz * ez) * (ir * ir * ir);
+        const uint64_t mp = __ballot(act == kTakeProxy), md = __ballot(act == kTakeDirect);
+        if (mp) {
+            if (__popcll(mp) > 32) {
+                for (int32_t k = nd.proxy; k < nd.proxy + nd.n_proxy; ++k) {
+                    const Proxy &p = prox[k];
+                    if (act == kTakeProxy) acc += proxy_term(x, y, z, p);
                 }
+            } else {
+                packed_sum(mp, nd.proxy, nd.n_proxy, prox, x, y, z, acc, pterm, lx, ly, lz, part);
             }
             if (act == kTakeProxy) n_prox += nd.n_proxy;
         }
-        if (__any(act == kTakeDirect)) {
-            for (int32_t k = nd.b; k < nd.e; ++k) {
-                const TileSource &s = src[k];
-                if (act == kTakeDirect) {
-                    const double ex = x - s.x, ey = y - s.y, ez = z - s.z;
-                    const double ir = rsqrt(ex * ex + ey * ey + ez * ez);
-                    acc += s.ws * ir - s.wf * (ex * s.nx + ey * s.ny + ez * s.nz) * (ir * ir * ir);
+        if (md) {
+            if (__popcll(md) > 32) {
+                for (int32_t k = nd.b; k < nd.e; ++k) {
+                    const TileSource &q = src[k];
+                    if (act == kTakeDirect) acc += source_term(x, y, z, q);
                 }
+            } else {
+                packed_sum(md, nd.b, nd.e - nd.b, src, x, y, z, acc, sterm, lx, ly, lz, part);
             }
             if (act == kTakeDirect) n_dir += nd.e - nd.b;
         }
