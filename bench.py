@@ -350,7 +350,6 @@ def box_holes(precision, steps, with_cpu=True, se_target=None, tune=True, with_f
                          walks_used=used, capped=capped)
         plan.solve(stats, precision=precision, neumann=neu, neumann_se=nse)
     torch.cuda.synchronize()
-    dtn.walk_counters(g)  # clear: count the timed steps only
     times = []
     for _ in range(steps):
         torch.cuda.synchronize()
@@ -359,7 +358,15 @@ def box_holes(precision, steps, with_cpu=True, se_target=None, tune=True, with_f
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         print(f"[bench] box_holes step {times[-1]:.2f} s", file=sys.stderr, flush=True)
-    iters, visits = dtn.walk_counters(g)
+    # one more step, untimed and eager, with the walk counters on (their
+    # atomics are kept out of the timed steps): holes per wave iteration.
+    # Same seed and budgets, so it walks exactly the timed steps' walks
+    dtn.walk_counters(g, enable=True)
+    dtn.wos_adaptive(g, nodes, cfg["seed"], *budget, precision=precision, schedule=sched, stats=torch.empty_like(stats),
+                     walks_used=torch.empty_like(used), capped=torch.empty_like(capped))
+    iters, visits = dtn.walk_counters(g, enable=False)
+    print(f"[bench] box_holes counted step: {visits / max(iters, 1):.3f} holes per wave iteration",
+          file=sys.stderr, flush=True)
     st = stats.cpu().numpy()
     u = used.cpu().numpy()
     se = np.sqrt(st[:, 2] / np.maximum(st[:, 0] - 1, 1) / st[:, 0])
@@ -381,13 +388,15 @@ def box_holes(precision, steps, with_cpu=True, se_target=None, tune=True, with_f
     # planning kernels are under 0.1 % of it, counted in the time)
     holes_per_iter = visits / max(iters, 1)
     steps_n, walks_n = float(st[:, 3].sum()), float(u.sum())
+    n_counted = 1
     slots_step = HOLES_SLOTS_PER_STEP[precision] + holes_per_iter * HOLE_SLOTS
     slots_walk = HOLES_SLOTS_PER_WALK + holes_per_iter * HOLE_SLOTS
     achieved = (slots_step * steps_n + slots_walk * walks_n) / sec
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK / 1e12, "unit": "T lane-op slots/s",
             "frac": achieved / ALU_PEAK, "traffic": None, "slots_per_step": slots_step, "slots_per_walk": slots_walk,
-            "holes_per_wave_iteration": holes_per_iter, "wave_iterations_per_step": iters / max(steps, 1),
-            "walking_lanes_per_wave_iteration": steps_n * steps / max(iters, 1)}
+            "holes_per_wave_iteration": holes_per_iter, "wave_iterations_per_step": iters / n_counted,
+            "walking_lanes_per_wave_iteration": steps_n * n_counted / max(iters, 1),
+            "counted": "one extra untimed step with the walk counters on"}
     fp64 = None
     if with_fp64:
         stats64, used64 = torch.empty_like(stats), torch.empty_like(used)

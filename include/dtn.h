@@ -156,7 +156,10 @@ typedef struct {
 /* Message of the last failing call on this thread ("" if none). */
 const char *dtn_last_error(void);
 
-/* Library version string. */
+/* Library version string.  Its last word is the first 16 hex digits of the
+ * SHA-256 of the dtn.h the library was built against (a binding compares it
+ * with the header it follows before it calls anything else).  Static
+ * storage, never NULL. */
 const char *dtn_version(void);
 
 /* Create / destroy a geometry.  Uploads the boundary description and data to
@@ -307,14 +310,20 @@ dtn_status dtn_plan_set_max_sweeps(dtn_plan p, int32_t max_sweeps);
 dtn_status dtn_check(dtn_geometry g, void *stream);
 
 /* Work counters of the walks on a box minus holes (diagnostic, for the
- * roofline of the walk kernel): waits for the work enqueued on `stream`,
- * then reads and clears, over all completed walk launches on this geometry,
+ * roofline of the walk kernel).  Waits for the work enqueued on `stream`,
+ * reads and clears the counters into out (if not NULL), then switches
+ * counting on (enable = 1) or off (0, the default) for walk launches
+ * enqueued on this geometry afterwards.  While counting is on, each chunk of
+ * walks adds, with two device-wide atomics (a few per cent of the walk
+ * time on the box-with-holes workload),
  *   out[0]  wave iterations (each computes one distance per lane of its wave)
  *   out[1]  hole distances computed per wave: the sum over wave iterations
  *           of the holes listed for the cells of the wave's walking lanes
  *           (every hole for more than 32 holes).
- * Zero for other domains.  Errors: DTN_E_ARG (NULL), DTN_E_DEVICE. */
-dtn_status dtn_walk_counters(dtn_geometry g, void *stream, int64_t out[2]);
+ * Zero for other domains.  Not while another thread enqueues walks on the
+ * geometry.  Errors: DTN_E_ARG (NULL geometry, enable not 0 or 1),
+ * DTN_E_DEVICE. */
+dtn_status dtn_walk_counters(dtn_geometry g, void *stream, int32_t enable, int64_t out[2]);
 
 /* Sizes of a plan: total nodes and total panels over its patches. */
 int64_t dtn_plan_num_nodes(dtn_plan p);

@@ -1,4 +1,5 @@
 """Build the HIP library libdtn.so for gfx950 (in-tree)."""
+import hashlib
 import os
 import shutil
 import subprocess
@@ -6,6 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdtn.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "dtn.h")
 SOURCES = ["dtn_wos.hip", "dtn_patch.hip", "dtn_points.hip", "dtn_tree.hip", "dtn_operators.cpp", "dtn_capi.cpp", "dtn_server.cpp"]
 
 
@@ -31,10 +33,20 @@ def build_calib(verbose: bool = False, arch: str = "gfx950") -> str:
     return CALIB
 
 
+def header_digest(path: str = None) -> str:
+    """First 16 hex digits of the SHA-256 of the C-ABI header.  The library
+    carries the digest of the header it was built against (in
+    dtn_version()), and the binding refuses a library whose digest differs
+    from the header beside it: a stale build would otherwise be called with
+    the argument lists of a newer header."""
+    with open(HEADER if path is None else path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
 def build(verbose: bool = False, arch: str = "gfx950", extra=()) -> str:
     cmd = [hipcc(), f"--offload-arch={arch}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-command-line-argument", "-pthread",
+           "-Wno-unused-command-line-argument", "-pthread", f"-DDTN_HEADER_DIGEST=\"{header_digest()}\"",
            *[os.path.join(CSRC, s) for s in SOURCES], "-o", LIB + ".tmp", *extra]
     if verbose:
         print(" ".join(cmd), flush=True)

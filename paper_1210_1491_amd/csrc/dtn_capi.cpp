@@ -367,7 +367,13 @@ extern "C" {
 
 
 const char *dtn_last_error(void) { return g_last_error.c_str(); }
-const char *dtn_version(void) { return "dtn-wos-mi355x 0.1 (gfx950)"; }
+// The build passes the digest of the header it compiles against, so that a
+// binding can tell a library built against another version of the header.
+#ifndef DTN_HEADER_DIGEST
+#error "define DTN_HEADER_DIGEST (first 16 hex digits of the SHA-256 of include/dtn.h)"
+#endif
+
+const char *dtn_version(void) { return "dtn-wos-mi355x 0.1 (gfx950) dtn.h " DTN_HEADER_DIGEST; }
 
 dtn_status dtn_create_geometry(const dtn_geometry_desc *desc, dtn_geometry *out)
 {
@@ -829,16 +835,20 @@ dtn_status dtn_check(dtn_geometry g, void *stream)
     }
 }
 
-dtn_status dtn_walk_counters(dtn_geometry g, void *stream, int64_t out[2])
+dtn_status dtn_walk_counters(dtn_geometry g, void *stream, int32_t enable, int64_t out[2])
 {
     try {
-        if (!g || !out) return fail(DTN_E_ARG, "dtn_walk_counters: NULL argument");
+        if (!g) return fail(DTN_E_ARG, "dtn_walk_counters: NULL geometry");
+        if (enable != 0 && enable != 1) return fail(DTN_E_ARG, "dtn_walk_counters: enable must be 0 or 1");
         static std::mutex mu;  // one snapshot per geometry
         std::lock_guard<std::mutex> lk(mu);
         unsigned long long c[2] = {0, 0};
         const dtn_status st = take_counters(g->g, (hipStream_t)stream, c);
-        out[0] = (int64_t)c[0];
-        out[1] = (int64_t)c[1];
+        if (out) {
+            out[0] = (int64_t)c[0];
+            out[1] = (int64_t)c[1];
+        }
+        g->g.dev.count_walks = enable;
         return st;
     } catch (...) {
         return fail(DTN_E_OOM, "dtn_walk_counters: exception");

@@ -46,6 +46,7 @@ struct DevGeom {
     double tab_sc[3][2];
     // Status of the work on this geometry (device, see DevStatus).
     struct DevStatus *status;
+    int32_t count_walks;  // box minus holes: add the walk counters (dtn_walk_counters)
 };
 
 // Sticky status bits raised by kernels working on a geometry (kFlag*), read

@@ -285,7 +285,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
         // stopping lane is capped when it is not inside the shell
         uint64_t steps = 0, capped = 0;
         // box minus holes: wave iterations and hole distances computed
-        // (scalar counters, reported by dtn_walk_counters)
+        // (scalar counters, added up when counting is on)
         uint64_t n_iters = 0, n_visits = 0;
         int64_t next = w_lo;  // wave-uniform: next walk to hand out
         int qn = 0;           // wave-uniform: queued exit points
@@ -443,7 +443,9 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
         const unsigned long long ts = steps;
         const unsigned long long tc = capped;
         if constexpr (has_holes(KIND)) {
-            if (lane == 0) {
+            // two device-wide atomics per chunk serialise on one address:
+            // only in the counting mode dtn_walk_counters switches on
+            if (g.count_walks && lane == 0) {
                 atomicAdd(&g.status->iters, (unsigned long long)n_iters);
                 atomicAdd(&g.status->visits, (unsigned long long)n_visits);
             }

@@ -11,6 +11,8 @@ import os
 import numpy as np
 import torch
 
+from . import build as _build
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdtn.so")
 
@@ -93,6 +95,13 @@ def lib():
         vp = C.c_void_p
         L.dtn_last_error.restype = C.c_char_p
         L.dtn_version.restype = C.c_char_p
+        # the argument lists below follow the header beside the package: a
+        # library built against another version of it is refused
+        if os.path.exists(_build.HEADER):
+            want, got = _build.header_digest(), L.dtn_version().decode().rsplit(" ", 1)[-1]
+            if got != want:
+                raise ImportError(f"{LIB_PATH} was built against another include/dtn.h (digest {got}, the header "
+                                  f"has {want}): rebuild it (python -c 'import __graft_entry__ as g; g.build()')")
         L.dtn_create_geometry.argtypes = [C.POINTER(GeometryDesc), C.POINTER(vp)]
         L.dtn_destroy_geometry.argtypes = [vp]
         L.dtn_destroy_geometry.restype = None
@@ -143,7 +152,7 @@ def lib():
         L.dtn_class_operators.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
                                           dp, dp, dp, dp, dp, dp]
         L.dtn_check.argtypes = [vp, vp]
-        L.dtn_walk_counters.argtypes = [vp, vp, C.POINTER(C.c_int64)]
+        L.dtn_walk_counters.argtypes = [vp, vp, C.c_int32, C.POINTER(C.c_int64)]
         L.dtn_wos_eval_noalloc.argtypes = [vp, vp, C.c_int64, vp, vp, C.c_uint64, vp, C.c_int32, vp, vp, vp]
         L.dtn_plan_set_max_sweeps.argtypes = [vp, C.c_int32]
         for f in ("dtn_create_geometry", "dtn_wos_eval", "dtn_wos_adaptive", "dtn_wos_time_schedules",
@@ -270,11 +279,12 @@ def wos_eval_noalloc(geom, pts, walks, seed, stats, capped, walk_begin=None, str
     return stats, capped
 
 
-def walk_counters(geom):
-    """(wave iterations, hole distances computed by waves) of the walks on a
-    box minus holes since the last call (waits for torch's current stream)."""
+def walk_counters(geom, enable=False):
+    """(wave iterations, hole distances computed by waves) of the counted
+    walks on a box minus holes since the last call (waits for torch's
+    current stream); counting stays on for later launches when enable."""
     out = (C.c_int64 * 2)()
-    _check(lib().dtn_walk_counters(geom.handle, _stream(), out), "dtn_walk_counters")
+    _check(lib().dtn_walk_counters(geom.handle, _stream(), 1 if enable else 0, out), "dtn_walk_counters")
     return int(out[0]), int(out[1])
 
 

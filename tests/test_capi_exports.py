@@ -173,6 +173,7 @@ def test_status_entry_points_check_their_arguments_on_the_host():
     L = dtn.lib()
     assert L.dtn_check(None, None) == -1
     assert L.dtn_plan_set_max_sweeps(None, 4) == -1
+    assert L.dtn_walk_counters(None, None, 0, None) == -1
     assert "NULL" in L.dtn_last_error().decode()
 
 
@@ -246,3 +247,18 @@ def test_curved_second_kind_tables_agree_with_oracle(layout):
         pts, nrm, W = SK.s_rule_c(X[i], 1.0, rr, 1e-6)
         wsum = np.sum(W * SK.d2green(X[i][None, :], N[i][None, :], pts, nrm, 1.0))
         assert abs(t["c2"][i] - (Q2[i].sum() - wsum)) < 1e-9 * max(1.0, abs(wsum))
+
+
+def test_binding_refuses_a_library_built_against_another_header(tmp_path, monkeypatch):
+    """The library's version string carries the digest of the header it was
+    built against; the binding loads it only when that matches the header
+    beside the package (a stale library called with a newer header's
+    argument lists would read its arguments wrongly)."""
+    from paper_1210_1491_amd import build, dtn
+    assert dtn.version().endswith(" dtn.h " + build.header_digest())
+    other = tmp_path / "dtn.h"
+    other.write_bytes(open(build.HEADER, "rb").read() + b"\n/* changed */\n")
+    monkeypatch.setattr(build, "HEADER", str(other))
+    monkeypatch.setattr(dtn, "_lib", None)
+    with pytest.raises(ImportError, match="another include/dtn.h"):
+        dtn.lib()

@@ -120,3 +120,35 @@ def test_potential_rejects_partial_and_overlapping_tilings():
     with pytest.raises(dtn.DtnError) as e:
         p.potential(torch.zeros(p.num_panels, dtype=torch.float64, device="cuda"), tg)
     assert e.value.status == -4
+
+
+def test_walk_counters_count_only_when_switched_on():
+    """The wave-iteration and hole-distance counters of the walks on a box
+    minus holes: zero unless switched on; when on, every wave iteration
+    advances at most 64 walks by one step, and computes distances to at
+    most all of the holes."""
+    dtn = _dtn()
+    gd = I.geometry_box_holes()
+    g = dtn.Geometry(gd)
+    pd = I.patches_box_holes(gd)
+    plan = dtn.Plan(g, I.subset_patches(pd, I.box_holes_sample(pd)))
+    nodes = plan.nodes()
+    w = torch.full((plan.num_nodes,), 64, dtype=torch.int64, device="cuda")
+    print("[gpu] status: walk counters", flush=True)
+    assert dtn.walk_counters(g) == (0, 0)
+    st, _ = dtn.wos_eval(g, nodes, w, 5)
+    assert dtn.walk_counters(g) == (0, 0)  # off by default
+    assert dtn.walk_counters(g, enable=True) == (0, 0)
+    st, _ = dtn.wos_eval(g, nodes, w, 5)
+    iters, visits = dtn.walk_counters(g, enable=False)
+    steps = float(st[:, 3].sum())
+    assert iters > 0 and 64 * iters >= steps
+    assert 0 < visits <= len(gd["holes"]) * iters
+    dtn.wos_eval(g, nodes, w, 5)
+    assert dtn.walk_counters(g) == (0, 0)  # switched off again
+    # a geometry without holes counts nothing
+    cube = dtn.Geometry(I.geometry_cube_sources())
+    dtn.walk_counters(cube, enable=True)
+    dtn.wos_eval(cube, torch.tensor(I.interior_points_box(64, 9), device="cuda"),
+                 torch.full((64,), 64, dtype=torch.int64, device="cuda"), 5)
+    assert dtn.walk_counters(cube) == (0, 0)
