@@ -139,14 +139,14 @@ EXT_SLOTS_PER_WALK = slots(EXT_WALK_OPS)
 # the kernel sources it was measured on (SHA-256 of these files).
 TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_amd/csrc/dtn_device.h",
                      "paper_1210_1491_amd/csrc/dtn_internal.h"],
-           "sha256": ["5ef310b5c4bb8484fdb70bd2eab9dcb269cb157546e3f306fcc8d3dc3b5aa57e",
-                      "32e1aa880c5fc692e427e9181a9b47d14aeeb1ddc66d47bf4bcf324aa713e4f7",
-                      "484a48b7f92b8e6cf794651f517f0a16c59de700e3f5cffad7a2065c3bbf38bb"],
-           "fetch_bytes": 71753.688 * 1024 * (262144 / 131088.5), "write_bytes": 43008.0 * 1024 * 1.00,
+           "sha256": ["3c936000d8fec434d1b060b12420db4912a265a93353ac53848120caacafc023",
+                      "d66826bb38d451cac70715699db844176ce8bc475575ae59257bf8b242b89abd",
+                      "3ba5aaa8cff36fcabd3602a4f75e1f6a528fc5a5cd5d175510ed3897d9d2cf24"],
+           "fetch_bytes": 30803.188 * 1024 * (262144 / 131089.938), "write_bytes": 36864.25 * 1024 * 1.00,
            # the half-space point workload's walk kernel (same sources), scaled
-           # by the copy in its own run (fetch 131086.438 KiB for 262144)
-           "halfspace_fetch_bytes": 156223.625 * 1024 * (262144 / 131086.438),
-           "halfspace_write_bytes": 89600.0 * 1024 * 1.00}
+           # by the copy in its own run; None until measured on these sources
+           "halfspace_fetch_bytes": None,
+           "halfspace_write_bytes": None}
 
 
 # ------------------------------------------------- exact data, panel layout
@@ -220,7 +220,7 @@ def traffic_if_current():
 
 
 def halfspace_traffic_if_current():
-    if traffic_if_current() is None:
+    if traffic_if_current() is None or TRAFFIC["halfspace_fetch_bytes"] is None:
         return None
     return TRAFFIC["halfspace_fetch_bytes"] + TRAFFIC["halfspace_write_bytes"]
 

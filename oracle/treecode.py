@@ -14,11 +14,20 @@ Tlupova, Commun. Comput. Phys. 28, 2020), stated here in its plain form:
              single-layer weight a_j = w_j sigma_j and a double-layer vector
              b_j = -w_j phi_j n_j, so that
                u(x) = sum_j [a_j / |x - y_j| + b_j . (x - y_j) / |x - y_j|^3] / (4 pi);
-  tree       clusters split at the midpoint of their tight bounding box
-             along every dimension whose extent is at least the largest
-             extent / sqrt(2), children ordered by their octant code
-             (bit d set for the upper half in dimension d), until a cluster
-             holds at most leaf_size sources (or cannot be split);
+  tree       the root's children are the boundary's faces: one cluster per
+             face label of the sources (the face of a tile is the axis of
+             its normal's largest component and that component's sign,
+             label 2 axis + (sign > 0)), in increasing label order, each
+             keeping its sources in input order.  Below them, clusters
+             split at the midpoint of their tight bounding box along every
+             dimension whose extent is at least the largest extent /
+             sqrt(2), children ordered by their octant code (bit d set for
+             the upper half in dimension d), until a cluster holds at most
+             leaf_size sources (or cannot be split).  A face cluster lies in
+             one plane, so its proxy grid and those of all its descendants
+             are two-dimensional (degree 0 along the normal): the reading
+             taken for this design choice, which the paper leaves open, is
+             that clusters never straddle an edge of the box;
   proxies    per cluster, a tensor grid of Chebyshev points of the second
              kind on the box padded by 1e-12 of the root extent, degree n in
              each dimension whose tight extent exceeds 1e-9 of the largest
@@ -73,7 +82,7 @@ def lagrange_1d(y, nodes, w):
 
 
 class Cluster:
-    def __init__(self, idx, y, pad, degree, leaf_size):
+    def __init__(self, idx, y, pad, degree, leaf_size, groups=None):
         self.idx = idx
         P = y[idx]
         tlo, thi = P.min(axis=0), P.max(axis=0)
@@ -85,7 +94,10 @@ class Cluster:
         self.deg = [degree if ext[d] > FLAT_REL * big else 0 for d in range(3)]
         self.n_proxy = int(np.prod([k + 1 for k in self.deg]))
         self.children = []
-        if len(idx) > leaf_size and big > 0.0:
+        if groups is not None:
+            for c in np.unique(groups):
+                self.children.append(Cluster(idx[groups == c], y, pad, degree, leaf_size))
+        elif len(idx) > leaf_size and big > 0.0:
             mid = 0.5 * (tlo + thi)
             code = np.zeros(len(idx), dtype=np.int64)
             for d in range(3):
@@ -107,10 +119,19 @@ class Cluster:
         return S, L.T @ a[self.idx], L.T @ b[self.idx]
 
 
-def build_tree(y, leaf_size=64, degree=6):
+def build_tree(y, faces, leaf_size=64, degree=6):
+    """The tree over the sources y with face labels `faces` (one per source)."""
     y = np.asarray(y, dtype=np.float64)
     pad = PAD_REL * float((y.max(axis=0) - y.min(axis=0)).max())
-    return Cluster(np.arange(len(y)), y, pad, degree, leaf_size)
+    return Cluster(np.arange(len(y)), y, pad, degree, leaf_size, groups=np.asarray(faces))
+
+
+def face_label(n):
+    """Face label of a tile with normal n: 2 axis + (sign > 0) for the axis
+    of the largest component (the first such axis on ties)."""
+    n = np.asarray(n, dtype=np.float64)
+    k = int(np.argmax(np.abs(n)))
+    return 2 * k + int(n[k] > 0.0)
 
 
 def _direct(x, y, a, b):
@@ -159,8 +180,13 @@ def tile_sources(patches, sigmas, geom):
     return np.concatenate(ys), np.concatenate(As), np.concatenate(Bs)
 
 
+def tile_faces(patches):
+    """Face label of every source of tile_sources (its tile's label)."""
+    return np.concatenate([np.full(16, face_label(p.n)) for p in patches])
+
+
 def potential_tree(patches, sigmas, geom, targets, theta=0.5, degree=6, leaf_size=64):
     """u at the targets from the tiles' Neumann data, by the treecode."""
     y, a, b = tile_sources(patches, sigmas, geom)
-    tree = build_tree(y, leaf_size, degree)
+    tree = build_tree(y, tile_faces(patches), leaf_size, degree)
     return evaluate(tree, y, a, b, targets, theta)[0]

@@ -8,9 +8,12 @@
 // p_k = sum_j L_k(y_j) b_j, which interpolate y -> 1/|x - y| and its gradient.
 //
 //   host, per handle       tree over the tile sources in depth-first
-//                          pre-order: node j's subtree is nodes [j, skip_j),
-//                          its sources [b, e) in tree order; proxy grids and
-//                          the proxy pass's work items (cluster, source chunk)
+//                          pre-order: the root's children are the box's
+//                          faces (flat clusters: 2-D proxy grids below
+//                          them), then octant splits; node j's subtree is
+//                          nodes [j, skip_j), its sources [b, e) in tree
+//                          order; proxy grids and the proxy pass's work
+//                          items (cluster, source chunk)
 //   k_tree_proxy_partial   one block per work item: 1-D Lagrange values of 64
 //                          sources at a time in LDS, each thread accumulates
 //                          up to 3 proxies of the cluster
@@ -92,9 +95,11 @@ struct HostTree {
     double box_lo[3], box_ext[3];  // tight box of all sources (Morton frame)
 };
 
-// Recursive build of node [b, e) of perm (depth-first pre-order).
-void build_node(const std::vector<double> &pos, int32_t b, int32_t e, int degree, int leaf_size, double pad,
-                HostTree &T, std::vector<int32_t> &tmp)
+// Recursive build of node [b, e) of perm (depth-first pre-order).  With
+// `face` (the root only) the children are the boundary's faces, one per
+// face label present, in label order; otherwise the octants of the split.
+void build_node(const std::vector<double> &pos, const int8_t *face, int32_t b, int32_t e, int degree,
+                int leaf_size, double pad, HostTree &T, std::vector<int32_t> &tmp)
 {
     double tlo[3], thi[3];
     for (int d = 0; d < 3; ++d) {
@@ -127,7 +132,7 @@ void build_node(const std::vector<double> &pos, int32_t b, int32_t e, int degree
     nd.b = b;
     nd.e = e;
     nd.proxy = -1;
-    const bool split = e - b > leaf_size && big > 0.0;
+    const bool split = face || (e - b > leaf_size && big > 0.0);
     nd.leaf = split ? 0 : 1;
     const int32_t j = (int32_t)T.nodes.size();
     T.nodes.push_back(nd);
@@ -138,9 +143,10 @@ void build_node(const std::vector<double> &pos, int32_t b, int32_t e, int degree
             mid[d] = 0.5 * (tlo[d] + thi[d]);
             cut[d] = ext[d] >= big / std::sqrt(2.0);
         }
-        // stable counting sort of the sources by octant code
+        // stable counting sort of the sources by octant code (face label at the root)
         int32_t cnt[9] = {0};
         auto code = [&](int32_t s) {
+            if (face) return (int)face[s];
             int c = 0;
             for (int d = 0; d < 3; ++d)
                 if (cut[d] && pos[3 * (size_t)s + d] >= mid[d]) c |= 1 << d;
@@ -153,12 +159,19 @@ void build_node(const std::vector<double> &pos, int32_t b, int32_t e, int degree
         for (int32_t i = b; i < e; ++i) tmp[at[code(T.perm[i])]++] = T.perm[i];
         std::copy(tmp.begin() + b, tmp.begin() + e, T.perm.begin() + b);
         for (int c = 0; c < 8; ++c)
-            if (cnt[c + 1] > cnt[c]) build_node(pos, b + cnt[c], b + cnt[c + 1], degree, leaf_size, pad, T, tmp);
+            if (cnt[c + 1] > cnt[c])
+                build_node(pos, nullptr, b + cnt[c], b + cnt[c + 1], degree, leaf_size, pad, T, tmp);
     }
     T.nodes[j].skip = (int32_t)T.nodes.size();
 }
 
-void build_tree(const std::vector<double> &pos, int degree, int leaf_size, HostTree &T)
+// The tree over the sources at `pos` with face labels `face` (one per
+// source, 0..5).  The root's children are the faces, so that no cluster
+// below it straddles an edge of the box: each lies in one plane and its
+// proxy grid is two-dimensional (degree 0 along the normal), 49 proxies at
+// degree 6 where a cluster across an edge needs 343.
+void build_tree(const std::vector<double> &pos, const std::vector<int8_t> &face, int degree, int leaf_size,
+                HostTree &T)
 {
     const int32_t n = (int32_t)(pos.size() / 3);
     double lo[3], hi[3], big = 0.0;
@@ -179,7 +192,7 @@ void build_tree(const std::vector<double> &pos, int degree, int leaf_size, HostT
     T.perm.resize(n);
     for (int32_t i = 0; i < n; ++i) T.perm[i] = i;
     std::vector<int32_t> tmp(n);
-    build_node(pos, 0, n, degree, leaf_size, kPadRel * big, T, tmp);
+    build_node(pos, face.data(), 0, n, degree, leaf_size, kPadRel * big, T, tmp);
     T.slot.resize(n);
     for (int32_t i = 0; i < n; ++i) T.slot[T.perm[i]] = i;
     // proxies of every cluster holding more sources than proxies, in node order
@@ -456,6 +469,21 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Tile sources on the host: c + h (xi t1 + eta t2) for the 4 x 4 Gauss points
 // (xi, eta), t2 = n x t1, source 4 a + b of a tile at (xi_a, xi_b).
+// Face label of every tile source (16 per tile): 2 axis + (sign > 0) for the
+// axis of the largest component of the tile's normal (the first on ties).
+std::vector<int8_t> tile_faces(const dtn_patch *patches, int64_t n)
+{
+    std::vector<int8_t> f((size_t)n * 16);
+    for (int64_t i = 0; i < n; ++i) {
+        const double *nv = patches[i].n;
+        int k = 0;
+        for (int d = 1; d < 3; ++d)
+            if (std::fabs(nv[d]) > std::fabs(nv[k])) k = d;
+        std::fill(f.begin() + 16 * i, f.begin() + 16 * (i + 1), (int8_t)(2 * k + (nv[k] > 0.0 ? 1 : 0)));
+    }
+    return f;
+}
+
 std::vector<double> tile_positions(const dtn_patch *patches, int64_t n)
 {
     std::vector<double> gx, gw;
@@ -530,7 +558,7 @@ dtn_status dtn_create_tree(dtn_plan p, int32_t degree, int32_t leaf_size, dtn_tr
         const std::vector<double> pos = tile_positions(P.patches.data(), (int64_t)P.patches.size());
         std::unique_ptr<dtn_tree_s> T(new dtn_tree_s());
         T->t.plan = &P;
-        build_tree(pos, degree, leaf_size, T->t.host);
+        build_tree(pos, tile_faces(P.patches.data(), (int64_t)P.patches.size()), degree, leaf_size, T->t.host);
         hipError_t e = hipGetDevice(&T->t.device);
         if (e == hipSuccess) e = upload_vec(T->t.host.nodes, &T->t.d_nodes);
         if (e == hipSuccess) e = upload_vec(T->t.host.slot, &T->t.d_slot);
@@ -566,7 +594,7 @@ dtn_status dtn_tree_layout(const dtn_patch *patches, int64_t n_patches, int32_t 
         if (degree < 1 || degree > kMaxDegree) return fail(DTN_E_ARG, at + "degree outside [1, 8]");
         if (leaf_size < 8 || leaf_size > 4096) return fail(DTN_E_ARG, at + "leaf_size outside [8, 4096]");
         HostTree H;
-        build_tree(tile_positions(patches, n_patches), degree, leaf_size, H);
+        build_tree(tile_positions(patches, n_patches), tile_faces(patches, n_patches), degree, leaf_size, H);
         *n_nodes = (int64_t)H.nodes.size();
         if ((int64_t)H.nodes.size() > cap) return fail(DTN_E_ARG, at + "cap below the number of nodes");
         for (size_t j = 0; j < H.nodes.size(); ++j) {

@@ -50,7 +50,7 @@ def test_tree_matches_oracle_treecode(degree, leaf, theta):
     gd, pd, ps, sig = _cube()
     tg = _targets(24, 8, degree)
     y, a, b = OT.tile_sources(ps, sig, OW.Geometry(gd))
-    ref, ref_cnt = OT.evaluate(OT.build_tree(y, leaf, degree), y, a, b, tg, theta)
+    ref, ref_cnt = OT.evaluate(OT.build_tree(y, OT.tile_faces(ps), leaf, degree), y, a, b, tg, theta)
     print(f"[gpu] tree vs oracle degree={degree} leaf={leaf} theta={theta}", flush=True)
     plan = dtn.Plan(dtn.Geometry(gd), pd)
     tree = dtn.Tree(plan, degree, leaf)
@@ -91,7 +91,7 @@ def test_tree_vs_direct_on_every_target(m_tiles, n_targets):
     if m_tiles == 16:
         worst = np.argsort(err)[-6:]
         y, a, b = OT.tile_sources(ps, sig, OW.Geometry(gd))
-        o, _ = OT.evaluate(OT.build_tree(y, 64, 6), y, a, b, tg_np[worst], 0.5)
+        o, _ = OT.evaluate(OT.build_tree(y, OT.tile_faces(ps), 64, 6), y, a, b, tg_np[worst], 0.5)
         np.testing.assert_allclose(u[worst], o, rtol=0, atol=1e-11 * scale)
 
 

@@ -48,7 +48,7 @@ def _cube_sources(n_tiles=None):
 def test_tree_partitions_the_sources():
     ps, sig, g, _ = _cube_sources()
     y, a, b = T.tile_sources(ps, sig, g)
-    tree = T.build_tree(y, leaf_size=40, degree=6)
+    tree = T.build_tree(y, T.tile_faces(ps), leaf_size=40, degree=6)
     seen = []
 
     def walk(C):
@@ -65,22 +65,28 @@ def test_tree_partitions_the_sources():
 
     walk(tree)
     np.testing.assert_array_equal(np.sort(np.concatenate(seen)), np.arange(len(y)))
-    # clusters on one face are flat: one proxy layer in the normal direction
-    leaves = []
+    # the root's children are the six faces, in label order (2 axis + (outward
+    # normal along +axis)): face f holds the tiles on the plane x_axis = f % 2
+    assert len(tree.children) == 6
+    for f, ch in enumerate(tree.children):
+        assert len(ch.idx) == len(y) // 6
+        assert np.all(y[ch.idx, f // 2] == float(f % 2))
+    # every cluster below the root lies in its face's plane, so its proxy
+    # grid is one layer in the normal direction (49 proxies at degree 6)
+    below = []
 
     def collect(C):
-        if C.children:
-            for ch in C.children:
-                collect(ch)
-        else:
-            leaves.append(C)
+        below.append(C)
+        for ch in C.children:
+            collect(ch)
 
-    collect(tree)
-    flat = [C for C in leaves if sorted(C.deg) == [0, 6, 6]]
-    assert len(flat) > len(leaves) // 2 and all(C.n_proxy == 49 for C in flat)
-    for C in flat:
-        d = C.deg.index(0)
-        assert np.ptp(y[C.idx, d]) == 0.0
+    for f, ch in enumerate(tree.children):
+        below.clear()
+        collect(ch)
+        for C in below:
+            assert np.ptp(y[C.idx, f // 2]) == 0.0
+            if len(C.idx) > 1 and np.ptp(y[C.idx], axis=0).max() > 0.0:
+                assert C.deg[f // 2] == 0 and C.n_proxy <= 49
 
 
 def test_proxies_keep_the_moments_up_to_the_degree():
@@ -89,7 +95,7 @@ def test_proxies_keep_the_moments_up_to_the_degree():
     those monomials exactly."""
     ps, sig, g, _ = _cube_sources()
     y, a, b = T.tile_sources(ps, sig, g)
-    tree = T.build_tree(y, leaf_size=64, degree=4)
+    tree = T.build_tree(y, T.tile_faces(ps), leaf_size=64, degree=4)
     for C in (tree, tree.children[0], tree.children[-1].children[0]):
         S, q, p = C.proxies(y, a, b)
         c = C.center
@@ -128,7 +134,7 @@ def test_error_falls_with_the_degree():
     scale = np.max(np.abs(u_dir))
     errs = []
     for n in (2, 4, 6, 8):
-        tree = T.build_tree(y, leaf_size=64, degree=n)
+        tree = T.build_tree(y, T.tile_faces(ps), leaf_size=64, degree=n)
         u, cnt = T.evaluate(tree, y, a, b, tg, theta=0.5)
         assert cnt[:, 0].sum() > 0  # the proxies are used
         errs.append(np.max(np.abs(u - u_dir)) / scale)

@@ -33,7 +33,7 @@ def test_tree_layout_equals_oracle(degree, leaf, tiles):
     nodes, perm = dtn.tree_layout(pd, degree, leaf)
     ps = P.patches_from_desc(pd, gd)
     y, _, _ = T.tile_sources(ps, [np.zeros(p.n_rings * p.n_sectors) for p in ps], wos.Geometry(gd))
-    pre = _preorder(T.build_tree(y, leaf, degree), [])
+    pre = _preorder(T.build_tree(y, T.tile_faces(ps), leaf, degree), [])
     assert len(pre) == len(nodes)
     pos = {id(C): j for j, C in enumerate(pre)}
 
