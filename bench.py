@@ -140,13 +140,13 @@ EXT_SLOTS_PER_WALK = slots(EXT_WALK_OPS)
 TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_amd/csrc/dtn_device.h",
                      "paper_1210_1491_amd/csrc/dtn_internal.h"],
            "sha256": ["3c936000d8fec434d1b060b12420db4912a265a93353ac53848120caacafc023",
-                      "d66826bb38d451cac70715699db844176ce8bc475575ae59257bf8b242b89abd",
+                      "19671560cc811f1b8a60b74d4037267882fa3f71950dead4aab4cc74733a45da",
                       "3ba5aaa8cff36fcabd3602a4f75e1f6a528fc5a5cd5d175510ed3897d9d2cf24"],
-           "fetch_bytes": 30803.188 * 1024 * (262144 / 131089.938), "write_bytes": 36864.25 * 1024 * 1.00,
+           "fetch_bytes": 41788.938 * 1024 * (262144 / 131091.938), "write_bytes": 38400.0 * 1024 * 1.00,
            # the half-space point workload's walk kernel (same sources), scaled
-           # by the copy in its own run; None until measured on these sources
-           "halfspace_fetch_bytes": None,
-           "halfspace_write_bytes": None}
+           # by the copy in its own run (fetch 131086.188 KiB for 262144)
+           "halfspace_fetch_bytes": 92470.312 * 1024 * (262144 / 131086.188),
+           "halfspace_write_bytes": 80000.0 * 1024 * 1.00}
 
 
 # ------------------------------------------------- exact data, panel layout
@@ -838,6 +838,21 @@ def treecode_potential(m_tiles=96, n_targets=1_000_000, degree=6, theta=0.5, lea
         sweep.append({"degree": deg, "theta": th, "ms": ev[0].elapsed_time(ev[1]) / reps,
                       "max_rel_diff_vs_direct": err})
         del tr
+    # whole calls at other target counts (seeded uniform targets, the same
+    # tree): the share of fixed work and of the traversal's tail
+    scaling = []
+    for n_s in (250_000, 4_000_000):
+        tg_s = torch.tensor(np.random.default_rng([6, n_s]).random((n_s, 3)), device="cuda")
+        u_s = tree.potential(neu, tg_s, theta)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            tree.potential(neu, tg_s, theta, out=u_s)
+        ev[1].record()
+        torch.cuda.synchronize()
+        scaling.append({"targets": n_s, "ms": ev[0].elapsed_time(ev[1]) / reps})
+        del tg_s, u_s
+    scaling.insert(1, {"targets": n_targets, "ms": ms_tree})
     u_t, u_d, cnt = u_t.cpu().numpy(), u_d.cpu().numpy(), counts.cpu().numpy()
     far = np.min(np.minimum(tg_np, 1.0 - tg_np), axis=1) >= 2.0 / m_tiles
     ex = exact_u(gd, tg_np[far])
@@ -856,6 +871,7 @@ def treecode_potential(m_tiles=96, n_targets=1_000_000, degree=6, theta=0.5, lea
         "max_err_vs_exact_direct": float(np.max(np.abs(u_d[far] - ex))),
         "targets_vs_exact": int(far.sum()),
         "sweep": sweep,
+        "scaling": scaling,
     }
     print(f"[bench] treecode potential: {ms_tree:.1f} ms vs direct {ms_direct:.1f} ms "
           f"({out['speedup']:.1f}x), {inter:.0f} interactions per target", file=sys.stderr, flush=True)

@@ -388,10 +388,14 @@ dtn_status dtn_potential(dtn_plan p, const double *neumann, const double *target
  * kernel-independent treecode, the fast summation the paper names for this
  * step (Sec. 6): barycentric Lagrange interpolation on Chebyshev points
  * (Wang, Krasny & Tlupova 2020).
- *   tree      clusters split at the midpoint of their tight bounding box
- *             along every dimension with extent >= the largest / sqrt(2),
- *             children in octant-code order (bit d: upper half in
- *             dimension d), down to <= leaf_size sources;
+ *   tree      the root's children are the box's faces (a tile's face: the
+ *             axis of its normal's largest component and that component's
+ *             sign, label 2 axis + (sign > 0), in label order), so every
+ *             cluster below the root lies in one plane; below them clusters
+ *             split at the midpoint of their tight bounding box along every
+ *             dimension with extent >= the largest / sqrt(2), children in
+ *             octant-code order (bit d: upper half in dimension d), down to
+ *             <= leaf_size sources;
  *   proxies   per cluster a tensor grid of Chebyshev points of the second
  *             kind on its box padded by 1e-12 of the root extent, `degree`
  *             in each dimension whose extent exceeds 1e-9 of the largest
@@ -409,7 +413,11 @@ dtn_status dtn_potential(dtn_plan p, const double *neumann, const double *target
  * device), so a wave's 64 targets share most of their traversal; a node that
  * at most 32 of a wave's targets take is evaluated by the whole wave
  * repacked, 64/k lanes per taking target, so a target's sum depends on its
- * wave companions only through rounding.
+ * wave companions only through rounding.  Each face's subtree is walked by
+ * its own wave per group of 64 targets, the faces' sums added per target in
+ * face order.  Proxies are built only for clusters that some target of the
+ * call could take (the test against the targets' bounding box), so interior
+ * targets pay nothing for the root's and the faces' proxies.
  * Create: degree in [1, 8], leaf_size in [8, 4096].  Errors: DTN_E_ARG,
  * DTN_E_UNSUPPORTED (a plan dtn_potential rejects), DTN_E_OOM.
  * The tree refers to the plan: destroy it before the plan. */
@@ -430,7 +438,10 @@ dtn_status dtn_tree_layout(const dtn_patch *patches, int64_t n_patches, int32_t 
 
 /* u at m targets (as dtn_potential) by the treecode with MAC parameter theta
  * in (0, 1).  counts: device [m][2] out (proxy and direct interactions of
- * each target), or NULL.  Device scratch is allocated stream-ordered.
+ * each target), or NULL.  Device scratch is allocated stream-ordered: the
+ * tile sources, proxies and their partials, the sort, and the faces' partial
+ * sums for up to 2^22 targets at a time (8 B per face and target, 24 B with
+ * counts).
  *   neumann device [num_panels]; targets device [m][3]; u_out device [m].
  * Errors: DTN_E_ARG (NULL arrays with m > 0, theta out of range), DTN_E_OOM. */
 dtn_status dtn_tree_potential(dtn_tree t, const double *neumann, const double *targets, int64_t m,

@@ -480,16 +480,24 @@ __device__ __forceinline__ KSum wave_ksum(KSum a)
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 // Workgroups are dispatched to the 8 XCDs round-robin (workgroup i to XCD
-// i mod 8), and each XCD has its own L2.  This bijection of [0, G) gives
-// XCD x the contiguous range of logical blocks [x q + min(x, r), ...), q =
-// G / 8, r = G mod 8, in dispatch order, so the rows a block reads (points,
-// walk counts, chunk offsets) are shared with its XCD neighbours' rows
-// instead of being fetched into all eight L2s.
+// i mod 8), and each XCD has its own L2.  This bijection of [0, G) gives the
+// workgroups an XCD receives runs of kXcdStripe consecutive logical blocks
+// (neighbouring chunks: the same or adjacent nodes, whose walks share cache
+// lines of their inputs and of the boundary tables on that XCD), and deals
+// the 8 runs of each round to the XCDs under a rotation that changes from
+// round to round, so that no XCD sees the same position of a periodic node
+// layout every time (with a fixed assignment, XCD x would always get the
+// same rings of every patch, and their walk lengths differ).  Blocks past
+// the last whole round map to themselves.
 constexpr int kXcds = 8;
-__device__ __forceinline__ int64_t xcd_block(int64_t i, int64_t G)
+constexpr int64_t kXcdStripe = 4;
+__host__ __device__ __forceinline__ int64_t xcd_block(int64_t i, int64_t G)
 {
-    const int64_t x = i % kXcds, q = G / kXcds, r = G % kXcds;
-    return x * q + (x < r ? x : r) + i / kXcds;
+    const int64_t F = G - G % (kXcds * kXcdStripe);
+    if (i >= F) return i;
+    const int64_t x = i % kXcds, k = i / kXcds, j = k / kXcdStripe;
+    const int64_t rot = (int64_t)(((uint32_t)j * 2654435761u) >> 29);
+    return (j * kXcds + ((x + rot) & (kXcds - 1))) * kXcdStripe + k % kXcdStripe;
 }
 
 // Exit-point queue entry (3 doubles) `first + rank` of a queue in LDS,

@@ -14,22 +14,27 @@
 //                          nodes [j, skip_j), its sources [b, e) in tree
 //                          order; proxy grids and the proxy pass's work
 //                          items (cluster, source chunk)
+//   k_tree_tbox_*          bounding box of the targets: clusters that no
+//                          target in it can take get no proxies this call
 //   k_tree_proxy_partial   one block per work item: 1-D Lagrange values of 64
 //                          sources at a time in LDS, each thread accumulates
-//                          up to 3 proxies of the cluster
+//                          up to 3 proxies of the cluster (flat clusters:
+//                          2 or 4 thread groups over alternate sources)
 //   k_tree_proxy_reduce    per cluster: chunk partials summed in order, proxy
 //                          points written beside their charges
 //   k_tree_keys            Morton keys of the targets (10 bits per axis in the
 //                          sources' bounding box, clamped), then a radix sort
 //                          of (key, target) pairs (hipCUB)
-//   k_tree_eval            one wave per 64 consecutive sorted targets: a
-//                          stackless walk of the node list under wave-uniform
-//                          control.  Each lane keeps the node index below
-//                          which it is done (it took an ancestor whole); a
+//   k_tree_eval            one wave per 64 consecutive sorted targets and
+//                          face subtree: a stackless walk of the subtree's
+//                          node range under wave-uniform control.  Each
+//                          lane keeps the node index below which it is
+//                          done (it took an ancestor whole); a
 //                          node is opened when a lane still inside it needs
 //                          it opened, else the walk jumps past its subtree.
 //                          Proxies and sources are read at wave-uniform
 //                          addresses.  All FP64.
+//   k_tree_sum             per target: the face subtrees' sums in order
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
@@ -85,7 +90,19 @@ struct ProxyCluster {
 static_assert(sizeof(TreeNode) == 128, "node layout");
 static_assert((kMaxDegree + 1) * (kMaxDegree + 1) * (kMaxDegree + 1) <= kProxyThreads * kProxySlots, "slots");
 
+// Node ranges the traversal is split into: the root's subtrees (the
+// faces), each walked by its own wave per target group, so that a target
+// group's work is spread over several waves; their sums are added per
+// target, in range order, by k_tree_sum.
+constexpr int kMaxParts = 8;
+constexpr int64_t kEvalBatch = (int64_t)1 << 22;  // targets per traversal launch
+struct TreeParts {
+    int32_t n;
+    int32_t lo[kMaxParts], hi[kMaxParts];
+};
+
 struct HostTree {
+    TreeParts parts;
     std::vector<TreeNode> nodes;
     std::vector<int32_t> perm;  // tree position -> source index (16 patch + q)
     std::vector<int32_t> slot;  // source index -> tree position
@@ -195,6 +212,24 @@ void build_tree(const std::vector<double> &pos, const std::vector<int8_t> &face,
     build_node(pos, face.data(), 0, n, degree, leaf_size, kPadRel * big, T, tmp);
     T.slot.resize(n);
     for (int32_t i = 0; i < n; ++i) T.slot[T.perm[i]] = i;
+    // the root's subtrees as traversal parts (sibling subtrees are
+    // contiguous in pre-order, so any overflow joins the last part)
+    TreeParts &P = T.parts;
+    P.n = 0;
+    const int32_t nn = (int32_t)T.nodes.size();
+    for (int32_t c = 1; c < nn; c = T.nodes[c].skip) {
+        if (P.n == kMaxParts) {
+            P.hi[kMaxParts - 1] = nn;
+            break;
+        }
+        P.lo[P.n] = c;
+        P.hi[P.n] = T.nodes[c].skip;
+        ++P.n;
+    }
+    if (P.n == 0) {  // the root is a leaf: nothing below it
+        P.n = 1;
+        P.lo[0] = P.hi[0] = nn;
+    }
     // proxies of every cluster holding more sources than proxies, in node order
     for (int32_t j = 0; j < (int32_t)T.nodes.size(); ++j) {
         TreeNode &nd = T.nodes[j];
@@ -240,21 +275,93 @@ __device__ __forceinline__ double cheb_point(const TreeNode &nd, int d, int k)
     return 0.5 * (nd.lo[d] + nd.hi[d]) + 0.5 * (nd.hi[d] - nd.lo[d]) * cos(M_PI * k / nd.deg[d]);
 }
 
+// Can any target accept node nd?  The acceptance test r^2 < theta^2 |x - c|^2
+// fails for every x in the targets' box when r^2 exceeds theta^2 times the
+// squared distance from c to the box's farthest corner (a relative margin
+// covers the rounding of the per-target distances).  Proxies of clusters
+// no target can accept are never read, so they are not built.
+__device__ __forceinline__ bool acceptable(const TreeNode &nd, const double *__restrict__ tbox, double theta2)
+{
+    double d2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const double a = fmax(fabs(nd.c[d] - tbox[d]), fabs(tbox[3 + d] - nd.c[d]));
+        d2 += a * a;
+    }
+    return !(nd.r2 > theta2 * d2 * (1.0 + 1e-12));
+}
+
+// Bounding box of the targets: per-block partial (lo, hi) rows, then one
+// block folds them into tbox[6].  Min and max are exact, so the order is
+// immaterial.
+__global__ __launch_bounds__(256) void k_tree_tbox_partial(const double *__restrict__ targets, int64_t m,
+                                                           double *__restrict__ rows)
+{
+    __shared__ double r[6][256];
+    const int tid = threadIdx.x;
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = INFINITY;
+        hi[d] = -INFINITY;
+    }
+    for (int64_t t = (int64_t)blockIdx.x * 256 + tid; t < m; t += (int64_t)gridDim.x * 256)
+        for (int d = 0; d < 3; ++d) {
+            const double v = targets[3 * t + d];
+            lo[d] = fmin(lo[d], v);
+            hi[d] = fmax(hi[d], v);
+        }
+    for (int d = 0; d < 3; ++d) {
+        r[d][tid] = lo[d];
+        r[3 + d][tid] = hi[d];
+    }
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h)
+            for (int d = 0; d < 3; ++d) {
+                r[d][tid] = fmin(r[d][tid], r[d][tid + h]);
+                r[3 + d][tid] = fmax(r[3 + d][tid], r[3 + d][tid + h]);
+            }
+        __syncthreads();
+    }
+    if (tid < 6) rows[6 * (int64_t)blockIdx.x + tid] = r[tid][0];
+}
+
+__global__ __launch_bounds__(64) void k_tree_tbox_final(const double *__restrict__ rows, int32_t n_rows,
+                                                        double *__restrict__ tbox)
+{
+    const int q = threadIdx.x;
+    if (q >= 6) return;
+    double v = q < 3 ? INFINITY : -INFINITY;
+    for (int i = 0; i < n_rows; ++i) v = q < 3 ? fmin(v, rows[6 * i + q]) : fmax(v, rows[6 * i + q]);
+    tbox[q] = v;
+}
+
+// Proxy partials of one work item (a cluster's sources [b, e), at most
+// kProxyChunk).  Per batch of 64 sources, 192 threads compute the 1-D
+// Lagrange values (one source and axis each) and 64 the charge and vector
+// weights into LDS; then each proxy accumulates over the batch.  Clusters
+// with at most 64 (128) proxies split the block into 4 (2) groups that take
+// alternate sources of each batch, their sums added in group order at the
+// end, so that the block's threads stay busy on flat clusters.
 __global__ __launch_bounds__(kProxyThreads) void k_tree_proxy_partial(const TreeNode *__restrict__ nodes,
                                                                       const Item *__restrict__ items,
                                                                       const TileSource *__restrict__ src,
-                                                                      double *__restrict__ part)
+                                                                      const double *__restrict__ tbox,
+                                                                      double theta2, double *__restrict__ part)
 {
     __shared__ double sl[3][64][kMaxDegree + 1];
     __shared__ double sw[64][4];
+    __shared__ double red[kProxyThreads][4];
     const Item it = items[blockIdx.x];
     const TreeNode &nd = nodes[it.node];
+    if (!acceptable(nd, tbox, theta2)) return;  // uniform per block
     const int tid = threadIdx.x;
     const int n1 = nd.deg[1] + 1, n2 = nd.deg[2] + 1, np = nd.n_proxy;
+    const int ng = np > 128 ? 1 : (np > 64 ? 2 : 4);
+    const int gs = kProxyThreads / ng, gi = tid / gs, kt = tid - gi * gs;
     int k0[kProxySlots], k1[kProxySlots], k2[kProxySlots];
     double acc[kProxySlots][4];
     for (int s = 0; s < kProxySlots; ++s) {
-        const int k = tid + kProxyThreads * s;
+        const int k = kt + gs * s;
         k2[s] = k % n2;
         k1[s] = (k / n2) % n1;
         k0[s] = k / (n1 * n2);
@@ -263,40 +370,57 @@ __global__ __launch_bounds__(kProxyThreads) void k_tree_proxy_partial(const Tree
     for (int32_t base = it.b; base < it.e; base += 64) {
         const int cnt = min(64, it.e - base);
         __syncthreads();
-        if (tid < cnt) {
-            const TileSource s = src[base + tid];
-            sw[tid][0] = s.ws;
-            sw[tid][1] = -s.wf * s.nx;
-            sw[tid][2] = -s.wf * s.ny;
-            sw[tid][3] = -s.wf * s.nz;
-            lagrange_1d(s.x, nd.lo[0], nd.hi[0], nd.deg[0], sl[0][tid]);
-            lagrange_1d(s.y, nd.lo[1], nd.hi[1], nd.deg[1], sl[1][tid]);
-            lagrange_1d(s.z, nd.lo[2], nd.hi[2], nd.deg[2], sl[2][tid]);
+        {
+            const int j = tid & 63, d = tid >> 6;
+            if (j < cnt) {
+                const TileSource q = src[base + j];
+                if (d == 3) {
+                    sw[j][0] = q.ws;
+                    sw[j][1] = -q.wf * q.nx;
+                    sw[j][2] = -q.wf * q.ny;
+                    sw[j][3] = -q.wf * q.nz;
+                } else {
+                    lagrange_1d(d == 0 ? q.x : (d == 1 ? q.y : q.z), nd.lo[d], nd.hi[d], nd.deg[d], sl[d][j]);
+                }
+            }
         }
         __syncthreads();
         for (int s = 0; s < kProxySlots; ++s) {
-            if (tid + kProxyThreads * s >= np) break;
-            for (int j = 0; j < cnt; ++j) {
+            if (kt + gs * s >= np) break;
+            for (int j = gi; j < cnt; j += ng) {
                 const double L = sl[0][j][k0[s]] * sl[1][j][k1[s]] * sl[2][j][k2[s]];
                 for (int c = 0; c < 4; ++c) acc[s][c] += L * sw[j][c];
             }
         }
     }
-    for (int s = 0; s < kProxySlots; ++s) {
-        const int k = tid + kProxyThreads * s;
-        if (k < np)
-            for (int c = 0; c < 4; ++c) part[it.part + 4 * (int64_t)k + c] = acc[s][c];
+    if (ng == 1) {
+        for (int s = 0; s < kProxySlots; ++s) {
+            const int k = kt + gs * s;
+            if (k < np)
+                for (int c = 0; c < 4; ++c) part[it.part + 4 * (int64_t)k + c] = acc[s][c];
+        }
+        return;
     }
+    for (int c = 0; c < 4; ++c) red[tid][c] = acc[0][c];
+    __syncthreads();
+    if (gi == 0 && kt < np)
+        for (int c = 0; c < 4; ++c) {
+            double v = red[kt][c];
+            for (int g = 1; g < ng; ++g) v += red[g * gs + kt][c];
+            part[it.part + 4 * (int64_t)kt + c] = v;
+        }
 }
 
 __global__ __launch_bounds__(kProxyThreads) void k_tree_proxy_reduce(const TreeNode *__restrict__ nodes,
                                                                      const ProxyCluster *__restrict__ pcl,
                                                                      const Item *__restrict__ items,
                                                                      const double *__restrict__ part,
-                                                                     Proxy *__restrict__ prox)
+                                                                     const double *__restrict__ tbox,
+                                                                     double theta2, Proxy *__restrict__ prox)
 {
     const ProxyCluster pc = pcl[blockIdx.x];
     const TreeNode &nd = nodes[pc.node];
+    if (!acceptable(nd, tbox, theta2)) return;
     const int n1 = nd.deg[1] + 1, n2 = nd.deg[2] + 1;
     for (int k = threadIdx.x; k < nd.n_proxy; k += kProxyThreads) {
         double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -343,17 +467,27 @@ __global__ __launch_bounds__(256) void k_tree_keys(const double *__restrict__ ta
 
 enum : int { kNone = 0, kTakeProxy = 1, kTakeDirect = 2, kOpen = 3 };
 
+// 1/|x - y| for the interactions: the hardware reciprocal square root
+// (relative error below 6e-8) and one Newton step, relative error ~5e-15,
+// far below the interpolation error that sets the treecode's accuracy.  Five
+// instructions where a correctly rounded one takes nine.
+__device__ __forceinline__ double rsqrt_1nr(double q)
+{
+    const double r = __builtin_amdgcn_rsq(q);
+    return fma(r, fma(-0.5 * q * r, r, 0.5), r);
+}
+
 __device__ __forceinline__ double proxy_term(double x, double y, double z, const Proxy &p)
 {
     const double ex = x - p.x, ey = y - p.y, ez = z - p.z;
-    const double ir = rsqrt(ex * ex + ey * ey + ez * ez);
+    const double ir = rsqrt_1nr(ex * ex + ey * ey + ez * ez);
     return p.q * ir + (p.px * ex + p.py * ey + p.pz * ez) * (ir * ir * ir);
 }
 
 __device__ __forceinline__ double source_term(double x, double y, double z, const TileSource &s)
 {
     const double ex = x - s.x, ey = y - s.y, ez = z - s.z;
-    const double ir = rsqrt(ex * ex + ey * ey + ez * ez);
+    const double ir = rsqrt_1nr(ex * ex + ey * ey + ez * ez);
     return s.ws * ir - s.wf * (ex * s.nx + ey * s.ny + ez * s.nz) * (ir * ir * ir);
 }
 
@@ -400,68 +534,144 @@ __device__ __forceinline__ void packed_sum(uint64_t mask, int32_t base, int32_t 
     tree_wave_sync();
 }
 
-__global__ __launch_bounds__(64) void k_tree_eval(const TreeNode *__restrict__ nodes, int32_t n_nodes,
+// What a lane does at node nd (kNone for lanes outside it).
+__device__ __forceinline__ int node_action(const TreeNode &nd, bool inside, double x, double y, double z,
+                                           double theta2)
+{
+    if (!inside) return kNone;
+    const double dx = x - nd.c[0], dy = y - nd.c[1], dz = z - nd.c[2];
+    const double R2 = dx * dx + dy * dy + dz * dz;
+    return nd.r2 < theta2 * R2 ? (nd.proxy >= 0 ? kTakeProxy : kTakeDirect) : (nd.leaf ? kTakeDirect : kOpen);
+}
+
+// Node nd summed into acc for the lanes that take it: by the whole wave
+// (wave-uniform loads, lanes that do not take it masked) when more than 32
+// lanes take it, else by the repacked wave.
+__device__ __forceinline__ void take_node(const TreeNode &nd, int act, const Proxy *__restrict__ prox,
+                                          const TileSource *__restrict__ src, double x, double y, double z,
+                                          double &acc, int64_t &n_prox, int64_t &n_dir, double *lx, double *ly,
+                                          double *lz, double *part)
+{
+    const auto pterm = [](double a, double b, double c, const Proxy &q) { return proxy_term(a, b, c, q); };
+    const auto sterm = [](double a, double b, double c, const TileSource &q) { return source_term(a, b, c, q); };
+    const uint64_t mp = __ballot(act == kTakeProxy), md = __ballot(act == kTakeDirect);
+    if (mp) {
+        if (__popcll(mp) > 32) {
+            // the taking lanes walk the proxies at wave-uniform addresses
+            // (scalar loads), two per iteration
+            if (act == kTakeProxy) {
+                const int32_t k_end = nd.proxy + nd.n_proxy;
+                int32_t k = nd.proxy;
+                for (; k + 1 < k_end; k += 2) {
+                    const Proxy a = prox[k], b = prox[k + 1];
+                    acc += proxy_term(x, y, z, a);
+                    acc += proxy_term(x, y, z, b);
+                }
+                if (k < k_end) acc += proxy_term(x, y, z, prox[k]);
+            }
+        } else {
+            packed_sum(mp, nd.proxy, nd.n_proxy, prox, x, y, z, acc, pterm, lx, ly, lz, part);
+        }
+        if (act == kTakeProxy) n_prox += nd.n_proxy;
+    }
+    if (md) {
+        if (__popcll(md) > 32) {
+            if (act == kTakeDirect) {
+                int32_t k = nd.b;
+                for (; k + 1 < nd.e; k += 2) {
+                    const TileSource a = src[k], b = src[k + 1];
+                    acc += source_term(x, y, z, a);
+                    acc += source_term(x, y, z, b);
+                }
+                if (k < nd.e) acc += source_term(x, y, z, src[k]);
+            }
+        } else {
+            packed_sum(md, nd.b, nd.e - nd.b, src, x, y, z, acc, sterm, lx, ly, lz, part);
+        }
+        if (act == kTakeDirect) n_dir += nd.e - nd.b;
+    }
+}
+
+// One wave per (group of 64 consecutive sorted targets, part).  The root
+// is decided first: lanes that take it whole are done in every part (part
+// 0 sums it); the others walk the part's node range.  With one part the
+// wave writes u (and the counts) itself, else its part's sums.
+__global__ __launch_bounds__(64) void k_tree_eval(const TreeNode *__restrict__ nodes,
                                                   const Proxy *__restrict__ prox,
                                                   const TileSource *__restrict__ src,
                                                   const double *__restrict__ targets,
-                                                  const uint32_t *__restrict__ order, int64_t m, double theta2,
-                                                  double *__restrict__ u, int64_t *__restrict__ counts)
+                                                  const uint32_t *__restrict__ order, int64_t t0, int64_t nt,
+                                                  double theta2, TreeParts parts, double *__restrict__ upart,
+                                                  int64_t *__restrict__ cpart, double *__restrict__ u,
+                                                  int64_t *__restrict__ counts)
 {
     __shared__ double lx[64], ly[64], lz[64], part[64];
-    const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    const bool valid = t < m;
-    const int64_t id = valid ? (int64_t)order[t] : 0;
+    const int64_t w = blockIdx.x;
+    const int64_t grp = w / parts.n;
+    const int p = (int)(w - grp * parts.n);
+    const int64_t lt = grp * 64 + threadIdx.x;  // position in this batch of sorted targets
+    const bool valid = lt < nt;
+    const int64_t id = valid ? (int64_t)order[t0 + lt] : 0;
     double x = 0.0, y = 0.0, z = 0.0;
     if (valid) {
         x = targets[3 * id];
         y = targets[3 * id + 1];
         z = targets[3 * id + 2];
     }
-    int32_t done_below = valid ? 0 : INT32_MAX;  // the lane is inside node j iff j >= done_below
     double acc = 0.0;
     int64_t n_prox = 0, n_dir = 0;
-    int32_t j = 0;
-    const auto pterm = [](double a, double b, double c, const Proxy &p) { return proxy_term(a, b, c, p); };
-    const auto sterm = [](double a, double b, double c, const TileSource &q) { return source_term(a, b, c, q); };
-    while (j < n_nodes) {
+    int32_t done_below = valid ? 0 : INT32_MAX;  // the lane is inside node j iff j >= done_below
+    {
+        const TreeNode &nd = nodes[0];
+        const int act = node_action(nd, valid, x, y, z, theta2);
+        if (p == 0) take_node(nd, act, prox, src, x, y, z, acc, n_prox, n_dir, lx, ly, lz, part);
+        if (act == kTakeProxy || act == kTakeDirect) done_below = INT32_MAX;
+    }
+    int32_t j = parts.lo[p];
+    const int32_t j_end = parts.hi[p];
+    while (j < j_end) {
         const TreeNode &nd = nodes[j];
-        const double dx = x - nd.c[0], dy = y - nd.c[1], dz = z - nd.c[2];
-        const double R2 = dx * dx + dy * dy + dz * dz;
-        int act = kNone;
-        if (j >= done_below)
-            act = nd.r2 < theta2 * R2 ? (nd.proxy >= 0 ? kTakeProxy : kTakeDirect) : (nd.leaf ? kTakeDirect : kOpen);
-        const uint64_t mp = __ballot(act == kTakeProxy), md = __ballot(act == kTakeDirect);
-        if (mp) {
-            if (__popcll(mp) > 32) {
-                for (int32_t k = nd.proxy; k < nd.proxy + nd.n_proxy; ++k) {
-                    const Proxy &p = prox[k];
-                    if (act == kTakeProxy) acc += proxy_term(x, y, z, p);
-                }
-            } else {
-                packed_sum(mp, nd.proxy, nd.n_proxy, prox, x, y, z, acc, pterm, lx, ly, lz, part);
-            }
-            if (act == kTakeProxy) n_prox += nd.n_proxy;
-        }
-        if (md) {
-            if (__popcll(md) > 32) {
-                for (int32_t k = nd.b; k < nd.e; ++k) {
-                    const TileSource &q = src[k];
-                    if (act == kTakeDirect) acc += source_term(x, y, z, q);
-                }
-            } else {
-                packed_sum(md, nd.b, nd.e - nd.b, src, x, y, z, acc, sterm, lx, ly, lz, part);
-            }
-            if (act == kTakeDirect) n_dir += nd.e - nd.b;
-        }
+        const int act = node_action(nd, j >= done_below, x, y, z, theta2);
+        take_node(nd, act, prox, src, x, y, z, acc, n_prox, n_dir, lx, ly, lz, part);
         if (act == kTakeProxy || act == kTakeDirect) done_below = nd.skip;
         j = __any(act == kOpen) ? j + 1 : nd.skip;
     }
-    if (valid) {
+    if (!valid) return;
+    if (parts.n == 1) {
         u[id] = acc * (1.0 / (4.0 * M_PI));
         if (counts) {
             counts[2 * id] = n_prox;
             counts[2 * id + 1] = n_dir;
         }
+    } else {
+        upart[p * nt + lt] = acc;
+        if (cpart) {
+            cpart[2 * (p * nt + lt)] = n_prox;
+            cpart[2 * (p * nt + lt) + 1] = n_dir;
+        }
+    }
+}
+
+// Per target: the parts' sums added in part order.
+__global__ __launch_bounds__(256) void k_tree_sum(const double *__restrict__ upart,
+                                                  const int64_t *__restrict__ cpart, int32_t n_parts,
+                                                  const uint32_t *__restrict__ order, int64_t t0, int64_t nt,
+                                                  double *__restrict__ u, int64_t *__restrict__ counts)
+{
+    const int64_t lt = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (lt >= nt) return;
+    const int64_t id = order[t0 + lt];
+    double s = 0.0;
+    for (int p = 0; p < n_parts; ++p) s += upart[p * nt + lt];
+    u[id] = s * (1.0 / (4.0 * M_PI));
+    if (counts) {
+        int64_t a = 0, b = 0;
+        for (int p = 0; p < n_parts; ++p) {
+            a += cpart[2 * (p * nt + lt)];
+            b += cpart[2 * (p * nt + lt) + 1];
+        }
+        counts[2 * id] = a;
+        counts[2 * id + 1] = b;
     }
 }
 
@@ -637,6 +847,12 @@ dtn_status dtn_tree_potential(dtn_tree t, const double *neumann, const double *t
                                                           (uint32_t *)nullptr, (const uint32_t *)nullptr,
                                                           (uint32_t *)nullptr, (int)m, 0, 30, s);
         if (e != hipSuccess) return fail(DTN_E_DEVICE, at + hipGetErrorString(e));
+        // targets per eval batch: the parts' partial sums of a batch stay
+        // within a few hundred MB
+        const TreeParts &P = H.parts;
+        const int64_t batch = std::min<int64_t>(m, kEvalBatch);
+        const int64_t n_up = P.n > 1 ? (int64_t)P.n * batch : 1;
+        const int nb_box = (int)std::min<int64_t>(64, (m + 255) / 256);
         const size_t o_src = 0;
         const size_t o_part = o_src + align256(sizeof(TileSource) * (size_t)n_src);
         const size_t o_prox = o_part + align256(sizeof(double) * (size_t)std::max<int64_t>(H.part_len, 1));
@@ -644,7 +860,11 @@ dtn_status dtn_tree_potential(dtn_tree t, const double *neumann, const double *t
         const size_t o_sorted = o_keys + align256(sizeof(uint32_t) * (size_t)m);
         const size_t o_ids = o_sorted + align256(sizeof(uint32_t) * (size_t)m);
         const size_t o_order = o_ids + align256(sizeof(uint32_t) * (size_t)m);
-        const size_t o_tmp = o_order + align256(sizeof(uint32_t) * (size_t)m);
+        const size_t o_rows = o_order + align256(sizeof(uint32_t) * (size_t)m);
+        const size_t o_tbox = o_rows + align256(sizeof(double) * 6 * (size_t)nb_box);
+        const size_t o_up = o_tbox + align256(sizeof(double) * 6);
+        const size_t o_cp = o_up + align256(sizeof(double) * (size_t)n_up);
+        const size_t o_tmp = o_cp + (counts && P.n > 1 ? align256(2 * sizeof(int64_t) * (size_t)n_up) : 0);
         const size_t bytes = o_tmp + align256(std::max<size_t>(sort_bytes, 1));
         char *w = nullptr;
         e = hipMallocAsync((void **)&w, bytes, s);
@@ -654,16 +874,22 @@ dtn_status dtn_tree_potential(dtn_tree t, const double *neumann, const double *t
         Proxy *prox = (Proxy *)(w + o_prox);
         uint32_t *keys = (uint32_t *)(w + o_keys), *sorted = (uint32_t *)(w + o_sorted);
         uint32_t *ids = (uint32_t *)(w + o_ids), *order = (uint32_t *)(w + o_order);
+        double *rows = (double *)(w + o_rows), *tbox = (double *)(w + o_tbox);
+        double *upart = P.n > 1 ? (double *)(w + o_up) : nullptr;
+        int64_t *cpart = counts && P.n > 1 ? (int64_t *)(w + o_cp) : nullptr;
         dtn_status st = launch_tile_sources(*t->t.plan, neumann, t->t.d_slot, src, s);
         if (st != DTN_OK) {
             (void)hipFreeAsync(w, s);
             return st;
         }
+        const double theta2 = theta * theta;
+        hipLaunchKernelGGL(k_tree_tbox_partial, dim3((unsigned)nb_box), dim3(256), 0, s, targets, m, rows);
+        hipLaunchKernelGGL(k_tree_tbox_final, dim3(1), dim3(64), 0, s, rows, (int32_t)nb_box, tbox);
         if (!H.items.empty()) {
             hipLaunchKernelGGL(k_tree_proxy_partial, dim3((unsigned)H.items.size()), dim3(kProxyThreads), 0, s,
-                               t->t.d_nodes, t->t.d_items, src, part);
+                               t->t.d_nodes, t->t.d_items, src, tbox, theta2, part);
             hipLaunchKernelGGL(k_tree_proxy_reduce, dim3((unsigned)H.pcl.size()), dim3(kProxyThreads), 0, s,
-                               t->t.d_nodes, t->t.d_pcl, t->t.d_items, part, prox);
+                               t->t.d_nodes, t->t.d_pcl, t->t.d_items, part, tbox, theta2, prox);
         }
         double sc[3];
         for (int d = 0; d < 3; ++d) sc[d] = H.box_ext[d] > 0.0 ? 1024.0 / H.box_ext[d] : 0.0;
@@ -673,10 +899,14 @@ dtn_status dtn_tree_potential(dtn_tree t, const double *neumann, const double *t
         if (e == hipSuccess)
             e = hipcub::DeviceRadixSort::SortPairs((void *)(w + o_tmp), sort_bytes, keys, sorted, ids, order, (int)m,
                                                    0, 30, s);
-        if (e == hipSuccess) {
-            const double theta2 = theta * theta;
-            hipLaunchKernelGGL(k_tree_eval, dim3((unsigned)((m + 63) / 64)), dim3(64), 0, s, t->t.d_nodes,
-                               (int32_t)H.nodes.size(), prox, src, targets, order, m, theta2, u_out, counts);
+        for (int64_t t0 = 0; e == hipSuccess && t0 < m; t0 += batch) {
+            const int64_t nt = std::min(batch, m - t0);
+            const int64_t waves = (nt + 63) / 64 * P.n;
+            hipLaunchKernelGGL(k_tree_eval, dim3((unsigned)waves), dim3(64), 0, s, t->t.d_nodes, prox, src, targets,
+                               order, t0, nt, theta2, P, upart, cpart, u_out, counts);
+            if (P.n > 1)
+                hipLaunchKernelGGL(k_tree_sum, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, upart, cpart,
+                                   P.n, order, t0, nt, u_out, counts);
             e = hipGetLastError();
         }
         const hipError_t ef = hipFreeAsync(w, s);

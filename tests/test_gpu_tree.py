@@ -8,8 +8,9 @@ against the oracle's eq. bw03 sum): within the interpolation error the oracle
 measures for the same degree and theta, on every target of larger sets; equal
 to rounding when theta is so small that nothing is taken whole.  Edge cases:
 no targets, one target, a ragged last wave, far targets (the root's proxies
-alone), target order (each target's sum is bit-identical whatever its wave
-companions), argument errors.
+alone), target order (a target's sum depends on its wave companions through
+rounding only), proxies built only for clusters some target of the call can
+take, calls beyond one traversal batch (2^22 targets), argument errors.
 """
 import numpy as np
 import pytest
@@ -131,6 +132,45 @@ def test_tree_edge_cases():
     assert torch.equal(c1[perm], c2)  # the same interactions
     scale = float(u1.abs().max())
     torch.testing.assert_close(u2, u1[perm], rtol=1e-13, atol=1e-13 * scale)
+
+
+def test_tree_proxy_selection_and_batches():
+    """Interior targets get the same interactions, and sums equal to
+    rounding, whether or not a far target rides along (it makes the root's
+    proxies needed, which interior targets alone never build); a call of
+    more than 2^22 targets (two traversal batches) equals two smaller calls
+    to rounding, with the same interaction counts."""
+    dtn = _dtn()
+    gd, pd, ps, sig = _cube()
+    plan = dtn.Plan(dtn.Geometry(gd), pd)
+    neu = torch.tensor(np.concatenate(sig), device="cuda")
+    tree = dtn.Tree(plan, 6, 64)
+    print("[gpu] tree proxy selection", flush=True)
+    inner = np.random.default_rng(21).uniform(0.05, 0.95, (5000, 3))
+    both = np.concatenate([inner, [[40.0, 0.5, 0.5]]])
+    c1 = torch.zeros((len(inner), 2), dtype=torch.int64, device="cuda")
+    c2 = torch.zeros((len(both), 2), dtype=torch.int64, device="cuda")
+    u1 = tree.potential(neu, torch.tensor(inner, device="cuda"), counts=c1)
+    u2 = tree.potential(neu, torch.tensor(both, device="cuda"), counts=c2)
+    torch.cuda.synchronize()
+    assert torch.equal(c2[: len(inner)], c1)
+    assert c2[-1].tolist() == [343, 0]  # the root's proxies, built for this call
+    scale = float(u1.abs().max())
+    torch.testing.assert_close(u2[: len(inner)], u1, rtol=1e-13, atol=1e-13 * scale)
+    print("[gpu] tree batches", flush=True)
+    n = (1 << 22) + 4096
+    big = torch.rand((n, 3), generator=torch.Generator().manual_seed(5), dtype=torch.float64).cuda()
+    cb = torch.zeros((n, 2), dtype=torch.int64, device="cuda")
+    ub = tree.potential(neu, big, counts=cb)
+    h = n // 2
+    ca, cc = torch.zeros((h, 2), dtype=torch.int64, device="cuda"), torch.zeros((n - h, 2), dtype=torch.int64,
+                                                                                 device="cuda")
+    ua = torch.cat([tree.potential(neu, big[:h].contiguous(), counts=ca),
+                    tree.potential(neu, big[h:].contiguous(), counts=cc)])
+    torch.cuda.synchronize()
+    assert torch.equal(torch.cat([ca, cc]), cb)
+    scale = float(ub.abs().max())
+    torch.testing.assert_close(ub, ua, rtol=1e-13, atol=1e-13 * scale)
 
 
 def test_tree_arguments_are_checked():
