@@ -71,9 +71,16 @@ struct TreeNode {
     int32_t proxy;    // first proxy, -1 without proxies
     int32_t n_proxy;  // (deg0 + 1)(deg1 + 1)(deg2 + 1)
     int32_t deg[3];
-    int32_t pad[3];
+    // In-plane cluster: its sources lie on one plane x_axis = c[axis] and
+    // their normals are exactly +-e_axis (so is every proxy vector); -1
+    // otherwise.  Such a cluster's proxies are stored in its plane's frame.
+    int32_t axis;
+    int32_t pad[2];
 };
 
+// A proxy: position, charge and vector.  Of an in-plane cluster (axis a,
+// b = a + 1, c = a + 2 mod 3): x, y are its coordinates along b and c, z
+// the plane's, px the vector's component along a (py = pz = 0).
 struct Proxy {
     double x, y, z, q, px, py, pz, pad;
 };
@@ -187,8 +194,8 @@ void build_node(const std::vector<double> &pos, const int8_t *face, int32_t b, i
 // below it straddles an edge of the box: each lies in one plane and its
 // proxy grid is two-dimensional (degree 0 along the normal), 49 proxies at
 // degree 6 where a cluster across an edge needs 343.
-void build_tree(const std::vector<double> &pos, const std::vector<int8_t> &face, int degree, int leaf_size,
-                HostTree &T)
+void build_tree(const std::vector<double> &pos, const std::vector<int8_t> &face, const std::vector<int8_t> &along,
+                int degree, int leaf_size, HostTree &T)
 {
     const int32_t n = (int32_t)(pos.size() / 3);
     double lo[3], hi[3], big = 0.0;
@@ -212,6 +219,19 @@ void build_tree(const std::vector<double> &pos, const std::vector<int8_t> &face,
     build_node(pos, face.data(), 0, n, degree, leaf_size, kPadRel * big, T, tmp);
     T.slot.resize(n);
     for (int32_t i = 0; i < n; ++i) T.slot[T.perm[i]] = i;
+    // in-plane clusters: every source's normal exactly along one axis a, and
+    // every source on one plane x_a = const (then the cluster's degree along
+    // a is 0 and its proxies' coordinate along a is the box centre's)
+    for (TreeNode &nd : T.nodes) {
+        nd.axis = -1;
+        const int a = along[T.perm[nd.b]];
+        if (a < 0 || nd.deg[a] != 0) continue;
+        const double xa = pos[3 * (size_t)T.perm[nd.b] + a];
+        bool ok = true;
+        for (int32_t i = nd.b; i < nd.e && ok; ++i)
+            ok = along[T.perm[i]] == a && pos[3 * (size_t)T.perm[i] + a] == xa;
+        if (ok) nd.axis = a;
+    }
     // the root's subtrees as traversal parts (sibling subtrees are
     // contiguous in pre-order, so any overflow joins the last part)
     TreeParts &P = T.parts;
@@ -426,15 +446,27 @@ __global__ __launch_bounds__(kProxyThreads) void k_tree_proxy_reduce(const TreeN
         double v[4] = {0.0, 0.0, 0.0, 0.0};
         for (int32_t i = pc.item_b; i < pc.item_e; ++i)
             for (int c = 0; c < 4; ++c) v[c] += part[items[i].part + 4 * (int64_t)k + c];
+        const double pt[3] = {cheb_point(nd, 0, k / (n1 * n2)), cheb_point(nd, 1, (k / n2) % n1),
+                              cheb_point(nd, 2, k % n2)};
         Proxy o;
-        o.x = cheb_point(nd, 0, k / (n1 * n2));
-        o.y = cheb_point(nd, 1, (k / n2) % n1);
-        o.z = cheb_point(nd, 2, k % n2);
         o.q = v[0];
-        o.px = v[1];
-        o.py = v[2];
-        o.pz = v[3];
         o.pad = 0.0;
+        if (nd.axis >= 0) {  // the plane's frame
+            const int a = nd.axis;
+            o.x = pt[(a + 1) % 3];
+            o.y = pt[(a + 2) % 3];
+            o.z = pt[a];
+            o.px = v[1 + a];
+            o.py = 0.0;
+            o.pz = 0.0;
+        } else {
+            o.x = pt[0];
+            o.y = pt[1];
+            o.z = pt[2];
+            o.px = v[1];
+            o.py = v[2];
+            o.pz = v[3];
+        }
         prox[nd.proxy + k] = o;
     }
 }
@@ -482,6 +514,16 @@ __device__ __forceinline__ double proxy_term(double x, double y, double z, const
     const double ex = x - p.x, ey = y - p.y, ez = z - p.z;
     const double ir = rsqrt_1nr(ex * ex + ey * ey + ez * ez);
     return p.q * ir + (p.px * ex + p.py * ey + p.pz * ez) * (ir * ir * ir);
+}
+
+// The same term for a proxy of an in-plane cluster, with the target in the
+// plane's frame: (tb, tc) its in-plane coordinates, ea its height above the
+// plane (the same for every proxy of the cluster).
+__device__ __forceinline__ double plane_proxy_term(double tb, double tc, double ea, const Proxy &p)
+{
+    const double eb = tb - p.x, ec = tc - p.y;
+    const double ir = rsqrt_1nr(fma(eb, eb, fma(ec, ec, ea * ea)));
+    return p.q * ir + (p.px * ea) * (ir * ir * ir);
 }
 
 __device__ __forceinline__ double source_term(double x, double y, double z, const TileSource &s)
@@ -555,7 +597,30 @@ __device__ __forceinline__ void take_node(const TreeNode &nd, int act, const Pro
     const auto pterm = [](double a, double b, double c, const Proxy &q) { return proxy_term(a, b, c, q); };
     const auto sterm = [](double a, double b, double c, const TileSource &q) { return source_term(a, b, c, q); };
     const uint64_t mp = __ballot(act == kTakeProxy), md = __ballot(act == kTakeDirect);
-    if (mp) {
+    if (mp && nd.axis >= 0) {
+        // in-plane cluster: the target in the plane's frame
+        const int a = nd.axis;
+        const double ta = a == 0 ? x : (a == 1 ? y : z);
+        const double tb = a == 0 ? y : (a == 1 ? z : x);
+        const double tc = a == 0 ? z : (a == 1 ? x : y);
+        const double ea = ta - nd.c[a];
+        const auto fterm = [](double b, double c, double h, const Proxy &q) { return plane_proxy_term(b, c, h, q); };
+        if (__popcll(mp) > 32) {
+            if (act == kTakeProxy) {
+                const int32_t k_end = nd.proxy + nd.n_proxy;
+                int32_t k = nd.proxy;
+                for (; k + 1 < k_end; k += 2) {
+                    const Proxy pa = prox[k], pb = prox[k + 1];
+                    acc += plane_proxy_term(tb, tc, ea, pa);
+                    acc += plane_proxy_term(tb, tc, ea, pb);
+                }
+                if (k < k_end) acc += plane_proxy_term(tb, tc, ea, prox[k]);
+            }
+        } else {
+            packed_sum(mp, nd.proxy, nd.n_proxy, prox, tb, tc, ea, acc, fterm, lx, ly, lz, part);
+        }
+        if (act == kTakeProxy) n_prox += nd.n_proxy;
+    } else if (mp) {
         if (__popcll(mp) > 32) {
             // the taking lanes walk the proxies at wave-uniform addresses
             // (scalar loads), two per iteration
@@ -595,21 +660,29 @@ __device__ __forceinline__ void take_node(const TreeNode &nd, int act, const Pro
 // One wave per (group of 64 consecutive sorted targets, part).  The root
 // is decided first: lanes that take it whole are done in every part (part
 // 0 sums it); the others walk the part's node range.  With one part the
-// wave writes u (and the counts) itself, else its part's sums.
-__global__ __launch_bounds__(64) void k_tree_eval(const TreeNode *__restrict__ nodes,
-                                                  const Proxy *__restrict__ prox,
-                                                  const TileSource *__restrict__ src,
-                                                  const double *__restrict__ targets,
-                                                  const uint32_t *__restrict__ order, int64_t t0, int64_t nt,
-                                                  double theta2, TreeParts parts, double *__restrict__ upart,
-                                                  int64_t *__restrict__ cpart, double *__restrict__ u,
-                                                  int64_t *__restrict__ counts)
+// wave writes u (and the counts) itself, else its part's sums.  A block
+// holds kEvalWaves independent waves, each with its own LDS rows: one per
+// block measured fastest (blocks of 4 waves issued VALU work 45 % of the
+// cycles instead of 61 %, 5.2-5.5 ms instead of 4.1-4.7 ms per launch).
+constexpr int kEvalWaves = 1;
+__global__ __launch_bounds__(64 * kEvalWaves) void k_tree_eval(const TreeNode *__restrict__ nodes,
+                                                               const Proxy *__restrict__ prox,
+                                                               const TileSource *__restrict__ src,
+                                                               const double *__restrict__ targets,
+                                                               const uint32_t *__restrict__ order, int64_t t0,
+                                                               int64_t nt, int64_t n_waves, double theta2,
+                                                               TreeParts parts, double *__restrict__ upart,
+                                                               int64_t *__restrict__ cpart, double *__restrict__ u,
+                                                               int64_t *__restrict__ counts)
 {
-    __shared__ double lx[64], ly[64], lz[64], part[64];
-    const int64_t w = blockIdx.x;
+    __shared__ double lx_[kEvalWaves][64], ly_[kEvalWaves][64], lz_[kEvalWaves][64], part_[kEvalWaves][64];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    const int64_t w = (int64_t)blockIdx.x * kEvalWaves + wv;
+    if (w >= n_waves) return;  // the whole wave
+    double *lx = lx_[wv], *ly = ly_[wv], *lz = lz_[wv], *part = part_[wv];
     const int64_t grp = w / parts.n;
     const int p = (int)(w - grp * parts.n);
-    const int64_t lt = grp * 64 + threadIdx.x;  // position in this batch of sorted targets
+    const int64_t lt = grp * 64 + __lane_id();  // position in this batch of sorted targets
     const bool valid = lt < nt;
     const int64_t id = valid ? (int64_t)order[t0 + lt] : 0;
     double x = 0.0, y = 0.0, z = 0.0;
@@ -694,6 +767,21 @@ std::vector<int8_t> tile_faces(const dtn_patch *patches, int64_t n)
     return f;
 }
 
+// Per tile source: the axis its tile's normal lies exactly along (the other
+// two components exactly 0), else -1.
+std::vector<int8_t> tile_axes(const dtn_patch *patches, int64_t n)
+{
+    std::vector<int8_t> f((size_t)n * 16);
+    for (int64_t i = 0; i < n; ++i) {
+        const double *nv = patches[i].n;
+        int a = -1;
+        for (int d = 0; d < 3; ++d)
+            if (nv[d] != 0.0 && nv[(d + 1) % 3] == 0.0 && nv[(d + 2) % 3] == 0.0) a = d;
+        std::fill(f.begin() + 16 * i, f.begin() + 16 * (i + 1), (int8_t)a);
+    }
+    return f;
+}
+
 std::vector<double> tile_positions(const dtn_patch *patches, int64_t n)
 {
     std::vector<double> gx, gw;
@@ -768,7 +856,8 @@ dtn_status dtn_create_tree(dtn_plan p, int32_t degree, int32_t leaf_size, dtn_tr
         const std::vector<double> pos = tile_positions(P.patches.data(), (int64_t)P.patches.size());
         std::unique_ptr<dtn_tree_s> T(new dtn_tree_s());
         T->t.plan = &P;
-        build_tree(pos, tile_faces(P.patches.data(), (int64_t)P.patches.size()), degree, leaf_size, T->t.host);
+        build_tree(pos, tile_faces(P.patches.data(), (int64_t)P.patches.size()),
+                   tile_axes(P.patches.data(), (int64_t)P.patches.size()), degree, leaf_size, T->t.host);
         hipError_t e = hipGetDevice(&T->t.device);
         if (e == hipSuccess) e = upload_vec(T->t.host.nodes, &T->t.d_nodes);
         if (e == hipSuccess) e = upload_vec(T->t.host.slot, &T->t.d_slot);
@@ -804,7 +893,8 @@ dtn_status dtn_tree_layout(const dtn_patch *patches, int64_t n_patches, int32_t 
         if (degree < 1 || degree > kMaxDegree) return fail(DTN_E_ARG, at + "degree outside [1, 8]");
         if (leaf_size < 8 || leaf_size > 4096) return fail(DTN_E_ARG, at + "leaf_size outside [8, 4096]");
         HostTree H;
-        build_tree(tile_positions(patches, n_patches), tile_faces(patches, n_patches), degree, leaf_size, H);
+        build_tree(tile_positions(patches, n_patches), tile_faces(patches, n_patches), tile_axes(patches, n_patches),
+                   degree, leaf_size, H);
         *n_nodes = (int64_t)H.nodes.size();
         if ((int64_t)H.nodes.size() > cap) return fail(DTN_E_ARG, at + "cap below the number of nodes");
         for (size_t j = 0; j < H.nodes.size(); ++j) {
@@ -902,8 +992,9 @@ dtn_status dtn_tree_potential(dtn_tree t, const double *neumann, const double *t
         for (int64_t t0 = 0; e == hipSuccess && t0 < m; t0 += batch) {
             const int64_t nt = std::min(batch, m - t0);
             const int64_t waves = (nt + 63) / 64 * P.n;
-            hipLaunchKernelGGL(k_tree_eval, dim3((unsigned)waves), dim3(64), 0, s, t->t.d_nodes, prox, src, targets,
-                               order, t0, nt, theta2, P, upart, cpart, u_out, counts);
+            hipLaunchKernelGGL(k_tree_eval, dim3((unsigned)((waves + kEvalWaves - 1) / kEvalWaves)),
+                               dim3(64 * kEvalWaves), 0, s, t->t.d_nodes, prox, src, targets, order, t0, nt, waves,
+                               theta2, P, upart, cpart, u_out, counts);
             if (P.n > 1)
                 hipLaunchKernelGGL(k_tree_sum, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, upart, cpart,
                                    P.n, order, t0, nt, u_out, counts);

@@ -64,6 +64,36 @@ def test_tree_matches_oracle_treecode(degree, leaf, theta):
     np.testing.assert_allclose(u.cpu().numpy(), ref, rtol=0, atol=1e-11 * np.max(np.abs(ref)))
 
 
+def test_tree_tilted_normals_take_the_general_path():
+    """Clusters whose tiles' normals lie exactly along an axis keep their
+    proxies in the plane's frame; a tile whose normal is tilted by 1e-13
+    (still a box tiling) keeps its cluster on the general three-component
+    path.  Both plans match the oracle treecode on their own data, with the
+    same interaction counts."""
+    dtn = _dtn()
+    gd, pd, ps, sig = _cube()
+    tilted = {k: v.copy() for k, v in pd.items()}
+    rng = np.random.default_rng(13)
+    idx = rng.choice(len(pd["h"]), 40, replace=False)
+    for i in idx:
+        a = int(np.argmax(np.abs(tilted["n"][i])))
+        tilted["n"][i][(a + 1) % 3] = 1e-13
+    tps = OP.patches_from_desc(tilted, gd)
+    tg = _targets(24, 8, 99)
+    print("[gpu] tree tilted normals", flush=True)
+    for desc, pats in ((pd, ps), (tilted, tps)):
+        y, a, b = OT.tile_sources(pats, sig, OW.Geometry(gd))
+        ref, ref_cnt = OT.evaluate(OT.build_tree(y, OT.tile_faces(pats), 64, 6), y, a, b, tg, 0.5)
+        plan = dtn.Plan(dtn.Geometry(gd), desc)
+        tree = dtn.Tree(plan, 6, 64)
+        cnt = torch.zeros((len(tg), 2), dtype=torch.int64, device="cuda")
+        u = tree.potential(torch.tensor(np.concatenate(sig), device="cuda"), torch.tensor(tg, device="cuda"), 0.5,
+                           counts=cnt)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(cnt.cpu().numpy(), ref_cnt)
+        np.testing.assert_allclose(u.cpu().numpy(), ref, rtol=0, atol=1e-11 * np.max(np.abs(ref)))
+
+
 @pytest.mark.parametrize("m_tiles,n_targets", [(16, 20_000), (48, 4_099)])
 def test_tree_vs_direct_on_every_target(m_tiles, n_targets):
     """Degree 6, theta 0.5, targets down to 0.02 from the faces: every target
