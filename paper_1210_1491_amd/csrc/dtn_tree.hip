@@ -78,12 +78,19 @@ struct TreeNode {
     int32_t pad[2];
 };
 
-// A proxy: position, charge and vector.  Of an in-plane cluster (axis a,
-// b = a + 1, c = a + 2 mod 3): x, y are its coordinates along b and c, z
-// the plane's, px the vector's component along a (py = pz = 0).
+// A proxy: position, charge and vector.
 struct Proxy {
     double x, y, z, q, px, py, pz, pad;
 };
+
+// The same 64 bytes for a proxy of an in-plane cluster (axis a, b = a + 1,
+// c = a + 2 mod 3): its coordinates along b and c, its charge, the vector's
+// component along a (the others are 0), then the plane's coordinate; what
+// an interaction reads is the first 32 bytes.
+struct PlaneProxy {
+    double b, c, q, pn, a, pad[3];
+};
+static_assert(sizeof(PlaneProxy) == sizeof(Proxy), "proxy layouts");
 
 struct Item {      // proxy pass work item: one cluster's sources [b, e)
     int32_t node, b, e, pad;
@@ -448,26 +455,28 @@ __global__ __launch_bounds__(kProxyThreads) void k_tree_proxy_reduce(const TreeN
             for (int c = 0; c < 4; ++c) v[c] += part[items[i].part + 4 * (int64_t)k + c];
         const double pt[3] = {cheb_point(nd, 0, k / (n1 * n2)), cheb_point(nd, 1, (k / n2) % n1),
                               cheb_point(nd, 2, k % n2)};
-        Proxy o;
-        o.q = v[0];
-        o.pad = 0.0;
         if (nd.axis >= 0) {  // the plane's frame
             const int a = nd.axis;
-            o.x = pt[(a + 1) % 3];
-            o.y = pt[(a + 2) % 3];
-            o.z = pt[a];
-            o.px = v[1 + a];
-            o.py = 0.0;
-            o.pz = 0.0;
+            PlaneProxy o;
+            o.b = pt[(a + 1) % 3];
+            o.c = pt[(a + 2) % 3];
+            o.q = v[0];
+            o.pn = v[1 + a];
+            o.a = pt[a];
+            o.pad[0] = o.pad[1] = o.pad[2] = 0.0;
+            reinterpret_cast<PlaneProxy *>(prox)[nd.proxy + k] = o;
         } else {
+            Proxy o;
             o.x = pt[0];
             o.y = pt[1];
             o.z = pt[2];
+            o.q = v[0];
             o.px = v[1];
             o.py = v[2];
             o.pz = v[3];
+            o.pad = 0.0;
+            prox[nd.proxy + k] = o;
         }
-        prox[nd.proxy + k] = o;
     }
 }
 
@@ -519,11 +528,11 @@ __device__ __forceinline__ double proxy_term(double x, double y, double z, const
 // The same term for a proxy of an in-plane cluster, with the target in the
 // plane's frame: (tb, tc) its in-plane coordinates, ea its height above the
 // plane (the same for every proxy of the cluster).
-__device__ __forceinline__ double plane_proxy_term(double tb, double tc, double ea, const Proxy &p)
+__device__ __forceinline__ double plane_proxy_term(double tb, double tc, double ea, const PlaneProxy &p)
 {
-    const double eb = tb - p.x, ec = tc - p.y;
+    const double eb = tb - p.b, ec = tc - p.c;
     const double ir = rsqrt_1nr(fma(eb, eb, fma(ec, ec, ea * ea)));
-    return p.q * ir + (p.px * ea) * (ir * ir * ir);
+    return p.q * ir + (p.pn * ea) * (ir * ir * ir);
 }
 
 __device__ __forceinline__ double source_term(double x, double y, double z, const TileSource &s)
@@ -604,20 +613,33 @@ __device__ __forceinline__ void take_node(const TreeNode &nd, int act, const Pro
         const double tb = a == 0 ? y : (a == 1 ? z : x);
         const double tc = a == 0 ? z : (a == 1 ? x : y);
         const double ea = ta - nd.c[a];
-        const auto fterm = [](double b, double c, double h, const Proxy &q) { return plane_proxy_term(b, c, h, q); };
+        const auto fterm = [](double b, double c, double h, const PlaneProxy &q) {
+            return plane_proxy_term(b, c, h, q);
+        };
+        const PlaneProxy *pp = reinterpret_cast<const PlaneProxy *>(prox);
         if (__popcll(mp) > 32) {
             if (act == kTakeProxy) {
-                const int32_t k_end = nd.proxy + nd.n_proxy;
-                int32_t k = nd.proxy;
-                for (; k + 1 < k_end; k += 2) {
-                    const Proxy pa = prox[k], pb = prox[k + 1];
+                // two proxies per iteration, the next two loaded before the
+                // current two are summed (their latency under the arithmetic)
+                const PlaneProxy *e = pp + nd.proxy;
+                const int32_t n = nd.n_proxy;
+                int32_t k = 0;
+                if (n >= 2) {
+                    PlaneProxy pa = e[0], pb = e[1];
+                    for (k = 2; k + 1 < n; k += 2) {
+                        const PlaneProxy pc = e[k], pd = e[k + 1];
+                        acc += plane_proxy_term(tb, tc, ea, pa);
+                        acc += plane_proxy_term(tb, tc, ea, pb);
+                        pa = pc;
+                        pb = pd;
+                    }
                     acc += plane_proxy_term(tb, tc, ea, pa);
                     acc += plane_proxy_term(tb, tc, ea, pb);
                 }
-                if (k < k_end) acc += plane_proxy_term(tb, tc, ea, prox[k]);
+                if (k < n) acc += plane_proxy_term(tb, tc, ea, e[k]);
             }
         } else {
-            packed_sum(mp, nd.proxy, nd.n_proxy, prox, tb, tc, ea, acc, fterm, lx, ly, lz, part);
+            packed_sum(mp, nd.proxy, nd.n_proxy, pp, tb, tc, ea, acc, fterm, lx, ly, lz, part);
         }
         if (act == kTakeProxy) n_prox += nd.n_proxy;
     } else if (mp) {
