@@ -573,7 +573,23 @@ __device__ __forceinline__ void packed_sum(uint64_t mask, int32_t base, int32_t 
     double a = 0.0;
     if (t < k) {
         const double px = lx[t], py = ly[t], pz = lz[t];
-        for (int32_t e = sub; e < count; e += g) a += term(px, py, pz, E[base + e]);
+        // entries sub, sub + g, ... two per iteration, the next two loaded
+        // before the current two are summed
+        const Entry *Q = E + base;
+        int32_t e = sub;
+        if (e + g < count) {
+            Entry ea = Q[e], eb = Q[e + g];
+            for (e += 2 * g; e + g < count; e += 2 * g) {
+                const Entry ec = Q[e], ed = Q[e + g];
+                a += term(px, py, pz, ea);
+                a += term(px, py, pz, eb);
+                ea = ec;
+                eb = ed;
+            }
+            a += term(px, py, pz, ea);
+            a += term(px, py, pz, eb);
+        }
+        if (e < count) a += term(px, py, pz, Q[e]);
     }
     part[lane] = a;
     tree_wave_sync();
