@@ -381,16 +381,18 @@ __global__ __launch_bounds__(kLuBlock) void k_lu32(DevClass *__restrict__ classe
 // --------------------------------------------------------------- potential
 
 template <int DATA>
+// Four tiles per 64-thread block, 16 threads (one per Gauss point) each.
 __global__ __launch_bounds__(64) void k_tile_sources(DevGeom g, const dtn_patch *__restrict__ patches,
                                                      const int32_t *__restrict__ pclass,
                                                      const DevClass *__restrict__ classes,
                                                      const int64_t *__restrict__ panel_off,
                                                      const double *__restrict__ neumann,
                                                      const int32_t *__restrict__ slot,
-                                                     TileSource *__restrict__ src)
+                                                     TileSource *__restrict__ src, int64_t n_tiles)
 {
-    const int pi = blockIdx.x, q = threadIdx.x;
-    if (q >= 16) return;
+    const int64_t pi = (int64_t)blockIdx.x * 4 + threadIdx.x / 16;
+    const int q = threadIdx.x % 16;
+    if (pi >= n_tiles) return;
     const dtn_patch p = patches[pi];
     const DevClass &cl = classes[pclass[pi]];
     double t2[3];
@@ -703,16 +705,17 @@ dtn_status launch_lu32(const Plan &p, hipStream_t s)
 dtn_status launch_tile_sources(const Plan &p, const double *neumann, const int32_t *slot, TileSource *src,
                                hipStream_t s)
 {
-    const dim3 grid((unsigned)p.patches.size());
+    const int64_t n = (int64_t)p.patches.size();
+    const dim3 grid((unsigned)((n + 3) / 4));
     if (p.geom->dev.data_kind == DTN_DATA_TABULATED)
         hipLaunchKernelGGL(k_tile_sources<DTN_DATA_TABULATED>, grid, dim3(64), 0, s, p.geom->dev, p.d_patches,
-                           p.d_patch_class, p.d_classes, p.d_panel_off, neumann, slot, src);
+                           p.d_patch_class, p.d_classes, p.d_panel_off, neumann, slot, src, n);
     else if (p.geom->dev.data_kind == DTN_DATA_POINT_SOURCES)
         hipLaunchKernelGGL(k_tile_sources<DTN_DATA_POINT_SOURCES>, grid, dim3(64), 0, s, p.geom->dev, p.d_patches,
-                           p.d_patch_class, p.d_classes, p.d_panel_off, neumann, slot, src);
+                           p.d_patch_class, p.d_classes, p.d_panel_off, neumann, slot, src, n);
     else
         hipLaunchKernelGGL(k_tile_sources<DTN_DATA_HARMONIC_QUADRATIC>, grid, dim3(64), 0, s, p.geom->dev,
-                           p.d_patches, p.d_patch_class, p.d_classes, p.d_panel_off, neumann, slot, src);
+                           p.d_patches, p.d_patch_class, p.d_classes, p.d_panel_off, neumann, slot, src, n);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DTN_E_DEVICE, std::string("tile sources: ") + hipGetErrorString(e));
     return DTN_OK;

@@ -276,7 +276,8 @@ void build_tree(const std::vector<double> &pos, const std::vector<int8_t> &face,
 // Lagrange basis at y through the Chebyshev points of the second kind on
 // [lo, hi] (degree n; the centre alone for n = 0), second barycentric form;
 // the unit vector when y equals a node.
-__device__ void lagrange_1d(double y, double lo, double hi, int n, double *L)
+// cosk[k] = cos(pi k / n), the points on [-1, 1].
+__device__ void lagrange_1d(double y, double lo, double hi, int n, const double *cosk, double *L)
 {
     if (n == 0) {
         L[0] = 1.0;
@@ -286,14 +287,15 @@ __device__ void lagrange_1d(double y, double lo, double hi, int n, double *L)
     double sum = 0.0;
     int hit = -1;
     for (int k = 0; k <= n; ++k) {
-        const double d = y - (c + h * cos(M_PI * k / n));
+        const double d = y - (c + h * cosk[k]);
         const double w = ((k & 1) ? -1.0 : 1.0) * ((k == 0 || k == n) ? 0.5 : 1.0);
         if (d == 0.0) hit = k;
         const double t = d == 0.0 ? 0.0 : w / d;
         L[k] = t;
         sum += t;
     }
-    for (int k = 0; k <= n; ++k) L[k] = hit >= 0 ? (k == hit ? 1.0 : 0.0) : L[k] / sum;
+    const double inv = 1.0 / sum;
+    for (int k = 0; k <= n; ++k) L[k] = hit >= 0 ? (k == hit ? 1.0 : 0.0) : L[k] * inv;
 }
 
 __device__ __forceinline__ double cheb_point(const TreeNode &nd, int d, int k)
@@ -378,11 +380,16 @@ __global__ __launch_bounds__(kProxyThreads) void k_tree_proxy_partial(const Tree
     __shared__ double sl[3][64][kMaxDegree + 1];
     __shared__ double sw[64][4];
     __shared__ double red[kProxyThreads][4];
+    __shared__ double cosk[kMaxDegree + 1];
     const Item it = items[blockIdx.x];
     const TreeNode &nd = nodes[it.node];
     if (!acceptable(nd, tbox, theta2)) return;  // uniform per block
     const int tid = threadIdx.x;
     const int n1 = nd.deg[1] + 1, n2 = nd.deg[2] + 1, np = nd.n_proxy;
+    // the Chebyshev points' cosines, once per block (every axis with
+    // points uses the same degree)
+    const int nmax = max(nd.deg[0], max(nd.deg[1], nd.deg[2]));
+    if (tid <= nmax && nmax > 0) cosk[tid] = cos(M_PI * tid / nmax);
     const int ng = np > 128 ? 1 : (np > 64 ? 2 : 4);
     const int gs = kProxyThreads / ng, gi = tid / gs, kt = tid - gi * gs;
     int k0[kProxySlots], k1[kProxySlots], k2[kProxySlots];
@@ -407,7 +414,7 @@ __global__ __launch_bounds__(kProxyThreads) void k_tree_proxy_partial(const Tree
                     sw[j][2] = -q.wf * q.ny;
                     sw[j][3] = -q.wf * q.nz;
                 } else {
-                    lagrange_1d(d == 0 ? q.x : (d == 1 ? q.y : q.z), nd.lo[d], nd.hi[d], nd.deg[d], sl[d][j]);
+                    lagrange_1d(d == 0 ? q.x : (d == 1 ? q.y : q.z), nd.lo[d], nd.hi[d], nd.deg[d], cosk, sl[d][j]);
                 }
             }
         }
