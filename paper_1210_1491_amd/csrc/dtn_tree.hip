@@ -21,7 +21,8 @@
 //                          up to 3 proxies of the cluster (flat clusters:
 //                          2 or 4 thread groups over alternate sources)
 //   k_tree_proxy_reduce    per cluster: chunk partials summed in order, proxy
-//                          points written beside their charges
+//                          points written beside their charges (in-plane
+//                          clusters: in the plane's frame, PlaneProxy)
 //   k_tree_keys            Morton keys of the targets (10 bits per axis in the
 //                          sources' bounding box, clamped), then a radix sort
 //                          of (key, target) pairs (hipCUB)
@@ -29,11 +30,12 @@
 //                          face subtree: a stackless walk of the subtree's
 //                          node range under wave-uniform control.  Each
 //                          lane keeps the node index below which it is
-//                          done (it took an ancestor whole); a
-//                          node is opened when a lane still inside it needs
-//                          it opened, else the walk jumps past its subtree.
+//                          done (it took an ancestor whole); a node is
+//                          opened when a lane still inside it needs it
+//                          opened, else the walk jumps past its subtree.
 //                          Proxies and sources are read at wave-uniform
-//                          addresses.  All FP64.
+//                          addresses (a node few lanes take: by the wave
+//                          repacked over those lanes' targets).  All FP64.
 //   k_tree_sum             per target: the face subtrees' sums in order
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
