@@ -717,7 +717,8 @@ __global__ __launch_bounds__(64 * kEvalWaves) void k_tree_eval(const TreeNode *_
                                                                const TileSource *__restrict__ src,
                                                                const double *__restrict__ targets,
                                                                const uint32_t *__restrict__ order, int64_t t0,
-                                                               int64_t nt, int64_t n_waves, double theta2,
+                                                               int64_t nt, int64_t n_waves, int32_t n_nodes,
+                                                               double theta2,
                                                                TreeParts parts, double *__restrict__ upart,
                                                                int64_t *__restrict__ cpart, double *__restrict__ u,
                                                                int64_t *__restrict__ counts)
@@ -727,8 +728,31 @@ __global__ __launch_bounds__(64 * kEvalWaves) void k_tree_eval(const TreeNode *_
     const int64_t w = (int64_t)blockIdx.x * kEvalWaves + wv;
     if (w >= n_waves) return;  // the whole wave
     double *lx = lx_[wv], *ly = ly_[wv], *lz = lz_[wv], *part = part_[wv];
-    const int64_t grp = w / parts.n;
-    const int p = (int)(w - grp * parts.n);
+    // Waves in dispatch order: every group's nearest part first, then every
+    // group's second nearest, ... (the nearest parts carry most of the
+    // work, so the long waves start early and the short ones fill the
+    // tail).  Nearness: the group's first target to the part's box centre.
+    const int64_t n_grp = (nt + 63) / 64;
+    const int r = (int)(w / n_grp);
+    const int64_t grp = w - (int64_t)r * n_grp;
+    int p = 0;
+    {
+        const int64_t id0 = (int64_t)order[t0 + grp * 64];
+        const double x0 = targets[3 * id0], y0 = targets[3 * id0 + 1], z0 = targets[3 * id0 + 2];
+        double dist[kMaxParts];
+        for (int q = 0; q < parts.n; ++q) {
+            const TreeNode &c = nodes[min(parts.lo[q], n_nodes - 1)];
+            const double dx = x0 - c.c[0], dy = y0 - c.c[1], dz = z0 - c.c[2];
+            const double d2 = dx * dx + dy * dy + dz * dz;
+            dist[q] = d2 == d2 ? d2 : INFINITY;  // a NaN target ranks by index (ties below)
+        }
+        for (int q = 0; q < parts.n; ++q) {
+            int rank = 0;
+            for (int o = 0; o < parts.n; ++o) rank += dist[o] < dist[q] || (dist[o] == dist[q] && o < q);
+            if (rank == r) p = q;
+        }
+        p = __builtin_amdgcn_readfirstlane(p);
+    }
     const int64_t lt = grp * 64 + __lane_id();  // position in this batch of sorted targets
     const bool valid = lt < nt;
     const int64_t id = valid ? (int64_t)order[t0 + lt] : 0;
@@ -1041,7 +1065,7 @@ dtn_status dtn_tree_potential(dtn_tree t, const double *neumann, const double *t
             const int64_t waves = (nt + 63) / 64 * P.n;
             hipLaunchKernelGGL(k_tree_eval, dim3((unsigned)((waves + kEvalWaves - 1) / kEvalWaves)),
                                dim3(64 * kEvalWaves), 0, s, t->t.d_nodes, prox, src, targets, order, t0, nt, waves,
-                               theta2, P, upart, cpart, u_out, counts);
+                               (int32_t)H.nodes.size(), theta2, P, upart, cpart, u_out, counts);
             if (P.n > 1)
                 hipLaunchKernelGGL(k_tree_sum, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, upart, cpart,
                                    P.n, order, t0, nt, u_out, counts);

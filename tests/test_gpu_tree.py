@@ -229,6 +229,30 @@ def test_tree_proxy_selection_and_batches():
     torch.testing.assert_close(ub, ua, rtol=1e-13, atol=1e-13 * scale)
 
 
+def test_tree_nan_target_leaves_the_others_unchanged():
+    """A target with NaN coordinates gets NaN and changes no other target's
+    interactions or sum (beyond the rounding of its wave companions): it
+    takes nothing whole, and the order in which the face waves of its group
+    are dispatched stays a permutation of the faces."""
+    dtn = _dtn()
+    gd, pd, ps, sig = _cube()
+    plan = dtn.Plan(dtn.Geometry(gd), pd)
+    neu = torch.tensor(np.concatenate(sig), device="cuda")
+    tree = dtn.Tree(plan, 6, 64)
+    print("[gpu] tree NaN target", flush=True)
+    tg = _targets(3000, 300, 77)
+    bad = np.concatenate([tg, np.full((4, 3), np.nan)])
+    c1 = torch.zeros((len(tg), 2), dtype=torch.int64, device="cuda")
+    c2 = torch.zeros((len(bad), 2), dtype=torch.int64, device="cuda")
+    u1 = tree.potential(neu, torch.tensor(tg, device="cuda"), counts=c1)
+    u2 = tree.potential(neu, torch.tensor(bad, device="cuda"), counts=c2)
+    torch.cuda.synchronize()
+    assert torch.isnan(u2[len(tg):]).all()
+    assert torch.equal(c2[: len(tg)], c1)
+    scale = float(u1.abs().max())
+    torch.testing.assert_close(u2[: len(tg)], u1, rtol=1e-13, atol=1e-13 * scale)
+
+
 def test_tree_arguments_are_checked():
     dtn = _dtn()
     gd, pd, ps, sig = _cube()
