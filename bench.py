@@ -132,6 +132,16 @@ DISK_SLOTS_PER_STEP = {k: slots(v) for k, v in DISK_STEP_OPS.items()}
 DISK_SLOTS_PER_WALK = slots(DISK_WALK_OPS)
 EXT_SLOTS_PER_STEP = {k: slots(v) for k, v in EXT_STEP_OPS.items()}
 EXT_SLOTS_PER_WALK = slots(EXT_WALK_OPS)
+# Treecode interactions, counted from what an interaction needs: a proxy of
+# an in-plane cluster (two in-plane differences, r^2 by two FMAs onto the
+# square of the target's height above the plane, 1/r by the hardware
+# estimate and one Newton step (two products, two FMAs), the cube of 1/r,
+# the dipole product and its scaling, the charge term's FMA, the add) and a
+# tile source taken directly (three differences, r^2, 1/r as above, the
+# cube, the normal product, the single- and double-layer terms, the add).
+# Targets inside the cube take only in-plane clusters' proxies.
+TREE_PROXY_SLOTS = slots({"f64": 9, "f64fma": 5, "rsq64": 1})
+TREE_SOURCE_SLOTS = slots({"f64": 12, "f64fma": 7, "rsq64": 1})
 
 # HBM traffic of the walk kernel on the unit-cube workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs, each scaled by the same counter on a plain
@@ -857,6 +867,10 @@ def treecode_potential(m_tiles=96, n_targets=1_000_000, degree=6, theta=0.5, lea
     far = np.min(np.minimum(tg_np, 1.0 - tg_np), axis=1) >= 2.0 / m_tiles
     ex = exact_u(gd, tg_np[far])
     inter = float(cnt.sum()) / n_targets
+    # ALU roofline of the whole call (proxies, sort and traversal in the
+    # time; the traversal's interactions as the work)
+    tree_slots = float(cnt[:, 0].sum()) * TREE_PROXY_SLOTS + float(cnt[:, 1].sum()) * TREE_SOURCE_SLOTS
+    tree_achieved = tree_slots / (ms_tree * 1e-3)
     out = {
         "workload": f"unit cube, {m_tiles}x{m_tiles} tiles per face ({tree.n_sources} sources), "
                     f"{n_targets} targets uniform in the cube, exact du/dn",
@@ -872,6 +886,10 @@ def treecode_potential(m_tiles=96, n_targets=1_000_000, degree=6, theta=0.5, lea
         "targets_vs_exact": int(far.sum()),
         "sweep": sweep,
         "scaling": scaling,
+        "roofline": {"bound": "alu", "achieved": tree_achieved / 1e12, "peak": ALU_PEAK / 1e12,
+                     "unit": "T lane-op slots/s", "frac": tree_achieved / ALU_PEAK, "traffic": None,
+                     "slots_per_proxy_interaction": TREE_PROXY_SLOTS,
+                     "slots_per_source_interaction": TREE_SOURCE_SLOTS, "time": "whole call"},
     }
     print(f"[bench] treecode potential: {ms_tree:.1f} ms vs direct {ms_direct:.1f} ms "
           f"({out['speedup']:.1f}x), {inter:.0f} interactions per target", file=sys.stderr, flush=True)
