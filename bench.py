@@ -133,15 +133,18 @@ DISK_SLOTS_PER_WALK = slots(DISK_WALK_OPS)
 EXT_SLOTS_PER_STEP = {k: slots(v) for k, v in EXT_STEP_OPS.items()}
 EXT_SLOTS_PER_WALK = slots(EXT_WALK_OPS)
 # Treecode interactions, counted from what an interaction needs: a proxy of
-# an in-plane cluster (two in-plane differences, r^2 by two FMAs onto the
-# square of the target's height above the plane, 1/r by the hardware
-# estimate and one Newton step (two products, two FMAs), the cube of 1/r,
-# the dipole product and its scaling, the charge term's FMA, the add) and a
-# tile source taken directly (three differences, r^2, 1/r as above, the
-# cube, the normal product, the single- and double-layer terms, the add).
-# Targets inside the cube take only in-plane clusters' proxies.
-TREE_PROXY_SLOTS = slots({"f64": 9, "f64fma": 5, "rsq64": 1})
-TREE_SOURCE_SLOTS = slots({"f64": 12, "f64fma": 7, "rsq64": 1})
+# an in-plane cluster (r^2 as the target's row sum plus its column term, one
+# add; 1/r and 1/r^2 from the hardware estimate y of 1/r and its residual
+# e = 1 - r^2 y^2: y^2 (a product), e (an FMA), y (1 + e/2) (an FMA and a
+# product), y^2 (1 + e) (an FMA); the dipole product, the charge term's FMA
+# and the accumulating FMA) and a tile source taken directly (three
+# differences, r^2 (a product, two FMAs), the two powers as above, the
+# normal product (a product, two FMAs) and its scaling, the charge term's
+# FMA, the accumulating FMA).  The row sums and column terms are per target
+# and row or column, not per interaction.  Targets inside the cube take only
+# in-plane clusters' proxies.
+TREE_PROXY_SLOTS = slots({"f64": 4, "f64fma": 5, "rsq64": 1})
+TREE_SOURCE_SLOTS = slots({"f64": 8, "f64fma": 9, "rsq64": 1})
 
 # HBM traffic of the walk kernel on the unit-cube workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs, each scaled by the same counter on a plain

@@ -22,7 +22,8 @@
 //                          2 or 4 thread groups over alternate sources)
 //   k_tree_proxy_reduce    per cluster: chunk partials summed in order, proxy
 //                          points written beside their charges (in-plane
-//                          clusters: in the plane's frame, PlaneProxy)
+//                          clusters: a row/column table in the plane's
+//                          frame)
 //   k_tree_keys            Morton keys of the targets (10 bits per axis in the
 //                          sources' bounding box, clamped), then a radix sort
 //                          of (key, target) pairs (hipCUB)
@@ -85,14 +86,19 @@ struct Proxy {
     double x, y, z, q, px, py, pz, pad;
 };
 
-// The same 64 bytes for a proxy of an in-plane cluster (axis a, b = a + 1,
-// c = a + 2 mod 3): its coordinates along b and c, its charge, the vector's
-// component along a (the others are 0), then the plane's coordinate; what
-// an interaction reads is the first 32 bytes.
-struct PlaneProxy {
-    double b, c, q, pn, a, pad[3];
-};
-static_assert(sizeof(PlaneProxy) == sizeof(Proxy), "proxy layouts");
+// An in-plane cluster (axis a, in-plane axes b = a + 1 and c = a + 2 mod 3)
+// keeps its proxies in its plane's frame, as a table over its proxies' 64-byte
+// slots: the proxies form an nb x nc grid (nb, nc the Chebyshev point counts
+// along b and c), so with pb_i, pc_j the grid's offsets from the cluster's
+// centre the table holds, in doubles, the column terms (-2 pc_j, pc_j^2) for
+// j < nc, then per row i its row terms (-2 pb_i, pb_i^2) followed by, per
+// proxy (i, j), its charge and its vector's component along a (the others
+// are 0).  16 (nb + nc + nb nc) bytes of the 64 nb nc; a row is 2 + 2 nc
+// contiguous doubles, read with one wait.
+__host__ __device__ __forceinline__ int plane_row(int nc, int i)
+{
+    return 2 * nc + i * (2 + 2 * nc);
+}
 
 struct Item {      // proxy pass work item: one cluster's sources [b, e)
     int32_t node, b, e, pad;
@@ -464,16 +470,24 @@ __global__ __launch_bounds__(kProxyThreads) void k_tree_proxy_reduce(const TreeN
             for (int c = 0; c < 4; ++c) v[c] += part[items[i].part + 4 * (int64_t)k + c];
         const double pt[3] = {cheb_point(nd, 0, k / (n1 * n2)), cheb_point(nd, 1, (k / n2) % n1),
                               cheb_point(nd, 2, k % n2)};
-        if (nd.axis >= 0) {  // the plane's frame
-            const int a = nd.axis;
-            PlaneProxy o;
-            o.b = pt[(a + 1) % 3];
-            o.c = pt[(a + 2) % 3];
-            o.q = v[0];
-            o.pn = v[1 + a];
-            o.a = pt[a];
-            o.pad[0] = o.pad[1] = o.pad[2] = 0.0;
-            reinterpret_cast<PlaneProxy *>(prox)[nd.proxy + k] = o;
+        if (nd.axis >= 0) {  // the plane's table
+            const int a = nd.axis, ib = (a + 1) % 3, ic = (a + 2) % 3;
+            const int idx[3] = {k / (n1 * n2), (k / n2) % n1, k % n2};
+            const int nb = nd.deg[ib] + 1, nc = nd.deg[ic] + 1, i = idx[ib], j = idx[ic];
+            double *D = reinterpret_cast<double *>(prox + nd.proxy);
+            double *R = D + plane_row(nc, i);
+            R[2 + 2 * j] = v[0];
+            R[3 + 2 * j] = v[1 + a];
+            if (j == 0) {
+                const double pb = pt[ib] - nd.c[ib];
+                R[0] = -2.0 * pb;
+                R[1] = pb * pb;
+            }
+            if (i == 0) {
+                const double pc = pt[ic] - nd.c[ic];
+                D[2 * j] = -2.0 * pc;
+                D[2 * j + 1] = pc * pc;
+            }
         } else {
             Proxy o;
             o.x = pt[0];
@@ -517,38 +531,109 @@ __global__ __launch_bounds__(256) void k_tree_keys(const double *__restrict__ ta
 
 enum : int { kNone = 0, kTakeProxy = 1, kTakeDirect = 2, kOpen = 3 };
 
-// 1/|x - y| for the interactions: the hardware reciprocal square root
-// (relative error below 6e-8) and one Newton step, relative error ~5e-15,
-// far below the interpolation error that sets the treecode's accuracy.  Five
-// instructions where a correctly rounded one takes nine.
-__device__ __forceinline__ double rsqrt_1nr(double q)
+// 1/|x - y| and 1/|x - y|^2 from q = |x - y|^2 for the interactions: the
+// hardware reciprocal square root r (relative error below 6e-8) and its
+// residual e = 1 - q r^2, then r (1 + e/2) and r^2 (1 + e), the first-order
+// corrections (relative errors ~5e-15 and ~1.5e-14, far below the
+// interpolation error that sets the treecode's accuracy).  Six instructions
+// for both; a correctly rounded root alone takes nine.
+struct InvPowers {
+    double r1, r2;
+};
+__device__ __forceinline__ InvPowers inv_powers(double q)
 {
     const double r = __builtin_amdgcn_rsq(q);
-    return fma(r, fma(-0.5 * q * r, r, 0.5), r);
+    const double s = r * r, e = fma(-q, s, 1.0);
+    return {r * fma(e, 0.5, 1.0), fma(s, e, s)};
 }
 
+// Every interaction is (q + (m . (x - y)) / |x - y|^2) / |x - y| for a
+// charge q and a vector m at y (a source's m is -wf n).
 __device__ __forceinline__ double proxy_term(double x, double y, double z, const Proxy &p)
 {
     const double ex = x - p.x, ey = y - p.y, ez = z - p.z;
-    const double ir = rsqrt_1nr(ex * ex + ey * ey + ez * ez);
-    return p.q * ir + (p.px * ex + p.py * ey + p.pz * ez) * (ir * ir * ir);
+    const InvPowers v = inv_powers(ex * ex + ey * ey + ez * ez);
+    return fma(p.px * ex + p.py * ey + p.pz * ez, v.r2, p.q) * v.r1;
 }
 
-// The same term for a proxy of an in-plane cluster, with the target in the
-// plane's frame: (tb, tc) its in-plane coordinates, ea its height above the
-// plane (the same for every proxy of the cluster).
-__device__ __forceinline__ double plane_proxy_term(double tb, double tc, double ea, const PlaneProxy &p)
+// In-plane clusters: the target enters as its offsets from the cluster's
+// centre (tb, tc in the plane, h above it) and d2 = tb^2 + tc^2 + h^2, and
+// |x - y|^2 for the proxy (i, j) is expanded as d2 + (pb_i^2 - 2 pb_i tb) +
+// (pc_j^2 - 2 pc_j tc): per target, a row term per row and a column term per
+// column, then one add per proxy.  Acceptance keeps |y - c| <= r <
+// theta |x - c|, so |x - y|^2 >= (1 - theta)^2 d2 while the summands stay
+// below (1 + theta)^2 d2: the expansion costs a few roundings times
+// (1 + theta)^2 / (1 - theta)^2 (9 at theta = 0.5).
+struct PlaneEntry {
+    double b2, c2, p2, q, pn;  // -2 pb_i, -2 pc_j, pb_i^2 + pc_j^2, charge, vector
+};
+
+// a b + c with c in scalar registers (the wave-uniform charge): the
+// compiler's own choice copies c into vector registers first.
+__device__ __forceinline__ double fma_uniform_addend(double a, double b, double c)
 {
-    const double eb = tb - p.b, ec = tc - p.c;
-    const double ir = rsqrt_1nr(fma(eb, eb, fma(ec, ec, ea * ea)));
-    return p.q * ir + (p.pn * ea) * (ir * ir * ir);
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+    return d;
+}
+
+// acc += (q + pn h / |x - y|^2) / |x - y| for |x - y|^2 = q2; q and pn are
+// wave-uniform.
+__device__ __forceinline__ void plane_add(double q2, double h, double q, double pn, double &acc)
+{
+    const InvPowers v = inv_powers(q2);
+    acc = fma(fma_uniform_addend(pn * h, v.r2, q), v.r1, acc);
+}
+
+// All proxies of an in-plane cluster with NC columns for the taking lanes
+// of a wave, with wave-uniform (scalar) loads: the column terms once, then
+// a row per iteration, read whole, so that the row's NC interactions follow
+// one wait.
+template <int NC>
+__device__ __forceinline__ void plane_rows_n(const double *__restrict__ D, int nb, double tb, double tc, double h,
+                                             double d2, double &acc)
+{
+    double cv[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) cv[j] = fma(D[2 * j], tc, D[2 * j + 1]);
+    for (int i = 0; i < nb; ++i) {
+        const double *R = D + plane_row(NC, i);
+        double rv[2 + 2 * NC];
+#pragma unroll
+        for (int k = 0; k < 2 + 2 * NC; ++k) rv[k] = R[k];
+        const double bi = d2 + fma(rv[0], tb, rv[1]);
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            plane_add(bi + cv[j], h, rv[2 + 2 * j], rv[3 + 2 * j], acc);
+            // at most two interactions interleaved by the scheduler (a
+            // whole row interleaved needs 127 registers)
+            if (j % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+__device__ __forceinline__ void plane_rows(const double *__restrict__ D, int nb, int nc, double tb, double tc,
+                                           double h, double d2, double &acc)
+{
+    static_assert(kMaxDegree + 1 == 9, "one case per column count");
+    switch (nc) {
+    case 1: plane_rows_n<1>(D, nb, tb, tc, h, d2, acc); break;
+    case 2: plane_rows_n<2>(D, nb, tb, tc, h, d2, acc); break;
+    case 3: plane_rows_n<3>(D, nb, tb, tc, h, d2, acc); break;
+    case 4: plane_rows_n<4>(D, nb, tb, tc, h, d2, acc); break;
+    case 5: plane_rows_n<5>(D, nb, tb, tc, h, d2, acc); break;
+    case 6: plane_rows_n<6>(D, nb, tb, tc, h, d2, acc); break;
+    case 7: plane_rows_n<7>(D, nb, tb, tc, h, d2, acc); break;
+    case 8: plane_rows_n<8>(D, nb, tb, tc, h, d2, acc); break;
+    default: plane_rows_n<9>(D, nb, tb, tc, h, d2, acc); break;
+    }
 }
 
 __device__ __forceinline__ double source_term(double x, double y, double z, const TileSource &s)
 {
     const double ex = x - s.x, ey = y - s.y, ez = z - s.z;
-    const double ir = rsqrt_1nr(ex * ex + ey * ey + ez * ez);
-    return s.ws * ir - s.wf * (ex * s.nx + ey * s.ny + ez * s.nz) * (ir * ir * ir);
+    const InvPowers v = inv_powers(ex * ex + ey * ey + ez * ez);
+    return fma(-s.wf * (ex * s.nx + ey * s.ny + ez * s.nz), v.r2, s.ws) * v.r1;
 }
 
 __device__ __forceinline__ void tree_wave_sync()
@@ -557,16 +642,16 @@ __device__ __forceinline__ void tree_wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-// Entries [base, base + count) of a node taken by the k <= 32 lanes of
-// `mask`: the wave is repacked so that g = 64 / k lanes work on each taking
-// lane's target (lane l on the target of rank l / g, entries l mod g, l mod g
-// + g, ...), each reading its own entries; the g partial sums of a target
-// are then added, in lane order, to its lane's sum.  With k > 32 the whole
-// wave walks the entries together instead (wave-uniform loads).
-template <class Entry, class Term>
-__device__ __forceinline__ void packed_sum(uint64_t mask, int32_t base, int32_t count, const Entry *__restrict__ E,
-                                           double x, double y, double z, double &acc, Term term, double *lx,
-                                           double *ly, double *lz, double *part)
+// Entries 0 .. count - 1 of a node (fetch(e) reads entry e) taken by the
+// k <= 32 lanes of `mask`: the wave is repacked so that g = 64 / k lanes
+// work on each taking lane's target (lane l on the target of rank l / g,
+// entries l mod g, l mod g + g, ...), each reading its own entries; the g
+// partial sums of a target are then added, in lane order, to its lane's
+// sum.  With k > 32 the whole wave walks the entries together instead
+// (wave-uniform loads).
+template <bool kAhead = true, class Fetch, class Term>
+__device__ __forceinline__ void packed_sum(uint64_t mask, int32_t count, Fetch fetch, double x, double y, double z,
+                                           double &acc, Term term, double *lx, double *ly, double *lz, double *part)
 {
     const int lane = __lane_id();
     const int k = __popcll(mask), g = 64 / k;
@@ -583,13 +668,13 @@ __device__ __forceinline__ void packed_sum(uint64_t mask, int32_t base, int32_t 
     if (t < k) {
         const double px = lx[t], py = ly[t], pz = lz[t];
         // entries sub, sub + g, ... two per iteration, the next two loaded
-        // before the current two are summed
-        const Entry *Q = E + base;
+        // before the current two are summed (kAhead; else one at a time,
+        // for entries whose registers would crowd the wave's)
         int32_t e = sub;
-        if (e + g < count) {
-            Entry ea = Q[e], eb = Q[e + g];
+        if (kAhead && e + g < count) {
+            auto ea = fetch(e), eb = fetch(e + g);
             for (e += 2 * g; e + g < count; e += 2 * g) {
-                const Entry ec = Q[e], ed = Q[e + g];
+                const auto ec = fetch(e), ed = fetch(e + g);
                 a += term(px, py, pz, ea);
                 a += term(px, py, pz, eb);
                 ea = ec;
@@ -598,7 +683,11 @@ __device__ __forceinline__ void packed_sum(uint64_t mask, int32_t base, int32_t 
             a += term(px, py, pz, ea);
             a += term(px, py, pz, eb);
         }
-        if (e < count) a += term(px, py, pz, Q[e]);
+        if (kAhead) {
+            if (e < count) a += term(px, py, pz, fetch(e));
+        } else {
+            for (; e < count; e += g) a += term(px, py, pz, fetch(e));
+        }
     }
     part[lane] = a;
     tree_wave_sync();
@@ -632,39 +721,32 @@ __device__ __forceinline__ void take_node(const TreeNode &nd, int act, const Pro
     const auto sterm = [](double a, double b, double c, const TileSource &q) { return source_term(a, b, c, q); };
     const uint64_t mp = __ballot(act == kTakeProxy), md = __ballot(act == kTakeDirect);
     if (mp && nd.axis >= 0) {
-        // in-plane cluster: the target in the plane's frame
-        const int a = nd.axis;
+        // in-plane cluster: the target in the plane's frame, the proxies
+        // from the plane's table
+        const int a = nd.axis, ib = a == 2 ? 0 : a + 1, ic = a == 0 ? 2 : a - 1;
         const double ta = a == 0 ? x : (a == 1 ? y : z);
-        const double tb = a == 0 ? y : (a == 1 ? z : x);
-        const double tc = a == 0 ? z : (a == 1 ? x : y);
+        const double tb = (a == 0 ? y : (a == 1 ? z : x)) - nd.c[ib];
+        const double tc = (a == 0 ? z : (a == 1 ? x : y)) - nd.c[ic];
         const double ea = ta - nd.c[a];
-        const auto fterm = [](double b, double c, double h, const PlaneProxy &q) {
-            return plane_proxy_term(b, c, h, q);
-        };
-        const PlaneProxy *pp = reinterpret_cast<const PlaneProxy *>(prox);
+        const double *D = reinterpret_cast<const double *>(prox + nd.proxy);
+        const int nb = nd.deg[ib] + 1, nc = nd.deg[ic] + 1;
         if (__popcll(mp) > 32) {
-            if (act == kTakeProxy) {
-                // two proxies per iteration, the next two loaded before the
-                // current two are summed (their latency under the arithmetic)
-                const PlaneProxy *e = pp + nd.proxy;
-                const int32_t n = nd.n_proxy;
-                int32_t k = 0;
-                if (n >= 2) {
-                    PlaneProxy pa = e[0], pb = e[1];
-                    for (k = 2; k + 1 < n; k += 2) {
-                        const PlaneProxy pc = e[k], pd = e[k + 1];
-                        acc += plane_proxy_term(tb, tc, ea, pa);
-                        acc += plane_proxy_term(tb, tc, ea, pb);
-                        pa = pc;
-                        pb = pd;
-                    }
-                    acc += plane_proxy_term(tb, tc, ea, pa);
-                    acc += plane_proxy_term(tb, tc, ea, pb);
-                }
-                if (k < n) acc += plane_proxy_term(tb, tc, ea, e[k]);
-            }
+            if (act == kTakeProxy) plane_rows(D, nb, nc, tb, tc, ea, fma(tb, tb, fma(tc, tc, ea * ea)), acc);
         } else {
-            packed_sum(mp, nd.proxy, nd.n_proxy, pp, tb, tc, ea, acc, fterm, lx, ly, lz, part);
+            // entry e is proxy (e / nc, e mod nc); the row by a multiply
+            // and shift, exact for e < 65536 / (nc - 1) (>= 8192)
+            const uint32_t inv = (65536u + (uint32_t)nc - 1u) / (uint32_t)nc;
+            const auto fetch = [=](int32_t e) {
+                const int32_t i = (int32_t)(((uint32_t)e * inv) >> 16), j = e - i * nc;
+                const double *R = D + plane_row(nc, i);
+                return PlaneEntry{R[0], D[2 * j], R[1] + D[2 * j + 1], R[2 + 2 * j], R[3 + 2 * j]};
+            };
+            const auto fterm = [](double b, double c, double h, const PlaneEntry &q) {
+                const double d2 = fma(b, b, fma(c, c, h * h));
+                const InvPowers v = inv_powers(fma(q.b2, b, fma(q.c2, c, d2 + q.p2)));
+                return fma(q.pn * h, v.r2, q.q) * v.r1;
+            };
+            packed_sum<false>(mp, nb * nc, fetch, tb, tc, ea, acc, fterm, lx, ly, lz, part);
         }
         if (act == kTakeProxy) n_prox += nd.n_proxy;
     } else if (mp) {
@@ -682,7 +764,8 @@ __device__ __forceinline__ void take_node(const TreeNode &nd, int act, const Pro
                 if (k < k_end) acc += proxy_term(x, y, z, prox[k]);
             }
         } else {
-            packed_sum(mp, nd.proxy, nd.n_proxy, prox, x, y, z, acc, pterm, lx, ly, lz, part);
+            const Proxy *P = prox + nd.proxy;
+            packed_sum(mp, nd.n_proxy, [=](int32_t e) { return P[e]; }, x, y, z, acc, pterm, lx, ly, lz, part);
         }
         if (act == kTakeProxy) n_prox += nd.n_proxy;
     }
@@ -698,7 +781,8 @@ __device__ __forceinline__ void take_node(const TreeNode &nd, int act, const Pro
                 if (k < nd.e) acc += source_term(x, y, z, src[k]);
             }
         } else {
-            packed_sum(md, nd.b, nd.e - nd.b, src, x, y, z, acc, sterm, lx, ly, lz, part);
+            const TileSource *S = src + nd.b;
+            packed_sum(md, nd.e - nd.b, [=](int32_t e) { return S[e]; }, x, y, z, acc, sterm, lx, ly, lz, part);
         }
         if (act == kTakeDirect) n_dir += nd.e - nd.b;
     }
@@ -712,29 +796,40 @@ __device__ __forceinline__ void take_node(const TreeNode &nd, int act, const Pro
 // block measured fastest (blocks of 4 waves issued VALU work 45 % of the
 // cycles instead of 61 %, 5.2-5.5 ms instead of 4.1-4.7 ms per launch).
 constexpr int kEvalWaves = 1;
-__global__ __launch_bounds__(64 * kEvalWaves) void k_tree_eval(const TreeNode *__restrict__ nodes,
-                                                               const Proxy *__restrict__ prox,
-                                                               const TileSource *__restrict__ src,
-                                                               const double *__restrict__ targets,
-                                                               const uint32_t *__restrict__ order, int64_t t0,
-                                                               int64_t nt, int64_t n_waves, int32_t n_nodes,
-                                                               double theta2,
-                                                               TreeParts parts, double *__restrict__ upart,
-                                                               int64_t *__restrict__ cpart, double *__restrict__ u,
-                                                               int64_t *__restrict__ counts)
+
+// Target groups per part in the launch: the groups rounded up to a whole
+// number of blocks per XCD (the surplus waves exit at once).
+__host__ __device__ __forceinline__ int64_t eval_groups_padded(int64_t nt)
+{
+    const int64_t q = (int64_t)kXcds * kEvalWaves;
+    return ((nt + 63) / 64 + q - 1) / q * q;
+}
+
+// Seven waves per SIMD (71 registers; the compiler's own choice, 75, allows
+// six, measured ~1 % slower).
+__global__ __launch_bounds__(64 * kEvalWaves) __attribute__((amdgpu_waves_per_eu(7))) void k_tree_eval(
+    const TreeNode *__restrict__ nodes, const Proxy *__restrict__ prox, const TileSource *__restrict__ src,
+    const double *__restrict__ targets, const uint32_t *__restrict__ order, int64_t t0, int64_t nt, int32_t n_nodes,
+    double theta2, TreeParts parts, double *__restrict__ upart, int64_t *__restrict__ cpart, double *__restrict__ u,
+    int64_t *__restrict__ counts)
 {
     __shared__ double lx_[kEvalWaves][64], ly_[kEvalWaves][64], lz_[kEvalWaves][64], part_[kEvalWaves][64];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
-    const int64_t w = (int64_t)blockIdx.x * kEvalWaves + wv;
-    if (w >= n_waves) return;  // the whole wave
-    double *lx = lx_[wv], *ly = ly_[wv], *lz = lz_[wv], *part = part_[wv];
     // Waves in dispatch order: every group's nearest part first, then every
     // group's second nearest, ... (the nearest parts carry most of the
     // work, so the long waves start early and the short ones fill the
     // tail).  Nearness: the group's first target to the part's box centre.
-    const int64_t n_grp = (nt + 63) / 64;
-    const int r = (int)(w / n_grp);
-    const int64_t grp = w - (int64_t)r * n_grp;
+    // Within a rank, the XCD that runs a block (blocks go to the XCDs in
+    // turn) takes one contiguous eighth of the groups, in order: sorted
+    // targets are spatially compact, so each XCD's L2 holds the clusters
+    // near its own region instead of every region's.
+    const int64_t n_grp = (nt + 63) / 64, n_pad = eval_groups_padded(nt);
+    const int64_t per_rank = n_pad / kEvalWaves;  // blocks per rank, a multiple of kXcds
+    const int r = (int)(blockIdx.x / per_rank);
+    const int64_t ib = blockIdx.x - (int64_t)r * per_rank;
+    const int64_t grp = (ib % kXcds) * (n_pad / kXcds) + (ib / kXcds) * kEvalWaves + wv;
+    if (grp >= n_grp) return;  // the whole wave
+    double *lx = lx_[wv], *ly = ly_[wv], *lz = lz_[wv], *part = part_[wv];
     int p = 0;
     {
         const int64_t id0 = (int64_t)order[t0 + grp * 64];
@@ -1062,9 +1157,9 @@ dtn_status dtn_tree_potential(dtn_tree t, const double *neumann, const double *t
                                                    0, 30, s);
         for (int64_t t0 = 0; e == hipSuccess && t0 < m; t0 += batch) {
             const int64_t nt = std::min(batch, m - t0);
-            const int64_t waves = (nt + 63) / 64 * P.n;
-            hipLaunchKernelGGL(k_tree_eval, dim3((unsigned)((waves + kEvalWaves - 1) / kEvalWaves)),
-                               dim3(64 * kEvalWaves), 0, s, t->t.d_nodes, prox, src, targets, order, t0, nt, waves,
+            const int64_t blocks = eval_groups_padded(nt) / kEvalWaves * P.n;
+            hipLaunchKernelGGL(k_tree_eval, dim3((unsigned)blocks),
+                               dim3(64 * kEvalWaves), 0, s, t->t.d_nodes, prox, src, targets, order, t0, nt,
                                (int32_t)H.nodes.size(), theta2, P, upart, cpart, u_out, counts);
             if (P.n > 1)
                 hipLaunchKernelGGL(k_tree_sum, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, upart, cpart,
