@@ -730,7 +730,11 @@ __device__ __forceinline__ void take_node(const TreeNode &nd, int act, const Pro
         const double ea = ta - nd.c[a];
         const double *D = reinterpret_cast<const double *>(prox + nd.proxy);
         const int nb = nd.deg[ib] + 1, nc = nd.deg[ic] + 1;
-        if (__popcll(mp) > 32) {
+        if (64 / __popcll(mp) < 3) {
+            // the row loop costs the wave 10.7 instructions per proxy, the
+            // repacked loop 28 per iteration (each lane one entry of its
+            // target's): repacking pays from three lanes per target (21
+            // or fewer taking lanes), not from two
             if (act == kTakeProxy) plane_rows(D, nb, nc, tb, tc, ea, fma(tb, tb, fma(tc, tc, ea * ea)), acc);
         } else {
             // entry e is proxy (e / nc, e mod nc); the row by a multiply
@@ -860,14 +864,17 @@ __global__ __launch_bounds__(64 * kEvalWaves) __attribute__((amdgpu_waves_per_eu
     double acc = 0.0;
     int64_t n_prox = 0, n_dir = 0;
     int32_t done_below = valid ? 0 : INT32_MAX;  // the lane is inside node j iff j >= done_below
-    {
-        const TreeNode &nd = nodes[0];
-        const int act = node_action(nd, valid, x, y, z, theta2);
-        if (p == 0) take_node(nd, act, prox, src, x, y, z, acc, n_prox, n_dir, lx, ly, lz, part);
-        if (act == kTakeProxy || act == kTakeDirect) done_below = INT32_MAX;
-    }
     int32_t j = parts.lo[p];
     const int32_t j_end = parts.hi[p];
+    if (p == 0) {
+        // part 0's wave walks the root first (then its first child, node 1,
+        // is part 0's first node; lanes that take the root skip everything)
+        j = 0;
+    } else {
+        // lanes that take the root whole are done in every part
+        const int act = node_action(nodes[0], valid, x, y, z, theta2);
+        if (act == kTakeProxy || act == kTakeDirect) done_below = INT32_MAX;
+    }
     while (j < j_end) {
         const TreeNode &nd = nodes[j];
         const int act = node_action(nd, j >= done_below, x, y, z, theta2);
