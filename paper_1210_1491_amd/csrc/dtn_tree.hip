@@ -831,7 +831,7 @@ __global__ __launch_bounds__(64 * kEvalWaves) __attribute__((amdgpu_waves_per_eu
     const int64_t per_rank = n_pad / kEvalWaves;  // blocks per rank, a multiple of kXcds
     const int r = (int)(blockIdx.x / per_rank);
     const int64_t ib = blockIdx.x - (int64_t)r * per_rank;
-    const int64_t grp = (ib % kXcds) * (n_pad / kXcds) + (ib / kXcds) * kEvalWaves + wv;
+    const int64_t grp = xcd_contiguous(ib, wv, n_pad, kEvalWaves);
     if (grp >= n_grp) return;  // the whole wave
     double *lx = lx_[wv], *ly = ly_[wv], *lz = lz_[wv], *part = part_[wv];
     int p = 0;

@@ -45,7 +45,8 @@ def _targets(n_in, n_out, seed):
     return np.concatenate([inside, outside])
 
 
-@pytest.mark.parametrize("degree,leaf,theta", [(6, 64, 0.5), (3, 8, 0.7), (8, 300, 0.3), (1, 4096, 0.9)])
+@pytest.mark.parametrize("degree,leaf,theta",
+                         [(6, 64, 0.5), (3, 8, 0.7), (8, 300, 0.3), (1, 4096, 0.9), (5, 32, 0.6), (7, 128, 0.5)])
 def test_tree_matches_oracle_treecode(degree, leaf, theta):
     dtn = _dtn()
     gd, pd, ps, sig = _cube()

@@ -1,7 +1,8 @@
 // Host check of the walk kernel's workgroup -> chunk-block mapping: a
 // bijection of [0, G) for every grid size, with each XCD's workgroups
 // taking runs of consecutive blocks and each round's runs dealt to distinct
-// XCDs.  Prints "ok" or the first failure.
+// XCDs; and of the treecode traversal's contiguous mapping.  Prints "ok" or
+// the first failure.
 #include <cstdio>
 #include <vector>
 
@@ -39,6 +40,28 @@ int main()
             }
         }
     }
+    // the traversal's contiguous mapping: a bijection of [0, n) for n a
+    // multiple of 8 W, each XCD's blocks (ib, ib + 8, ...) taking one
+    // eighth of the range in order
+    for (int W : {1, 2, 4})
+        for (long long n = 8LL * W; n <= 8LL * W * 300; n += 8LL * W) {
+            std::vector<char> hit(n, 0);
+            const long long blocks = n / W;
+            for (long long ib = 0; ib < blocks; ++ib)
+                for (int wv = 0; wv < W; ++wv) {
+                    const long long g = dtn::xcd_contiguous(ib, wv, n, W);
+                    const long long x = ib % dtn::kXcds, lo = x * (n / dtn::kXcds), hi = lo + n / dtn::kXcds;
+                    if (g < lo || g >= hi || hit[g]) {
+                        std::printf("contiguous map broken: n=%lld W=%d ib=%lld wv=%d g=%lld\n", n, W, ib, wv, g);
+                        return 1;
+                    }
+                    hit[g] = 1;
+                    if (ib >= dtn::kXcds && dtn::xcd_contiguous(ib - dtn::kXcds, wv, n, W) != g - W) {
+                        std::printf("contiguous map out of order: n=%lld W=%d ib=%lld\n", n, W, ib);
+                        return 1;
+                    }
+                }
+        }
     std::printf("ok\n");
     return 0;
 }
