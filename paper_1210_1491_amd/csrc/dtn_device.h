@@ -500,16 +500,6 @@ __host__ __device__ __forceinline__ int64_t xcd_block(int64_t i, int64_t G)
     return (j * kXcds + ((x + rot) & (kXcds - 1))) * kXcdStripe + k % kXcdStripe;
 }
 
-// The other mapping, for work whose neighbouring items share data across a
-// whole eighth of the range: n items (a multiple of kXcds * W) in blocks of
-// W waves; block ib (XCD ib mod 8) and its wave wv take item
-// (ib mod 8) n/8 + (ib / 8) W + wv, so XCD x works through the contiguous
-// range [x n/8, (x + 1) n/8) in order.
-__host__ __device__ __forceinline__ int64_t xcd_contiguous(int64_t ib, int wv, int64_t n, int W)
-{
-    return (ib % kXcds) * (n / kXcds) + (ib / kXcds) * W + wv;
-}
-
 // Exit-point queue entry (3 doubles) `first + rank` of a queue in LDS,
 // addressed in 32 bits: rank x 24 B (one 24-bit multiply-add) onto the
 // wave-uniform byte offset of entry `first`.

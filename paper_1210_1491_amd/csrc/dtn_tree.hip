@@ -52,6 +52,7 @@
 #include "dtn_device.h"
 #include "dtn_internal.h"
 #include "dtn_potential.h"
+#include "dtn_xcd.h"
 
 namespace dtn {
 namespace {

@@ -1,9 +1,9 @@
-"""The XCD-aware workgroup mappings (dtn_device.h), checked on the host: the
-walk kernel's xcd_block, a bijection of [0, G) for every grid size up to
+"""The XCD-aware workgroup mappings, checked on the host: the walk kernel's
+xcd_block (dtn_device.h), a bijection of [0, G) for every grid size up to
 4096 and several large ones, runs of consecutive blocks per XCD, rounds
-kept together; the treecode traversal's xcd_contiguous, a bijection with
-each XCD's blocks taking one eighth of the range in order.  No GPU needed
-(hipcc builds the header's host side)."""
+kept together; the treecode traversal's xcd_contiguous (dtn_xcd.h), a
+bijection with each XCD's blocks taking one eighth of the range in order.
+No GPU needed (hipcc builds the headers' host side)."""
 import os
 import shutil
 import subprocess

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "../paper_1210_1491_amd/csrc/dtn_device.h"
+#include "../paper_1210_1491_amd/csrc/dtn_xcd.h"
 
 int main()
 {
