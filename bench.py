@@ -152,13 +152,13 @@ TREE_SOURCE_SLOTS = slots({"f64": 8, "f64fma": 9, "rsq64": 1})
 # the kernel sources it was measured on (SHA-256 of these files).
 TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_amd/csrc/dtn_device.h",
                      "paper_1210_1491_amd/csrc/dtn_internal.h"],
-           "sha256": ["3c936000d8fec434d1b060b12420db4912a265a93353ac53848120caacafc023",
+           "sha256": ["d9f297f958e61c878045f9110c0d8ce139b7500a2cfe0e12e70b912b8788f67a",
                       "19671560cc811f1b8a60b74d4037267882fa3f71950dead4aab4cc74733a45da",
                       "3ba5aaa8cff36fcabd3602a4f75e1f6a528fc5a5cd5d175510ed3897d9d2cf24"],
-           "fetch_bytes": 41788.938 * 1024 * (262144 / 131091.938), "write_bytes": 38400.0 * 1024 * 1.00,
+           "fetch_bytes": 41790.938 * 1024 * (262144 / 131088.5), "write_bytes": 38400.0 * 1024 * 1.00,
            # the half-space point workload's walk kernel (same sources), scaled
-           # by the copy in its own run (fetch 131086.188 KiB for 262144)
-           "halfspace_fetch_bytes": 92470.312 * 1024 * (262144 / 131086.188),
+           # by the copy in its own run (fetch 131086.812 KiB for 262144)
+           "halfspace_fetch_bytes": 92472.188 * 1024 * (262144 / 131086.812),
            "halfspace_write_bytes": 80000.0 * 1024 * 1.00}
 
 
