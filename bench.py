@@ -152,13 +152,13 @@ TREE_SOURCE_SLOTS = slots({"f64": 8, "f64fma": 9, "rsq64": 1})
 # the kernel sources it was measured on (SHA-256 of these files).
 TRAFFIC = {"files": ["paper_1210_1491_amd/csrc/dtn_wos.hip", "paper_1210_1491_amd/csrc/dtn_device.h",
                      "paper_1210_1491_amd/csrc/dtn_internal.h"],
-           "sha256": ["d9f297f958e61c878045f9110c0d8ce139b7500a2cfe0e12e70b912b8788f67a",
+           "sha256": ["87e9164055f41ec601b7f142fabe11c48a5f850b56c6bfd2515da790ea038347",
                       "19671560cc811f1b8a60b74d4037267882fa3f71950dead4aab4cc74733a45da",
                       "3ba5aaa8cff36fcabd3602a4f75e1f6a528fc5a5cd5d175510ed3897d9d2cf24"],
-           "fetch_bytes": 41790.938 * 1024 * (262144 / 131088.5), "write_bytes": 38400.0 * 1024 * 1.00,
+           "fetch_bytes": 41790.938 * 1024 * (262144 / 131088.688), "write_bytes": 38400.0 * 1024 * 1.00,
            # the half-space point workload's walk kernel (same sources), scaled
-           # by the copy in its own run (fetch 131086.812 KiB for 262144)
-           "halfspace_fetch_bytes": 92472.188 * 1024 * (262144 / 131086.812),
+           # by the copy in its own run (fetch 131086.375 KiB for 262144)
+           "halfspace_fetch_bytes": 92472.438 * 1024 * (262144 / 131086.375),
            "halfspace_write_bytes": 80000.0 * 1024 * 1.00}
 
 

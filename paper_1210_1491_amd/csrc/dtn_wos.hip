@@ -299,34 +299,41 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
         const uint64_t per_lane = (uint64_t)((w_hi - w_lo + kWave - 1) / kWave + 1);
         const uint64_t it_max = per_lane > ~0ull / per_walk ? ~0ull : per_walk * per_lane;
 
-        // The distance at a lane's position is taken right after the jump
-        // that reached it, so a walk's exit (inside the shell, beyond the
-        // truncation sphere, or at the step cap) is known in the iteration of
-        // its last jump and its lane is free for the next refill: a walk of
-        // S steps holds its lane S iterations, not S + 1.  Every walk starts
-        // at the chunk's point, so the start's distance and exit test are
-        // taken once per chunk.
-        uint32_t cand0 = 0;
-        if constexpr (KIND == DTN_BOX_MINUS_BOXES)
-            cand0 = hole_candidates(g, co, true, (float)y0, (float)y1, (float)y2);
-        const double d0 = dist_f64<KIND, PREC != DTN_FP64>(g, y0, y1, y2, cand0);
-        if constexpr (has_holes(KIND)) {
-            ++n_iters;
-            n_visits += KIND == DTN_BOX_MINUS_BOXES ? (uint64_t)__builtin_popcount(cand0) : (uint64_t)g.n_holes;
+        // Where a walk's exit is tested, by measurement per kernel: right
+        // after the jump that reached its position (the distance taken
+        // there), so that a walk of S steps holds its lane S iterations, not
+        // S + 1 (FP64 walks and box-with-holes walks: 0.6 % and 1 % faster),
+        // or at the top of the next iteration, where the distance runs
+        // beside the direction (FP32-mixed walks on the other kinds: their
+        // hardware sin/cos overlaps the FP64 distance there, 4 % faster).
+        // With the test after the jump every walk starts at the chunk's
+        // point, so the start's distance and exit test are taken once.
+        constexpr bool kExitAfterJump = PREC == DTN_FP64 || KIND == DTN_BOX_MINUS_BOXES;
+        double d = 0.0;
+        bool start_ends = false;
+        if constexpr (kExitAfterJump) {
+            uint32_t cand0 = 0;
+            if constexpr (KIND == DTN_BOX_MINUS_BOXES)
+                cand0 = hole_candidates(g, co, true, (float)y0, (float)y1, (float)y2);
+            d = dist_f64<KIND, PREC != DTN_FP64>(g, y0, y1, y2, cand0);
+            if constexpr (has_holes(KIND)) {
+                ++n_iters;
+                n_visits += KIND == DTN_BOX_MINUS_BOXES ? (uint64_t)__builtin_popcount(cand0) : (uint64_t)g.n_holes;
+            }
+            bool start_gone = false;
+            if constexpr (has_truncation(KIND)) {
+                const double ex = y0 - g.c[0], ey = y1 - g.c[1], ez = y2 - g.c[2];
+                start_gone = ex * ex + ey * ey + ez * ez >= g.trunc_r * g.trunc_r;
+            }
+            // every lane computed the same start; the ballot makes that
+            // wave-uniform for the compiler
+            start_ends = __builtin_amdgcn_ballot_w64(d < eps || start_gone) != 0 || cap == 0u;
         }
-        bool start_gone = false;
-        if constexpr (has_truncation(KIND)) {
-            const double ex = y0 - g.c[0], ey = y1 - g.c[1], ez = y2 - g.c[2];
-            start_gone = ex * ex + ey * ey + ez * ez >= g.trunc_r * g.trunc_r;
-        }
-        // a walk ends at its start (no step); every lane computed the same
-        // start, the ballot makes that wave-uniform for the compiler
-        const bool start_ends = __builtin_amdgcn_ballot_w64(d0 < eps || start_gone) != 0 || cap == 0u;
-        double d = d0;
+        const double d0 = d;
 
         for (uint64_t it = 0; it < it_max; ++it) {
             uint32_t w1, w2;  // this step's two random words
-            uint64_t fm0 = 0;  // walks handed out now that end at their start
+            uint64_t fm0 = 0;  // walks handed out now that end at their start (exit after the jump)
             if ((it & 1ull) == 0ull) {
                 const uint64_t want = ~wmask;
                 if (want) {
@@ -345,7 +352,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                     }
                     wmask |= sm;
                     next += __popcll(want);
-                    fm0 = start_ends ? sm : 0;
+                    if constexpr (kExitAfterJump) fm0 = start_ends ? sm : 0;
                 }
                 if (wmask == 0) break;
                 const Philox4 r = philox4x32_10((uint32_t)walk, (uint32_t)(walk >> 32), nstep >> 1, sid, k0, k1);
@@ -357,9 +364,40 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                 w1 = r2;
                 w2 = r3;
             }
-            // the walking lanes not ending at their start jump by d (the
-            // distance at their position, at least eps)
-            const uint64_t jm = wmask & ~fm0;
+            // The distance at the lanes' positions and the exit tests: inside
+            // the shell, beyond the truncation sphere, at the step cap (the
+            // last returned).  Distance and epsilon test in FP64 on both paths
+            // (an FP32 distance would need an FP64 recheck inside a rounding
+            // band around the shell, which some lane of a wave needs at almost
+            // every step, and a shrunken jump everywhere).  Every lane
+            // computes it (an idle lane's point is its last one, inside the
+            // domain); only the walking lanes' results are used.
+            uint64_t in_shell = 0, gone = 0;
+            const auto exit_tests = [&]() {
+                // candidate holes of the walking lanes' cells (whole wave active here)
+                uint32_t cand = 0;
+                if constexpr (KIND == DTN_BOX_MINUS_BOXES)
+                    cand = hole_candidates(g, co, lane_in(wmask), (float)x, (float)y, (float)z);
+                if constexpr (has_holes(KIND)) {
+                    ++n_iters;
+                    n_visits += KIND == DTN_BOX_MINUS_BOXES ? (uint64_t)__builtin_popcount(cand) : (uint64_t)g.n_holes;
+                }
+                d = dist_f64<KIND, PREC != DTN_FP64>(g, x, y, z, cand);
+                in_shell = __builtin_amdgcn_ballot_w64(d < eps);
+                if constexpr (has_truncation(KIND)) {
+                    const double ex = x - g.c[0], ey = y - g.c[1], ez = z - g.c[2];
+                    gone = __builtin_amdgcn_ballot_w64(ex * ex + ey * ey + ez * ez >= g.trunc_r * g.trunc_r);
+                }
+                return __builtin_amdgcn_ballot_w64(nstep >= cap);
+            };
+            uint64_t fm = 0;  // walks that end in this iteration
+            if constexpr (!kExitAfterJump) {
+                const uint64_t at_cap = exit_tests();
+                fm = wmask & (in_shell | gone | at_cap);
+            }
+            // the walking lanes that go on jump by d (the distance at their
+            // position, at least eps)
+            const uint64_t jm = wmask & ~(kExitAfterJump ? fm0 : fm);
             steps += (uint64_t)__popcll(jm);
             if (lane_in(jm)) {
                 if constexpr (PREC == DTN_FP64) {
@@ -389,29 +427,10 @@ __global__ __launch_bounds__(kWalkBlock) void k_wos_walk(DevGeom g, const double
                 }
                 ++nstep;
             }
-            const bool walking = lane_in(wmask);
-            // candidate holes of the walking lanes' cells (whole wave active here)
-            uint32_t cand = 0;
-            if constexpr (KIND == DTN_BOX_MINUS_BOXES)
-                cand = hole_candidates(g, co, walking, (float)x, (float)y, (float)z);
-            if constexpr (has_holes(KIND)) {
-                ++n_iters;
-                n_visits += KIND == DTN_BOX_MINUS_BOXES ? (uint64_t)__builtin_popcount(cand) : (uint64_t)g.n_holes;
+            if constexpr (kExitAfterJump) {
+                const uint64_t at_cap = exit_tests();
+                fm = (jm & (in_shell | gone | at_cap)) | fm0;
             }
-            // distance and epsilon test in FP64 on both paths (an FP32
-            // distance would need an FP64 recheck inside a rounding band
-            // around the shell, which some lane of a wave needs at almost
-            // every step, and a shrunken jump everywhere).  Every lane
-            // computes it (an idle lane's point is its last one, inside the
-            // domain); only the walking lanes' results are used.
-            d = dist_f64<KIND, PREC != DTN_FP64>(g, x, y, z, cand);
-            const uint64_t in_shell = __builtin_amdgcn_ballot_w64(d < eps);
-            uint64_t gone = 0;  // lanes at or beyond the truncation sphere
-            if constexpr (has_truncation(KIND)) {
-                const double ex = x - g.c[0], ey = y - g.c[1], ez = z - g.c[2];
-                gone = __builtin_amdgcn_ballot_w64(ex * ex + ey * ey + ez * ez >= g.trunc_r * g.trunc_r);
-            }
-            const uint64_t fm = (jm & (in_shell | gone | __builtin_amdgcn_ballot_w64(nstep >= cap))) | fm0;
             capped += (uint64_t)__popcll(fm & ~(in_shell | gone));
             if (fm) {
                 if (lane_in(fm)) {
